@@ -1,0 +1,56 @@
+"""Centred cardinal B-spline shape functions (oracle; test infrastructure only).
+
+The paper deposits J and gathers fields with tensor products of symmetric
+B-splines (Sec. 2.2, after the PIC current density; Sec. 4.1, the paragraph on
+the current weighting), but it does not print the spline.  The reading used
+here: the centred cardinal B-spline M_m of degree m is the (m+1)-fold
+convolution of the unit box on [-1/2, 1/2); nodes sit at i*dx, and a particle
+at x contributes with weight M_m((x_i - x)/dx) * M_m((y_j - y)/dy) / (dx*dy).
+
+M_m is written below as its piecewise polynomial in |t| (the plain definition),
+not as per-node weight formulas.
+"""
+
+import numpy as np
+
+# support radius (m+1)/2 of M_m
+SUPPORT = {0: 0.5, 1: 1.0, 2: 1.5, 3: 2.0}
+
+
+def M(m, t):
+    """Centred cardinal B-spline of degree m (0..3) evaluated at t (array)."""
+    a = np.abs(np.asarray(t, dtype=np.float64))
+    out = np.zeros_like(a)
+    if m == 0:
+        out[a < 0.5] = 1.0
+    elif m == 1:
+        s = a < 1.0
+        out[s] = 1.0 - a[s]
+    elif m == 2:
+        s = a < 0.5
+        out[s] = 0.75 - a[s] ** 2
+        s = (a >= 0.5) & (a < 1.5)
+        out[s] = 0.5 * (1.5 - a[s]) ** 2
+    elif m == 3:
+        s = a < 1.0
+        out[s] = 2.0 / 3.0 - a[s] ** 2 + 0.5 * a[s] ** 3
+        s = (a >= 1.0) & (a < 2.0)
+        out[s] = (2.0 - a[s]) ** 3 / 6.0
+    else:
+        raise ValueError("spline degree must be 0..3")
+    return out
+
+
+def stencil(m, xi):
+    """Node indices (unwrapped) and weights M_m(g - xi) for positions xi = x/dx.
+
+    Returns (g, w) of shape (N, 4): the four nodes floor(xi)-1 .. floor(xi)+2
+    cover the support |t| < 2 of every degree m <= 3; weights outside the
+    support evaluate to zero.
+    """
+    xi = np.asarray(xi, dtype=np.float64)
+    base = np.floor(xi).astype(np.int64)
+    offs = np.arange(-1, 3)
+    g = base[:, None] + offs[None, :]
+    w = M(m, g - xi[:, None])
+    return g, w

@@ -1,0 +1,281 @@
+"""Algorithm 1 of arXiv 2410.18414 in plain FP64 (oracle; test infrastructure only).
+
+One PIC step (Algorithm 1, Sec. 4.2), for one mobile species of macro-particles
+on a periodic 2-D grid, 2D3V (x, y; three momentum/velocity components):
+
+  1. x^{n+1} = x^n + v^n dt, wrapped into [0, L)             (IAEM, Sec. 4.1)
+  2. J^{n+1} = sum_p q v_p^n S(x - x_p^{n+1})                 (Sec. 2.2, Sec. 4.1)
+  3. rho from the continuity equation, in the stepper's own form
+  4. phi, A by BDF-k / implicit CDF-2 / DIRK-2, L^{-1} by FFT  (Sec. 3)
+  5. spectral gradients of phi~ and A on the mesh             (Sec. 4.1)
+  6. gather at x^{n+1} with the same spline S
+  7. v* = 2 v^n - v^{n-1};  P^{n+1} = P^n + q(-grad phi~ + (grad A) . v*) dt;
+     v^{n+1} = c^2 (P - qA) / sqrt(c^2 (P - qA)^2 + (m c^2)^2)
+  8. shift the history
+
+Readings (the paper is silent, ambiguous or misprinted):
+  * BDF continuity: Algorithm 1 prints rho^{n+1} with flipped signs and a
+    shifted index; the defining equation of Sec. 3.2 (the BDF-k continuity
+    equation) is followed: rho^{n+1} = -(1/a_0)[sum_{j>=1} a_j rho^{n+1-j}
+    + dt div J^{n+1}].
+  * BDF wave equations: "1/(Delta c^2)" is read as 1/c^2; the A source is
+    mu0 J (the update formula prints rho/eps0); alpha = a_0/(c dt), the
+    Helmholtz solve divides by C_0 = a_0^2; the Laplacian acts on level n+1.
+  * DIRK stage equations for k^v: the factor c^2 on the source and on the
+    Laplacian of the stage value is restored (it is present in the generic
+    stage equations of Sec. 3.3 and dropped in the specialised ones).
+  * The DIRK "gauge update" for phi is the gauge constraint, used as the
+    diagnostic; phi is advanced by its own stage equations.
+  * CDF-2 is the implicit form (sources averaged over n+1 and n-1).
+  * v^{-1} by Taylor expansion: with the cold start below the force at t=0 is
+    zero, so v^{-1} = v^0.
+  * Cold start: immobile ions are the negative of the t=0 electron charge, so
+    rho^0 = 0; every field history level with n <= 0 is zero.
+  * A position that wraps to exactly L (floating point) is set to 0.
+  * (grad A . v*)_j = sum_l v*_l d_j A_l; d/dz = 0 in 2-D, so P_z is constant.
+"""
+
+import numpy as np
+
+from . import bspline, spectral, schemes
+
+# order of the 12 mesh fields the gather interpolates (slot 11 is phi~ itself)
+FIELD_NAMES = ("dphi_dx", "dphi_dy", "Ax", "Ay", "Az",
+               "dAx_dx", "dAy_dx", "dAz_dx", "dAx_dy", "dAy_dy", "dAz_dy", "phi")
+
+
+class Params:
+    def __init__(self, nx, ny, lx, ly, degree, scheme, dt, c=1.0, eps0=1.0,
+                 mu0=1.0, q=-1.0, m=1.0, bdf_order=2):
+        if scheme not in ("bdf", "cdf2", "dirk2"):
+            raise ValueError(scheme)
+        if abs(c * c * eps0 * mu0 - 1.0) > 1e-12:
+            raise ValueError("c^2 eps0 mu0 must equal 1")
+        self.nx, self.ny, self.lx, self.ly = int(nx), int(ny), float(lx), float(ly)
+        self.dx, self.dy = self.lx / self.nx, self.ly / self.ny
+        self.degree, self.scheme, self.bdf_order = int(degree), scheme, int(bdf_order)
+        self.dt, self.c, self.eps0, self.mu0 = float(dt), float(c), float(eps0), float(mu0)
+        self.q, self.m = float(q), float(m)
+        self.ikx, self.iky, self.lap = spectral.symbols(self.nx, self.ny, self.lx, self.ly)
+
+    @property
+    def spec_shape(self):
+        return (self.ny, self.nx // 2 + 1)
+
+
+# ----------------------------------------------------------------------------
+# particles
+
+def wrap(x, L):
+    x = x - L * np.floor(x / L)
+    x = np.where(x >= L, 0.0, x)
+    return x
+
+
+def velocity(p, P, A):
+    """v = c^2 (P - qA) / sqrt(c^2 |P - qA|^2 + (m c^2)^2)  (Sec. 2.2)."""
+    u = P - p.q * A
+    s = np.sqrt(p.c ** 2 * np.sum(u * u, axis=1) + (p.m * p.c ** 2) ** 2)
+    return p.c ** 2 * u / s[:, None]
+
+
+def init_particles(p, x, y, P):
+    """Given x^0, P^0 with A^0 = 0: v^0 from P^0, and v^{-1} = v^0 (cold start)."""
+    x = wrap(np.asarray(x, np.float64), p.lx)
+    y = wrap(np.asarray(y, np.float64), p.ly)
+    P = np.array(P, np.float64)
+    v = velocity(p, P, np.zeros_like(P))
+    return dict(x=x, y=y, P=P, v=v, vprev=v.copy())
+
+
+def position_update(p, x, y, v):
+    return wrap(x + v[:, 0] * p.dt, p.lx), wrap(y + v[:, 1] * p.dt, p.ly)
+
+
+def deposit_current(p, x, y, v):
+    """J(x_g) = sum_p q v_p S(x_g - x_p), S = M(dx)M(dy)/(dx dy); shape [3, ny, nx]."""
+    gx, wx = bspline.stencil(p.degree, x / p.dx)
+    gy, wy = bspline.stencil(p.degree, y / p.dy)
+    n = p.nx * p.ny
+    J = np.zeros((3, n))
+    qv = p.q * v
+    for a in range(4):
+        for b in range(4):
+            idx = (gy[:, b] % p.ny) * p.nx + (gx[:, a] % p.nx)
+            w = wx[:, a] * wy[:, b] / (p.dx * p.dy)
+            for c in range(3):
+                J[c] += np.bincount(idx, weights=w * qv[:, c], minlength=n)
+    return J.reshape(3, p.ny, p.nx)
+
+
+def gather(p, fields, x, y):
+    """Interpolate mesh fields [F, ny, nx] at the particles with the same spline."""
+    gx, wx = bspline.stencil(p.degree, x / p.dx)
+    gy, wy = bspline.stencil(p.degree, y / p.dy)
+    F = fields.reshape(fields.shape[0], -1)
+    out = np.zeros((x.shape[0], fields.shape[0]))
+    for a in range(4):
+        for b in range(4):
+            idx = (gy[:, b] % p.ny) * p.nx + (gx[:, a] % p.nx)
+            out += (wx[:, a] * wy[:, b])[:, None] * F[:, idx].T
+    return out
+
+
+def push(p, P, v, vprev, g):
+    """IAEM momentum and velocity update (Sec. 4.1) from gathered fields g [N, 12]."""
+    vs = 2.0 * v - vprev
+    Fx = -g[:, 0] + vs[:, 0] * g[:, 5] + vs[:, 1] * g[:, 6] + vs[:, 2] * g[:, 7]
+    Fy = -g[:, 1] + vs[:, 0] * g[:, 8] + vs[:, 1] * g[:, 9] + vs[:, 2] * g[:, 10]
+    Pn = P.copy()
+    Pn[:, 0] += p.q * Fx * p.dt
+    Pn[:, 1] += p.q * Fy * p.dt
+    vn = velocity(p, Pn, g[:, 2:5])
+    return Pn, vn
+
+
+# ----------------------------------------------------------------------------
+# fields
+
+def cold_history(p):
+    """Zero history for the chosen stepper (all levels n <= 0 vanish)."""
+    z = lambda: np.zeros(p.spec_shape, np.complex128)  # noqa: E731
+    z3 = lambda: np.zeros((3,) + p.spec_shape, np.complex128)  # noqa: E731
+    if p.scheme == "bdf":
+        k = p.bdf_order
+        return dict(rho=[z() for _ in range(k)], phi=[z() for _ in range(2 * k)],
+                    A=[z3() for _ in range(2 * k)])
+    if p.scheme == "cdf2":
+        return dict(rho=[z() for _ in range(3)], phi=[z() for _ in range(3)],
+                    A=[z3() for _ in range(2)], J=[z3() for _ in range(2)])
+    return dict(rho=[z(), z()], phi=[z(), z()], vphi=z(), A=[z3(), z3()], vA=z3(), J=z3())
+
+
+def div(p, Vh):
+    return p.ikx * Vh[0] + p.iky * Vh[1]
+
+
+def field_update(p, hist, Jh):
+    """Continuity + wave update given J^{n+1} (spectral).  Returns (hist', phi~, A)."""
+    if p.scheme == "bdf":
+        return _bdf_update(p, hist, Jh)
+    if p.scheme == "cdf2":
+        return _cdf2_update(p, hist, Jh)
+    return _dirk2_update(p, hist, Jh)
+
+
+def _bdf_update(p, hist, Jh):
+    # Sec. 3.2: BDF-k continuity, wave equations and the L^{-1} update form
+    k = p.bdf_order
+    a = schemes.bdf_a(k)
+    C = schemes.bdf_C(k)
+    rho_new = -(sum(a[j] * hist["rho"][j - 1] for j in range(1, k + 1))
+                + p.dt * div(p, Jh)) / a[0]
+    alpha2 = (a[0] / (p.c * p.dt)) ** 2
+    Lh = 1.0 - p.lap / alpha2
+    phi_new = (rho_new / (p.eps0 * alpha2)
+               - sum(C[i] / C[0] * hist["phi"][i - 1] for i in range(1, 2 * k + 1))) / Lh
+    A_new = (p.mu0 * Jh / alpha2
+             - sum(C[i] / C[0] * hist["A"][i - 1] for i in range(1, 2 * k + 1))) / Lh
+    out = dict(rho=[rho_new] + hist["rho"][:-1], phi=[phi_new] + hist["phi"][:-1],
+               A=[A_new] + hist["A"][:-1])
+    return out, phi_new, A_new
+
+
+def _cdf2_update(p, hist, Jh):
+    # Sec. 3.1: staggered continuity and the Crank-Nicolson form L(u^{n+1}+u^{n-1})
+    #   = 2u^n + Gamma/alpha^2 with alpha = sqrt(2)/(c dt)
+    rho_h, rho_mh = hist["rho"][0], hist["rho"][1]          # rho^{n+1/2}, rho^{n-1/2}
+    phi_h, phi_mh = hist["phi"][0], hist["phi"][1]          # phi^{n+1/2}, phi^{n-1/2}
+    A_n, A_m = hist["A"][0], hist["A"][1]                   # A^n, A^{n-1}
+    J_m = hist["J"][1]                                      # J^{n-1}
+    rho_new = rho_h - p.dt * div(p, Jh)                     # rho^{n+3/2}
+    alpha2 = 2.0 / (p.c * p.dt) ** 2
+    Lh = 1.0 - p.lap / alpha2
+    phi_new = -phi_mh + (2.0 * phi_h + (rho_new + rho_mh) / (alpha2 * p.eps0)) / Lh
+    A_new = -A_m + (2.0 * A_n + p.mu0 * (Jh + J_m) / alpha2) / Lh
+    phi_tilde = 0.5 * (phi_new + phi_h)                     # Sec. 4.1, staggered phi
+    out = dict(rho=[rho_new, rho_h, rho_mh], phi=[phi_new, phi_h, phi_mh],
+               A=[A_new, A_n], J=[Jh, hist["J"][0]])
+    return out, phi_tilde, A_new
+
+
+def _dirk2_update(p, hist, Jh):
+    # Sec. 3.3: s-stage DIRK on (u, v) with u' = v, v' = c^2 (S + Lap u)
+    A_t, b, cc = schemes.DIRK2_A, schemes.DIRK2_B, schemes.DIRK2_C
+    s = len(b)
+    h, c2, lap = p.dt, p.c ** 2, p.lap
+    J_n = hist["J"]
+    J_st = [(1.0 - cc[i]) * J_n + cc[i] * Jh for i in range(s)]
+    rho_n = hist["rho"][0]
+    rho_new = rho_n - h * sum(b[i] * div(p, J_st[i]) for i in range(s))
+    rho_st = [(1.0 - cc[i]) * rho_n + cc[i] * rho_new for i in range(s)]
+
+    def advance(u, v, S):
+        ku, kv = [], []
+        for i in range(s):
+            U = u + h * sum(A_t[i, j] * ku[j] for j in range(i))
+            V = v + h * sum(A_t[i, j] * kv[j] for j in range(i))
+            Li = 1.0 - (h * A_t[i, i] * p.c) ** 2 * lap
+            ku.append((V + h * A_t[i, i] * c2 * (S[i] + lap * U)) / Li)
+            kv.append((c2 * (S[i] + lap * U) + h * A_t[i, i] * c2 * lap * V) / Li)
+        return (u + h * sum(b[i] * ku[i] for i in range(s)),
+                v + h * sum(b[i] * kv[i] for i in range(s)))
+
+    phi_new, vphi_new = advance(hist["phi"][0], hist["vphi"],
+                                [rho_st[i] / p.eps0 for i in range(s)])
+    A_new = np.empty_like(Jh)
+    vA_new = np.empty_like(Jh)
+    for l in range(3):
+        A_new[l], vA_new[l] = advance(hist["A"][0][l], hist["vA"][l],
+                                      [p.mu0 * J_st[i][l] for i in range(s)])
+    out = dict(rho=[rho_new, rho_n], phi=[phi_new, hist["phi"][0]], vphi=vphi_new,
+               A=[A_new, hist["A"][0]], vA=vA_new, J=Jh)
+    return out, phi_new, A_new
+
+
+def gradient_fields(p, phi_h, A_h):
+    """The 12 mesh fields (order FIELD_NAMES) by spectral multiply + inverse FFT."""
+    spec = [p.ikx * phi_h, p.iky * phi_h, A_h[0], A_h[1], A_h[2],
+            p.ikx * A_h[0], p.ikx * A_h[1], p.ikx * A_h[2],
+            p.iky * A_h[0], p.iky * A_h[1], p.iky * A_h[2], phi_h]
+    return np.stack([spectral.ifft2(f, p.nx, p.ny) for f in spec])
+
+
+# ----------------------------------------------------------------------------
+# the whole step
+
+class State:
+    """Particles + field history; `step()` runs Algorithm 1 once."""
+
+    def __init__(self, p, x, y, P):
+        self.p = p
+        self.part = init_particles(p, x, y, P)
+        self.hist = cold_history(p)
+        self.J = None
+        self.fields = None
+        self.n = 0
+
+    def deposit(self):
+        pt = self.part
+        pt["x"], pt["y"] = position_update(self.p, pt["x"], pt["y"], pt["v"])
+        self.J = deposit_current(self.p, pt["x"], pt["y"], pt["v"])
+        return self.J
+
+    def solve(self):
+        Jh = np.stack([spectral.fft2(self.J[c]) for c in range(3)])
+        self.hist, phi_t, A_new = field_update(self.p, self.hist, Jh)
+        self.fields = gradient_fields(self.p, phi_t, A_new)
+        return self.fields
+
+    def gather_push(self):
+        pt = self.part
+        g = gather(self.p, self.fields, pt["x"], pt["y"])
+        Pn, vn = push(self.p, pt["P"], pt["v"], pt["vprev"], g)
+        pt["P"], pt["vprev"], pt["v"] = Pn, pt["v"], vn
+        self.n += 1
+
+    def step(self, nsteps=1):
+        for _ in range(nsteps):
+            self.deposit()
+            self.solve()
+            self.gather_push()

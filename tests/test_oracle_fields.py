@@ -1,0 +1,211 @@
+"""Pins of the oracle's spectral operators and time steppers (CPU only).
+
+* FFT usage and derivative symbols against a direct DFT and trig polynomials.
+* BDF coefficients against the values the paper prints and the textbook table
+  (tests/golden/bdf_dirk_coefficients.json), plus polynomial exactness.
+* Each stepper's update against its closed-form single-Fourier-mode
+  dispersion relation, source free, with c != 1.
+"""
+
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import pic, schemes, spectral
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                   "bdf_dirk_coefficients.json")))
+
+
+def direct_dft2(f):
+    ny, nx = f.shape
+    out = np.zeros((ny, nx // 2 + 1), complex)
+    for ky in range(ny):
+        for kx in range(nx // 2 + 1):
+            s = 0.0
+            for j in range(ny):
+                for i in range(nx):
+                    s += f[j, i] * np.exp(-2j * np.pi * (kx * i / nx + ky * j / ny))
+            out[ky, kx] = s
+    return out
+
+
+@pytest.mark.parametrize("nx,ny", [(4, 4), (8, 6), (16, 16)])
+def test_fft_matches_direct_dft(nx, ny):
+    f = np.random.default_rng(nx * ny).normal(size=(ny, nx))
+    np.testing.assert_allclose(spectral.fft2(f), direct_dft2(f), atol=1e-11)
+    np.testing.assert_allclose(spectral.ifft2(spectral.fft2(f), nx, ny), f, atol=1e-13)
+
+
+def test_spectral_derivatives_of_trig_polynomial():
+    nx, ny, lx, ly = 16, 8, 2.0, 3.0
+    ikx, iky, lap = spectral.symbols(nx, ny, lx, ly)
+    X, Y = np.meshgrid(np.arange(nx) * lx / nx, np.arange(ny) * ly / ny)
+    ax, ay = 2 * np.pi * 3 / lx, 2 * np.pi * 2 / ly
+    f = np.sin(ax * X) * np.cos(ay * Y) + 0.5 * np.cos(2 * np.pi * 7 / lx * X)
+    fh = spectral.fft2(f)
+    dfx = spectral.ifft2(ikx * fh, nx, ny)
+    dfy = spectral.ifft2(iky * fh, nx, ny)
+    lf = spectral.ifft2(lap * fh, nx, ny)
+    np.testing.assert_allclose(
+        dfx, ax * np.cos(ax * X) * np.cos(ay * Y)
+        - 0.5 * 2 * np.pi * 7 / lx * np.sin(2 * np.pi * 7 / lx * X), atol=1e-12)
+    np.testing.assert_allclose(dfy, -ay * np.sin(ax * X) * np.sin(ay * Y), atol=1e-12)
+    np.testing.assert_allclose(
+        lf, -(ax ** 2 + ay ** 2) * np.sin(ax * X) * np.cos(ay * Y)
+        - 0.5 * (2 * np.pi * 7 / lx) ** 2 * np.cos(2 * np.pi * 7 / lx * X), atol=1e-10)
+
+
+def test_nyquist_rule_div_grad_equals_laplacian():
+    nx, ny = 8, 8
+    ikx, iky, lap = spectral.symbols(nx, ny, 1.0, 1.0)
+    np.testing.assert_allclose(ikx * ikx + iky * iky, lap, atol=0)
+    # the Nyquist cosine has no derivative under the reading
+    X, _ = np.meshgrid(np.arange(nx) / nx, np.arange(ny) / ny)
+    fh = spectral.fft2(np.cos(np.pi * nx * X))
+    assert np.abs(spectral.ifft2(ikx * fh, nx, ny)).max() < 1e-14
+
+
+def _frac(s):
+    return [Fraction(v) for v in s]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_bdf_coefficients_golden(k):
+    assert schemes.bdf_a_exact(k) == _frac(GOLD["bdf_first_derivative_over_dt"][str(k)])
+
+
+def test_bdf2_values_printed_in_paper():
+    a = schemes.bdf_a_exact(2)
+    C = schemes.bdf_C_exact(2)
+    assert [v / a[0] for v in a] == _frac(GOLD["bdf2_first_derivative_over_two_thirds_dt"])
+    assert [v / C[0] for v in C] == _frac(
+        GOLD["bdf2_second_derivative_over_two_thirds_dt_squared"])
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_bdf_polynomial_exactness(k):
+    """a reproduces d/dt and C = a*a reproduces d2/dt2 for polynomials of degree <= k."""
+    a = schemes.bdf_a_exact(k)
+    C = schemes.bdf_C_exact(k)
+    n = 11
+    for deg in range(k + 1):
+        d1 = sum(a[j] * Fraction(n - j) ** deg for j in range(k + 1))
+        assert d1 == (deg * Fraction(n) ** (deg - 1) if deg else 0)
+        d2 = sum(C[j] * Fraction(n - j) ** deg for j in range(2 * k + 1))
+        assert d2 == (deg * (deg - 1) * Fraction(n) ** (deg - 2) if deg >= 2 else 0)
+
+
+def test_table1_structure():
+    """Table 1: C_{2k} = a_k^2, C_{2k-1} = 2 a_{k-1} a_k, C_0 = a_0^2, symmetric sums."""
+    for k in range(1, 7):
+        a, C = schemes.bdf_a_exact(k), schemes.bdf_C_exact(k)
+        assert C[0] == a[0] * a[0] and C[2 * k] == a[k] * a[k]
+        assert C[2 * k - 1] == 2 * a[k - 1] * a[k] and C[1] == 2 * a[0] * a[1]
+        assert sum(C) == 0 and sum(a) == 0   # consistency: constants have no derivative
+
+
+def test_dirk2_tableau_reading():
+    g = GOLD["dirk2_qin_zhang"]
+    A = np.array([[float(Fraction(v)) for v in r] for r in g["A"]])
+    np.testing.assert_array_equal(schemes.DIRK2_A, A)
+    np.testing.assert_array_equal(schemes.DIRK2_B, [float(Fraction(v)) for v in g["b"]])
+    np.testing.assert_array_equal(schemes.DIRK2_C, [float(Fraction(v)) for v in g["c"]])
+    np.testing.assert_allclose(schemes.DIRK2_A.sum(1), schemes.DIRK2_C)   # row sums
+    # second order: b.1 = 1, b.c = 1/2; symplectic: b_i a_ij + b_j a_ji = b_i b_j
+    b, Am = schemes.DIRK2_B, schemes.DIRK2_A
+    assert b.sum() == 1.0 and b @ schemes.DIRK2_C == 0.5
+    M = b[:, None] * Am + (b[:, None] * Am).T - np.outer(b, b)
+    np.testing.assert_allclose(M, 0, atol=1e-15)
+    # the printed tableau is not consistent (row sums 1/2, 3/4 vs c = 1/4, 1/4)
+    gp = GOLD["dirk2_printed_garbled"]
+    Ap = np.array([[float(Fraction(v)) for v in r] for r in gp["A"]])
+    assert not np.allclose(Ap.sum(1), [float(Fraction(v)) for v in gp["c"]])
+
+
+# ---------------------------------------------------------------------------
+# closed-form single-mode dispersion (source free, J = rho = 0), c != 1
+
+C_LIGHT = 2.0
+MODE = (2, 3)          # (kx index, ky index) on a 16 x 16 grid of size 1.6 x 1.2
+
+
+def _params(scheme, k=2, dt=0.07):
+    return pic.Params(16, 16, 1.6, 1.2, 3, scheme, dt, c=C_LIGHT, eps0=1.0,
+                      mu0=1.0 / C_LIGHT ** 2, bdf_order=k)
+
+
+def _theta(p):
+    kx = 2 * np.pi * MODE[0] / p.lx
+    ky = 2 * np.pi * MODE[1] / p.ly
+    return p.c * np.hypot(kx, ky) * p.dt
+
+
+def _mode_field(p, val):
+    f = np.zeros(p.spec_shape, complex)
+    f[MODE[1], MODE[0]] = val
+    return f
+
+
+def _run(p, hist, nsteps):
+    J0 = np.zeros((3,) + p.spec_shape, complex)
+    for _ in range(nsteps):
+        hist, _, _ = pic.field_update(p, hist, J0)
+    return hist
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_bdf_dispersion(k):
+    p = _params("bdf", k)
+    th = _theta(p)
+    if k == 1:
+        z = 1.0 / (1.0 - 1j * th)            # 1 - 1/z = i theta
+    else:
+        # 3/2 - 2w + w^2/2 = +-i theta, w = 1/z: take the principal (least damped)
+        # root, so that round-off in the other modes cannot swamp z^n
+        roots = [1.0 / (2.0 + sg * np.sqrt(1.0 + 2j * s * th))
+                 for sg in (1, -1) for s in (1, -1)]
+        z = max((r for r in roots if abs(r) <= 1 + 1e-14), key=abs)
+    hist = pic.cold_history(p)
+    hist["phi"] = [_mode_field(p, z ** (-j)) for j in range(2 * k)]
+    hist["A"] = [np.stack([_mode_field(p, 0.5 * z ** (-j))] * 3) for j in range(2 * k)]
+    n = 100
+    out = _run(p, hist, n)
+    np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** n, rtol=1e-11)
+    np.testing.assert_allclose(out["A"][0][2][MODE[1], MODE[0]], 0.5 * z ** n, rtol=1e-11)
+
+
+def test_cdf2_dispersion():
+    p = _params("cdf2")
+    th = _theta(p)
+    r = 1.0 / (1.0 + th * th / 2)            # z + 1/z = 2 r, |z| = 1
+    z = r + 1j * np.sqrt(1 - r * r)
+    hist = pic.cold_history(p)
+    hist["phi"] = [_mode_field(p, z ** (-j)) for j in range(3)]
+    hist["A"] = [np.stack([_mode_field(p, z ** (-j))] * 3) for j in range(2)]
+    n = 100
+    out = _run(p, hist, n)
+    np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** n, rtol=1e-11)
+    np.testing.assert_allclose(out["A"][0][1][MODE[1], MODE[0]], z ** n, rtol=1e-11)
+    assert abs(abs(z) - 1) < 1e-15
+
+
+def test_dirk2_dispersion():
+    p = _params("dirk2")
+    th = _theta(p)
+    om = th / p.dt
+    z = ((1 + 0.25j * th) / (1 - 0.25j * th)) ** 2
+    hist = pic.cold_history(p)
+    hist["phi"] = [_mode_field(p, 1.0), _mode_field(p, 0.0)]
+    hist["vphi"] = _mode_field(p, 1j * om)
+    hist["A"] = [np.stack([_mode_field(p, 1.0)] * 3), np.zeros((3,) + p.spec_shape, complex)]
+    hist["vA"] = np.stack([_mode_field(p, 1j * om)] * 3)
+    n = 100
+    out = _run(p, hist, n)
+    np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** n, rtol=1e-11)
+    np.testing.assert_allclose(out["vphi"][MODE[1], MODE[0]], 1j * om * z ** n, rtol=1e-11)
+    np.testing.assert_allclose(out["A"][0][0][MODE[1], MODE[0]], z ** n, rtol=1e-11)
+    assert abs(abs(z) - 1) < 1e-14

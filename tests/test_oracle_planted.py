@@ -1,0 +1,92 @@
+"""Planted mistakes in the oracle must make its pins fail (CPU only).
+
+Each case patches one plausible error into the oracle (a flipped sign, a
+dropped factor, a transposed operand, a wrong coefficient) and re-runs the pin
+that should catch it.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import bspline, pic, schemes
+import test_oracle_fields as F
+import test_oracle_invariants as I
+import test_oracle_spline_deposit as S
+
+
+def test_flipped_continuity_sign_breaks_gauge(monkeypatch):
+    orig = pic.div
+    monkeypatch.setattr(pic, "div", lambda p, V: -orig(p, V))
+    with pytest.raises(AssertionError):
+        I.test_gauge_and_gauss("bdf", 2, 3, 1.0)
+
+
+def test_dropped_cell_area_breaks_total_current(monkeypatch):
+    orig = pic.deposit_current
+    monkeypatch.setattr(pic, "deposit_current",
+                        lambda p, x, y, v: orig(p, x, y, v) * p.dx * p.dy)
+    with pytest.raises(AssertionError):
+        S.test_deposit_total_current()
+
+
+def test_transposed_gather_breaks_linear_reproduction(monkeypatch):
+    orig = pic.gather
+    monkeypatch.setattr(pic, "gather", lambda p, f, x, y: orig(p, f, y * p.lx / p.ly,
+                                                               x * p.ly / p.lx))
+    with pytest.raises(AssertionError):
+        S.test_gather_reproduces_linear_fields(3)
+
+
+def test_wrong_spline_piece_breaks_cox_de_boor(monkeypatch):
+    orig = bspline.M
+    monkeypatch.setattr(bspline, "M", lambda m, t: orig(m, t) * (1 + 1e-3 * (np.abs(t) > 1)))
+    with pytest.raises(AssertionError):
+        S.test_spline_matches_cox_de_boor(3)
+
+
+def test_printed_dirk2_tableau_fails_dispersion(monkeypatch):
+    monkeypatch.setattr(schemes, "DIRK2_A", np.array([[0.5, 0.0], [0.25, 0.5]]))
+    monkeypatch.setattr(schemes, "DIRK2_C", np.array([0.25, 0.25]))
+    with pytest.raises(AssertionError):
+        F.test_dirk2_dispersion()
+
+
+def test_wrong_bdf_alpha_fails_dispersion(monkeypatch):
+    orig = schemes.bdf_a
+    # a_0 scaled alone: alpha = a_0/(c dt) and the continuity divisor change
+    monkeypatch.setattr(schemes, "bdf_a", lambda k: orig(k) * np.r_[1.1, np.ones(k)])
+    with pytest.raises(AssertionError):
+        F.test_bdf_dispersion(2)
+
+
+def test_missing_c2_in_dirk_kv_fails_dispersion(monkeypatch):
+    """The c^2 the specialised DIRK stage equations drop is caught with c != 1."""
+    src = pic._dirk2_update
+
+    def patched(p, hist, Jh):
+        # the same update with k^v's source term lacking c^2, i.e. c2 -> 1 there
+        A_t, b, cc = schemes.DIRK2_A, schemes.DIRK2_B, schemes.DIRK2_C
+        h, c2, lap = p.dt, p.c ** 2, p.lap
+
+        def advance(u, v, Sv):
+            ku, kv = [], []
+            for i in range(2):
+                U = u + h * sum(A_t[i, j] * ku[j] for j in range(i))
+                V = v + h * sum(A_t[i, j] * kv[j] for j in range(i))
+                Li = 1.0 - (h * A_t[i, i] * p.c) ** 2 * lap
+                ku.append((V + h * A_t[i, i] * c2 * (Sv[i] + lap * U)) / Li)
+                kv.append(((Sv[i] + lap * U) + h * A_t[i, i] * c2 * lap * V) / Li)
+            return (u + h * sum(b[i] * ku[i] for i in range(2)),
+                    v + h * sum(b[i] * kv[i] for i in range(2)))
+        z = [np.zeros(p.spec_shape)] * 2
+        phi, vphi = advance(hist["phi"][0], hist["vphi"], z)
+        A = np.empty_like(Jh)
+        vA = np.empty_like(Jh)
+        for l in range(3):
+            A[l], vA[l] = advance(hist["A"][0][l], hist["vA"][l], z)
+        return (dict(rho=hist["rho"], phi=[phi, hist["phi"][0]], vphi=vphi,
+                     A=[A, hist["A"][0]], vA=vA, J=Jh), phi, A)
+    assert src is not None
+    monkeypatch.setattr(pic, "_dirk2_update", patched)
+    with pytest.raises(AssertionError):
+        F.test_dirk2_dispersion()
