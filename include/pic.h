@@ -1,0 +1,167 @@
+/*
+ * pic.h -- C ABI of libpic: the per-step particle-mesh hot path of the
+ * gauge-conserving PIC method with generalized momentum (arXiv 2410.18414),
+ * on a periodic 2-D grid, 2D3V, one mobile species of macro-particles.
+ *
+ * One step is Algorithm 1 (Sec. 4.2):
+ *   deposit_current  x^{n+1} = x^n + v^n dt (periodic wrap); J^{n+1} by
+ *                    tensor-product B-spline deposition of q v^n at x^{n+1}
+ *                    (Sec. 2.2 PIC current density; Sec. 4.1).
+ *   field_solve      FFT of J; rho from the stepper's continuity equation;
+ *                    phi and A by BDF-k (Sec. 3.2), implicit CDF-2 (Sec. 3.1)
+ *                    or DIRK-2 (Sec. 3.3), each modified-Helmholtz operator
+ *                    L = I - Laplacian/alpha^2 inverted mode by mode in Fourier
+ *                    space; spectral gradients of phi~ and A on the mesh
+ *                    (Sec. 4.1: derivatives must be spectral).
+ *   gather_push      interpolate the mesh fields at x^{n+1} with the same
+ *                    spline; IAEM push (Sec. 4.1): v* = 2v^n - v^{n-1},
+ *                    P^{n+1} = P^n + q(-grad phi~ + (grad A).v*) dt,
+ *                    v^{n+1} = c^2 (P - qA)/sqrt(c^2 |P - qA|^2 + (m c^2)^2);
+ *                    shift the history.
+ *   step             nsteps x (deposit_current, field_solve, gather_push),
+ *                    with the gather/push of step n fused with the deposit of
+ *                    step n+1 (same results).
+ *
+ * Conventions
+ *   - Pointers are DEVICE pointers unless marked [host].  Work is enqueued
+ *     asynchronously on the HIP stream given to pic_create; results are valid
+ *     once that stream has synchronised.  Calls returning data to [host]
+ *     memory synchronise the stream themselves.
+ *   - Mesh nodes sit at (i dx, j dy), i < nx, j < ny; real mesh arrays are
+ *     row-major [ny][nx] float64 (x fastest).  Spectral arrays are the
+ *     half spectrum [ny][nx/2+1] of complex128 (interleaved re, im), forward
+ *     transform unnormalised with exp(-i k.x).
+ *   - Particle arrays passed in or out are float64 SoA blocks of length n.
+ *   - The caller allocates the workspace (pic_workspace_bytes) and owns it
+ *     and every buffer it passes; the library allocates no device memory.
+ *   - Errors: arguments are validated before anything is enqueued; on error
+ *     nothing is enqueued, the context is unchanged, and pic_last_error()
+ *     describes the failure.  No call aborts the process.
+ *   - A context is not thread-safe.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_ABI_VERSION 1
+
+typedef struct pic_ctx_s* pic_ctx_t;
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_ERR_INVALID_ARG = 1, /* a pointer, size or parameter is invalid          */
+  PIC_ERR_UNSUPPORTED = 2, /* a valid parameter this build does not implement  */
+  PIC_ERR_WORKSPACE = 3,   /* workspace too small or misaligned (256 B)        */
+  PIC_ERR_HIP = 4,         /* a HIP runtime call or launch failed              */
+  PIC_ERR_STATE = 5,       /* call out of order (see the phase rules below)    */
+  PIC_ERR_NONFINITE = 6    /* pic_diagnostics found a NaN/Inf particle value   */
+} pic_status_t;
+
+typedef enum { PIC_SCHEME_BDF = 0, PIC_SCHEME_CDF2 = 1, PIC_SCHEME_DIRK2 = 2 } pic_scheme_t;
+typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
+
+/* flags */
+#define PIC_FLAG_NO_SORT 1u      /* never reorder particles by tile            */
+#define PIC_FLAG_UNFUSED_STEP 2u /* step() runs the three calls separately     */
+
+typedef struct {                /* [host] */
+  int32_t abi_version;          /* == PIC_ABI_VERSION                                    */
+  int32_t nx, ny;               /* mesh nodes per axis: powers of two, 8 .. 1024          */
+  int32_t spline_degree;        /* 1 (linear), 2 (quadratic, the paper's), 3 (cubic)      */
+  double lx, ly;                /* periodic box [0,lx) x [0,ly)                          */
+  int32_t scheme;               /* pic_scheme_t                                          */
+  int32_t bdf_order;            /* BDF-k order 1..6 (Sec. 3.2), used when scheme == BDF  */
+  int32_t particle_dtype;       /* pic_dtype_t of particle state and gather; mesh FFT and
+                                   spectral history are float64 in both cases           */
+  int32_t sort_interval;        /* steps between tile re-sorts; 0 = default (4)          */
+  double dt;                    /* time step                                             */
+  double c, eps0, mu0;          /* |c^2 eps0 mu0 - 1| <= 1e-12 required (Sec. 2.1)      */
+  double q, m;                  /* macro-particle charge and mass                        */
+  int64_t max_particles;        /* capacity, >= 1                                        */
+  uint32_t flags;               /* PIC_FLAG_*                                            */
+  int32_t reserved[7];          /* must be zero                                          */
+} pic_config_t;
+
+/* Workspace bytes pic_create needs for cfg (0 if cfg is invalid). */
+size_t pic_workspace_bytes(const pic_config_t* cfg);
+
+/* Create a context.  workspace: device buffer of ws_bytes >= pic_workspace_bytes,
+ * 256-byte aligned, owned by the caller and untouched by it until pic_destroy.
+ * hip_stream: hipStream_t to enqueue on (NULL = default stream).  Zero-fills
+ * the field history (cold start: all levels n <= 0 vanish). */
+pic_status_t pic_create(const pic_config_t* cfg, void* workspace, size_t ws_bytes,
+                        void* hip_stream, pic_ctx_t* out);
+void pic_destroy(pic_ctx_t ctx);
+
+/* Message of the last failed call on ctx; with ctx == NULL, of the last failed
+ * pic_create / pic_workspace_bytes on this thread. */
+const char* pic_last_error(pic_ctx_t ctx);
+
+/* Load n particles: x[n], y[n] positions (wrapped into the box) and P[3n]
+ * generalized momenta as blocks Px, Py, Pz (float64, device).  With the cold
+ * start A^0 = 0, so v^0 = c^2 P/sqrt(c^2 |P|^2 + (m c^2)^2) (Sec. 2.2); the
+ * Taylor start of Algorithm 1 gives v^{-1} = v^0 because the t = 0 force
+ * vanishes.  Resets the step counter and the field history.  Phase -> READY. */
+pic_status_t init_particles(pic_ctx_t ctx, int64_t n, const double* x, const double* y,
+                            const double* P);
+
+/* READY -> DEPOSITED.  Position update and current deposition (Algorithm 1,
+ * first two steps). */
+pic_status_t deposit_current(pic_ctx_t ctx);
+/* DEPOSITED -> SOLVED.  Continuity, field update, spectral gradients
+ * (Algorithm 1, steps three to five). */
+pic_status_t field_solve(pic_ctx_t ctx);
+/* SOLVED -> READY.  Gather, IAEM push, history shift (Algorithm 1, remaining
+ * steps). */
+pic_status_t gather_push(pic_ctx_t ctx);
+/* READY -> READY.  nsteps >= 0 complete steps. */
+pic_status_t step(pic_ctx_t ctx, int32_t nsteps);
+
+/* Particle state in the ORIGINAL particle order, float64 device out[11 n]:
+ * blocks x, y, Px, Py, Pz, vx^n, vy^n, vz^n, vx^{n-1}, vy^{n-1}, vz^{n-1}. */
+pic_status_t pic_get_particles(pic_ctx_t ctx, double* out);
+/* Replace the particle state (same layout, original order); phase -> READY.
+ * Values are rounded to the particle dtype; positions are wrapped. */
+pic_status_t pic_set_particles(pic_ctx_t ctx, const double* in);
+
+/* Real mesh fields, float64 device dst:
+ *   PIC_FIELD_J      [3][ny][nx]  J^{n+1}; valid in phase DEPOSITED
+ *   PIC_FIELD_MESH  [12][ny][nx]  the gathered fields, valid in phase SOLVED:
+ *        dphi/dx, dphi/dy, Ax, Ay, Az, dAx/dx, dAy/dx, dAz/dx,
+ *        dAx/dy, dAy/dy, dAz/dy, phi~   (phi~ = phi^{n+1}; CDF-2: the mean
+ *        of phi^{n+3/2} and phi^{n+1/2}, Sec. 4.1) */
+#define PIC_FIELD_J 0
+#define PIC_FIELD_MESH 1
+pic_status_t pic_get_field(pic_ctx_t ctx, int32_t which, double* dst);
+
+/* Spectral field history, pic_history_fields(cfg) complex half spectra
+ * [ny][nx/2+1], newest level first within each group:
+ *   BDF-k : rho (k levels), phi (2k), A (2k levels x 3 components)
+ *   CDF-2 : rho^{n+1/2..n-3/2} (3), phi (3), A^{n..n-1} (2 x 3), J^{n..n-1} (2 x 3)
+ *   DIRK-2: rho (2), phi (2), v_phi (1), A (2 x 3), v_A (3), J^n (3)
+ * (v_phi, v_A: the time derivatives the DIRK first-order system carries.) */
+int32_t pic_history_fields(const pic_config_t* cfg);
+pic_status_t pic_get_history(pic_ctx_t ctx, double* dst);
+pic_status_t pic_set_history(pic_ctx_t ctx, const double* src);
+
+/* Diagnostics of the newest level (untimed, synchronises the stream).
+ * [host] out[PIC_DIAG_COUNT]:
+ *   0 gauge residual L2   1 gauge scale   2 Gauss residual L2   3 Gauss scale
+ *   4 total charge        5 field energy  6 particle kinetic energy
+ *   7 non-finite particle values (count)
+ * Residuals as defined per stepper in Sec. 3 (epsilon_1 and Gauss's law);
+ * L2 = sqrt(dx dy sum f^2) by Parseval.  Returns PIC_ERR_NONFINITE when
+ * out[7] > 0 (the values are still written). */
+#define PIC_DIAG_COUNT 8
+pic_status_t pic_diagnostics(pic_ctx_t ctx, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

@@ -1,0 +1,564 @@
+// Field solve on the periodic grid: R2C FFT of J, continuity, the stepper's
+// modified-Helmholtz update in Fourier space, spectral gradients and C2R FFTs.
+//
+// Paper: the update formulas of Sec. 3.1 (implicit CDF-2, Crank-Nicolson form
+// with alpha = sqrt(2)/(c dt)), Sec. 3.2 (BDF-k, L^{-1} update with C = a*a),
+// Sec. 3.3 (s-stage DIRK on the first-order system, stage operators
+// L_i = I - Laplacian/alpha_i^2, alpha_i = 1/(h a_ii c)); continuity in each
+// stepper's form (Algorithm 1, third step); spectral derivatives (Sec. 4.1).
+//
+// Data flow (x fastest in real space, complex128 spectra):
+//   J   [3][ny][nx]        real, consumed (zeroed) by k_rows_r2c
+//   T   [3][nxh][ny]       x-transformed J, transposed so columns are contiguous
+//   H   [slot][nxh][ny]    spectral history (ring slots chosen by the host)
+//   U   [8][nxh][ny]       y-inverse-transformed phi~, d_y phi~, A, d_y A
+//   F   [12][ny][nx]       real mesh fields for the gather (float64, + float32 copy)
+// Reading of the Nyquist mode (the paper is silent): the first-derivative
+// symbol is zero at index n/2 of each axis and the Laplacian is built from the
+// same symbols, so div(grad) equals the Laplacian exactly.
+#include "pic_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace pic {
+
+namespace {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 mul_i(double2 a) { return make_double2(-a.y, a.x); }      // i a
+__device__ __forceinline__ double2 mul_mi(double2 a) { return make_double2(a.y, -a.x); }     // -i a
+__device__ __forceinline__ double2 cdivr(double2 a, double r) { return make_double2(a.x / r, a.y / r); }
+
+// B independent length-N FFTs (N a power of two) held in LDS at a[f*N + j].
+// Stockham autosort, radix 4 with one radix-2 pass when log2 N is odd;
+// ping-pongs between a and b and returns the buffer holding the result.
+// tw[t] = exp(-2 pi i t / N), t < N.  INV: exp(+...) (unnormalised inverse).
+// All threads of the block must call it; the caller synchronises before.
+template <bool INV>
+__device__ double2* fft_lds(double2* a, double2* b, int N, int B, const double2* __restrict__ tw) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  int Ns = 1;
+  while (Ns < N) {
+    if (N >= 4 * Ns) {
+      const int q = N >> 2;
+      const int stride = N / (4 * Ns);
+      const int lq = __ffs(q) - 1;
+      for (int t = tid; t < B * q; t += nth) {
+        const int f = t >> lq;
+        const int j = t & (q - 1);
+        const double2* in = a + f * N;
+        double2* out = b + f * N;
+        const int k = j & (Ns - 1);
+        double2 v0 = in[j], v1 = in[j + q], v2 = in[j + 2 * q], v3 = in[j + 3 * q];
+        if (k) {
+          double2 w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
+          if (INV) { w1 = cconj(w1); w2 = cconj(w2); w3 = cconj(w3); }
+          v1 = cmul(v1, w1);
+          v2 = cmul(v2, w2);
+          v3 = cmul(v3, w3);
+        }
+        const double2 s02 = cadd(v0, v2), d02 = csub(v0, v2);
+        const double2 s13 = cadd(v1, v3), d13 = csub(v1, v3);
+        const int d = ((j - k) << 2) + k;
+        out[d] = cadd(s02, s13);
+        out[d + 2 * Ns] = csub(s02, s13);
+        if (INV) {
+          out[d + Ns] = cadd(d02, mul_i(d13));
+          out[d + 3 * Ns] = cadd(d02, mul_mi(d13));
+        } else {
+          out[d + Ns] = cadd(d02, mul_mi(d13));
+          out[d + 3 * Ns] = cadd(d02, mul_i(d13));
+        }
+      }
+      Ns <<= 2;
+    } else {
+      const int h = N >> 1;
+      const int stride = N / (2 * Ns);
+      const int lh = __ffs(h) - 1;
+      for (int t = tid; t < B * h; t += nth) {
+        const int f = t >> lh;
+        const int j = t & (h - 1);
+        const double2* in = a + f * N;
+        double2* out = b + f * N;
+        const int k = j & (Ns - 1);
+        double2 w = tw[k * stride];
+        if (INV) w = cconj(w);
+        const double2 v0 = in[j], v1 = cmul(in[j + h], w);
+        const int d = ((j - k) << 1) + k;
+        out[d] = cadd(v0, v1);
+        out[d + Ns] = csub(v0, v1);
+      }
+      Ns <<= 1;
+    }
+    __syncthreads();
+    double2* t = a;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+__device__ __forceinline__ double kx_sym(int kx, const GridP& g) {
+  return (2 * kx == g.nx) ? 0.0 : 2.0 * M_PI * kx / g.lx;
+}
+__device__ __forceinline__ double ky_sym(int ky, const GridP& g) {
+  if (2 * ky == g.ny) return 0.0;
+  const int m = (2 * ky < g.ny) ? ky : ky - g.ny;
+  return 2.0 * M_PI * m / g.ly;
+}
+
+// ---------------------------------------------------------------------------
+// rows: R real rows (R even) of one J component -> R/2 complex FFTs along x.
+__global__ void __launch_bounds__(256) k_rows_r2c(double* __restrict__ J, double2* __restrict__ T,
+                                                  const double2* __restrict__ twx, GridP g, int R) {
+  extern __shared__ double2 sm[];
+  const int N = g.nx, B = R >> 1;
+  double2* a = sm;
+  double2* b = sm + B * N;
+  const int y0 = blockIdx.x * R;
+  const int c = blockIdx.y;
+  double* Jc = J + (size_t)c * g.nx * g.ny;
+  for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
+    const int r = t / N, x = t - r * N;
+    const size_t i0 = (size_t)(y0 + 2 * r) * N + x, i1 = i0 + N;
+    a[t] = make_double2(Jc[i0], Jc[i1]);
+    Jc[i0] = 0.0;  // J is consumed: ready for the next deposit
+    Jc[i1] = 0.0;
+  }
+  __syncthreads();
+  const double2* res = fft_lds<false>(a, b, N, B, twx);
+  // split the two real transforms: X = (Z_k + conj Z_{N-k})/2, Y = (Z_k - conj Z_{N-k})/(2i)
+  for (int t = threadIdx.x; t < g.nxh * R; t += blockDim.x) {
+    const int k = t / R, rr = t - k * R, r = rr >> 1;
+    const double2 zk = res[r * N + k];
+    const double2 zn = cconj(res[r * N + ((N - k) & (N - 1))]);
+    double2 o;
+    if ((rr & 1) == 0) {
+      o = cscale(cadd(zk, zn), 0.5);
+    } else {
+      const double2 d = csub(zk, zn);
+      o = make_double2(0.5 * d.y, -0.5 * d.x);
+    }
+    T[((size_t)c * g.nxh + k) * g.ny + y0 + rr] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// columns: one block per kx.  Forward y-FFT of the three J columns, the
+// stepper's update for every ky of this column, and inverse y-FFTs of the
+// eight columns phi~, d_y phi~, A_l, d_y A_l (scaled by 1/(nx ny)).
+struct ModeOut {
+  double2 phi, A[3];
+};
+
+template <int SCHEME>
+__device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, double2 J0, double2 J1,
+                               double2 J2, double kxs, double kys, const SchemeCoef& sc,
+                               const HistSlots& hs) {
+  const double kappa = kxs * kxs + kys * kys;  // -Laplacian symbol
+  auto at = [&](int slot) -> double2& { return H[(size_t)slot * plane + m]; };
+  // i k . J
+  auto divv = [&](double2 X, double2 Y) { return mul_i(make_double2(kxs * X.x + kys * Y.x, kxs * X.y + kys * Y.y)); };
+  ModeOut o;
+  const double2 Jn1[3] = {J0, J1, J2};
+  if (SCHEME == PIC_SCHEME_BDF) {
+    const int k = sc.k;
+    // continuity: sum_j a_j rho^{n+1-j} + dt div J^{n+1} = 0
+    double2 acc = cscale(divv(J0, J1), sc.dt);
+    for (int j = 1; j <= k; ++j) acc = cadd(acc, cscale(at(hs.rho[j - 1]), sc.a[j]));
+    const double2 rho = cscale(acc, -1.0 / sc.a[0]);
+    const double Lh = 1.0 + kappa * sc.inv_alpha2;
+    double2 s = cscale(rho, sc.inv_alpha2 / sc.eps0);
+    for (int i = 1; i <= 2 * k; ++i) s = csub(s, cscale(at(hs.phi[i - 1]), sc.Cn[i]));
+    const double2 phi = cdivr(s, Lh);
+    at(hs.rho_new) = rho;
+    at(hs.phi_new) = phi;
+    o.phi = phi;
+    for (int l = 0; l < 3; ++l) {
+      double2 sa = cscale(Jn1[l], sc.mu0 * sc.inv_alpha2);
+      for (int i = 1; i <= 2 * k; ++i) sa = csub(sa, cscale(at(hs.A[i - 1] + l), sc.Cn[i]));
+      const double2 A = cdivr(sa, Lh);
+      at(hs.A_new + l) = A;
+      o.A[l] = A;
+    }
+  } else if (SCHEME == PIC_SCHEME_CDF2) {
+    const double2 rho_h = at(hs.rho[0]), rho_mh = at(hs.rho[1]);
+    const double2 rho = csub(rho_h, cscale(divv(J0, J1), sc.dt));  // rho^{n+3/2}
+    const double Lh = 1.0 + kappa * sc.inv_alpha2;
+    const double2 phi_h = at(hs.phi[0]), phi_mh = at(hs.phi[1]);
+    const double2 rhs = cadd(cscale(phi_h, 2.0), cscale(cadd(rho, rho_mh), sc.inv_alpha2 / sc.eps0));
+    const double2 phi = csub(cdivr(rhs, Lh), phi_mh);
+    at(hs.rho_new) = rho;
+    at(hs.phi_new) = phi;
+    o.phi = cscale(cadd(phi, phi_h), 0.5);
+    for (int l = 0; l < 3; ++l) {
+      const double2 An = at(hs.A[0] + l), Am = at(hs.A[1] + l), Jm = at(hs.J[1] + l);
+      const double2 r = cadd(cscale(An, 2.0), cscale(cadd(Jn1[l], Jm), sc.mu0 * sc.inv_alpha2));
+      const double2 A = csub(cdivr(r, Lh), Am);
+      at(hs.A_new + l) = A;
+      at(hs.J_new + l) = Jn1[l];
+      o.A[l] = A;
+    }
+  } else {  // DIRK-2
+    const double h = sc.dt, c2 = sc.c * sc.c;
+    double2 Jn[3], Jst[2][3];
+    for (int l = 0; l < 3; ++l) Jn[l] = at(hs.J[0] + l);
+    for (int i = 0; i < 2; ++i)
+      for (int l = 0; l < 3; ++l)
+        Jst[i][l] = cadd(cscale(Jn[l], 1.0 - sc.dirkC[i]), cscale(Jn1[l], sc.dirkC[i]));
+    const double2 rho_n = at(hs.rho[0]);
+    double2 rho = rho_n;
+    for (int i = 0; i < 2; ++i) rho = csub(rho, cscale(divv(Jst[i][0], Jst[i][1]), h * sc.dirkB[i]));
+    double2 rst[2];
+    for (int i = 0; i < 2; ++i) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
+    // one scalar wave component: (u, v)' = (v, c^2 (S + Lap u)), Lap = -kappa
+    auto advance = [&](double2& u, double2& v, const double2 S[2]) {
+      double2 ku[2], kv[2];
+      for (int i = 0; i < 2; ++i) {
+        double2 U = u, V = v;
+        for (int j = 0; j < i; ++j) {
+          U = cadd(U, cscale(ku[j], h * sc.dirkA[i][j]));
+          V = cadd(V, cscale(kv[j], h * sc.dirkA[i][j]));
+        }
+        const double hai = h * sc.dirkA[i][i];
+        const double Li = 1.0 + hai * hai * c2 * kappa;
+        const double2 src = csub(S[i], cscale(U, kappa));  // S + Lap U
+        ku[i] = cdivr(cadd(V, cscale(src, hai * c2)), Li);
+        kv[i] = cdivr(csub(cscale(src, c2), cscale(V, hai * c2 * kappa)), Li);
+      }
+      for (int i = 0; i < 2; ++i) {
+        u = cadd(u, cscale(ku[i], h * sc.dirkB[i]));
+        v = cadd(v, cscale(kv[i], h * sc.dirkB[i]));
+      }
+    };
+    double2 u = at(hs.phi[0]), v = at(hs.vphi);
+    {
+      const double2 S[2] = {cscale(rst[0], 1.0 / sc.eps0), cscale(rst[1], 1.0 / sc.eps0)};
+      advance(u, v, S);
+    }
+    at(hs.rho_new) = rho;
+    at(hs.phi_new) = u;
+    at(hs.vphi) = v;
+    o.phi = u;
+    for (int l = 0; l < 3; ++l) {
+      double2 ua = at(hs.A[0] + l), va = at(hs.vA + l);
+      const double2 S[2] = {cscale(Jst[0][l], sc.mu0), cscale(Jst[1][l], sc.mu0)};
+      advance(ua, va, S);
+      at(hs.A_new + l) = ua;
+      at(hs.vA + l) = va;
+      at(hs.J[0] + l) = Jn1[l];
+      o.A[l] = ua;
+    }
+  }
+  return o;
+}
+
+template <int SCHEME>
+__global__ void __launch_bounds__(256) k_columns(const double2* __restrict__ T, double2* __restrict__ H,
+                                                 double2* __restrict__ U, const double2* __restrict__ twy,
+                                                 GridP g, SchemeCoef sc, HistSlots hs) {
+  extern __shared__ double2 sm[];  // 8 N
+  const int N = g.ny, kx = blockIdx.x;
+  const size_t plane = (size_t)g.nxh * g.ny;
+  for (int t = threadIdx.x; t < 3 * N; t += blockDim.x) {
+    const int c = t / N, y = t - c * N;
+    sm[t] = T[((size_t)c * g.nxh + kx) * N + y];
+  }
+  __syncthreads();
+  const double2* Jh = fft_lds<false>(sm, sm + 3 * N, N, 3, twy);
+  double2* store = sm + 4 * N;  // phi~, A0, A1, A2 (scaled); see the note on aliasing below
+  const double kxs = kx_sym(kx, g);
+  const double scale = 1.0 / ((double)g.nx * g.ny);
+  for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
+    // each ky is owned by one thread, which reads its three J values before it
+    // writes its four outputs, so the partial overlap of `store` with the
+    // second FFT buffer never crosses threads
+    const double2 J0 = Jh[ky], J1 = Jh[N + ky], J2 = Jh[2 * N + ky];
+    const ModeOut o = mode_update<SCHEME>(H, plane, (size_t)kx * N + ky, J0, J1, J2, kxs,
+                                          ky_sym(ky, g), sc, hs);
+    store[ky] = cscale(o.phi, scale);
+    store[N + ky] = cscale(o.A[0], scale);
+    store[2 * N + ky] = cscale(o.A[1], scale);
+    store[3 * N + ky] = cscale(o.A[2], scale);
+  }
+  __syncthreads();
+  // eight outputs G0..G7 = phi~, d_y phi~, Ax, Ay, Az, d_y Ax, d_y Ay, d_y Az in four batches of two
+  const int src[8] = {0, 0, 1, 2, 3, 1, 2, 3};
+  for (int bb = 0; bb < 4; ++bb) {
+    for (int t = threadIdx.x; t < 2 * N; t += blockDim.x) {
+      const int f = 2 * bb + (t >= N ? 1 : 0), ky = t - (t >= N ? N : 0);
+      double2 v = store[src[f] * N + ky];
+      if (f == 1 || f >= 5) v = mul_i(cscale(v, ky_sym(ky, g)));
+      sm[t] = v;
+    }
+    __syncthreads();
+    const double2* res = fft_lds<true>(sm, sm + 2 * N, N, 2, twy);
+    for (int t = threadIdx.x; t < 2 * N; t += blockDim.x) {
+      const int f = 2 * bb + (t >= N ? 1 : 0), y = t - (t >= N ? N : 0);
+      U[((size_t)f * g.nxh + kx) * N + y] = res[t];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// rows C2R: R rows of one output pair (two real fields from one complex FFT).
+// Pair p of the 12 mesh fields and the U column (and whether it is multiplied
+// by i kx) each is made from:
+//   0 d_x phi = ikx G0   1 d_y phi = G1   2 Ax = G2   3 Ay = G3   4 Az = G4
+//   5 d_x Ax = ikx G2    6 d_x Ay = ikx G3   7 d_x Az = ikx G4
+//   8 d_y Ax = G5        9 d_y Ay = G6      10 d_y Az = G7     11 phi~ = G0
+__constant__ int kSrcG[12] = {0, 1, 2, 3, 4, 2, 3, 4, 5, 6, 7, 0};
+__constant__ int kMulKx[12] = {1, 0, 0, 0, 0, 1, 1, 1, 0, 0, 0, 0};
+
+__global__ void __launch_bounds__(256) k_rows_c2r(const double2* __restrict__ U, double* __restrict__ F64,
+                                                  float* __restrict__ F32, const double2* __restrict__ twx,
+                                                  GridP g, int R) {
+  extern __shared__ double2 sm[];
+  const int N = g.nx, h = N >> 1;
+  double2* a = sm;
+  double2* b = sm + R * N;
+  const int y0 = blockIdx.x * R;
+  const int s0 = 2 * blockIdx.y, s1 = s0 + 1;
+  const int g0 = kSrcG[s0], g1 = kSrcG[s1];
+  for (int t = threadIdx.x; t < g.nxh * R; t += blockDim.x) {
+    const int k = t / R, r = t - k * R;
+    const double kxs = 2.0 * M_PI * k / g.lx * ((k == h) ? 0.0 : 1.0);
+    double2 X = U[((size_t)g0 * g.nxh + k) * g.ny + y0 + r];
+    double2 Y = U[((size_t)g1 * g.nxh + k) * g.ny + y0 + r];
+    if (kMulKx[s0]) X = mul_i(cscale(X, kxs));
+    if (kMulKx[s1]) Y = mul_i(cscale(Y, kxs));
+    if (k == 0 || k == h) {  // real-signal spectrum: these bins are real
+      X.y = 0.0;
+      Y.y = 0.0;
+    }
+    a[r * N + k] = cadd(X, mul_i(Y));
+    if (k > 0 && k < h) a[r * N + N - k] = cadd(cconj(X), mul_i(cconj(Y)));
+  }
+  __syncthreads();
+  const double2* res = fft_lds<true>(a, b, N, R, twx);
+  const size_t plane = (size_t)g.nx * g.ny;
+  for (int t = threadIdx.x; t < R * N; t += blockDim.x) {
+    const int r = t / N, x = t - r * N;
+    const size_t o = (size_t)(y0 + r) * N + x;
+    const double2 z = res[t];
+    F64[s0 * plane + o] = z.x;
+    F64[s1 * plane + o] = z.y;
+    if (F32) {
+      F32[s0 * plane + o] = (float)z.x;
+      F32[s1 * plane + o] = (float)z.y;
+    }
+  }
+}
+
+// history slot [nxh][ny] (internal) <-> [ny][nxh] (external)
+__global__ void k_hist_transpose(const double2* __restrict__ src, double2* __restrict__ dst, int nfield,
+                                 GridP g, int to_external) {
+  const size_t plane = (size_t)g.nxh * g.ny;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < plane * nfield;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const size_t f = t / plane, r = t - f * plane;
+    if (to_external) {  // r = ky*nxh + kx
+      const size_t ky = r / g.nxh, kx = r - ky * g.nxh;
+      dst[t] = src[f * plane + kx * g.ny + ky];
+    } else {  // r = kx*ny + ky
+      const size_t kx = r / g.ny, ky = r - kx * g.ny;
+      dst[t] = src[f * plane + ky * g.nxh + kx];
+    }
+  }
+}
+
+// Diagnostics over the half spectrum (one block).  Sums of w |f|^2 with
+// w = 1 on the kx = 0 and kx = nx/2 columns and 2 elsewhere (Parseval for the
+// half spectrum of a real field).
+template <int SCHEME>
+__global__ void __launch_bounds__(1024) k_field_diag(const double2* __restrict__ H, GridP g, SchemeCoef sc,
+                                                     HistSlots hs, double* __restrict__ out) {
+  __shared__ double red[6][1024];
+  const size_t plane = (size_t)g.nxh * g.ny;
+  double acc[6] = {0, 0, 0, 0, 0, 0};  // gauge, gauge_t, gauge_d, gauss, rho+divE parts, energy
+  double accr = 0, accd = 0;
+  auto at = [&](int slot, size_t m) { return H[(size_t)slot * plane + m]; };
+  for (size_t m = threadIdx.x; m < plane; m += blockDim.x) {
+    const int kx = (int)(m / g.ny), ky = (int)(m - (size_t)kx * g.ny);
+    const double kxs = kx_sym(kx, g), kys = ky_sym(ky, g);
+    const double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
+    auto divA = [&](int slot) {
+      const double2 X = at(slot, m), Y = at(slot + 1, m);
+      return mul_i(make_double2(kxs * X.x + kys * Y.x, kxs * X.y + kys * Y.y));
+    };
+    double2 gt, gd, rho, phi, E[3], A[3];
+    if (SCHEME == PIC_SCHEME_BDF) {
+      gt = make_double2(0, 0);
+      double2 dA[3] = {{0, 0}, {0, 0}, {0, 0}};
+      for (int j = 0; j <= sc.k; ++j) {
+        gt = cadd(gt, cscale(at(hs.phi[j], m), sc.a[j] / (sc.c * sc.c * sc.dt)));
+        for (int l = 0; l < 3; ++l) dA[l] = cadd(dA[l], cscale(at(hs.A[j] + l, m), sc.a[j] / sc.dt));
+      }
+      gd = divA(hs.A[0]);
+      phi = at(hs.phi[0], m);
+      rho = at(hs.rho[0], m);
+      E[0] = csub(mul_i(cscale(phi, -kxs)), dA[0]);
+      E[1] = csub(mul_i(cscale(phi, -kys)), dA[1]);
+      E[2] = cscale(dA[2], -1.0);
+      for (int l = 0; l < 3; ++l) A[l] = at(hs.A[0] + l, m);
+    } else if (SCHEME == PIC_SCHEME_CDF2) {
+      gt = cscale(csub(at(hs.phi[0], m), at(hs.phi[1], m)), 1.0 / (sc.c * sc.c * sc.dt));
+      gd = divA(hs.A[0]);
+      phi = cscale(cadd(at(hs.phi[0], m), at(hs.phi[2], m)), 0.5);
+      rho = cscale(cadd(at(hs.rho[0], m), at(hs.rho[2], m)), 0.5);
+      double2 dA[3];
+      for (int l = 0; l < 3; ++l) {
+        dA[l] = cscale(csub(at(hs.A[0] + l, m), at(hs.A[1] + l, m)), 1.0 / sc.dt);
+        A[l] = cscale(cadd(at(hs.A[0] + l, m), at(hs.A[1] + l, m)), 0.5);
+      }
+      E[0] = csub(mul_i(cscale(phi, -kxs)), dA[0]);
+      E[1] = csub(mul_i(cscale(phi, -kys)), dA[1]);
+      E[2] = cscale(dA[2], -1.0);
+    } else {
+      const double Rn = sc.dirkB[0] * (1 - sc.dirkC[0]) + sc.dirkB[1] * (1 - sc.dirkC[1]);
+      const double Rn1 = sc.dirkB[0] * sc.dirkC[0] + sc.dirkB[1] * sc.dirkC[1];
+      gt = cscale(csub(at(hs.phi[0], m), at(hs.phi[1], m)), -1.0);
+      gd = cscale(cadd(cscale(divA(hs.A[1]), Rn), cscale(divA(hs.A[0]), Rn1)), -sc.c * sc.c * sc.dt);
+      phi = at(hs.phi[0], m);
+      rho = at(hs.rho[0], m);
+      E[0] = csub(mul_i(cscale(phi, -kxs)), at(hs.vA, m));
+      E[1] = csub(mul_i(cscale(phi, -kys)), at(hs.vA + 1, m));
+      E[2] = cscale(at(hs.vA + 2, m), -1.0);
+      for (int l = 0; l < 3; ++l) A[l] = at(hs.A[0] + l, m);
+    }
+    const double2 gsum = cadd(gt, gd);
+    const double2 divE = mul_i(make_double2(kxs * E[0].x + kys * E[1].x, kxs * E[0].y + kys * E[1].y));
+    const double2 rr = cscale(rho, 1.0 / sc.eps0);
+    const double2 gauss = csub(divE, rr);
+    const double2 Bx = mul_i(cscale(A[2], kys)), By = mul_i(cscale(A[2], -kxs));
+    const double2 Bz = mul_i(make_double2(kxs * A[1].x - kys * A[0].x, kxs * A[1].y - kys * A[0].y));
+    auto n2 = [](double2 z) { return z.x * z.x + z.y * z.y; };
+    acc[0] += wgt * n2(gsum);
+    acc[1] += wgt * n2(gt);
+    acc[2] += wgt * n2(gd);
+    acc[3] += wgt * n2(gauss);
+    accr += wgt * n2(rr);
+    accd += wgt * n2(divE);
+    acc[5] += wgt * (sc.eps0 * (n2(E[0]) + n2(E[1]) + n2(E[2])) + (n2(Bx) + n2(By) + n2(Bz)) / sc.mu0);
+    if (m == 0) acc[4] = rho.x;
+  }
+  // rho and divE norms share slot 4's neighbours: pack them into the reduction
+  double vals[6] = {acc[0], acc[1], acc[2], acc[3], accr, accd};
+  double e = acc[5], ch = acc[4];
+  for (int i = 0; i < 6; ++i) red[i][threadIdx.x] = vals[i];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int i = 0; i < 6; ++i) red[i][threadIdx.x] += red[i][threadIdx.x + s];
+    __syncthreads();
+  }
+  double sums[6];
+  for (int i = 0; i < 6; ++i) sums[i] = red[i][0];
+  __syncthreads();
+  red[0][threadIdx.x] = e;
+  red[1][threadIdx.x] = ch;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double norm = g.dx * g.dy / ((double)g.nx * g.ny);  // dx dy * (1/N) sum |f^|^2
+    out[0] = sqrt(norm * sums[0]);
+    out[1] = sqrt(norm * sums[1]) + sqrt(norm * sums[2]);
+    out[2] = sqrt(norm * sums[3]);
+    out[3] = sqrt(norm * sums[4]) + sqrt(norm * sums[5]);
+    out[4] = red[1][0] * g.dx * g.dy;
+    out[5] = 0.5 * norm * red[0][0];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+
+void fft_make_twiddles(int n, double* h) {
+  for (int t = 0; t < n; ++t) {
+    const long double ang = 2.0L * 3.14159265358979323846264338327950288L * t / n;
+    h[2 * t] = (double)cosl(ang);
+    h[2 * t + 1] = (double)(-sinl(ang));
+  }
+}
+
+static int rows_r2c_R(const GridP& g) {
+  int R = 8;
+  while (R > 2 && (R > g.ny || R * g.nx > 4096)) R >>= 1;
+  return R;
+}
+static int rows_c2r_R(const GridP& g) {
+  int R = 8;
+  while (R > 1 && (R > g.ny || R * g.nx > 2048)) R >>= 1;
+  return R;
+}
+
+hipError_t launch_rows_r2c(double* J, double2* T, const double2* twx, GridP g, hipStream_t s) {
+  const int R = rows_r2c_R(g);
+  const size_t lds = (size_t)R * g.nx * sizeof(double2);
+  hipFuncSetAttribute((const void*)k_rows_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_rows_r2c, dim3(g.ny / R, 3), dim3(256), lds, s, J, T, twx, g, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_columns(const double2* T, double2* H, double2* U, const double2* twy, GridP g,
+                          SchemeCoef sc, HistSlots hs, hipStream_t s) {
+  const size_t lds = (size_t)8 * g.ny * sizeof(double2);
+  const void* fn = sc.scheme == PIC_SCHEME_BDF    ? (const void*)k_columns<PIC_SCHEME_BDF>
+                   : sc.scheme == PIC_SCHEME_CDF2 ? (const void*)k_columns<PIC_SCHEME_CDF2>
+                                                  : (const void*)k_columns<PIC_SCHEME_DIRK2>;
+  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (sc.scheme == PIC_SCHEME_BDF)
+    hipLaunchKernelGGL(k_columns<PIC_SCHEME_BDF>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs);
+  else if (sc.scheme == PIC_SCHEME_CDF2)
+    hipLaunchKernelGGL(k_columns<PIC_SCHEME_CDF2>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs);
+  else
+    hipLaunchKernelGGL(k_columns<PIC_SCHEME_DIRK2>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_c2r(const double2* U, double* F64, float* F32, const double2* twx, GridP g,
+                           hipStream_t s) {
+  const int R = rows_c2r_R(g);
+  const size_t lds = (size_t)2 * R * g.nx * sizeof(double2);
+  hipFuncSetAttribute((const void*)k_rows_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_rows_c2r, dim3(g.ny / R, 6), dim3(256), lds, s, U, F64, F32, twx, g, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_transpose(const double2* src, double2* dst, int nfield, GridP g, bool to_external,
+                                 hipStream_t s) {
+  const size_t n = (size_t)g.nxh * g.ny * nfield;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_hist_transpose, dim3(blocks), dim3(256), 0, s, src, dst, nfield, g,
+                     to_external ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_diag(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double* out,
+                             hipStream_t s) {
+  if (sc.scheme == PIC_SCHEME_BDF)
+    hipLaunchKernelGGL(k_field_diag<PIC_SCHEME_BDF>, dim3(1), dim3(1024), 0, s, H, g, sc, hs, out);
+  else if (sc.scheme == PIC_SCHEME_CDF2)
+    hipLaunchKernelGGL(k_field_diag<PIC_SCHEME_CDF2>, dim3(1), dim3(1024), 0, s, H, g, sc, hs, out);
+  else
+    hipLaunchKernelGGL(k_field_diag<PIC_SCHEME_DIRK2>, dim3(1), dim3(1024), 0, s, H, g, sc, hs, out);
+  return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,389 @@
+// Particle kernels: position update + current deposit, gather + IAEM push,
+// the fused gather/push/position/deposit pass, and particle state I/O.
+//
+// Paper: IAEM (Sec. 4.1) and Algorithm 1 (Sec. 4.2); current deposition with
+// tensor-product B-splines at x^{n+1} weighted by q v^n (Sec. 4.1, Sec. 5:
+// "J^{n+1} from x^{n+1}, v^n and q"), full order in every direction; the
+// velocity from the generalized momentum (Sec. 2.2).
+//
+// Spline (the paper cites it without printing it): nodes at i dx, centred
+// cardinal B-spline of degree DEG; a particle at xi = x/dx touches nodes
+// s .. s+DEG with the per-node weights of eval_spline below.
+#include <algorithm>
+
+#include "pic_internal.h"
+
+namespace pic {
+
+namespace {
+
+template <typename T, int DEG>
+struct Spline {
+  static constexpr int NW = DEG + 1;
+  // first node index s (may be -1 or up to n+1 before wrapping) and weights
+  __device__ __forceinline__ static void eval(T xi, int& s, T* w) {
+    if (DEG == 1) {
+      const T f = floor(xi);
+      const T d = xi - f;
+      s = (int)f;
+      w[0] = T(1) - d;
+      w[1] = d;
+    } else if (DEG == 2) {
+      const T f = floor(xi + T(0.5));
+      const T d = xi - f;  // in [-1/2, 1/2)
+      s = (int)f - 1;
+      const T a = T(0.5) - d, b = T(0.5) + d;
+      w[0] = T(0.5) * a * a;
+      w[1] = T(0.75) - d * d;
+      w[2] = T(0.5) * b * b;
+    } else {
+      const T f = floor(xi);
+      const T d = xi - f;  // in [0, 1)
+      s = (int)f - 1;
+      const T d2 = d * d, d3 = d2 * d, e = T(1) - d;
+      const T sixth = T(1) / T(6);
+      w[0] = e * e * e * sixth;
+      w[1] = (T(4) - T(6) * d2 + T(3) * d3) * sixth;
+      w[2] = (T(1) + T(3) * d + T(3) * d2 - T(3) * d3) * sixth;
+      w[3] = d3 * sixth;
+    }
+  }
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// x in (-L, 2L) -> [0, L); a value that rounds to L is set to 0
+template <typename T>
+__device__ __forceinline__ T wrapx(T x, T L) {
+  if (x < T(0)) x += L;
+  else if (x >= L) x -= L;
+  if (x >= L) x = T(0);
+  return x;
+}
+
+// node coordinates xi = x/dx, eta = y/dy inside [0, n] (NaN fails the test);
+// the stencil of such a point stays within one period of the wrap
+template <typename T>
+__device__ __forceinline__ bool in_box(T xi, T eta, const GridP& g) {
+  return xi >= T(0) && xi <= T(g.nx) && eta >= T(0) && eta <= T(g.ny);
+}
+
+template <typename T, int DEG>
+__device__ __forceinline__ void deposit_one(T x, T y, T jx, T jy, T jz, double* __restrict__ J,
+                                            const GridP& g) {
+  using S = Spline<T, DEG>;
+  const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
+  if (!in_box(xi, eta, g)) return;  // non-finite or unwrapped: touch no memory
+  int sx, sy;
+  T wx[S::NW], wy[S::NW];
+  S::eval(xi, sx, wx);
+  S::eval(eta, sy, wy);
+  const size_t plane = (size_t)g.nx * g.ny;
+#pragma unroll
+  for (int b = 0; b < S::NW; ++b) {
+    const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
+#pragma unroll
+    for (int a = 0; a < S::NW; ++a) {
+      const T w = wx[a] * wy[b];
+      const size_t o = row + wrapi(sx + a, g.nx);
+      atomicAdd(J + o, (double)(jx * w));
+      atomicAdd(J + plane + o, (double)(jy * w));
+      atomicAdd(J + 2 * plane + o, (double)(jz * w));
+    }
+  }
+}
+
+// gathered values: 0 dphi/dx, 1 dphi/dy, 2..4 A, 5..7 dA/dx, 8..10 dA/dy
+template <typename T, int DEG>
+__device__ __forceinline__ void gather_one(T x, T y, const T* __restrict__ F, const GridP& g, T* out) {
+  using S = Spline<T, DEG>;
+#pragma unroll
+  for (int f = 0; f < 11; ++f) out[f] = T(0);
+  const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
+  if (!in_box(xi, eta, g)) return;  // non-finite or unwrapped: touch no memory
+  int sx, sy;
+  T wx[S::NW], wy[S::NW];
+  S::eval(xi, sx, wx);
+  S::eval(eta, sy, wy);
+  const size_t plane = (size_t)g.nx * g.ny;
+#pragma unroll
+  for (int b = 0; b < S::NW; ++b) {
+    const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
+    T acc[11];
+#pragma unroll
+    for (int f = 0; f < 11; ++f) acc[f] = T(0);
+#pragma unroll
+    for (int a = 0; a < S::NW; ++a) {
+      const size_t o = row + wrapi(sx + a, g.nx);
+#pragma unroll
+      for (int f = 0; f < 11; ++f) acc[f] += wx[a] * F[f * plane + o];
+    }
+#pragma unroll
+    for (int f = 0; f < 11; ++f) out[f] += wy[b] * acc[f];
+  }
+}
+
+// IAEM: v* = 2 v^n - v^{n-1}; P += q dt (-grad phi + (grad A).v*) (x, y only:
+// d/dz = 0); v = c^2 u / sqrt(c^2 |u|^2 + (m c^2)^2), u = P - q A.
+template <typename T>
+__device__ __forceinline__ void push_one(const T* gv, T& Px, T& Py, T Pz, T vx, T vy, T vz, T wx, T wy,
+                                         T wz, const PhysP& ph, T& nx, T& ny, T& nz) {
+  const T q = T(ph.q), dt = T(ph.dt), c = T(ph.c), m = T(ph.m);
+  const T sx = T(2) * vx - wx, sy = T(2) * vy - wy, sz = T(2) * vz - wz;
+  const T Fx = -gv[0] + sx * gv[5] + sy * gv[6] + sz * gv[7];
+  const T Fy = -gv[1] + sx * gv[8] + sy * gv[9] + sz * gv[10];
+  Px += q * Fx * dt;
+  Py += q * Fy * dt;
+  const T ux = Px - q * gv[2], uy = Py - q * gv[3], uz = Pz - q * gv[4];
+  const T c2 = c * c, mc2 = m * c2;
+  const T inv = c2 / sqrt(c2 * (ux * ux + uy * uy + uz * uz) + mc2 * mc2);
+  nx = ux * inv;
+  ny = uy * inv;
+  nz = uz * inv;
+}
+
+template <typename T, int DEG>
+__global__ void __launch_bounds__(256) k_deposit(Parts<T> p, int64_t n, double* __restrict__ J, GridP g,
+                                                 PhysP ph) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T dt = T(ph.dt), q = T(ph.q);
+  const T vx = p.v[0][i], vy = p.v[1][i], vz = p.v[2][i];
+  const T x = wrapx<T>(p.x[i] + vx * dt, T(g.lx));
+  const T y = wrapx<T>(p.y[i] + vy * dt, T(g.ly));
+  p.x[i] = x;
+  p.y[i] = y;
+  const T s = q * T(g.inv_area);
+  deposit_one<T, DEG>(x, y, s * vx, s * vy, s * vz, J, g);
+}
+
+template <typename T, int DEG, bool FUSED>
+__global__ void __launch_bounds__(256) k_gather_push(Parts<T> p, int64_t n, const T* __restrict__ F,
+                                                     double* __restrict__ J, GridP g, PhysP ph) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T x = p.x[i], y = p.y[i];
+  T gv[11];
+  gather_one<T, DEG>(x, y, F, g, gv);
+  T Px = p.P[0][i], Py = p.P[1][i];
+  const T Pz = p.P[2][i];
+  const T vx = p.v[0][i], vy = p.v[1][i], vz = p.v[2][i];
+  const T wx = p.w[0][i], wy = p.w[1][i], wz = p.w[2][i];
+  T nx, ny, nz;
+  push_one<T>(gv, Px, Py, Pz, vx, vy, vz, wx, wy, wz, ph, nx, ny, nz);
+  p.P[0][i] = Px;
+  p.P[1][i] = Py;
+  p.w[0][i] = nx;
+  p.w[1][i] = ny;
+  p.w[2][i] = nz;
+  if (FUSED) {  // next step's position update and deposit with v^{n+1}
+    const T dt = T(ph.dt), q = T(ph.q);
+    x = wrapx<T>(x + nx * dt, T(g.lx));
+    y = wrapx<T>(y + ny * dt, T(g.ly));
+    p.x[i] = x;
+    p.y[i] = y;
+    const T s = q * T(g.inv_area);
+    deposit_one<T, DEG>(x, y, s * nx, s * ny, s * nz, J, g);
+  }
+}
+
+template <typename T>
+__global__ void k_init_particles(Parts<T> p, int64_t n, const double* __restrict__ x,
+                                 const double* __restrict__ y, const double* __restrict__ P, GridP g,
+                                 PhysP ph) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double xx = x[i] - g.lx * floor(x[i] / g.lx);
+  if (xx >= g.lx) xx = 0.0;
+  double yy = y[i] - g.ly * floor(y[i] / g.ly);
+  if (yy >= g.ly) yy = 0.0;
+  const double px = P[i], py = P[n + i], pz = P[2 * n + i];
+  const double c2 = ph.c * ph.c, mc2 = ph.m * c2;
+  const double inv = c2 / sqrt(c2 * (px * px + py * py + pz * pz) + mc2 * mc2);
+  T xt = (T)xx, yt = (T)yy;
+  if (xt >= T(g.lx)) xt = T(0);  // rounding to the particle dtype can reach L
+  if (yt >= T(g.ly)) yt = T(0);
+  p.x[i] = xt;
+  p.y[i] = yt;
+  p.P[0][i] = (T)px;
+  p.P[1][i] = (T)py;
+  p.P[2][i] = (T)pz;
+  p.v[0][i] = p.w[0][i] = (T)(px * inv);
+  p.v[1][i] = p.w[1][i] = (T)(py * inv);
+  p.v[2][i] = p.w[2][i] = (T)(pz * inv);
+  p.id[i] = (int32_t)i;
+}
+
+template <typename T>
+__global__ void k_get_particles(Parts<T> p, int64_t n, double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = p.id[i];
+  const T* src[11] = {p.x, p.y, p.P[0], p.P[1], p.P[2], p.v[0], p.v[1], p.v[2], p.w[0], p.w[1], p.w[2]};
+#pragma unroll
+  for (int k = 0; k < 11; ++k) out[k * n + o] = (double)src[k][i];
+}
+
+template <typename T>
+__global__ void k_set_particles(Parts<T> p, int64_t n, const double* __restrict__ in, GridP g) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T* dst[11] = {p.x, p.y, p.P[0], p.P[1], p.P[2], p.v[0], p.v[1], p.v[2], p.w[0], p.w[1], p.w[2]};
+#pragma unroll
+  for (int k = 2; k < 11; ++k) dst[k][i] = (T)in[k * n + i];
+  double xx = in[i] - g.lx * floor(in[i] / g.lx);
+  if (xx >= g.lx) xx = 0.0;
+  double yy = in[n + i] - g.ly * floor(in[n + i] / g.ly);
+  if (yy >= g.ly) yy = 0.0;
+  T xt = (T)xx, yt = (T)yy;
+  if (xt >= T(g.lx)) xt = T(0);  // rounding to the particle dtype can reach L
+  if (yt >= T(g.ly)) yt = T(0);
+  p.x[i] = xt;
+  p.y[i] = yt;
+  p.id[i] = (int32_t)i;
+}
+
+// kinetic energy sum (gamma - 1) m c^2 from v^n, and a count of non-finite
+// values; per-block partials in out2[2*block + {0,1}]
+template <typename T>
+__global__ void __launch_bounds__(256) k_particle_diag(Parts<T> p, int64_t n, PhysP ph, double* out2) {
+  __shared__ double s0[256], s1[256];
+  double ke = 0, bad = 0;
+  const double c2 = ph.c * ph.c;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T* src[11] = {p.x, p.y, p.P[0], p.P[1], p.P[2], p.v[0], p.v[1], p.v[2], p.w[0], p.w[1], p.w[2]};
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) fin = fin && isfinite((double)src[k][i]);
+    if (!fin) {
+      bad += 1;
+      continue;
+    }
+    const double vx = p.v[0][i], vy = p.v[1][i], vz = p.v[2][i];
+    const double b2 = (vx * vx + vy * vy + vz * vz) / c2;
+    ke += (1.0 / sqrt(1.0 - b2) - 1.0) * ph.m * c2;
+  }
+  s0[threadIdx.x] = ke;
+  s1[threadIdx.x] = bad;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      s0[threadIdx.x] += s0[threadIdx.x + s];
+      s1[threadIdx.x] += s1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out2[2 * blockIdx.x] = s0[0];
+    out2[2 * blockIdx.x + 1] = s1[0];
+  }
+}
+
+__global__ void k_fill_f64(double* p, size_t n, double v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s) {
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+  if (n) hipLaunchKernelGGL(k_fill_f64, dim3(blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_particles(int dtype, void* parts, int64_t n, const double* x, const double* y,
+                                 const double* P, GridP g, PhysP ph, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (dtype == PIC_F32)
+    hipLaunchKernelGGL(k_init_particles<float>, dim3(blocks_for(n)), dim3(256), 0, s,
+                       *(Parts<float>*)parts, n, x, y, P, g, ph);
+  else
+    hipLaunchKernelGGL(k_init_particles<double>, dim3(blocks_for(n)), dim3(256), 0, s,
+                       *(Parts<double>*)parts, n, x, y, P, g, ph);
+  return hipGetLastError();
+}
+
+#define PIC_DISPATCH_DEG(DEG_, ...)                 \
+  switch (DEG_) {                                   \
+    case 1: { constexpr int D = 1; __VA_ARGS__; } break; \
+    case 2: { constexpr int D = 2; __VA_ARGS__; } break; \
+    default: { constexpr int D = 3; __VA_ARGS__; } break; \
+  }
+
+hipError_t launch_deposit(int dtype, int degree, const void* parts, int64_t n, double* J, GridP g, PhysP ph,
+                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (dtype == PIC_F32) {
+    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_deposit<float, D>), dim3(blocks_for(n)), dim3(256), 0, s,
+                                                *(const Parts<float>*)parts, n, J, g, ph))
+  } else {
+    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_deposit<double, D>), dim3(blocks_for(n)), dim3(256), 0, s,
+                                                *(const Parts<double>*)parts, n, J, g, ph))
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_push(int dtype, int degree, const void* parts, int64_t n, const void* F, GridP g,
+                              PhysP ph, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (dtype == PIC_F32) {
+    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_gather_push<float, D, false>), dim3(blocks_for(n)), dim3(256),
+                                                0, s, *(const Parts<float>*)parts, n, (const float*)F,
+                                                (double*)nullptr, g, ph))
+  } else {
+    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_gather_push<double, D, false>), dim3(blocks_for(n)), dim3(256),
+                                                0, s, *(const Parts<double>*)parts, n, (const double*)F,
+                                                (double*)nullptr, g, ph))
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(int dtype, int degree, const void* parts, int64_t n, const void* F, double* J, GridP g,
+                        PhysP ph, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (dtype == PIC_F32) {
+    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_gather_push<float, D, true>), dim3(blocks_for(n)), dim3(256),
+                                                0, s, *(const Parts<float>*)parts, n, (const float*)F, J, g, ph))
+  } else {
+    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_gather_push<double, D, true>), dim3(blocks_for(n)), dim3(256),
+                                                0, s, *(const Parts<double>*)parts, n, (const double*)F, J, g, ph))
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_get_particles(int dtype, const void* parts, int64_t n, double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (dtype == PIC_F32)
+    hipLaunchKernelGGL(k_get_particles<float>, dim3(blocks_for(n)), dim3(256), 0, s,
+                       *(const Parts<float>*)parts, n, out);
+  else
+    hipLaunchKernelGGL(k_get_particles<double>, dim3(blocks_for(n)), dim3(256), 0, s,
+                       *(const Parts<double>*)parts, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_particles(int dtype, void* parts, int64_t n, const double* in, GridP g, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (dtype == PIC_F32)
+    hipLaunchKernelGGL(k_set_particles<float>, dim3(blocks_for(n)), dim3(256), 0, s, *(Parts<float>*)parts, n,
+                       in, g);
+  else
+    hipLaunchKernelGGL(k_set_particles<double>, dim3(blocks_for(n)), dim3(256), 0, s, *(Parts<double>*)parts, n,
+                       in, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_particle_diag(int dtype, const void* parts, int64_t n, PhysP ph, double* out2, hipStream_t s) {
+  if (dtype == PIC_F32)
+    hipLaunchKernelGGL(k_particle_diag<float>, dim3(256), dim3(256), 0, s, *(const Parts<float>*)parts, n, ph,
+                       out2);
+  else
+    hipLaunchKernelGGL(k_particle_diag<double>, dim3(256), dim3(256), 0, s, *(const Parts<double>*)parts, n, ph,
+                       out2);
+  return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,243 @@
+"""Thin ctypes binding of libpic (include/pic.h): argument marshalling only.
+
+Every step of the PIC path runs in libpic's HIP kernels; PyTorch supplies the
+device memory (workspace, particle inputs/outputs) and the HIP stream.  There
+is no fallback: if libpic.so is missing, :func:`load` raises.
+
+    ctx = Context(Config(nx=128, ny=128, lx=12.8, ly=12.8, ...), max_particles=n)
+    init_particles(ctx, x, y, P)      # float64 CUDA tensors
+    step(ctx, 10)
+    parts = get_particles(ctx)        # [11, n] float64, original order
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpic.so")
+
+PIC_ABI_VERSION = 1
+SCHEMES = {"bdf": 0, "cdf2": 1, "dirk2": 2}
+DTYPES = {"f32": 0, "f64": 1}
+FLAG_NO_SORT = 1
+FLAG_UNFUSED_STEP = 2
+FIELD_J = 0
+FIELD_MESH = 1
+DIAG_NAMES = ("gauge_l2", "gauge_scale", "gauss_l2", "gauss_scale", "charge", "energy",
+              "kinetic", "nonfinite")
+STATUS = {0: "PIC_OK", 1: "PIC_ERR_INVALID_ARG", 2: "PIC_ERR_UNSUPPORTED", 3: "PIC_ERR_WORKSPACE",
+          4: "PIC_ERR_HIP", 5: "PIC_ERR_STATE", 6: "PIC_ERR_NONFINITE"}
+
+# every entry point pic.h declares (checked by the CPU test suite)
+EXPORTS = ("pic_workspace_bytes", "pic_create", "pic_destroy", "pic_last_error",
+           "init_particles", "deposit_current", "field_solve", "gather_push", "step",
+           "pic_get_particles", "pic_set_particles", "pic_get_field", "pic_history_fields",
+           "pic_get_history", "pic_set_history", "pic_diagnostics")
+
+
+class PicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class ConfigStruct(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("spline_degree", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("scheme", ctypes.c_int32), ("bdf_order", ctypes.c_int32),
+                ("particle_dtype", ctypes.c_int32), ("sort_interval", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("c", ctypes.c_double), ("eps0", ctypes.c_double),
+                ("mu0", ctypes.c_double), ("q", ctypes.c_double), ("m", ctypes.c_double),
+                ("max_particles", ctypes.c_int64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+_lib = None
+
+
+def load():
+    """Load libpic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libpic.so not built: run python -m paper_2410_18414_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t,
+                          ctypes.c_double)
+    cfgp = ctypes.POINTER(ConfigStruct)
+    sig = {
+        "pic_workspace_bytes": (SZ, [cfgp]),
+        "pic_create": (I32, [cfgp, P, SZ, P, ctypes.POINTER(P)]),
+        "pic_destroy": (None, [P]),
+        "pic_last_error": (ctypes.c_char_p, [P]),
+        "init_particles": (I32, [P, I64, P, P, P]),
+        "deposit_current": (I32, [P]),
+        "field_solve": (I32, [P]),
+        "gather_push": (I32, [P]),
+        "step": (I32, [P, I32]),
+        "pic_get_particles": (I32, [P, P]),
+        "pic_set_particles": (I32, [P, P]),
+        "pic_get_field": (I32, [P, I32, P]),
+        "pic_history_fields": (I32, [cfgp]),
+        "pic_get_history": (I32, [P, P]),
+        "pic_set_history": (I32, [P, P]),
+        "pic_diagnostics": (I32, [P, ctypes.POINTER(D)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def make_config(nx, ny, lx, ly, dt, degree=3, scheme="bdf", bdf_order=2, dtype="f32",
+                c=1.0, eps0=1.0, mu0=1.0, q=-1.0, m=1.0, max_particles=1, flags=0,
+                sort_interval=0):
+    s = ConfigStruct()
+    s.abi_version = PIC_ABI_VERSION
+    s.nx, s.ny, s.spline_degree = nx, ny, degree
+    s.lx, s.ly = lx, ly
+    s.scheme, s.bdf_order = SCHEMES[scheme], bdf_order
+    s.particle_dtype = DTYPES[dtype]
+    s.sort_interval = sort_interval
+    s.dt, s.c, s.eps0, s.mu0, s.q, s.m = dt, c, eps0, mu0, q, m
+    s.max_particles = max_particles
+    s.flags = flags
+    return s
+
+
+def workspace_bytes(cfg):
+    n = load().pic_workspace_bytes(ctypes.byref(cfg))
+    if n == 0:
+        raise PicError(1, load().pic_last_error(None).decode())
+    return n
+
+
+def history_fields(cfg):
+    return load().pic_history_fields(ctypes.byref(cfg))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns the torch workspace tensor and the libpic context."""
+
+    def __init__(self, cfg, device="cuda", stream=None):
+        lib = load()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(cfg)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = lib.pic_create(ctypes.byref(cfg), ctypes.c_void_p(base + off), nbytes,
+                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise PicError(st, lib.pic_last_error(None).decode())
+        self.handle = h
+        self.n = 0
+
+    def check(self, st):
+        if st != 0:
+            raise PicError(st, load().pic_last_error(self.handle).decode())
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().pic_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nx(self):
+        return self.cfg.nx
+
+    @property
+    def ny(self):
+        return self.cfg.ny
+
+
+# ---------------------------------------------------------------------------
+# entry points, named as in pic.h
+
+def init_particles(ctx, x, y, P):
+    """x, y: [n] float64; P: [3, n] float64 (CUDA tensors)."""
+    n = x.numel()
+    x = x.to(ctx.device, torch.float64).contiguous()
+    y = y.to(ctx.device, torch.float64).contiguous()
+    P = P.to(ctx.device, torch.float64).contiguous()
+    assert y.numel() == n and P.numel() == 3 * n
+    ctx._inputs = (x, y, P)  # kept alive until the stream has consumed them
+    ctx.check(load().init_particles(ctx.handle, n, _ptr(x), _ptr(y), _ptr(P)))
+    ctx.n = n
+
+
+def deposit_current(ctx):
+    ctx.check(load().deposit_current(ctx.handle))
+
+
+def field_solve(ctx):
+    ctx.check(load().field_solve(ctx.handle))
+
+
+def gather_push(ctx):
+    ctx.check(load().gather_push(ctx.handle))
+
+
+def step(ctx, nsteps=1):
+    ctx.check(load().step(ctx.handle, int(nsteps)))
+
+
+def get_particles(ctx):
+    out = torch.empty((11, ctx.n), dtype=torch.float64, device=ctx.device)
+    ctx.check(load().pic_get_particles(ctx.handle, _ptr(out)))
+    return out
+
+
+def set_particles(ctx, parts):
+    parts = parts.to(ctx.device, torch.float64).contiguous()
+    assert parts.shape == (11, ctx.n)
+    ctx._inputs = (parts,)
+    ctx.check(load().pic_set_particles(ctx.handle, _ptr(parts)))
+
+
+def get_field(ctx, which):
+    nf = 3 if which == FIELD_J else 12
+    out = torch.empty((nf, ctx.ny, ctx.nx), dtype=torch.float64, device=ctx.device)
+    ctx.check(load().pic_get_field(ctx.handle, int(which), _ptr(out)))
+    return out
+
+
+def get_history(ctx):
+    nf = history_fields(ctx.cfg)
+    out = torch.empty((nf, ctx.ny, ctx.nx // 2 + 1), dtype=torch.complex128, device=ctx.device)
+    ctx.check(load().pic_get_history(ctx.handle, _ptr(out)))
+    return out
+
+
+def set_history(ctx, hist):
+    nf = history_fields(ctx.cfg)
+    hist = hist.to(ctx.device, torch.complex128).contiguous()
+    assert hist.shape == (nf, ctx.ny, ctx.nx // 2 + 1)
+    ctx._inputs = (hist,)
+    ctx.check(load().pic_set_history(ctx.handle, _ptr(hist)))
+
+
+def diagnostics(ctx, allow_nonfinite=False):
+    buf = (ctypes.c_double * 8)()
+    st = load().pic_diagnostics(ctx.handle, buf)
+    if st != 0 and not (allow_nonfinite and st == 6):
+        ctx.check(st)
+    return dict(zip(DIAG_NAMES, list(buf)))

@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports what include/pic.h declares (CPU only).
+
+Only calls that validate arguments before touching the GPU are made here.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_18414_amd import pic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pic.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b([A-Za-z_]\w*)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pic.load()
+    decl = declared_functions()
+    assert len(decl) >= 16
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(pic.EXPORTS) == decl
+
+
+def _cfg(**kw):
+    base = dict(nx=32, ny=32, lx=1.0, ly=1.0, dt=0.01, degree=2, scheme="bdf", bdf_order=1,
+                dtype="f64", max_particles=100)
+    base.update(kw)
+    return pic.make_config(**base)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=30), dict(ny=4), dict(nx=2048), dict(degree=4), dict(degree=0), dict(bdf_order=7),
+    dict(dt=0.0), dict(dt=2.0), dict(c=2.0), dict(max_particles=0), dict(m=0.0), dict(lx=-1.0)])
+def test_invalid_configs_rejected(bad):
+    cfg = _cfg(**bad)
+    assert pic.load().pic_workspace_bytes(ctypes.byref(cfg)) == 0
+    assert pic.load().pic_last_error(None)
+
+
+def test_valid_config_and_history_counts():
+    assert pic.workspace_bytes(_cfg()) > 0
+    assert pic.history_fields(_cfg(scheme="bdf", bdf_order=2)) == 18
+    assert pic.history_fields(_cfg(scheme="bdf", bdf_order=3)) == 27
+    assert pic.history_fields(_cfg(scheme="cdf2")) == 18
+    assert pic.history_fields(_cfg(scheme="dirk2")) == 17
+
+
+def test_create_rejects_bad_workspace_without_gpu():
+    lib = pic.load()
+    cfg = _cfg()
+    h = ctypes.c_void_p()
+    st = lib.pic_create(ctypes.byref(cfg), None, 0, None, ctypes.byref(h))
+    assert st == 3 and not h.value          # PIC_ERR_WORKSPACE
+    st = lib.pic_create(ctypes.byref(cfg), ctypes.c_void_p(256), 16, None, ctypes.byref(h))
+    assert st == 3 and b"too small" in lib.pic_last_error(None)
+    cfg.abi_version = 99
+    assert lib.pic_create(ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 40, None,
+                          ctypes.byref(h)) == 1
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = pic.load()
+    for name in ("deposit_current", "field_solve", "gather_push"):
+        assert getattr(lib, name)(None) == 1
+    assert lib.step(None, 1) == 1
