@@ -1,0 +1,162 @@
+"""Throughput of the full PIC step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload weibel128]
+
+One step = Algorithm 1 once over every particle: position update and current
+deposit, FFT field solve (continuity + stepper update + spectral gradients),
+gather and IAEM push (the libpic `step` entry point, gather/push of step n
+fused with the deposit of step n+1).  Inputs are resident in HBM before the
+timed region; the K timed steps are bracketed by stream synchronisations.
+
+Prints one JSON line with the particle-steps/s value, a roofline entry for the
+dominant kernel (the fused gather/push/deposit particle pass, timed with HIP
+events on the library's stream inside the timed region) and the FP64 oracle
+timed on the host on a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s per full PIC step; batched and adjoint vs plain at 1e-10 rel"
+HBM_PEAK_GBS = 8000.0
+
+# name -> (workload id in paper_2410_18414_amd.workloads, overrides, label)
+WORKLOADS = {
+    "weibel128": (2, {}, "weibel-128x128-64ppc-cubic-bdf2-f32"),
+    "weibel512-dirk2": (3, {}, "weibel-512x512-256ppc-cubic-dirk2-f32"),
+    "weibel512-cdf2": (3, {"scheme": "cdf2"}, "weibel-512x512-256ppc-cubic-cdf2-f32"),
+    "cloud32": (1, {}, "cloud-32x32-4ppc-quadratic-bdf1-f64"),
+}
+
+
+def particle_bytes(dtype):
+    """Algorithmic HBM bytes per particle of the fused pass: read x, y, P(3),
+    v^n(3), v^{n-1}(3); write x, y, Px, Py, v^{n+1}(3) (P_z is constant in 2-D)."""
+    es = 4 if dtype == "f32" else 8
+    return (11 + 7) * es
+
+
+def grid_bytes(nx, ny, dtype):
+    """Per launch: one read of the 11 gathered mesh fields (particle dtype) and
+    one read-modify-write of the three float64 J planes."""
+    es = 4 if dtype == "f32" else 8
+    return nx * ny * (11 * es + 3 * 8 * 2)
+
+
+def cpu_baseline(w, spec, nsteps):
+    """The FP64 oracle (numpy, single thread) on the same particles and grid."""
+    from oracle import pic as opic
+    p = opic.Params(w["nx"], w["ny"], w["lx"], w["ly"], spec["degree"], spec["scheme"], w["dt"],
+                    q=w["q"], m=w["m"], bdf_order=spec["bdf_order"])
+    s = opic.State(p, w["x"], w["y"], w["P"])
+    t0 = time.perf_counter()
+    s.step(nsteps)
+    dt = time.perf_counter() - t0
+    n = len(w["x"])
+    return dict(value=n * nsteps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample="%d full steps of the same %d-particle workload (numpy float64, one thread)"
+                       % (nsteps, n))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="weibel128", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--unfused", action="store_true", help="run deposit and gather/push as separate kernels")
+    ap.add_argument("--no-sort", action="store_true", help="plain global-atomic kernels, no tile sort")
+    ap.add_argument("--sort-interval", type=int, default=0)
+    ap.add_argument("--tile-cells", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--slack", type=int, default=0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_18414_amd import pic, workloads
+
+    wid, over, label = WORKLOADS[args.workload]
+    w = workloads.make(wid)
+    spec = dict(degree=w["degree"], scheme=over.get("scheme", w["scheme"]),
+                bdf_order=w["bdf_order"], dtype=w["dtype"])
+    n = len(w["x"])
+    torch.cuda.set_device(0)
+    cfg = pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=spec["degree"],
+                          scheme=spec["scheme"], bdf_order=spec["bdf_order"], dtype=spec["dtype"],
+                          q=w["q"], m=w["m"], max_particles=n,
+                          flags=(pic.FLAG_UNFUSED_STEP if args.unfused else 0)
+                          | (pic.FLAG_NO_SORT if args.no_sort else 0),
+                          sort_interval=args.sort_interval, tile_cells=args.tile_cells,
+                          chunk=args.chunk, slack=args.slack)
+    ctx = pic.Context(cfg, device="cuda:0")
+    dev = ctx.device
+    pic.init_particles(ctx, torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
+                       torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev))
+    pic.step(ctx, args.warmup)
+    torch.cuda.synchronize()
+
+    pic.set_kernel_timing(ctx, True)
+    pic.kernel_timing(ctx)  # reset
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(ctx.stream)
+    t0 = time.perf_counter()
+    pic.step(ctx, args.steps)
+    stop.record(ctx.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    kt = pic.kernel_timing(ctx)
+    pic.set_kernel_timing(ctx, False)
+    diag = pic.diagnostics(ctx)
+
+    ms_step = ms / args.steps
+    value = n * args.steps / (ms * 1e-3)
+    fused_ms, fused_n = kt["fused"]
+    if fused_n == 0:  # unfused run: deposit + gather/push stand in for the fused pass
+        fused_ms, fused_n = kt["deposit"][0] + kt["gather_push"][0], max(kt["gather_push"][1], 1)
+    avg_fused = fused_ms / max(fused_n, 1)
+    alg = n * particle_bytes(spec["dtype"]) + grid_bytes(w["nx"], w["ny"], spec["dtype"])
+    achieved = alg / (avg_fused * 1e-3) / 1e9 if avg_fused > 0 else 0.0
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel="k_gather_push<float,3,true> (fused gather/push/position/deposit)",
+                avg_launch_us=round(avg_fused * 1e3, 2),
+                algorithmic_bytes_per_launch=int(alg))
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": spec["dtype"], "data": "synthetic",
+        "config": {"workload": label, "grid": [w["nx"], w["ny"]], "particles": n,
+                   "ppc": n // (w["nx"] * w["ny"]), "spline_degree": spec["degree"],
+                   "scheme": spec["scheme"] + (str(spec["bdf_order"]) if spec["scheme"] == "bdf" else ""),
+                   "particle_dtype": spec["dtype"], "field_dtype": "f64",
+                   "parallelism": "single-gpu"},
+        "roofline": roof,
+        "kernels_ms_per_step": {k: round(v[0] / max(args.steps, 1), 5) for k, v in kt.items()},
+        "wall_s": round(wall, 4),
+        "gauge_rel": diag["gauge_l2"] / diag["gauge_scale"] if diag["gauge_scale"] else 0.0,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, spec, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,7 +85,13 @@ typedef struct {                /* [host] */
   double q, m;                  /* macro-particle charge and mass                        */
   int64_t max_particles;        /* capacity, >= 1                                        */
   uint32_t flags;               /* PIC_FLAG_*                                            */
-  int32_t reserved[7];          /* must be zero                                          */
+  int32_t tile_cells;           /* tile edge in cells for the sorted passes (power of two,
+                                   4..64, at most nx and ny); 0 = default (16)           */
+  int32_t chunk;                /* particles per workgroup of the sorted passes
+                                   (64..65536); 0 = default                              */
+  int32_t slack;                /* cells a particle may drift from its tile and still use
+                                   the tile's LDS window (1..8); 0 = default (3)         */
+  int32_t reserved[4];          /* must be zero                                          */
 } pic_config_t;
 
 /* Workspace bytes pic_create needs for cfg (0 if cfg is invalid). */
@@ -160,6 +166,17 @@ pic_status_t pic_set_history(pic_ctx_t ctx, const double* src);
  * out[7] > 0 (the values are still written). */
 #define PIC_DIAG_COUNT 8
 pic_status_t pic_diagnostics(pic_ctx_t ctx, double* out);
+
+/* Kernel timing with HIP events recorded on the context's stream around each
+ * launch group (for roofline reporting; adds an event pair per launch).
+ * Classes: 0 deposit (position update + deposit), 1 field solve (R2C rows,
+ * column update, C2R rows), 2 gather + push, 3 fused gather/push/deposit,
+ * 4 tile sort (count, scan, scatter).
+ * pic_kernel_timing synchronises the stream, writes [host] out[2*PIC_KCLASS_COUNT]
+ * = {total ms, launches} per class, and resets the counters. */
+#define PIC_KCLASS_COUNT 5
+pic_status_t pic_set_kernel_timing(pic_ctx_t ctx, int32_t enable);
+pic_status_t pic_kernel_timing(pic_ctx_t ctx, double* out);
 
 #ifdef __cplusplus
 }

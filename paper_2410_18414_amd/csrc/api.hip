@@ -1,5 +1,6 @@
 // libpic C ABI: validation, workspace layout, phase state machine and launch
 // sequencing of Algorithm 1 (arXiv 2410.18414, Sec. 4.2).
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,7 +22,9 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 inline bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 struct Layout {
-  size_t part_arrays;  // particle arrays (11 x cap x es) + ids
+  size_t part_arrays;  // two particle sets, each 11 arrays (cap x es) + ids
+  size_t set_bytes;    // bytes of one set
+  size_t tkey, tcount, tstart, tcursor, twork, tnwork;
   size_t J, T, H, U, F64, F32, twx, twy, diag, total;
   size_t plane_c;      // complex entries per spectral plane
 };
@@ -111,9 +114,45 @@ bool validate(const pic_config_t* c, std::string& msg) {
     return false;
   }
   if (c->sort_interval < 0) { msg = "sort_interval must be >= 0"; return false; }
-  for (int i = 0; i < 7; ++i)
+  if (c->tile_cells && (!pow2(c->tile_cells) || c->tile_cells < 4 || c->tile_cells > 64 ||
+                        c->tile_cells > c->nx || c->tile_cells > c->ny)) {
+    msg = "tile_cells must be 0 or a power of two in [4, 64] not above nx, ny";
+    return false;
+  }
+  if (c->chunk && (c->chunk < 64 || c->chunk > 65536)) { msg = "chunk must be 0 or in [64, 65536]"; return false; }
+  if (c->slack < 0 || c->slack > 8) { msg = "slack must be in [0, 8]"; return false; }
+  for (int i = 0; i < 4; ++i)
     if (c->reserved[i]) { msg = "reserved fields must be zero"; return false; }
   return true;
+}
+
+// Tile plan: tiles of 16x16 cells (smaller on small grids), a slack of three
+// cells, chunks of at most 1024 particles per workgroup, unless the config
+// sets them.
+TileP plan_tiles(const pic_config_t& c) {
+  TileP t{};
+  t.nx = c.nx;
+  t.ny = c.ny;
+  t.ts = c.tile_cells ? c.tile_cells : std::min(16, std::min(c.nx, c.ny));
+  t.ntx = c.nx / t.ts;
+  t.nty = c.ny / t.ts;
+  t.ntiles = t.ntx * t.nty;
+  t.log_ts = 0;
+  while ((1 << t.log_ts) < t.ts) t.log_ts++;
+  t.log_ntx = 0;
+  while ((1 << t.log_ntx) < t.ntx) t.log_ntx++;
+  t.slack = c.slack ? c.slack : 3;
+  t.win = t.ts + 2 * t.slack + 3;
+  t.win_pad = (t.win * t.win + 63) / 64 * 64;
+  t.row_lanes = 1;
+  t.log_row_lanes = 0;
+  while (t.row_lanes < t.win) {
+    t.row_lanes <<= 1;
+    t.log_row_lanes += 1;
+  }
+  t.chunk = c.chunk ? c.chunk : 1024;
+  t.max_work = t.ntiles + (int)((c.max_particles + t.chunk - 1) / t.chunk);
+  return t;
 }
 
 Layout plan(const pic_config_t& c) {
@@ -130,7 +169,15 @@ Layout plan(const pic_config_t& c) {
     o = align_up(o + bytes);
     return at;
   };
-  L.part_arrays = take(11 * align_up(cap * es) + align_up(cap * 4));
+  L.set_bytes = 11 * align_up(cap * es) + align_up(cap * 4);
+  L.part_arrays = take(2 * L.set_bytes);
+  const TileP tp = plan_tiles(c);
+  L.tkey = take(cap * 4);
+  L.tcount = take((size_t)tp.ntiles * 4);
+  L.tstart = take(((size_t)tp.ntiles + 1) * 4);
+  L.tcursor = take((size_t)tp.ntiles * 4);
+  L.twork = take((size_t)tp.max_work * 16);
+  L.tnwork = take(4);
   L.J = take(3 * plane_r * 8);
   L.T = take(3 * L.plane_c * 16);
   L.H = take((size_t)h.nslots * L.plane_c * 16);
@@ -172,14 +219,71 @@ struct pic_ctx_s {
   int64_t n = 0;
   int64_t nupd = 0;  // completed field updates (history head)
   int vflip = 0;     // which velocity block holds v^n
+  int cur = 0;       // which particle set is current
+  TileP tp{};
+  TileBufs tb{};
+  bool sorted = false;   // tiled kernels in use (no PIC_FLAG_NO_SORT)
+  int sort_every = 4;    // position updates between sorts
+  int moves = 0;         // position updates since the last sort
   Phase phase = EMPTY;
   std::string err;
   int device = 0;
 
+  // optional per-launch-group timing (pic_set_kernel_timing)
+  bool timing = false;
+  struct EvPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    int cls = 0;
+  };
+  std::vector<EvPair> ev;  // pool; the first ev_used entries hold pending pairs
+  size_t ev_used = 0;
+  double t_ms[PIC_KCLASS_COUNT] = {0};
+  double t_n[PIC_KCLASS_COUNT] = {0};
+
+  ~pic_ctx_s() {
+    for (auto& e : ev) {
+      if (e.a) hipEventDestroy(e.a);
+      if (e.b) hipEventDestroy(e.b);
+    }
+  }
+  // fold pending pairs into the totals (synchronises the stream)
+  hipError_t fold_timing() {
+    if (!ev_used) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i < ev_used; ++i) {
+      float ms = 0;
+      e = hipEventElapsedTime(&ms, ev[i].a, ev[i].b);
+      if (e != hipSuccess) return e;
+      t_ms[ev[i].cls] += ms;
+      t_n[ev[i].cls] += 1;
+    }
+    ev_used = 0;
+    return hipSuccess;
+  }
+  // returns the pair to record around a launch of class cls, or nullptr
+  EvPair* begin_timed(int cls) {
+    if (!timing) return nullptr;
+    if (ev_used == 4096 && fold_timing() != hipSuccess) return nullptr;
+    if (ev_used == ev.size()) {
+      EvPair p;
+      if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return nullptr;
+      ev.push_back(p);
+    }
+    EvPair* p = &ev[ev_used++];
+    p->cls = cls;
+    hipEventRecord(p->a, stream);
+    return p;
+  }
+  void end_timed(EvPair* p) {
+    if (p) hipEventRecord(p->b, stream);
+  }
+
   int es() const { return cfg.particle_dtype == PIC_F32 ? 4 : 8; }
   size_t cap_bytes() const { return align_up((size_t)cfg.max_particles * es()); }
-  char* arr(int k) const { return ws + L.part_arrays + (size_t)k * cap_bytes(); }
-  int32_t* ids() const { return (int32_t*)(ws + L.part_arrays + 11 * cap_bytes()); }
+  char* arr(int k, int set) const { return ws + L.part_arrays + set * L.set_bytes + (size_t)k * cap_bytes(); }
+  char* arr(int k) const { return arr(k, cur); }
+  int32_t* ids(int set) const { return (int32_t*)arr(11, set); }
   double* J() const { return (double*)(ws + L.J); }
   double2* T() const { return (double2*)(ws + L.T); }
   double2* H() const { return (double2*)(ws + L.H); }
@@ -195,17 +299,17 @@ struct pic_ctx_s {
 
   // particle pointer block in the layout of Parts<T> (same for float/double)
   template <typename T>
-  Parts<T> parts_t() const {
+  Parts<T> parts_t(int set) const {
     Parts<T> p;
-    p.x = (T*)arr(0);
-    p.y = (T*)arr(1);
-    for (int c = 0; c < 3; ++c) p.P[c] = (T*)arr(2 + c);
+    p.x = (T*)arr(0, set);
+    p.y = (T*)arr(1, set);
+    for (int c = 0; c < 3; ++c) p.P[c] = (T*)arr(2 + c, set);
     const int vb = vflip ? 8 : 5, wb = vflip ? 5 : 8;
     for (int c = 0; c < 3; ++c) {
-      p.v[c] = (T*)arr(vb + c);
-      p.w[c] = (T*)arr(wb + c);
+      p.v[c] = (T*)arr(vb + c, set);
+      p.w[c] = (T*)arr(wb + c, set);
     }
-    p.id = ids();
+    p.id = ids(set);
     return p;
   }
   // storage for either instantiation (identical layout of pointers)
@@ -215,12 +319,13 @@ struct pic_ctx_s {
       Parts<double> d;
     };
   };
-  PartsAny parts() const {
+  PartsAny parts(int set) const {
     PartsAny a;
-    if (cfg.particle_dtype == PIC_F32) a.f = parts_t<float>();
-    else a.d = parts_t<double>();
+    if (cfg.particle_dtype == PIC_F32) a.f = parts_t<float>(set);
+    else a.d = parts_t<double>(set);
     return a;
   }
+  PartsAny parts() const { return parts(cur); }
 
   HistSlots slots(int64_t s) const {
     HistSlots h{};
@@ -251,31 +356,73 @@ struct pic_ctx_s {
 
 namespace {
 
+// counting sort of the particles by tile into the other set
+pic_status_t do_sort(pic_ctx_t c) {
+  if (!c->sorted) return PIC_OK;
+  auto src = c->parts(c->cur);
+  auto dst = c->parts(c->cur ^ 1);
+  auto* t = c->begin_timed(4);
+  hipError_t e = launch_tile_sort(c->cfg.particle_dtype, &src, &dst, c->n, c->tb, c->g, c->tp, c->stream);
+  c->end_timed(t);
+  pic_status_t st = c->hip(e, "tile sort");
+  if (st) return st;
+  c->cur ^= 1;
+  c->moves = 0;
+  return PIC_OK;
+}
+
+// sort first when the next position update could carry a particle past the slack
+pic_status_t maybe_sort(pic_ctx_t c) {
+  if (c->sorted && c->moves >= c->sort_every) return do_sort(c);
+  return PIC_OK;
+}
+
 pic_status_t do_deposit(pic_ctx_t c) {
+  pic_status_t st = maybe_sort(c);
+  if (st) return st;
   auto pa = c->parts();
-  return c->hip(launch_deposit(c->cfg.particle_dtype, c->cfg.spline_degree, &pa, c->n, c->J(), c->g, c->ph,
-                               c->stream),
-                "deposit launch");
+  auto* t = c->begin_timed(0);
+  hipError_t e = c->sorted ? launch_tiled(c->cfg.particle_dtype, 0, c->cfg.spline_degree, &pa, c->tb, nullptr,
+                                          c->J(), c->g, c->ph, c->tp, c->stream)
+                           : launch_deposit(c->cfg.particle_dtype, c->cfg.spline_degree, &pa, c->n, c->J(), c->g,
+                                            c->ph, c->stream);
+  c->end_timed(t);
+  c->moves += 1;
+  return c->hip(e, "deposit launch");
 }
 
 pic_status_t do_solve(pic_ctx_t c) {
+  auto* t = c->begin_timed(1);
   pic_status_t st = c->hip(launch_rows_r2c(c->J(), c->T(), c->twx(), c->g, c->stream), "rows_r2c launch");
   if (st) return st;
   st = c->hip(launch_columns(c->T(), c->H(), c->U(), c->twy(), c->g, c->sc, c->slots(c->nupd), c->stream),
               "columns launch");
   if (st) return st;
   st = c->hip(launch_rows_c2r(c->U(), c->F64(), c->F32(), c->twx(), c->g, c->stream), "rows_c2r launch");
+  c->end_timed(t);
   if (st) return st;
   c->nupd += 1;
   return PIC_OK;
 }
 
 pic_status_t do_gather_push(pic_ctx_t c, bool fused) {
+  if (fused) {
+    pic_status_t st = maybe_sort(c);
+    if (st) return st;
+  }
   auto pa = c->parts();
-  hipError_t e = fused ? launch_fused(c->cfg.particle_dtype, c->cfg.spline_degree, &pa, c->n, c->Fgather(),
-                                      c->J(), c->g, c->ph, c->stream)
-                       : launch_gather_push(c->cfg.particle_dtype, c->cfg.spline_degree, &pa, c->n,
-                                            c->Fgather(), c->g, c->ph, c->stream);
+  auto* t = c->begin_timed(fused ? 3 : 2);
+  hipError_t e;
+  if (c->sorted)
+    e = launch_tiled(c->cfg.particle_dtype, fused ? 2 : 1, c->cfg.spline_degree, &pa, c->tb, c->Fgather(), c->J(),
+                     c->g, c->ph, c->tp, c->stream);
+  else
+    e = fused ? launch_fused(c->cfg.particle_dtype, c->cfg.spline_degree, &pa, c->n, c->Fgather(), c->J(), c->g,
+                             c->ph, c->stream)
+              : launch_gather_push(c->cfg.particle_dtype, c->cfg.spline_degree, &pa, c->n, c->Fgather(), c->g,
+                                   c->ph, c->stream);
+  c->end_timed(t);
+  if (fused) c->moves += 1;
   pic_status_t st = c->hip(e, fused ? "fused launch" : "gather_push launch");
   if (st) return st;
   c->vflip ^= 1;  // v^{n+1} was written over v^{n-1}
@@ -378,7 +525,7 @@ pic_status_t pic_create(const pic_config_t* cfg, void* workspace, size_t ws_byte
   }
   int max_lds = 0;
   hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  if ((size_t)8 * cfg->ny * 16 > (size_t)max_lds) {
+  if (columns_lds_bytes(cfg->ny) > (size_t)max_lds) {
     g_err = "ny too large for this device's LDS";
     return PIC_ERR_UNSUPPORTED;
   }
@@ -401,6 +548,21 @@ pic_status_t pic_create(const pic_config_t* cfg, void* workspace, size_t ws_byte
   g.inv_dy = 1.0 / g.dy;
   g.inv_area = 1.0 / (g.dx * g.dy);
   c->ph = PhysP{cfg->dt, cfg->q, cfg->m, cfg->c};
+  c->tp = plan_tiles(*cfg);
+  c->tb.key = (int32_t*)(c->ws + L.tkey);
+  c->tb.count = (int32_t*)(c->ws + L.tcount);
+  c->tb.start = (int32_t*)(c->ws + L.tstart);
+  c->tb.cursor = (int32_t*)(c->ws + L.tcursor);
+  c->tb.work = (int4*)(c->ws + L.twork);
+  c->tb.nwork = (int32_t*)(c->ws + L.tnwork);
+  c->sorted = (cfg->flags & PIC_FLAG_NO_SORT) == 0;
+  {
+    // a position update moves a particle by less than c dt; the window's slack
+    // absorbs sort_every updates without any particle leaving it
+    const double cells = cfg->c * cfg->dt / std::min(g.dx, g.dy);
+    const int auto_every = std::max(1, (int)std::floor(c->tp.slack / std::max(cells, 1e-300)));
+    c->sort_every = cfg->sort_interval > 0 ? cfg->sort_interval : std::min(auto_every, 64);
+  }
   SchemeCoef& sc = c->sc;
   sc.scheme = cfg->scheme;
   sc.k = cfg->scheme == PIC_SCHEME_BDF ? cfg->bdf_order : 0;
@@ -443,6 +605,14 @@ pic_status_t pic_create(const pic_config_t* cfg, void* workspace, size_t ws_byte
     delete c;
     return PIC_ERR_HIP;
   }
+  if (c->sorted) {
+    hipError_t ez = hipMemsetAsync(c->tb.count, 0, (size_t)c->tp.ntiles * 4, c->stream);
+    if (ez != hipSuccess) {
+      g_err = std::string("tile count clear: ") + hipGetErrorString(ez);
+      delete c;
+      return PIC_ERR_HIP;
+    }
+  }
   if (reset_fields(c) != PIC_OK) {
     g_err = c->err;
     delete c;
@@ -466,6 +636,8 @@ pic_status_t init_particles(pic_ctx_t c, int64_t n, const double* x, const doubl
   st = reset_fields(c);
   if (st) return st;
   c->n = n;
+  st = do_sort(c);
+  if (st) return st;
   c->phase = READY;
   return PIC_OK;
 }
@@ -537,6 +709,8 @@ pic_status_t pic_set_particles(pic_ctx_t c, const double* in) {
   pic_status_t st =
       c->hip(launch_set_particles(c->cfg.particle_dtype, &pa, c->n, in, c->g, c->stream), "set_particles");
   if (st) return st;
+  st = do_sort(c);
+  if (st) return st;
   c->phase = READY;
   return PIC_OK;
 }
@@ -597,6 +771,25 @@ pic_status_t pic_diagnostics(pic_ctx_t c, double* out) {
   out[6] = ke;
   out[7] = bad;
   return bad > 0 ? c->fail(PIC_ERR_NONFINITE, "non-finite particle values") : PIC_OK;
+}
+
+pic_status_t pic_set_kernel_timing(pic_ctx_t c, int32_t enable) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  c->timing = enable != 0;
+  return PIC_OK;
+}
+
+pic_status_t pic_kernel_timing(pic_ctx_t c, double* out) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  if (!out) return c->fail(PIC_ERR_INVALID_ARG, "out is NULL");
+  pic_status_t st = c->hip(c->fold_timing(), "kernel timing");
+  if (st) return st;
+  for (int k = 0; k < PIC_KCLASS_COUNT; ++k) {
+    out[2 * k] = c->t_ms[k];
+    out[2 * k + 1] = c->t_n[k];
+    c->t_ms[k] = c->t_n[k] = 0;
+  }
+  return PIC_OK;
 }
 
 }  // extern "C"

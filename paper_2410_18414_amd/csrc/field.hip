@@ -263,23 +263,23 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
 template <int SCHEME>
 __global__ void __launch_bounds__(256) k_columns(const double2* __restrict__ T, double2* __restrict__ H,
                                                  double2* __restrict__ U, const double2* __restrict__ twy,
-                                                 GridP g, SchemeCoef sc, HistSlots hs) {
-  extern __shared__ double2 sm[];  // 8 N
+                                                 GridP g, SchemeCoef sc, HistSlots hs, int NB) {
+  // LDS: store [0, 4N) = phi~, A0, A1, A2 (scaled); work buffers from 4N:
+  // forward 2 x 3N, inverse 2 x NB*N (NB = 8, 4 or 2 fields per batch)
+  extern __shared__ double2 sm[];
   const int N = g.ny, kx = blockIdx.x;
   const size_t plane = (size_t)g.nxh * g.ny;
+  double2* store = sm;
+  double2* wk = sm + 4 * N;
   for (int t = threadIdx.x; t < 3 * N; t += blockDim.x) {
     const int c = t / N, y = t - c * N;
-    sm[t] = T[((size_t)c * g.nxh + kx) * N + y];
+    wk[t] = T[((size_t)c * g.nxh + kx) * N + y];
   }
   __syncthreads();
-  const double2* Jh = fft_lds<false>(sm, sm + 3 * N, N, 3, twy);
-  double2* store = sm + 4 * N;  // phi~, A0, A1, A2 (scaled); see the note on aliasing below
+  const double2* Jh = fft_lds<false>(wk, wk + 3 * N, N, 3, twy);
   const double kxs = kx_sym(kx, g);
   const double scale = 1.0 / ((double)g.nx * g.ny);
   for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
-    // each ky is owned by one thread, which reads its three J values before it
-    // writes its four outputs, so the partial overlap of `store` with the
-    // second FFT buffer never crosses threads
     const double2 J0 = Jh[ky], J1 = Jh[N + ky], J2 = Jh[2 * N + ky];
     const ModeOut o = mode_update<SCHEME>(H, plane, (size_t)kx * N + ky, J0, J1, J2, kxs,
                                           ky_sym(ky, g), sc, hs);
@@ -289,20 +289,20 @@ __global__ void __launch_bounds__(256) k_columns(const double2* __restrict__ T, 
     store[3 * N + ky] = cscale(o.A[2], scale);
   }
   __syncthreads();
-  // eight outputs G0..G7 = phi~, d_y phi~, Ax, Ay, Az, d_y Ax, d_y Ay, d_y Az in four batches of two
+  // eight outputs G0..G7 = phi~, d_y phi~, Ax, Ay, Az, d_y Ax, d_y Ay, d_y Az
   const int src[8] = {0, 0, 1, 2, 3, 1, 2, 3};
-  for (int bb = 0; bb < 4; ++bb) {
-    for (int t = threadIdx.x; t < 2 * N; t += blockDim.x) {
-      const int f = 2 * bb + (t >= N ? 1 : 0), ky = t - (t >= N ? N : 0);
+  for (int f0 = 0; f0 < 8; f0 += NB) {
+    for (int t = threadIdx.x; t < NB * N; t += blockDim.x) {
+      const int q = t / N, ky = t - q * N, f = f0 + q;
       double2 v = store[src[f] * N + ky];
       if (f == 1 || f >= 5) v = mul_i(cscale(v, ky_sym(ky, g)));
-      sm[t] = v;
+      wk[t] = v;
     }
     __syncthreads();
-    const double2* res = fft_lds<true>(sm, sm + 2 * N, N, 2, twy);
-    for (int t = threadIdx.x; t < 2 * N; t += blockDim.x) {
-      const int f = 2 * bb + (t >= N ? 1 : 0), y = t - (t >= N ? N : 0);
-      U[((size_t)f * g.nxh + kx) * N + y] = res[t];
+    const double2* res = fft_lds<true>(wk, wk + NB * N, N, NB, twy);
+    for (int t = threadIdx.x; t < NB * N; t += blockDim.x) {
+      const int q = t / N, y = t - q * N;
+      U[((size_t)(f0 + q) * g.nxh + kx) * N + y] = res[t];
     }
     __syncthreads();
   }
@@ -516,19 +516,27 @@ hipError_t launch_rows_r2c(double* J, double2* T, const double2* twx, GridP g, h
   return hipGetLastError();
 }
 
+// inverse batch size of the column kernel and its LDS bytes (<= 160 KiB)
+static int columns_nb(int ny) { return ny <= 256 ? 8 : (ny <= 512 ? 4 : 2); }
+size_t columns_lds_bytes(int ny) {
+  const int nb = columns_nb(ny);
+  return (size_t)(4 + std::max(6, 2 * nb)) * ny * sizeof(double2);
+}
+
 hipError_t launch_columns(const double2* T, double2* H, double2* U, const double2* twy, GridP g,
                           SchemeCoef sc, HistSlots hs, hipStream_t s) {
-  const size_t lds = (size_t)8 * g.ny * sizeof(double2);
+  const size_t lds = columns_lds_bytes(g.ny);
+  const int nb = columns_nb(g.ny);
   const void* fn = sc.scheme == PIC_SCHEME_BDF    ? (const void*)k_columns<PIC_SCHEME_BDF>
                    : sc.scheme == PIC_SCHEME_CDF2 ? (const void*)k_columns<PIC_SCHEME_CDF2>
                                                   : (const void*)k_columns<PIC_SCHEME_DIRK2>;
   hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (sc.scheme == PIC_SCHEME_BDF)
-    hipLaunchKernelGGL(k_columns<PIC_SCHEME_BDF>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs);
+    hipLaunchKernelGGL(k_columns<PIC_SCHEME_BDF>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs, nb);
   else if (sc.scheme == PIC_SCHEME_CDF2)
-    hipLaunchKernelGGL(k_columns<PIC_SCHEME_CDF2>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs);
+    hipLaunchKernelGGL(k_columns<PIC_SCHEME_CDF2>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs, nb);
   else
-    hipLaunchKernelGGL(k_columns<PIC_SCHEME_DIRK2>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs);
+    hipLaunchKernelGGL(k_columns<PIC_SCHEME_DIRK2>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs, nb);
   return hipGetLastError();
 }
 

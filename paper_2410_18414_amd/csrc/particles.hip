@@ -11,136 +11,11 @@
 // s .. s+DEG with the per-node weights of eval_spline below.
 #include <algorithm>
 
-#include "pic_internal.h"
+#include "particle_math.h"
 
 namespace pic {
 
 namespace {
-
-template <typename T, int DEG>
-struct Spline {
-  static constexpr int NW = DEG + 1;
-  // first node index s (may be -1 or up to n+1 before wrapping) and weights
-  __device__ __forceinline__ static void eval(T xi, int& s, T* w) {
-    if (DEG == 1) {
-      const T f = floor(xi);
-      const T d = xi - f;
-      s = (int)f;
-      w[0] = T(1) - d;
-      w[1] = d;
-    } else if (DEG == 2) {
-      const T f = floor(xi + T(0.5));
-      const T d = xi - f;  // in [-1/2, 1/2)
-      s = (int)f - 1;
-      const T a = T(0.5) - d, b = T(0.5) + d;
-      w[0] = T(0.5) * a * a;
-      w[1] = T(0.75) - d * d;
-      w[2] = T(0.5) * b * b;
-    } else {
-      const T f = floor(xi);
-      const T d = xi - f;  // in [0, 1)
-      s = (int)f - 1;
-      const T d2 = d * d, d3 = d2 * d, e = T(1) - d;
-      const T sixth = T(1) / T(6);
-      w[0] = e * e * e * sixth;
-      w[1] = (T(4) - T(6) * d2 + T(3) * d3) * sixth;
-      w[2] = (T(1) + T(3) * d + T(3) * d2 - T(3) * d3) * sixth;
-      w[3] = d3 * sixth;
-    }
-  }
-};
-
-__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-// x in (-L, 2L) -> [0, L); a value that rounds to L is set to 0
-template <typename T>
-__device__ __forceinline__ T wrapx(T x, T L) {
-  if (x < T(0)) x += L;
-  else if (x >= L) x -= L;
-  if (x >= L) x = T(0);
-  return x;
-}
-
-// node coordinates xi = x/dx, eta = y/dy inside [0, n] (NaN fails the test);
-// the stencil of such a point stays within one period of the wrap
-template <typename T>
-__device__ __forceinline__ bool in_box(T xi, T eta, const GridP& g) {
-  return xi >= T(0) && xi <= T(g.nx) && eta >= T(0) && eta <= T(g.ny);
-}
-
-template <typename T, int DEG>
-__device__ __forceinline__ void deposit_one(T x, T y, T jx, T jy, T jz, double* __restrict__ J,
-                                            const GridP& g) {
-  using S = Spline<T, DEG>;
-  const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
-  if (!in_box(xi, eta, g)) return;  // non-finite or unwrapped: touch no memory
-  int sx, sy;
-  T wx[S::NW], wy[S::NW];
-  S::eval(xi, sx, wx);
-  S::eval(eta, sy, wy);
-  const size_t plane = (size_t)g.nx * g.ny;
-#pragma unroll
-  for (int b = 0; b < S::NW; ++b) {
-    const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
-#pragma unroll
-    for (int a = 0; a < S::NW; ++a) {
-      const T w = wx[a] * wy[b];
-      const size_t o = row + wrapi(sx + a, g.nx);
-      atomicAdd(J + o, (double)(jx * w));
-      atomicAdd(J + plane + o, (double)(jy * w));
-      atomicAdd(J + 2 * plane + o, (double)(jz * w));
-    }
-  }
-}
-
-// gathered values: 0 dphi/dx, 1 dphi/dy, 2..4 A, 5..7 dA/dx, 8..10 dA/dy
-template <typename T, int DEG>
-__device__ __forceinline__ void gather_one(T x, T y, const T* __restrict__ F, const GridP& g, T* out) {
-  using S = Spline<T, DEG>;
-#pragma unroll
-  for (int f = 0; f < 11; ++f) out[f] = T(0);
-  const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
-  if (!in_box(xi, eta, g)) return;  // non-finite or unwrapped: touch no memory
-  int sx, sy;
-  T wx[S::NW], wy[S::NW];
-  S::eval(xi, sx, wx);
-  S::eval(eta, sy, wy);
-  const size_t plane = (size_t)g.nx * g.ny;
-#pragma unroll
-  for (int b = 0; b < S::NW; ++b) {
-    const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
-    T acc[11];
-#pragma unroll
-    for (int f = 0; f < 11; ++f) acc[f] = T(0);
-#pragma unroll
-    for (int a = 0; a < S::NW; ++a) {
-      const size_t o = row + wrapi(sx + a, g.nx);
-#pragma unroll
-      for (int f = 0; f < 11; ++f) acc[f] += wx[a] * F[f * plane + o];
-    }
-#pragma unroll
-    for (int f = 0; f < 11; ++f) out[f] += wy[b] * acc[f];
-  }
-}
-
-// IAEM: v* = 2 v^n - v^{n-1}; P += q dt (-grad phi + (grad A).v*) (x, y only:
-// d/dz = 0); v = c^2 u / sqrt(c^2 |u|^2 + (m c^2)^2), u = P - q A.
-template <typename T>
-__device__ __forceinline__ void push_one(const T* gv, T& Px, T& Py, T Pz, T vx, T vy, T vz, T wx, T wy,
-                                         T wz, const PhysP& ph, T& nx, T& ny, T& nz) {
-  const T q = T(ph.q), dt = T(ph.dt), c = T(ph.c), m = T(ph.m);
-  const T sx = T(2) * vx - wx, sy = T(2) * vy - wy, sz = T(2) * vz - wz;
-  const T Fx = -gv[0] + sx * gv[5] + sy * gv[6] + sz * gv[7];
-  const T Fy = -gv[1] + sx * gv[8] + sy * gv[9] + sz * gv[10];
-  Px += q * Fx * dt;
-  Py += q * Fy * dt;
-  const T ux = Px - q * gv[2], uy = Py - q * gv[3], uz = Pz - q * gv[4];
-  const T c2 = c * c, mc2 = m * c2;
-  const T inv = c2 / sqrt(c2 * (ux * ux + uy * uy + uz * uz) + mc2 * mc2);
-  nx = ux * inv;
-  ny = uy * inv;
-  nz = uz * inv;
-}
 
 template <typename T, int DEG>
 __global__ void __launch_bounds__(256) k_deposit(Parts<T> p, int64_t n, double* __restrict__ J, GridP g,

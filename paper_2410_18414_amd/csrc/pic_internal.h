@@ -46,6 +46,30 @@ struct HistSlots {
   int vphi, vA, J[2], J_new;
 };
 
+// Tile decomposition for the sorted particle passes (tiles.hip)
+struct TileP {
+  int nx, ny;      // mesh nodes
+  int ts;          // tile edge in cells
+  int ntx, nty, ntiles;
+  int log_ts, log_ntx;
+  int slack;       // cells a particle may drift after the sort and stay in the window
+  int win;         // window edge in nodes: ts + 2*slack + 3
+  int win_pad;     // win*win rounded up to a multiple of 64 (LDS plane stride)
+  int row_lanes;   // power of two >= win: threads per window row in the sweeps
+  int log_row_lanes;
+  int chunk;       // max particles per workgroup
+  int max_work;    // ntiles + ceil(capacity/chunk): bound on the chunk count
+};
+
+struct TileBufs {
+  int32_t* key;     // [capacity] tile of each particle at the last sort
+  int32_t* count;   // [ntiles]   zero between sorts
+  int32_t* start;   // [ntiles+1] first particle of each tile
+  int32_t* cursor;  // [ntiles]
+  int4* work;       // [max_work] (tile, first particle, count, 0)
+  int32_t* nwork;   // [1]        chunks in use
+};
+
 struct SchemeCoef {
   int scheme, k;            // scheme id; BDF order
   double a[7];              // BDF first-derivative coefficients (step dt)
@@ -77,10 +101,18 @@ hipError_t launch_set_particles(int dtype, void* parts, int64_t n, const double*
 hipError_t launch_particle_diag(int dtype, const void* parts, int64_t n, PhysP ph,
                                 double* out2, hipStream_t s);
 
+// tiles.hip  (mode: 0 deposit, 1 gather+push, 2 fused)
+size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp);
+hipError_t launch_tile_sort(int dtype, const void* src, void* dst, int64_t n, const TileBufs& tb, GridP g,
+                            TileP tp, hipStream_t s);
+hipError_t launch_tiled(int dtype, int mode, int degree, const void* parts, const TileBufs& tb, const void* F,
+                        double* J, GridP g, PhysP ph, TileP tp, hipStream_t s);
+
 // field.hip
 size_t fft_twiddle_count(int n);
 void fft_make_twiddles(int n, double* host_re_im);    // n complex entries
 hipError_t launch_rows_r2c(double* J, double2* T, const double2* twx, GridP g, hipStream_t s);
+size_t columns_lds_bytes(int ny);
 hipError_t launch_columns(const double2* T, double2* H, double2* U, const double2* twy,
                           GridP g, SchemeCoef sc, HistSlots hs, hipStream_t s);
 hipError_t launch_rows_c2r(const double2* U, double* F64, float* F32, const double2* twx,

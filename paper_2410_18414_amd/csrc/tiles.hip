@@ -1,0 +1,391 @@
+// Tile-sorted particle passes with LDS-privatised gather and deposition.
+//
+// The grid's cells are split into tiles of TS x TS cells.  Every few steps the
+// particles are counting-sorted by the tile of their position (k_tile_count,
+// k_tile_scan, k_tile_scatter), and the scan cuts each tile's particle range
+// into chunks of at most CH particles: one chunk per workgroup.
+//
+// A workgroup owns a window of W x W mesh nodes around its tile: the tile's
+// TS cells, a slack of S cells on each side (particles drift after the sort),
+// and the widest stencil reach (one node below, two above the cell).  It
+// copies the eleven gathered fields of the window into LDS, node-interleaved,
+// gathers from there, accumulates its J contributions in an LDS window, and
+// adds that window to the global float64 J with one atomic per non-zero node
+// component.  A particle whose stencil leaves the window (it drifted further
+// than S cells since the sort) takes the global-memory path for that
+// operation, so results never depend on the sort.
+//
+// The per-particle arithmetic (spline weights, IAEM push, position update) is
+// shared with the untiled kernels through particle_math.h.
+#include "particle_math.h"
+
+namespace pic {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// tile of a position (cells floor(xi), clamped into the grid)
+__device__ __forceinline__ int tile_of(float xi, float eta, const TileP& tp) {
+  int cx = (int)floorf(xi), cy = (int)floorf(eta);
+  cx = cx < 0 ? 0 : (cx >= tp.nx ? tp.nx - 1 : cx);
+  cy = cy < 0 ? 0 : (cy >= tp.ny ? tp.ny - 1 : cy);
+  return (cy >> tp.log_ts) * tp.ntx + (cx >> tp.log_ts);
+}
+
+// Lanes of one wave that share a key: one LDS atomic per distinct key in the
+// wave (particles are nearly sorted between sorts, so a wave holds few keys).
+// Returns the lane's rank among the wave's lanes with its key, and the value
+// the group's atomic returned (the group's base) broadcast to the group.
+__device__ __forceinline__ int wave_group_add(int32_t* __restrict__ counters, int key, bool active, int& rank) {
+  const int lane = threadIdx.x & 63;
+  uint64_t pending = __ballot(active);
+  int base = 0;
+  rank = 0;
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int k0 = __shfl(key, leader);
+    const uint64_t grp = __ballot(active && key == k0);
+    int b = 0;
+    if (lane == leader) b = atomicAdd(&counters[k0], __popcll(grp));
+    b = __shfl(b, leader);
+    if (active && key == k0) {
+      base = b;
+      rank = __popcll(grp & ((1ull << lane) - 1ull));
+    }
+    pending &= ~grp;
+  }
+  return base;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_tile_count(Parts<T> p, int64_t n, int32_t* __restrict__ key,
+                                                         int32_t* __restrict__ count, GridP g, TileP tp) {
+  extern __shared__ int32_t hist[];  // ntiles
+  for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x) hist[t] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nloop = (n + stride - 1) / stride * stride;  // whole waves stay in the loop
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nloop; i += stride) {
+    const bool act = i < n;
+    int t = 0;
+    if (act) {
+      const float xi = (float)(p.x[i] * T(g.inv_dx)), eta = (float)(p.y[i] * T(g.inv_dy));
+      const bool ok = xi == xi && eta == eta;  // non-finite positions go to tile 0
+      t = ok ? tile_of(xi, eta, tp) : 0;
+      key[i] = t;
+    }
+    int r;
+    wave_group_add(hist, t, act, r);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x)
+    if (hist[t]) atomicAdd(&count[t], hist[t]);
+}
+
+// one block: exclusive scan of the tile counts, cursors, and the chunk list
+__global__ void __launch_bounds__(1024) k_tile_scan(int32_t* __restrict__ count, int32_t* __restrict__ start,
+                                                    int32_t* __restrict__ cursor, int4* __restrict__ work,
+                                                    int32_t* __restrict__ nwork, TileP tp) {
+  __shared__ int32_t s_cnt[1024], s_chk[1024];
+  __shared__ int32_t carry_p, carry_c;
+  if (threadIdx.x == 0) {
+    carry_p = 0;
+    carry_c = 0;
+  }
+  __syncthreads();
+  for (int base = 0; base < tp.ntiles; base += 1024) {
+    const int t = base + threadIdx.x;
+    const int c = t < tp.ntiles ? count[t] : 0;
+    const int k = (c + tp.chunk - 1) / tp.chunk;
+    s_cnt[threadIdx.x] = c;
+    s_chk[threadIdx.x] = k;
+    __syncthreads();
+    // Hillis-Steele inclusive scans
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int a = threadIdx.x >= off ? s_cnt[threadIdx.x - off] : 0;
+      const int b = threadIdx.x >= off ? s_chk[threadIdx.x - off] : 0;
+      __syncthreads();
+      s_cnt[threadIdx.x] += a;
+      s_chk[threadIdx.x] += b;
+      __syncthreads();
+    }
+    const int p0 = carry_p + s_cnt[threadIdx.x] - c;  // exclusive
+    const int k0 = carry_c + s_chk[threadIdx.x] - k;
+    if (t < tp.ntiles) {
+      start[t] = p0;
+      cursor[t] = p0;
+      for (int j = 0; j < k; ++j) {
+        const int s = p0 + j * tp.chunk;
+        const int e = min(p0 + c, s + tp.chunk);
+        work[k0 + j] = make_int4(t, s, e - s, 0);
+      }
+      count[t] = 0;  // ready for the next sort
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) {
+      carry_p += s_cnt[1023];
+      carry_c += s_chk[1023];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    start[tp.ntiles] = carry_p;
+    *nwork = carry_c;
+  }
+}
+
+// scatter into the other particle set; one global atomic per (block, tile)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_tile_scatter(Parts<T> src, Parts<T> dst, int64_t n,
+                                                           const int32_t* __restrict__ key,
+                                                           int32_t* __restrict__ cursor, TileP tp) {
+  extern __shared__ int32_t sh[];  // ntiles local counts, then ntiles bases
+  int32_t* lc = sh;
+  int32_t* lb = sh + tp.ntiles;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x) lc[t] = 0;
+  __syncthreads();
+  const bool act = i < n;
+  const int k = act ? key[i] : 0;
+  int rr;
+  const int r = wave_group_add(lc, k, act, rr) + rr;
+  __syncthreads();
+  for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x)
+    lb[t] = lc[t] ? atomicAdd(&cursor[t], lc[t]) : 0;
+  __syncthreads();
+  if (i < n) {
+    const int64_t o = lb[k] + r;
+    dst.x[o] = src.x[i];
+    dst.y[o] = src.y[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      dst.P[c][o] = src.P[c][i];
+      dst.v[c][o] = src.v[c][i];
+      dst.w[c][o] = src.w[c][i];
+    }
+    dst.id[o] = src.id[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the tiled particle pass
+
+enum { MODE_DEPOSIT = 0, MODE_GATHER_PUSH = 1, MODE_FUSED = 2 };
+
+// LDS accumulator of the deposit: float64 for both particle precisions.  On
+// gfx950 the LDS float64 add (ds_add_f64) sustains several times the rate of
+// the float32 add, and it keeps the per-tile partial sums exact to float64.
+template <typename T>
+struct Acc {
+  using type = double;
+};
+
+template <typename T, int DEG, int MODE>
+__global__ void __launch_bounds__(kThreads) k_tiled(Parts<T> p, const int4* __restrict__ work,
+                                                    const int32_t* __restrict__ nwork, const T* __restrict__ F,
+                                                    double* __restrict__ J, GridP g, PhysP ph, TileP tp) {
+  constexpr bool GATHER = MODE != MODE_DEPOSIT;
+  constexpr bool DEPOSIT = MODE != MODE_GATHER_PUSH;
+  using A = typename Acc<T>::type;
+  if ((int)blockIdx.x >= *nwork) return;
+  const int4 it = work[blockIdx.x];
+  const int W = tp.win;
+  const int WP = tp.win_pad;  // plane stride of the LDS windows (field f at f*WP)
+  const int tiy = it.x >> tp.log_ntx, tix = it.x - (tiy << tp.log_ntx);
+  const int ox = tix * tp.ts - tp.slack - 1, oy = tiy * tp.ts - tp.slack - 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* fw = reinterpret_cast<T*>(smem);
+  A* jw = reinterpret_cast<A*>(smem + (GATHER ? (size_t)11 * WP * sizeof(T) : 0));
+  const size_t plane = (size_t)g.nx * g.ny;
+  // window sweeps without integer division: lanes of a row-group cover x
+  // (tp.row_lanes >= W, a power of two), row-groups cover y
+  const int rl = tp.row_lanes, lrl = tp.log_row_lanes;
+  const int wi = threadIdx.x & (rl - 1), wj0 = threadIdx.x >> lrl, wjs = blockDim.x >> lrl;
+  const int gxw = (ox + wi) & (g.nx - 1);
+  if (GATHER && wi < W) {
+    for (int j = wj0; j < W; j += wjs) {
+      const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
+      const int node = j * W + wi;
+#pragma unroll
+      for (int f = 0; f < 11; ++f) fw[f * WP + node] = F[f * plane + go];
+    }
+  }
+  if (DEPOSIT)
+    for (int idx = threadIdx.x; idx < 3 * WP; idx += blockDim.x) jw[idx] = A(0);
+  __syncthreads();
+
+  using S = Spline<T, DEG>;
+  const T dt = T(ph.dt), qs = T(ph.q) * T(g.inv_area);
+  for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
+    const int64_t i = it.y + k;
+    T x = p.x[i], y = p.y[i];
+    T vx = p.v[0][i], vy = p.v[1][i], vz = p.v[2][i];
+    if (GATHER) {
+      T gv[11];
+#pragma unroll
+      for (int f = 0; f < 11; ++f) gv[f] = T(0);
+      const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
+      if (in_box(xi, eta, g)) {
+        int sx, sy;
+        T wx[S::NW], wy[S::NW];
+        S::eval(xi, sx, wx);
+        S::eval(eta, sy, wy);
+        const int lx = (sx - ox) & (g.nx - 1), ly = (sy - oy) & (g.ny - 1);
+        if (lx + DEG < W && ly + DEG < W) {
+#pragma unroll
+          for (int b = 0; b < S::NW; ++b) {
+#pragma unroll
+            for (int a = 0; a < S::NW; ++a) {
+              const T w = wx[a] * wy[b];
+              const T* nd = fw + (ly + b) * W + lx + a;
+#pragma unroll
+              for (int f = 0; f < 11; ++f) gv[f] += w * nd[f * WP];
+            }
+          }
+        } else {
+          gather_global<T, DEG>(sx, sy, wx, wy, F, g, gv);
+        }
+      }
+      T Px = p.P[0][i], Py = p.P[1][i];
+      const T Pz = p.P[2][i];
+      const T wx0 = p.w[0][i], wy0 = p.w[1][i], wz0 = p.w[2][i];
+      T nvx, nvy, nvz;
+      push_one<T>(gv, Px, Py, Pz, vx, vy, vz, wx0, wy0, wz0, ph, nvx, nvy, nvz);
+      p.P[0][i] = Px;
+      p.P[1][i] = Py;
+      p.w[0][i] = nvx;
+      p.w[1][i] = nvy;
+      p.w[2][i] = nvz;
+      vx = nvx;
+      vy = nvy;
+      vz = nvz;
+    }
+    if (DEPOSIT) {
+      x = wrapx<T>(x + vx * dt, T(g.lx));
+      y = wrapx<T>(y + vy * dt, T(g.ly));
+      p.x[i] = x;
+      p.y[i] = y;
+      const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
+      if (in_box(xi, eta, g)) {
+        int sx, sy;
+        T wx[S::NW], wy[S::NW];
+        S::eval(xi, sx, wx);
+        S::eval(eta, sy, wy);
+        const T jx = qs * vx, jy = qs * vy, jz = qs * vz;
+        const int lx = (sx - ox) & (g.nx - 1), ly = (sy - oy) & (g.ny - 1);
+        if (lx + DEG < W && ly + DEG < W) {
+#pragma unroll
+          for (int b = 0; b < S::NW; ++b) {
+#pragma unroll
+            for (int a = 0; a < S::NW; ++a) {
+              const T w = wx[a] * wy[b];
+              A* nd = jw + (ly + b) * W + lx + a;
+              atomicAdd(nd, A(jx * w));
+              atomicAdd(nd + WP, A(jy * w));
+              atomicAdd(nd + 2 * WP, A(jz * w));
+            }
+          }
+        } else {
+          deposit_global<T, DEG>(sx, sy, wx, wy, jx, jy, jz, J, g);
+        }
+      }
+    }
+  }
+  if (DEPOSIT) {
+    __syncthreads();
+    if (wi < W) {
+      for (int j = wj0; j < W; j += wjs) {
+        const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
+        const int node = j * W + wi;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const A v = jw[c * WP + node];
+          if (v != A(0)) atomicAdd(J + c * plane + go, (double)v);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int DEG, int MODE>
+size_t tiled_lds(const TileP& tp) {
+  return (MODE != MODE_DEPOSIT ? (size_t)11 * tp.win_pad * sizeof(T) : 0) +
+         (MODE != MODE_GATHER_PUSH ? (size_t)3 * tp.win_pad * sizeof(typename Acc<T>::type) : 0);
+}
+
+template <typename T, int DEG, int MODE>
+hipError_t launch_tiled_t(const Parts<T>& p, const TileBufs& tb, const T* F, double* J, GridP g, PhysP ph,
+                          TileP tp, hipStream_t s) {
+  const size_t lds = tiled_lds<T, DEG, MODE>(tp);
+  hipFuncSetAttribute((const void*)k_tiled<T, DEG, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_tiled<T, DEG, MODE>), dim3(tp.max_work), dim3(kThreads), lds, s, p, tb.work, tb.nwork, F,
+                     J, g, ph, tp);
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+hipError_t launch_tiled_deg(int degree, const Parts<T>& p, const TileBufs& tb, const T* F, double* J, GridP g,
+                            PhysP ph, TileP tp, hipStream_t s) {
+  switch (degree) {
+    case 1: return launch_tiled_t<T, 1, MODE>(p, tb, F, J, g, ph, tp, s);
+    case 2: return launch_tiled_t<T, 2, MODE>(p, tb, F, J, g, ph, tp, s);
+    default: return launch_tiled_t<T, 3, MODE>(p, tb, F, J, g, ph, tp, s);
+  }
+}
+
+template <typename T>
+hipError_t launch_tiled_mode(int mode, int degree, const Parts<T>& p, const TileBufs& tb, const T* F, double* J,
+                             GridP g, PhysP ph, TileP tp, hipStream_t s) {
+  switch (mode) {
+    case MODE_DEPOSIT: return launch_tiled_deg<T, MODE_DEPOSIT>(degree, p, tb, F, J, g, ph, tp, s);
+    case MODE_GATHER_PUSH: return launch_tiled_deg<T, MODE_GATHER_PUSH>(degree, p, tb, F, J, g, ph, tp, s);
+    default: return launch_tiled_deg<T, MODE_FUSED>(degree, p, tb, F, J, g, ph, tp, s);
+  }
+}
+
+}  // namespace
+
+size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp) {
+  const size_t es = dtype == PIC_F32 ? 4 : 8;
+  return (mode != MODE_DEPOSIT ? (size_t)11 * tp.win_pad * es : 0) +
+         (mode != MODE_GATHER_PUSH ? (size_t)3 * tp.win_pad * 8 : 0);
+}
+
+hipError_t launch_tile_sort(int dtype, const void* src, void* dst, int64_t n, const TileBufs& tb, GridP g, TileP tp,
+                            hipStream_t s) {
+  if (n == 0) {
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, tb.count, tb.start, tb.cursor, tb.work, tb.nwork,
+                       tp);
+    return hipGetLastError();
+  }
+  const int blocks = (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 1024);
+  const size_t lds1 = (size_t)tp.ntiles * sizeof(int32_t);
+  const unsigned sblocks = (unsigned)((n + kThreads - 1) / kThreads);
+  if (dtype == PIC_F32) {
+    hipLaunchKernelGGL(k_tile_count<float>, dim3(blocks), dim3(kThreads), lds1, s, *(const Parts<float>*)src, n,
+                       tb.key, tb.count, g, tp);
+  } else {
+    hipLaunchKernelGGL(k_tile_count<double>, dim3(blocks), dim3(kThreads), lds1, s, *(const Parts<double>*)src, n,
+                       tb.key, tb.count, g, tp);
+  }
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, tb.count, tb.start, tb.cursor, tb.work, tb.nwork, tp);
+  if (dtype == PIC_F32) {
+    hipLaunchKernelGGL(k_tile_scatter<float>, dim3(sblocks), dim3(kThreads), 2 * lds1, s, *(const Parts<float>*)src,
+                       *(Parts<float>*)dst, n, tb.key, tb.cursor, tp);
+  } else {
+    hipLaunchKernelGGL(k_tile_scatter<double>, dim3(sblocks), dim3(kThreads), 2 * lds1, s,
+                       *(const Parts<double>*)src, *(Parts<double>*)dst, n, tb.key, tb.cursor, tp);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tiled(int dtype, int mode, int degree, const void* parts, const TileBufs& tb, const void* F,
+                        double* J, GridP g, PhysP ph, TileP tp, hipStream_t s) {
+  if (dtype == PIC_F32)
+    return launch_tiled_mode<float>(mode, degree, *(const Parts<float>*)parts, tb, (const float*)F, J, g, ph, tp, s);
+  return launch_tiled_mode<double>(mode, degree, *(const Parts<double>*)parts, tb, (const double*)F, J, g, ph, tp,
+                                   s);
+}
+
+}  // namespace pic

@@ -34,7 +34,9 @@ STATUS = {0: "PIC_OK", 1: "PIC_ERR_INVALID_ARG", 2: "PIC_ERR_UNSUPPORTED", 3: "P
 EXPORTS = ("pic_workspace_bytes", "pic_create", "pic_destroy", "pic_last_error",
            "init_particles", "deposit_current", "field_solve", "gather_push", "step",
            "pic_get_particles", "pic_set_particles", "pic_get_field", "pic_history_fields",
-           "pic_get_history", "pic_set_history", "pic_diagnostics")
+           "pic_get_history", "pic_set_history", "pic_diagnostics", "pic_set_kernel_timing",
+           "pic_kernel_timing")
+KCLASSES = ("deposit", "field_solve", "gather_push", "fused", "sort")
 
 
 class PicError(RuntimeError):
@@ -51,7 +53,8 @@ class ConfigStruct(ctypes.Structure):
                 ("dt", ctypes.c_double), ("c", ctypes.c_double), ("eps0", ctypes.c_double),
                 ("mu0", ctypes.c_double), ("q", ctypes.c_double), ("m", ctypes.c_double),
                 ("max_particles", ctypes.c_int64), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("tile_cells", ctypes.c_int32), ("chunk", ctypes.c_int32), ("slack", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 _lib = None
@@ -85,6 +88,8 @@ def load():
         "pic_get_history": (I32, [P, P]),
         "pic_set_history": (I32, [P, P]),
         "pic_diagnostics": (I32, [P, ctypes.POINTER(D)]),
+        "pic_set_kernel_timing": (I32, [P, I32]),
+        "pic_kernel_timing": (I32, [P, ctypes.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -96,7 +101,7 @@ def load():
 
 def make_config(nx, ny, lx, ly, dt, degree=3, scheme="bdf", bdf_order=2, dtype="f32",
                 c=1.0, eps0=1.0, mu0=1.0, q=-1.0, m=1.0, max_particles=1, flags=0,
-                sort_interval=0):
+                sort_interval=0, tile_cells=0, chunk=0, slack=0):
     s = ConfigStruct()
     s.abi_version = PIC_ABI_VERSION
     s.nx, s.ny, s.spline_degree = nx, ny, degree
@@ -107,6 +112,7 @@ def make_config(nx, ny, lx, ly, dt, degree=3, scheme="bdf", bdf_order=2, dtype="
     s.dt, s.c, s.eps0, s.mu0, s.q, s.m = dt, c, eps0, mu0, q, m
     s.max_particles = max_particles
     s.flags = flags
+    s.tile_cells, s.chunk, s.slack = tile_cells, chunk, slack
     return s
 
 
@@ -241,3 +247,14 @@ def diagnostics(ctx, allow_nonfinite=False):
     if st != 0 and not (allow_nonfinite and st == 6):
         ctx.check(st)
     return dict(zip(DIAG_NAMES, list(buf)))
+
+
+def set_kernel_timing(ctx, enable=True):
+    ctx.check(load().pic_set_kernel_timing(ctx.handle, 1 if enable else 0))
+
+
+def kernel_timing(ctx):
+    """{class: (total ms, launches)} since the last call (synchronises)."""
+    buf = (ctypes.c_double * (2 * len(KCLASSES)))()
+    ctx.check(load().pic_kernel_timing(ctx.handle, buf))
+    return {k: (buf[2 * i], int(buf[2 * i + 1])) for i, k in enumerate(KCLASSES)}

@@ -113,6 +113,31 @@ def test_fused_step_equals_unfused(gpu_lib):
         assert rel(pa[key], pb[key]) <= 1e-12, key
 
 
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_tiled_equals_untiled(gpu_lib, dtype, tol):
+    """The tile-sorted LDS path and the plain global-atomic path agree."""
+    w = weibel_small(nx=64, ny=32, ppc=9, seed=6)
+    a = make_gpu(w, 3, "bdf", dtype, bdf_order=2)
+    b = make_gpu(w, 3, "bdf", dtype, bdf_order=2, flags=pic.FLAG_NO_SORT)
+    pic.step(a, 10)
+    pic.step(b, 10)
+    pa, pb = gpu_parts(a), gpu_parts(b)
+    for key in pa:
+        assert rel(pa[key], pb[key]) <= tol, (key, rel(pa[key], pb[key]))
+
+
+def test_drift_beyond_slack_uses_global_path(gpu_lib):
+    """A fast drift with a long sort interval moves particles out of their tile
+    window; results must not change."""
+    w = workloads.cloud(nx=32, ny=32, ppc=6, seed=8, drift=3.0, vth=0.2)
+    o = make_oracle(w, 3, "bdf", 2)
+    ctx = make_gpu(w, 3, "bdf", "f64", bdf_order=2, sort_interval=40)
+    o.step(30)
+    pic.step(ctx, 30)
+    errs, bad = compare_particles(gpu_parts(ctx), o.part, w["lx"], w["ly"], 1e-10)
+    assert not bad, errs
+
+
 @pytest.mark.parametrize("scheme,k", [("bdf", 2), ("cdf2", 2), ("dirk2", 2)])
 def test_f32_step_from_oracle_state(gpu_lib, scheme, k):
     """float32: run the oracle 8 steps, load its state into the GPU, compare one step."""
