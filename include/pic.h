@@ -167,6 +167,25 @@ pic_status_t pic_set_history(pic_ctx_t ctx, const double* src);
 #define PIC_DIAG_COUNT 8
 pic_status_t pic_diagnostics(pic_ctx_t ctx, double* out);
 
+/* ---- Ensembles (batched instances) ----------------------------------------
+ * A context may hold ninst independent instances of the method: the ensemble
+ * of SURVEY-style uneven workloads (different grids, particle counts, time
+ * steps).  They must share scheme, bdf_order, particle_dtype, spline_degree,
+ * flags and c, eps0, mu0.  Every hot-path kernel then covers all instances in
+ * one launch per phase (a flattened grid), and the instances advance in
+ * lockstep: deposit_current, field_solve, gather_push, step and step_batched
+ * act on all of them.  init_particles, pic_get/set_particles, pic_get_field,
+ * pic_get/set_history and pic_diagnostics act on the instance chosen with
+ * pic_select_instance (0 after creation).  In an ensemble, every instance is
+ * loaded with init_particles before the first step. */
+size_t pic_batch_workspace_bytes(const pic_config_t* cfgs, int32_t ninst);
+pic_status_t pic_batch_create(const pic_config_t* cfgs, int32_t ninst, void* workspace, size_t ws_bytes,
+                              void* hip_stream, pic_ctx_t* out);
+int32_t pic_instance_count(pic_ctx_t ctx);
+pic_status_t pic_select_instance(pic_ctx_t ctx, int32_t index);
+/* nsteps complete steps of every instance (the same as step()). */
+pic_status_t step_batched(pic_ctx_t ctx, int32_t nsteps);
+
 /* Kernel timing with HIP events recorded on the context's stream around each
  * launch group (for roofline reporting; adds an event pair per launch).
  * Classes: 0 deposit (position update + deposit), 1 field solve (R2C rows,

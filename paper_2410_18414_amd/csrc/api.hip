@@ -1,5 +1,10 @@
 // libpic C ABI: validation, workspace layout, phase state machine and launch
 // sequencing of Algorithm 1 (arXiv 2410.18414, Sec. 4.2).
+//
+// A context holds one or more instances of the method (an ensemble); every
+// hot-path kernel is launched once per phase over a flattened grid covering
+// all instances, which advance in lockstep.  The plain API is a context of one
+// instance.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -20,14 +25,7 @@ enum Phase { EMPTY = 0, READY = 1, DEPOSITED = 2, SOLVED = 3 };
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 inline bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-
-struct Layout {
-  size_t part_arrays;  // two particle sets, each 11 arrays (cap x es) + ids
-  size_t set_bytes;    // bytes of one set
-  size_t tkey, tcount, tstart, tcursor, twork, tnwork;
-  size_t J, T, H, U, F64, F32, twx, twy, diag, total;
-  size_t plane_c;      // complex entries per spectral plane
-};
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // History groups: ring sizes and slot bases.  A ring of R levels for a field
 // of `width` components occupies R*width consecutive slots; level j of the
@@ -80,6 +78,21 @@ Hist plan_history(const pic_config_t& c) {
   return h;
 }
 
+HistSlots slots_of(const Hist& r, int64_t s) {
+  HistSlots h{};
+  for (int j = 0; j < r.rho.size && j < 6; ++j) h.rho[j] = r.rho.slot(s, j);
+  h.rho_new = r.rho.slot(s + 1, 0);
+  for (int j = 0; j < r.phi.size && j < 12; ++j) h.phi[j] = r.phi.slot(s, j);
+  h.phi_new = r.phi.slot(s + 1, 0);
+  for (int j = 0; j < r.A.size && j < 12; ++j) h.A[j] = r.A.slot(s, j);
+  h.A_new = r.A.slot(s + 1, 0);
+  h.vphi = r.vphi.base;
+  h.vA = r.vA.base;
+  for (int j = 0; j < r.J.size && j < 2; ++j) h.J[j] = r.J.slot(s, j);
+  h.J_new = r.J.slot(s + 1, 0);
+  return h;
+}
+
 bool validate(const pic_config_t* c, std::string& msg) {
   if (!c) { msg = "cfg is NULL"; return false; }
   if (c->abi_version != PIC_ABI_VERSION) { msg = "abi_version mismatch"; return false; }
@@ -126,6 +139,18 @@ bool validate(const pic_config_t* c, std::string& msg) {
   return true;
 }
 
+// instances of one context must share the method (stepper, order, precision,
+// spline, flags, c/eps0/mu0); grids, particle counts and time steps may differ
+bool compatible(const pic_config_t& a, const pic_config_t& b, std::string& msg) {
+  if (a.scheme != b.scheme || (a.scheme == PIC_SCHEME_BDF && a.bdf_order != b.bdf_order) ||
+      a.particle_dtype != b.particle_dtype || a.spline_degree != b.spline_degree || a.flags != b.flags ||
+      a.c != b.c || a.eps0 != b.eps0 || a.mu0 != b.mu0) {
+    msg = "ensemble instances must share scheme, bdf_order, particle_dtype, spline_degree, flags, c, eps0, mu0";
+    return false;
+  }
+  return true;
+}
+
 // Tile plan: tiles of 16x16 cells (smaller on small grids), a slack of three
 // cells, chunks of at most 1024 particles per workgroup, unless the config
 // sets them.
@@ -151,11 +176,17 @@ TileP plan_tiles(const pic_config_t& c) {
     t.log_row_lanes += 1;
   }
   t.chunk = c.chunk ? c.chunk : 1024;
-  t.max_work = t.ntiles + (int)((c.max_particles + t.chunk - 1) / t.chunk);
+  t.max_work = t.ntiles + ceil_div(c.max_particles, t.chunk);
   return t;
 }
 
-Layout plan(const pic_config_t& c) {
+struct Layout {
+  size_t set_bytes;  // one particle set: 11 arrays (cap x es) + ids
+  size_t parts, J, T, H, U, F64, F32, twx, twy, tcount, tstart, tcursor, twork, tnwork, total;
+  size_t plane_c;    // complex entries per spectral plane
+};
+
+Layout plan_instance(const pic_config_t& c) {
   Layout L{};
   const size_t es = c.particle_dtype == PIC_F32 ? 4 : 8;
   const size_t cap = (size_t)c.max_particles;
@@ -163,6 +194,7 @@ Layout plan(const pic_config_t& c) {
   const size_t plane_r = (size_t)c.nx * c.ny;
   L.plane_c = nxh * c.ny;
   const Hist h = plan_history(c);
+  const TileP tp = plan_tiles(c);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -170,14 +202,7 @@ Layout plan(const pic_config_t& c) {
     return at;
   };
   L.set_bytes = 11 * align_up(cap * es) + align_up(cap * 4);
-  L.part_arrays = take(2 * L.set_bytes);
-  const TileP tp = plan_tiles(c);
-  L.tkey = take(cap * 4);
-  L.tcount = take((size_t)tp.ntiles * 4);
-  L.tstart = take(((size_t)tp.ntiles + 1) * 4);
-  L.tcursor = take((size_t)tp.ntiles * 4);
-  L.twork = take((size_t)tp.max_work * 16);
-  L.tnwork = take(4);
+  L.parts = take(2 * L.set_bytes);
   L.J = take(3 * plane_r * 8);
   L.T = take(3 * L.plane_c * 16);
   L.H = take((size_t)h.nslots * L.plane_c * 16);
@@ -186,9 +211,23 @@ Layout plan(const pic_config_t& c) {
   L.F32 = c.particle_dtype == PIC_F32 ? take(12 * plane_r * 4) : 0;
   L.twx = take((size_t)c.nx * 16);
   L.twy = take((size_t)c.ny * 16);
-  L.diag = take((16 + 2 * 256) * 8);
+  L.tcount = take((size_t)tp.ntiles * 4);
+  L.tstart = take(((size_t)tp.ntiles + 1) * 4);
+  L.tcursor = take((size_t)tp.ntiles * 4);
+  L.twork = take((size_t)tp.max_work * 16);
+  L.tnwork = take(4);
   L.total = o;
   return L;
+}
+
+// context-level buffers ahead of the instances: descriptors and diagnostics
+constexpr size_t kDiagDoubles = 16 + 2 * 256;
+size_t head_bytes(int ninst) { return align_up(ninst * sizeof(InstDesc)) + align_up(kDiagDoubles * 8); }
+
+size_t total_bytes(const pic_config_t* cfgs, int ninst) {
+  size_t t = head_bytes(ninst);
+  for (int i = 0; i < ninst; ++i) t += plan_instance(cfgs[i]).total;
+  return t;
 }
 
 // BDF-k first-derivative coefficients by differentiating the Lagrange
@@ -205,29 +244,68 @@ void bdf_coefficients(int k, double* a) {
   }
 }
 
+SchemeCoef make_scheme(const pic_config_t& c) {
+  SchemeCoef sc{};
+  sc.scheme = c.scheme;
+  sc.k = c.scheme == PIC_SCHEME_BDF ? c.bdf_order : 0;
+  sc.dt = c.dt;
+  sc.c = c.c;
+  sc.eps0 = c.eps0;
+  sc.mu0 = c.mu0;
+  if (c.scheme == PIC_SCHEME_BDF) {
+    // Sec. 3.2: C = a*a; alpha = a_0/(c dt) so that the solve divides by C_0
+    bdf_coefficients(sc.k, sc.a);
+    double C[13] = {0};
+    for (int i = 0; i <= sc.k; ++i)
+      for (int j = 0; j <= sc.k; ++j) C[i + j] += sc.a[i] * sc.a[j];
+    for (int i = 0; i <= 2 * sc.k; ++i) sc.Cn[i] = C[i] / C[0];
+    const double alpha = sc.a[0] / (c.c * c.dt);
+    sc.inv_alpha2 = 1.0 / (alpha * alpha);
+  } else if (c.scheme == PIC_SCHEME_CDF2) {
+    sc.inv_alpha2 = 0.5 * c.c * c.c * c.dt * c.dt;  // alpha = sqrt(2)/(c dt), Sec. 3.1
+  } else {
+    // Qin-Zhang two-stage symplectic DIRK (the printed tableau in Sec. 5 is
+    // garbled; this is the consistent second-order, |R(i theta)| = 1 scheme)
+    sc.dirkA[0][0] = 0.25;
+    sc.dirkA[0][1] = 0.0;
+    sc.dirkA[1][0] = 0.5;
+    sc.dirkA[1][1] = 0.25;
+    sc.dirkB[0] = sc.dirkB[1] = 0.5;
+    sc.dirkC[0] = 0.25;
+    sc.dirkC[1] = 0.75;
+  }
+  return sc;
+}
+
+struct Instance {
+  pic_config_t cfg{};
+  Layout L{};
+  size_t off = 0;  // byte offset of the instance region in the workspace
+  InstDesc d{};    // host copy of the device descriptor
+};
+
 }  // namespace
 
 struct pic_ctx_s {
-  pic_config_t cfg{};
+  std::vector<Instance> inst;
+  int sel = 0;  // instance addressed by the per-instance entry points
   hipStream_t stream = nullptr;
   char* ws = nullptr;
-  Layout L{};
   Hist hist{};
-  GridP g{};
-  PhysP ph{};
-  SchemeCoef sc{};
-  int64_t n = 0;
+  InstDesc* d_desc = nullptr;
+  double* d_diag = nullptr;
+  int nblk[BK_NKINDS] = {0};
+  size_t lds_r2c = 0, lds_c2r = 0, lds_col = 0, lds_tiled[3] = {0, 0, 0}, lds_count = 0, lds_scatter = 0;
+  int dtype = 0, degree = 3, scheme = 0;
+  bool sorted = true;
+  int sort_every = 4;
   int64_t nupd = 0;  // completed field updates (history head)
-  int vflip = 0;     // which velocity block holds v^n
-  int cur = 0;       // which particle set is current
-  TileP tp{};
-  TileBufs tb{};
-  bool sorted = false;   // tiled kernels in use (no PIC_FLAG_NO_SORT)
-  int sort_every = 4;    // position updates between sorts
-  int moves = 0;         // position updates since the last sort
+  int vflip = 0;     // 0: V0 holds v^n; 1: V1 holds v^n
+  int cur = 0;       // current particle set
+  int moves = 0;     // position updates since the last sort
+  bool stepped = false;
   Phase phase = EMPTY;
   std::string err;
-  int device = 0;
 
   // optional per-launch-group timing (pic_set_kernel_timing)
   bool timing = false;
@@ -246,6 +324,10 @@ struct pic_ctx_s {
       if (e.b) hipEventDestroy(e.b);
     }
   }
+  int ninst() const { return (int)inst.size(); }
+  Instance& I() { return inst[sel]; }
+  StepArgs sargs() const { return StepArgs{cur, vflip}; }
+
   // fold pending pairs into the totals (synchronises the stream)
   hipError_t fold_timing() {
     if (!ev_used) return hipSuccess;
@@ -279,70 +361,6 @@ struct pic_ctx_s {
     if (p) hipEventRecord(p->b, stream);
   }
 
-  int es() const { return cfg.particle_dtype == PIC_F32 ? 4 : 8; }
-  size_t cap_bytes() const { return align_up((size_t)cfg.max_particles * es()); }
-  char* arr(int k, int set) const { return ws + L.part_arrays + set * L.set_bytes + (size_t)k * cap_bytes(); }
-  char* arr(int k) const { return arr(k, cur); }
-  int32_t* ids(int set) const { return (int32_t*)arr(11, set); }
-  double* J() const { return (double*)(ws + L.J); }
-  double2* T() const { return (double2*)(ws + L.T); }
-  double2* H() const { return (double2*)(ws + L.H); }
-  double2* U() const { return (double2*)(ws + L.U); }
-  double* F64() const { return (double*)(ws + L.F64); }
-  float* F32() const { return cfg.particle_dtype == PIC_F32 ? (float*)(ws + L.F32) : nullptr; }
-  const void* Fgather() const {
-    return cfg.particle_dtype == PIC_F32 ? (const void*)F32() : (const void*)F64();
-  }
-  double2* twx() const { return (double2*)(ws + L.twx); }
-  double2* twy() const { return (double2*)(ws + L.twy); }
-  double* diag() const { return (double*)(ws + L.diag); }
-
-  // particle pointer block in the layout of Parts<T> (same for float/double)
-  template <typename T>
-  Parts<T> parts_t(int set) const {
-    Parts<T> p;
-    p.x = (T*)arr(0, set);
-    p.y = (T*)arr(1, set);
-    for (int c = 0; c < 3; ++c) p.P[c] = (T*)arr(2 + c, set);
-    const int vb = vflip ? 8 : 5, wb = vflip ? 5 : 8;
-    for (int c = 0; c < 3; ++c) {
-      p.v[c] = (T*)arr(vb + c, set);
-      p.w[c] = (T*)arr(wb + c, set);
-    }
-    p.id = ids(set);
-    return p;
-  }
-  // storage for either instantiation (identical layout of pointers)
-  struct PartsAny {
-    union {
-      Parts<float> f;
-      Parts<double> d;
-    };
-  };
-  PartsAny parts(int set) const {
-    PartsAny a;
-    if (cfg.particle_dtype == PIC_F32) a.f = parts_t<float>(set);
-    else a.d = parts_t<double>(set);
-    return a;
-  }
-  PartsAny parts() const { return parts(cur); }
-
-  HistSlots slots(int64_t s) const {
-    HistSlots h{};
-    const Hist& r = hist;
-    for (int j = 0; j < r.rho.size && j < 6; ++j) h.rho[j] = r.rho.slot(s, j);
-    h.rho_new = r.rho.slot(s + 1, 0);
-    for (int j = 0; j < r.phi.size && j < 12; ++j) h.phi[j] = r.phi.slot(s, j);
-    h.phi_new = r.phi.slot(s + 1, 0);
-    for (int j = 0; j < r.A.size && j < 12; ++j) h.A[j] = r.A.slot(s, j);
-    h.A_new = r.A.slot(s + 1, 0);
-    h.vphi = r.vphi.base;
-    h.vA = r.vA.base;
-    for (int j = 0; j < r.J.size && j < 2; ++j) h.J[j] = r.J.slot(s, j);
-    h.J_new = r.J.slot(s + 1, 0);
-    return h;
-  }
-
   pic_status_t fail(pic_status_t st, const std::string& m) {
     err = m;
     return st;
@@ -352,17 +370,24 @@ struct pic_ctx_s {
     err = std::string(what) + ": " + hipGetErrorString(e);
     return PIC_ERR_HIP;
   }
+  // upload the host descriptors (synchronises the stream; not on the step path)
+  pic_status_t upload_desc() {
+    std::vector<InstDesc> h(inst.size());
+    for (size_t i = 0; i < inst.size(); ++i) h[i] = inst[i].d;
+    hipError_t e = hipMemcpyAsync(d_desc, h.data(), h.size() * sizeof(InstDesc), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    return hip(e, "descriptor upload");
+  }
 };
 
 namespace {
 
-// counting sort of the particles by tile into the other set
+// counting sort of every instance's particles by tile into the other set
 pic_status_t do_sort(pic_ctx_t c) {
   if (!c->sorted) return PIC_OK;
-  auto src = c->parts(c->cur);
-  auto dst = c->parts(c->cur ^ 1);
   auto* t = c->begin_timed(4);
-  hipError_t e = launch_tile_sort(c->cfg.particle_dtype, &src, &dst, c->n, c->tb, c->g, c->tp, c->stream);
+  hipError_t e = launch_tile_sort(c->dtype, c->d_desc, c->ninst(), c->nblk[BK_COUNT], c->nblk[BK_PART], c->lds_count,
+                                  c->lds_scatter, c->cur, c->stream);
   c->end_timed(t);
   pic_status_t st = c->hip(e, "tile sort");
   if (st) return st;
@@ -377,72 +402,215 @@ pic_status_t maybe_sort(pic_ctx_t c) {
   return PIC_OK;
 }
 
-pic_status_t do_deposit(pic_ctx_t c) {
-  pic_status_t st = maybe_sort(c);
-  if (st) return st;
-  auto pa = c->parts();
-  auto* t = c->begin_timed(0);
-  hipError_t e = c->sorted ? launch_tiled(c->cfg.particle_dtype, 0, c->cfg.spline_degree, &pa, c->tb, nullptr,
-                                          c->J(), c->g, c->ph, c->tp, c->stream)
-                           : launch_deposit(c->cfg.particle_dtype, c->cfg.spline_degree, &pa, c->n, c->J(), c->g,
-                                            c->ph, c->stream);
+// mode: 0 deposit, 1 gather + push, 2 fused
+pic_status_t particle_pass(pic_ctx_t c, int mode) {
+  // the phases start with a deposit, so a sort due after loading happens there
+  if (mode != 1) {
+    pic_status_t st = maybe_sort(c);
+    if (st) return st;
+  }
+  static const int cls[3] = {0, 2, 3};
+  auto* t = c->begin_timed(cls[mode]);
+  hipError_t e = c->sorted ? launch_tiled(c->dtype, mode, c->degree, c->d_desc, c->ninst(), c->nblk[BK_WORK],
+                                          c->lds_tiled[mode], c->sargs(), c->stream)
+                           : launch_untiled(c->dtype, mode, c->degree, c->d_desc, c->ninst(), c->nblk[BK_PART],
+                                            c->sargs(), c->stream);
   c->end_timed(t);
-  c->moves += 1;
-  return c->hip(e, "deposit launch");
+  pic_status_t st = c->hip(e, "particle pass");
+  if (st) return st;
+  if (mode != 1) c->moves += 1;
+  if (mode != 0) c->vflip ^= 1;  // v^{n+1} was written over v^{n-1}
+  c->stepped = true;
+  return PIC_OK;
 }
 
 pic_status_t do_solve(pic_ctx_t c) {
   auto* t = c->begin_timed(1);
-  pic_status_t st = c->hip(launch_rows_r2c(c->J(), c->T(), c->twx(), c->g, c->stream), "rows_r2c launch");
-  if (st) return st;
-  st = c->hip(launch_columns(c->T(), c->H(), c->U(), c->twy(), c->g, c->sc, c->slots(c->nupd), c->stream),
-              "columns launch");
-  if (st) return st;
-  st = c->hip(launch_rows_c2r(c->U(), c->F64(), c->F32(), c->twx(), c->g, c->stream), "rows_c2r launch");
+  const int ni = c->ninst();
+  pic_status_t st = c->hip(launch_rows_r2c(c->d_desc, ni, c->nblk[BK_R2C], c->lds_r2c, c->stream), "rows_r2c");
+  if (!st)
+    st = c->hip(launch_columns(c->scheme, c->d_desc, ni, c->nblk[BK_COL], c->lds_col, slots_of(c->hist, c->nupd),
+                               c->stream),
+                "columns");
+  if (!st) st = c->hip(launch_rows_c2r(c->d_desc, ni, c->nblk[BK_C2R], c->lds_c2r, c->stream), "rows_c2r");
   c->end_timed(t);
   if (st) return st;
   c->nupd += 1;
+  c->stepped = true;
   return PIC_OK;
 }
 
-pic_status_t do_gather_push(pic_ctx_t c, bool fused) {
-  if (fused) {
-    pic_status_t st = maybe_sort(c);
-    if (st) return st;
-  }
-  auto pa = c->parts();
-  auto* t = c->begin_timed(fused ? 3 : 2);
-  hipError_t e;
-  if (c->sorted)
-    e = launch_tiled(c->cfg.particle_dtype, fused ? 2 : 1, c->cfg.spline_degree, &pa, c->tb, c->Fgather(), c->J(),
-                     c->g, c->ph, c->tp, c->stream);
-  else
-    e = fused ? launch_fused(c->cfg.particle_dtype, c->cfg.spline_degree, &pa, c->n, c->Fgather(), c->J(), c->g,
-                             c->ph, c->stream)
-              : launch_gather_push(c->cfg.particle_dtype, c->cfg.spline_degree, &pa, c->n, c->Fgather(), c->g,
-                                   c->ph, c->stream);
-  c->end_timed(t);
-  if (fused) c->moves += 1;
-  pic_status_t st = c->hip(e, fused ? "fused launch" : "gather_push launch");
-  if (st) return st;
-  c->vflip ^= 1;  // v^{n+1} was written over v^{n-1}
-  return PIC_OK;
-}
-
-pic_status_t reset_fields(pic_ctx_t c) {
-  pic_status_t st = c->hip(launch_fill_f64((double*)c->H(), (size_t)c->hist.nslots * c->L.plane_c * 2, 0.0,
-                                           c->stream),
+pic_status_t reset_fields(pic_ctx_t c, Instance& in) {
+  const InstDesc& d = in.d;
+  pic_status_t st = c->hip(launch_fill_f64((double*)d.H, (size_t)c->hist.nslots * in.L.plane_c * 2, 0.0, c->stream),
                            "history fill");
   if (st) return st;
-  st = c->hip(launch_fill_f64(c->J(), (size_t)3 * c->cfg.nx * c->cfg.ny, 0.0, c->stream), "J fill");
-  if (st) return st;
-  c->nupd = 0;
+  return c->hip(launch_fill_f64(d.J, (size_t)3 * in.cfg.nx * in.cfg.ny, 0.0, c->stream), "J fill");
+}
+
+struct PartsAny {
+  union {
+    Parts<float> f;
+    Parts<double> d;
+  };
+};
+PartsAny parts_of(pic_ctx_t c, const InstDesc& d, int set) {
+  PartsAny a;
+  if (c->dtype == PIC_F32) a.f = make_parts<float>(d, set, c->vflip);
+  else a.d = make_parts<double>(d, set, c->vflip);
+  return a;
+}
+
+pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t ws_bytes, void* hip_stream,
+                    pic_ctx_t* out) {
+  std::string m;
+  if (!out) {
+    g_err = "out is NULL";
+    return PIC_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  if (!cfgs || ninst < 1 || ninst > 4096) {
+    g_err = "need 1..4096 configs";
+    return PIC_ERR_INVALID_ARG;
+  }
+  for (int i = 0; i < ninst; ++i) {
+    if (!validate(&cfgs[i], m) || !compatible(cfgs[0], cfgs[i], m)) {
+      g_err = ninst > 1 ? "instance " + std::to_string(i) + ": " + m : m;
+      return PIC_ERR_INVALID_ARG;
+    }
+  }
+  const size_t need = total_bytes(cfgs, ninst);
+  if (!workspace || ((uintptr_t)workspace & (kAlign - 1))) {
+    g_err = "workspace must be a 256-byte aligned device pointer";
+    return PIC_ERR_WORKSPACE;
+  }
+  if (ws_bytes < need) {
+    g_err = "workspace too small: need " + std::to_string(need) + " bytes";
+    return PIC_ERR_WORKSPACE;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    g_err = "hipGetDevice failed";
+    return PIC_ERR_HIP;
+  }
+  int max_lds = 0;
+  hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  auto* c = new pic_ctx_s();
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace;
+  c->hist = plan_history(cfgs[0]);
+  c->dtype = cfgs[0].particle_dtype;
+  c->degree = cfgs[0].spline_degree;
+  c->scheme = cfgs[0].scheme;
+  c->sorted = (cfgs[0].flags & PIC_FLAG_NO_SORT) == 0;
+  c->d_desc = (InstDesc*)c->ws;
+  c->d_diag = (double*)(c->ws + align_up(ninst * sizeof(InstDesc)));
+  c->inst.resize(ninst);
+  size_t off = head_bytes(ninst);
+  int every = 64;
+  std::vector<double> tw;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < ninst && e == hipSuccess; ++i) {
+    Instance& in = c->inst[i];
+    const pic_config_t& cf = cfgs[i];
+    in.cfg = cf;
+    in.L = plan_instance(cf);
+    in.off = off;
+    off += in.L.total;
+    char* b = c->ws + in.off;
+    InstDesc& d = in.d;
+    GridP& g = d.g;
+    g.nx = cf.nx;
+    g.ny = cf.ny;
+    g.nxh = cf.nx / 2 + 1;
+    g.lx = cf.lx;
+    g.ly = cf.ly;
+    g.dx = cf.lx / cf.nx;
+    g.dy = cf.ly / cf.ny;
+    g.inv_dx = 1.0 / g.dx;
+    g.inv_dy = 1.0 / g.dy;
+    g.inv_area = 1.0 / (g.dx * g.dy);
+    d.ph = PhysP{cf.dt, cf.q, cf.m, cf.c};
+    d.tp = plan_tiles(cf);
+    d.sc = make_scheme(cf);
+    const size_t es = cf.particle_dtype == PIC_F32 ? 4 : 8;
+    const size_t cb = align_up((size_t)cf.max_particles * es);
+    for (int s = 0; s < 2; ++s) {
+      char* sb = b + in.L.parts + s * in.L.set_bytes;
+      for (int k = 0; k < 11; ++k) d.set[s][k] = sb + k * cb;
+      d.ids[s] = (int32_t*)(sb + 11 * cb);
+    }
+    d.J = (double*)(b + in.L.J);
+    d.T = (double2*)(b + in.L.T);
+    d.H = (double2*)(b + in.L.H);
+    d.U = (double2*)(b + in.L.U);
+    d.F64 = (double*)(b + in.L.F64);
+    d.F32 = cf.particle_dtype == PIC_F32 ? (float*)(b + in.L.F32) : nullptr;
+    d.twx = (const double2*)(b + in.L.twx);
+    d.twy = (const double2*)(b + in.L.twy);
+    d.tb.count = (int32_t*)(b + in.L.tcount);
+    d.tb.start = (int32_t*)(b + in.L.tstart);
+    d.tb.cursor = (int32_t*)(b + in.L.tcursor);
+    d.tb.work = (int4*)(b + in.L.twork);
+    d.tb.nwork = (int32_t*)(b + in.L.tnwork);
+    d.n = 0;
+    d.R_r2c = rows_r2c_R(cf.nx, cf.ny);
+    d.R_c2r = rows_c2r_R(cf.nx, cf.ny);
+    d.nb_col = columns_nb(cf.ny);
+    // flattened block ranges
+    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * 3, cf.nx / 2 + 1, cf.ny / d.R_c2r * 6, d.tp.max_work,
+                               ceil_div(cf.max_particles, 256), ceil_div(cf.max_particles, 1024)};
+    for (int k = 0; k < BK_NKINDS; ++k) {
+      d.blk[k] = c->nblk[k];
+      c->nblk[k] += nb[k];
+    }
+    c->lds_r2c = std::max(c->lds_r2c, rows_r2c_lds_bytes(cf.nx, cf.ny));
+    c->lds_c2r = std::max(c->lds_c2r, rows_c2r_lds_bytes(cf.nx, cf.ny));
+    c->lds_col = std::max(c->lds_col, columns_lds_bytes(cf.ny));
+    for (int mode = 0; mode < 3; ++mode)
+      c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp));
+    c->lds_count = std::max(c->lds_count, sort_count_lds_bytes(d.tp));
+    c->lds_scatter = std::max(c->lds_scatter, sort_scatter_lds_bytes(d.tp));
+    // a position update moves a particle by less than c dt; the window's slack
+    // absorbs sort_every updates without any particle leaving it
+    const double cells = cf.c * cf.dt / std::min(g.dx, g.dy);
+    const int auto_every = std::max(1, (int)std::floor(d.tp.slack / std::max(cells, 1e-300)));
+    every = std::min(every, cf.sort_interval > 0 ? cf.sort_interval : auto_every);
+    // twiddles
+    tw.assign(2 * (size_t)std::max(cf.nx, cf.ny), 0.0);
+    fft_make_twiddles(cf.nx, tw.data());
+    e = hipMemcpy((void*)d.twx, tw.data(), (size_t)cf.nx * 16, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+      fft_make_twiddles(cf.ny, tw.data());
+      e = hipMemcpy((void*)d.twy, tw.data(), (size_t)cf.ny * 16, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMemset(d.tb.count, 0, (size_t)d.tp.ntiles * 4);
+  }
+  c->sort_every = every;
+  if (e != hipSuccess) {
+    g_err = std::string("context setup: ") + hipGetErrorString(e);
+    delete c;
+    return PIC_ERR_HIP;
+  }
+  const size_t lds_need = std::max({c->lds_col, c->lds_r2c, c->lds_c2r, c->lds_tiled[0], c->lds_tiled[1],
+                                    c->lds_tiled[2], c->lds_scatter});
+  if (lds_need > (size_t)max_lds) {
+    g_err = "grid or tile too large for this device's LDS";
+    delete c;
+    return PIC_ERR_UNSUPPORTED;
+  }
+  pic_status_t st = c->upload_desc();
+  for (int i = 0; i < ninst && !st; ++i) st = reset_fields(c, c->inst[i]);
+  if (st) {
+    g_err = c->err;
+    delete c;
+    return st;
+  }
+  c->moves = c->sort_every;  // sort before the first particle pass
+  *out = c;
   return PIC_OK;
 }
 
-}  // namespace
-
-namespace {
 // external history order (see pic.h) as a list of internal slots
 std::vector<int> export_slots(pic_ctx_t c) {
   std::vector<int> v;
@@ -454,25 +622,51 @@ std::vector<int> export_slots(pic_ctx_t c) {
   };
   ring(h.rho, h.rho.size);
   ring(h.phi, h.phi.size);
-  if (c->cfg.scheme == PIC_SCHEME_DIRK2) ring(h.vphi, 1);
+  if (c->scheme == PIC_SCHEME_DIRK2) ring(h.vphi, 1);
   ring(h.A, h.A.size);
-  if (c->cfg.scheme == PIC_SCHEME_DIRK2) ring(h.vA, 1);
-  if (c->cfg.scheme != PIC_SCHEME_BDF) ring(h.J, h.J.size);
+  if (c->scheme == PIC_SCHEME_DIRK2) ring(h.vA, 1);
+  if (c->scheme != PIC_SCHEME_BDF) ring(h.J, h.J.size);
   return v;
 }
 
 pic_status_t history_io(pic_ctx_t c, double* ext, bool to_external) {
   const std::vector<int> slots = export_slots(c);
-  const size_t plane = c->L.plane_c;
+  Instance& in = c->I();
+  const size_t plane = in.L.plane_c;
   for (size_t f = 0; f < slots.size(); ++f) {
-    double2* in_slot = c->H() + (size_t)slots[f] * plane;
+    double2* in_slot = in.d.H + (size_t)slots[f] * plane;
     double2* ext_f = (double2*)ext + f * plane;
-    hipError_t e = to_external ? launch_hist_transpose(in_slot, ext_f, 1, c->g, true, c->stream)
-                               : launch_hist_transpose(ext_f, in_slot, 1, c->g, false, c->stream);
+    hipError_t e = to_external ? launch_hist_transpose(in_slot, ext_f, 1, in.d.g, true, c->stream)
+                               : launch_hist_transpose(ext_f, in_slot, 1, in.d.g, false, c->stream);
     if (e != hipSuccess) return c->hip(e, "history transpose");
   }
   return PIC_OK;
 }
+
+pic_status_t run_steps(pic_ctx_t c, int32_t nsteps) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  if (nsteps < 0) return c->fail(PIC_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (c->phase != READY) return c->fail(PIC_ERR_STATE, "step needs phase READY");
+  if (nsteps == 0) return PIC_OK;
+  const bool unfused = (c->inst[0].cfg.flags & PIC_FLAG_UNFUSED_STEP) != 0;
+  pic_status_t st = particle_pass(c, 0);
+  for (int s = 0; s < nsteps && !st; ++s) {
+    st = do_solve(c);
+    if (st) break;
+    const bool last = s == nsteps - 1;
+    if (last || unfused) {
+      st = particle_pass(c, 1);
+      if (!st && !last) st = particle_pass(c, 0);
+    } else {
+      st = particle_pass(c, 2);
+    }
+  }
+  // a failed launch leaves the state undefined; report it and require a reload
+  c->phase = st ? EMPTY : READY;
+  return st;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -483,7 +677,21 @@ size_t pic_workspace_bytes(const pic_config_t* cfg) {
     g_err = m;
     return 0;
   }
-  return plan(*cfg).total;
+  return total_bytes(cfg, 1);
+}
+
+size_t pic_batch_workspace_bytes(const pic_config_t* cfgs, int32_t ninst) {
+  std::string m;
+  if (!cfgs || ninst < 1 || ninst > 4096) {
+    g_err = "need 1..4096 configs";
+    return 0;
+  }
+  for (int i = 0; i < ninst; ++i)
+    if (!validate(&cfgs[i], m) || !compatible(cfgs[0], cfgs[i], m)) {
+      g_err = "instance " + std::to_string(i) + ": " + m;
+      return 0;
+    }
+  return total_bytes(cfgs, ninst);
 }
 
 int32_t pic_history_fields(const pic_config_t* cfg) {
@@ -499,145 +707,53 @@ const char* pic_last_error(pic_ctx_t ctx) { return ctx ? ctx->err.c_str() : g_er
 
 pic_status_t pic_create(const pic_config_t* cfg, void* workspace, size_t ws_bytes, void* hip_stream,
                         pic_ctx_t* out) {
-  std::string m;
-  if (!out) {
-    g_err = "out is NULL";
+  if (!cfg) {
+    g_err = "cfg is NULL";
+    if (out) *out = nullptr;
     return PIC_ERR_INVALID_ARG;
   }
-  *out = nullptr;
-  if (!validate(cfg, m)) {
-    g_err = m;
-    return PIC_ERR_INVALID_ARG;
-  }
-  const Layout L = plan(*cfg);
-  if (!workspace || ((uintptr_t)workspace & (kAlign - 1))) {
-    g_err = "workspace must be a 256-byte aligned device pointer";
-    return PIC_ERR_WORKSPACE;
-  }
-  if (ws_bytes < L.total) {
-    g_err = "workspace too small: need " + std::to_string(L.total) + " bytes";
-    return PIC_ERR_WORKSPACE;
-  }
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) {
-    g_err = "hipGetDevice failed";
-    return PIC_ERR_HIP;
-  }
-  int max_lds = 0;
-  hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  if (columns_lds_bytes(cfg->ny) > (size_t)max_lds) {
-    g_err = "ny too large for this device's LDS";
-    return PIC_ERR_UNSUPPORTED;
-  }
-  auto* c = new pic_ctx_s();
-  c->cfg = *cfg;
-  c->stream = (hipStream_t)hip_stream;
-  c->ws = (char*)workspace;
-  c->L = L;
-  c->hist = plan_history(*cfg);
-  c->device = dev;
-  GridP& g = c->g;
-  g.nx = cfg->nx;
-  g.ny = cfg->ny;
-  g.nxh = cfg->nx / 2 + 1;
-  g.lx = cfg->lx;
-  g.ly = cfg->ly;
-  g.dx = cfg->lx / cfg->nx;
-  g.dy = cfg->ly / cfg->ny;
-  g.inv_dx = 1.0 / g.dx;
-  g.inv_dy = 1.0 / g.dy;
-  g.inv_area = 1.0 / (g.dx * g.dy);
-  c->ph = PhysP{cfg->dt, cfg->q, cfg->m, cfg->c};
-  c->tp = plan_tiles(*cfg);
-  c->tb.key = (int32_t*)(c->ws + L.tkey);
-  c->tb.count = (int32_t*)(c->ws + L.tcount);
-  c->tb.start = (int32_t*)(c->ws + L.tstart);
-  c->tb.cursor = (int32_t*)(c->ws + L.tcursor);
-  c->tb.work = (int4*)(c->ws + L.twork);
-  c->tb.nwork = (int32_t*)(c->ws + L.tnwork);
-  c->sorted = (cfg->flags & PIC_FLAG_NO_SORT) == 0;
-  {
-    // a position update moves a particle by less than c dt; the window's slack
-    // absorbs sort_every updates without any particle leaving it
-    const double cells = cfg->c * cfg->dt / std::min(g.dx, g.dy);
-    const int auto_every = std::max(1, (int)std::floor(c->tp.slack / std::max(cells, 1e-300)));
-    c->sort_every = cfg->sort_interval > 0 ? cfg->sort_interval : std::min(auto_every, 64);
-  }
-  SchemeCoef& sc = c->sc;
-  sc.scheme = cfg->scheme;
-  sc.k = cfg->scheme == PIC_SCHEME_BDF ? cfg->bdf_order : 0;
-  sc.dt = cfg->dt;
-  sc.c = cfg->c;
-  sc.eps0 = cfg->eps0;
-  sc.mu0 = cfg->mu0;
-  if (cfg->scheme == PIC_SCHEME_BDF) {
-    // Sec. 3.2: C = a*a; alpha = a_0/(c dt) so that the solve divides by C_0
-    bdf_coefficients(sc.k, sc.a);
-    double C[13] = {0};
-    for (int i = 0; i <= sc.k; ++i)
-      for (int j = 0; j <= sc.k; ++j) C[i + j] += sc.a[i] * sc.a[j];
-    for (int i = 0; i <= 2 * sc.k; ++i) sc.Cn[i] = C[i] / C[0];
-    const double alpha = sc.a[0] / (cfg->c * cfg->dt);
-    sc.inv_alpha2 = 1.0 / (alpha * alpha);
-  } else if (cfg->scheme == PIC_SCHEME_CDF2) {
-    sc.inv_alpha2 = 0.5 * cfg->c * cfg->c * cfg->dt * cfg->dt;  // alpha = sqrt(2)/(c dt), Sec. 3.1
-  } else {
-    // Qin-Zhang two-stage symplectic DIRK (the printed tableau in Sec. 5 is
-    // garbled; this is the consistent second-order, |R(i theta)| = 1 scheme)
-    sc.dirkA[0][0] = 0.25;
-    sc.dirkA[0][1] = 0.0;
-    sc.dirkA[1][0] = 0.5;
-    sc.dirkA[1][1] = 0.25;
-    sc.dirkB[0] = sc.dirkB[1] = 0.5;
-    sc.dirkC[0] = 0.25;
-    sc.dirkC[1] = 0.75;
-  }
-  // twiddles
-  std::vector<double> tw(2 * (size_t)std::max(cfg->nx, cfg->ny));
-  fft_make_twiddles(cfg->nx, tw.data());
-  hipError_t e = hipMemcpy(c->twx(), tw.data(), (size_t)cfg->nx * 16, hipMemcpyHostToDevice);
-  if (e == hipSuccess) {
-    fft_make_twiddles(cfg->ny, tw.data());
-    e = hipMemcpy(c->twy(), tw.data(), (size_t)cfg->ny * 16, hipMemcpyHostToDevice);
-  }
-  if (e != hipSuccess) {
-    g_err = std::string("twiddle upload: ") + hipGetErrorString(e);
-    delete c;
-    return PIC_ERR_HIP;
-  }
-  if (c->sorted) {
-    hipError_t ez = hipMemsetAsync(c->tb.count, 0, (size_t)c->tp.ntiles * 4, c->stream);
-    if (ez != hipSuccess) {
-      g_err = std::string("tile count clear: ") + hipGetErrorString(ez);
-      delete c;
-      return PIC_ERR_HIP;
-    }
-  }
-  if (reset_fields(c) != PIC_OK) {
-    g_err = c->err;
-    delete c;
-    return PIC_ERR_HIP;
-  }
-  *out = c;
-  return PIC_OK;
+  return create(cfg, 1, workspace, ws_bytes, hip_stream, out);
+}
+
+pic_status_t pic_batch_create(const pic_config_t* cfgs, int32_t ninst, void* workspace, size_t ws_bytes,
+                              void* hip_stream, pic_ctx_t* out) {
+  return create(cfgs, ninst, workspace, ws_bytes, hip_stream, out);
 }
 
 void pic_destroy(pic_ctx_t ctx) { delete ctx; }
 
+int32_t pic_instance_count(pic_ctx_t c) { return c ? c->ninst() : 0; }
+
+pic_status_t pic_select_instance(pic_ctx_t c, int32_t i) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  if (i < 0 || i >= c->ninst()) return c->fail(PIC_ERR_INVALID_ARG, "instance index out of range");
+  c->sel = i;
+  return PIC_OK;
+}
+
 pic_status_t init_particles(pic_ctx_t c, int64_t n, const double* x, const double* y, const double* P) {
   if (!c) return PIC_ERR_INVALID_ARG;
-  if (n < 0 || n > c->cfg.max_particles) return c->fail(PIC_ERR_INVALID_ARG, "n must be in [0, max_particles]");
+  Instance& in = c->I();
+  if (n < 0 || n > in.cfg.max_particles) return c->fail(PIC_ERR_INVALID_ARG, "n must be in [0, max_particles]");
   if (n > 0 && (!x || !y || !P)) return c->fail(PIC_ERR_INVALID_ARG, "x, y, P must be device pointers");
-  c->vflip = 0;
-  auto pa = c->parts();
-  pic_status_t st = c->hip(launch_init_particles(c->cfg.particle_dtype, &pa, n, x, y, P, c->g, c->ph, c->stream),
-                           "init launch");
+  if (c->ninst() > 1 && c->stepped)
+    return c->fail(PIC_ERR_STATE, "ensemble instances are loaded before the first step");
+  if (c->ninst() == 1) {  // a fresh start: counters and sets back to their initial state
+    c->vflip = 0;
+    c->cur = 0;
+    c->nupd = 0;
+    c->stepped = false;
+  }
+  auto pa = parts_of(c, in.d, c->cur);
+  pic_status_t st =
+      c->hip(launch_init_particles(c->dtype, &pa, n, x, y, P, in.d.g, in.d.ph, c->stream), "init launch");
   if (st) return st;
-  st = reset_fields(c);
+  st = reset_fields(c, in);
   if (st) return st;
-  c->n = n;
-  st = do_sort(c);
+  in.d.n = n;
+  st = c->upload_desc();
   if (st) return st;
+  c->moves = c->sort_every;  // sort before the next particle pass
   c->phase = READY;
   return PIC_OK;
 }
@@ -645,7 +761,7 @@ pic_status_t init_particles(pic_ctx_t c, int64_t n, const double* x, const doubl
 pic_status_t deposit_current(pic_ctx_t c) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (c->phase != READY) return c->fail(PIC_ERR_STATE, "deposit_current needs phase READY");
-  pic_status_t st = do_deposit(c);
+  pic_status_t st = particle_pass(c, 0);
   if (st) return st;
   c->phase = DEPOSITED;
   return PIC_OK;
@@ -663,74 +779,55 @@ pic_status_t field_solve(pic_ctx_t c) {
 pic_status_t gather_push(pic_ctx_t c) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "gather_push needs phase SOLVED");
-  pic_status_t st = do_gather_push(c, false);
+  pic_status_t st = particle_pass(c, 1);
   if (st) return st;
   c->phase = READY;
   return PIC_OK;
 }
 
-pic_status_t step(pic_ctx_t c, int32_t nsteps) {
-  if (!c) return PIC_ERR_INVALID_ARG;
-  if (nsteps < 0) return c->fail(PIC_ERR_INVALID_ARG, "nsteps must be >= 0");
-  if (c->phase != READY) return c->fail(PIC_ERR_STATE, "step needs phase READY");
-  if (nsteps == 0) return PIC_OK;
-  const bool unfused = (c->cfg.flags & PIC_FLAG_UNFUSED_STEP) != 0;
-  pic_status_t st = do_deposit(c);
-  for (int s = 0; s < nsteps && !st; ++s) {
-    st = do_solve(c);
-    if (st) break;
-    const bool last = s == nsteps - 1;
-    if (last || unfused) {
-      st = do_gather_push(c, false);
-      if (!st && !last) st = do_deposit(c);
-    } else {
-      st = do_gather_push(c, true);
-    }
-  }
-  // a failed launch leaves the state undefined; report it and require a reload
-  c->phase = st ? EMPTY : READY;
-  return st;
-}
+// exported names stay out of internal calls: a call to a global symbol from
+// inside the library could bind to another library's symbol of the same name
+pic_status_t step(pic_ctx_t c, int32_t nsteps) { return run_steps(c, nsteps); }
+pic_status_t step_batched(pic_ctx_t c, int32_t nsteps) { return run_steps(c, nsteps); }
 
 pic_status_t pic_get_particles(pic_ctx_t c, double* out) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (c->phase == EMPTY) return c->fail(PIC_ERR_STATE, "no particles loaded");
-  if (c->n > 0 && !out) return c->fail(PIC_ERR_INVALID_ARG, "out is NULL");
-  auto pa = c->parts();
-  return c->hip(launch_get_particles(c->cfg.particle_dtype, &pa, c->n, out, c->stream), "get_particles");
+  Instance& in = c->I();
+  if (in.d.n > 0 && !out) return c->fail(PIC_ERR_INVALID_ARG, "out is NULL");
+  auto pa = parts_of(c, in.d, c->cur);
+  return c->hip(launch_get_particles(c->dtype, &pa, in.d.n, out, c->stream), "get_particles");
 }
 
-pic_status_t pic_set_particles(pic_ctx_t c, const double* in) {
+pic_status_t pic_set_particles(pic_ctx_t c, const double* src) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (c->phase == EMPTY) return c->fail(PIC_ERR_STATE, "no particles loaded");
-  if (c->n > 0 && !in) return c->fail(PIC_ERR_INVALID_ARG, "in is NULL");
-  c->vflip = 0;
-  auto pa = c->parts();
-  pic_status_t st =
-      c->hip(launch_set_particles(c->cfg.particle_dtype, &pa, c->n, in, c->g, c->stream), "set_particles");
+  Instance& in = c->I();
+  if (in.d.n > 0 && !src) return c->fail(PIC_ERR_INVALID_ARG, "in is NULL");
+  if (c->phase != READY) return c->fail(PIC_ERR_STATE, "set_particles needs phase READY");
+  auto pa = parts_of(c, in.d, c->cur);
+  pic_status_t st = c->hip(launch_set_particles(c->dtype, &pa, in.d.n, src, in.d.g, c->stream), "set_particles");
   if (st) return st;
-  st = do_sort(c);
-  if (st) return st;
-  c->phase = READY;
+  c->moves = c->sort_every;  // re-sort before the next particle pass
   return PIC_OK;
 }
 
 pic_status_t pic_get_field(pic_ctx_t c, int32_t which, double* dst) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (!dst) return c->fail(PIC_ERR_INVALID_ARG, "dst is NULL");
-  const size_t plane = (size_t)c->cfg.nx * c->cfg.ny;
+  Instance& in = c->I();
+  const size_t plane = (size_t)in.cfg.nx * in.cfg.ny;
   if (which == PIC_FIELD_J) {
     if (c->phase != DEPOSITED) return c->fail(PIC_ERR_STATE, "J is valid in phase DEPOSITED");
-    return c->hip(hipMemcpyAsync(dst, c->J(), 3 * plane * 8, hipMemcpyDeviceToDevice, c->stream), "copy J");
+    return c->hip(hipMemcpyAsync(dst, in.d.J, 3 * plane * 8, hipMemcpyDeviceToDevice, c->stream), "copy J");
   }
   if (which == PIC_FIELD_MESH) {
     if (c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "mesh fields are valid in phase SOLVED");
-    return c->hip(hipMemcpyAsync(dst, c->F64(), 12 * plane * 8, hipMemcpyDeviceToDevice, c->stream),
+    return c->hip(hipMemcpyAsync(dst, in.d.F64, 12 * plane * 8, hipMemcpyDeviceToDevice, c->stream),
                   "copy mesh fields");
   }
   return c->fail(PIC_ERR_INVALID_ARG, "unknown field id");
 }
-
 
 pic_status_t pic_get_history(pic_ctx_t c, double* dst) {
   if (!c) return PIC_ERR_INVALID_ARG;
@@ -749,16 +846,16 @@ pic_status_t pic_set_history(pic_ctx_t c, const double* src) {
 pic_status_t pic_diagnostics(pic_ctx_t c, double* out) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (!out) return c->fail(PIC_ERR_INVALID_ARG, "out is NULL");
+  Instance& in = c->I();
   // the newest level is the one written by the last update: slots of s = nupd
-  HistSlots hs = c->slots(c->nupd);
-  pic_status_t st = c->hip(launch_field_diag(c->H(), c->g, c->sc, hs, c->diag(), c->stream), "field diag");
+  HistSlots hs = slots_of(c->hist, c->nupd);
+  pic_status_t st = c->hip(launch_field_diag(in.d.H, in.d.g, in.d.sc, hs, c->d_diag, c->stream), "field diag");
   if (st) return st;
-  auto pa = c->parts();
-  st = c->hip(launch_particle_diag(c->cfg.particle_dtype, &pa, c->n, c->ph, c->diag() + 16, c->stream),
-              "particle diag");
+  auto pa = parts_of(c, in.d, c->cur);
+  st = c->hip(launch_particle_diag(c->dtype, &pa, in.d.n, in.d.ph, c->d_diag + 16, c->stream), "particle diag");
   if (st) return st;
-  std::vector<double> h(16 + 512);
-  st = c->hip(hipMemcpyAsync(h.data(), c->diag(), h.size() * 8, hipMemcpyDeviceToHost, c->stream), "diag copy");
+  std::vector<double> h(kDiagDoubles);
+  st = c->hip(hipMemcpyAsync(h.data(), c->d_diag, h.size() * 8, hipMemcpyDeviceToHost, c->stream), "diag copy");
   if (st) return st;
   st = c->hip(hipStreamSynchronize(c->stream), "diag sync");
   if (st) return st;

@@ -116,15 +116,20 @@ __device__ __forceinline__ double ky_sym(int ky, const GridP& g) {
 
 // ---------------------------------------------------------------------------
 // rows: R real rows (R even) of one J component -> R/2 complex FFTs along x.
-__global__ void __launch_bounds__(256) k_rows_r2c(double* __restrict__ J, double2* __restrict__ T,
-                                                  const double2* __restrict__ twx, GridP g, int R) {
+// Flattened over instances: local block = component * (ny/R) + row group.
+__global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D, int ninst) {
   extern __shared__ double2 sm[];
+  const int ii = find_inst(D, ninst, BK_R2C, blockIdx.x);
+  const InstDesc& d = D[ii];
+  const GridP g = d.g;
+  const int R = d.R_r2c, ngr = g.ny / R;
+  const int lb = blockIdx.x - d.blk[BK_R2C];
+  const int c = lb / ngr, y0 = (lb - c * ngr) * R;
+  double* __restrict__ Jc = d.J + (size_t)c * g.nx * g.ny;
+  double2* __restrict__ T = d.T;
   const int N = g.nx, B = R >> 1;
   double2* a = sm;
   double2* b = sm + B * N;
-  const int y0 = blockIdx.x * R;
-  const int c = blockIdx.y;
-  double* Jc = J + (size_t)c * g.nx * g.ny;
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     const int r = t / N, x = t - r * N;
     const size_t i0 = (size_t)(y0 + 2 * r) * N + x, i1 = i0 + N;
@@ -133,7 +138,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(double* __restrict__ J, double
     Jc[i1] = 0.0;
   }
   __syncthreads();
-  const double2* res = fft_lds<false>(a, b, N, B, twx);
+  const double2* res = fft_lds<false>(a, b, N, B, d.twx);
   // split the two real transforms: X = (Z_k + conj Z_{N-k})/2, Y = (Z_k - conj Z_{N-k})/(2i)
   for (int t = threadIdx.x; t < g.nxh * R; t += blockDim.x) {
     const int k = t / R, rr = t - k * R, r = rr >> 1;
@@ -143,8 +148,8 @@ __global__ void __launch_bounds__(256) k_rows_r2c(double* __restrict__ J, double
     if ((rr & 1) == 0) {
       o = cscale(cadd(zk, zn), 0.5);
     } else {
-      const double2 d = csub(zk, zn);
-      o = make_double2(0.5 * d.y, -0.5 * d.x);
+      const double2 dd = csub(zk, zn);
+      o = make_double2(0.5 * dd.y, -0.5 * dd.x);
     }
     T[((size_t)c * g.nxh + k) * g.ny + y0 + rr] = o;
   }
@@ -261,13 +266,19 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
 }
 
 template <int SCHEME>
-__global__ void __launch_bounds__(256) k_columns(const double2* __restrict__ T, double2* __restrict__ H,
-                                                 double2* __restrict__ U, const double2* __restrict__ twy,
-                                                 GridP g, SchemeCoef sc, HistSlots hs, int NB) {
+__global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
   // LDS: store [0, 4N) = phi~, A0, A1, A2 (scaled); work buffers from 4N:
   // forward 2 x 3N, inverse 2 x NB*N (NB = 8, 4 or 2 fields per batch)
   extern __shared__ double2 sm[];
-  const int N = g.ny, kx = blockIdx.x;
+  const int ii = find_inst(D, ninst, BK_COL, blockIdx.x);
+  const InstDesc& d = D[ii];
+  const GridP g = d.g;
+  const SchemeCoef sc = d.sc;
+  const int kx = blockIdx.x - d.blk[BK_COL];
+  const int N = g.ny, NB = d.nb_col;
+  const double2* __restrict__ T = d.T;
+  double2* __restrict__ H = d.H;
+  double2* __restrict__ U = d.U;
   const size_t plane = (size_t)g.nxh * g.ny;
   double2* store = sm;
   double2* wk = sm + 4 * N;
@@ -276,7 +287,7 @@ __global__ void __launch_bounds__(256) k_columns(const double2* __restrict__ T, 
     wk[t] = T[((size_t)c * g.nxh + kx) * N + y];
   }
   __syncthreads();
-  const double2* Jh = fft_lds<false>(wk, wk + 3 * N, N, 3, twy);
+  const double2* Jh = fft_lds<false>(wk, wk + 3 * N, N, 3, d.twy);
   const double kxs = kx_sym(kx, g);
   const double scale = 1.0 / ((double)g.nx * g.ny);
   for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
@@ -299,7 +310,7 @@ __global__ void __launch_bounds__(256) k_columns(const double2* __restrict__ T, 
       wk[t] = v;
     }
     __syncthreads();
-    const double2* res = fft_lds<true>(wk, wk + NB * N, N, NB, twy);
+    const double2* res = fft_lds<true>(wk, wk + NB * N, N, NB, d.twy);
     for (int t = threadIdx.x; t < NB * N; t += blockDim.x) {
       const int q = t / N, y = t - q * N;
       U[((size_t)(f0 + q) * g.nxh + kx) * N + y] = res[t];
@@ -318,15 +329,21 @@ __global__ void __launch_bounds__(256) k_columns(const double2* __restrict__ T, 
 __constant__ int kSrcG[12] = {0, 1, 2, 3, 4, 2, 3, 4, 5, 6, 7, 0};
 __constant__ int kMulKx[12] = {1, 0, 0, 0, 0, 1, 1, 1, 0, 0, 0, 0};
 
-__global__ void __launch_bounds__(256) k_rows_c2r(const double2* __restrict__ U, double* __restrict__ F64,
-                                                  float* __restrict__ F32, const double2* __restrict__ twx,
-                                                  GridP g, int R) {
+__global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D, int ninst) {
   extern __shared__ double2 sm[];
+  const int ii = find_inst(D, ninst, BK_C2R, blockIdx.x);
+  const InstDesc& d = D[ii];
+  const GridP g = d.g;
+  const int R = d.R_c2r, ngr = g.ny / R;
+  const int lb = blockIdx.x - d.blk[BK_C2R];
+  const int pr = lb / ngr, y0 = (lb - pr * ngr) * R;
+  const double2* __restrict__ U = d.U;
+  double* __restrict__ F64 = d.F64;
+  float* __restrict__ F32 = d.F32;
   const int N = g.nx, h = N >> 1;
   double2* a = sm;
   double2* b = sm + R * N;
-  const int y0 = blockIdx.x * R;
-  const int s0 = 2 * blockIdx.y, s1 = s0 + 1;
+  const int s0 = 2 * pr, s1 = s0 + 1;
   const int g0 = kSrcG[s0], g1 = kSrcG[s1];
   for (int t = threadIdx.x; t < g.nxh * R; t += blockDim.x) {
     const int k = t / R, r = t - k * R;
@@ -343,7 +360,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const double2* __restrict__ U,
     if (k > 0 && k < h) a[r * N + N - k] = cadd(cconj(X), mul_i(cconj(Y)));
   }
   __syncthreads();
-  const double2* res = fft_lds<true>(a, b, N, R, twx);
+  const double2* res = fft_lds<true>(a, b, N, R, d.twx);
   const size_t plane = (size_t)g.nx * g.ny;
   for (int t = threadIdx.x; t < R * N; t += blockDim.x) {
     const int r = t / N, x = t - r * N;
@@ -497,55 +514,49 @@ void fft_make_twiddles(int n, double* h) {
   }
 }
 
-static int rows_r2c_R(const GridP& g) {
+int rows_r2c_R(int nx, int ny) {
   int R = 8;
-  while (R > 2 && (R > g.ny || R * g.nx > 4096)) R >>= 1;
+  while (R > 2 && (R > ny || R * nx > 4096)) R >>= 1;
   return R;
 }
-static int rows_c2r_R(const GridP& g) {
+int rows_c2r_R(int nx, int ny) {
   int R = 8;
-  while (R > 1 && (R > g.ny || R * g.nx > 2048)) R >>= 1;
+  while (R > 1 && (R > ny || R * nx > 2048)) R >>= 1;
   return R;
 }
-
-hipError_t launch_rows_r2c(double* J, double2* T, const double2* twx, GridP g, hipStream_t s) {
-  const int R = rows_r2c_R(g);
-  const size_t lds = (size_t)R * g.nx * sizeof(double2);
-  hipFuncSetAttribute((const void*)k_rows_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_rows_r2c, dim3(g.ny / R, 3), dim3(256), lds, s, J, T, twx, g, R);
-  return hipGetLastError();
-}
-
+size_t rows_r2c_lds_bytes(int nx, int ny) { return (size_t)rows_r2c_R(nx, ny) * nx * sizeof(double2); }
+size_t rows_c2r_lds_bytes(int nx, int ny) { return (size_t)2 * rows_c2r_R(nx, ny) * nx * sizeof(double2); }
 // inverse batch size of the column kernel and its LDS bytes (<= 160 KiB)
-static int columns_nb(int ny) { return ny <= 256 ? 8 : (ny <= 512 ? 4 : 2); }
+int columns_nb(int ny) { return ny <= 256 ? 8 : (ny <= 512 ? 4 : 2); }
 size_t columns_lds_bytes(int ny) {
   const int nb = columns_nb(ny);
   return (size_t)(4 + std::max(6, 2 * nb)) * ny * sizeof(double2);
 }
 
-hipError_t launch_columns(const double2* T, double2* H, double2* U, const double2* twy, GridP g,
-                          SchemeCoef sc, HistSlots hs, hipStream_t s) {
-  const size_t lds = columns_lds_bytes(g.ny);
-  const int nb = columns_nb(g.ny);
-  const void* fn = sc.scheme == PIC_SCHEME_BDF    ? (const void*)k_columns<PIC_SCHEME_BDF>
-                   : sc.scheme == PIC_SCHEME_CDF2 ? (const void*)k_columns<PIC_SCHEME_CDF2>
-                                                  : (const void*)k_columns<PIC_SCHEME_DIRK2>;
-  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (sc.scheme == PIC_SCHEME_BDF)
-    hipLaunchKernelGGL(k_columns<PIC_SCHEME_BDF>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs, nb);
-  else if (sc.scheme == PIC_SCHEME_CDF2)
-    hipLaunchKernelGGL(k_columns<PIC_SCHEME_CDF2>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs, nb);
-  else
-    hipLaunchKernelGGL(k_columns<PIC_SCHEME_DIRK2>, dim3(g.nxh), dim3(256), lds, s, T, H, U, twy, g, sc, hs, nb);
+hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s) {
+  hipFuncSetAttribute((const void*)k_rows_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_rows_r2c, dim3(nblocks), dim3(256), lds, s, D, ninst);
   return hipGetLastError();
 }
 
-hipError_t launch_rows_c2r(const double2* U, double* F64, float* F32, const double2* twx, GridP g,
-                           hipStream_t s) {
-  const int R = rows_c2r_R(g);
-  const size_t lds = (size_t)2 * R * g.nx * sizeof(double2);
+hipError_t launch_columns(int scheme, const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
+                          hipStream_t s) {
+  const void* fn = scheme == PIC_SCHEME_BDF    ? (const void*)k_columns<PIC_SCHEME_BDF>
+                   : scheme == PIC_SCHEME_CDF2 ? (const void*)k_columns<PIC_SCHEME_CDF2>
+                                               : (const void*)k_columns<PIC_SCHEME_DIRK2>;
+  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (scheme == PIC_SCHEME_BDF)
+    hipLaunchKernelGGL(k_columns<PIC_SCHEME_BDF>, dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
+  else if (scheme == PIC_SCHEME_CDF2)
+    hipLaunchKernelGGL(k_columns<PIC_SCHEME_CDF2>, dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
+  else
+    hipLaunchKernelGGL(k_columns<PIC_SCHEME_DIRK2>, dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s) {
   hipFuncSetAttribute((const void*)k_rows_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_rows_c2r, dim3(g.ny / R, 6), dim3(256), lds, s, U, F64, F32, twx, g, R);
+  hipLaunchKernelGGL(k_rows_c2r, dim3(nblocks), dim3(256), lds, s, D, ninst);
   return hipGetLastError();
 }
 

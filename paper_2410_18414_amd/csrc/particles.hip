@@ -17,48 +17,47 @@ namespace pic {
 
 namespace {
 
-template <typename T, int DEG>
-__global__ void __launch_bounds__(256) k_deposit(Parts<T> p, int64_t n, double* __restrict__ J, GridP g,
-                                                 PhysP ph) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Untiled passes (PIC_FLAG_NO_SORT): one particle per thread, gather from the
+// planar mesh fields in global memory, deposit with global float64 atomics.
+// Flattened over instances (BK_PART blocks of 256 particles each).
+template <typename T, int DEG, int MODE>
+__global__ void __launch_bounds__(256) k_untiled(const InstDesc* __restrict__ D, int ninst, StepArgs sa) {
+  const int ii = find_inst(D, ninst, BK_PART, blockIdx.x);
+  const InstDesc& d = D[ii];
+  const int64_t i = (int64_t)(blockIdx.x - d.blk[BK_PART]) * 256 + threadIdx.x;
+  if (i >= d.n) return;
+  const GridP g = d.g;
+  const PhysP ph = d.ph;
+  const Parts<T> p = make_parts<T>(d, sa.cur, sa.vflip);
+  double* __restrict__ J = d.J;
   const T dt = T(ph.dt), q = T(ph.q);
-  const T vx = p.v[0][i], vy = p.v[1][i], vz = p.v[2][i];
-  const T x = wrapx<T>(p.x[i] + vx * dt, T(g.lx));
-  const T y = wrapx<T>(p.y[i] + vy * dt, T(g.ly));
-  p.x[i] = x;
-  p.y[i] = y;
-  const T s = q * T(g.inv_area);
-  deposit_one<T, DEG>(x, y, s * vx, s * vy, s * vz, J, g);
-}
-
-template <typename T, int DEG, bool FUSED>
-__global__ void __launch_bounds__(256) k_gather_push(Parts<T> p, int64_t n, const T* __restrict__ F,
-                                                     double* __restrict__ J, GridP g, PhysP ph) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
   T x = p.x[i], y = p.y[i];
-  T gv[11];
-  gather_one<T, DEG>(x, y, F, g, gv);
-  T Px = p.P[0][i], Py = p.P[1][i];
-  const T Pz = p.P[2][i];
-  const T vx = p.v[0][i], vy = p.v[1][i], vz = p.v[2][i];
-  const T wx = p.w[0][i], wy = p.w[1][i], wz = p.w[2][i];
-  T nx, ny, nz;
-  push_one<T>(gv, Px, Py, Pz, vx, vy, vz, wx, wy, wz, ph, nx, ny, nz);
-  p.P[0][i] = Px;
-  p.P[1][i] = Py;
-  p.w[0][i] = nx;
-  p.w[1][i] = ny;
-  p.w[2][i] = nz;
-  if (FUSED) {  // next step's position update and deposit with v^{n+1}
-    const T dt = T(ph.dt), q = T(ph.q);
-    x = wrapx<T>(x + nx * dt, T(g.lx));
-    y = wrapx<T>(y + ny * dt, T(g.ly));
+  T vx = p.v[0][i], vy = p.v[1][i], vz = p.v[2][i];
+  if (MODE != 0) {
+    const T* __restrict__ F = d.F32 ? (const T*)(const void*)d.F32 : (const T*)(const void*)d.F64;
+    T gv[11];
+    gather_one<T, DEG>(x, y, F, g, gv);
+    T Px = p.P[0][i], Py = p.P[1][i];
+    const T Pz = p.P[2][i];
+    const T wx = p.w[0][i], wy = p.w[1][i], wz = p.w[2][i];
+    T nx, ny, nz;
+    push_one<T>(gv, Px, Py, Pz, vx, vy, vz, wx, wy, wz, ph, nx, ny, nz);
+    p.P[0][i] = Px;
+    p.P[1][i] = Py;
+    p.w[0][i] = nx;
+    p.w[1][i] = ny;
+    p.w[2][i] = nz;
+    vx = nx;
+    vy = ny;
+    vz = nz;
+  }
+  if (MODE != 1) {  // position update and deposit with the newest velocity
+    x = wrapx<T>(x + vx * dt, T(g.lx));
+    y = wrapx<T>(y + vy * dt, T(g.ly));
     p.x[i] = x;
     p.y[i] = y;
     const T s = q * T(g.inv_area);
-    deposit_one<T, DEG>(x, y, s * nx, s * ny, s * nz, J, g);
+    deposit_one<T, DEG>(x, y, s * vx, s * vy, s * vz, J, g);
   }
 }
 
@@ -169,64 +168,44 @@ hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_particles(int dtype, void* parts, int64_t n, const double* x, const double* y,
+hipError_t launch_init_particles(int dtype, const void* parts, int64_t n, const double* x, const double* y,
                                  const double* P, GridP g, PhysP ph, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (dtype == PIC_F32)
     hipLaunchKernelGGL(k_init_particles<float>, dim3(blocks_for(n)), dim3(256), 0, s,
-                       *(Parts<float>*)parts, n, x, y, P, g, ph);
+                       *(const Parts<float>*)parts, n, x, y, P, g, ph);
   else
     hipLaunchKernelGGL(k_init_particles<double>, dim3(blocks_for(n)), dim3(256), 0, s,
-                       *(Parts<double>*)parts, n, x, y, P, g, ph);
+                       *(const Parts<double>*)parts, n, x, y, P, g, ph);
   return hipGetLastError();
 }
 
-#define PIC_DISPATCH_DEG(DEG_, ...)                 \
-  switch (DEG_) {                                   \
-    case 1: { constexpr int D = 1; __VA_ARGS__; } break; \
-    case 2: { constexpr int D = 2; __VA_ARGS__; } break; \
-    default: { constexpr int D = 3; __VA_ARGS__; } break; \
+template <typename T, int MODE>
+static hipError_t launch_untiled_deg(int degree, const InstDesc* D, int ninst, int nblocks, StepArgs sa,
+                                     hipStream_t s) {
+  switch (degree) {
+    case 1: hipLaunchKernelGGL((k_untiled<T, 1, MODE>), dim3(nblocks), dim3(256), 0, s, D, ninst, sa); break;
+    case 2: hipLaunchKernelGGL((k_untiled<T, 2, MODE>), dim3(nblocks), dim3(256), 0, s, D, ninst, sa); break;
+    default: hipLaunchKernelGGL((k_untiled<T, 3, MODE>), dim3(nblocks), dim3(256), 0, s, D, ninst, sa); break;
   }
+  return hipGetLastError();
+}
 
-hipError_t launch_deposit(int dtype, int degree, const void* parts, int64_t n, double* J, GridP g, PhysP ph,
+template <typename T>
+static hipError_t launch_untiled_mode(int mode, int degree, const InstDesc* D, int ninst, int nblocks, StepArgs sa,
+                                      hipStream_t s) {
+  switch (mode) {
+    case 0: return launch_untiled_deg<T, 0>(degree, D, ninst, nblocks, sa, s);
+    case 1: return launch_untiled_deg<T, 1>(degree, D, ninst, nblocks, sa, s);
+    default: return launch_untiled_deg<T, 2>(degree, D, ninst, nblocks, sa, s);
+  }
+}
+
+hipError_t launch_untiled(int dtype, int mode, int degree, const InstDesc* D, int ninst, int nblocks, StepArgs sa,
                           hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  if (dtype == PIC_F32) {
-    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_deposit<float, D>), dim3(blocks_for(n)), dim3(256), 0, s,
-                                                *(const Parts<float>*)parts, n, J, g, ph))
-  } else {
-    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_deposit<double, D>), dim3(blocks_for(n)), dim3(256), 0, s,
-                                                *(const Parts<double>*)parts, n, J, g, ph))
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_gather_push(int dtype, int degree, const void* parts, int64_t n, const void* F, GridP g,
-                              PhysP ph, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  if (dtype == PIC_F32) {
-    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_gather_push<float, D, false>), dim3(blocks_for(n)), dim3(256),
-                                                0, s, *(const Parts<float>*)parts, n, (const float*)F,
-                                                (double*)nullptr, g, ph))
-  } else {
-    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_gather_push<double, D, false>), dim3(blocks_for(n)), dim3(256),
-                                                0, s, *(const Parts<double>*)parts, n, (const double*)F,
-                                                (double*)nullptr, g, ph))
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_fused(int dtype, int degree, const void* parts, int64_t n, const void* F, double* J, GridP g,
-                        PhysP ph, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  if (dtype == PIC_F32) {
-    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_gather_push<float, D, true>), dim3(blocks_for(n)), dim3(256),
-                                                0, s, *(const Parts<float>*)parts, n, (const float*)F, J, g, ph))
-  } else {
-    PIC_DISPATCH_DEG(degree, hipLaunchKernelGGL((k_gather_push<double, D, true>), dim3(blocks_for(n)), dim3(256),
-                                                0, s, *(const Parts<double>*)parts, n, (const double*)F, J, g, ph))
-  }
-  return hipGetLastError();
+  if (nblocks == 0) return hipSuccess;
+  if (dtype == PIC_F32) return launch_untiled_mode<float>(mode, degree, D, ninst, nblocks, sa, s);
+  return launch_untiled_mode<double>(mode, degree, D, ninst, nblocks, sa, s);
 }
 
 hipError_t launch_get_particles(int dtype, const void* parts, int64_t n, double* out, hipStream_t s) {
@@ -240,13 +219,13 @@ hipError_t launch_get_particles(int dtype, const void* parts, int64_t n, double*
   return hipGetLastError();
 }
 
-hipError_t launch_set_particles(int dtype, void* parts, int64_t n, const double* in, GridP g, hipStream_t s) {
+hipError_t launch_set_particles(int dtype, const void* parts, int64_t n, const double* in, GridP g, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (dtype == PIC_F32)
-    hipLaunchKernelGGL(k_set_particles<float>, dim3(blocks_for(n)), dim3(256), 0, s, *(Parts<float>*)parts, n,
+    hipLaunchKernelGGL(k_set_particles<float>, dim3(blocks_for(n)), dim3(256), 0, s, *(const Parts<float>*)parts, n,
                        in, g);
   else
-    hipLaunchKernelGGL(k_set_particles<double>, dim3(blocks_for(n)), dim3(256), 0, s, *(Parts<double>*)parts, n,
+    hipLaunchKernelGGL(k_set_particles<double>, dim3(blocks_for(n)), dim3(256), 0, s, *(const Parts<double>*)parts, n,
                        in, g);
   return hipGetLastError();
 }

@@ -1,4 +1,9 @@
 // Internal declarations shared by the libpic translation units.
+//
+// Every hot-path kernel runs over a flattened grid that covers all instances
+// of a context (one instance for the plain API, many for an ensemble): each
+// instance owns a contiguous range of blocks, found by binary search over the
+// per-instance block offsets in its descriptor (InstDesc, device memory).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,7 +16,7 @@
 namespace pic {
 
 // ---------------------------------------------------------------------------
-// geometry / physics passed to kernels by value
+// geometry / physics
 
 struct GridP {
   int nx, ny, nxh;          // nxh = nx/2 + 1
@@ -35,7 +40,6 @@ struct Parts {
 };
 
 // Spectral history slot table for one update: slot index of each (group, level).
-// Groups (per scheme) are documented in field.hip; up to 12 level entries.
 struct HistSlots {
   int rho[6];
   int rho_new;
@@ -62,7 +66,6 @@ struct TileP {
 };
 
 struct TileBufs {
-  int32_t* key;     // [capacity] tile of each particle at the last sort
   int32_t* count;   // [ntiles]   zero between sorts
   int32_t* start;   // [ntiles+1] first particle of each tile
   int32_t* cursor;  // [ntiles]
@@ -79,47 +82,109 @@ struct SchemeCoef {
   double dt, c, eps0, mu0;
 };
 
+// block ranges of the flattened kernels
+enum BlockKind {
+  BK_R2C = 0,    // (ny/R_r2c) x 3 blocks
+  BK_COL = 1,    // nxh blocks
+  BK_C2R = 2,    // (ny/R_c2r) x 6 blocks
+  BK_WORK = 3,   // tp.max_work blocks (tiled particle pass)
+  BK_PART = 4,   // ceil(capacity/256) blocks (untiled passes, scatter)
+  BK_COUNT = 5,  // ceil(capacity/1024) blocks (tile counting)
+  BK_NKINDS = 6
+};
+
+// One instance of the method: static for the life of a context.
+struct InstDesc {
+  GridP g;
+  PhysP ph;
+  TileP tp;
+  SchemeCoef sc;
+  void* set[2][11];         // particle arrays of the two sort sets: x, y, P(3), V0(3), V1(3)
+  int32_t* ids[2];
+  double* J;
+  double2* T;
+  double2* H;
+  double2* U;
+  double* F64;
+  float* F32;
+  const double2* twx;
+  const double2* twy;
+  TileBufs tb;
+  int64_t n;                // particles loaded
+  int R_r2c, R_c2r, nb_col; // rows per block of the row kernels; inverse batch of the column kernel
+  int blk[BK_NKINDS];       // first block of this instance in each flattened grid
+};
+
+// Per-launch state common to every instance of a context (instances advance in lockstep).
+struct StepArgs {
+  int cur;    // current particle set (0/1)
+  int vflip;  // 0: V0 = v^n, V1 = v^{n-1}; 1: swapped
+};
+
+template <typename T>
+__host__ __device__ inline Parts<T> make_parts(const InstDesc& d, int set, int vflip) {
+  Parts<T> p;
+  p.x = (T*)d.set[set][0];
+  p.y = (T*)d.set[set][1];
+  for (int c = 0; c < 3; ++c) p.P[c] = (T*)d.set[set][2 + c];
+  const int vb = vflip ? 8 : 5, wb = vflip ? 5 : 8;
+  for (int c = 0; c < 3; ++c) {
+    p.v[c] = (T*)d.set[set][vb + c];
+    p.w[c] = (T*)d.set[set][wb + c];
+  }
+  p.id = d.ids[set];
+  return p;
+}
+
+// instance owning flattened block b of kind k: largest i with D[i].blk[k] <= b
+__device__ __forceinline__ int find_inst(const InstDesc* __restrict__ D, int ninst, int kind, int b) {
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (D[mid].blk[kind] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ---------------------------------------------------------------------------
-// launchers (each returns hipGetLastError() of its launch)
+// launchers (each returns hipGetLastError() of its launches)
 
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
 
-// particles.hip
-hipError_t launch_init_particles(int dtype, void* parts, int64_t n, const double* x,
-                                 const double* y, const double* P, GridP g, PhysP ph,
-                                 hipStream_t s);
-hipError_t launch_deposit(int dtype, int degree, const void* parts, int64_t n, double* J,
-                          GridP g, PhysP ph, hipStream_t s);
-hipError_t launch_gather_push(int dtype, int degree, const void* parts, int64_t n,
-                              const void* F, GridP g, PhysP ph, hipStream_t s);
-hipError_t launch_fused(int dtype, int degree, const void* parts, int64_t n, const void* F,
-                        double* J, GridP g, PhysP ph, hipStream_t s);
-hipError_t launch_get_particles(int dtype, const void* parts, int64_t n, double* out,
-                                hipStream_t s);
-hipError_t launch_set_particles(int dtype, void* parts, int64_t n, const double* in, GridP g,
-                                hipStream_t s);
-hipError_t launch_particle_diag(int dtype, const void* parts, int64_t n, PhysP ph,
-                                double* out2, hipStream_t s);
+// particles.hip: untiled passes (flattened over instances) and per-instance I/O
+// mode: 0 deposit (position update + deposit), 1 gather + push, 2 fused
+hipError_t launch_untiled(int dtype, int mode, int degree, const InstDesc* D, int ninst, int nblocks, StepArgs sa,
+                          hipStream_t s);
+hipError_t launch_init_particles(int dtype, const void* parts, int64_t n, const double* x, const double* y,
+                                 const double* P, GridP g, PhysP ph, hipStream_t s);
+hipError_t launch_get_particles(int dtype, const void* parts, int64_t n, double* out, hipStream_t s);
+hipError_t launch_set_particles(int dtype, const void* parts, int64_t n, const double* in, GridP g, hipStream_t s);
+hipError_t launch_particle_diag(int dtype, const void* parts, int64_t n, PhysP ph, double* out2, hipStream_t s);
 
-// tiles.hip  (mode: 0 deposit, 1 gather+push, 2 fused)
+// tiles.hip
 size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp);
-hipError_t launch_tile_sort(int dtype, const void* src, void* dst, int64_t n, const TileBufs& tb, GridP g,
-                            TileP tp, hipStream_t s);
-hipError_t launch_tiled(int dtype, int mode, int degree, const void* parts, const TileBufs& tb, const void* F,
-                        double* J, GridP g, PhysP ph, TileP tp, hipStream_t s);
+size_t sort_count_lds_bytes(const TileP& tp);
+size_t sort_scatter_lds_bytes(const TileP& tp);
+hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_part, size_t lds_count,
+                            size_t lds_scatter, int src_set, hipStream_t s);
+hipError_t launch_tiled(int dtype, int mode, int degree, const InstDesc* D, int ninst, int nblocks, size_t lds,
+                        StepArgs sa, hipStream_t s);
 
 // field.hip
-size_t fft_twiddle_count(int n);
-void fft_make_twiddles(int n, double* host_re_im);    // n complex entries
-hipError_t launch_rows_r2c(double* J, double2* T, const double2* twx, GridP g, hipStream_t s);
+void fft_make_twiddles(int n, double* host_re_im);  // n complex entries
+int rows_r2c_R(int nx, int ny);
+int rows_c2r_R(int nx, int ny);
+int columns_nb(int ny);
+size_t rows_r2c_lds_bytes(int nx, int ny);
+size_t rows_c2r_lds_bytes(int nx, int ny);
 size_t columns_lds_bytes(int ny);
-hipError_t launch_columns(const double2* T, double2* H, double2* U, const double2* twy,
-                          GridP g, SchemeCoef sc, HistSlots hs, hipStream_t s);
-hipError_t launch_rows_c2r(const double2* U, double* F64, float* F32, const double2* twx,
-                           GridP g, hipStream_t s);
-hipError_t launch_hist_transpose(const double2* src, double2* dst, int nfield, GridP g,
-                                 bool to_external, hipStream_t s);
-hipError_t launch_field_diag(const double2* H, GridP g, SchemeCoef sc, HistSlots hs,
-                             double* out, hipStream_t s);
+hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s);
+hipError_t launch_columns(int scheme, const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
+                          hipStream_t s);
+hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s);
+hipError_t launch_hist_transpose(const double2* src, double2* dst, int nfield, GridP g, bool to_external,
+                                 hipStream_t s);
+hipError_t launch_field_diag(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double* out, hipStream_t s);
 
 }  // namespace pic

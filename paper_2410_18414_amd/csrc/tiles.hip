@@ -33,6 +33,13 @@ __device__ __forceinline__ int tile_of(float xi, float eta, const TileP& tp) {
   return (cy >> tp.log_ts) * tp.ntx + (cx >> tp.log_ts);
 }
 
+template <typename T>
+__device__ __forceinline__ int tile_key(T x, T y, const GridP& g, const TileP& tp) {
+  const float xi = (float)(x * T(g.inv_dx)), eta = (float)(y * T(g.inv_dy));
+  const bool ok = xi == xi && eta == eta;  // non-finite positions go to tile 0
+  return ok ? tile_of(xi, eta, tp) : 0;
+}
+
 // Lanes of one wave that share a key: one LDS atomic per distinct key in the
 // wave (particles are nearly sorted between sorts, so a wave holds few keys).
 // Returns the lane's rank among the wave's lanes with its key, and the value
@@ -58,37 +65,40 @@ __device__ __forceinline__ int wave_group_add(int32_t* __restrict__ counters, in
   return base;
 }
 
+// Tile histogram of the current positions: each block counts 1024 particles
+// of one instance (flattened over instances, BK_COUNT).
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_tile_count(Parts<T> p, int64_t n, int32_t* __restrict__ key,
-                                                         int32_t* __restrict__ count, GridP g, TileP tp) {
-  extern __shared__ int32_t hist[];  // ntiles
+__global__ void __launch_bounds__(kThreads) k_tile_count(const InstDesc* __restrict__ D, int ninst, int set) {
+  extern __shared__ int32_t hist[];  // ntiles of this instance
+  const int ii = find_inst(D, ninst, BK_COUNT, blockIdx.x);
+  const InstDesc& d = D[ii];
+  const TileP tp = d.tp;
+  const GridP g = d.g;
+  const T* __restrict__ px = (const T*)d.set[set][0];
+  const T* __restrict__ py = (const T*)d.set[set][1];
   for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x) hist[t] = 0;
   __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t nloop = (n + stride - 1) / stride * stride;  // whole waves stay in the loop
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nloop; i += stride) {
-    const bool act = i < n;
+  const int64_t base = (int64_t)(blockIdx.x - d.blk[BK_COUNT]) * 1024;
+  for (int k = 0; k < 4; ++k) {  // whole waves stay in the loop
+    const int64_t i = base + k * kThreads + threadIdx.x;
+    const bool act = i < d.n;
     int t = 0;
-    if (act) {
-      const float xi = (float)(p.x[i] * T(g.inv_dx)), eta = (float)(p.y[i] * T(g.inv_dy));
-      const bool ok = xi == xi && eta == eta;  // non-finite positions go to tile 0
-      t = ok ? tile_of(xi, eta, tp) : 0;
-      key[i] = t;
-    }
+    if (act) t = tile_key(px[i], py[i], g, tp);
     int r;
     wave_group_add(hist, t, act, r);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x)
-    if (hist[t]) atomicAdd(&count[t], hist[t]);
+    if (hist[t]) atomicAdd(&d.tb.count[t], hist[t]);
 }
 
-// one block: exclusive scan of the tile counts, cursors, and the chunk list
-__global__ void __launch_bounds__(1024) k_tile_scan(int32_t* __restrict__ count, int32_t* __restrict__ start,
-                                                    int32_t* __restrict__ cursor, int4* __restrict__ work,
-                                                    int32_t* __restrict__ nwork, TileP tp) {
+// one block per instance: exclusive scan of the tile counts, cursors, chunk list
+__global__ void __launch_bounds__(1024) k_tile_scan(const InstDesc* __restrict__ D, int ninst) {
   __shared__ int32_t s_cnt[1024], s_chk[1024];
   __shared__ int32_t carry_p, carry_c;
+  const InstDesc& d = D[blockIdx.x];
+  const TileP tp = d.tp;
+  int32_t* __restrict__ count = d.tb.count;
   if (threadIdx.x == 0) {
     carry_p = 0;
     carry_c = 0;
@@ -113,12 +123,12 @@ __global__ void __launch_bounds__(1024) k_tile_scan(int32_t* __restrict__ count,
     const int p0 = carry_p + s_cnt[threadIdx.x] - c;  // exclusive
     const int k0 = carry_c + s_chk[threadIdx.x] - k;
     if (t < tp.ntiles) {
-      start[t] = p0;
-      cursor[t] = p0;
+      d.tb.start[t] = p0;
+      d.tb.cursor[t] = p0;
       for (int j = 0; j < k; ++j) {
         const int s = p0 + j * tp.chunk;
         const int e = min(p0 + c, s + tp.chunk);
-        work[k0 + j] = make_int4(t, s, e - s, 0);
+        d.tb.work[k0 + j] = make_int4(t, s, e - s, 0);
       }
       count[t] = 0;  // ready for the next sort
     }
@@ -130,41 +140,38 @@ __global__ void __launch_bounds__(1024) k_tile_scan(int32_t* __restrict__ count,
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    start[tp.ntiles] = carry_p;
-    *nwork = carry_c;
+    d.tb.start[tp.ntiles] = carry_p;
+    *d.tb.nwork = carry_c;
   }
 }
 
-// scatter into the other particle set; one global atomic per (block, tile)
+// scatter set `src` into set `src ^ 1`; one global atomic per (block, tile)
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_tile_scatter(Parts<T> src, Parts<T> dst, int64_t n,
-                                                           const int32_t* __restrict__ key,
-                                                           int32_t* __restrict__ cursor, TileP tp) {
+__global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __restrict__ D, int ninst, int src) {
   extern __shared__ int32_t sh[];  // ntiles local counts, then ntiles bases
+  const int ii = find_inst(D, ninst, BK_PART, blockIdx.x);
+  const InstDesc& d = D[ii];
+  const TileP tp = d.tp;
   int32_t* lc = sh;
   int32_t* lb = sh + tp.ntiles;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)(blockIdx.x - d.blk[BK_PART]) * kThreads + threadIdx.x;
   for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x) lc[t] = 0;
   __syncthreads();
-  const bool act = i < n;
-  const int k = act ? key[i] : 0;
+  const bool act = i < d.n;
+  const void* const* S = d.set[src];
+  void* const* Dd = d.set[src ^ 1];
+  const int k = act ? tile_key(((const T*)S[0])[i], ((const T*)S[1])[i], d.g, tp) : 0;
   int rr;
   const int r = wave_group_add(lc, k, act, rr) + rr;
   __syncthreads();
   for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x)
-    lb[t] = lc[t] ? atomicAdd(&cursor[t], lc[t]) : 0;
+    lb[t] = lc[t] ? atomicAdd(&d.tb.cursor[t], lc[t]) : 0;
   __syncthreads();
-  if (i < n) {
+  if (act) {
     const int64_t o = lb[k] + r;
-    dst.x[o] = src.x[i];
-    dst.y[o] = src.y[i];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      dst.P[c][o] = src.P[c][i];
-      dst.v[c][o] = src.v[c][i];
-      dst.w[c][o] = src.w[c][i];
-    }
-    dst.id[o] = src.id[i];
+    for (int a = 0; a < 11; ++a) ((T*)Dd[a])[o] = ((const T*)S[a])[i];
+    d.ids[src ^ 1][o] = d.ids[src][i];
   }
 }
 
@@ -182,14 +189,21 @@ struct Acc {
 };
 
 template <typename T, int DEG, int MODE>
-__global__ void __launch_bounds__(kThreads) k_tiled(Parts<T> p, const int4* __restrict__ work,
-                                                    const int32_t* __restrict__ nwork, const T* __restrict__ F,
-                                                    double* __restrict__ J, GridP g, PhysP ph, TileP tp) {
+__global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__ D, int ninst, StepArgs sa) {
   constexpr bool GATHER = MODE != MODE_DEPOSIT;
   constexpr bool DEPOSIT = MODE != MODE_GATHER_PUSH;
   using A = typename Acc<T>::type;
-  if ((int)blockIdx.x >= *nwork) return;
-  const int4 it = work[blockIdx.x];
+  const int ii = find_inst(D, ninst, BK_WORK, blockIdx.x);
+  const InstDesc& d = D[ii];
+  const int item = blockIdx.x - d.blk[BK_WORK];
+  if (item >= *d.tb.nwork) return;
+  const int4 it = d.tb.work[item];
+  const GridP g = d.g;
+  const PhysP ph = d.ph;
+  const TileP tp = d.tp;
+  const Parts<T> p = make_parts<T>(d, sa.cur, sa.vflip);
+  const T* __restrict__ F = GATHER ? (d.F32 ? (const T*)(const void*)d.F32 : (const T*)(const void*)d.F64) : nullptr;
+  double* __restrict__ J = d.J;
   const int W = tp.win;
   const int WP = tp.win_pad;  // plane stride of the LDS windows (field f at f*WP)
   const int tiy = it.x >> tp.log_ntx, tix = it.x - (tiy << tp.log_ntx);
@@ -309,38 +323,29 @@ __global__ void __launch_bounds__(kThreads) k_tiled(Parts<T> p, const int4* __re
 }
 
 template <typename T, int DEG, int MODE>
-size_t tiled_lds(const TileP& tp) {
-  return (MODE != MODE_DEPOSIT ? (size_t)11 * tp.win_pad * sizeof(T) : 0) +
-         (MODE != MODE_GATHER_PUSH ? (size_t)3 * tp.win_pad * sizeof(typename Acc<T>::type) : 0);
-}
-
-template <typename T, int DEG, int MODE>
-hipError_t launch_tiled_t(const Parts<T>& p, const TileBufs& tb, const T* F, double* J, GridP g, PhysP ph,
-                          TileP tp, hipStream_t s) {
-  const size_t lds = tiled_lds<T, DEG, MODE>(tp);
+hipError_t launch_tiled_t(const InstDesc* D, int ninst, int nblocks, size_t lds, StepArgs sa, hipStream_t s) {
   hipFuncSetAttribute((const void*)k_tiled<T, DEG, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_tiled<T, DEG, MODE>), dim3(tp.max_work), dim3(kThreads), lds, s, p, tb.work, tb.nwork, F,
-                     J, g, ph, tp);
+  hipLaunchKernelGGL((k_tiled<T, DEG, MODE>), dim3(nblocks), dim3(kThreads), lds, s, D, ninst, sa);
   return hipGetLastError();
 }
 
 template <typename T, int MODE>
-hipError_t launch_tiled_deg(int degree, const Parts<T>& p, const TileBufs& tb, const T* F, double* J, GridP g,
-                            PhysP ph, TileP tp, hipStream_t s) {
+hipError_t launch_tiled_deg(int degree, const InstDesc* D, int ninst, int nblocks, size_t lds, StepArgs sa,
+                            hipStream_t s) {
   switch (degree) {
-    case 1: return launch_tiled_t<T, 1, MODE>(p, tb, F, J, g, ph, tp, s);
-    case 2: return launch_tiled_t<T, 2, MODE>(p, tb, F, J, g, ph, tp, s);
-    default: return launch_tiled_t<T, 3, MODE>(p, tb, F, J, g, ph, tp, s);
+    case 1: return launch_tiled_t<T, 1, MODE>(D, ninst, nblocks, lds, sa, s);
+    case 2: return launch_tiled_t<T, 2, MODE>(D, ninst, nblocks, lds, sa, s);
+    default: return launch_tiled_t<T, 3, MODE>(D, ninst, nblocks, lds, sa, s);
   }
 }
 
 template <typename T>
-hipError_t launch_tiled_mode(int mode, int degree, const Parts<T>& p, const TileBufs& tb, const T* F, double* J,
-                             GridP g, PhysP ph, TileP tp, hipStream_t s) {
+hipError_t launch_tiled_mode(int mode, int degree, const InstDesc* D, int ninst, int nblocks, size_t lds,
+                             StepArgs sa, hipStream_t s) {
   switch (mode) {
-    case MODE_DEPOSIT: return launch_tiled_deg<T, MODE_DEPOSIT>(degree, p, tb, F, J, g, ph, tp, s);
-    case MODE_GATHER_PUSH: return launch_tiled_deg<T, MODE_GATHER_PUSH>(degree, p, tb, F, J, g, ph, tp, s);
-    default: return launch_tiled_deg<T, MODE_FUSED>(degree, p, tb, F, J, g, ph, tp, s);
+    case MODE_DEPOSIT: return launch_tiled_deg<T, MODE_DEPOSIT>(degree, D, ninst, nblocks, lds, sa, s);
+    case MODE_GATHER_PUSH: return launch_tiled_deg<T, MODE_GATHER_PUSH>(degree, D, ninst, nblocks, lds, sa, s);
+    default: return launch_tiled_deg<T, MODE_FUSED>(degree, D, ninst, nblocks, lds, sa, s);
   }
 }
 
@@ -351,41 +356,30 @@ size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp) {
   return (mode != MODE_DEPOSIT ? (size_t)11 * tp.win_pad * es : 0) +
          (mode != MODE_GATHER_PUSH ? (size_t)3 * tp.win_pad * 8 : 0);
 }
+size_t sort_count_lds_bytes(const TileP& tp) { return (size_t)tp.ntiles * sizeof(int32_t); }
+size_t sort_scatter_lds_bytes(const TileP& tp) { return (size_t)2 * tp.ntiles * sizeof(int32_t); }
 
-hipError_t launch_tile_sort(int dtype, const void* src, void* dst, int64_t n, const TileBufs& tb, GridP g, TileP tp,
-                            hipStream_t s) {
-  if (n == 0) {
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, tb.count, tb.start, tb.cursor, tb.work, tb.nwork,
-                       tp);
-    return hipGetLastError();
-  }
-  const int blocks = (int)std::min<int64_t>((n + kThreads - 1) / kThreads, 1024);
-  const size_t lds1 = (size_t)tp.ntiles * sizeof(int32_t);
-  const unsigned sblocks = (unsigned)((n + kThreads - 1) / kThreads);
+// count (BK_COUNT blocks), scan (one block per instance), scatter (BK_PART blocks)
+hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_part, size_t lds_count,
+                            size_t lds_scatter, int src_set, hipStream_t s) {
   if (dtype == PIC_F32) {
-    hipLaunchKernelGGL(k_tile_count<float>, dim3(blocks), dim3(kThreads), lds1, s, *(const Parts<float>*)src, n,
-                       tb.key, tb.count, g, tp);
+    if (nb_count) hipLaunchKernelGGL(k_tile_count<float>, dim3(nb_count), dim3(kThreads), lds_count, s, D, ninst, src_set);
   } else {
-    hipLaunchKernelGGL(k_tile_count<double>, dim3(blocks), dim3(kThreads), lds1, s, *(const Parts<double>*)src, n,
-                       tb.key, tb.count, g, tp);
+    if (nb_count) hipLaunchKernelGGL(k_tile_count<double>, dim3(nb_count), dim3(kThreads), lds_count, s, D, ninst, src_set);
   }
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, tb.count, tb.start, tb.cursor, tb.work, tb.nwork, tp);
+  hipLaunchKernelGGL(k_tile_scan, dim3(ninst), dim3(1024), 0, s, D, ninst);
   if (dtype == PIC_F32) {
-    hipLaunchKernelGGL(k_tile_scatter<float>, dim3(sblocks), dim3(kThreads), 2 * lds1, s, *(const Parts<float>*)src,
-                       *(Parts<float>*)dst, n, tb.key, tb.cursor, tp);
+    if (nb_part) hipLaunchKernelGGL(k_tile_scatter<float>, dim3(nb_part), dim3(kThreads), lds_scatter, s, D, ninst, src_set);
   } else {
-    hipLaunchKernelGGL(k_tile_scatter<double>, dim3(sblocks), dim3(kThreads), 2 * lds1, s,
-                       *(const Parts<double>*)src, *(Parts<double>*)dst, n, tb.key, tb.cursor, tp);
+    if (nb_part) hipLaunchKernelGGL(k_tile_scatter<double>, dim3(nb_part), dim3(kThreads), lds_scatter, s, D, ninst, src_set);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_tiled(int dtype, int mode, int degree, const void* parts, const TileBufs& tb, const void* F,
-                        double* J, GridP g, PhysP ph, TileP tp, hipStream_t s) {
-  if (dtype == PIC_F32)
-    return launch_tiled_mode<float>(mode, degree, *(const Parts<float>*)parts, tb, (const float*)F, J, g, ph, tp, s);
-  return launch_tiled_mode<double>(mode, degree, *(const Parts<double>*)parts, tb, (const double*)F, J, g, ph, tp,
-                                   s);
+hipError_t launch_tiled(int dtype, int mode, int degree, const InstDesc* D, int ninst, int nblocks, size_t lds,
+                        StepArgs sa, hipStream_t s) {
+  if (dtype == PIC_F32) return launch_tiled_mode<float>(mode, degree, D, ninst, nblocks, lds, sa, s);
+  return launch_tiled_mode<double>(mode, degree, D, ninst, nblocks, lds, sa, s);
 }
 
 }  // namespace pic

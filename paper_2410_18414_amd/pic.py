@@ -35,7 +35,8 @@ EXPORTS = ("pic_workspace_bytes", "pic_create", "pic_destroy", "pic_last_error",
            "init_particles", "deposit_current", "field_solve", "gather_push", "step",
            "pic_get_particles", "pic_set_particles", "pic_get_field", "pic_history_fields",
            "pic_get_history", "pic_set_history", "pic_diagnostics", "pic_set_kernel_timing",
-           "pic_kernel_timing")
+           "pic_kernel_timing", "pic_batch_workspace_bytes", "pic_batch_create",
+           "pic_instance_count", "pic_select_instance", "step_batched")
 KCLASSES = ("deposit", "field_solve", "gather_push", "fused", "sort")
 
 
@@ -90,6 +91,11 @@ def load():
         "pic_diagnostics": (I32, [P, ctypes.POINTER(D)]),
         "pic_set_kernel_timing": (I32, [P, I32]),
         "pic_kernel_timing": (I32, [P, ctypes.POINTER(D)]),
+        "pic_batch_workspace_bytes": (SZ, [cfgp, I32]),
+        "pic_batch_create": (I32, [cfgp, I32, P, SZ, P, ctypes.POINTER(P)]),
+        "pic_instance_count": (I32, [P]),
+        "pic_select_instance": (I32, [P, I32]),
+        "step_batched": (I32, [P, I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -132,24 +138,47 @@ def _ptr(t):
 
 
 class Context:
-    """Owns the torch workspace tensor and the libpic context."""
+    """Owns the torch workspace tensor and the libpic context.
+
+    `cfg` is one ConfigStruct (plain) or a list of them (an ensemble)."""
 
     def __init__(self, cfg, device="cuda", stream=None):
         lib = load()
-        self.cfg = cfg
+        cfgs = list(cfg) if isinstance(cfg, (list, tuple)) else [cfg]
+        arr = (ConfigStruct * len(cfgs))(*cfgs)
+        self.cfgs = cfgs
+        self.cfg = cfgs[0]
         self.device = torch.device(device)
-        nbytes = workspace_bytes(cfg)
+        if len(cfgs) == 1:
+            nbytes = workspace_bytes(cfgs[0])
+        else:
+            nbytes = lib.pic_batch_workspace_bytes(arr, len(cfgs))
+            if nbytes == 0:
+                raise PicError(1, lib.pic_last_error(None).decode())
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         off = (-base) % 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        st = lib.pic_create(ctypes.byref(cfg), ctypes.c_void_p(base + off), nbytes,
-                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if len(cfgs) == 1:
+            st = lib.pic_create(ctypes.byref(cfgs[0]), ctypes.c_void_p(base + off), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        else:
+            st = lib.pic_batch_create(arr, len(cfgs), ctypes.c_void_p(base + off), nbytes,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != 0:
             raise PicError(st, lib.pic_last_error(None).decode())
         self.handle = h
-        self.n = 0
+        self.ns = [0] * len(cfgs)
+        self.sel = 0
+
+    @property
+    def n(self):
+        return self.ns[self.sel]
+
+    @n.setter
+    def n(self, v):
+        self.ns[self.sel] = v
 
     def check(self, st):
         if st != 0:
@@ -168,11 +197,11 @@ class Context:
 
     @property
     def nx(self):
-        return self.cfg.nx
+        return self.cfgs[self.sel].nx
 
     @property
     def ny(self):
-        return self.cfg.ny
+        return self.cfgs[self.sel].ny
 
 
 # ---------------------------------------------------------------------------
@@ -206,6 +235,19 @@ def step(ctx, nsteps=1):
     ctx.check(load().step(ctx.handle, int(nsteps)))
 
 
+def select_instance(ctx, index):
+    ctx.check(load().pic_select_instance(ctx.handle, int(index)))
+    ctx.sel = int(index)
+
+
+def instance_count(ctx):
+    return load().pic_instance_count(ctx.handle)
+
+
+def step_batched(ctx, nsteps=1):
+    ctx.check(load().step_batched(ctx.handle, int(nsteps)))
+
+
 def get_particles(ctx):
     out = torch.empty((11, ctx.n), dtype=torch.float64, device=ctx.device)
     ctx.check(load().pic_get_particles(ctx.handle, _ptr(out)))
@@ -227,14 +269,14 @@ def get_field(ctx, which):
 
 
 def get_history(ctx):
-    nf = history_fields(ctx.cfg)
+    nf = history_fields(ctx.cfgs[ctx.sel])
     out = torch.empty((nf, ctx.ny, ctx.nx // 2 + 1), dtype=torch.complex128, device=ctx.device)
     ctx.check(load().pic_get_history(ctx.handle, _ptr(out)))
     return out
 
 
 def set_history(ctx, hist):
-    nf = history_fields(ctx.cfg)
+    nf = history_fields(ctx.cfgs[ctx.sel])
     hist = hist.to(ctx.device, torch.complex128).contiguous()
     assert hist.shape == (nf, ctx.ny, ctx.nx // 2 + 1)
     ctx._inputs = (hist,)

@@ -72,3 +72,16 @@ def test_null_context_calls_fail_cleanly():
     for name in ("deposit_current", "field_solve", "gather_push"):
         assert getattr(lib, name)(None) == 1
     assert lib.step(None, 1) == 1
+
+
+def test_batch_config_rules_without_gpu():
+    lib = pic.load()
+    a = _cfg(nx=32, ny=32)
+    b = _cfg(nx=64, ny=16, max_particles=500)
+    arr = (pic.ConfigStruct * 2)(a, b)
+    assert lib.pic_batch_workspace_bytes(arr, 2) > 0
+    c = _cfg(scheme="cdf2")
+    arr2 = (pic.ConfigStruct * 2)(a, c)
+    assert lib.pic_batch_workspace_bytes(arr2, 2) == 0
+    assert b"share" in lib.pic_last_error(None)
+    assert lib.pic_batch_workspace_bytes(arr, 0) == 0
