@@ -20,7 +20,10 @@
  *                    shift the history.
  *   step             nsteps x (deposit_current, field_solve, gather_push),
  *                    with the gather/push of step n fused with the deposit of
- *                    step n+1 (same results).
+ *                    step n+1 (same results).  Its launches repeat with a
+ *                    period of a few steps; step() captures one period into a
+ *                    HIP graph (on an internal stream) and replays it on the
+ *                    context's stream.
  *
  * Conventions
  *   - Pointers are DEVICE pointers unless marked [host].  Work is enqueued
@@ -69,6 +72,7 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
 /* flags */
 #define PIC_FLAG_NO_SORT 1u      /* never reorder particles by tile            */
 #define PIC_FLAG_UNFUSED_STEP 2u /* step() runs the three calls separately     */
+#define PIC_FLAG_NO_GRAPH 4u     /* step() never replays a captured HIP graph    */
 
 typedef struct {                /* [host] */
   int32_t abi_version;          /* == PIC_ABI_VERSION                                    */

@@ -23,6 +23,7 @@ SCHEMES = {"bdf": 0, "cdf2": 1, "dirk2": 2}
 DTYPES = {"f32": 0, "f64": 1}
 FLAG_NO_SORT = 1
 FLAG_UNFUSED_STEP = 2
+FLAG_NO_GRAPH = 4
 FIELD_J = 0
 FIELD_MESH = 1
 DIAG_NAMES = ("gauge_l2", "gauge_scale", "gauss_l2", "gauss_scale", "charge", "energy",

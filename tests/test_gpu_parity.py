@@ -264,3 +264,23 @@ def test_full_size_weibel_one_step_f32(gpu_lib):
     assert not bad, errs
     d = pic.diagnostics(ctx)
     assert d["gauge_l2"] <= 1e3 * EPS * d["gauge_scale"]
+
+
+@pytest.mark.parametrize("scheme,k", [("bdf", 2), ("cdf2", 2), ("dirk2", 2)])
+def test_graph_replay_matches_oracle_and_direct(gpu_lib, scheme, k):
+    """step() replays captured HIP graphs for long calls; results are those of
+    direct launches and of the oracle."""
+    w = cloud_small(seed=51)
+    o = make_oracle(w, 2, scheme, k)
+    g = make_gpu(w, 2, scheme, "f64", bdf_order=k)
+    d = make_gpu(w, 2, scheme, "f64", bdf_order=k, flags=pic.FLAG_NO_GRAPH)
+    for n in (40, 7, 25):   # uneven call lengths: capture, replay, remainder
+        o.step(n)
+        pic.step(g, n)
+        pic.step(d, n)
+    pg, pd = gpu_parts(g), gpu_parts(d)
+    for key in pg:
+        assert rel(pg[key], pd[key]) <= 1e-12, key
+    errs, bad = compare_particles(pg, o.part, w["lx"], w["ly"], 1e-10)
+    assert not bad, errs
+    assert rel(pic.get_history(g).cpu().numpy(), hist_to_flat(o.p, o.hist)) <= 1e-10
