@@ -73,6 +73,7 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
 #define PIC_FLAG_NO_SORT 1u      /* never reorder particles by tile            */
 #define PIC_FLAG_UNFUSED_STEP 2u /* step() runs the three calls separately     */
 #define PIC_FLAG_NO_GRAPH 4u     /* step() never replays a captured HIP graph    */
+#define PIC_FLAG_ADJOINT 8u      /* reserve the adjoint buffers (step_adjoint)   */
 
 typedef struct {                /* [host] */
   int32_t abi_version;          /* == PIC_ABI_VERSION                                    */
@@ -136,8 +137,9 @@ pic_status_t step(pic_ctx_t ctx, int32_t nsteps);
 /* Particle state in the ORIGINAL particle order, float64 device out[11 n]:
  * blocks x, y, Px, Py, Pz, vx^n, vy^n, vz^n, vx^{n-1}, vy^{n-1}, vz^{n-1}. */
 pic_status_t pic_get_particles(pic_ctx_t ctx, double* out);
-/* Replace the particle state (same layout, original order); phase -> READY.
- * Values are rounded to the particle dtype; positions are wrapped. */
+/* Replace the particle state (same layout, original order) in phase READY or
+ * SOLVED; phase -> READY.  Values are rounded to the particle dtype; positions
+ * are wrapped. */
 pic_status_t pic_set_particles(pic_ctx_t ctx, const double* in);
 
 /* Real mesh fields, float64 device dst:
@@ -172,9 +174,8 @@ pic_status_t pic_set_history(pic_ctx_t ctx, const double* src);
 pic_status_t pic_diagnostics(pic_ctx_t ctx, double* out);
 
 /* ---- Ensembles (batched instances) ----------------------------------------
- * A context may hold ninst independent instances of the method: the ensemble
- * of SURVEY-style uneven workloads (different grids, particle counts, time
- * steps).  They must share scheme, bdf_order, particle_dtype, spline_degree,
+ * A context may hold ninst independent instances of the method: an ensemble
+ * of uneven workloads (different grids, particle counts, time steps).  They must share scheme, bdf_order, particle_dtype, spline_degree,
  * flags and c, eps0, mu0.  Every hot-path kernel then covers all instances in
  * one launch per phase (a flattened grid), and the instances advance in
  * lockstep: deposit_current, field_solve, gather_push, step and step_batched
@@ -189,6 +190,45 @@ int32_t pic_instance_count(pic_ctx_t ctx);
 pic_status_t pic_select_instance(pic_ctx_t ctx, int32_t index);
 /* nsteps complete steps of every instance (the same as step()). */
 pic_status_t step_batched(pic_ctx_t ctx, int32_t nsteps);
+
+/* ---- Discrete adjoint (reverse mode) -------------------------------------
+ * The exact transpose of one step's Jacobian, for gradients of a function of
+ * the final state with respect to the initial particles.  Float64 particles,
+ * the BDF-k stepper (Sec. 3.2), single-instance contexts created with
+ * PIC_FLAG_ADJOINT (else PIC_ERR_UNSUPPORTED).  A state S^n is the particle
+ * arrays of pic_get_particles plus the history of pic_get_history.
+ *
+ * Adjoint state (device float64, caller-owned, updated in place):
+ *   lam       [11][n]  d(loss)/d(particle state), the pic_get_particles layout
+ *                      and original particle order
+ *   lam_hist  [pic_history_fields][ny][nx/2+1] complex (re, im pairs):
+ *                      d(loss)/d(history), the pic_get_history layout; the
+ *                      adjoint of a complex value z is dL/dRe z + i dL/dIm z.
+ *
+ * adjoint_seed_energy: phase READY.  lam_hist = scale * dW/d(history) for the
+ * field energy W of the newest level (pic_diagnostics out[5]: E from the
+ * BDF-k time derivative of A, Sec. 2.2 and 3.2).  The particle adjoint of W is
+ * zero (the caller clears lam).
+ *
+ * step_adjoint: phase READY with the context holding S^n.  Recomputes the
+ * position update, deposit and field solve of step n -> n+1 (as
+ * deposit_current + field_solve; phase -> SOLVED afterwards, so the caller
+ * reloads the next state with pic_set_particles and pic_set_history), then
+ * maps (lam, lam_hist) = lambda^{n+1} to lambda^n = (dS^{n+1}/dS^n)^T
+ * lambda^{n+1}: the push and gather adjoint (a scatter onto the 11 gathered
+ * mesh fields; spline derivative weights for the position), the field-solve
+ * adjoint (conjugate transforms and the transposed per-mode BDF recurrence)
+ * and the deposit adjoint (a gather of d/dJ with spline and derivative
+ * weights).  Wrap-around of positions counts as the identity.
+ *
+ * adjoint_initial: any loaded phase.  Maps the adjoint of S^0 to the adjoint of
+ * the init_particles inputs, P0 [3n] as given to init_particles (original
+ * order): lam[Px..Pz] += (dv^0/dP)^T (lam[v^n] + lam[v^{n-1}]) (both start at
+ * v^0), then the velocity blocks of lam are cleared; lam[x], lam[y] are
+ * already d/dx0, d/dy0. */
+pic_status_t adjoint_seed_energy(pic_ctx_t ctx, double scale, double* lam_hist);
+pic_status_t step_adjoint(pic_ctx_t ctx, double* lam, double* lam_hist);
+pic_status_t adjoint_initial(pic_ctx_t ctx, const double* P0, double* lam);
 
 /* Kernel timing with HIP events recorded on the context's stream around each
  * launch group (for roofline reporting; adds an event pair per launch).

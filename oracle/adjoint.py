@@ -13,8 +13,9 @@ B = curl A) with the BDF-k time derivative of Sec. 3.2:
     E = -grad phi^n - (1/dt) sum_j a_j A^{n-j},  B = curl A^n.
 
 Pins (tests/test_oracle_adjoint.py): the forward equals the numpy oracle to
-round-off, and the gradients equal central finite differences of the same
-forward.
+round-off; the gradients equal central finite differences of the same
+forward; the one-step vector-Jacobian product passes the dot-product test
+against directional differences of the numpy oracle's step.
 """
 
 import numpy as np
@@ -138,23 +139,96 @@ def cold_history(pr):
                 A=[torch.zeros((3,) + p.spec_shape, dtype=torch.complex128) for _ in range(2 * k)])
 
 
+def step_from(pr, x, y, P, v, vp, hist):
+    """One step of Algorithm 1 from the state (x^n, P^n, v^n, v^{n-1}, history)."""
+    p = pr.p
+    x = wrap(x + v[:, 0] * p.dt, p.lx)
+    y = wrap(y + v[:, 1] * p.dt, p.ly)
+    J = deposit(pr, x, y, v)
+    Jh = torch.stack([torch.fft.rfft2(J[c]) for c in range(3)])
+    hist, phi, A = bdf_update(pr, hist, Jh)
+    F = fields(pr, phi, A)
+    g = gather(pr, F, x, y)
+    P, vn = push(pr, P, v, vp, g)
+    return x, y, P, vn, v, hist
+
+
 def run(pr, x, y, P, nsteps):
     """Forward from x^0, P^0 (A^0 = 0, v^{-1} = v^0, cold history)."""
-    p = pr.p
     v = velocity(pr, P, torch.zeros_like(P))
     vp = v
     hist = cold_history(pr)
     for _ in range(nsteps):
-        x = wrap(x + v[:, 0] * p.dt, p.lx)
-        y = wrap(y + v[:, 1] * p.dt, p.ly)
-        J = deposit(pr, x, y, v)
-        Jh = torch.stack([torch.fft.rfft2(J[c]) for c in range(3)])
-        hist, phi, A = bdf_update(pr, hist, Jh)
-        F = fields(pr, phi, A)
-        g = gather(pr, F, x, y)
-        P, vn = push(pr, P, v, vp, g)
-        vp, v = v, vn
+        x, y, P, v, vp, hist = step_from(pr, x, y, P, v, vp, hist)
     return dict(x=x, y=y, P=P, v=v, vprev=vp, hist=hist)
+
+
+def _hist_leaves(hist):
+    """numpy history dict -> torch leaves (requires_grad) in the same structure."""
+    mk = lambda a: torch.tensor(a, dtype=torch.complex128, requires_grad=True)  # noqa: E731
+    return dict(rho=[mk(a) for a in hist["rho"]], phi=[mk(a) for a in hist["phi"]],
+                A=[mk(a) for a in hist["A"]])
+
+
+def _hist_flat(hist):
+    """History dict -> list of per-field tensors in the exported order (rho levels,
+    phi levels, then A levels with their three components)."""
+    out = list(hist["rho"]) + list(hist["phi"])
+    for A in hist["A"]:
+        out += [A[0], A[1], A[2]]
+    return out
+
+
+def _pairing(lam, z):
+    """Real inner product <lam, z> = sum Re(conj(lam) z)."""
+    if torch.is_complex(z):
+        return (torch.conj(lam) * z).real.sum()
+    return (lam * z).sum()
+
+
+def step_vjp(p: pic.Params, part, hist, lam_part, lam_hist):
+    """(dS^{n+1}/dS^n)^T lambda for one step from the numpy state (part: x, y,
+    P, v, vprev as in oracle/pic.py; hist: its history dict).  lam_part has
+    the same keys; lam_hist is [nfield, ny, nx/2+1] complex in the exported
+    order.  Complex adjoints use dL/dRe + i dL/dIm (torch's convention).
+    Returns (lam_part_n, lam_hist_n) in the same forms."""
+    pr = Problem(p)
+    t = lambda a: torch.tensor(np.asarray(a), dtype=T, requires_grad=True)  # noqa: E731
+    x, y, P, v, vp = t(part["x"]), t(part["y"]), t(part["P"]), t(part["v"]), t(part["vprev"])
+    h = _hist_leaves(hist)
+    xo, yo, Po, vo, vpo, ho = step_from(pr, x, y, P, v, vp, h)
+    L = 0.0
+    for key, z in (("x", xo), ("y", yo), ("P", Po), ("v", vo), ("vprev", vpo)):
+        L = L + _pairing(torch.tensor(np.asarray(lam_part[key]), dtype=T), z)
+    lh = torch.tensor(np.asarray(lam_hist), dtype=torch.complex128)
+    for f, z in enumerate(_hist_flat(ho)):
+        L = L + _pairing(lh[f], z)
+    # A levels are leaves of shape (3, ny, nxh): differentiate the leaves, then split
+    leaves = [x, y, P, v, vp] + list(h["rho"]) + list(h["phi"]) + list(h["A"])
+    g = torch.autograd.grad(L, leaves, allow_unused=True)
+    g = [torch.zeros_like(a) if gi is None else gi for a, gi in zip(leaves, g)]
+    out = dict(x=g[0].numpy(), y=g[1].numpy(), P=g[2].numpy(), v=g[3].numpy(), vprev=g[4].numpy())
+    k = p.bdf_order
+    rho_g, phi_g, A_g = g[5:5 + k], g[5 + k:5 + 3 * k], g[5 + 3 * k:]
+    flat = [a.numpy() for a in rho_g] + [a.numpy() for a in phi_g]
+    for A in A_g:
+        flat += [A[0].numpy(), A[1].numpy(), A[2].numpy()]
+    return out, np.stack(flat)
+
+
+def energy_hist_grad(p: pic.Params, hist):
+    """dW/d(history) of the field energy of the newest level, [nfield, ny, nx/2+1]."""
+    pr = Problem(p)
+    h = _hist_leaves(hist)
+    W = energy(pr, h)
+    leaves = list(h["rho"]) + list(h["phi"]) + list(h["A"])
+    g = torch.autograd.grad(W, leaves, allow_unused=True)
+    g = [torch.zeros_like(a) if gi is None else gi for a, gi in zip(leaves, g)]
+    k = p.bdf_order
+    flat = [a.numpy() for a in g[:3 * k]]
+    for A in g[3 * k:]:
+        flat += [A[0].numpy(), A[1].numpy(), A[2].numpy()]
+    return np.stack(flat)
 
 
 def energy(pr, hist):
@@ -181,7 +255,7 @@ def loss_and_grad(p: pic.Params, x, y, P, nsteps):
     out = run(pr, xt, yt, Pt, nsteps)
     W = energy(pr, out["hist"])
     gx, gy, gP = torch.autograd.grad(W, (xt, yt, Pt))
-    return float(W), gx.numpy(), gy.numpy(), gP.numpy()
+    return float(W.detach()), gx.detach().numpy(), gy.detach().numpy(), gP.detach().numpy()
 
 
 def loss(p: pic.Params, x, y, P, nsteps):

@@ -1,0 +1,430 @@
+// Discrete adjoint of one BDF-k step (Algorithm 1 with the BDF-k update of
+// Sec. 3.2), float64, one instance.  Given the step's recomputed forward
+// quantities and the adjoint lambda^{n+1} of its outputs, these kernels form
+// lambda^n = (d S^{n+1} / d S^n)^T lambda^{n+1}; the state S^n is the particle
+// arrays (x, y, P, v^n, v^{n-1}) and the spectral history.
+//
+// The sweep runs the forward phases backwards:
+//   k_adj_push     push and gather adjoint: v' = c^2 u / s (Sec. 2.2) has the
+//                  symmetric Jacobian (c^2/s)(I - c^2 u u^T / s^2); the IAEM
+//                  force (Sec. 4.1) is linear in the gathered values; the
+//                  gather's adjoint scatters lambda_g onto the 11 mesh fields
+//                  with the same spline weights and gives lambda_x through the
+//                  spline derivative.
+//   k_rows_r2c(adj), k_adj_columns, k_rows_c2r(adj)
+//                  field-solve adjoint: the real-to-complex transforms of the
+//                  11 mesh-field adjoints, the conjugate spectral symbols, the
+//                  transposed per-mode BDF recurrence (continuity, both
+//                  Helmholtz solves and the history shift), then the adjoint
+//                  of J^ = rfft2(J), which is N irfft2(lambda_J^ / w).
+//   k_adj_deposit  deposit adjoint: a gather of lambda_J with the spline
+//                  weights (lambda_v) and their derivatives (lambda_x), then
+//                  the position update x' = x + v dt.
+//
+// Complex adjoints follow the real-pair convention lambda_z = dL/dRe z + i
+// dL/dIm z, so a complex-linear map y = s z transposes to lambda_z = conj(s)
+// lambda_y.  For a real field F = irfft2(Z) the adjoint is lambda_Z =
+// (w_kx / N) rfft2(lambda_F) with w = 1 on the kx = 0 and kx = nx/2 columns
+// and 2 elsewhere.
+//
+// Adjoint particle state lam[11][n] (original particle order, like
+// pic_get_particles): x, y, Px, Py, Pz, v^n (3), v^{n-1} (3).
+#include "fft_lds.h"
+#include "particle_math.h"
+
+#include <algorithm>
+
+namespace pic {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// push + gather adjoint.  Particle arrays hold x^{n+1} (recomputed), P^n, v^n
+// and v^{n-1}; F64 holds the mesh fields of level n+1.
+template <int DEG>
+__global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D, StepArgs sa, double* __restrict__ lam) {
+  using S = Spline<double, DEG>;
+  const InstDesc& d = D[0];
+  const int64_t n = d.n;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const GridP g = d.g;
+  const PhysP ph = d.ph;
+  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
+  const int64_t o = p.id[i];
+  const size_t plane = (size_t)g.nx * g.ny;
+  const double* __restrict__ F = d.F64;
+  const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
+  const bool inside = in_box(xi, eta, g);
+  int sx = 0, sy = 0;
+  double wx[S::NW], dwx[S::NW], wy[S::NW], dwy[S::NW];
+  double gv[11], gdx[11], gdy[11];
+#pragma unroll
+  for (int f = 0; f < 11; ++f) gv[f] = gdx[f] = gdy[f] = 0.0;
+  if (inside) {
+    S::eval_d(xi, sx, wx, dwx);
+    S::eval_d(eta, sy, wy, dwy);
+#pragma unroll
+    for (int b = 0; b < S::NW; ++b) {
+      const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
+      double aw[11], ad[11];
+#pragma unroll
+      for (int f = 0; f < 11; ++f) aw[f] = ad[f] = 0.0;
+#pragma unroll
+      for (int a = 0; a < S::NW; ++a) {
+        const size_t m = row + wrapi(sx + a, g.nx);
+#pragma unroll
+        for (int f = 0; f < 11; ++f) {
+          const double v = F[f * plane + m];
+          aw[f] += wx[a] * v;
+          ad[f] += dwx[a] * v;
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < 11; ++f) {
+        gv[f] += wy[b] * aw[f];
+        gdx[f] += wy[b] * ad[f];
+        gdy[f] += dwy[b] * aw[f];
+      }
+    }
+  }
+  // forward push (IAEM) with its intermediates
+  const double q = ph.q, dt = ph.dt, c2 = ph.c * ph.c, mc2 = ph.m * c2;
+  const double v0 = p.v[0][i], v1 = p.v[1][i], v2 = p.v[2][i];
+  const double s0 = 2.0 * v0 - p.w[0][i], s1 = 2.0 * v1 - p.w[1][i], s2 = 2.0 * v2 - p.w[2][i];
+  const double Fx = -gv[0] + s0 * gv[5] + s1 * gv[6] + s2 * gv[7];
+  const double Fy = -gv[1] + s0 * gv[8] + s1 * gv[9] + s2 * gv[10];
+  const double ux = p.P[0][i] + q * Fx * dt - q * gv[2];
+  const double uy = p.P[1][i] + q * Fy * dt - q * gv[3];
+  const double uz = p.P[2][i] - q * gv[4];
+  const double ss = sqrt(c2 * (ux * ux + uy * uy + uz * uz) + mc2 * mc2);
+  // adjoint of v' = c^2 u / ss
+  const double lvx = lam[5 * n + o], lvy = lam[6 * n + o], lvz = lam[7 * n + o];
+  const double ud = (ux * lvx + uy * lvy + uz * lvz) * c2 / (ss * ss);
+  const double k1 = c2 / ss;
+  const double lux = k1 * (lvx - ud * ux), luy = k1 * (lvy - ud * uy), luz = k1 * (lvz - ud * uz);
+  // P' = P + q dt (Fx, Fy, 0), u = P' - q A
+  const double lPx = lam[2 * n + o] + lux, lPy = lam[3 * n + o] + luy, lPz = lam[4 * n + o] + luz;
+  const double lFx = q * dt * lPx, lFy = q * dt * lPy;
+  double lg[11];
+  lg[0] = -lFx;
+  lg[1] = -lFy;
+  lg[2] = -q * lux;
+  lg[3] = -q * luy;
+  lg[4] = -q * luz;
+  lg[5] = lFx * s0;
+  lg[6] = lFx * s1;
+  lg[7] = lFx * s2;
+  lg[8] = lFy * s0;
+  lg[9] = lFy * s1;
+  lg[10] = lFy * s2;
+  // v* = 2 v^n - v^{n-1}
+  const double lsx = lFx * gv[5] + lFy * gv[8];
+  const double lsy = lFx * gv[6] + lFy * gv[9];
+  const double lsz = lFx * gv[7] + lFy * gv[10];
+  double lxg = 0.0, lyg = 0.0;
+#pragma unroll
+  for (int f = 0; f < 11; ++f) {
+    lxg += lg[f] * gdx[f];
+    lyg += lg[f] * gdy[f];
+  }
+  lam[o] += lxg * g.inv_dx;  // lambda of x^{n+1}, deposit part still to come
+  lam[n + o] += lyg * g.inv_dy;
+  lam[2 * n + o] = lPx;  // final: P enters only through P'
+  lam[3 * n + o] = lPy;
+  lam[4 * n + o] = lPz;
+  // v^n: the outgoing v^{n-1} slot of S^{n+1} is v^n itself, plus 2 lambda_v*
+  lam[5 * n + o] = lam[8 * n + o] + 2.0 * lsx;
+  lam[6 * n + o] = lam[9 * n + o] + 2.0 * lsy;
+  lam[7 * n + o] = lam[10 * n + o] + 2.0 * lsz;
+  lam[8 * n + o] = -lsx;
+  lam[9 * n + o] = -lsy;
+  lam[10 * n + o] = -lsz;
+  if (!inside) return;
+  double* __restrict__ LF = d.LF;
+#pragma unroll
+  for (int b = 0; b < S::NW; ++b) {
+    const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
+#pragma unroll
+    for (int a = 0; a < S::NW; ++a) {
+      const size_t m = row + wrapi(sx + a, g.nx);
+      const double w = wx[a] * wy[b];
+#pragma unroll
+      for (int f = 0; f < 11; ++f) atomicAdd(LF + f * plane + m, lg[f] * w);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// columns of the field-solve adjoint: one block per kx.
+// In:  LS[f][kx][y]   x-transforms of the 11 mesh-field adjoints
+//      lamH           adjoint of the history after the update (external
+//                     layout [field][ky][kx]; BDF-k order: rho (k levels),
+//                     phi (2k), A (2k levels x 3 components))
+// Out: lamH           adjoint of the history before the update (in place)
+//      LS[c][kx][y]   c < 3: y-inverse transforms of lambda_J^ / w
+// Mesh field f is irfft2(sigma_f X_src(f)) with X = phi or A_l and sigma one
+// of 1, i kx, i ky (the forward column and row kernels); its adjoint adds
+// conj(sigma_f) (w / N) rfft2(lambda_F_f) to lambda_X.
+__constant__ int kAdjSrc[11] = {0, 0, 1, 2, 3, 1, 2, 3, 1, 2, 3};  // 0 phi, 1..3 A_l
+__constant__ int kAdjSym[11] = {1, 2, 0, 0, 0, 1, 1, 1, 2, 2, 2};  // 0: 1, 1: i kx, 2: i ky
+
+__global__ void __launch_bounds__(256) k_adj_columns(const InstDesc* __restrict__ D, double2* __restrict__ lamH) {
+  // LDS: acc [0, 4N) = lambda of phi^{n+1}, A_l^{n+1} from the mesh fields;
+  // work buffers from 4N: 2 x NB*N (forward batches), 2 x 3N (inverse)
+  extern __shared__ double2 sm[];
+  const InstDesc& d = D[0];
+  const GridP g = d.g;
+  const SchemeCoef sc = d.sc;
+  const int kx = blockIdx.x;
+  const int N = g.ny, NB = d.nb_col, nxh = g.nxh;
+  double2* __restrict__ LS = d.LS;
+  double2* acc = sm;
+  double2* wk = sm + 4 * N;
+  const double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
+  const double norm = wgt / ((double)g.nx * g.ny);
+  const double kxs = kx_sym(kx, g);
+  for (int t = threadIdx.x; t < 4 * N; t += blockDim.x) acc[t] = make_double2(0.0, 0.0);
+  for (int f0 = 0; f0 < 11; f0 += NB) {
+    const int nb = min(NB, 11 - f0);
+    for (int t = threadIdx.x; t < nb * N; t += blockDim.x) {
+      const int qf = t / N, y = t - qf * N;
+      wk[t] = LS[((size_t)(f0 + qf) * nxh + kx) * N + y];
+    }
+    __syncthreads();
+    const double2* res = fft_lds<false>(wk, wk + nb * N, N, nb, d.twy);
+    // each thread owns its ky entries of acc: the field loop is serial
+    for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
+      const double kys = ky_sym(ky, g);
+      for (int qf = 0; qf < nb; ++qf) {
+        const int f = f0 + qf;
+        double2 z = cscale(res[qf * N + ky], norm);
+        const int sy = kAdjSym[f];
+        if (sy == 1) z = mul_mi(cscale(z, kxs));       // conj(i kx) = -i kx
+        else if (sy == 2) z = mul_mi(cscale(z, kys));  // conj(i ky) = -i ky
+        double2& a = acc[kAdjSrc[f] * N + ky];
+        a = cadd(a, z);
+      }
+    }
+    __syncthreads();
+  }
+  // transposed per-mode BDF-k update.  Forward (per mode, Lh = 1 + kappa/alpha^2):
+  //   rho' = -(sum_{j=1..k} a_j R_{j-1} + dt i k.J^) / a_0
+  //   phi' = (rho' / (eps0 alpha^2) - sum_{i=1..2k} Cn_i Phi_{i-1}) / Lh
+  //   A'_l = (mu0 J^_l / alpha^2 - sum_{i=1..2k} Cn_i A_{i-1,l}) / Lh
+  //   history shift: R <- (rho', R_0 .. R_{k-2}), Phi and A likewise
+  const int k = sc.k;
+  const size_t fstride = (size_t)N * nxh;
+  for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
+    const double kys = ky_sym(ky, g);
+    const double Lh = 1.0 + (kxs * kxs + kys * kys) * sc.inv_alpha2;
+    double2* h = lamH + (size_t)ky * nxh + kx;
+    auto R = [&](int j) -> double2& { return h[(size_t)j * fstride]; };
+    auto Ph = [&](int j) -> double2& { return h[(size_t)(k + j) * fstride]; };
+    auto Al = [&](int j, int l) -> double2& { return h[(size_t)(3 * k + 3 * j + l) * fstride]; };
+    const double2 lphi = cadd(Ph(0), acc[ky]);
+    double2 lA[3];
+    for (int l = 0; l < 3; ++l) lA[l] = cadd(Al(0, l), acc[(1 + l) * N + ky]);
+    const double2 lrho = cadd(R(0), cscale(lphi, sc.inv_alpha2 / (sc.eps0 * Lh)));
+    // shifts (ascending: slot j is read before it is overwritten)
+    for (int i = 1; i <= 2 * k; ++i) {
+      const double2 up = i < 2 * k ? Ph(i) : make_double2(0.0, 0.0);
+      Ph(i - 1) = csub(up, cscale(lphi, sc.Cn[i] / Lh));
+    }
+    for (int l = 0; l < 3; ++l)
+      for (int i = 1; i <= 2 * k; ++i) {
+        const double2 up = i < 2 * k ? Al(i, l) : make_double2(0.0, 0.0);
+        Al(i - 1, l) = csub(up, cscale(lA[l], sc.Cn[i] / Lh));
+      }
+    for (int j = 1; j <= k; ++j) {
+      const double2 up = j < k ? R(j) : make_double2(0.0, 0.0);
+      R(j - 1) = csub(up, cscale(lrho, sc.a[j] / sc.a[0]));
+    }
+    // lambda_J^_l = mu0/(alpha^2 Lh) lambda_A'_l + conj(-dt i k_l / a_0) lambda_rho'
+    const double cA = sc.mu0 * sc.inv_alpha2 / Lh;
+    const double cr = sc.dt / sc.a[0];
+    const double2 lJx = cadd(cscale(lA[0], cA), mul_i(cscale(lrho, cr * kxs)));
+    const double2 lJy = cadd(cscale(lA[1], cA), mul_i(cscale(lrho, cr * kys)));
+    const double2 lJz = cscale(lA[2], cA);
+    // lambda_J = N irfft2(lambda_J^ / w): the y-inverse here, the rows next
+    wk[ky] = cscale(lJx, 1.0 / wgt);
+    wk[N + ky] = cscale(lJy, 1.0 / wgt);
+    wk[2 * N + ky] = cscale(lJz, 1.0 / wgt);
+  }
+  __syncthreads();
+  const double2* res = fft_lds<true>(wk, wk + 3 * N, N, 3, d.twy);
+  for (int t = threadIdx.x; t < 3 * N; t += blockDim.x) {
+    const int c = t / N, y = t - c * N;
+    LS[((size_t)c * nxh + kx) * N + y] = res[t];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// deposit adjoint + position update adjoint.  Particle arrays hold x^{n+1}
+// and v^n; LJ holds lambda_J.
+template <int DEG>
+__global__ void __launch_bounds__(256) k_adj_deposit(const InstDesc* __restrict__ D, StepArgs sa,
+                                                     double* __restrict__ lam) {
+  using S = Spline<double, DEG>;
+  const InstDesc& d = D[0];
+  const int64_t n = d.n;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const GridP g = d.g;
+  const PhysP ph = d.ph;
+  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
+  const int64_t o = p.id[i];
+  const size_t plane = (size_t)g.nx * g.ny;
+  const double* __restrict__ LJ = d.LJ;
+  const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
+  double av[3] = {0, 0, 0}, bx[3] = {0, 0, 0}, by[3] = {0, 0, 0};
+  if (in_box(xi, eta, g)) {
+    int sx, sy;
+    double wx[S::NW], dwx[S::NW], wy[S::NW], dwy[S::NW];
+    S::eval_d(xi, sx, wx, dwx);
+    S::eval_d(eta, sy, wy, dwy);
+#pragma unroll
+    for (int b = 0; b < S::NW; ++b) {
+      const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
+      double aw[3] = {0, 0, 0}, ad[3] = {0, 0, 0};
+#pragma unroll
+      for (int a = 0; a < S::NW; ++a) {
+        const size_t m = row + wrapi(sx + a, g.nx);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double v = LJ[c * plane + m];
+          aw[c] += wx[a] * v;
+          ad[c] += dwx[a] * v;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        av[c] += wy[b] * aw[c];
+        bx[c] += wy[b] * ad[c];
+        by[c] += dwy[b] * aw[c];
+      }
+    }
+  }
+  // J = sum q v^n S(x' - X) / (dx dy)
+  const double s = ph.q * g.inv_area;
+  const double v0 = p.v[0][i], v1 = p.v[1][i], v2 = p.v[2][i];
+  const double lx = lam[o] + s * (v0 * bx[0] + v1 * bx[1] + v2 * bx[2]) * g.inv_dx;
+  const double ly = lam[n + o] + s * (v0 * by[0] + v1 * by[1] + v2 * by[2]) * g.inv_dy;
+  // x' = wrap(x + v^n dt): unit derivative in x, dt in v
+  lam[o] = lx;
+  lam[n + o] = ly;
+  lam[5 * n + o] += s * av[0] + ph.dt * lx;
+  lam[6 * n + o] += s * av[1] + ph.dt * ly;
+  lam[7 * n + o] += s * av[2];
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the field energy of the newest level (BDF-k time derivative):
+//   W = (dx dy / 2N) sum_modes w (eps0 |E^|^2 + |B^|^2 / mu0),
+//   E^ = -i k phi^n - (1/dt) sum_j a_j A^{n-j},  B^ = i k x A^n,
+// the Parseval form of the mesh sum of (eps0 |E|^2 + |B|^2/mu0) dx dy / 2.
+// Writes scale * dW/dH for every external history field.
+__global__ void k_adj_seed_energy(const double2* __restrict__ H, GridP g, SchemeCoef sc, HistSlots hs, double scale,
+                                  double2* __restrict__ lamH, int nf) {
+  const size_t plane = (size_t)g.nxh * g.ny;
+  const int k = sc.k;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < plane; t += (size_t)gridDim.x * blockDim.x) {
+    const int ky = (int)(t / g.nxh), kx = (int)(t - (size_t)ky * g.nxh);
+    const size_t m = (size_t)kx * g.ny + ky;  // internal [kx][ky]
+    const double kxs = kx_sym(kx, g), kys = ky_sym(ky, g);
+    const double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
+    const double s = scale * wgt * g.dx * g.dy / ((double)g.nx * g.ny);
+    auto at = [&](int slot) { return H[(size_t)slot * plane + m]; };
+    const double2 phi = at(hs.phi[0]);
+    double2 dA[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int j = 0; j <= k; ++j)
+      for (int l = 0; l < 3; ++l) dA[l] = cadd(dA[l], cscale(at(hs.A[j] + l), sc.a[j] / sc.dt));
+    double2 A0[3];
+    for (int l = 0; l < 3; ++l) A0[l] = at(hs.A[0] + l);
+    const double2 Ex = csub(mul_i(cscale(phi, -kxs)), dA[0]);
+    const double2 Ey = csub(mul_i(cscale(phi, -kys)), dA[1]);
+    const double2 Ez = cscale(dA[2], -1.0);
+    const double2 Bx = mul_i(cscale(A0[2], kys)), By = mul_i(cscale(A0[2], -kxs));
+    const double2 Bz = mul_i(make_double2(kxs * A0[1].x - kys * A0[0].x, kxs * A0[1].y - kys * A0[0].y));
+    const double2 lE[3] = {cscale(Ex, s * sc.eps0), cscale(Ey, s * sc.eps0), cscale(Ez, s * sc.eps0)};
+    const double2 lBx = cscale(Bx, s / sc.mu0), lBy = cscale(By, s / sc.mu0), lBz = cscale(Bz, s / sc.mu0);
+    for (int f = 0; f < nf; ++f) lamH[(size_t)f * plane + t] = make_double2(0.0, 0.0);
+    // phi^n: conj(-i k) = i k
+    lamH[(size_t)k * plane + t] = mul_i(make_double2(kxs * lE[0].x + kys * lE[1].x, kxs * lE[0].y + kys * lE[1].y));
+    for (int j = 0; j <= k; ++j)
+      for (int l = 0; l < 3; ++l) {
+        double2 v = cscale(lE[l], -sc.a[j] / sc.dt);
+        if (j == 0) {  // curl A^n
+          if (l == 0) v = cadd(v, mul_i(cscale(lBz, kys)));
+          if (l == 1) v = cadd(v, mul_i(cscale(lBz, -kxs)));
+          if (l == 2) v = cadd(v, mul_i(make_double2(kxs * lBy.x - kys * lBx.x, kxs * lBy.y - kys * lBx.y)));
+        }
+        lamH[(size_t)(3 * k + 3 * j + l) * plane + t] = v;
+      }
+  }
+}
+
+// adjoint of the cold start v^0 = v^{-1} = c^2 P / sqrt(c^2 |P|^2 + (m c^2)^2):
+// lambda_P += J^T (lambda_{v^0} + lambda_{v^{-1}}), velocity adjoints cleared
+__global__ void k_adj_initial(int64_t n, const double* __restrict__ P, PhysP ph, double* __restrict__ lam) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double c2 = ph.c * ph.c, mc2 = ph.m * c2;
+  const double ux = P[i], uy = P[n + i], uz = P[2 * n + i];
+  const double ss = sqrt(c2 * (ux * ux + uy * uy + uz * uz) + mc2 * mc2);
+  const double lvx = lam[5 * n + i] + lam[8 * n + i];
+  const double lvy = lam[6 * n + i] + lam[9 * n + i];
+  const double lvz = lam[7 * n + i] + lam[10 * n + i];
+  const double ud = (ux * lvx + uy * lvy + uz * lvz) * c2 / (ss * ss);
+  const double k1 = c2 / ss;
+  lam[2 * n + i] += k1 * (lvx - ud * ux);
+  lam[3 * n + i] += k1 * (lvy - ud * uy);
+  lam[4 * n + i] += k1 * (lvz - ud * uz);
+  for (int c = 5; c < 11; ++c) lam[c * n + i] = 0.0;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_adj_push(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  switch (degree) {
+    case 1: hipLaunchKernelGGL(k_adj_push<1>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
+    case 2: hipLaunchKernelGGL(k_adj_push<2>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
+    default: hipLaunchKernelGGL(k_adj_push<3>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  switch (degree) {
+    case 1: hipLaunchKernelGGL(k_adj_deposit<1>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
+    case 2: hipLaunchKernelGGL(k_adj_deposit<2>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
+    default: hipLaunchKernelGGL(k_adj_deposit<3>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_columns(const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s) {
+  hipFuncSetAttribute((const void*)k_adj_columns, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_adj_columns, dim3(nxh), dim3(256), lds, s, D, (double2*)lam_hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_seed_energy(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double scale,
+                                  double* lam_hist, int nf, hipStream_t s) {
+  const size_t plane = (size_t)g.nxh * g.ny;
+  const int blocks = (int)std::min<size_t>((plane + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_adj_seed_energy, dim3(blocks), dim3(256), 0, s, H, g, sc, hs, scale, (double2*)lam_hist, nf);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_initial(int64_t n, const double* P, PhysP ph, double* lam, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_initial, dim3(blocks_for(n)), dim3(256), 0, s, n, P, ph, lam);
+  return hipGetLastError();
+}
+
+}  // namespace pic

@@ -182,7 +182,7 @@ TileP plan_tiles(const pic_config_t& c) {
 
 struct Layout {
   size_t set_bytes;  // one particle set: 11 arrays (cap x es) + ids
-  size_t parts, J, T, H, U, F64, F32, twx, twy, tcount, tstart, tcursor, twork, tnwork, total;
+  size_t parts, J, T, H, U, F64, F32, twx, twy, tcount, tstart, tcursor, twork, tnwork, LF, LS, LJ, total;
   size_t plane_c;    // complex entries per spectral plane
 };
 
@@ -216,6 +216,11 @@ Layout plan_instance(const pic_config_t& c) {
   L.tcursor = take((size_t)tp.ntiles * 4);
   L.twork = take((size_t)tp.max_work * 16);
   L.tnwork = take(4);
+  if (c.flags & PIC_FLAG_ADJOINT) {
+    L.LF = take(11 * plane_r * 8);
+    L.LS = take(11 * L.plane_c * 16);
+    L.LJ = take(3 * plane_r * 8);
+  }
   L.total = o;
   return L;
 }
@@ -456,7 +461,9 @@ pic_status_t reset_fields(pic_ctx_t c, Instance& in) {
   pic_status_t st = c->hip(launch_fill_f64((double*)d.H, (size_t)c->hist.nslots * in.L.plane_c * 2, 0.0, c->stream),
                            "history fill");
   if (st) return st;
-  return c->hip(launch_fill_f64(d.J, (size_t)3 * in.cfg.nx * in.cfg.ny, 0.0, c->stream), "J fill");
+  st = c->hip(launch_fill_f64(d.J, (size_t)3 * in.cfg.nx * in.cfg.ny, 0.0, c->stream), "J fill");
+  if (st || !d.LF) return st;
+  return c->hip(launch_fill_f64(d.LF, (size_t)11 * in.cfg.nx * in.cfg.ny, 0.0, c->stream), "adjoint fill");
 }
 
 struct PartsAny {
@@ -578,6 +585,10 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.tb.cursor = (int32_t*)(b + in.L.tcursor);
     d.tb.work = (int4*)(b + in.L.twork);
     d.tb.nwork = (int32_t*)(b + in.L.tnwork);
+    const bool adj = (cf.flags & PIC_FLAG_ADJOINT) != 0;
+    d.LF = adj ? (double*)(b + in.L.LF) : nullptr;
+    d.LS = adj ? (double2*)(b + in.L.LS) : nullptr;
+    d.LJ = adj ? (double*)(b + in.L.LJ) : nullptr;
     d.n = 0;
     d.R_r2c = rows_r2c_R(cf.nx, cf.ny);
     d.R_c2r = rows_c2r_R(cf.nx, cf.ny);
@@ -903,11 +914,13 @@ pic_status_t pic_set_particles(pic_ctx_t c, const double* src) {
   if (c->phase == EMPTY) return c->fail(PIC_ERR_STATE, "no particles loaded");
   Instance& in = c->I();
   if (in.d.n > 0 && !src) return c->fail(PIC_ERR_INVALID_ARG, "in is NULL");
-  if (c->phase != READY) return c->fail(PIC_ERR_STATE, "set_particles needs phase READY");
+  // J is zero in both phases (consumed by the last field solve)
+  if (c->phase != READY && c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "set_particles needs phase READY or SOLVED");
   auto pa = parts_of(c, in.d, c->cur);
   pic_status_t st = c->hip(launch_set_particles(c->dtype, &pa, in.d.n, src, in.d.g, c->stream), "set_particles");
   if (st) return st;
   c->moves = c->sort_every;  // re-sort before the next particle pass
+  c->phase = READY;
   return PIC_OK;
 }
 
@@ -967,6 +980,61 @@ pic_status_t pic_diagnostics(pic_ctx_t c, double* out) {
   out[6] = ke;
   out[7] = bad;
   return bad > 0 ? c->fail(PIC_ERR_NONFINITE, "non-finite particle values") : PIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// discrete adjoint (float64 BDF-k, one instance, PIC_FLAG_ADJOINT)
+
+static pic_status_t adjoint_check(pic_ctx_t c, bool need_ready) {
+  if (c->ninst() != 1) return c->fail(PIC_ERR_UNSUPPORTED, "the adjoint runs on single-instance contexts");
+  if (!(c->I().cfg.flags & PIC_FLAG_ADJOINT))
+    return c->fail(PIC_ERR_UNSUPPORTED, "the adjoint needs a context created with PIC_FLAG_ADJOINT");
+  if (c->dtype != PIC_F64 || c->scheme != PIC_SCHEME_BDF)
+    return c->fail(PIC_ERR_UNSUPPORTED, "the adjoint supports float64 particles and the BDF-k stepper");
+  if (need_ready && c->phase != READY) return c->fail(PIC_ERR_STATE, "adjoint_seed_energy and step_adjoint need phase READY");
+  if (c->phase == EMPTY) return c->fail(PIC_ERR_STATE, "no particles loaded");
+  return PIC_OK;
+}
+
+pic_status_t adjoint_seed_energy(pic_ctx_t c, double scale, double* lam_hist) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  pic_status_t st = adjoint_check(c, true);
+  if (st) return st;
+  if (!lam_hist) return c->fail(PIC_ERR_INVALID_ARG, "lam_hist is NULL");
+  Instance& in = c->I();
+  return c->hip(launch_adj_seed_energy(in.d.H, in.d.g, in.d.sc, slots_of(c->hist, c->nupd), scale, lam_hist,
+                                       c->hist.nexport, c->stream),
+                "adjoint seed");
+}
+
+pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  pic_status_t st = adjoint_check(c, true);
+  if (st) return st;
+  Instance& in = c->I();
+  if (!lam_hist || (in.d.n > 0 && !lam)) return c->fail(PIC_ERR_INVALID_ARG, "lam and lam_hist must be device pointers");
+  // recompute x^{n+1}, J^{n+1} and the level-(n+1) fields from the loaded state
+  st = particle_pass(c, 0);
+  if (!st) st = do_solve(c);
+  const InstDesc* D = c->d_desc;
+  const int nx = in.cfg.nx, ny = in.cfg.ny;
+  const StepArgs sa = c->sargs();
+  if (!st) st = c->hip(launch_adj_push(c->degree, D, in.d.n, sa, lam, c->stream), "adjoint push");
+  if (!st) st = c->hip(launch_rows_r2c(D, 1, 11 * (ny / in.d.R_r2c), c->lds_r2c, c->stream, true), "adjoint rows_r2c");
+  if (!st) st = c->hip(launch_adj_columns(D, nx / 2 + 1, c->lds_col, lam_hist, c->stream), "adjoint columns");
+  if (!st) st = c->hip(launch_rows_c2r(D, 1, 2 * (ny / in.d.R_c2r), c->lds_c2r, c->stream, true), "adjoint rows_c2r");
+  if (!st) st = c->hip(launch_adj_deposit(c->degree, D, in.d.n, sa, lam, c->stream), "adjoint deposit");
+  c->phase = st ? EMPTY : SOLVED;
+  return st;
+}
+
+pic_status_t adjoint_initial(pic_ctx_t c, const double* P0, double* lam) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  pic_status_t st = adjoint_check(c, false);
+  if (st) return st;
+  Instance& in = c->I();
+  if (in.d.n > 0 && (!P0 || !lam)) return c->fail(PIC_ERR_INVALID_ARG, "P0 and lam must be device pointers");
+  return c->hip(launch_adj_initial(in.d.n, P0, in.d.ph, lam, c->stream), "adjoint initial");
 }
 
 pic_status_t pic_set_kernel_timing(pic_ctx_t c, int32_t enable) {

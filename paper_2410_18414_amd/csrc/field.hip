@@ -16,7 +16,7 @@
 // Reading of the Nyquist mode (the paper is silent): the first-derivative
 // symbol is zero at index n/2 of each axis and the Laplacian is built from the
 // same symbols, so div(grad) equals the Laplacian exactly.
-#include "pic_internal.h"
+#include "fft_lds.h"
 
 #include <algorithm>
 #include <cmath>
@@ -25,99 +25,12 @@ namespace pic {
 
 namespace {
 
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double2 mul_i(double2 a) { return make_double2(-a.y, a.x); }      // i a
-__device__ __forceinline__ double2 mul_mi(double2 a) { return make_double2(a.y, -a.x); }     // -i a
-__device__ __forceinline__ double2 cdivr(double2 a, double r) { return make_double2(a.x / r, a.y / r); }
-
-// B independent length-N FFTs (N a power of two) held in LDS at a[f*N + j].
-// Stockham autosort, radix 4 with one radix-2 pass when log2 N is odd;
-// ping-pongs between a and b and returns the buffer holding the result.
-// tw[t] = exp(-2 pi i t / N), t < N.  INV: exp(+...) (unnormalised inverse).
-// All threads of the block must call it; the caller synchronises before.
-template <bool INV>
-__device__ double2* fft_lds(double2* a, double2* b, int N, int B, const double2* __restrict__ tw) {
-  const int tid = threadIdx.x, nth = blockDim.x;
-  int Ns = 1;
-  while (Ns < N) {
-    if (N >= 4 * Ns) {
-      const int q = N >> 2;
-      const int stride = N / (4 * Ns);
-      const int lq = __ffs(q) - 1;
-      for (int t = tid; t < B * q; t += nth) {
-        const int f = t >> lq;
-        const int j = t & (q - 1);
-        const double2* in = a + f * N;
-        double2* out = b + f * N;
-        const int k = j & (Ns - 1);
-        double2 v0 = in[j], v1 = in[j + q], v2 = in[j + 2 * q], v3 = in[j + 3 * q];
-        if (k) {
-          double2 w1 = tw[k * stride], w2 = tw[2 * k * stride], w3 = tw[3 * k * stride];
-          if (INV) { w1 = cconj(w1); w2 = cconj(w2); w3 = cconj(w3); }
-          v1 = cmul(v1, w1);
-          v2 = cmul(v2, w2);
-          v3 = cmul(v3, w3);
-        }
-        const double2 s02 = cadd(v0, v2), d02 = csub(v0, v2);
-        const double2 s13 = cadd(v1, v3), d13 = csub(v1, v3);
-        const int d = ((j - k) << 2) + k;
-        out[d] = cadd(s02, s13);
-        out[d + 2 * Ns] = csub(s02, s13);
-        if (INV) {
-          out[d + Ns] = cadd(d02, mul_i(d13));
-          out[d + 3 * Ns] = cadd(d02, mul_mi(d13));
-        } else {
-          out[d + Ns] = cadd(d02, mul_mi(d13));
-          out[d + 3 * Ns] = cadd(d02, mul_i(d13));
-        }
-      }
-      Ns <<= 2;
-    } else {
-      const int h = N >> 1;
-      const int stride = N / (2 * Ns);
-      const int lh = __ffs(h) - 1;
-      for (int t = tid; t < B * h; t += nth) {
-        const int f = t >> lh;
-        const int j = t & (h - 1);
-        const double2* in = a + f * N;
-        double2* out = b + f * N;
-        const int k = j & (Ns - 1);
-        double2 w = tw[k * stride];
-        if (INV) w = cconj(w);
-        const double2 v0 = in[j], v1 = cmul(in[j + h], w);
-        const int d = ((j - k) << 1) + k;
-        out[d] = cadd(v0, v1);
-        out[d + Ns] = csub(v0, v1);
-      }
-      Ns <<= 1;
-    }
-    __syncthreads();
-    double2* t = a;
-    a = b;
-    b = t;
-  }
-  return a;
-}
-
-__device__ __forceinline__ double kx_sym(int kx, const GridP& g) {
-  return (2 * kx == g.nx) ? 0.0 : 2.0 * M_PI * kx / g.lx;
-}
-__device__ __forceinline__ double ky_sym(int ky, const GridP& g) {
-  if (2 * ky == g.ny) return 0.0;
-  const int m = (2 * ky < g.ny) ? ky : ky - g.ny;
-  return 2.0 * M_PI * m / g.ly;
-}
 
 // ---------------------------------------------------------------------------
 // rows: R real rows (R even) of one J component -> R/2 complex FFTs along x.
 // Flattened over instances: local block = component * (ny/R) + row group.
-__global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D, int ninst) {
+// adj: the same transform of the 11 adjoint mesh fields LF into LS.
+__global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D, int ninst, int adj) {
   extern __shared__ double2 sm[];
   const int ii = find_inst(D, ninst, BK_R2C, blockIdx.x);
   const InstDesc& d = D[ii];
@@ -125,8 +38,8 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
   const int R = d.R_r2c, ngr = g.ny / R;
   const int lb = blockIdx.x - d.blk[BK_R2C];
   const int c = lb / ngr, y0 = (lb - c * ngr) * R;
-  double* __restrict__ Jc = d.J + (size_t)c * g.nx * g.ny;
-  double2* __restrict__ T = d.T;
+  double* __restrict__ Jc = (adj ? d.LF : d.J) + (size_t)c * g.nx * g.ny;
+  double2* __restrict__ T = adj ? d.LS : d.T;
   const int N = g.nx, B = R >> 1;
   double2* a = sm;
   double2* b = sm + B * N;
@@ -134,7 +47,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
     const int r = t / N, x = t - r * N;
     const size_t i0 = (size_t)(y0 + 2 * r) * N + x, i1 = i0 + N;
     a[t] = make_double2(Jc[i0], Jc[i1]);
-    Jc[i0] = 0.0;  // J is consumed: ready for the next deposit
+    Jc[i0] = 0.0;  // consumed: zero for the next deposit (or adjoint scatter)
     Jc[i1] = 0.0;
   }
   __syncthreads();
@@ -329,7 +242,10 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
 __constant__ int kSrcG[12] = {0, 1, 2, 3, 4, 2, 3, 4, 5, 6, 7, 0};
 __constant__ int kMulKx[12] = {1, 0, 0, 0, 0, 1, 1, 1, 0, 0, 0, 0};
 
-__global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D, int ninst) {
+//
+// adj: the three columns LS[0..2] of the adjoint solve to the real fields LJ
+// (pairs (0, 1) and (2, -); no kx factor).
+__global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D, int ninst, int adj) {
   extern __shared__ double2 sm[];
   const int ii = find_inst(D, ninst, BK_C2R, blockIdx.x);
   const InstDesc& d = D[ii];
@@ -337,21 +253,22 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
   const int R = d.R_c2r, ngr = g.ny / R;
   const int lb = blockIdx.x - d.blk[BK_C2R];
   const int pr = lb / ngr, y0 = (lb - pr * ngr) * R;
-  const double2* __restrict__ U = d.U;
-  double* __restrict__ F64 = d.F64;
-  float* __restrict__ F32 = d.F32;
+  const double2* __restrict__ U = adj ? d.LS : d.U;
+  double* __restrict__ F64 = adj ? d.LJ : d.F64;
+  float* __restrict__ F32 = adj ? nullptr : d.F32;
   const int N = g.nx, h = N >> 1;
   double2* a = sm;
   double2* b = sm + R * N;
   const int s0 = 2 * pr, s1 = s0 + 1;
-  const int g0 = kSrcG[s0], g1 = kSrcG[s1];
+  const int g0 = adj ? s0 : kSrcG[s0], g1 = adj ? s1 : kSrcG[s1];
+  const bool has1 = !adj || s1 < 3;
   for (int t = threadIdx.x; t < g.nxh * R; t += blockDim.x) {
     const int k = t / R, r = t - k * R;
     const double kxs = 2.0 * M_PI * k / g.lx * ((k == h) ? 0.0 : 1.0);
     double2 X = U[((size_t)g0 * g.nxh + k) * g.ny + y0 + r];
-    double2 Y = U[((size_t)g1 * g.nxh + k) * g.ny + y0 + r];
-    if (kMulKx[s0]) X = mul_i(cscale(X, kxs));
-    if (kMulKx[s1]) Y = mul_i(cscale(Y, kxs));
+    double2 Y = has1 ? U[((size_t)g1 * g.nxh + k) * g.ny + y0 + r] : make_double2(0.0, 0.0);
+    if (!adj && kMulKx[s0]) X = mul_i(cscale(X, kxs));
+    if (!adj && kMulKx[s1]) Y = mul_i(cscale(Y, kxs));
     if (k == 0 || k == h) {  // real-signal spectrum: these bins are real
       X.y = 0.0;
       Y.y = 0.0;
@@ -367,7 +284,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
     const size_t o = (size_t)(y0 + r) * N + x;
     const double2 z = res[t];
     F64[s0 * plane + o] = z.x;
-    F64[s1 * plane + o] = z.y;
+    if (has1) F64[s1 * plane + o] = z.y;
     if (F32) {
       F32[s0 * plane + o] = (float)z.x;
       F32[s1 * plane + o] = (float)z.y;
@@ -533,9 +450,9 @@ size_t columns_lds_bytes(int ny) {
   return (size_t)(4 + std::max(6, 2 * nb)) * ny * sizeof(double2);
 }
 
-hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s) {
+hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {
   hipFuncSetAttribute((const void*)k_rows_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_rows_r2c, dim3(nblocks), dim3(256), lds, s, D, ninst);
+  hipLaunchKernelGGL(k_rows_r2c, dim3(nblocks), dim3(256), lds, s, D, ninst, adj ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -554,9 +471,9 @@ hipError_t launch_columns(int scheme, const InstDesc* D, int ninst, int nblocks,
   return hipGetLastError();
 }
 
-hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s) {
+hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {
   hipFuncSetAttribute((const void*)k_rows_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_rows_c2r, dim3(nblocks), dim3(256), lds, s, D, ninst);
+  hipLaunchKernelGGL(k_rows_c2r, dim3(nblocks), dim3(256), lds, s, D, ninst, adj ? 1 : 0);
   return hipGetLastError();
 }
 

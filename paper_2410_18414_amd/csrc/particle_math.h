@@ -42,6 +42,27 @@ struct Spline {
       w[3] = d3 * sixth;
     }
   }
+  // weights and their derivatives dw/dxi (the adjoint passes differentiate
+  // through the particle position)
+  __device__ __forceinline__ static void eval_d(T xi, int& s, T* w, T* dw) {
+    eval(xi, s, w);
+    if (DEG == 1) {
+      dw[0] = T(-1);
+      dw[1] = T(1);
+    } else if (DEG == 2) {
+      const T d = xi - T(s + 1);
+      dw[0] = d - T(0.5);
+      dw[1] = T(-2) * d;
+      dw[2] = d + T(0.5);
+    } else {
+      const T d = xi - T(s + 1);
+      const T e = T(1) - d;
+      dw[0] = T(-0.5) * e * e;
+      dw[1] = d * (T(1.5) * d - T(2));
+      dw[2] = T(0.5) + d - T(1.5) * d * d;
+      dw[3] = T(0.5) * d * d;
+    }
+  }
 };
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }

@@ -109,6 +109,9 @@ struct InstDesc {
   float* F32;
   const double2* twx;
   const double2* twy;
+  double* LF;               // adjoint buffers (PIC_FLAG_ADJOINT, else null): [11][ny][nx] mesh-field adjoints,
+  double2* LS;              // [11][nxh][ny] their x-transforms (planes 0..2 reused for the J adjoint columns),
+  double* LJ;               // [3][ny][nx] adjoint of J
   TileBufs tb;
   int64_t n;                // particles loaded
   int R_r2c, R_c2r, nb_col; // rows per block of the row kernels; inverse batch of the column kernel
@@ -179,12 +182,21 @@ int columns_nb(int ny);
 size_t rows_r2c_lds_bytes(int nx, int ny);
 size_t rows_c2r_lds_bytes(int nx, int ny);
 size_t columns_lds_bytes(int ny);
-hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s);
+// adj = true: the adjoint field solve's transforms (LF -> LS, LS -> LJ; one instance)
+hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false);
 hipError_t launch_columns(int scheme, const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
                           hipStream_t s);
-hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s);
+hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false);
 hipError_t launch_hist_transpose(const double2* src, double2* dst, int nfield, GridP g, bool to_external,
                                  hipStream_t s);
+// adjoint.hip (one float64 BDF-k instance; D[0])
+hipError_t launch_adj_push(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s);
+hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s);
+hipError_t launch_adj_columns(const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s);
+hipError_t launch_adj_seed_energy(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double scale,
+                                  double* lam_hist, int nf, hipStream_t s);
+hipError_t launch_adj_initial(int64_t n, const double* P, PhysP ph, double* lam, hipStream_t s);
+
 hipError_t launch_field_diag(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double* out, hipStream_t s);
 
 }  // namespace pic

@@ -24,6 +24,7 @@ DTYPES = {"f32": 0, "f64": 1}
 FLAG_NO_SORT = 1
 FLAG_UNFUSED_STEP = 2
 FLAG_NO_GRAPH = 4
+FLAG_ADJOINT = 8
 FIELD_J = 0
 FIELD_MESH = 1
 DIAG_NAMES = ("gauge_l2", "gauge_scale", "gauss_l2", "gauss_scale", "charge", "energy",
@@ -37,7 +38,8 @@ EXPORTS = ("pic_workspace_bytes", "pic_create", "pic_destroy", "pic_last_error",
            "pic_get_particles", "pic_set_particles", "pic_get_field", "pic_history_fields",
            "pic_get_history", "pic_set_history", "pic_diagnostics", "pic_set_kernel_timing",
            "pic_kernel_timing", "pic_batch_workspace_bytes", "pic_batch_create",
-           "pic_instance_count", "pic_select_instance", "step_batched")
+           "pic_instance_count", "pic_select_instance", "step_batched", "adjoint_seed_energy",
+           "step_adjoint", "adjoint_initial")
 KCLASSES = ("deposit", "field_solve", "gather_push", "fused", "sort")
 
 
@@ -97,6 +99,9 @@ def load():
         "pic_instance_count": (I32, [P]),
         "pic_select_instance": (I32, [P, I32]),
         "step_batched": (I32, [P, I32]),
+        "adjoint_seed_energy": (I32, [P, D, P]),
+        "step_adjoint": (I32, [P, P, P]),
+        "adjoint_initial": (I32, [P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -301,3 +306,27 @@ def kernel_timing(ctx):
     buf = (ctypes.c_double * (2 * len(KCLASSES)))()
     ctx.check(load().pic_kernel_timing(ctx.handle, buf))
     return {k: (buf[2 * i], int(buf[2 * i + 1])) for i, k in enumerate(KCLASSES)}
+
+
+def adjoint_seed_energy(ctx, scale=1.0):
+    """d(scale * field energy)/d(history) as a complex [nf, ny, nx/2+1] tensor."""
+    nf = history_fields(ctx.cfgs[ctx.sel])
+    out = torch.empty((nf, ctx.ny, ctx.nx // 2 + 1), dtype=torch.complex128, device=ctx.device)
+    ctx.check(load().adjoint_seed_energy(ctx.handle, float(scale), _ptr(out)))
+    return out
+
+
+def step_adjoint(ctx, lam, lam_hist):
+    """lambda^{n+1} -> lambda^n in place; the context must hold S^n (phase READY)."""
+    assert lam.dtype == torch.float64 and lam.is_contiguous() and lam.shape == (11, ctx.n)
+    assert lam_hist.dtype == torch.complex128 and lam_hist.is_contiguous()
+    assert lam_hist.shape == (history_fields(ctx.cfgs[ctx.sel]), ctx.ny, ctx.nx // 2 + 1)
+    ctx.check(load().step_adjoint(ctx.handle, _ptr(lam), _ptr(lam_hist)))
+
+
+def adjoint_initial(ctx, P0, lam):
+    """Fold the adjoint of v^0 = v^{-1} = V(P0) into lam[2:5] (in place)."""
+    P0 = P0.to(ctx.device, torch.float64).contiguous()
+    assert P0.numel() == 3 * ctx.n and lam.shape == (11, ctx.n) and lam.is_contiguous()
+    ctx._inputs = (P0,)
+    ctx.check(load().adjoint_initial(ctx.handle, _ptr(P0), _ptr(lam)))
