@@ -51,6 +51,29 @@ def grid_bytes(nx, ny, dtype):
     return nx * ny * (11 * es + 3 * 8 * 2)
 
 
+def measured_traffic(tag):
+    """HBM bytes per launch of the fused pass from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (profiles/traffic_<tag>.md), or None when
+    there is none or the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s.md" % tag)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        key, sep, val = line.strip().partition(": ")
+        if sep and key in ("traffic_bytes_per_launch", "kernel_sources_sha256", "kernel_sources"):
+            fields[key] = val.strip()
+    if len(fields) != 3:
+        return None
+    h = hashlib.sha256()
+    for src in fields["kernel_sources"].split():
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != fields["kernel_sources_sha256"]:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(w, spec, nsteps):
     """The FP64 oracle (numpy, single thread) on the same particles and grid."""
     from oracle import pic as opic
@@ -72,7 +95,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="weibel128", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="run deposit and gather/push as separate kernels")
     ap.add_argument("--no-sort", action="store_true", help="plain global-atomic kernels, no tile sort")
@@ -80,6 +103,8 @@ def main():
     ap.add_argument("--tile-cells", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--slack", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -96,6 +121,15 @@ def main():
                 bdf_order=w["bdf_order"], dtype=w["dtype"])
     n = len(w["x"])
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # a plain copy of known size: the FETCH_SIZE / WRITE_SIZE it reads scale
+        # the counters of the particle pass to bytes
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=spec["degree"],
                           scheme=spec["scheme"], bdf_order=spec["bdf_order"], dtype=spec["dtype"],
                           q=w["q"], m=w["m"], max_particles=n,
@@ -142,8 +176,11 @@ def main():
     avg_fused = fused_ms / max(fused_n, 1)
     alg = n * particle_bytes(spec["dtype"]) + grid_bytes(w["nx"], w["ny"], spec["dtype"])
     achieved = alg / (avg_fused * 1e-3) / 1e9 if avg_fused > 0 else 0.0
+    default_launch = not (args.unfused or args.no_sort or args.sort_interval or args.tile_cells
+                          or args.chunk or args.slack)
+    traffic = measured_traffic(args.workload) if default_launch else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 kernel="k_tiled<float,3,2> (fused gather/push/position/deposit)",
                 avg_launch_us=round(avg_fused * 1e3, 2),
                 algorithmic_bytes_per_launch=int(alg))
