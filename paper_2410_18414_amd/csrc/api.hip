@@ -26,6 +26,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 inline bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+// one particle array of the given capacity, 256-byte aligned
+inline size_t array_bytes(size_t cap, size_t es) { return align_up(cap * es); }
 
 // History groups: ring sizes and slot bases.  A ring of R levels for a field
 // of `width` components occupies R*width consecutive slots; level j of the
@@ -182,7 +184,7 @@ TileP plan_tiles(const pic_config_t& c) {
 
 struct Layout {
   size_t set_bytes;  // one particle set: 11 arrays (cap x es) + ids
-  size_t parts, J, T, H, U, F64, F32, twx, twy, tcount, tstart, tcursor, twork, tnwork, LF, LS, LJ, total;
+  size_t parts, J, T, H, U, F64, F32, twx, twy, tcount, tstart, ccount, ccursor, twork, tnwork, LF, LS, LJ, total;
   size_t plane_c;    // complex entries per spectral plane
 };
 
@@ -201,7 +203,7 @@ Layout plan_instance(const pic_config_t& c) {
     o = align_up(o + bytes);
     return at;
   };
-  L.set_bytes = 11 * align_up(cap * es) + align_up(cap * 4);
+  L.set_bytes = 11 * array_bytes(cap, es) + align_up(cap * 4);
   L.parts = take(2 * L.set_bytes);
   L.J = take(3 * plane_r * 8);
   L.T = take(3 * L.plane_c * 16);
@@ -213,7 +215,8 @@ Layout plan_instance(const pic_config_t& c) {
   L.twy = take((size_t)c.ny * 16);
   L.tcount = take((size_t)tp.ntiles * 4);
   L.tstart = take(((size_t)tp.ntiles + 1) * 4);
-  L.tcursor = take((size_t)tp.ntiles * 4);
+  L.ccount = take(plane_r * 4);
+  L.ccursor = take(plane_r * 4);
   L.twork = take((size_t)tp.max_work * 16);
   L.tnwork = take(4);
   if (c.flags & PIC_FLAG_ADJOINT) {
@@ -300,8 +303,9 @@ struct pic_ctx_s {
   InstDesc* d_desc = nullptr;
   double* d_diag = nullptr;
   int nblk[BK_NKINDS] = {0};
-  size_t lds_r2c = 0, lds_c2r = 0, lds_col = 0, lds_tiled[3] = {0, 0, 0}, lds_count = 0, lds_scatter = 0;
+  size_t lds_r2c = 0, lds_c2r = 0, lds_col = 0, lds_tiled[3] = {0, 0, 0}, lds_count = 0;
   int dtype = 0, degree = 3, scheme = 0;
+  int geo = 0;  // compiled window geometry shared by every instance (0: none, runtime geometry)
   bool sorted = true;
   int sort_every = 4;
   int64_t nupd = 0;  // completed field updates (history head)
@@ -402,8 +406,8 @@ namespace {
 pic_status_t do_sort(pic_ctx_t c) {
   if (!c->sorted) return PIC_OK;
   auto* t = c->begin_timed(4);
-  hipError_t e = launch_tile_sort(c->dtype, c->d_desc, c->ninst(), c->nblk[BK_COUNT], c->nblk[BK_PART], c->lds_count,
-                                  c->lds_scatter, c->cur, c->stream);
+  hipError_t e = launch_tile_sort(c->dtype, c->d_desc, c->ninst(), c->nblk[BK_COUNT], c->nblk[BK_TILES],
+                                  c->nblk[BK_PART], c->lds_count, c->cur, c->stream);
   c->end_timed(t);
   pic_status_t st = c->hip(e, "tile sort");
   if (st) return st;
@@ -427,7 +431,7 @@ pic_status_t particle_pass(pic_ctx_t c, int mode) {
   }
   static const int cls[3] = {0, 2, 3};
   auto* t = c->begin_timed(cls[mode]);
-  hipError_t e = c->sorted ? launch_tiled(c->dtype, mode, c->degree, c->d_desc, c->ninst(), c->nblk[BK_WORK],
+  hipError_t e = c->sorted ? launch_tiled(c->dtype, mode, c->degree, c->geo, c->d_desc, c->ninst(), c->nblk[BK_WORK],
                                           c->lds_tiled[mode], c->sargs(), c->stream)
                            : launch_untiled(c->dtype, mode, c->degree, c->d_desc, c->ninst(), c->nblk[BK_PART],
                                             c->sargs(), c->stream);
@@ -566,7 +570,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.tp = plan_tiles(cf);
     d.sc = make_scheme(cf);
     const size_t es = cf.particle_dtype == PIC_F32 ? 4 : 8;
-    const size_t cb = align_up((size_t)cf.max_particles * es);
+    const size_t cb = array_bytes((size_t)cf.max_particles, es);
     for (int s = 0; s < 2; ++s) {
       char* sb = b + in.L.parts + s * in.L.set_bytes;
       for (int k = 0; k < 11; ++k) d.set[s][k] = sb + k * cb;
@@ -582,7 +586,8 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.twy = (const double2*)(b + in.L.twy);
     d.tb.count = (int32_t*)(b + in.L.tcount);
     d.tb.start = (int32_t*)(b + in.L.tstart);
-    d.tb.cursor = (int32_t*)(b + in.L.tcursor);
+    d.tb.ccount = (int32_t*)(b + in.L.ccount);
+    d.tb.ccursor = (int32_t*)(b + in.L.ccursor);
     d.tb.work = (int4*)(b + in.L.twork);
     d.tb.nwork = (int32_t*)(b + in.L.tnwork);
     const bool adj = (cf.flags & PIC_FLAG_ADJOINT) != 0;
@@ -595,7 +600,8 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.nb_col = columns_nb(cf.ny);
     // flattened block ranges
     const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * 3, cf.nx / 2 + 1, cf.ny / d.R_c2r * 6, d.tp.max_work,
-                               ceil_div(cf.max_particles, 256), ceil_div(cf.max_particles, 1024)};
+                               ceil_div(cf.max_particles, 256), ceil_div(cf.max_particles, 1024),
+                               ceil_div(d.tp.ntiles, 4)};
     for (int k = 0; k < BK_NKINDS; ++k) {
       d.blk[k] = c->nblk[k];
       c->nblk[k] += nb[k];
@@ -606,7 +612,6 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     for (int mode = 0; mode < 3; ++mode)
       c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp));
     c->lds_count = std::max(c->lds_count, sort_count_lds_bytes(d.tp));
-    c->lds_scatter = std::max(c->lds_scatter, sort_scatter_lds_bytes(d.tp));
     // a position update moves a particle by less than c dt; the window's slack
     // absorbs sort_every updates without any particle leaving it
     const double cells = cf.c * cf.dt / std::min(g.dx, g.dy);
@@ -621,15 +626,19 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
       e = hipMemcpy((void*)d.twy, tw.data(), (size_t)cf.ny * 16, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemset(d.tb.count, 0, (size_t)d.tp.ntiles * 4);
+    if (e == hipSuccess) e = hipMemset(d.tb.ccount, 0, (size_t)cf.nx * cf.ny * 4);
   }
   c->sort_every = every;
+  c->geo = tiled_geometry(c->inst[0].d.tp);
+  for (int i = 1; i < ninst; ++i)
+    if (tiled_geometry(c->inst[i].d.tp) != c->geo) c->geo = 0;
   if (e != hipSuccess) {
     g_err = std::string("context setup: ") + hipGetErrorString(e);
     delete c;
     return PIC_ERR_HIP;
   }
   const size_t lds_need = std::max({c->lds_col, c->lds_r2c, c->lds_c2r, c->lds_tiled[0], c->lds_tiled[1],
-                                    c->lds_tiled[2], c->lds_scatter});
+                                    c->lds_tiled[2], c->lds_count});
   if (lds_need > (size_t)max_lds) {
     g_err = "grid or tile too large for this device's LDS";
     delete c;

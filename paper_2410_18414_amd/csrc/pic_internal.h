@@ -65,12 +65,16 @@ struct TileP {
   int max_work;    // ntiles + ceil(capacity/chunk): bound on the chunk count
 };
 
+// Particles are counting-sorted by cell, cells numbered tile-major (the
+// ts*ts cells of tile t are keys t*ts*ts .. (t+1)*ts*ts - 1), so each tile's
+// particles are contiguous and, inside the tile, grouped by cell.
 struct TileBufs {
-  int32_t* count;   // [ntiles]   zero between sorts
-  int32_t* start;   // [ntiles+1] first particle of each tile
-  int32_t* cursor;  // [ntiles]
-  int4* work;       // [max_work] (tile, first particle, count, 0)
-  int32_t* nwork;   // [1]        chunks in use
+  int32_t* count;    // [ntiles]   particles per tile; zero between sorts
+  int32_t* start;    // [ntiles+1] first particle of each tile
+  int32_t* ccount;   // [nx*ny]    particles per cell; zero between sorts
+  int32_t* ccursor;  // [nx*ny]    next free slot of each cell during the scatter
+  int4* work;        // [max_work] (tile, first particle, count, 0)
+  int32_t* nwork;    // [1]        chunks in use
 };
 
 struct SchemeCoef {
@@ -90,7 +94,8 @@ enum BlockKind {
   BK_WORK = 3,   // tp.max_work blocks (tiled particle pass)
   BK_PART = 4,   // ceil(capacity/256) blocks (untiled passes, scatter)
   BK_COUNT = 5,  // ceil(capacity/1024) blocks (tile counting)
-  BK_NKINDS = 6
+  BK_TILES = 6,  // ceil(ntiles/4) blocks (per-tile cell scan, one wave per tile)
+  BK_NKINDS = 7
 };
 
 // One instance of the method: static for the life of a context.
@@ -168,11 +173,12 @@ hipError_t launch_particle_diag(int dtype, const void* parts, int64_t n, PhysP p
 // tiles.hip
 size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp);
 size_t sort_count_lds_bytes(const TileP& tp);
-size_t sort_scatter_lds_bytes(const TileP& tp);
-hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_part, size_t lds_count,
-                            size_t lds_scatter, int src_set, hipStream_t s);
-hipError_t launch_tiled(int dtype, int mode, int degree, const InstDesc* D, int ninst, int nblocks, size_t lds,
-                        StepArgs sa, hipStream_t s);
+hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_tiles, int nb_part,
+                            size_t lds_count, int src_set, hipStream_t s);
+// geometry code of a tile plan: a compiled window shape (1, 2) or 0 (from TileP)
+int tiled_geometry(const TileP& tp);
+hipError_t launch_tiled(int dtype, int mode, int degree, int geo, const InstDesc* D, int ninst, int nblocks,
+                        size_t lds, StepArgs sa, hipStream_t s);
 
 // field.hip
 void fft_make_twiddles(int n, double* host_re_im);  // n complex entries

@@ -1,19 +1,25 @@
-// Tile-sorted particle passes with LDS-privatised gather and deposition.
+// Cell-sorted particle passes with LDS-privatised gather and deposition.
 //
 // The grid's cells are split into tiles of TS x TS cells.  Every few steps the
-// particles are counting-sorted by the tile of their position (k_tile_count,
-// k_tile_scan, k_tile_scatter), and the scan cuts each tile's particle range
-// into chunks of at most CH particles: one chunk per workgroup.
+// particles are counting-sorted by cell, cells numbered tile-major
+// (k_tile_count, k_tile_scan, k_cell_scan, k_tile_scatter): each tile's
+// particles are contiguous and grouped by cell inside it.  The scan cuts each
+// tile's range into chunks of at most CH particles, one chunk per workgroup.
 //
 // A workgroup owns a window of W x W mesh nodes around its tile: the tile's
 // TS cells, a slack of S cells on each side (particles drift after the sort),
 // and the widest stencil reach (one node below, two above the cell).  It
-// copies the eleven gathered fields of the window into LDS, node-interleaved,
-// gathers from there, accumulates its J contributions in an LDS window, and
-// adds that window to the global float64 J with one atomic per non-zero node
-// component.  A particle whose stencil leaves the window (it drifted further
-// than S cells since the sort) takes the global-memory path for that
-// operation, so results never depend on the sort.
+// copies the eleven gathered fields of the window into LDS (one plane per
+// field), gathers from there, accumulates its J contributions in an LDS
+// window, and adds that window to the global float64 J with one atomic per
+// non-zero node component.  A particle whose stencil leaves the window (it
+// drifted further than S cells since the sort) takes the global-memory path
+// for that operation, so results never depend on the sort.
+//
+// Consecutive lanes take consecutive particles, so the lanes of a wave mostly
+// share a cell: the gather's LDS reads become broadcasts, and the deposit
+// rotates each lane's stencil order so that lanes of one cell add to
+// different LDS addresses at each atomic instruction.
 //
 // The per-particle arithmetic (spline weights, IAEM push, position update) is
 // shared with the untiled kernels through particle_math.h.
@@ -25,19 +31,22 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// tile of a position (cells floor(xi), clamped into the grid)
-__device__ __forceinline__ int tile_of(float xi, float eta, const TileP& tp) {
+// cell key of a position (cells floor(xi), clamped into the grid), numbered
+// tile-major: tile * ts^2 + (row in tile) * ts + (column in tile)
+__device__ __forceinline__ int cell_of(float xi, float eta, const TileP& tp) {
   int cx = (int)floorf(xi), cy = (int)floorf(eta);
   cx = cx < 0 ? 0 : (cx >= tp.nx ? tp.nx - 1 : cx);
   cy = cy < 0 ? 0 : (cy >= tp.ny ? tp.ny - 1 : cy);
-  return (cy >> tp.log_ts) * tp.ntx + (cx >> tp.log_ts);
+  const int tile = (cy >> tp.log_ts) * tp.ntx + (cx >> tp.log_ts);
+  const int m = tp.ts - 1;
+  return (tile << (2 * tp.log_ts)) + ((cy & m) << tp.log_ts) + (cx & m);
 }
 
 template <typename T>
-__device__ __forceinline__ int tile_key(T x, T y, const GridP& g, const TileP& tp) {
+__device__ __forceinline__ int cell_key(T x, T y, const GridP& g, const TileP& tp) {
   const float xi = (float)(x * T(g.inv_dx)), eta = (float)(y * T(g.inv_dy));
-  const bool ok = xi == xi && eta == eta;  // non-finite positions go to tile 0
-  return ok ? tile_of(xi, eta, tp) : 0;
+  const bool ok = xi == xi && eta == eta;  // non-finite positions go to cell 0
+  return ok ? cell_of(xi, eta, tp) : 0;
 }
 
 // Lanes of one wave that share a key: one LDS atomic per distinct key in the
@@ -65,8 +74,10 @@ __device__ __forceinline__ int wave_group_add(int32_t* __restrict__ counters, in
   return base;
 }
 
-// Tile histogram of the current positions: each block counts 1024 particles
-// of one instance (flattened over instances, BK_COUNT).
+// Cell and tile histograms of the current positions: each block counts 1024
+// particles of one instance (flattened over instances, BK_COUNT).  Tile
+// counts go through an LDS histogram; cell counts straight to global memory,
+// one atomic per distinct cell of a wave (particles stay nearly sorted).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_tile_count(const InstDesc* __restrict__ D, int ninst, int set) {
   extern __shared__ int32_t hist[];  // ntiles of this instance
@@ -82,10 +93,10 @@ __global__ void __launch_bounds__(kThreads) k_tile_count(const InstDesc* __restr
   for (int k = 0; k < 4; ++k) {  // whole waves stay in the loop
     const int64_t i = base + k * kThreads + threadIdx.x;
     const bool act = i < d.n;
-    int t = 0;
-    if (act) t = tile_key(px[i], py[i], g, tp);
+    const int c = act ? cell_key(px[i], py[i], g, tp) : 0;
     int r;
-    wave_group_add(hist, t, act, r);
+    wave_group_add(hist, c >> (2 * tp.log_ts), act, r);
+    wave_group_add(d.tb.ccount, c, act, r);
   }
   __syncthreads();
   for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x)
@@ -124,7 +135,6 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const InstDesc* __restrict__
     const int k0 = carry_c + s_chk[threadIdx.x] - k;
     if (t < tp.ntiles) {
       d.tb.start[t] = p0;
-      d.tb.cursor[t] = p0;
       for (int j = 0; j < k; ++j) {
         const int s = p0 + j * tp.chunk;
         const int e = min(p0 + c, s + tp.chunk);
@@ -145,30 +155,51 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const InstDesc* __restrict__
   }
 }
 
-// scatter set `src` into set `src ^ 1`; one global atomic per (block, tile)
+// cell cursors: one wave per tile scans the tile's ts^2 cell counts from the
+// tile's start (flattened over instances, BK_TILES: four tiles per block)
+__global__ void __launch_bounds__(kThreads) k_cell_scan(const InstDesc* __restrict__ D, int ninst) {
+  const int ii = find_inst(D, ninst, BK_TILES, blockIdx.x);
+  const InstDesc& d = D[ii];
+  const TileP tp = d.tp;
+  const int t = (blockIdx.x - d.blk[BK_TILES]) * (kThreads / 64) + (threadIdx.x >> 6);
+  if (t >= tp.ntiles) return;  // whole waves leave together
+  const int lane = threadIdx.x & 63;
+  const int cells = tp.ts * tp.ts;
+  int32_t* __restrict__ cc = d.tb.ccount + (size_t)t * cells;
+  int32_t* __restrict__ cu = d.tb.ccursor + (size_t)t * cells;
+  int run = d.tb.start[t];
+  for (int j0 = 0; j0 < cells; j0 += 64) {
+    const int j = j0 + lane;
+    const int c = j < cells ? cc[j] : 0;
+    int v = c;  // inclusive wave scan
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(v, off);
+      if (lane >= off) v += u;
+    }
+    if (j < cells) {
+      cu[j] = run + v - c;
+      cc[j] = 0;  // ready for the next sort
+    }
+    run += __shfl(v, 63);
+  }
+}
+
+// scatter set `src` into set `src ^ 1`, grouped by cell: one global atomic
+// per distinct cell of a wave
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __restrict__ D, int ninst, int src) {
-  extern __shared__ int32_t sh[];  // ntiles local counts, then ntiles bases
   const int ii = find_inst(D, ninst, BK_PART, blockIdx.x);
   const InstDesc& d = D[ii];
   const TileP tp = d.tp;
-  int32_t* lc = sh;
-  int32_t* lb = sh + tp.ntiles;
   const int64_t i = (int64_t)(blockIdx.x - d.blk[BK_PART]) * kThreads + threadIdx.x;
-  for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x) lc[t] = 0;
-  __syncthreads();
   const bool act = i < d.n;
   const void* const* S = d.set[src];
   void* const* Dd = d.set[src ^ 1];
-  const int k = act ? tile_key(((const T*)S[0])[i], ((const T*)S[1])[i], d.g, tp) : 0;
+  const int c = act ? cell_key(((const T*)S[0])[i], ((const T*)S[1])[i], d.g, tp) : 0;
   int rr;
-  const int r = wave_group_add(lc, k, act, rr) + rr;
-  __syncthreads();
-  for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x)
-    lb[t] = lc[t] ? atomicAdd(&d.tb.cursor[t], lc[t]) : 0;
-  __syncthreads();
+  const int base = wave_group_add(d.tb.ccursor, c, act, rr);
   if (act) {
-    const int64_t o = lb[k] + r;
+    const int64_t o = base + rr;
 #pragma unroll
     for (int a = 0; a < 11; ++a) ((T*)Dd[a])[o] = ((const T*)S[a])[i];
     d.ids[src ^ 1][o] = d.ids[src][i];
@@ -188,10 +219,24 @@ struct Acc {
   using type = double;
 };
 
-template <typename T, int DEG, int MODE>
+// Window geometry: compile-time for the compiled tile shapes (TS > 0: tiles of
+// TS x TS cells, slack SL), so that every window offset of the gather and the
+// deposit is an immediate of the LDS instruction; TS = 0 reads it from TileP.
+template <int TS, int SL>
+struct Geo {
+  static constexpr int W = TS + 2 * SL + 3;
+  static constexpr int WP = (W * W + 63) / 64 * 64;
+  static constexpr int RL = W <= 8 ? 8 : (W <= 16 ? 16 : (W <= 32 ? 32 : 64));
+  static constexpr int LRL = RL == 8 ? 3 : (RL == 16 ? 4 : (RL == 32 ? 5 : 6));
+};
+
+template <typename T, int DEG, int MODE, int TS, int SL>
 __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__ D, int ninst, StepArgs sa) {
   constexpr bool GATHER = MODE != MODE_DEPOSIT;
   constexpr bool DEPOSIT = MODE != MODE_GATHER_PUSH;
+  constexpr bool ROTATE = sizeof(T) == 4;  // rotated deposit order (float32 particles)
+  constexpr bool FIXED = TS > 0;
+  using G = Geo<(FIXED ? TS : 1), (FIXED ? SL : 0)>;
   using A = typename Acc<T>::type;
   const int ii = find_inst(D, ninst, BK_WORK, blockIdx.x);
   const InstDesc& d = D[ii];
@@ -204,17 +249,18 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   const Parts<T> p = make_parts<T>(d, sa.cur, sa.vflip);
   const T* __restrict__ F = GATHER ? (d.F32 ? (const T*)(const void*)d.F32 : (const T*)(const void*)d.F64) : nullptr;
   double* __restrict__ J = d.J;
-  const int W = tp.win;
-  const int WP = tp.win_pad;  // plane stride of the LDS windows (field f at f*WP)
+  const int W = FIXED ? G::W : tp.win;
+  const int WP = FIXED ? G::WP : tp.win_pad;  // plane stride of the LDS windows (field f at f*WP)
+  const int ts = FIXED ? TS : tp.ts, slack = FIXED ? SL : tp.slack;
   const int tiy = it.x >> tp.log_ntx, tix = it.x - (tiy << tp.log_ntx);
-  const int ox = tix * tp.ts - tp.slack - 1, oy = tiy * tp.ts - tp.slack - 1;
+  const int ox = tix * ts - slack - 1, oy = tiy * ts - slack - 1;
   extern __shared__ __align__(16) unsigned char smem[];
   T* fw = reinterpret_cast<T*>(smem);
   A* jw = reinterpret_cast<A*>(smem + (GATHER ? (size_t)11 * WP * sizeof(T) : 0));
   const size_t plane = (size_t)g.nx * g.ny;
   // window sweeps without integer division: lanes of a row-group cover x
-  // (tp.row_lanes >= W, a power of two), row-groups cover y
-  const int rl = tp.row_lanes, lrl = tp.log_row_lanes;
+  // (row_lanes >= W, a power of two), row-groups cover y
+  const int rl = FIXED ? G::RL : tp.row_lanes, lrl = FIXED ? G::LRL : tp.log_row_lanes;
   const int wi = threadIdx.x & (rl - 1), wj0 = threadIdx.x >> lrl, wjs = blockDim.x >> lrl;
   const int gxw = (ox + wi) & (g.nx - 1);
   if (GATHER && wi < W) {
@@ -230,29 +276,55 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   __syncthreads();
 
   using S = Spline<T, DEG>;
+  constexpr int NW = S::NW;
   const T dt = T(ph.dt), qs = T(ph.q) * T(g.inv_area);
-  for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
-    const int64_t i = it.y + k;
-    T x = p.x[i], y = p.y[i];
-    T vx = p.v[0][i], vy = p.v[1][i], vz = p.v[2][i];
+  // One particle per lane, consecutive lanes on consecutive particles.  The
+  // set is sorted by cell, so the lanes of a wave mostly share one or two
+  // cells: their gather reads hit the same LDS addresses (broadcasts).
+  const int lane = threadIdx.x & 63;
+  T cx = T(0), cy = T(0), cvx = T(0), cvy = T(0), cvz = T(0), cP[3] = {T(0), T(0), T(0)},
+    cw[3] = {T(0), T(0), T(0)};
+  auto load = [&](int64_t i) {
+    cx = p.x[i];
+    cy = p.y[i];
+    cvx = p.v[0][i];
+    cvy = p.v[1][i];
+    cvz = p.v[2][i];
     if (GATHER) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cP[c] = p.P[c][i];
+        cw[c] = p.w[c][i];
+      }
+    }
+  };
+  if ((int)threadIdx.x < it.z) load(it.y + threadIdx.x);
+  for (int k0 = 0; k0 < it.z; k0 += blockDim.x) {
+    const int k = k0 + threadIdx.x;
+    const bool act = k < it.z;
+    const int64_t i = it.y + k;
+    T x = cx, y = cy, vx = cvx, vy = cvy, vz = cvz;
+    T Px = cP[0], Py = cP[1], Pz = cP[2], w0 = cw[0], w1 = cw[1], w2 = cw[2];
+    if (k + (int)blockDim.x < it.z) load(i + blockDim.x);  // next particle, in flight meanwhile
+    if (GATHER && act) {
       T gv[11];
 #pragma unroll
       for (int f = 0; f < 11; ++f) gv[f] = T(0);
       const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
       if (in_box(xi, eta, g)) {
         int sx, sy;
-        T wx[S::NW], wy[S::NW];
+        T wx[NW], wy[NW];
         S::eval(xi, sx, wx);
         S::eval(eta, sy, wy);
         const int lx = (sx - ox) & (g.nx - 1), ly = (sy - oy) & (g.ny - 1);
         if (lx + DEG < W && ly + DEG < W) {
+          const T* nd0 = fw + ly * W + lx;
 #pragma unroll
-          for (int b = 0; b < S::NW; ++b) {
+          for (int b = 0; b < NW; ++b) {
 #pragma unroll
-            for (int a = 0; a < S::NW; ++a) {
+            for (int a = 0; a < NW; ++a) {
               const T w = wx[a] * wy[b];
-              const T* nd = fw + (ly + b) * W + lx + a;
+              const T* nd = nd0 + b * W + a;
 #pragma unroll
               for (int f = 0; f < 11; ++f) gv[f] += w * nd[f * WP];
             }
@@ -261,11 +333,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
           gather_global<T, DEG>(sx, sy, wx, wy, F, g, gv);
         }
       }
-      T Px = p.P[0][i], Py = p.P[1][i];
-      const T Pz = p.P[2][i];
-      const T wx0 = p.w[0][i], wy0 = p.w[1][i], wz0 = p.w[2][i];
       T nvx, nvy, nvz;
-      push_one<T>(gv, Px, Py, Pz, vx, vy, vz, wx0, wy0, wz0, ph, nvx, nvy, nvz);
+      push_one<T>(gv, Px, Py, Pz, vx, vy, vz, w0, w1, w2, ph, nvx, nvy, nvz);
       p.P[0][i] = Px;
       p.P[1][i] = Py;
       p.w[0][i] = nvx;
@@ -276,32 +345,87 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       vz = nvz;
     }
     if (DEPOSIT) {
-      x = wrapx<T>(x + vx * dt, T(g.lx));
-      y = wrapx<T>(y + vy * dt, T(g.ly));
-      p.x[i] = x;
-      p.y[i] = y;
-      const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
-      if (in_box(xi, eta, g)) {
-        int sx, sy;
-        T wx[S::NW], wy[S::NW];
-        S::eval(xi, sx, wx);
-        S::eval(eta, sy, wy);
-        const T jx = qs * vx, jy = qs * vy, jz = qs * vz;
-        const int lx = (sx - ox) & (g.nx - 1), ly = (sy - oy) & (g.ny - 1);
-        if (lx + DEG < W && ly + DEG < W) {
+      bool inw = false;
+      int sx = 0, sy = 0, lx = 0, ly = 0;
+      T wx[NW], wy[NW];
 #pragma unroll
-          for (int b = 0; b < S::NW; ++b) {
+      for (int a = 0; a < NW; ++a) wx[a] = wy[a] = T(0);
+      T jx = T(0), jy = T(0), jz = T(0);
+      if (act) {
+        x = wrapx<T>(x + vx * dt, T(g.lx));
+        y = wrapx<T>(y + vy * dt, T(g.ly));
+        p.x[i] = x;
+        p.y[i] = y;
+        const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
+        if (in_box(xi, eta, g)) {
+          S::eval(xi, sx, wx);
+          S::eval(eta, sy, wy);
+          jx = qs * vx;
+          jy = qs * vy;
+          jz = qs * vz;
+          lx = (sx - ox) & (g.nx - 1);
+          ly = (sy - oy) & (g.ny - 1);
+          inw = lx + DEG < W && ly + DEG < W;
+          if (!inw) deposit_global<T, DEG>(sx, sy, wx, wy, jx, jy, jz, J, g);
+        }
+      }
+      if (ROTATE) {
+        // per-lane rotation of stencil columns, rows and components: lanes
+        // of one cell (neighbours in the cell-sorted order) add to different
+        // window addresses at each instruction
+        const int ra = lane % NW, rb = (lane / NW) % NW, rc = (lane / (NW * NW)) % 3;
+        T wxr[NW], wyr[NW];
+        int coff[NW], roff[NW];
 #pragma unroll
-            for (int a = 0; a < S::NW; ++a) {
-              const T w = wx[a] * wy[b];
-              A* nd = jw + (ly + b) * W + lx + a;
-              atomicAdd(nd, A(jx * w));
-              atomicAdd(nd + WP, A(jy * w));
-              atomicAdd(nd + 2 * WP, A(jz * w));
+        for (int t = 0; t < NW; ++t) {
+          int ia = t + ra, ib = t + rb;
+          ia = ia >= NW ? ia - NW : ia;
+          ib = ib >= NW ? ib - NW : ib;
+          T va = wx[0], vb = wy[0];
+#pragma unroll
+          for (int u = 1; u < NW; ++u) {
+            va = ia == u ? wx[u] : va;
+            vb = ib == u ? wy[u] : vb;
+          }
+          wxr[t] = va;
+          wyr[t] = vb;
+          coff[t] = ia;
+          roff[t] = ib * W;
+        }
+        T jr[3];
+        int poff[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          int ic = c + rc;
+          ic = ic >= 3 ? ic - 3 : ic;
+          jr[c] = ic == 0 ? jx : (ic == 1 ? jy : jz);
+          poff[c] = ic * WP;
+        }
+        if (inw) {
+          A* nd0 = jw + ly * W + lx;
+#pragma unroll
+          for (int b = 0; b < NW; ++b) {
+#pragma unroll
+            for (int a = 0; a < NW; ++a) {
+              const T w = wxr[a] * wyr[b];
+              A* nd = nd0 + roff[b] + coff[a];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) atomicAdd(nd + poff[c], A(jr[c] * w));
             }
           }
-        } else {
-          deposit_global<T, DEG>(sx, sy, wx, wy, jx, jy, jz, J, g);
+        }
+      } else if (inw) {
+        A* nd0 = jw + ly * W + lx;
+#pragma unroll
+        for (int b = 0; b < NW; ++b) {
+#pragma unroll
+          for (int a = 0; a < NW; ++a) {
+            const T w = wx[a] * wy[b];
+            A* nd = nd0 + b * W + a;
+            atomicAdd(nd, A(jx * w));
+            atomicAdd(nd + WP, A(jy * w));
+            atomicAdd(nd + 2 * WP, A(jz * w));
+          }
         }
       }
     }
@@ -322,30 +446,41 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   }
 }
 
+// compiled window geometries: geo 0 = from TileP, 1 = 16x16 tiles with slack
+// 3, 2 = 8x8 tiles with slack 3
 template <typename T, int DEG, int MODE>
-hipError_t launch_tiled_t(const InstDesc* D, int ninst, int nblocks, size_t lds, StepArgs sa, hipStream_t s) {
-  hipFuncSetAttribute((const void*)k_tiled<T, DEG, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_tiled<T, DEG, MODE>), dim3(nblocks), dim3(kThreads), lds, s, D, ninst, sa);
+hipError_t launch_tiled_t(int geo, const InstDesc* D, int ninst, int nblocks, size_t lds, StepArgs sa,
+                          hipStream_t s) {
+  const void* fn = geo == 1 ? (const void*)k_tiled<T, DEG, MODE, 16, 3>
+                   : geo == 2 ? (const void*)k_tiled<T, DEG, MODE, 8, 3>
+                              : (const void*)k_tiled<T, DEG, MODE, 0, 0>;
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (geo == 1)
+    hipLaunchKernelGGL((k_tiled<T, DEG, MODE, 16, 3>), dim3(nblocks), dim3(kThreads), lds, s, D, ninst, sa);
+  else if (geo == 2)
+    hipLaunchKernelGGL((k_tiled<T, DEG, MODE, 8, 3>), dim3(nblocks), dim3(kThreads), lds, s, D, ninst, sa);
+  else
+    hipLaunchKernelGGL((k_tiled<T, DEG, MODE, 0, 0>), dim3(nblocks), dim3(kThreads), lds, s, D, ninst, sa);
   return hipGetLastError();
 }
 
 template <typename T, int MODE>
-hipError_t launch_tiled_deg(int degree, const InstDesc* D, int ninst, int nblocks, size_t lds, StepArgs sa,
+hipError_t launch_tiled_deg(int degree, int geo, const InstDesc* D, int ninst, int nblocks, size_t lds, StepArgs sa,
                             hipStream_t s) {
   switch (degree) {
-    case 1: return launch_tiled_t<T, 1, MODE>(D, ninst, nblocks, lds, sa, s);
-    case 2: return launch_tiled_t<T, 2, MODE>(D, ninst, nblocks, lds, sa, s);
-    default: return launch_tiled_t<T, 3, MODE>(D, ninst, nblocks, lds, sa, s);
+    case 1: return launch_tiled_t<T, 1, MODE>(geo, D, ninst, nblocks, lds, sa, s);
+    case 2: return launch_tiled_t<T, 2, MODE>(geo, D, ninst, nblocks, lds, sa, s);
+    default: return launch_tiled_t<T, 3, MODE>(geo, D, ninst, nblocks, lds, sa, s);
   }
 }
 
 template <typename T>
-hipError_t launch_tiled_mode(int mode, int degree, const InstDesc* D, int ninst, int nblocks, size_t lds,
+hipError_t launch_tiled_mode(int mode, int degree, int geo, const InstDesc* D, int ninst, int nblocks, size_t lds,
                              StepArgs sa, hipStream_t s) {
   switch (mode) {
-    case MODE_DEPOSIT: return launch_tiled_deg<T, MODE_DEPOSIT>(degree, D, ninst, nblocks, lds, sa, s);
-    case MODE_GATHER_PUSH: return launch_tiled_deg<T, MODE_GATHER_PUSH>(degree, D, ninst, nblocks, lds, sa, s);
-    default: return launch_tiled_deg<T, MODE_FUSED>(degree, D, ninst, nblocks, lds, sa, s);
+    case MODE_DEPOSIT: return launch_tiled_deg<T, MODE_DEPOSIT>(degree, geo, D, ninst, nblocks, lds, sa, s);
+    case MODE_GATHER_PUSH: return launch_tiled_deg<T, MODE_GATHER_PUSH>(degree, geo, D, ninst, nblocks, lds, sa, s);
+    default: return launch_tiled_deg<T, MODE_FUSED>(degree, geo, D, ninst, nblocks, lds, sa, s);
   }
 }
 
@@ -357,29 +492,38 @@ size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp) {
          (mode != MODE_GATHER_PUSH ? (size_t)3 * tp.win_pad * 8 : 0);
 }
 size_t sort_count_lds_bytes(const TileP& tp) { return (size_t)tp.ntiles * sizeof(int32_t); }
-size_t sort_scatter_lds_bytes(const TileP& tp) { return (size_t)2 * tp.ntiles * sizeof(int32_t); }
 
-// count (BK_COUNT blocks), scan (one block per instance), scatter (BK_PART blocks)
-hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_part, size_t lds_count,
-                            size_t lds_scatter, int src_set, hipStream_t s) {
-  if (dtype == PIC_F32) {
-    if (nb_count) hipLaunchKernelGGL(k_tile_count<float>, dim3(nb_count), dim3(kThreads), lds_count, s, D, ninst, src_set);
-  } else {
-    if (nb_count) hipLaunchKernelGGL(k_tile_count<double>, dim3(nb_count), dim3(kThreads), lds_count, s, D, ninst, src_set);
+// count (BK_COUNT blocks), tile scan (one block per instance), cell scan
+// (BK_TILES blocks), scatter (BK_PART blocks)
+hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_tiles, int nb_part,
+                            size_t lds_count, int src_set, hipStream_t s) {
+  if (nb_count) {
+    if (dtype == PIC_F32)
+      hipLaunchKernelGGL(k_tile_count<float>, dim3(nb_count), dim3(kThreads), lds_count, s, D, ninst, src_set);
+    else
+      hipLaunchKernelGGL(k_tile_count<double>, dim3(nb_count), dim3(kThreads), lds_count, s, D, ninst, src_set);
   }
   hipLaunchKernelGGL(k_tile_scan, dim3(ninst), dim3(1024), 0, s, D, ninst);
-  if (dtype == PIC_F32) {
-    if (nb_part) hipLaunchKernelGGL(k_tile_scatter<float>, dim3(nb_part), dim3(kThreads), lds_scatter, s, D, ninst, src_set);
-  } else {
-    if (nb_part) hipLaunchKernelGGL(k_tile_scatter<double>, dim3(nb_part), dim3(kThreads), lds_scatter, s, D, ninst, src_set);
+  hipLaunchKernelGGL(k_cell_scan, dim3(nb_tiles), dim3(kThreads), 0, s, D, ninst);
+  if (nb_part) {
+    if (dtype == PIC_F32)
+      hipLaunchKernelGGL(k_tile_scatter<float>, dim3(nb_part), dim3(kThreads), 0, s, D, ninst, src_set);
+    else
+      hipLaunchKernelGGL(k_tile_scatter<double>, dim3(nb_part), dim3(kThreads), 0, s, D, ninst, src_set);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_tiled(int dtype, int mode, int degree, const InstDesc* D, int ninst, int nblocks, size_t lds,
-                        StepArgs sa, hipStream_t s) {
-  if (dtype == PIC_F32) return launch_tiled_mode<float>(mode, degree, D, ninst, nblocks, lds, sa, s);
-  return launch_tiled_mode<double>(mode, degree, D, ninst, nblocks, lds, sa, s);
+int tiled_geometry(const TileP& tp) {
+  if (tp.slack == 3 && tp.ts == 16) return 1;
+  if (tp.slack == 3 && tp.ts == 8) return 2;
+  return 0;
+}
+
+hipError_t launch_tiled(int dtype, int mode, int degree, int geo, const InstDesc* D, int ninst, int nblocks,
+                        size_t lds, StepArgs sa, hipStream_t s) {
+  if (dtype == PIC_F32) return launch_tiled_mode<float>(mode, degree, geo, D, ninst, nblocks, lds, sa, s);
+  return launch_tiled_mode<double>(mode, degree, geo, D, ninst, nblocks, lds, sa, s);
 }
 
 }  // namespace pic
