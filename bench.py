@@ -10,8 +10,10 @@ timed region; the K timed steps are bracketed by stream synchronisations.
 
 Prints one JSON line with the particle-steps/s value, a roofline entry for the
 dominant kernel (the fused gather/push/deposit particle pass, timed with HIP
-events on the library's stream inside the timed region) and the FP64 oracle
-timed on the host on a bounded sample of the same workload.
+events on the library's stream inside the timed region), the batched form
+(64-instance uneven ensemble, tile plan from the autotuner) and the adjoint
+form (gradient through 20 float64 steps) against the plain step, and the FP64
+oracle timed on the host on a bounded sample of the same workload.
 """
 
 import argparse
@@ -89,6 +91,124 @@ def cpu_baseline(w, spec, nsteps):
                        % (nsteps, n))
 
 
+def _events(stream):
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    return a, b
+
+
+def bench_batched(steps, warmup):
+    """The 64-instance uneven ensemble (grids 32..256 per side, 4..64
+    particles/cell, Maxwellian clouds, cubic, BDF-2, float32) as one context
+    (step_batched: one launch per phase over all instances, graph-replayed),
+    with the tile plan from the autotuner, against the same 64 instances run
+    one after another as plain contexts with the same plan."""
+    import torch
+    from paper_2410_18414_amd import autotune, pic, workloads
+    ws = workloads.ensemble()
+    dev = torch.device("cuda:0")
+    data = [(torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
+             torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev)) for w in ws]
+    total = sum(len(w["x"]) for w in ws)
+
+    def make_cfgs():
+        return [pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=3, scheme="bdf",
+                                bdf_order=2, dtype="f32", q=w["q"], m=w["m"], max_particles=len(w["x"]))
+                for w in ws]
+
+    def load(ctx):
+        for i, (x, y, P) in enumerate(data):
+            if pic.instance_count(ctx) > 1:
+                pic.select_instance(ctx, i)
+            pic.init_particles(ctx, x, y, P)
+
+    plan = autotune.tune("ensemble64-draw4999-seeds4000-cubic-bdf2-f32", make_cfgs, load)
+    cfgs = autotune.apply(make_cfgs(), plan)
+    ctx = pic.Context(cfgs)
+    load(ctx)
+    pic.step_batched(ctx, warmup)
+    a, b = _events(ctx.stream)
+    torch.cuda.synchronize()
+    a.record(ctx.stream)
+    pic.step_batched(ctx, steps)
+    b.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms_b = a.elapsed_time(b) / steps
+    ctx.close()
+    del ctx
+    # the same instances one after another, each its own context
+    ms_p = 0.0
+    for i, cfg in enumerate(cfgs):
+        c = pic.Context(cfg)
+        pic.init_particles(c, *data[i])
+        pic.step(c, warmup)
+        a, b = _events(c.stream)
+        torch.cuda.synchronize()
+        a.record(c.stream)
+        pic.step(c, steps)
+        b.record(c.stream)
+        torch.cuda.synchronize()
+        ms_p += a.elapsed_time(b) / steps
+        c.close()
+    return dict(workload="ensemble of 64 uneven Maxwellian clouds (grids 32..256 per side, 4..64 ppc, "
+                         "cubic, BDF-2, f32)", instances=len(ws), particles=total, steps=steps,
+                ms_per_step=round(ms_b, 5), value=round(total / (ms_b * 1e-3), 1),
+                plain_ms_per_step=round(ms_p, 5), plain_value=round(total / (ms_p * 1e-3), 1),
+                speedup_vs_plain=round(ms_p / ms_b, 3),
+                tile_plan={k: plan[k] for k in ("tile_cells", "chunk", "unfused")},
+                tile_plan_cached=bool(plan.get("cached")))
+
+
+def bench_adjoint(every=5):
+    """Gradient of the final field energy through 20 BDF-2 steps of the
+    128 x 128, 64 particles/cell anisotropic workload with drift (float64,
+    cubic, checkpoints every 5 steps) against the plain float64 forward."""
+    import torch
+    from paper_2410_18414_amd import adjoint, pic, workloads
+    w = workloads.make(5)
+    nsteps = w["steps"]
+    n = len(w["x"])
+    dev = torch.device("cuda:0")
+    cfg = pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=3, scheme="bdf", bdf_order=2,
+                          dtype="f64", q=w["q"], m=w["m"], max_particles=n, flags=pic.FLAG_ADJOINT)
+    ctx = pic.Context(cfg)
+    x0 = torch.as_tensor(w["x"], device=dev)
+    y0 = torch.as_tensor(w["y"], device=dev)
+    P0 = torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev)
+    # plain forward (warm, then timed)
+    pic.init_particles(ctx, x0, y0, P0)
+    pic.step(ctx, nsteps)
+    pic.init_particles(ctx, x0, y0, P0)
+    a, b = _events(ctx.stream)
+    torch.cuda.synchronize()
+    a.record(ctx.stream)
+    pic.step(ctx, nsteps)
+    b.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms_fwd = a.elapsed_time(b) / nsteps
+    # gradient: checkpointed forward + reverse sweep (warm once, then timed)
+    for timed in (False, True):
+        xg, yg, Pg = x0.clone().requires_grad_(), y0.clone().requires_grad_(), P0.clone().requires_grad_()
+        torch.cuda.synchronize()
+        a.record(ctx.stream)
+        t0 = time.perf_counter()
+        W = adjoint.field_energy(ctx, xg, yg, Pg, nsteps, every=every)
+        W.backward()
+        b.record(ctx.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    ms_grad = a.elapsed_time(b)
+    ctx.close()
+    return dict(workload="weibel-128x128-64ppc-drift0.1-cubic-bdf2-f64, gradient of the field energy after "
+                         "%d steps, checkpoints every %d" % (nsteps, every), particles=n, steps=nsteps,
+                forward_ms_per_step=round(ms_fwd, 5), gradient_ms=round(ms_grad, 3),
+                gradient_wall_s=round(wall, 4),
+                gradient_ms_per_step=round(ms_grad / nsteps, 5),
+                gradient_vs_forward=round(ms_grad / (ms_fwd * nsteps), 2),
+                particle_steps_per_s=round(n * nsteps / (ms_grad * 1e-3), 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +223,9 @@ def main():
     ap.add_argument("--tile-cells", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--slack", type=int, default=0)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance ensemble section")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) section")
+    ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (counter calibration)")
     args = ap.parse_args()
@@ -200,6 +323,11 @@ def main():
         "wall_s": round(wall, 4),
         "gauge_rel": diag["gauge_l2"] / diag["gauge_scale"] if diag["gauge_scale"] else 0.0,
     }
+    ctx.close()
+    if not args.no_batched:
+        out["batched"] = bench_batched(args.batched_steps, 6)
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, spec, args.cpu_steps)
     print(json.dumps(out), flush=True)
