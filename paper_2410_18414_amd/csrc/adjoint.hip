@@ -5,7 +5,7 @@
 // arrays (x, y, P, v^n, v^{n-1}) and the spectral history.
 //
 // The sweep runs the forward phases backwards:
-//   k_adj_push     push and gather adjoint: v' = c^2 u / s (Sec. 2.2) has the
+//   k_adj_push(_t) push and gather adjoint: v' = c^2 u / s (Sec. 2.2) has the
 //                  symmetric Jacobian (c^2/s)(I - c^2 u u^T / s^2); the IAEM
 //                  force (Sec. 4.1) is linear in the gathered values; the
 //                  gather's adjoint scatters lambda_g onto the 11 mesh fields
@@ -17,7 +17,7 @@
 //                  transposed per-mode BDF recurrence (continuity, both
 //                  Helmholtz solves and the history shift), then the adjoint
 //                  of J^ = rfft2(J), which is N irfft2(lambda_J^ / w).
-//   k_adj_deposit  deposit adjoint: a gather of lambda_J with the spline
+//   k_adj_deposit(_t) deposit adjoint: a gather of lambda_J with the spline
 //                  weights (lambda_v) and their derivatives (lambda_x), then
 //                  the position update x' = x + v dt.
 //
@@ -38,65 +38,22 @@ namespace pic {
 
 namespace {
 
-// ---------------------------------------------------------------------------
-// push + gather adjoint.  Particle arrays hold x^{n+1} (recomputed), P^n, v^n
-// and v^{n-1}; F64 holds the mesh fields of level n+1.
-template <int DEG>
-__global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D, StepArgs sa, double* __restrict__ lam) {
-  using S = Spline<double, DEG>;
-  const InstDesc& d = D[0];
-  const int64_t n = d.n;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const GridP g = d.g;
-  const PhysP ph = d.ph;
-  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
-  const int64_t o = p.id[i];
-  const size_t plane = (size_t)g.nx * g.ny;
-  const double* __restrict__ F = d.F64;
-  const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
-  const bool inside = in_box(xi, eta, g);
-  int sx = 0, sy = 0;
-  double wx[S::NW], dwx[S::NW], wy[S::NW], dwy[S::NW];
-  double gv[11], gdx[11], gdy[11];
-#pragma unroll
-  for (int f = 0; f < 11; ++f) gv[f] = gdx[f] = gdy[f] = 0.0;
-  if (inside) {
-    S::eval_d(xi, sx, wx, dwx);
-    S::eval_d(eta, sy, wy, dwy);
-#pragma unroll
-    for (int b = 0; b < S::NW; ++b) {
-      const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
-      double aw[11], ad[11];
-#pragma unroll
-      for (int f = 0; f < 11; ++f) aw[f] = ad[f] = 0.0;
-#pragma unroll
-      for (int a = 0; a < S::NW; ++a) {
-        const size_t m = row + wrapi(sx + a, g.nx);
-#pragma unroll
-        for (int f = 0; f < 11; ++f) {
-          const double v = F[f * plane + m];
-          aw[f] += wx[a] * v;
-          ad[f] += dwx[a] * v;
-        }
-      }
-#pragma unroll
-      for (int f = 0; f < 11; ++f) {
-        gv[f] += wy[b] * aw[f];
-        gdx[f] += wy[b] * ad[f];
-        gdy[f] += dwy[b] * aw[f];
-      }
-    }
-  }
+// Push adjoint of one particle: gathered values gv (and their x, y
+// derivatives gdx, gdy, per unit node coordinate) at x^{n+1}; P^n, v^n,
+// v^{n-1}; lambda^{n+1} in lam[.][o] in, lambda (all but the deposit part) out.
+// Returns lambda_g in lg[11] (to be scattered onto the mesh fields).
+__device__ __forceinline__ void adj_push_one(const double* gv, const double* gdx, const double* gdy, double P0,
+                                             double P1, double P2, double v0, double v1, double v2, double w0,
+                                             double w1, double w2, const PhysP& ph, const GridP& g,
+                                             double* __restrict__ lam, int64_t n, int64_t o, double* lg) {
   // forward push (IAEM) with its intermediates
   const double q = ph.q, dt = ph.dt, c2 = ph.c * ph.c, mc2 = ph.m * c2;
-  const double v0 = p.v[0][i], v1 = p.v[1][i], v2 = p.v[2][i];
-  const double s0 = 2.0 * v0 - p.w[0][i], s1 = 2.0 * v1 - p.w[1][i], s2 = 2.0 * v2 - p.w[2][i];
+  const double s0 = 2.0 * v0 - w0, s1 = 2.0 * v1 - w1, s2 = 2.0 * v2 - w2;
   const double Fx = -gv[0] + s0 * gv[5] + s1 * gv[6] + s2 * gv[7];
   const double Fy = -gv[1] + s0 * gv[8] + s1 * gv[9] + s2 * gv[10];
-  const double ux = p.P[0][i] + q * Fx * dt - q * gv[2];
-  const double uy = p.P[1][i] + q * Fy * dt - q * gv[3];
-  const double uz = p.P[2][i] - q * gv[4];
+  const double ux = P0 + q * Fx * dt - q * gv[2];
+  const double uy = P1 + q * Fy * dt - q * gv[3];
+  const double uz = P2 - q * gv[4];
   const double ss = sqrt(c2 * (ux * ux + uy * uy + uz * uz) + mc2 * mc2);
   // adjoint of v' = c^2 u / ss
   const double lvx = lam[5 * n + o], lvy = lam[6 * n + o], lvz = lam[7 * n + o];
@@ -106,7 +63,6 @@ __global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D
   // P' = P + q dt (Fx, Fy, 0), u = P' - q A
   const double lPx = lam[2 * n + o] + lux, lPy = lam[3 * n + o] + luy, lPz = lam[4 * n + o] + luz;
   const double lFx = q * dt * lPx, lFy = q * dt * lPy;
-  double lg[11];
   lg[0] = -lFx;
   lg[1] = -lFy;
   lg[2] = -q * lux;
@@ -140,6 +96,75 @@ __global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D
   lam[8 * n + o] = -lsx;
   lam[9 * n + o] = -lsy;
   lam[10 * n + o] = -lsz;
+}
+
+// gathered values and their node-coordinate derivatives from planar fields
+// F[f * stride + node] with nodes (sx + a, sy + b) at row pitch `pitch` (a
+// window, or the global mesh with wrapped indices when `wrap`)
+template <int DEG, int NF>
+__device__ __forceinline__ void gather_d(const double* __restrict__ F, size_t stride, const double* wx,
+                                         const double* dwx, const double* wy, const double* dwy, int sx, int sy,
+                                         const GridP& g, int pitch, bool wrap, double* gv, double* gdx,
+                                         double* gdy) {
+  constexpr int NW = DEG + 1;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) gv[f] = gdx[f] = gdy[f] = 0.0;
+#pragma unroll
+  for (int b = 0; b < NW; ++b) {
+    const size_t row = wrap ? (size_t)wrapi(sy + b, g.ny) * g.nx : (size_t)(sy + b) * pitch;
+    double aw[NF], ad[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) aw[f] = ad[f] = 0.0;
+#pragma unroll
+    for (int a = 0; a < NW; ++a) {
+      const size_t m = row + (wrap ? wrapi(sx + a, g.nx) : sx + a);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const double v = F[f * stride + m];
+        aw[f] += wx[a] * v;
+        ad[f] += dwx[a] * v;
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      gv[f] += wy[b] * aw[f];
+      gdx[f] += wy[b] * ad[f];
+      gdy[f] += dwy[b] * aw[f];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// push + gather adjoint.  Particle arrays hold x^{n+1} (recomputed), P^n, v^n
+// and v^{n-1}; F64 holds the mesh fields of level n+1.
+template <int DEG>
+__global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D, StepArgs sa, double* __restrict__ lam) {
+  using S = Spline<double, DEG>;
+  const InstDesc& d = D[0];
+  const int64_t n = d.n;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const GridP g = d.g;
+  const PhysP ph = d.ph;
+  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
+  const int64_t o = p.id[i];
+  const size_t plane = (size_t)g.nx * g.ny;
+  const double* __restrict__ F = d.F64;
+  const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
+  const bool inside = in_box(xi, eta, g);
+  int sx = 0, sy = 0;
+  double wx[S::NW], dwx[S::NW], wy[S::NW], dwy[S::NW];
+  double gv[11], gdx[11], gdy[11];
+#pragma unroll
+  for (int f = 0; f < 11; ++f) gv[f] = gdx[f] = gdy[f] = 0.0;
+  if (inside) {
+    S::eval_d(xi, sx, wx, dwx);
+    S::eval_d(eta, sy, wy, dwy);
+    gather_d<DEG, 11>(F, plane, wx, dwx, wy, dwy, sx, sy, g, 0, true, gv, gdx, gdy);
+  }
+  double lg[11];
+  adj_push_one(gv, gdx, gdy, p.P[0][i], p.P[1][i], p.P[2][i], p.v[0][i], p.v[1][i], p.v[2][i], p.w[0][i],
+               p.w[1][i], p.w[2][i], ph, g, lam, n, o, lg);
   if (!inside) return;
   double* __restrict__ LF = d.LF;
 #pragma unroll
@@ -152,6 +177,189 @@ __global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D
 #pragma unroll
       for (int f = 0; f < 11; ++f) atomicAdd(LF + f * plane + m, lg[f] * w);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same two particle passes over the cell-sorted chunks of the forward
+// (one workgroup per chunk, the tile's W x W window in LDS): the push adjoint
+// gathers the mesh fields from the window and scatters lambda_g into an LDS
+// window of the field adjoints (flushed to LF once per chunk); the deposit
+// adjoint gathers lambda_J from a window.  A particle whose stencil leaves the
+// window uses the global arrays, as in the forward passes.
+struct AdjWin {
+  int W, WP, ox, oy, wi, wj0, wjs, gxw;
+};
+
+__device__ __forceinline__ AdjWin adj_window(const InstDesc& d, const int4& it) {
+  const TileP tp = d.tp;
+  AdjWin a;
+  a.W = tp.win;
+  a.WP = tp.win_pad;
+  const int tiy = it.x >> tp.log_ntx, tix = it.x - (tiy << tp.log_ntx);
+  a.ox = tix * tp.ts - tp.slack - 1;
+  a.oy = tiy * tp.ts - tp.slack - 1;
+  a.wi = threadIdx.x & (tp.row_lanes - 1);
+  a.wj0 = threadIdx.x >> tp.log_row_lanes;
+  a.wjs = blockDim.x >> tp.log_row_lanes;
+  a.gxw = (a.ox + a.wi) & (d.g.nx - 1);
+  return a;
+}
+
+// copy nf planes of the mesh array src[f][ny][nx] into the window dst[f][WP]
+__device__ __forceinline__ void adj_load_window(double* __restrict__ dst, const double* __restrict__ src, int nf,
+                                                const AdjWin& a, const GridP& g) {
+  const size_t plane = (size_t)g.nx * g.ny;
+  if (a.wi < a.W)
+    for (int j = a.wj0; j < a.W; j += a.wjs) {
+      const size_t go = (size_t)((a.oy + j) & (g.ny - 1)) * g.nx + a.gxw;
+      const int node = j * a.W + a.wi;
+      for (int f = 0; f < nf; ++f) dst[f * a.WP + node] = src[f * plane + go];
+    }
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) k_adj_push_t(const InstDesc* __restrict__ D, StepArgs sa,
+                                                    double* __restrict__ lam) {
+  using S = Spline<double, DEG>;
+  constexpr int NW = S::NW;
+  const InstDesc& d = D[0];
+  if ((int)blockIdx.x >= *d.tb.nwork) return;
+  const int4 it = d.tb.work[blockIdx.x];
+  const GridP g = d.g;
+  const PhysP ph = d.ph;
+  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
+  const int64_t n = d.n;
+  const size_t plane = (size_t)g.nx * g.ny;
+  const AdjWin a = adj_window(d, it);
+  const int W = a.W, WP = a.WP;
+  extern __shared__ double2 sm[];
+  double* fw = reinterpret_cast<double*>(sm);  // [11][WP] mesh fields of level n+1
+  double* lw = fw + 11 * WP;                   // [11][WP] their adjoints
+  adj_load_window(fw, d.F64, 11, a, g);
+  for (int t = threadIdx.x; t < 11 * WP; t += blockDim.x) lw[t] = 0.0;
+  __syncthreads();
+  // lanes of one cell (neighbours in the cell-sorted order) scatter in a
+  // rotated node order: different window addresses at each atomic
+  const int lane = threadIdx.x & 63;
+  const int ra = lane % NW, rb = (lane / NW) % NW;
+  for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
+    const int64_t i = it.y + k;
+    const int64_t o = p.id[i];
+    const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
+    const bool inside = in_box(xi, eta, g);
+    int sx = 0, sy = 0, lx = 0, ly = 0;
+    bool inw = false;
+    double wx[NW], dwx[NW], wy[NW], dwy[NW];
+    double gv[11], gdx[11], gdy[11];
+#pragma unroll
+    for (int f = 0; f < 11; ++f) gv[f] = gdx[f] = gdy[f] = 0.0;
+    if (inside) {
+      S::eval_d(xi, sx, wx, dwx);
+      S::eval_d(eta, sy, wy, dwy);
+      lx = (sx - a.ox) & (g.nx - 1);
+      ly = (sy - a.oy) & (g.ny - 1);
+      inw = lx + DEG < W && ly + DEG < W;
+      if (inw)
+        gather_d<DEG, 11>(fw + ly * W + lx, WP, wx, dwx, wy, dwy, 0, 0, g, W, false, gv, gdx, gdy);
+      else
+        gather_d<DEG, 11>(d.F64, plane, wx, dwx, wy, dwy, sx, sy, g, 0, true, gv, gdx, gdy);
+    }
+    double lg[11];
+    adj_push_one(gv, gdx, gdy, p.P[0][i], p.P[1][i], p.P[2][i], p.v[0][i], p.v[1][i], p.v[2][i], p.w[0][i],
+                 p.w[1][i], p.w[2][i], ph, g, lam, n, o, lg);
+    if (inw) {
+      double* nd0 = lw + ly * W + lx;
+#pragma unroll
+      for (int tb = 0; tb < NW; ++tb) {
+        int bb = tb + rb;
+        bb = bb >= NW ? bb - NW : bb;
+        double vb = wy[0];
+#pragma unroll
+        for (int u = 1; u < NW; ++u) vb = bb == u ? wy[u] : vb;
+#pragma unroll
+        for (int ta = 0; ta < NW; ++ta) {
+          int aa = ta + ra;
+          aa = aa >= NW ? aa - NW : aa;
+          double va = wx[0];
+#pragma unroll
+          for (int u = 1; u < NW; ++u) va = aa == u ? wx[u] : va;
+          const double w = va * vb;
+          double* nd = nd0 + bb * W + aa;
+#pragma unroll
+          for (int f = 0; f < 11; ++f) atomicAdd(nd + f * WP, lg[f] * w);
+        }
+      }
+    } else if (inside) {
+#pragma unroll
+      for (int b = 0; b < NW; ++b) {
+        const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
+#pragma unroll
+        for (int aa = 0; aa < NW; ++aa) {
+          const size_t m = row + wrapi(sx + aa, g.nx);
+          const double w = wx[aa] * wy[b];
+#pragma unroll
+          for (int f = 0; f < 11; ++f) atomicAdd(d.LF + f * plane + m, lg[f] * w);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (a.wi < W)
+    for (int j = a.wj0; j < W; j += a.wjs) {
+      const size_t go = (size_t)((a.oy + j) & (g.ny - 1)) * g.nx + a.gxw;
+      const int node = j * W + a.wi;
+      for (int f = 0; f < 11; ++f) {
+        const double v = lw[f * WP + node];
+        if (v != 0.0) atomicAdd(d.LF + f * plane + go, v);
+      }
+    }
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) k_adj_deposit_t(const InstDesc* __restrict__ D, StepArgs sa,
+                                                       double* __restrict__ lam) {
+  using S = Spline<double, DEG>;
+  constexpr int NW = S::NW;
+  const InstDesc& d = D[0];
+  if ((int)blockIdx.x >= *d.tb.nwork) return;
+  const int4 it = d.tb.work[blockIdx.x];
+  const GridP g = d.g;
+  const PhysP ph = d.ph;
+  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
+  const int64_t n = d.n;
+  const size_t plane = (size_t)g.nx * g.ny;
+  const AdjWin a = adj_window(d, it);
+  const int W = a.W, WP = a.WP;
+  extern __shared__ double2 sm[];
+  double* jw = reinterpret_cast<double*>(sm);  // [3][WP] lambda_J
+  adj_load_window(jw, d.LJ, 3, a, g);
+  __syncthreads();
+  const double s = ph.q * g.inv_area;
+  for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
+    const int64_t i = it.y + k;
+    const int64_t o = p.id[i];
+    const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
+    double av[3] = {0, 0, 0}, bx[3] = {0, 0, 0}, by[3] = {0, 0, 0};
+    if (in_box(xi, eta, g)) {
+      int sx, sy;
+      double wx[NW], dwx[NW], wy[NW], dwy[NW];
+      S::eval_d(xi, sx, wx, dwx);
+      S::eval_d(eta, sy, wy, dwy);
+      const int lx = (sx - a.ox) & (g.nx - 1), ly = (sy - a.oy) & (g.ny - 1);
+      if (lx + DEG < W && ly + DEG < W)
+        gather_d<DEG, 3>(jw + ly * W + lx, WP, wx, dwx, wy, dwy, 0, 0, g, W, false, av, bx, by);
+      else
+        gather_d<DEG, 3>(d.LJ, plane, wx, dwx, wy, dwy, sx, sy, g, 0, true, av, bx, by);
+    }
+    const double v0 = p.v[0][i], v1 = p.v[1][i], v2 = p.v[2][i];
+    const double lx_ = lam[o] + s * (v0 * bx[0] + v1 * bx[1] + v2 * bx[2]) * g.inv_dx;
+    const double ly_ = lam[n + o] + s * (v0 * by[0] + v1 * by[1] + v2 * by[2]) * g.inv_dy;
+    lam[o] = lx_;
+    lam[n + o] = ly_;
+    lam[5 * n + o] += s * av[0] + ph.dt * lx_;
+    lam[6 * n + o] += s * av[1] + ph.dt * ly_;
+    lam[7 * n + o] += s * av[2];
   }
 }
 
@@ -407,8 +615,37 @@ hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs
   return hipGetLastError();
 }
 
+size_t adj_tiled_lds_bytes(const TileP& tp, bool push) { return (size_t)(push ? 22 : 3) * tp.win_pad * 8; }
+
+hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblocks, size_t lds, StepArgs sa,
+                            double* lam, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  const void* fn = nullptr;
+  if (push)
+    fn = degree == 1 ? (const void*)k_adj_push_t<1> : degree == 2 ? (const void*)k_adj_push_t<2>
+                                                                     : (const void*)k_adj_push_t<3>;
+  else
+    fn = degree == 1 ? (const void*)k_adj_deposit_t<1> : degree == 2 ? (const void*)k_adj_deposit_t<2>
+                                                                        : (const void*)k_adj_deposit_t<3>;
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (push) {
+    switch (degree) {
+      case 1: hipLaunchKernelGGL(k_adj_push_t<1>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
+      case 2: hipLaunchKernelGGL(k_adj_push_t<2>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
+      default: hipLaunchKernelGGL(k_adj_push_t<3>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
+    }
+  } else {
+    switch (degree) {
+      case 1: hipLaunchKernelGGL(k_adj_deposit_t<1>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
+      case 2: hipLaunchKernelGGL(k_adj_deposit_t<2>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
+      default: hipLaunchKernelGGL(k_adj_deposit_t<3>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
+    }
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_adj_columns(const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s) {
-  hipFuncSetAttribute((const void*)k_adj_columns, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)k_adj_columns, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_adj_columns, dim3(nxh), dim3(256), lds, s, D, (double2*)lam_hist);
   return hipGetLastError();
 }

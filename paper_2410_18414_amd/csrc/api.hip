@@ -1028,11 +1028,23 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
   const InstDesc* D = c->d_desc;
   const int nx = in.cfg.nx, ny = in.cfg.ny;
   const StepArgs sa = c->sargs();
-  if (!st) st = c->hip(launch_adj_push(c->degree, D, in.d.n, sa, lam, c->stream), "adjoint push");
+  // the cell-sorted passes when the forward is sorted and the windows fit in LDS
+  int max_lds = 0, dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  const size_t lds_push = adj_tiled_lds_bytes(in.d.tp, true), lds_dep = adj_tiled_lds_bytes(in.d.tp, false);
+  const bool tiled = c->sorted && lds_push <= (size_t)max_lds;
+  if (!st)
+    st = c->hip(tiled ? launch_adj_tiled(true, c->degree, D, c->nblk[BK_WORK], lds_push, sa, lam, c->stream)
+                      : launch_adj_push(c->degree, D, in.d.n, sa, lam, c->stream),
+                "adjoint push");
   if (!st) st = c->hip(launch_rows_r2c(D, 1, 11 * (ny / in.d.R_r2c), c->lds_r2c, c->stream, true), "adjoint rows_r2c");
   if (!st) st = c->hip(launch_adj_columns(D, nx / 2 + 1, c->lds_col, lam_hist, c->stream), "adjoint columns");
   if (!st) st = c->hip(launch_rows_c2r(D, 1, 2 * (ny / in.d.R_c2r), c->lds_c2r, c->stream, true), "adjoint rows_c2r");
-  if (!st) st = c->hip(launch_adj_deposit(c->degree, D, in.d.n, sa, lam, c->stream), "adjoint deposit");
+  if (!st)
+    st = c->hip(tiled ? launch_adj_tiled(false, c->degree, D, c->nblk[BK_WORK], lds_dep, sa, lam, c->stream)
+                      : launch_adj_deposit(c->degree, D, in.d.n, sa, lam, c->stream),
+                "adjoint deposit");
   c->phase = st ? EMPTY : SOLVED;
   return st;
 }

@@ -198,6 +198,11 @@ hipError_t launch_hist_transpose(const double2* src, double2* dst, int nfield, G
 // adjoint.hip (one float64 BDF-k instance; D[0])
 hipError_t launch_adj_push(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s);
 hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s);
+// cell-sorted variants over the forward's chunks (push: mesh fields and their
+// adjoints in LDS windows; deposit: lambda_J window)
+size_t adj_tiled_lds_bytes(const TileP& tp, bool push);
+hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblocks, size_t lds, StepArgs sa,
+                            double* lam, hipStream_t s);
 hipError_t launch_adj_columns(const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s);
 hipError_t launch_adj_seed_energy(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double scale,
                                   double* lam_hist, int nf, hipStream_t s);
