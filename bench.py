@@ -304,7 +304,7 @@ def main():
     traffic = measured_traffic(args.workload) if default_launch else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                kernel="k_tiled<float,3,2> (fused gather/push/position/deposit)",
+                kernel="k_tiled<float,3,2,16,3> (fused gather/push/position/deposit)",
                 avg_launch_us=round(avg_fused * 1e3, 2),
                 algorithmic_bytes_per_launch=int(alg))
     out = {
