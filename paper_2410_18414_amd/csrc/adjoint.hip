@@ -379,7 +379,8 @@ __constant__ int kAdjSym[11] = {1, 2, 0, 0, 0, 1, 1, 1, 2, 2, 2};  // 0: 1, 1: i
 
 __global__ void __launch_bounds__(256) k_adj_columns(const InstDesc* __restrict__ D, double2* __restrict__ lamH) {
   // LDS: acc [0, 4N) = lambda of phi^{n+1}, A_l^{n+1} from the mesh fields;
-  // work buffers from 4N: 2 x NB*N (forward batches), 2 x 3N (inverse)
+  // work buffers from 4N: 2 x NB*N (forward batches), 2 x 3N (inverse); then
+  // the N twiddles (ny <= 512)
   extern __shared__ double2 sm[];
   const InstDesc& d = D[0];
   const GridP g = d.g;
@@ -389,6 +390,13 @@ __global__ void __launch_bounds__(256) k_adj_columns(const InstDesc* __restrict_
   double2* __restrict__ LS = d.LS;
   double2* acc = sm;
   double2* wk = sm + 4 * N;
+  // twiddles staged in LDS where they fit (ny <= 512), else read from global
+  const double2* tws = d.twy;
+  if (N <= 512) {
+    double2* t_lds = wk + max(6, 2 * NB) * N;
+    for (int t = threadIdx.x; t < N; t += blockDim.x) t_lds[t] = d.twy[t];
+    tws = t_lds;
+  }
   const double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
   const double norm = wgt / ((double)g.nx * g.ny);
   const double kxs = kx_sym(kx, g);
@@ -400,7 +408,7 @@ __global__ void __launch_bounds__(256) k_adj_columns(const InstDesc* __restrict_
       wk[t] = LS[((size_t)(f0 + qf) * nxh + kx) * N + y];
     }
     __syncthreads();
-    const double2* res = fft_lds<false>(wk, wk + nb * N, N, nb, d.twy);
+    const double2* res = fft_lds<false>(wk, wk + nb * N, N, nb, tws);
     // each thread owns its ky entries of acc: the field loop is serial
     for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
       const double kys = ky_sym(ky, g);
@@ -460,7 +468,7 @@ __global__ void __launch_bounds__(256) k_adj_columns(const InstDesc* __restrict_
     wk[2 * N + ky] = cscale(lJz, 1.0 / wgt);
   }
   __syncthreads();
-  const double2* res = fft_lds<true>(wk, wk + 3 * N, N, 3, d.twy);
+  const double2* res = fft_lds<true>(wk, wk + 3 * N, N, 3, tws);
   for (int t = threadIdx.x; t < 3 * N; t += blockDim.x) {
     const int c = t / N, y = t - c * N;
     LS[((size_t)c * nxh + kx) * N + y] = res[t];

@@ -43,6 +43,8 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
   const int N = g.nx, B = R >> 1;
   double2* a = sm;
   double2* b = sm + B * N;
+  double2* tws = sm + R * N;  // twiddles staged in LDS
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = d.twx[t];
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     const int r = t / N, x = t - r * N;
     const size_t i0 = (size_t)(y0 + 2 * r) * N + x, i1 = i0 + N;
@@ -51,7 +53,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
     Jc[i1] = 0.0;
   }
   __syncthreads();
-  const double2* res = fft_lds<false>(a, b, N, B, d.twx);
+  const double2* res = fft_lds<false>(a, b, N, B, tws);
   // split the two real transforms: X = (Z_k + conj Z_{N-k})/2, Y = (Z_k - conj Z_{N-k})/(2i)
   for (int t = threadIdx.x; t < g.nxh * R; t += blockDim.x) {
     const int k = t / R, rr = t - k * R, r = rr >> 1;
@@ -181,7 +183,8 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
 template <int SCHEME>
 __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
   // LDS: store [0, 4N) = phi~, A0, A1, A2 (scaled); work buffers from 4N:
-  // forward 2 x 3N, inverse 2 x NB*N (NB = 8, 4 or 2 fields per batch)
+  // forward 2 x 3N, inverse 2 x NB*N (NB = 8, 4 or 2 fields per batch); then
+  // the N twiddles (ny <= 512)
   extern __shared__ double2 sm[];
   const int ii = find_inst(D, ninst, BK_COL, blockIdx.x);
   const InstDesc& d = D[ii];
@@ -195,12 +198,19 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
   const size_t plane = (size_t)g.nxh * g.ny;
   double2* store = sm;
   double2* wk = sm + 4 * N;
+  // twiddles staged in LDS where they fit (ny <= 512), else read from global
+  const double2* tws = d.twy;
+  if (N <= 512) {
+    double2* t_lds = wk + max(6, 2 * NB) * N;
+    for (int t = threadIdx.x; t < N; t += blockDim.x) t_lds[t] = d.twy[t];
+    tws = t_lds;
+  }
   for (int t = threadIdx.x; t < 3 * N; t += blockDim.x) {
     const int c = t / N, y = t - c * N;
     wk[t] = T[((size_t)c * g.nxh + kx) * N + y];
   }
   __syncthreads();
-  const double2* Jh = fft_lds<false>(wk, wk + 3 * N, N, 3, d.twy);
+  const double2* Jh = fft_lds<false>(wk, wk + 3 * N, N, 3, tws);
   const double kxs = kx_sym(kx, g);
   const double scale = 1.0 / ((double)g.nx * g.ny);
   for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
@@ -223,7 +233,7 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
       wk[t] = v;
     }
     __syncthreads();
-    const double2* res = fft_lds<true>(wk, wk + NB * N, N, NB, d.twy);
+    const double2* res = fft_lds<true>(wk, wk + NB * N, N, NB, tws);
     for (int t = threadIdx.x; t < NB * N; t += blockDim.x) {
       const int q = t / N, y = t - q * N;
       U[((size_t)(f0 + q) * g.nxh + kx) * N + y] = res[t];
@@ -259,6 +269,8 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
   const int N = g.nx, h = N >> 1;
   double2* a = sm;
   double2* b = sm + R * N;
+  double2* tws = sm + 2 * R * N;  // twiddles staged in LDS
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = d.twx[t];
   const int s0 = 2 * pr, s1 = s0 + 1;
   const int g0 = adj ? s0 : kSrcG[s0], g1 = adj ? s1 : kSrcG[s1];
   const bool has1 = !adj || s1 < 3;
@@ -277,7 +289,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
     if (k > 0 && k < h) a[r * N + N - k] = cadd(cconj(X), mul_i(cconj(Y)));
   }
   __syncthreads();
-  const double2* res = fft_lds<true>(a, b, N, R, d.twx);
+  const double2* res = fft_lds<true>(a, b, N, R, tws);
   const size_t plane = (size_t)g.nx * g.ny;
   for (int t = threadIdx.x; t < R * N; t += blockDim.x) {
     const int r = t / N, x = t - r * N;
@@ -441,13 +453,14 @@ int rows_c2r_R(int nx, int ny) {
   while (R > 1 && (R > ny || R * nx > 2048)) R >>= 1;
   return R;
 }
-size_t rows_r2c_lds_bytes(int nx, int ny) { return (size_t)rows_r2c_R(nx, ny) * nx * sizeof(double2); }
-size_t rows_c2r_lds_bytes(int nx, int ny) { return (size_t)2 * rows_c2r_R(nx, ny) * nx * sizeof(double2); }
+// work buffers plus the staged twiddles (n complex entries)
+size_t rows_r2c_lds_bytes(int nx, int ny) { return (size_t)(rows_r2c_R(nx, ny) + 1) * nx * sizeof(double2); }
+size_t rows_c2r_lds_bytes(int nx, int ny) { return (size_t)(2 * rows_c2r_R(nx, ny) + 1) * nx * sizeof(double2); }
 // inverse batch size of the column kernel and its LDS bytes (<= 160 KiB)
 int columns_nb(int ny) { return ny <= 256 ? 8 : (ny <= 512 ? 4 : 2); }
 size_t columns_lds_bytes(int ny) {
   const int nb = columns_nb(ny);
-  return (size_t)(4 + std::max(6, 2 * nb)) * ny * sizeof(double2);
+  return (size_t)(4 + std::max(6, 2 * nb) + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2);
 }
 
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {
