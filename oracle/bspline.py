@@ -20,25 +20,18 @@ SUPPORT = {0: 0.5, 1: 1.0, 2: 1.5, 3: 2.0}
 def M(m, t):
     """Centred cardinal B-spline of degree m (0..3) evaluated at t (array)."""
     a = np.abs(np.asarray(t, dtype=np.float64))
-    out = np.zeros_like(a)
     if m == 0:
-        out[a < 0.5] = 1.0
-    elif m == 1:
-        s = a < 1.0
-        out[s] = 1.0 - a[s]
-    elif m == 2:
-        s = a < 0.5
-        out[s] = 0.75 - a[s] ** 2
-        s = (a >= 0.5) & (a < 1.5)
-        out[s] = 0.5 * (1.5 - a[s]) ** 2
-    elif m == 3:
-        s = a < 1.0
-        out[s] = 2.0 / 3.0 - a[s] ** 2 + 0.5 * a[s] ** 3
-        s = (a >= 1.0) & (a < 2.0)
-        out[s] = (2.0 - a[s]) ** 3 / 6.0
-    else:
-        raise ValueError("spline degree must be 0..3")
-    return out
+        return np.where(a < 0.5, 1.0, 0.0)
+    if m == 1:
+        return np.where(a < 1.0, 1.0 - a, 0.0)
+    if m == 2:
+        b = 1.5 - a
+        return np.where(a < 0.5, 0.75 - a * a, np.where(a < 1.5, 0.5 * b * b, 0.0))
+    if m == 3:
+        b = 2.0 - a
+        return np.where(a < 1.0, 2.0 / 3.0 - a * a + 0.5 * a * a * a,
+                        np.where(a < 2.0, b * b * b / 6.0, 0.0))
+    raise ValueError("spline degree must be 0..3")
 
 
 def stencil(m, xi):

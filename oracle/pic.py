@@ -108,6 +108,54 @@ def deposit_current(p, x, y, v):
     return J.reshape(3, p.ny, p.nx)
 
 
+def current_at_nodes(p, x, y, v, nodes, batch=1 << 23):
+    """J at selected mesh nodes straight from the definition
+    J(x_g) = sum_p q v_p M(x_g/dx - x_p/dx) M(y_g/dy - y_p/dy) / (dx dy),
+    each particle taken at its periodic image nearest the node.  nodes is a
+    list of (ix, iy); returns [len(nodes), 3].  For workloads too large for
+    deposit_current's per-particle index arrays."""
+    out = np.zeros((len(nodes), 3))
+    sup = bspline.SUPPORT[p.degree]
+    for s in range(0, x.shape[0], batch):
+        xi, eta, vb = x[s:s + batch] / p.dx, y[s:s + batch] / p.dy, v[s:s + batch]
+        for k, (ix, iy) in enumerate(nodes):
+            tx = ix - xi
+            tx -= p.nx * np.round(tx / p.nx)
+            ty = iy - eta
+            ty -= p.ny * np.round(ty / p.ny)
+            sel = (np.abs(tx) < sup) & (np.abs(ty) < sup)
+            w = bspline.M(p.degree, tx[sel]) * bspline.M(p.degree, ty[sel]) / (p.dx * p.dy)
+            out[k] += p.q * (w[:, None] * vb[sel]).sum(axis=0)
+    return out
+
+
+def current_modes(p, x, y, v, modes, batch=1 << 23):
+    """rfft2 of J at selected modes (kx, ky) (numpy's unnormalised convention,
+    kx in 0..nx/2, ky in 0..ny-1), summed over particles: the DFT of one
+    particle's deposit is its weight on each stencil node times the node's
+    phase.  Returns [len(modes), 3] complex."""
+    out = np.zeros((len(modes), 3), np.complex128)
+    for s in range(0, x.shape[0], batch):
+        gx, wx = bspline.stencil(p.degree, x[s:s + batch] / p.dx)
+        gy, wy = bspline.stencil(p.degree, y[s:s + batch] / p.dy)
+        qv = p.q * v[s:s + batch] / (p.dx * p.dy)
+        offs = np.arange(gx.shape[1])  # stencil nodes are g[:, 0] + offs
+        bx = np.mod(gx[:, 0], p.nx)
+        by = np.mod(gy[:, 0], p.ny)
+        for k, (kx, ky) in enumerate(modes):
+            # sum_a w_a e^{-2 pi i kx (g0 + a)/nx}: the phase of the first node
+            # (a table over node indices) times the weights' transform
+            cx = np.exp(-2j * np.pi * kx * offs / p.nx)
+            cy = np.exp(-2j * np.pi * ky * offs / p.ny)
+            tx = np.exp(-2j * np.pi * kx * np.arange(p.nx) / p.nx)
+            ty = np.exp(-2j * np.pi * ky * np.arange(p.ny) / p.ny)
+            fx = tx[bx] * (wx @ cx.real + 1j * (wx @ cx.imag))
+            fy = ty[by] * (wy @ cy.real + 1j * (wy @ cy.imag))
+            f = fx * fy
+            out[k] += f.real @ qv + 1j * (f.imag @ qv)
+    return out
+
+
 def gather(p, fields, x, y):
     """Interpolate mesh fields [F, ny, nx] at the particles with the same spline."""
     gx, wx = bspline.stencil(p.degree, x / p.dx)

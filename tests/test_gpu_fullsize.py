@@ -1,0 +1,101 @@
+"""Full-size checks at the workload sizes the bench and the survey name.
+
+The 512 x 512, 256 particles/cell case (67,108,864 float32 particles, cubic,
+DIRK-2 and CDF-2) is too large for a full oracle step, so the oracle computes
+outputs one by one from the original inputs: J at sampled nodes (the
+definition summed over all particles) and the first update's spectral history
+at sampled modes (the direct Fourier sum of the deposit, then the per-mode
+stepper update).  After a few more steps, invariants that hold at any size:
+gauge residual at round-off, zero net charge, finite state.
+
+The 128 x 128 / 1,048,576-particle case runs through step() with HIP graph
+replay (the launch configuration bench.py times): invariants over 30 steps,
+and in float64 the graph-replayed run equals direct launches.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import pic as opic
+from paper_2410_18414_amd import pic, workloads
+from pic_harness import hist_to_flat, make_gpu, oracle_params, rel
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def big():
+    import time
+    t0 = time.time()
+    w = workloads.make(3)
+    assert len(w["x"]) == 512 * 512 * 256
+    print("generated 67M particles in %.0f s" % (time.time() - t0), flush=True)
+    p = oracle_params(w, 3, "dirk2")
+    part = opic.init_particles(p, w["x"], w["y"], w["P"])
+    x1, y1 = opic.position_update(p, part["x"], part["y"], part["v"])
+    nodes = [(0, 0), (511, 511), (256, 100), (37, 400), (510, 1), (300, 0)]
+    modes = [(0, 0), (1, 0), (3, 7), (40, 500), (256, 255)]
+    Jn = opic.current_at_nodes(p, x1, y1, part["v"], nodes)
+    print("oracle J at %d nodes after %.0f s" % (len(nodes), time.time() - t0), flush=True)
+    Jm = opic.current_modes(p, x1, y1, part["v"], modes)
+    print("oracle J^ at %d modes after %.0f s" % (len(modes), time.time() - t0), flush=True)
+    return dict(w=w, nodes=nodes, modes=modes, Jn=Jn, Jm=Jm)
+
+
+@pytest.mark.parametrize("scheme", ["dirk2", "cdf2"])
+def test_512_first_step_sampled_and_invariants(gpu_lib, big, scheme):
+    w = big["w"]
+    p = oracle_params(w, 3, scheme)
+    ctx = make_gpu(w, 3, scheme, "f32")
+    print("512x512 / 67M particles,", scheme, flush=True)
+    pic.deposit_current(ctx)
+    J = pic.get_field(ctx, pic.FIELD_J).cpu().numpy()
+    got = np.array([J[:, iy, ix] for ix, iy in big["nodes"]])
+    assert rel(got, big["Jn"]) <= 1e-4, rel(got, big["Jn"])
+    pic.field_solve(ctx)
+    # expected first update at the sampled modes: the per-mode stepper update of
+    # the sampled current spectrum (every other mode zero; the update is diagonal)
+    Jh = np.zeros((3,) + p.spec_shape, np.complex128)
+    for (kx, ky), val in zip(big["modes"], big["Jm"]):
+        Jh[:, ky, kx] = val
+    hist, _, _ = opic.field_update(p, opic.cold_history(p), Jh)
+    ref = hist_to_flat(p, hist)
+    H = pic.get_history(ctx).cpu().numpy()
+    got = np.array([H[:, ky, kx] for kx, ky in big["modes"]])
+    exp = np.array([ref[:, ky, kx] for kx, ky in big["modes"]])
+    assert rel(got, exp) <= 1e-4, rel(got, exp)
+    pic.gather_push(ctx)
+    pic.step(ctx, 3)
+    d = pic.diagnostics(ctx)
+    assert d["nonfinite"] == 0
+    assert d["gauge_l2"] <= 1e3 * EPS * d["gauge_scale"], d
+    assert abs(d["charge"]) <= 1e-9 * abs(w["q"]) * len(w["x"]), d
+    parts = pic.get_particles(ctx)
+    assert torch.isfinite(parts).all()
+    v2 = (parts[5:8] ** 2).sum(0)
+    assert float(v2.max()) < 1.0
+    ctx.close()
+
+
+def test_128_graph_replay_invariants_and_direct_equality(gpu_lib):
+    w = workloads.make(2)
+    ctx = make_gpu(w, 3, "bdf", "f32")
+    pic.step(ctx, 30)  # captured once, then replayed
+    d = pic.diagnostics(ctx)
+    assert d["nonfinite"] == 0
+    assert d["gauge_l2"] <= 1e3 * EPS * d["gauge_scale"], d
+    assert abs(d["charge"]) <= 1e-9 * abs(w["q"]) * len(w["x"]), d
+    ctx.close()
+    # float64: the replayed graph equals direct launches
+    g = make_gpu(w, 3, "bdf", "f64")
+    n = make_gpu(w, 3, "bdf", "f64", flags=pic.FLAG_NO_GRAPH)
+    pic.step(g, 30)
+    pic.step(n, 30)
+    a = pic.get_particles(g).cpu().numpy()
+    b = pic.get_particles(n).cpu().numpy()
+    for k in range(11):
+        assert rel(a[k], b[k]) <= 1e-10, k
+    assert rel(pic.get_history(g).cpu().numpy(), pic.get_history(n).cpu().numpy()) <= 1e-10

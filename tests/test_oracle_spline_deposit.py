@@ -127,3 +127,26 @@ def test_wrap_edge():
     w = pic.wrap(x, L)
     assert np.all(w >= 0) and np.all(w < L)
     np.testing.assert_allclose(w[2:], [0.5, 0.75, 0.999999999])
+
+
+def test_current_at_nodes_and_modes_match_full_deposit():
+    """The direct sums used for full-size sampled checks equal the oracle's
+    own deposit (at every sampled node) and numpy's rfft2 of it (at every
+    sampled mode), including particles near the periodic seam."""
+    from oracle import pic as opic
+    from paper_2410_18414_amd import workloads
+    for degree in (1, 2, 3):
+        w = workloads.weibel(nx=16, ny=8, ppc=6, seed=60 + degree, drift=0.1)
+        w["x"][:5] = [0.0, 1e-9, w["lx"] - 1e-9, 0.5 * w["lx"], w["lx"] * 0.999]
+        p = opic.Params(w["nx"], w["ny"], w["lx"], w["ly"], degree, "bdf", w["dt"], q=w["q"], m=w["m"])
+        part = opic.init_particles(p, w["x"], w["y"], w["P"])
+        J = opic.deposit_current(p, part["x"], part["y"], part["v"])
+        nodes = [(0, 0), (15, 7), (3, 4), (8, 0), (0, 7)]
+        got = opic.current_at_nodes(p, part["x"], part["y"], part["v"], nodes, batch=100)
+        ref = np.array([J[:, iy, ix] for ix, iy in nodes])
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(J).max()
+        modes = [(0, 0), (1, 0), (3, 5), (8, 4), (5, 7)]
+        Jh = np.fft.rfft2(J)
+        got = opic.current_modes(p, part["x"], part["y"], part["v"], modes, batch=100)
+        ref = np.array([Jh[:, ky, kx] for kx, ky in modes])
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(Jh).max()
