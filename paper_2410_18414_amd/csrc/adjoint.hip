@@ -377,6 +377,7 @@ __global__ void __launch_bounds__(256) k_adj_deposit_t(const InstDesc* __restric
 __constant__ int kAdjSrc[11] = {0, 0, 1, 2, 3, 1, 2, 3, 1, 2, 3};  // 0 phi, 1..3 A_l
 __constant__ int kAdjSym[11] = {1, 2, 0, 0, 0, 1, 1, 1, 2, 2, 2};  // 0: 1, 1: i kx, 2: i ky
 
+template <int K>  // the BDF order (static history indices)
 __global__ void __launch_bounds__(256) k_adj_columns(const InstDesc* __restrict__ D, double2* __restrict__ lamH) {
   // LDS: acc [0, 4N) = lambda of phi^{n+1}, A_l^{n+1} from the mesh fields;
   // work buffers from 4N: 2 x NB*N (forward batches), 2 x 3N (inverse); then
@@ -429,7 +430,7 @@ __global__ void __launch_bounds__(256) k_adj_columns(const InstDesc* __restrict_
   //   phi' = (rho' / (eps0 alpha^2) - sum_{i=1..2k} Cn_i Phi_{i-1}) / Lh
   //   A'_l = (mu0 J^_l / alpha^2 - sum_{i=1..2k} Cn_i A_{i-1,l}) / Lh
   //   history shift: R <- (rho', R_0 .. R_{k-2}), Phi and A likewise
-  const int k = sc.k;
+  constexpr int k = K;
   const size_t fstride = (size_t)N * nxh;
   for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
     const double kys = ky_sym(ky, g);
@@ -443,15 +444,18 @@ __global__ void __launch_bounds__(256) k_adj_columns(const InstDesc* __restrict_
     for (int l = 0; l < 3; ++l) lA[l] = cadd(Al(0, l), acc[(1 + l) * N + ky]);
     const double2 lrho = cadd(R(0), cscale(lphi, sc.inv_alpha2 / (sc.eps0 * Lh)));
     // shifts (ascending: slot j is read before it is overwritten)
+#pragma unroll
     for (int i = 1; i <= 2 * k; ++i) {
       const double2 up = i < 2 * k ? Ph(i) : make_double2(0.0, 0.0);
       Ph(i - 1) = csub(up, cscale(lphi, sc.Cn[i] / Lh));
     }
     for (int l = 0; l < 3; ++l)
+#pragma unroll
       for (int i = 1; i <= 2 * k; ++i) {
         const double2 up = i < 2 * k ? Al(i, l) : make_double2(0.0, 0.0);
         Al(i - 1, l) = csub(up, cscale(lA[l], sc.Cn[i] / Lh));
       }
+#pragma unroll
     for (int j = 1; j <= k; ++j) {
       const double2 up = j < k ? R(j) : make_double2(0.0, 0.0);
       R(j - 1) = csub(up, cscale(lrho, sc.a[j] / sc.a[0]));
@@ -652,10 +656,22 @@ hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblock
   return hipGetLastError();
 }
 
-hipError_t launch_adj_columns(const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s) {
-  (void)hipFuncSetAttribute((const void*)k_adj_columns, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_adj_columns, dim3(nxh), dim3(256), lds, s, D, (double2*)lam_hist);
+template <int K>
+static hipError_t launch_adj_columns_t(const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s) {
+  (void)hipFuncSetAttribute((const void*)k_adj_columns<K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k_adj_columns<K>, dim3(nxh), dim3(256), lds, s, D, (double2*)lam_hist);
   return hipGetLastError();
+}
+
+hipError_t launch_adj_columns(int bdf_order, const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s) {
+  switch (bdf_order) {
+    case 1: return launch_adj_columns_t<1>(D, nxh, lds, lam_hist, s);
+    case 2: return launch_adj_columns_t<2>(D, nxh, lds, lam_hist, s);
+    case 3: return launch_adj_columns_t<3>(D, nxh, lds, lam_hist, s);
+    case 4: return launch_adj_columns_t<4>(D, nxh, lds, lam_hist, s);
+    case 5: return launch_adj_columns_t<5>(D, nxh, lds, lam_hist, s);
+    default: return launch_adj_columns_t<6>(D, nxh, lds, lam_hist, s);
+  }
 }
 
 hipError_t launch_adj_seed_energy(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double scale,

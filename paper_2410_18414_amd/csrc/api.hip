@@ -449,8 +449,8 @@ pic_status_t do_solve(pic_ctx_t c) {
   const int ni = c->ninst();
   pic_status_t st = c->hip(launch_rows_r2c(c->d_desc, ni, c->nblk[BK_R2C], c->lds_r2c, c->stream), "rows_r2c");
   if (!st)
-    st = c->hip(launch_columns(c->scheme, c->d_desc, ni, c->nblk[BK_COL], c->lds_col, slots_of(c->hist, c->nupd),
-                               c->stream),
+    st = c->hip(launch_columns(c->scheme, c->inst[0].cfg.bdf_order, c->d_desc, ni, c->nblk[BK_COL], c->lds_col,
+                               slots_of(c->hist, c->nupd), c->stream),
                 "columns");
   if (!st) st = c->hip(launch_rows_c2r(c->d_desc, ni, c->nblk[BK_C2R], c->lds_c2r, c->stream), "rows_c2r");
   c->end_timed(t);
@@ -1039,7 +1039,7 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
                       : launch_adj_push(c->degree, D, in.d.n, sa, lam, c->stream),
                 "adjoint push");
   if (!st) st = c->hip(launch_rows_r2c(D, 1, 11 * (ny / in.d.R_r2c), c->lds_r2c, c->stream, true), "adjoint rows_r2c");
-  if (!st) st = c->hip(launch_adj_columns(D, nx / 2 + 1, c->lds_col, lam_hist, c->stream), "adjoint columns");
+  if (!st) st = c->hip(launch_adj_columns(in.cfg.bdf_order, D, nx / 2 + 1, c->lds_col, lam_hist, c->stream), "adjoint columns");
   if (!st) st = c->hip(launch_rows_c2r(D, 1, 2 * (ny / in.d.R_c2r), c->lds_c2r, c->stream, true), "adjoint rows_c2r");
   if (!st)
     st = c->hip(tiled ? launch_adj_tiled(false, c->degree, D, c->nblk[BK_WORK], lds_dep, sa, lam, c->stream)

@@ -78,7 +78,9 @@ struct ModeOut {
   double2 phi, A[3];
 };
 
-template <int SCHEME>
+// K: the BDF order as a compile-time constant (0 for the other steppers), so
+// that every history slot index is static and all history loads issue at once
+template <int SCHEME, int K>
 __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, double2 J0, double2 J1,
                                double2 J2, double kxs, double kys, const SchemeCoef& sc,
                                const HistSlots& hs) {
@@ -89,13 +91,15 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
   ModeOut o;
   const double2 Jn1[3] = {J0, J1, J2};
   if (SCHEME == PIC_SCHEME_BDF) {
-    const int k = sc.k;
+    constexpr int k = K;
     // continuity: sum_j a_j rho^{n+1-j} + dt div J^{n+1} = 0
     double2 acc = cscale(divv(J0, J1), sc.dt);
+#pragma unroll
     for (int j = 1; j <= k; ++j) acc = cadd(acc, cscale(at(hs.rho[j - 1]), sc.a[j]));
     const double2 rho = cscale(acc, -1.0 / sc.a[0]);
     const double Lh = 1.0 + kappa * sc.inv_alpha2;
     double2 s = cscale(rho, sc.inv_alpha2 / sc.eps0);
+#pragma unroll
     for (int i = 1; i <= 2 * k; ++i) s = csub(s, cscale(at(hs.phi[i - 1]), sc.Cn[i]));
     const double2 phi = cdivr(s, Lh);
     at(hs.rho_new) = rho;
@@ -103,6 +107,7 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
     o.phi = phi;
     for (int l = 0; l < 3; ++l) {
       double2 sa = cscale(Jn1[l], sc.mu0 * sc.inv_alpha2);
+#pragma unroll
       for (int i = 1; i <= 2 * k; ++i) sa = csub(sa, cscale(at(hs.A[i - 1] + l), sc.Cn[i]));
       const double2 A = cdivr(sa, Lh);
       at(hs.A_new + l) = A;
@@ -180,7 +185,7 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
   return o;
 }
 
-template <int SCHEME>
+template <int SCHEME, int K>
 __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
   // LDS: store [0, 4N) = phi~, A0, A1, A2 (scaled); work buffers from 4N:
   // forward 2 x 3N, inverse 2 x NB*N (NB = 8, 4 or 2 fields per batch); then
@@ -215,7 +220,7 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
   const double scale = 1.0 / ((double)g.nx * g.ny);
   for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
     const double2 J0 = Jh[ky], J1 = Jh[N + ky], J2 = Jh[2 * N + ky];
-    const ModeOut o = mode_update<SCHEME>(H, plane, (size_t)kx * N + ky, J0, J1, J2, kxs,
+    const ModeOut o = mode_update<SCHEME, K>(H, plane, (size_t)kx * N + ky, J0, J1, J2, kxs,
                                           ky_sym(ky, g), sc, hs);
     store[ky] = cscale(o.phi, scale);
     store[N + ky] = cscale(o.A[0], scale);
@@ -469,19 +474,26 @@ hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds
   return hipGetLastError();
 }
 
-hipError_t launch_columns(int scheme, const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
-                          hipStream_t s) {
-  const void* fn = scheme == PIC_SCHEME_BDF    ? (const void*)k_columns<PIC_SCHEME_BDF>
-                   : scheme == PIC_SCHEME_CDF2 ? (const void*)k_columns<PIC_SCHEME_CDF2>
-                                               : (const void*)k_columns<PIC_SCHEME_DIRK2>;
-  hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (scheme == PIC_SCHEME_BDF)
-    hipLaunchKernelGGL(k_columns<PIC_SCHEME_BDF>, dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
-  else if (scheme == PIC_SCHEME_CDF2)
-    hipLaunchKernelGGL(k_columns<PIC_SCHEME_CDF2>, dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
-  else
-    hipLaunchKernelGGL(k_columns<PIC_SCHEME_DIRK2>, dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
+template <int SCHEME, int K>
+static hipError_t launch_columns_t(const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
+                                   hipStream_t s) {
+  (void)hipFuncSetAttribute((const void*)k_columns<SCHEME, K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((k_columns<SCHEME, K>), dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
   return hipGetLastError();
+}
+
+hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int ninst, int nblocks, size_t lds,
+                          HistSlots hs, hipStream_t s) {
+  if (scheme == PIC_SCHEME_CDF2) return launch_columns_t<PIC_SCHEME_CDF2, 0>(D, ninst, nblocks, lds, hs, s);
+  if (scheme == PIC_SCHEME_DIRK2) return launch_columns_t<PIC_SCHEME_DIRK2, 0>(D, ninst, nblocks, lds, hs, s);
+  switch (bdf_order) {
+    case 1: return launch_columns_t<PIC_SCHEME_BDF, 1>(D, ninst, nblocks, lds, hs, s);
+    case 2: return launch_columns_t<PIC_SCHEME_BDF, 2>(D, ninst, nblocks, lds, hs, s);
+    case 3: return launch_columns_t<PIC_SCHEME_BDF, 3>(D, ninst, nblocks, lds, hs, s);
+    case 4: return launch_columns_t<PIC_SCHEME_BDF, 4>(D, ninst, nblocks, lds, hs, s);
+    case 5: return launch_columns_t<PIC_SCHEME_BDF, 5>(D, ninst, nblocks, lds, hs, s);
+    default: return launch_columns_t<PIC_SCHEME_BDF, 6>(D, ninst, nblocks, lds, hs, s);
+  }
 }
 
 hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {

@@ -190,8 +190,8 @@ size_t rows_c2r_lds_bytes(int nx, int ny);
 size_t columns_lds_bytes(int ny);
 // adj = true: the adjoint field solve's transforms (LF -> LS, LS -> LJ; one instance)
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false);
-hipError_t launch_columns(int scheme, const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
-                          hipStream_t s);
+hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int ninst, int nblocks, size_t lds,
+                          HistSlots hs, hipStream_t s);
 hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false);
 hipError_t launch_hist_transpose(const double2* src, double2* dst, int nfield, GridP g, bool to_external,
                                  hipStream_t s);
@@ -203,7 +203,7 @@ hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs
 size_t adj_tiled_lds_bytes(const TileP& tp, bool push);
 hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblocks, size_t lds, StepArgs sa,
                             double* lam, hipStream_t s);
-hipError_t launch_adj_columns(const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s);
+hipError_t launch_adj_columns(int bdf_order, const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s);
 hipError_t launch_adj_seed_energy(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double scale,
                                   double* lam_hist, int nf, hipStream_t s);
 hipError_t launch_adj_initial(int64_t n, const double* P, PhysP ph, double* lam, hipStream_t s);
