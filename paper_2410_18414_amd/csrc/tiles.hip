@@ -235,6 +235,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   constexpr bool GATHER = MODE != MODE_DEPOSIT;
   constexpr bool DEPOSIT = MODE != MODE_GATHER_PUSH;
   constexpr bool ROTATE = sizeof(T) == 4;  // rotated deposit order (float32 particles)
+  constexpr bool FIXEDPT = ROTATE;          // fixed-point window (float32 particles)
   constexpr bool FIXED = TS > 0;
   using G = Geo<(FIXED ? TS : 1), (FIXED ? SL : 0)>;
   using A = typename Acc<T>::type;
@@ -251,6 +252,9 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   double* __restrict__ J = d.J;
   const int W = FIXED ? G::W : tp.win;
   const int WP = FIXED ? G::WP : tp.win_pad;  // plane stride of the LDS windows (field f at f*WP)
+  // plane stride of the float64 J window: WP + 8 puts the three components of
+  // a node 16 banks apart (WP itself is a multiple of the 64-bank cycle)
+  const int JWP = WP + 8;
   const int ts = FIXED ? TS : tp.ts, slack = FIXED ? SL : tp.slack;
   const int tiy = it.x >> tp.log_ntx, tix = it.x - (tiy << tp.log_ntx);
   const int ox = tix * ts - slack - 1, oy = tiy * ts - slack - 1;
@@ -272,12 +276,30 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
     }
   }
   if (DEPOSIT)
-    for (int idx = threadIdx.x; idx < 3 * WP; idx += blockDim.x) jw[idx] = A(0);
+    for (int idx = threadIdx.x; idx < 3 * JWP; idx += blockDim.x) jw[idx] = A(0);
   __syncthreads();
 
   using S = Spline<T, DEG>;
   constexpr int NW = S::NW;
   const T dt = T(ph.dt), qs = T(ph.q) * T(g.inv_area);
+  // Float32 particles deposit in fixed point: J_x and J_y as one packed pair
+  // of int32 in a 64-bit integer atomic, J_z in a 32-bit one (two LDS atomics
+  // per node instead of three float64 ones).  The scale is a power of two
+  // chosen per chunk so that no window sum can leave int32: every
+  // contribution is bounded by |q| c max(w) / (dx dy) (|v| < c), and a node
+  // collects at most one per particle of the chunk.
+  unsigned long long* jxy_w = reinterpret_cast<unsigned long long*>(jw);     // [JWP]
+  uint32_t* jz_w = reinterpret_cast<uint32_t*>(jw + JWP);                      // [JWP]
+  float qscale = 1.0f;
+  double inv_qscale = 1.0;
+  if (FIXEDPT) {
+    const double wmax = DEG == 1 ? 1.0 : (DEG == 2 ? 0.5625 : 4.0 / 9.0);
+    const double cmax = fabs(ph.q) * ph.c * g.inv_area * wmax * (double)max(it.z, 1);
+    int e = cmax > 0 ? (int)floor(log2(1073741824.0 / cmax)) : 0;
+    e = e > 100 ? 100 : (e < -100 ? -100 : e);  // a float scale, whatever q, c and the cell area
+    qscale = (float)ldexp(1.0, e);
+    inv_qscale = ldexp(1.0, -e);
+  }
   // One particle per lane, consecutive lanes on consecutive particles.  The
   // set is sorted by cell, so the lanes of a wave mostly share one or two
   // cells: their gather reads hit the same LDS addresses (broadcasts).
@@ -392,25 +414,24 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
           coff[t] = ia;
           roff[t] = ib * W;
         }
-        T jr[3];
-        int poff[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          int ic = c + rc;
-          ic = ic >= 3 ? ic - 3 : ic;
-          jr[c] = ic == 0 ? jx : (ic == 1 ? jy : jz);
-          poff[c] = ic * WP;
-        }
+        // the node's two slots (packed x/y, then z) in a lane-rotated order
+        const int zfirst = rc & 1;
         if (inw) {
-          A* nd0 = jw + ly * W + lx;
+          const int base = ly * W + lx;
 #pragma unroll
           for (int b = 0; b < NW; ++b) {
 #pragma unroll
             for (int a = 0; a < NW; ++a) {
               const T w = wxr[a] * wyr[b];
-              A* nd = nd0 + roff[b] + coff[a];
-#pragma unroll
-              for (int c = 0; c < 3; ++c) atomicAdd(nd + poff[c], A(jr[c] * w));
+              const int node = base + roff[b] + coff[a];
+              const int ix = __float2int_rn(jx * w * qscale);
+              const int iy = __float2int_rn(jy * w * qscale);
+              const int iz = __float2int_rn(jz * w * qscale);
+              // (int64) ix + 2^32 (int64) iy, modulo 2^64
+              const uint64_t pk = (uint64_t)(int64_t)ix + ((uint64_t)(uint32_t)iy << 32);
+              if (zfirst) atomicAdd(jz_w + node, (uint32_t)iz);
+              atomicAdd(jxy_w + node, (unsigned long long)pk);
+              if (!zfirst) atomicAdd(jz_w + node, (uint32_t)iz);
             }
           }
         }
@@ -423,8 +444,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
             const T w = wx[a] * wy[b];
             A* nd = nd0 + b * W + a;
             atomicAdd(nd, A(jx * w));
-            atomicAdd(nd + WP, A(jy * w));
-            atomicAdd(nd + 2 * WP, A(jz * w));
+            atomicAdd(nd + JWP, A(jy * w));
+            atomicAdd(nd + 2 * JWP, A(jz * w));
           }
         }
       }
@@ -436,10 +457,20 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       for (int j = wj0; j < W; j += wjs) {
         const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
         const int node = j * W + wi;
+        if (FIXEDPT) {
+          const uint64_t v = jxy_w[node];
+          const int32_t X = (int32_t)(uint32_t)v;
+          const int32_t Y = (int32_t)((int64_t)(v - (uint64_t)(int64_t)X) >> 32);
+          const int32_t Z = (int32_t)jz_w[node];
+          if (X) atomicAdd(J + go, X * inv_qscale);
+          if (Y) atomicAdd(J + plane + go, Y * inv_qscale);
+          if (Z) atomicAdd(J + 2 * plane + go, Z * inv_qscale);
+        } else {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const A v = jw[c * WP + node];
-          if (v != A(0)) atomicAdd(J + c * plane + go, (double)v);
+          for (int c = 0; c < 3; ++c) {
+            const A v = jw[c * JWP + node];
+            if (v != A(0)) atomicAdd(J + c * plane + go, (double)v);
+          }
         }
       }
     }
@@ -489,7 +520,7 @@ hipError_t launch_tiled_mode(int mode, int degree, int geo, const InstDesc* D, i
 size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp) {
   const size_t es = dtype == PIC_F32 ? 4 : 8;
   return (mode != MODE_DEPOSIT ? (size_t)11 * tp.win_pad * es : 0) +
-         (mode != MODE_GATHER_PUSH ? (size_t)3 * tp.win_pad * 8 : 0);
+         (mode != MODE_GATHER_PUSH ? (size_t)3 * (tp.win_pad + 8) * 8 : 0);
 }
 size_t sort_count_lds_bytes(const TileP& tp) { return (size_t)tp.ntiles * sizeof(int32_t); }
 
