@@ -275,8 +275,12 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       for (int f = 0; f < 11; ++f) fw[f * WP + node] = F[f * plane + go];
     }
   }
-  if (DEPOSIT)
-    for (int idx = threadIdx.x; idx < 3 * JWP; idx += blockDim.x) jw[idx] = A(0);
+  if (DEPOSIT) {
+    // float64 window: 3 planes of float64; fixed-point window (float32
+    // particles): JWP 64-bit x/y pairs then JWP 32-bit z values
+    const int nzero = sizeof(T) == 4 ? (3 * JWP + 1) / 2 : 3 * JWP;
+    for (int idx = threadIdx.x; idx < nzero; idx += blockDim.x) jw[idx] = A(0);
+  }
   __syncthreads();
 
   using S = Spline<T, DEG>;
@@ -520,7 +524,7 @@ hipError_t launch_tiled_mode(int mode, int degree, int geo, const InstDesc* D, i
 size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp) {
   const size_t es = dtype == PIC_F32 ? 4 : 8;
   return (mode != MODE_DEPOSIT ? (size_t)11 * tp.win_pad * es : 0) +
-         (mode != MODE_GATHER_PUSH ? (size_t)3 * (tp.win_pad + 8) * 8 : 0);
+         (mode != MODE_GATHER_PUSH ? (size_t)(dtype == PIC_F32 ? 12 : 24) * (tp.win_pad + 8) + 8 : 0);
 }
 size_t sort_count_lds_bytes(const TileP& tp) { return (size_t)tp.ntiles * sizeof(int32_t); }
 
