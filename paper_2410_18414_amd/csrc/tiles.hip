@@ -262,17 +262,63 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   T* fw = reinterpret_cast<T*>(smem);
   A* jw = reinterpret_cast<A*>(smem + (GATHER ? (size_t)11 * WP * sizeof(T) : 0));
   const size_t plane = (size_t)g.nx * g.ny;
+  // One particle per lane, consecutive lanes on consecutive particles.  The
+  // set is sorted by cell, so the lanes of a wave mostly share one or two
+  // cells: their gather reads hit the same LDS addresses (broadcasts).
+  const int lane = threadIdx.x & 63;
+  T cx = T(0), cy = T(0), cvx = T(0), cvy = T(0), cvz = T(0), cP[3] = {T(0), T(0), T(0)},
+    cw[3] = {T(0), T(0), T(0)};
+  auto load = [&](int64_t i) {
+    cx = p.x[i];
+    cy = p.y[i];
+    cvx = p.v[0][i];
+    cvy = p.v[1][i];
+    cvz = p.v[2][i];
+    if (GATHER) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cP[c] = p.P[c][i];
+        cw[c] = p.w[c][i];
+      }
+    }
+  };
+  // the first particle's inputs are in flight while the window loads
+  if ((int)threadIdx.x < it.z) load(it.y + threadIdx.x);
   // window sweeps without integer division: lanes of a row-group cover x
   // (row_lanes >= W, a power of two), row-groups cover y
   const int rl = FIXED ? G::RL : tp.row_lanes, lrl = FIXED ? G::LRL : tp.log_row_lanes;
   const int wi = threadIdx.x & (rl - 1), wj0 = threadIdx.x >> lrl, wjs = blockDim.x >> lrl;
   const int gxw = (ox + wi) & (g.nx - 1);
   if (GATHER && wi < W) {
-    for (int j = wj0; j < W; j += wjs) {
-      const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
-      const int node = j * W + wi;
+    if (FIXED) {
+      // compile-time sweep: a thread's rows (at most NJ) and fields all load
+      // before the first LDS store
+      constexpr int NJ = (G::W + (kThreads >> G::LRL) - 1) / (kThreads >> G::LRL);
+      T v[NJ][11];
 #pragma unroll
-      for (int f = 0; f < 11; ++f) fw[f * WP + node] = F[f * plane + go];
+      for (int r = 0; r < NJ; ++r) {
+        const int j = wj0 + r * wjs;
+        if (j < W) {
+          const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
+#pragma unroll
+          for (int f = 0; f < 11; ++f) v[r][f] = F[f * plane + go];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NJ; ++r) {
+        const int j = wj0 + r * wjs;
+        if (j < W) {
+#pragma unroll
+          for (int f = 0; f < 11; ++f) fw[f * WP + j * W + wi] = v[r][f];
+        }
+      }
+    } else {
+      for (int j = wj0; j < W; j += wjs) {
+        const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
+        const int node = j * W + wi;
+#pragma unroll
+        for (int f = 0; f < 11; ++f) fw[f * WP + node] = F[f * plane + go];
+      }
     }
   }
   if (DEPOSIT) {
@@ -304,27 +350,6 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
     qscale = (float)ldexp(1.0, e);
     inv_qscale = ldexp(1.0, -e);
   }
-  // One particle per lane, consecutive lanes on consecutive particles.  The
-  // set is sorted by cell, so the lanes of a wave mostly share one or two
-  // cells: their gather reads hit the same LDS addresses (broadcasts).
-  const int lane = threadIdx.x & 63;
-  T cx = T(0), cy = T(0), cvx = T(0), cvy = T(0), cvz = T(0), cP[3] = {T(0), T(0), T(0)},
-    cw[3] = {T(0), T(0), T(0)};
-  auto load = [&](int64_t i) {
-    cx = p.x[i];
-    cy = p.y[i];
-    cvx = p.v[0][i];
-    cvy = p.v[1][i];
-    cvz = p.v[2][i];
-    if (GATHER) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        cP[c] = p.P[c][i];
-        cw[c] = p.w[c][i];
-      }
-    }
-  };
-  if ((int)threadIdx.x < it.z) load(it.y + threadIdx.x);
   for (int k0 = 0; k0 < it.z; k0 += blockDim.x) {
     const int k = k0 + threadIdx.x;
     const bool act = k < it.z;
