@@ -195,14 +195,22 @@ __global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __res
   const bool act = i < d.n;
   const void* const* S = d.set[src];
   void* const* Dd = d.set[src ^ 1];
-  const int c = act ? cell_key(((const T*)S[0])[i], ((const T*)S[1])[i], d.g, tp) : 0;
+  // the particle's record is loaded while the cursor atomics are in flight
+  T rec[11];
+  int32_t id = 0;
+  if (act) {
+#pragma unroll
+    for (int a = 0; a < 11; ++a) rec[a] = ((const T*)S[a])[i];
+    id = d.ids[src][i];
+  }
+  const int c = act ? cell_key(rec[0], rec[1], d.g, tp) : 0;
   int rr;
   const int base = wave_group_add(d.tb.ccursor, c, act, rr);
   if (act) {
     const int64_t o = base + rr;
 #pragma unroll
-    for (int a = 0; a < 11; ++a) ((T*)Dd[a])[o] = ((const T*)S[a])[i];
-    d.ids[src ^ 1][o] = d.ids[src][i];
+    for (int a = 0; a < 11; ++a) ((T*)Dd[a])[o] = rec[a];
+    d.ids[src ^ 1][o] = id;
   }
 }
 
