@@ -156,7 +156,7 @@ def bench_batched(steps, warmup):
                 ms_per_step=round(ms_b, 5), value=round(total / (ms_b * 1e-3), 1),
                 plain_ms_per_step=round(ms_p, 5), plain_value=round(total / (ms_p * 1e-3), 1),
                 speedup_vs_plain=round(ms_p / ms_b, 3),
-                tile_plan={k: plan[k] for k in ("tile_cells", "chunk", "unfused")},
+                tile_plan={k: plan[k] for k in autotune.KNOBS},
                 tile_plan_cached=bool(plan.get("cached")))
 
 

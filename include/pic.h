@@ -84,7 +84,9 @@ typedef struct {                /* [host] */
   int32_t bdf_order;            /* BDF-k order 1..6 (Sec. 3.2), used when scheme == BDF  */
   int32_t particle_dtype;       /* pic_dtype_t of particle state and gather; mesh FFT and
                                    spectral history are float64 in both cases           */
-  int32_t sort_interval;        /* steps between tile re-sorts; 0 = default (4)          */
+  int32_t sort_interval;        /* position updates between re-sorts; 0 = the worst case
+                                   slack / (c dt / min(dx, dy)), no particle leaving its
+                                   window (longer intervals stay correct)               */
   double dt;                    /* time step                                             */
   double c, eps0, mu0;          /* |c^2 eps0 mu0 - 1| <= 1e-12 required (Sec. 2.1)      */
   double q, m;                  /* macro-particle charge and mass                        */
@@ -93,7 +95,7 @@ typedef struct {                /* [host] */
   int32_t tile_cells;           /* tile edge in cells for the sorted passes (power of two,
                                    4..64, at most nx and ny); 0 = default (16)           */
   int32_t chunk;                /* particles per workgroup of the sorted passes
-                                   (64..65536); 0 = default                              */
+                                   (64..65536); 0 = default (512)                        */
   int32_t slack;                /* cells a particle may drift from its tile and still use
                                    the tile's LDS window (1..8); 0 = default (3)         */
   int32_t reserved[4];          /* must be zero                                          */

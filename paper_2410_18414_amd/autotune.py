@@ -1,8 +1,9 @@
 """Tile-plan autotuner for the cell-sorted particle passes.
 
-The tiled passes have three knobs (pic_config_t): the tile edge in cells
-(`tile_cells`), the particles per workgroup (`chunk`) and whether step()
-fuses the gather/push with the next deposit (PIC_FLAG_UNFUSED_STEP).  Their
+The tiled passes have four knobs (pic_config_t): the tile edge in cells
+(`tile_cells`), the particles per workgroup (`chunk`), the steps between
+re-sorts (`sort_interval`) and whether step() fuses the gather/push with the
+next deposit (PIC_FLAG_UNFUSED_STEP).  Their
 best values depend on the grid, the particles per cell and the particle
 precision, so they are measured: every candidate plan runs a few steps of the
 caller's own workload (warm-up steps first, so the first sort and the graph
@@ -10,7 +11,7 @@ capture stay out of the timing), timed with HIP events on the context's
 stream, and the fastest plan wins.  Results are cached in a JSON file keyed
 by the workload's shape and the device name.
 
-    plan = tune(key, make_cfgs, load, count)   # {"tile_cells", "chunk", "unfused"}
+    plan = tune(key, make_cfgs, load)   # {"tile_cells", "chunk", "unfused", "sort_interval"}
     cfgs = apply(make_cfgs(), plan)
 
 `make_cfgs()` returns the pic_config_t list of the workload (one entry for a
@@ -25,9 +26,13 @@ import torch
 
 from . import pic
 
-# candidate plans: tile edge x chunk x fused/unfused
-CANDIDATES = [dict(tile_cells=t, chunk=c, unfused=u)
-              for t in (8, 16) for c in (512, 1024, 2048) for u in (False, True)]
+# candidate plans: tile edge x chunk x fused/unfused x sort interval (0: the
+# library's worst-case interval, slack / (c dt / dx); longer intervals stay
+# correct -- particles that leave their window take the global path -- and pay
+# off when particles are slower than c)
+CANDIDATES = [dict(tile_cells=t, chunk=c, unfused=u, sort_interval=si)
+              for t in (8, 16) for c in (512, 1024, 2048) for u in (False, True) for si in (0, 12)]
+KNOBS = ("tile_cells", "chunk", "unfused", "sort_interval")
 
 
 def default_cache_path():
@@ -45,6 +50,7 @@ def apply(cfgs, plan):
         ctypes_copy(d, c)
         d.tile_cells = min(plan["tile_cells"], c.nx, c.ny)
         d.chunk = plan["chunk"]
+        d.sort_interval = plan.get("sort_interval", 0)
         d.flags = (c.flags & ~pic.FLAG_UNFUSED_STEP) | (pic.FLAG_UNFUSED_STEP if plan["unfused"] else 0)
         out.append(d)
     return out
@@ -55,7 +61,7 @@ def ctypes_copy(dst, src):
         setattr(dst, name, getattr(src, name))
 
 
-def measure(cfgs, load, steps=8, warmup=6):
+def measure(cfgs, load, steps=24, warmup=6):
     """ms per step of one plan (the context is built, loaded and dropped)."""
     ctx = pic.Context(cfgs if len(cfgs) > 1 else cfgs[0])
     try:
@@ -74,7 +80,7 @@ def measure(cfgs, load, steps=8, warmup=6):
         ctx.close()
 
 
-def tune(key, make_cfgs, load, candidates=None, steps=8, warmup=6, cache_path=None, refresh=False):
+def tune(key, make_cfgs, load, candidates=None, steps=24, warmup=6, cache_path=None, refresh=False):
     """Best plan for the workload `key` (measured once, then read from the cache)."""
     cache_path = cache_path or default_cache_path()
     dev = torch.cuda.get_device_name(torch.cuda.current_device())
@@ -93,7 +99,7 @@ def tune(key, make_cfgs, load, candidates=None, steps=8, warmup=6, cache_path=No
         ms = measure(apply(make_cfgs(), cand), load, steps=steps, warmup=warmup)
         results.append(dict(cand, ms_per_step=ms))
     best = min(results, key=lambda r: r["ms_per_step"])
-    plan = {k: best[k] for k in ("tile_cells", "chunk", "unfused")}
+    plan = {k: best[k] for k in KNOBS}
     cache[full_key] = dict(best=plan, results=results)
     try:
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)

@@ -154,7 +154,7 @@ bool compatible(const pic_config_t& a, const pic_config_t& b, std::string& msg) 
 }
 
 // Tile plan: tiles of 16x16 cells (smaller on small grids), a slack of three
-// cells, chunks of at most 1024 particles per workgroup, unless the config
+// cells, chunks of at most 512 particles per workgroup, unless the config
 // sets them.
 TileP plan_tiles(const pic_config_t& c) {
   TileP t{};
@@ -177,7 +177,7 @@ TileP plan_tiles(const pic_config_t& c) {
     t.row_lanes <<= 1;
     t.log_row_lanes += 1;
   }
-  t.chunk = c.chunk ? c.chunk : 1024;
+  t.chunk = c.chunk ? c.chunk : 512;
   t.max_work = t.ntiles + ceil_div(c.max_particles, t.chunk);
   return t;
 }

@@ -16,9 +16,9 @@ def _cfgs():
 
 def test_apply_sets_knobs_and_keeps_the_rest():
     cfgs = _cfgs()
-    out = autotune.apply(cfgs, dict(tile_cells=16, chunk=512, unfused=True))
+    out = autotune.apply(cfgs, dict(tile_cells=16, chunk=512, unfused=True, sort_interval=9))
     for a, b in zip(cfgs, out):
-        assert b.tile_cells == 16 and b.chunk == 512
+        assert b.tile_cells == 16 and b.chunk == 512 and b.sort_interval == 9
         assert b.flags & pic.FLAG_UNFUSED_STEP
         assert (b.flags & ~pic.FLAG_UNFUSED_STEP) == a.flags
         assert (b.nx, b.ny, b.lx, b.dt, b.max_particles) == (a.nx, a.ny, a.lx, a.dt, a.max_particles)
@@ -66,6 +66,5 @@ def test_tune_measures_and_caches(gpu_lib, tmp_path):
     assert not plan["cached"] and len(plan["results"]) == 3
     assert all(r["ms_per_step"] > 0 for r in plan["results"])
     again = autotune.tune("two-clouds", make_cfgs, load, candidates=cands, cache_path=path)
-    assert again["cached"] and {k: again[k] for k in ("tile_cells", "chunk", "unfused")} == \
-        {k: plan[k] for k in ("tile_cells", "chunk", "unfused")}
+    assert again["cached"] and {k: again[k] for k in autotune.KNOBS} == {k: plan[k] for k in autotune.KNOBS}
     assert len(json.load(open(path))) == 1
