@@ -135,6 +135,13 @@ pic_status_t field_solve(pic_ctx_t ctx);
 pic_status_t gather_push(pic_ctx_t ctx);
 /* READY -> READY.  nsteps >= 0 complete steps. */
 pic_status_t step(pic_ctx_t ctx, int32_t nsteps);
+/* Steps in one replayed graph period (0: step() launches every kernel
+ * itself -- PIC_FLAG_NO_GRAPH, kernel timing on, or unsorted passes).  The
+ * first step() call of more than this many steps captures and instantiates
+ * the graph, a one-time host cost; later calls replay it, after at most
+ * period - 1 directly launched steps that bring the launch state back to the
+ * captured one. */
+int32_t pic_graph_period(pic_ctx_t ctx);
 
 /* Particle state in the ORIGINAL particle order, float64 device out[11 n]:
  * blocks x, y, Px, Py, Pz, vx^n, vy^n, vz^n, vx^{n-1}, vy^{n-1}, vz^{n-1}. */

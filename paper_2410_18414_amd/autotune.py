@@ -62,12 +62,14 @@ def ctypes_copy(dst, src):
 
 
 def measure(cfgs, load, steps=24, warmup=6):
-    """ms per step of one plan (the context is built, loaded and dropped)."""
+    """ms per step of one plan (the context is built, loaded and dropped).
+    The warm-up spans at least one graph period plus a step, so the one-time
+    graph capture is not timed."""
     ctx = pic.Context(cfgs if len(cfgs) > 1 else cfgs[0])
     try:
         load(ctx)
         run = pic.step_batched if len(cfgs) > 1 else pic.step
-        run(ctx, warmup)
+        run(ctx, max(warmup, pic.graph_period(ctx) + 1))
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()

@@ -701,6 +701,15 @@ pic_status_t loop_body(pic_ctx_t c, bool unfused) {
   return particle_pass(c, 2);
 }
 
+// steps per replayed graph: the launch state (history ring slots, velocity
+// and particle-set flips, position updates since the sort) repeats after
+// lcm(ring sizes, 2 sort intervals); 0 when step() does not use graphs
+int graph_period(pic_ctx_t c) {
+  int period = 2 * c->sort_every;
+  while (period % c->lr) period += 2 * c->sort_every;
+  return period <= 256 ? period : 0;
+}
+
 void state_key(pic_ctx_t c, int64_t* k) {
   k[0] = c->nupd % c->lr;
   k[1] = c->vflip;
@@ -761,22 +770,28 @@ pic_status_t run_steps(pic_ctx_t c, int32_t nsteps) {
   int iters = nsteps - 1;
   // the host-side launch state repeats after lcm(ring sizes, 2 sort intervals)
   // iterations: replay one captured period while the state matches it
-  int period = 2 * c->sort_every;
-  while (period % c->lr) period += 2 * c->sort_every;
-  const bool graphs = c->use_graphs && !c->timing && c->sorted && period <= 256;
+  const int period = graph_period(c);
+  const bool graphs = c->use_graphs && !c->timing && c->sorted && period > 0;
   while (!st && graphs && iters >= period) {
     int64_t k[4];
     state_key(c, k);
-    const bool match = c->gexec && c->gperiod == period && k[0] == c->gkey[0] && k[1] == c->gkey[1] &&
-                       k[2] == c->gkey[2] && k[3] == c->gkey[3];
+    const bool have = c->gexec && c->gperiod == period;
+    const bool match = have && k[0] == c->gkey[0] && k[1] == c->gkey[1] && k[2] == c->gkey[2] &&
+                       k[3] == c->gkey[3];
     if (match) {
       st = c->hip(hipGraphLaunch(c->gexec, c->stream), "graph launch");
       c->nupd += period;  // vflip, cur and moves return to their values
       c->stepped = true;
+      iters -= period;
+    } else if (have) {
+      // the captured period starts at another point of the cycle: step
+      // eagerly up to it (fewer than `period` iterations) and keep the graph
+      st = loop_body(c, unfused);
+      iters -= 1;
     } else {
       st = capture_and_launch(c, unfused, period);
+      iters -= period;
     }
-    iters -= period;
   }
   for (int s = 0; s < iters && !st; ++s) st = loop_body(c, unfused);
   if (!st) st = do_solve(c);
@@ -1056,6 +1071,11 @@ pic_status_t adjoint_initial(pic_ctx_t c, const double* P0, double* lam) {
   Instance& in = c->I();
   if (in.d.n > 0 && (!P0 || !lam)) return c->fail(PIC_ERR_INVALID_ARG, "P0 and lam must be device pointers");
   return c->hip(launch_adj_initial(in.d.n, P0, in.d.ph, lam, c->stream), "adjoint initial");
+}
+
+int32_t pic_graph_period(pic_ctx_t c) {
+  if (!c || !c->use_graphs || !c->sorted || c->timing) return 0;
+  return graph_period(c);
 }
 
 pic_status_t pic_set_kernel_timing(pic_ctx_t c, int32_t enable) {

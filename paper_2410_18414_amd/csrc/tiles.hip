@@ -9,10 +9,11 @@
 // A workgroup owns a window of W x W mesh nodes around its tile: the tile's
 // TS cells, a slack of S cells on each side (particles drift after the sort),
 // and the widest stencil reach (one node below, two above the cell).  It
-// copies the eleven gathered fields of the window into LDS (one plane per
-// field), gathers from there, accumulates its J contributions in an LDS
-// window, and adds that window to the global float64 J with one atomic per
-// non-zero node component.  A particle whose stencil leaves the window (it
+// copies the eleven gathered fields of the window into LDS, node-major (the
+// node's fields in one 12-slot record, read as 16-byte vectors), gathers from
+// there, accumulates its J contributions in an LDS window, and adds that
+// window to the global float64 J with one atomic per non-zero node
+// component.  A particle whose stencil leaves the window (it
 // drifted further than S cells since the sort) takes the global-memory path
 // for that operation, so results never depend on the sort.
 //
@@ -30,6 +31,53 @@ namespace pic {
 namespace {
 
 constexpr int kThreads = 256;
+// slots per node of the LDS field window: the eleven gathered fields and one
+// pad, so that a node's record is three 16-byte (float) or six (double) vectors
+constexpr int kNodeSlots = 12;
+
+__device__ __forceinline__ void load_node(const float* p, float* q) {
+  const float4* v = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float4 t = v[i];
+    q[4 * i] = t.x;
+    q[4 * i + 1] = t.y;
+    q[4 * i + 2] = t.z;
+    q[4 * i + 3] = t.w;
+  }
+}
+__device__ __forceinline__ void load_node(const double* p, double* q) {
+  const double2* v = reinterpret_cast<const double2*>(p);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const double2 t = v[i];
+    q[2 * i] = t.x;
+    q[2 * i + 1] = t.y;
+  }
+}
+
+// v[t] <- v[(t + r) % NW] for a per-lane r in [0, NW): a barrel shifter, one
+// select per element and bit of r, with the lane masks of the bits held in
+// scalar registers (written as explicit selects: the compiler otherwise turns
+// the shifter back into per-element compare chains)
+__device__ __forceinline__ float select_lanes(float a, float b, uint64_t lanes) {
+  float r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(lanes));
+  return r;
+}
+template <int NW>
+__device__ __forceinline__ void rotate_lanes(float (&v)[NW], int r) {
+#pragma unroll
+  for (int s = 1; s < NW; s <<= 1) {
+    const uint64_t lanes = __ballot((r & s) != 0);
+    float u[NW];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) u[t] = select_lanes(v[t], v[(t + s) % NW], lanes);
+#pragma unroll
+    for (int t = 0; t < NW; ++t) v[t] = u[t];
+  }
+}
+
 
 // cell key of a position (cells floor(xi), clamped into the grid), numbered
 // tile-major: tile * ts^2 + (row in tile) * ts + (column in tile)
@@ -268,7 +316,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   const int ox = tix * ts - slack - 1, oy = tiy * ts - slack - 1;
   extern __shared__ __align__(16) unsigned char smem[];
   T* fw = reinterpret_cast<T*>(smem);
-  A* jw = reinterpret_cast<A*>(smem + (GATHER ? (size_t)11 * WP * sizeof(T) : 0));
+  A* jw = reinterpret_cast<A*>(smem + (GATHER ? (size_t)kNodeSlots * WP * sizeof(T) : 0));
   const size_t plane = (size_t)g.nx * g.ny;
   // One particle per lane, consecutive lanes on consecutive particles.  The
   // set is sorted by cell, so the lanes of a wave mostly share one or two
@@ -317,7 +365,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         const int j = wj0 + r * wjs;
         if (j < W) {
 #pragma unroll
-          for (int f = 0; f < 11; ++f) fw[f * WP + j * W + wi] = v[r][f];
+          for (int f = 0; f < 11; ++f) fw[(j * W + wi) * kNodeSlots + f] = v[r][f];
         }
       }
     } else {
@@ -325,7 +373,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
         const int node = j * W + wi;
 #pragma unroll
-        for (int f = 0; f < 11; ++f) fw[f * WP + node] = F[f * plane + go];
+        for (int f = 0; f < 11; ++f) fw[node * kNodeSlots + f] = F[f * plane + go];
       }
     }
   }
@@ -377,15 +425,16 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         S::eval(eta, sy, wy);
         const int lx = (sx - ox) & (g.nx - 1), ly = (sy - oy) & (g.ny - 1);
         if (lx + DEG < W && ly + DEG < W) {
-          const T* nd0 = fw + ly * W + lx;
+          const T* nd0 = fw + (ly * W + lx) * kNodeSlots;
 #pragma unroll
           for (int b = 0; b < NW; ++b) {
 #pragma unroll
             for (int a = 0; a < NW; ++a) {
               const T w = wx[a] * wy[b];
-              const T* nd = nd0 + b * W + a;
+              T q[kNodeSlots];
+              load_node(nd0 + (b * W + a) * kNodeSlots, q);
 #pragma unroll
-              for (int f = 0; f < 11; ++f) gv[f] += w * nd[f * WP];
+              for (int f = 0; f < 11; ++f) gv[f] += w * q[f];
             }
           }
         } else {
@@ -428,47 +477,49 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
           if (!inw) deposit_global<T, DEG>(sx, sy, wx, wy, jx, jy, jz, J, g);
         }
       }
-      if (ROTATE) {
-        // per-lane rotation of stencil columns, rows and components: lanes
-        // of one cell (neighbours in the cell-sorted order) add to different
-        // window addresses at each instruction
-        const int ra = lane % NW, rb = (lane / NW) % NW, rc = (lane / (NW * NW)) % 3;
+      if constexpr (ROTATE) {
+        // per-lane rotation of stencil columns and rows: lanes of one cell
+        // (neighbours in the cell-sorted order) add to different window
+        // addresses at each instruction
+        const int ra = lane % NW, rb = (lane / NW) % NW;
         T wxr[NW], wyr[NW];
-        int coff[NW], roff[NW];
+        int roff[NW], cxy[NW], cz[NW];  // rotated row offsets (nodes), column offsets (bytes)
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
           int ia = t + ra, ib = t + rb;
           ia = ia >= NW ? ia - NW : ia;
           ib = ib >= NW ? ib - NW : ib;
-          T va = wx[0], vb = wy[0];
-#pragma unroll
-          for (int u = 1; u < NW; ++u) {
-            va = ia == u ? wx[u] : va;
-            vb = ib == u ? wy[u] : vb;
-          }
-          wxr[t] = va;
-          wyr[t] = vb;
-          coff[t] = ia;
+          wxr[t] = wx[t];
+          wyr[t] = wy[t];
           roff[t] = ib * W;
+          cxy[t] = ia * (int)sizeof(unsigned long long);
+          cz[t] = ia * (int)sizeof(uint32_t);
         }
-        // the node's two slots (packed x/y, then z) in a lane-rotated order
-        const int zfirst = rc & 1;
+        rotate_lanes<NW>(wxr, ra);
+        rotate_lanes<NW>(wyr, rb);
+        // one packed x/y atomic and one z atomic per node, the same order in
+        // every lane (a lane-dependent slot order splits the wave into two
+        // halves that each issue both atomics)
+        const T sjx = jx * qscale, sjy = jy * qscale, sjz = jz * qscale;
         if (inw) {
           const int base = ly * W + lx;
 #pragma unroll
           for (int b = 0; b < NW; ++b) {
+            unsigned char* xy_row = reinterpret_cast<unsigned char*>(jxy_w + base + roff[b]);
+            unsigned char* z_row = reinterpret_cast<unsigned char*>(jz_w + base + roff[b]);
 #pragma unroll
             for (int a = 0; a < NW; ++a) {
               const T w = wxr[a] * wyr[b];
-              const int node = base + roff[b] + coff[a];
-              const int ix = __float2int_rn(jx * w * qscale);
-              const int iy = __float2int_rn(jy * w * qscale);
-              const int iz = __float2int_rn(jz * w * qscale);
+              // round to nearest even: unbiased at the exact halves that
+              // scaled float32 products often are (rounding halves up would
+              // shift the mean current)
+              const int ix = __float2int_rn(sjx * w);
+              const int iy = __float2int_rn(sjy * w);
+              const int iz = __float2int_rn(sjz * w);
               // (int64) ix + 2^32 (int64) iy, modulo 2^64
               const uint64_t pk = (uint64_t)(int64_t)ix + ((uint64_t)(uint32_t)iy << 32);
-              if (zfirst) atomicAdd(jz_w + node, (uint32_t)iz);
-              atomicAdd(jxy_w + node, (unsigned long long)pk);
-              if (!zfirst) atomicAdd(jz_w + node, (uint32_t)iz);
+              atomicAdd(reinterpret_cast<unsigned long long*>(xy_row + cxy[a]), (unsigned long long)pk);
+              atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a]), (uint32_t)iz);
             }
           }
         }
@@ -556,7 +607,7 @@ hipError_t launch_tiled_mode(int mode, int degree, int geo, const InstDesc* D, i
 
 size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp) {
   const size_t es = dtype == PIC_F32 ? 4 : 8;
-  return (mode != MODE_DEPOSIT ? (size_t)11 * tp.win_pad * es : 0) +
+  return (mode != MODE_DEPOSIT ? (size_t)kNodeSlots * tp.win_pad * es : 0) +
          (mode != MODE_GATHER_PUSH ? (size_t)(dtype == PIC_F32 ? 12 : 24) * (tp.win_pad + 8) + 8 : 0);
 }
 size_t sort_count_lds_bytes(const TileP& tp) { return (size_t)tp.ntiles * sizeof(int32_t); }

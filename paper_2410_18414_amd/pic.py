@@ -39,7 +39,7 @@ EXPORTS = ("pic_workspace_bytes", "pic_create", "pic_destroy", "pic_last_error",
            "pic_get_history", "pic_set_history", "pic_diagnostics", "pic_set_kernel_timing",
            "pic_kernel_timing", "pic_batch_workspace_bytes", "pic_batch_create",
            "pic_instance_count", "pic_select_instance", "step_batched", "adjoint_seed_energy",
-           "step_adjoint", "adjoint_initial")
+           "step_adjoint", "adjoint_initial", "pic_graph_period")
 KCLASSES = ("deposit", "field_solve", "gather_push", "fused", "sort")
 
 
@@ -97,6 +97,7 @@ def load():
         "pic_batch_workspace_bytes": (SZ, [cfgp, I32]),
         "pic_batch_create": (I32, [cfgp, I32, P, SZ, P, ctypes.POINTER(P)]),
         "pic_instance_count": (I32, [P]),
+        "pic_graph_period": (I32, [P]),
         "pic_select_instance": (I32, [P, I32]),
         "step_batched": (I32, [P, I32]),
         "adjoint_seed_energy": (I32, [P, D, P]),
@@ -248,6 +249,12 @@ def select_instance(ctx, index):
 
 def instance_count(ctx):
     return load().pic_instance_count(ctx.handle)
+
+
+def graph_period(ctx):
+    """Steps per replayed graph period (0: no graph replay); the first step()
+    call of more steps than this captures the graph."""
+    return load().pic_graph_period(ctx.handle)
 
 
 def step_batched(ctx, nsteps=1):

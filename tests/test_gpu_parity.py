@@ -274,7 +274,11 @@ def test_graph_replay_matches_oracle_and_direct(gpu_lib, scheme, k):
     o = make_oracle(w, 2, scheme, k)
     g = make_gpu(w, 2, scheme, "f64", bdf_order=k)
     d = make_gpu(w, 2, scheme, "f64", bdf_order=k, flags=pic.FLAG_NO_GRAPH)
-    for n in (40, 7, 25):   # uneven call lengths: capture, replay, remainder
+    assert pic.graph_period(g) > 0 and pic.graph_period(d) == 0
+    # uneven call lengths: capture, replay, remainders, and calls that start
+    # at another phase of the captured period (direct steps up to it, then
+    # replays)
+    for n in (40, 7, 25, 31, 3, 19):
         o.step(n)
         pic.step(g, n)
         pic.step(d, n)
