@@ -303,7 +303,7 @@ struct pic_ctx_s {
   InstDesc* d_desc = nullptr;
   double* d_diag = nullptr;
   int nblk[BK_NKINDS] = {0};
-  size_t lds_r2c = 0, lds_c2r = 0, lds_col = 0, lds_tiled[3] = {0, 0, 0}, lds_count = 0;
+  size_t lds_r2c = 0, lds_c2r = 0, lds_col = 0, lds_adj_col = 0, lds_tiled[3] = {0, 0, 0}, lds_count = 0;
   int dtype = 0, degree = 3, scheme = 0;
   int geo = 0;  // compiled window geometry shared by every instance (0: none, runtime geometry)
   bool sorted = true;
@@ -321,6 +321,11 @@ struct pic_ctx_s {
   bool use_graphs = true;
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // second stream for the tile sort, which runs beside the field solve (the
+  // sort reads and writes particle sets, the solve mesh arrays), with the
+  // fork and join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int gperiod = 0;
   int64_t gkey[4] = {-1, -1, -1, -1};
   int lr = 1;  // lcm of the history ring sizes
@@ -339,6 +344,9 @@ struct pic_ctx_s {
   ~pic_ctx_s() {
     if (gexec) hipGraphExecDestroy(gexec);
     if (cap_stream) hipStreamDestroy(cap_stream);
+    if (side) hipStreamDestroy(side);
+    if (ev_fork) hipEventDestroy(ev_fork);
+    if (ev_join) hipEventDestroy(ev_join);
     for (auto& e : ev) {
       if (e.a) hipEventDestroy(e.a);
       if (e.b) hipEventDestroy(e.b);
@@ -599,7 +607,8 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.R_c2r = rows_c2r_R(cf.nx, cf.ny);
     d.nb_col = columns_nb(cf.ny);
     // flattened block ranges
-    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * 3, cf.nx / 2 + 1, cf.ny / d.R_c2r * 6, d.tp.max_work,
+    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * 3, (cf.nx / 2 + 1) * columns_parts(cf.scheme),
+                               cf.ny / d.R_c2r * 6, d.tp.max_work,
                                ceil_div(cf.max_particles, 256), ceil_div(cf.max_particles, 1024),
                                ceil_div(d.tp.ntiles, 4)};
     for (int k = 0; k < BK_NKINDS; ++k) {
@@ -608,7 +617,9 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     }
     c->lds_r2c = std::max(c->lds_r2c, rows_r2c_lds_bytes(cf.nx, cf.ny));
     c->lds_c2r = std::max(c->lds_c2r, rows_c2r_lds_bytes(cf.nx, cf.ny));
-    c->lds_col = std::max(c->lds_col, columns_lds_bytes(cf.ny));
+    c->lds_col = std::max(c->lds_col, columns_parts(cf.scheme) > 1 ? columns_split_lds_bytes(cf.ny)
+                                                                    : columns_lds_bytes(cf.ny));
+    if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, columns_lds_bytes(cf.ny));
     for (int mode = 0; mode < 3; ++mode)
       c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp));
     c->lds_count = std::max(c->lds_count, sort_count_lds_bytes(d.tp));
@@ -637,7 +648,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     delete c;
     return PIC_ERR_HIP;
   }
-  const size_t lds_need = std::max({c->lds_col, c->lds_r2c, c->lds_c2r, c->lds_tiled[0], c->lds_tiled[1],
+  const size_t lds_need = std::max({c->lds_col, c->lds_adj_col, c->lds_r2c, c->lds_c2r, c->lds_tiled[0], c->lds_tiled[1],
                                     c->lds_tiled[2], c->lds_count});
   if (lds_need > (size_t)max_lds) {
     g_err = "grid or tile too large for this device's LDS";
@@ -646,6 +657,9 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
   }
   pic_status_t st = c->upload_desc();
   for (int i = 0; i < ninst && !st; ++i) st = reset_fields(c, c->inst[i]);
+  if (!st) st = c->hip(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "sort stream");
+  if (!st) st = c->hip(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "sort fork event");
+  if (!st) st = c->hip(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "sort join event");
   if (st) {
     g_err = c->err;
     delete c;
@@ -689,8 +703,26 @@ pic_status_t history_io(pic_ctx_t c, double* ext, bool to_external) {
 }
 
 // one loop iteration of a multi-step call: field solve, then the gather/push
-// of this step fused with the next step's position update and deposit
+// of this step fused with the next step's position update and deposit.  A
+// sort due before the fused pass runs on the second stream beside the solve
+// (direct launches and captured graphs alike; not while kernel timing is on,
+// so that the timed classes do not overlap).
 pic_status_t loop_body(pic_ctx_t c, bool unfused) {
+  if (!unfused && !c->timing && c->sorted && c->moves >= c->sort_every) {
+    hipStream_t main = c->stream;
+    pic_status_t st = c->hip(hipEventRecord(c->ev_fork, main), "sort fork");
+    if (!st) st = c->hip(hipStreamWaitEvent(c->side, c->ev_fork, 0), "sort fork wait");
+    if (!st) {
+      c->stream = c->side;
+      st = do_sort(c);
+      c->stream = main;
+    }
+    if (!st) st = c->hip(hipEventRecord(c->ev_join, c->side), "sort join");
+    if (!st) st = do_solve(c);
+    if (!st) st = c->hip(hipStreamWaitEvent(main, c->ev_join, 0), "sort join wait");
+    if (!st) st = particle_pass(c, 2);
+    return st;
+  }
   pic_status_t st = do_solve(c);
   if (st) return st;
   if (unfused) {
@@ -1054,7 +1086,7 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
                       : launch_adj_push(c->degree, D, in.d.n, sa, lam, c->stream),
                 "adjoint push");
   if (!st) st = c->hip(launch_rows_r2c(D, 1, 11 * (ny / in.d.R_r2c), c->lds_r2c, c->stream, true), "adjoint rows_r2c");
-  if (!st) st = c->hip(launch_adj_columns(in.cfg.bdf_order, D, nx / 2 + 1, c->lds_col, lam_hist, c->stream), "adjoint columns");
+  if (!st) st = c->hip(launch_adj_columns(in.cfg.bdf_order, D, nx / 2 + 1, c->lds_adj_col, lam_hist, c->stream), "adjoint columns");
   if (!st) st = c->hip(launch_rows_c2r(D, 1, 2 * (ny / in.d.R_c2r), c->lds_c2r, c->stream, true), "adjoint rows_c2r");
   if (!st)
     st = c->hip(tiled ? launch_adj_tiled(false, c->degree, D, c->nblk[BK_WORK], lds_dep, sa, lam, c->stream)

@@ -248,6 +248,141 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
 }
 
 // ---------------------------------------------------------------------------
+// columns split by output (BDF-k and CDF-2): four blocks per kx.  Part 0
+// updates rho and phi from the forward y-FFTs of J_x and J_y (the
+// divergence); part 1 + l updates A_l from the forward y-FFT of J_l.  Each
+// part inverse-transforms its two outputs (phi~ and d_y phi~, or A_l and
+// d_y A_l).  The history terms of the update do not depend on J^{n+1}: they
+// are loaded and summed before the forward transform, so their loads overlap
+// it.  (DIRK-2 keeps the one-block-per-kx kernel: its single J history slot
+// is read by every component's update and overwritten by each.)
+constexpr int kColParts = 4;
+constexpr int kColMaxModes = 4;  // modes per thread: ny <= 1024 with 256 threads
+
+template <int SCHEME, int K>
+__global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
+  // LDS: [0, N) the scaled output column; [N, 5N) work (two ping-pong pairs
+  // of two columns); then the N twiddles (ny <= 512)
+  extern __shared__ double2 sm[];
+  const int ii = find_inst(D, ninst, BK_COL, blockIdx.x);
+  const InstDesc& d = D[ii];
+  const GridP g = d.g;
+  const SchemeCoef sc = d.sc;
+  const int lb = blockIdx.x - d.blk[BK_COL];
+  const int kx = lb / kColParts, part = lb - kx * kColParts;
+  const int N = g.ny, tid = threadIdx.x, nth = blockDim.x;
+  const double2* __restrict__ T = d.T;
+  double2* __restrict__ H = d.H;
+  double2* __restrict__ U = d.U;
+  const size_t plane = (size_t)g.nxh * N;
+  double2* store = sm;
+  double2* wk = sm + N;
+  const double2* tws = d.twy;
+  if (N <= 512) {
+    double2* t_lds = sm + 5 * N;
+    for (int i = tid; i < N; i += nth) t_lds[i] = d.twy[i];
+    tws = t_lds;
+  }
+  const int ncol = part == 0 ? 2 : 1;
+  const int c0 = part == 0 ? 0 : part - 1;  // first J component transformed
+  for (int i = tid; i < ncol * N; i += nth) {
+    const int c = i / N, y = i - c * N;
+    wk[i] = T[((size_t)(c0 + c) * g.nxh + kx) * N + y];
+  }
+  // history terms of this thread's modes ky = tid + m * nth
+  auto at = [&](int slot, int ky) -> double2& { return H[(size_t)slot * plane + (size_t)kx * N + ky]; };
+  double2 h0[kColMaxModes], h1[kColMaxModes], h2[kColMaxModes], h3[kColMaxModes];
+#pragma unroll
+  for (int m = 0; m < kColMaxModes; ++m) {
+    const int ky = tid + m * nth;
+    h0[m] = h1[m] = h2[m] = h3[m] = make_double2(0.0, 0.0);
+    if (ky >= N) continue;
+    if (SCHEME == PIC_SCHEME_BDF) {
+      if (part == 0) {
+        // sum_j a_j rho^{n+1-j} and sum_i C_i phi^{n+1-i}
+#pragma unroll
+        for (int j = 1; j <= K; ++j) h0[m] = cadd(h0[m], cscale(at(hs.rho[j - 1], ky), sc.a[j]));
+#pragma unroll
+        for (int i = 1; i <= 2 * K; ++i) h1[m] = cadd(h1[m], cscale(at(hs.phi[i - 1], ky), sc.Cn[i]));
+      } else {
+#pragma unroll
+        for (int i = 1; i <= 2 * K; ++i) h0[m] = cadd(h0[m], cscale(at(hs.A[i - 1] + c0, ky), sc.Cn[i]));
+      }
+    } else {  // CDF-2
+      if (part == 0) {
+        h0[m] = at(hs.rho[0], ky);
+        h1[m] = at(hs.rho[1], ky);
+        h2[m] = at(hs.phi[0], ky);
+        h3[m] = at(hs.phi[1], ky);
+      } else {
+        h0[m] = at(hs.A[0] + c0, ky);
+        h1[m] = at(hs.A[1] + c0, ky);
+        h2[m] = at(hs.J[1] + c0, ky);
+      }
+    }
+  }
+  __syncthreads();
+  const double2* Jh = fft_lds<false>(wk, wk + 2 * N, N, ncol, tws);
+  const double kxs = kx_sym(kx, g);
+  const double scale = 1.0 / ((double)g.nx * g.ny);
+#pragma unroll
+  for (int m = 0; m < kColMaxModes; ++m) {
+    const int ky = tid + m * nth;
+    if (ky >= N) continue;
+    const double kys = ky_sym(ky, g);
+    const double Lh = 1.0 + (kxs * kxs + kys * kys) * sc.inv_alpha2;
+    double2 out;
+    if (part == 0) {
+      const double2 J0 = Jh[ky], J1 = Jh[N + ky];
+      const double2 divJ = mul_i(make_double2(kxs * J0.x + kys * J1.x, kxs * J0.y + kys * J1.y));  // i k . J
+      if (SCHEME == PIC_SCHEME_BDF) {
+        // continuity: sum_j a_j rho^{n+1-j} + dt div J^{n+1} = 0
+        const double2 rho = cscale(cadd(cscale(divJ, sc.dt), h0[m]), -1.0 / sc.a[0]);
+        const double2 phi = cdivr(csub(cscale(rho, sc.inv_alpha2 / sc.eps0), h1[m]), Lh);
+        at(hs.rho_new, ky) = rho;
+        at(hs.phi_new, ky) = phi;
+        out = phi;
+      } else {
+        const double2 rho = csub(h0[m], cscale(divJ, sc.dt));  // rho^{n+3/2}
+        const double2 rhs = cadd(cscale(h2[m], 2.0), cscale(cadd(rho, h1[m]), sc.inv_alpha2 / sc.eps0));
+        const double2 phi = csub(cdivr(rhs, Lh), h3[m]);
+        at(hs.rho_new, ky) = rho;
+        at(hs.phi_new, ky) = phi;
+        out = cscale(cadd(phi, h2[m]), 0.5);
+      }
+    } else {
+      const double2 Jl = Jh[ky];
+      if (SCHEME == PIC_SCHEME_BDF) {
+        const double2 A = cdivr(csub(cscale(Jl, sc.mu0 * sc.inv_alpha2), h0[m]), Lh);
+        at(hs.A_new + c0, ky) = A;
+        out = A;
+      } else {
+        const double2 r = cadd(cscale(h0[m], 2.0), cscale(cadd(Jl, h2[m]), sc.mu0 * sc.inv_alpha2));
+        const double2 A = csub(cdivr(r, Lh), h1[m]);
+        at(hs.A_new + c0, ky) = A;
+        at(hs.J_new + c0, ky) = Jl;
+        out = A;
+      }
+    }
+    store[ky] = cscale(out, scale);
+  }
+  __syncthreads();
+  // outputs: the field and its y derivative (G0, G1 or G(2+l), G(5+l))
+  for (int i = tid; i < 2 * N; i += nth) {
+    const int q = i / N, ky = i - q * N;
+    const double2 v = store[ky];
+    wk[i] = q ? mul_i(cscale(v, ky_sym(ky, g))) : v;
+  }
+  __syncthreads();
+  const double2* res = fft_lds<true>(wk, wk + 2 * N, N, 2, tws);
+  const int g0 = part == 0 ? 0 : 2 + c0, g1 = part == 0 ? 1 : 5 + c0;
+  for (int i = tid; i < 2 * N; i += nth) {
+    const int q = i / N, y = i - q * N;
+    U[((size_t)(q ? g1 : g0) * g.nxh + kx) * N + y] = res[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // rows C2R: R rows of one output pair (two real fields from one complex FFT).
 // Pair p of the 12 mesh fields and the U column (and whether it is multiplied
 // by i kx) each is made from:
@@ -448,14 +583,19 @@ void fft_make_twiddles(int n, double* h) {
   }
 }
 
+// rows per block of the row kernels: at most 8, within the LDS budget, and
+// small enough that one instance's transform has 256 blocks or more (the row
+// kernels are latency-bound: more, shorter blocks finish sooner)
 int rows_r2c_R(int nx, int ny) {
   int R = 8;
   while (R > 2 && (R > ny || R * nx > 4096)) R >>= 1;
+  while (R > 2 && 3 * (ny / R) < 256) R >>= 1;
   return R;
 }
 int rows_c2r_R(int nx, int ny) {
   int R = 8;
   while (R > 1 && (R > ny || R * nx > 2048)) R >>= 1;
+  while (R > 2 && 6 * (ny / R) < 256) R >>= 1;
   return R;
 }
 // work buffers plus the staged twiddles (n complex entries)
@@ -482,17 +622,29 @@ static hipError_t launch_columns_t(const InstDesc* D, int ninst, int nblocks, si
   return hipGetLastError();
 }
 
+template <int SCHEME, int K>
+static hipError_t launch_columns_split_t(const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
+                                         hipStream_t s) {
+  (void)hipFuncSetAttribute((const void*)k_columns_split<SCHEME, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL((k_columns_split<SCHEME, K>), dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
+  return hipGetLastError();
+}
+
+int columns_parts(int scheme) { return scheme == PIC_SCHEME_DIRK2 ? 1 : kColParts; }
+size_t columns_split_lds_bytes(int ny) { return (size_t)(5 + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2); }
+
 hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int ninst, int nblocks, size_t lds,
                           HistSlots hs, hipStream_t s) {
-  if (scheme == PIC_SCHEME_CDF2) return launch_columns_t<PIC_SCHEME_CDF2, 0>(D, ninst, nblocks, lds, hs, s);
+  if (scheme == PIC_SCHEME_CDF2) return launch_columns_split_t<PIC_SCHEME_CDF2, 0>(D, ninst, nblocks, lds, hs, s);
   if (scheme == PIC_SCHEME_DIRK2) return launch_columns_t<PIC_SCHEME_DIRK2, 0>(D, ninst, nblocks, lds, hs, s);
   switch (bdf_order) {
-    case 1: return launch_columns_t<PIC_SCHEME_BDF, 1>(D, ninst, nblocks, lds, hs, s);
-    case 2: return launch_columns_t<PIC_SCHEME_BDF, 2>(D, ninst, nblocks, lds, hs, s);
-    case 3: return launch_columns_t<PIC_SCHEME_BDF, 3>(D, ninst, nblocks, lds, hs, s);
-    case 4: return launch_columns_t<PIC_SCHEME_BDF, 4>(D, ninst, nblocks, lds, hs, s);
-    case 5: return launch_columns_t<PIC_SCHEME_BDF, 5>(D, ninst, nblocks, lds, hs, s);
-    default: return launch_columns_t<PIC_SCHEME_BDF, 6>(D, ninst, nblocks, lds, hs, s);
+    case 1: return launch_columns_split_t<PIC_SCHEME_BDF, 1>(D, ninst, nblocks, lds, hs, s);
+    case 2: return launch_columns_split_t<PIC_SCHEME_BDF, 2>(D, ninst, nblocks, lds, hs, s);
+    case 3: return launch_columns_split_t<PIC_SCHEME_BDF, 3>(D, ninst, nblocks, lds, hs, s);
+    case 4: return launch_columns_split_t<PIC_SCHEME_BDF, 4>(D, ninst, nblocks, lds, hs, s);
+    case 5: return launch_columns_split_t<PIC_SCHEME_BDF, 5>(D, ninst, nblocks, lds, hs, s);
+    default: return launch_columns_split_t<PIC_SCHEME_BDF, 6>(D, ninst, nblocks, lds, hs, s);
   }
 }
 

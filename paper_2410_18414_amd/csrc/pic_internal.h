@@ -89,7 +89,7 @@ struct SchemeCoef {
 // block ranges of the flattened kernels
 enum BlockKind {
   BK_R2C = 0,    // (ny/R_r2c) x 3 blocks
-  BK_COL = 1,    // nxh blocks
+  BK_COL = 1,    // nxh x columns_parts(scheme) blocks
   BK_C2R = 2,    // (ny/R_c2r) x 6 blocks
   BK_WORK = 3,   // tp.max_work blocks (tiled particle pass)
   BK_PART = 4,   // ceil(capacity/256) blocks (untiled passes, scatter)
@@ -188,6 +188,10 @@ int columns_nb(int ny);
 size_t rows_r2c_lds_bytes(int nx, int ny);
 size_t rows_c2r_lds_bytes(int nx, int ny);
 size_t columns_lds_bytes(int ny);
+// blocks per kx of the forward column kernel (4 for BDF-k and CDF-2, split
+// by output; 1 for DIRK-2) and the split kernel's LDS bytes
+int columns_parts(int scheme);
+size_t columns_split_lds_bytes(int ny);
 // adj = true: the adjoint field solve's transforms (LF -> LS, LS -> LJ; one instance)
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false);
 hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int ninst, int nblocks, size_t lds,
