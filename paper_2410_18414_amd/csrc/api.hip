@@ -184,7 +184,8 @@ TileP plan_tiles(const pic_config_t& c) {
 
 struct Layout {
   size_t set_bytes;  // one particle set: 11 arrays (cap x es) + ids
-  size_t parts, J, T, H, U, F64, F32, twx, twy, tcount, tstart, ccount, ccursor, twork, tnwork, LF, LS, LJ, total;
+  size_t parts, J, T, H, U, F64, F32, twx, twy, tcount, tstart, ccount, ccursor, twork, tnwork, tdone, LF, LS, LJ,
+      total;
   size_t plane_c;    // complex entries per spectral plane
 };
 
@@ -219,6 +220,7 @@ Layout plan_instance(const pic_config_t& c) {
   L.ccursor = take(plane_r * 4);
   L.twork = take((size_t)tp.max_work * 16);
   L.tnwork = take(4);
+  L.tdone = take(4);
   if (c.flags & PIC_FLAG_ADJOINT) {
     L.LF = take(11 * plane_r * 8);
     L.LS = take(11 * L.plane_c * 16);
@@ -303,7 +305,7 @@ struct pic_ctx_s {
   InstDesc* d_desc = nullptr;
   double* d_diag = nullptr;
   int nblk[BK_NKINDS] = {0};
-  size_t lds_r2c = 0, lds_c2r = 0, lds_col = 0, lds_adj_col = 0, lds_tiled[3] = {0, 0, 0}, lds_count = 0;
+  size_t lds_r2c = 0, lds_c2r = 0, lds_col = 0, lds_adj_col = 0, lds_tiled[3] = {0, 0, 0};
   int dtype = 0, degree = 3, scheme = 0;
   int geo = 0;  // compiled window geometry shared by every instance (0: none, runtime geometry)
   bool sorted = true;
@@ -415,7 +417,7 @@ pic_status_t do_sort(pic_ctx_t c) {
   if (!c->sorted) return PIC_OK;
   auto* t = c->begin_timed(4);
   hipError_t e = launch_tile_sort(c->dtype, c->d_desc, c->ninst(), c->nblk[BK_COUNT], c->nblk[BK_TILES],
-                                  c->nblk[BK_PART], c->lds_count, c->cur, c->stream);
+                                  c->nblk[BK_PART], c->cur, c->stream);
   c->end_timed(t);
   pic_status_t st = c->hip(e, "tile sort");
   if (st) return st;
@@ -598,6 +600,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.tb.ccursor = (int32_t*)(b + in.L.ccursor);
     d.tb.work = (int4*)(b + in.L.twork);
     d.tb.nwork = (int32_t*)(b + in.L.tnwork);
+    d.tb.done = (int32_t*)(b + in.L.tdone);
     const bool adj = (cf.flags & PIC_FLAG_ADJOINT) != 0;
     d.LF = adj ? (double*)(b + in.L.LF) : nullptr;
     d.LS = adj ? (double2*)(b + in.L.LS) : nullptr;
@@ -622,7 +625,6 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, columns_lds_bytes(cf.ny));
     for (int mode = 0; mode < 3; ++mode)
       c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp));
-    c->lds_count = std::max(c->lds_count, sort_count_lds_bytes(d.tp));
     // a position update moves a particle by less than c dt; the window's slack
     // absorbs sort_every updates without any particle leaving it
     const double cells = cf.c * cf.dt / std::min(g.dx, g.dy);
@@ -638,6 +640,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     }
     if (e == hipSuccess) e = hipMemset(d.tb.count, 0, (size_t)d.tp.ntiles * 4);
     if (e == hipSuccess) e = hipMemset(d.tb.ccount, 0, (size_t)cf.nx * cf.ny * 4);
+    if (e == hipSuccess) e = hipMemset(d.tb.done, 0, 4);
   }
   c->sort_every = every;
   c->geo = tiled_geometry(c->inst[0].d.tp);
@@ -649,7 +652,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     return PIC_ERR_HIP;
   }
   const size_t lds_need = std::max({c->lds_col, c->lds_adj_col, c->lds_r2c, c->lds_c2r, c->lds_tiled[0], c->lds_tiled[1],
-                                    c->lds_tiled[2], c->lds_count});
+                                    c->lds_tiled[2]});
   if (lds_need > (size_t)max_lds) {
     g_err = "grid or tile too large for this device's LDS";
     delete c;

@@ -69,12 +69,13 @@ struct TileP {
 // ts*ts cells of tile t are keys t*ts*ts .. (t+1)*ts*ts - 1), so each tile's
 // particles are contiguous and, inside the tile, grouped by cell.
 struct TileBufs {
-  int32_t* count;    // [ntiles]   particles per tile; zero between sorts
+  int32_t* count;    // [ntiles]   particles per tile (written by the cell scan)
   int32_t* start;    // [ntiles+1] first particle of each tile
   int32_t* ccount;   // [nx*ny]    particles per cell; zero between sorts
-  int32_t* ccursor;  // [nx*ny]    next free slot of each cell during the scatter
+  int32_t* ccursor;  // [nx*ny]    next free slot of each cell, from its tile's start
   int4* work;        // [max_work] (tile, first particle, count, 0)
   int32_t* nwork;    // [1]        chunks in use
+  int32_t* done;     // [1]        blocks of the cell scan finished; zero between sorts
 };
 
 struct SchemeCoef {
@@ -172,9 +173,8 @@ hipError_t launch_particle_diag(int dtype, const void* parts, int64_t n, PhysP p
 
 // tiles.hip
 size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp);
-size_t sort_count_lds_bytes(const TileP& tp);
 hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_tiles, int nb_part,
-                            size_t lds_count, int src_set, hipStream_t s);
+                            int src_set, hipStream_t s);
 // geometry code of a tile plan: a compiled window shape (1, 2) or 0 (from TileP)
 int tiled_geometry(const TileP& tp);
 hipError_t launch_tiled(int dtype, int mode, int degree, int geo, const InstDesc* D, int ninst, int nblocks,

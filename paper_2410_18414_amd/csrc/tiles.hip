@@ -2,7 +2,7 @@
 //
 // The grid's cells are split into tiles of TS x TS cells.  Every few steps the
 // particles are counting-sorted by cell, cells numbered tile-major
-// (k_tile_count, k_tile_scan, k_cell_scan, k_tile_scatter): each tile's
+// (k_tile_count, k_cell_scan, k_tile_scatter): each tile's
 // particles are contiguous and grouped by cell inside it.  The scan cuts each
 // tile's range into chunks of at most CH particles, one chunk per workgroup.
 //
@@ -97,90 +97,92 @@ __device__ __forceinline__ int cell_key(T x, T y, const GridP& g, const TileP& t
   return ok ? cell_of(xi, eta, tp) : 0;
 }
 
-// Lanes of one wave that share a key: one LDS atomic per distinct key in the
-// wave (particles are nearly sorted between sorts, so a wave holds few keys).
-// Returns the lane's rank among the wave's lanes with its key, and the value
-// the group's atomic returned (the group's base) broadcast to the group.
-__device__ __forceinline__ int wave_group_add(int32_t* __restrict__ counters, int key, bool active, int& rank) {
-  const int lane = threadIdx.x & 63;
-  uint64_t pending = __ballot(active);
-  int base = 0;
-  rank = 0;
+// The lanes of this lane's wave that hold the same key (0 for an inactive
+// lane): a ballot per distinct key of the wave (particles are nearly sorted
+// between sorts, so a wave holds few keys).
+__device__ __forceinline__ uint64_t key_group(int key, bool active) {
+  uint64_t pending = __ballot(active), mine = 0;
   while (pending) {
     const int leader = __ffsll((unsigned long long)pending) - 1;
     const int k0 = __shfl(key, leader);
     const uint64_t grp = __ballot(active && key == k0);
-    int b = 0;
-    if (lane == leader) b = atomicAdd(&counters[k0], __popcll(grp));
-    b = __shfl(b, leader);
-    if (active && key == k0) {
-      base = b;
-      rank = __popcll(grp & ((1ull << lane) - 1ull));
-    }
+    if (active && key == k0) mine = grp;
     pending &= ~grp;
   }
-  return base;
+  return mine;
 }
 
-// Cell and tile histograms of the current positions: each block counts 1024
-// particles of one instance (flattened over instances, BK_COUNT).  Tile
-// counts go through an LDS histogram; cell counts straight to global memory,
-// one atomic per distinct cell of a wave (particles stay nearly sorted).
+// counters[key] += (lanes with this key): one atomic per distinct key of the
+// wave, all issued by one instruction (the lowest lane of each group).
+// Returns the counter's old value (the group's base) and the lane's rank in
+// its group; with RET false the atomics return nothing and base is 0.
+template <bool RET>
+__device__ __forceinline__ int wave_group_add(int32_t* __restrict__ counters, int key, bool active, int& rank) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t grp = key_group(key, active);
+  const int leader = grp ? __ffsll((unsigned long long)grp) - 1 : lane;
+  rank = __popcll(grp & ((1ull << lane) - 1ull));
+  int b = 0;
+  if (active && lane == leader) {
+    if (RET)
+      b = atomicAdd(&counters[key], __popcll(grp));
+    else
+      atomicAdd(&counters[key], __popcll(grp));
+  }
+  return RET ? __shfl(b, leader) : 0;
+}
+
+// Cell histogram of the current positions: each block counts 1024 particles
+// of one instance (flattened over instances, BK_COUNT), one atomic lane per
+// distinct cell of a wave (particles stay nearly sorted).
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_tile_count(const InstDesc* __restrict__ D, int ninst, int set) {
-  extern __shared__ int32_t hist[];  // ntiles of this instance
   const int ii = find_inst(D, ninst, BK_COUNT, blockIdx.x);
   const InstDesc& d = D[ii];
   const TileP tp = d.tp;
   const GridP g = d.g;
   const T* __restrict__ px = (const T*)d.set[set][0];
   const T* __restrict__ py = (const T*)d.set[set][1];
-  for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x) hist[t] = 0;
-  __syncthreads();
   const int64_t base = (int64_t)(blockIdx.x - d.blk[BK_COUNT]) * 1024;
   for (int k = 0; k < 4; ++k) {  // whole waves stay in the loop
     const int64_t i = base + k * kThreads + threadIdx.x;
     const bool act = i < d.n;
     const int c = act ? cell_key(px[i], py[i], g, tp) : 0;
     int r;
-    wave_group_add(hist, c >> (2 * tp.log_ts), act, r);
-    wave_group_add(d.tb.ccount, c, act, r);
+    wave_group_add<false>(d.tb.ccount, c, act, r);
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t < tp.ntiles; t += blockDim.x)
-    if (hist[t]) atomicAdd(&d.tb.count[t], hist[t]);
 }
 
-// one block per instance: exclusive scan of the tile counts, cursors, chunk list
-__global__ void __launch_bounds__(1024) k_tile_scan(const InstDesc* __restrict__ D, int ninst) {
-  __shared__ int32_t s_cnt[1024], s_chk[1024];
+// Tile starts and the chunk list from the tile totals (one block, all of its
+// threads): exclusive scan in passes of blockDim tiles.  The totals were
+// written by other blocks of the same launch: read them device-coherently.
+__device__ void tile_scan_block(const InstDesc& d, const TileP& tp) {
+  __shared__ int32_t s_cnt[kThreads], s_chk[kThreads];
   __shared__ int32_t carry_p, carry_c;
-  const InstDesc& d = D[blockIdx.x];
-  const TileP tp = d.tp;
-  int32_t* __restrict__ count = d.tb.count;
-  if (threadIdx.x == 0) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
     carry_p = 0;
     carry_c = 0;
   }
   __syncthreads();
-  for (int base = 0; base < tp.ntiles; base += 1024) {
-    const int t = base + threadIdx.x;
-    const int c = t < tp.ntiles ? count[t] : 0;
+  for (int base = 0; base < tp.ntiles; base += kThreads) {
+    const int t = base + tid;
+    const int c = t < tp.ntiles ? __hip_atomic_load(&d.tb.count[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     const int k = (c + tp.chunk - 1) / tp.chunk;
-    s_cnt[threadIdx.x] = c;
-    s_chk[threadIdx.x] = k;
+    s_cnt[tid] = c;
+    s_chk[tid] = k;
     __syncthreads();
     // Hillis-Steele inclusive scans
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int a = threadIdx.x >= off ? s_cnt[threadIdx.x - off] : 0;
-      const int b = threadIdx.x >= off ? s_chk[threadIdx.x - off] : 0;
+    for (int off = 1; off < kThreads; off <<= 1) {
+      const int a = tid >= off ? s_cnt[tid - off] : 0;
+      const int b = tid >= off ? s_chk[tid - off] : 0;
       __syncthreads();
-      s_cnt[threadIdx.x] += a;
-      s_chk[threadIdx.x] += b;
+      s_cnt[tid] += a;
+      s_chk[tid] += b;
       __syncthreads();
     }
-    const int p0 = carry_p + s_cnt[threadIdx.x] - c;  // exclusive
-    const int k0 = carry_c + s_chk[threadIdx.x] - k;
+    const int p0 = carry_p + s_cnt[tid] - c;  // exclusive
+    const int k0 = carry_c + s_chk[tid] - k;
     if (t < tp.ntiles) {
       d.tb.start[t] = p0;
       for (int j = 0; j < k; ++j) {
@@ -188,52 +190,69 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const InstDesc* __restrict__
         const int e = min(p0 + c, s + tp.chunk);
         d.tb.work[k0 + j] = make_int4(t, s, e - s, 0);
       }
-      count[t] = 0;  // ready for the next sort
     }
     __syncthreads();
-    if (threadIdx.x == 1023) {
-      carry_p += s_cnt[1023];
-      carry_c += s_chk[1023];
+    if (tid == kThreads - 1) {
+      carry_p += s_cnt[kThreads - 1];
+      carry_c += s_chk[kThreads - 1];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     d.tb.start[tp.ntiles] = carry_p;
     *d.tb.nwork = carry_c;
   }
 }
 
-// cell cursors: one wave per tile scans the tile's ts^2 cell counts from the
-// tile's start (flattened over instances, BK_TILES: four tiles per block)
+// Cell cursors and tile starts (flattened over instances, BK_TILES: four tiles
+// per block, one wave per tile).  A wave scans its tile's ts^2 cell counts
+// into offsets from the tile's first slot (the scatter's cursors) and writes
+// the tile's total; the block of the instance that finishes last (a
+// device-scope counter, reset by that block) then scans the tile totals into
+// tile starts and the chunk list.
 __global__ void __launch_bounds__(kThreads) k_cell_scan(const InstDesc* __restrict__ D, int ninst) {
   const int ii = find_inst(D, ninst, BK_TILES, blockIdx.x);
   const InstDesc& d = D[ii];
   const TileP tp = d.tp;
   const int t = (blockIdx.x - d.blk[BK_TILES]) * (kThreads / 64) + (threadIdx.x >> 6);
-  if (t >= tp.ntiles) return;  // whole waves leave together
   const int lane = threadIdx.x & 63;
-  const int cells = tp.ts * tp.ts;
-  int32_t* __restrict__ cc = d.tb.ccount + (size_t)t * cells;
-  int32_t* __restrict__ cu = d.tb.ccursor + (size_t)t * cells;
-  int run = d.tb.start[t];
-  for (int j0 = 0; j0 < cells; j0 += 64) {
-    const int j = j0 + lane;
-    const int c = j < cells ? cc[j] : 0;
-    int v = c;  // inclusive wave scan
-    for (int off = 1; off < 64; off <<= 1) {
-      const int u = __shfl_up(v, off);
-      if (lane >= off) v += u;
+  if (t < tp.ntiles) {
+    const int cells = tp.ts * tp.ts;
+    int32_t* __restrict__ cc = d.tb.ccount + (size_t)t * cells;
+    int32_t* __restrict__ cu = d.tb.ccursor + (size_t)t * cells;
+    int run = 0;
+    for (int j0 = 0; j0 < cells; j0 += 64) {
+      const int j = j0 + lane;
+      const int c = j < cells ? cc[j] : 0;
+      int v = c;  // inclusive wave scan
+      for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off);
+        if (lane >= off) v += u;
+      }
+      if (j < cells) {
+        cu[j] = run + v - c;
+        cc[j] = 0;  // ready for the next sort
+      }
+      run += __shfl(v, 63);
     }
-    if (j < cells) {
-      cu[j] = run + v - c;
-      cc[j] = 0;  // ready for the next sort
-    }
-    run += __shfl(v, 63);
+    if (lane == 0) d.tb.count[t] = run;
   }
+  __shared__ int last;
+  __threadfence();  // this block's totals are visible before it is counted
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nb = (tp.ntiles + kThreads / 64 - 1) / (kThreads / 64);  // blocks of this instance
+    last = atomicAdd(d.tb.done, 1) == nb - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  tile_scan_block(d, tp);
+  if (threadIdx.x == 0) *d.tb.done = 0;  // ready for the next sort
 }
 
-// scatter set `src` into set `src ^ 1`, grouped by cell: one global atomic
-// per distinct cell of a wave
+// scatter set `src` into set `src ^ 1`, grouped by cell: one returning global
+// atomic lane per distinct cell of a wave, one round trip per wave
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __restrict__ D, int ninst, int src) {
   const int ii = find_inst(D, ninst, BK_PART, blockIdx.x);
@@ -253,9 +272,9 @@ __global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __res
   }
   const int c = act ? cell_key(rec[0], rec[1], d.g, tp) : 0;
   int rr;
-  const int base = wave_group_add(d.tb.ccursor, c, act, rr);
+  const int base = wave_group_add<true>(d.tb.ccursor, c, act, rr);
   if (act) {
-    const int64_t o = base + rr;
+    const int64_t o = (int64_t)d.tb.start[c >> (2 * tp.log_ts)] + base + rr;
 #pragma unroll
     for (int a = 0; a < 11; ++a) ((T*)Dd[a])[o] = rec[a];
     d.ids[src ^ 1][o] = id;
@@ -610,19 +629,17 @@ size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp) {
   return (mode != MODE_DEPOSIT ? (size_t)kNodeSlots * tp.win_pad * es : 0) +
          (mode != MODE_GATHER_PUSH ? (size_t)(dtype == PIC_F32 ? 12 : 24) * (tp.win_pad + 8) + 8 : 0);
 }
-size_t sort_count_lds_bytes(const TileP& tp) { return (size_t)tp.ntiles * sizeof(int32_t); }
 
 // count (BK_COUNT blocks), tile scan (one block per instance), cell scan
 // (BK_TILES blocks), scatter (BK_PART blocks)
 hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_tiles, int nb_part,
-                            size_t lds_count, int src_set, hipStream_t s) {
+                            int src_set, hipStream_t s) {
   if (nb_count) {
     if (dtype == PIC_F32)
-      hipLaunchKernelGGL(k_tile_count<float>, dim3(nb_count), dim3(kThreads), lds_count, s, D, ninst, src_set);
+      hipLaunchKernelGGL(k_tile_count<float>, dim3(nb_count), dim3(kThreads), 0, s, D, ninst, src_set);
     else
-      hipLaunchKernelGGL(k_tile_count<double>, dim3(nb_count), dim3(kThreads), lds_count, s, D, ninst, src_set);
+      hipLaunchKernelGGL(k_tile_count<double>, dim3(nb_count), dim3(kThreads), 0, s, D, ninst, src_set);
   }
-  hipLaunchKernelGGL(k_tile_scan, dim3(ninst), dim3(1024), 0, s, D, ninst);
   hipLaunchKernelGGL(k_cell_scan, dim3(nb_tiles), dim3(kThreads), 0, s, D, ninst);
   if (nb_part) {
     if (dtype == PIC_F32)
