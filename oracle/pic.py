@@ -33,6 +33,14 @@ Readings (the paper is silent, ambiguous or misprinted):
     rho^0 = 0; every field history level with n <= 0 is zero.
   * A position that wraps to exactly L (floating point) is set to 0.
   * (grad A . v*)_j = sum_l v*_l d_j A_l; d/dz = 0 in 2-D, so P_z is constant.
+
+The naive comparison (Sec. 5.1, the "naive update" of the Weibel figures;
+Params(naive=True)): step 3 is replaced by mapping rho^{n+1} to the mesh with
+the same spline as J (the PIC charge density of Sec. 2.2), plus the immobile
+ion background, which is the negative of the t = 0 electron charge (so
+rho^0 = 0 as in the cold start).  Readings: rho is deposited at x^{n+1}, the
+positions J^{n+1} is deposited at; BDF-k and DIRK-2 only, since CDF-2 needs
+rho at half levels, which the particle positions never occupy.
 """
 
 import numpy as np
@@ -46,9 +54,12 @@ FIELD_NAMES = ("dphi_dx", "dphi_dy", "Ax", "Ay", "Az",
 
 class Params:
     def __init__(self, nx, ny, lx, ly, degree, scheme, dt, c=1.0, eps0=1.0,
-                 mu0=1.0, q=-1.0, m=1.0, bdf_order=2):
+                 mu0=1.0, q=-1.0, m=1.0, bdf_order=2, naive=False):
         if scheme not in ("bdf", "cdf2", "dirk2"):
             raise ValueError(scheme)
+        if naive and scheme == "cdf2":
+            raise ValueError("the naive charge deposit needs BDF-k or DIRK-2")
+        self.naive = bool(naive)
         if abs(c * c * eps0 * mu0 - 1.0) > 1e-12:
             raise ValueError("c^2 eps0 mu0 must equal 1")
         self.nx, self.ny, self.lx, self.ly = int(nx), int(ny), float(lx), float(ly)
@@ -106,6 +117,19 @@ def deposit_current(p, x, y, v):
             for c in range(3):
                 J[c] += np.bincount(idx, weights=w * qv[:, c], minlength=n)
     return J.reshape(3, p.ny, p.nx)
+
+
+def deposit_charge(p, x, y):
+    """rho(x_g) = sum_p q S(x_g - x_p) (Sec. 2.2, PIC charge density); [ny, nx]."""
+    gx, wx = bspline.stencil(p.degree, x / p.dx)
+    gy, wy = bspline.stencil(p.degree, y / p.dy)
+    n = p.nx * p.ny
+    rho = np.zeros(n)
+    for a in range(gx.shape[1]):
+        for b in range(gy.shape[1]):
+            idx = (gy[:, b] % p.ny) * p.nx + (gx[:, a] % p.nx)
+            rho += np.bincount(idx, weights=p.q * wx[:, a] * wy[:, b] / (p.dx * p.dy), minlength=n)
+    return rho.reshape(p.ny, p.nx)
 
 
 def current_at_nodes(p, x, y, v, nodes, batch=1 << 23):
@@ -202,22 +226,29 @@ def div(p, Vh):
     return p.ikx * Vh[0] + p.iky * Vh[1]
 
 
-def field_update(p, hist, Jh):
-    """Continuity + wave update given J^{n+1} (spectral).  Returns (hist', phi~, A)."""
+def field_update(p, hist, Jh, rho_h=None):
+    """Continuity + wave update given J^{n+1} (spectral).  Returns (hist', phi~, A).
+    rho_h: the deposited rho^{n+1} (spectral) of the naive comparison, used in
+    place of continuity (BDF-k and DIRK-2)."""
+    if rho_h is not None and p.scheme == "cdf2":
+        raise ValueError("the naive charge deposit needs BDF-k or DIRK-2")
     if p.scheme == "bdf":
-        return _bdf_update(p, hist, Jh)
+        return _bdf_update(p, hist, Jh, rho_h)
     if p.scheme == "cdf2":
         return _cdf2_update(p, hist, Jh)
-    return _dirk2_update(p, hist, Jh)
+    return _dirk2_update(p, hist, Jh, rho_h)
 
 
-def _bdf_update(p, hist, Jh):
+def _bdf_update(p, hist, Jh, rho_h=None):
     # Sec. 3.2: BDF-k continuity, wave equations and the L^{-1} update form
     k = p.bdf_order
     a = schemes.bdf_a(k)
     C = schemes.bdf_C(k)
-    rho_new = -(sum(a[j] * hist["rho"][j - 1] for j in range(1, k + 1))
-                + p.dt * div(p, Jh)) / a[0]
+    if rho_h is None:
+        rho_new = -(sum(a[j] * hist["rho"][j - 1] for j in range(1, k + 1))
+                    + p.dt * div(p, Jh)) / a[0]
+    else:
+        rho_new = rho_h
     alpha2 = (a[0] / (p.c * p.dt)) ** 2
     Lh = 1.0 - p.lap / alpha2
     phi_new = (rho_new / (p.eps0 * alpha2)
@@ -247,7 +278,7 @@ def _cdf2_update(p, hist, Jh):
     return out, phi_tilde, A_new
 
 
-def _dirk2_update(p, hist, Jh):
+def _dirk2_update(p, hist, Jh, rho_h=None):
     # Sec. 3.3: s-stage DIRK on (u, v) with u' = v, v' = c^2 (S + Lap u)
     A_t, b, cc = schemes.DIRK2_A, schemes.DIRK2_B, schemes.DIRK2_C
     s = len(b)
@@ -255,7 +286,10 @@ def _dirk2_update(p, hist, Jh):
     J_n = hist["J"]
     J_st = [(1.0 - cc[i]) * J_n + cc[i] * Jh for i in range(s)]
     rho_n = hist["rho"][0]
-    rho_new = rho_n - h * sum(b[i] * div(p, J_st[i]) for i in range(s))
+    if rho_h is None:
+        rho_new = rho_n - h * sum(b[i] * div(p, J_st[i]) for i in range(s))
+    else:
+        rho_new = rho_h
     rho_st = [(1.0 - cc[i]) * rho_n + cc[i] * rho_new for i in range(s)]
 
     def advance(u, v, S):
@@ -300,18 +334,24 @@ class State:
         self.part = init_particles(p, x, y, P)
         self.hist = cold_history(p)
         self.J = None
+        self.rho = None
         self.fields = None
         self.n = 0
+        # naive comparison: immobile ions = minus the t = 0 electron charge
+        self.rho_bg = -deposit_charge(p, self.part["x"], self.part["y"]) if p.naive else None
 
     def deposit(self):
         pt = self.part
         pt["x"], pt["y"] = position_update(self.p, pt["x"], pt["y"], pt["v"])
         self.J = deposit_current(self.p, pt["x"], pt["y"], pt["v"])
+        if self.p.naive:
+            self.rho = deposit_charge(self.p, pt["x"], pt["y"]) + self.rho_bg
         return self.J
 
     def solve(self):
         Jh = np.stack([spectral.fft2(self.J[c]) for c in range(3)])
-        self.hist, phi_t, A_new = field_update(self.p, self.hist, Jh)
+        rho_h = spectral.fft2(self.rho) if self.p.naive else None
+        self.hist, phi_t, A_new = field_update(self.p, self.hist, Jh, rho_h)
         self.fields = gradient_fields(self.p, phi_t, A_new)
         return self.fields
 
