@@ -74,6 +74,14 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
 #define PIC_FLAG_UNFUSED_STEP 2u /* step() runs the three calls separately     */
 #define PIC_FLAG_NO_GRAPH 4u     /* step() never replays a captured HIP graph    */
 #define PIC_FLAG_ADJOINT 8u      /* reserve the adjoint buffers (step_adjoint)   */
+/* The paper's naive comparison (Sec. 5.1, the "naive update" of the Weibel
+ * figures): rho^{n+1} is mapped to the mesh from the particles at x^{n+1} with
+ * the same spline as J (the PIC charge density of Sec. 2.2), plus an immobile
+ * ion background equal to minus the electron charge of init_particles (so
+ * rho^0 = 0), and replaces the continuity update.  BDF-k and DIRK-2 only
+ * (CDF-2 needs rho at half levels): PIC_ERR_UNSUPPORTED otherwise, and with
+ * PIC_FLAG_ADJOINT.  The particle passes are the untiled ones (global atomics). */
+#define PIC_FLAG_NAIVE_RHO 16u
 
 typedef struct {                /* [host] */
   int32_t abi_version;          /* == PIC_ABI_VERSION                                    */

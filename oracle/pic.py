@@ -232,11 +232,12 @@ def field_update(p, hist, Jh, rho_h=None):
     place of continuity (BDF-k and DIRK-2)."""
     if rho_h is not None and p.scheme == "cdf2":
         raise ValueError("the naive charge deposit needs BDF-k or DIRK-2")
+    extra = () if rho_h is None else (rho_h,)
     if p.scheme == "bdf":
-        return _bdf_update(p, hist, Jh, rho_h)
+        return _bdf_update(p, hist, Jh, *extra)
     if p.scheme == "cdf2":
         return _cdf2_update(p, hist, Jh)
-    return _dirk2_update(p, hist, Jh, rho_h)
+    return _dirk2_update(p, hist, Jh, *extra)
 
 
 def _bdf_update(p, hist, Jh, rho_h=None):

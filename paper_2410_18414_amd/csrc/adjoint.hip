@@ -218,9 +218,14 @@ __device__ __forceinline__ void adj_load_window(double* __restrict__ dst, const 
     }
 }
 
+// 512 threads: the two LDS windows (about 112 KB at 16-cell tiles) admit one
+// workgroup per CU, so the workgroup itself brings the waves that hide latency
+// (at most 256 VGPRs each: two waves per SIMD)
+constexpr int kAdjPushThreads = 512;
+
 template <int DEG>
-__global__ void __launch_bounds__(256) k_adj_push_t(const InstDesc* __restrict__ D, StepArgs sa,
-                                                    double* __restrict__ lam) {
+__global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* __restrict__ D, StepArgs sa,
+                                                                double* __restrict__ lam) {
   using S = Spline<double, DEG>;
   constexpr int NW = S::NW;
   const InstDesc& d = D[0];
@@ -642,9 +647,11 @@ hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblock
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (push) {
     switch (degree) {
-      case 1: hipLaunchKernelGGL(k_adj_push_t<1>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
-      case 2: hipLaunchKernelGGL(k_adj_push_t<2>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
-      default: hipLaunchKernelGGL(k_adj_push_t<3>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
+      case 1: hipLaunchKernelGGL(k_adj_push_t<1>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam); break;
+      case 2: hipLaunchKernelGGL(k_adj_push_t<2>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam); break;
+      default:
+        hipLaunchKernelGGL(k_adj_push_t<3>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam);
+        break;
     }
   } else {
     switch (degree) {

@@ -184,8 +184,8 @@ TileP plan_tiles(const pic_config_t& c) {
 
 struct Layout {
   size_t set_bytes;  // one particle set: 11 arrays (cap x es) + ids
-  size_t parts, J, T, H, U, F64, F32, twx, twy, tcount, tstart, ccount, ccursor, twork, tnwork, tdone, LF, LS, LJ,
-      total;
+  size_t parts, J, T, RB, H, U, F64, F32, twx, twy, tcount, tstart, ccount, ccursor, twork, tnwork, tdone, LF, LS,
+      LJ, total;
   size_t plane_c;    // complex entries per spectral plane
 };
 
@@ -206,8 +206,10 @@ Layout plan_instance(const pic_config_t& c) {
   };
   L.set_bytes = 11 * array_bytes(cap, es) + align_up(cap * 4);
   L.parts = take(2 * L.set_bytes);
-  L.J = take(3 * plane_r * 8);
-  L.T = take(3 * L.plane_c * 16);
+  const bool naive = (c.flags & PIC_FLAG_NAIVE_RHO) != 0;
+  L.J = take((naive ? 4 : 3) * plane_r * 8);
+  L.T = take((naive ? 4 : 3) * L.plane_c * 16);
+  L.RB = naive ? take(plane_r * 8) : 0;
   L.H = take((size_t)h.nslots * L.plane_c * 16);
   L.U = take(8 * L.plane_c * 16);
   L.F64 = take(12 * plane_r * 8);
@@ -511,6 +513,16 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
       return PIC_ERR_INVALID_ARG;
     }
   }
+  if (cfgs[0].flags & PIC_FLAG_NAIVE_RHO) {
+    if (cfgs[0].scheme == PIC_SCHEME_CDF2) {
+      g_err = "the naive charge deposit needs BDF-k or DIRK-2 (CDF-2 needs rho at half levels)";
+      return PIC_ERR_UNSUPPORTED;
+    }
+    if (cfgs[0].flags & PIC_FLAG_ADJOINT) {
+      g_err = "the adjoint is not available with the naive charge deposit";
+      return PIC_ERR_UNSUPPORTED;
+    }
+  }
   const size_t need = total_bytes(cfgs, ninst);
   if (!workspace || ((uintptr_t)workspace & (kAlign - 1))) {
     g_err = "workspace must be a 256-byte aligned device pointer";
@@ -548,7 +560,8 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
   c->dtype = cfgs[0].particle_dtype;
   c->degree = cfgs[0].spline_degree;
   c->scheme = cfgs[0].scheme;
-  c->sorted = (cfgs[0].flags & PIC_FLAG_NO_SORT) == 0;
+  // the naive charge deposit runs on the untiled passes
+  c->sorted = (cfgs[0].flags & (PIC_FLAG_NO_SORT | PIC_FLAG_NAIVE_RHO)) == 0;
   c->d_desc = (InstDesc*)c->ws;
   c->d_diag = (double*)(c->ws + align_up(ninst * sizeof(InstDesc)));
   c->inst.resize(ninst);
@@ -605,12 +618,14 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.LF = adj ? (double*)(b + in.L.LF) : nullptr;
     d.LS = adj ? (double2*)(b + in.L.LS) : nullptr;
     d.LJ = adj ? (double*)(b + in.L.LJ) : nullptr;
+    d.naive = (cf.flags & PIC_FLAG_NAIVE_RHO) ? 1 : 0;
+    d.RB = d.naive ? (double*)(b + in.L.RB) : nullptr;
     d.n = 0;
     d.R_r2c = rows_r2c_R(cf.nx, cf.ny);
     d.R_c2r = rows_c2r_R(cf.nx, cf.ny);
     d.nb_col = columns_nb(cf.ny);
     // flattened block ranges
-    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * 3, (cf.nx / 2 + 1) * columns_parts(cf.scheme),
+    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * (3 + d.naive), (cf.nx / 2 + 1) * columns_parts(cf.scheme),
                                cf.ny / d.R_c2r * 6, d.tp.max_work,
                                ceil_div(cf.max_particles, 256), ceil_div(cf.max_particles, 1024),
                                ceil_div(d.tp.ntiles, 4)};
@@ -919,6 +934,21 @@ pic_status_t init_particles(pic_ctx_t c, int64_t n, const double* x, const doubl
   if (st) return st;
   st = reset_fields(c, in);
   if (st) return st;
+  if (in.d.naive) {
+    // naive charge deposit: immobile ions = minus the electron charge at x^0,
+    // which is also where the deposited rho plane of J starts
+    const size_t plane = (size_t)in.cfg.nx * in.cfg.ny;
+    st = c->hip(launch_fill_f64(in.d.RB, plane, 0.0, c->stream), "ion background fill");
+    if (!st)
+      st = c->hip(launch_charge(c->dtype, c->degree, &pa, n, in.d.g, -in.d.ph.q * in.d.g.inv_area, in.d.RB,
+                                c->stream),
+                  "ion background");
+    if (!st)
+      st = c->hip(hipMemcpyAsync(in.d.J + 3 * plane, in.d.RB, plane * sizeof(double), hipMemcpyDeviceToDevice,
+                                 c->stream),
+                  "rho plane start");
+    if (st) return st;
+  }
   in.d.n = n;
   st = c->upload_desc();
   if (st) return st;

@@ -8,11 +8,15 @@
 // stepper's form (Algorithm 1, third step); spectral derivatives (Sec. 4.1).
 //
 // Data flow (x fastest in real space, complex128 spectra):
-//   J   [3][ny][nx]        real, consumed (zeroed) by k_rows_r2c
-//   T   [3][nxh][ny]       x-transformed J, transposed so columns are contiguous
+//   J   [3][ny][nx]        real, consumed (zeroed) by k_rows_r2c; naive charge
+//                          mode: a fourth plane, the deposited rho, reset to the
+//                          ion background instead of zero
+//   T   [3][nxh][ny]       x-transformed J (naive: [4], rho last), transposed so
+//                          columns are contiguous
 //   H   [slot][nxh][ny]    spectral history (ring slots chosen by the host)
 //   U   [8][nxh][ny]       y-inverse-transformed phi~, d_y phi~, A, d_y A
-//   F   [12][ny][nx]       real mesh fields for the gather (float64, + float32 copy)
+//   F   [12][ny][nx]       real mesh fields for the gather (float64); the float32
+//                          copy is node-major [ny][nx][12]
 // Reading of the Nyquist mode (the paper is silent): the first-derivative
 // symbol is zero at index n/2 of each axis and the Laplacian is built from the
 // same symbols, so div(grad) equals the Laplacian exactly.
@@ -39,6 +43,8 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
   const int lb = blockIdx.x - d.blk[BK_R2C];
   const int c = lb / ngr, y0 = (lb - c * ngr) * R;
   double* __restrict__ Jc = (adj ? d.LF : d.J) + (size_t)c * g.nx * g.ny;
+  // the naive mode's rho plane restarts from the ion background
+  const double* __restrict__ reset = (!adj && c == 3) ? d.RB : nullptr;
   double2* __restrict__ T = adj ? d.LS : d.T;
   const int N = g.nx, B = R >> 1;
   double2* a = sm;
@@ -49,8 +55,8 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
     const int r = t / N, x = t - r * N;
     const size_t i0 = (size_t)(y0 + 2 * r) * N + x, i1 = i0 + N;
     a[t] = make_double2(Jc[i0], Jc[i1]);
-    Jc[i0] = 0.0;  // consumed: zero for the next deposit (or adjoint scatter)
-    Jc[i1] = 0.0;
+    Jc[i0] = reset ? reset[i0] : 0.0;  // consumed: ready for the next deposit (or adjoint scatter)
+    Jc[i1] = reset ? reset[i1] : 0.0;
   }
   __syncthreads();
   const double2* res = fft_lds<false>(a, b, N, B, tws);
@@ -82,7 +88,7 @@ struct ModeOut {
 // that every history slot index is static and all history loads issue at once
 template <int SCHEME, int K>
 __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, double2 J0, double2 J1,
-                               double2 J2, double kxs, double kys, const SchemeCoef& sc,
+                               double2 J2, const double2* rho_dep, double kxs, double kys, const SchemeCoef& sc,
                                const HistSlots& hs) {
   const double kappa = kxs * kxs + kys * kys;  // -Laplacian symbol
   auto at = [&](int slot) -> double2& { return H[(size_t)slot * plane + m]; };
@@ -140,7 +146,10 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
         Jst[i][l] = cadd(cscale(Jn[l], 1.0 - sc.dirkC[i]), cscale(Jn1[l], sc.dirkC[i]));
     const double2 rho_n = at(hs.rho[0]);
     double2 rho = rho_n;
-    for (int i = 0; i < 2; ++i) rho = csub(rho, cscale(divv(Jst[i][0], Jst[i][1]), h * sc.dirkB[i]));
+    if (rho_dep)
+      rho = *rho_dep;  // naive comparison: the deposited rho^{n+1}
+    else
+      for (int i = 0; i < 2; ++i) rho = csub(rho, cscale(divv(Jst[i][0], Jst[i][1]), h * sc.dirkB[i]));
     double2 rst[2];
     for (int i = 0; i < 2; ++i) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
     // one scalar wave component: (u, v)' = (v, c^2 (S + Lap u)), Lap = -kappa
@@ -206,22 +215,23 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
   // twiddles staged in LDS where they fit (ny <= 512), else read from global
   const double2* tws = d.twy;
   if (N <= 512) {
-    double2* t_lds = wk + max(6, 2 * NB) * N;
+    double2* t_lds = wk + max(8, 2 * NB) * N;
     for (int t = threadIdx.x; t < N; t += blockDim.x) t_lds[t] = d.twy[t];
     tws = t_lds;
   }
-  for (int t = threadIdx.x; t < 3 * N; t += blockDim.x) {
+  const int ncol = 3 + d.naive;  // J (and the naive mode's deposited rho)
+  for (int t = threadIdx.x; t < ncol * N; t += blockDim.x) {
     const int c = t / N, y = t - c * N;
     wk[t] = T[((size_t)c * g.nxh + kx) * N + y];
   }
   __syncthreads();
-  const double2* Jh = fft_lds<false>(wk, wk + 3 * N, N, 3, tws);
+  const double2* Jh = fft_lds<false>(wk, wk + ncol * N, N, ncol, tws);
   const double kxs = kx_sym(kx, g);
   const double scale = 1.0 / ((double)g.nx * g.ny);
   for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
     const double2 J0 = Jh[ky], J1 = Jh[N + ky], J2 = Jh[2 * N + ky];
-    const ModeOut o = mode_update<SCHEME, K>(H, plane, (size_t)kx * N + ky, J0, J1, J2, kxs,
-                                          ky_sym(ky, g), sc, hs);
+    const ModeOut o = mode_update<SCHEME, K>(H, plane, (size_t)kx * N + ky, J0, J1, J2,
+                                          d.naive ? Jh + 3 * N + ky : nullptr, kxs, ky_sym(ky, g), sc, hs);
     store[ky] = cscale(o.phi, scale);
     store[N + ky] = cscale(o.A[0], scale);
     store[2 * N + ky] = cscale(o.A[1], scale);
@@ -283,8 +293,11 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
     for (int i = tid; i < N; i += nth) t_lds[i] = d.twy[i];
     tws = t_lds;
   }
-  const int ncol = part == 0 ? 2 : 1;
-  const int c0 = part == 0 ? 0 : part - 1;  // first J component transformed
+  // part 0 transforms J_x, J_y (the divergence), or in the naive mode the
+  // deposited rho (component 3); part 1 + l transforms J_l
+  const bool naive_rho = part == 0 && d.naive;
+  const int ncol = part == 0 && !naive_rho ? 2 : 1;
+  const int c0 = part == 0 ? (naive_rho ? 3 : 0) : part - 1;
   for (int i = tid; i < ncol * N; i += nth) {
     const int c = i / N, y = i - c * N;
     wk[i] = T[((size_t)(c0 + c) * g.nxh + kx) * N + y];
@@ -299,9 +312,11 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
     if (ky >= N) continue;
     if (SCHEME == PIC_SCHEME_BDF) {
       if (part == 0) {
-        // sum_j a_j rho^{n+1-j} and sum_i C_i phi^{n+1-i}
+        // sum_j a_j rho^{n+1-j} (continuity only) and sum_i C_i phi^{n+1-i}
+        if (!naive_rho) {
 #pragma unroll
-        for (int j = 1; j <= K; ++j) h0[m] = cadd(h0[m], cscale(at(hs.rho[j - 1], ky), sc.a[j]));
+          for (int j = 1; j <= K; ++j) h0[m] = cadd(h0[m], cscale(at(hs.rho[j - 1], ky), sc.a[j]));
+        }
 #pragma unroll
         for (int i = 1; i <= 2 * K; ++i) h1[m] = cadd(h1[m], cscale(at(hs.phi[i - 1], ky), sc.Cn[i]));
       } else {
@@ -333,11 +348,11 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
     const double Lh = 1.0 + (kxs * kxs + kys * kys) * sc.inv_alpha2;
     double2 out;
     if (part == 0) {
-      const double2 J0 = Jh[ky], J1 = Jh[N + ky];
+      const double2 J0 = Jh[ky], J1 = naive_rho ? J0 : Jh[N + ky];
       const double2 divJ = mul_i(make_double2(kxs * J0.x + kys * J1.x, kxs * J0.y + kys * J1.y));  // i k . J
       if (SCHEME == PIC_SCHEME_BDF) {
-        // continuity: sum_j a_j rho^{n+1-j} + dt div J^{n+1} = 0
-        const double2 rho = cscale(cadd(cscale(divJ, sc.dt), h0[m]), -1.0 / sc.a[0]);
+        // continuity: sum_j a_j rho^{n+1-j} + dt div J^{n+1} = 0 (naive: the deposited rho)
+        const double2 rho = naive_rho ? J0 : cscale(cadd(cscale(divJ, sc.dt), h0[m]), -1.0 / sc.a[0]);
         const double2 phi = cdivr(csub(cscale(rho, sc.inv_alpha2 / sc.eps0), h1[m]), Lh);
         at(hs.rho_new, ky) = rho;
         at(hs.phi_new, ky) = phi;
@@ -437,10 +452,8 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
     const double2 z = res[t];
     F64[s0 * plane + o] = z.x;
     if (has1) F64[s1 * plane + o] = z.y;
-    if (F32) {
-      F32[s0 * plane + o] = (float)z.x;
-      F32[s1 * plane + o] = (float)z.y;
-    }
+    if (F32)  // node-major record: slots s0, s0 + 1 of node o
+      *reinterpret_cast<float2*>(F32 + o * kFieldSlots + s0) = make_float2((float)z.x, (float)z.y);
   }
 }
 
@@ -605,7 +618,7 @@ size_t rows_c2r_lds_bytes(int nx, int ny) { return (size_t)(2 * rows_c2r_R(nx, n
 int columns_nb(int ny) { return ny <= 256 ? 8 : (ny <= 512 ? 4 : 2); }
 size_t columns_lds_bytes(int ny) {
   const int nb = columns_nb(ny);
-  return (size_t)(4 + std::max(6, 2 * nb) + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2);
+  return (size_t)(4 + std::max(8, 2 * nb) + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2);
 }
 
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {

@@ -103,6 +103,24 @@ __device__ __forceinline__ void deposit_global(int sx, int sy, const T* wx, cons
   }
 }
 
+// s S(x_g - x) added to one real mesh plane (global float64 atomics)
+template <typename T, int DEG>
+__device__ __forceinline__ void deposit_scalar_one(T x, T y, T s, double* __restrict__ R, const GridP& g) {
+  using S = Spline<T, DEG>;
+  const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
+  if (!in_box(xi, eta, g)) return;  // non-finite or unwrapped: touch no memory
+  int sx, sy;
+  T wx[S::NW], wy[S::NW];
+  S::eval(xi, sx, wx);
+  S::eval(eta, sy, wy);
+#pragma unroll
+  for (int b = 0; b < S::NW; ++b) {
+    const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
+#pragma unroll
+    for (int a = 0; a < S::NW; ++a) atomicAdd(R + row + wrapi(sx + a, g.nx), (double)(s * wx[a] * wy[b]));
+  }
+}
+
 template <typename T, int DEG>
 __device__ __forceinline__ void deposit_one(T x, T y, T jx, T jy, T jz, double* __restrict__ J,
                                             const GridP& g) {
@@ -118,6 +136,16 @@ __device__ __forceinline__ void deposit_one(T x, T y, T jx, T jy, T jz, double* 
 
 // gathered values: 0 dphi/dx, 1 dphi/dy, 2..4 A, 5..7 dA/dx, 8..10 dA/dy,
 // read from the planar mesh fields F[f][ny][nx]; out is accumulated into
+// Mesh fields read by the gathers: float64 planar, float32 node-major (see
+// kFieldSlots)
+template <typename T>
+__device__ __forceinline__ T field_at(const T* __restrict__ F, int f, size_t node, size_t plane) {
+  if constexpr (sizeof(T) == 4)
+    return F[node * kFieldSlots + f];
+  else
+    return F[f * plane + node];
+}
+
 template <typename T, int DEG>
 __device__ __forceinline__ void gather_global(int sx, int sy, const T* wx, const T* wy, const T* __restrict__ F,
                                               const GridP& g, T* out) {
@@ -133,7 +161,7 @@ __device__ __forceinline__ void gather_global(int sx, int sy, const T* wx, const
     for (int a = 0; a < S::NW; ++a) {
       const size_t o = row + wrapi(sx + a, g.nx);
 #pragma unroll
-      for (int f = 0; f < 11; ++f) acc[f] += wx[a] * F[f * plane + o];
+      for (int f = 0; f < 11; ++f) acc[f] += wx[a] * field_at(F, f, o, plane);
     }
 #pragma unroll
     for (int f = 0; f < 11; ++f) out[f] += wy[b] * acc[f];

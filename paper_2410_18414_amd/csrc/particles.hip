@@ -58,7 +58,18 @@ __global__ void __launch_bounds__(256) k_untiled(const InstDesc* __restrict__ D,
     p.y[i] = y;
     const T s = q * T(g.inv_area);
     deposit_one<T, DEG>(x, y, s * vx, s * vy, s * vz, J, g);
+    // naive comparison: rho^{n+1} from the same spline at x^{n+1}
+    if (d.naive) deposit_scalar_one<T, DEG>(x, y, s, J + 3 * (size_t)g.nx * g.ny, g);
   }
+}
+
+// s S(x_g - x_p) of every particle added to the plane R (the naive mode's ion
+// background: s = -q / (dx dy) at the initial positions)
+template <typename T, int DEG>
+__global__ void __launch_bounds__(256) k_charge(Parts<T> p, int64_t n, GridP g, double s, double* __restrict__ R) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  deposit_scalar_one<T, DEG>(p.x[i], p.y[i], T(s), R, g);
 }
 
 template <typename T>
@@ -165,6 +176,24 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s) {
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
   if (n) hipLaunchKernelGGL(k_fill_f64, dim3(blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_charge(int dtype, int degree, const void* parts, int64_t n, GridP g, double s, double* R,
+                         hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const dim3 nb(blocks_for(n)), th(256);
+  if (dtype == PIC_F32) {
+    const Parts<float>& p = *(const Parts<float>*)parts;
+    if (degree == 1) hipLaunchKernelGGL((k_charge<float, 1>), nb, th, 0, st, p, n, g, s, R);
+    else if (degree == 2) hipLaunchKernelGGL((k_charge<float, 2>), nb, th, 0, st, p, n, g, s, R);
+    else hipLaunchKernelGGL((k_charge<float, 3>), nb, th, 0, st, p, n, g, s, R);
+  } else {
+    const Parts<double>& p = *(const Parts<double>*)parts;
+    if (degree == 1) hipLaunchKernelGGL((k_charge<double, 1>), nb, th, 0, st, p, n, g, s, R);
+    else if (degree == 2) hipLaunchKernelGGL((k_charge<double, 2>), nb, th, 0, st, p, n, g, s, R);
+    else hipLaunchKernelGGL((k_charge<double, 3>), nb, th, 0, st, p, n, g, s, R);
+  }
   return hipGetLastError();
 }
 

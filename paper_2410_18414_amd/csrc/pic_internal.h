@@ -87,6 +87,12 @@ struct SchemeCoef {
   double dt, c, eps0, mu0;
 };
 
+// Mesh fields for the gather: the float64 fields are planar F[12][ny][nx];
+// the float32 copy (float32 particles) is node-major F[ny][nx][kFieldSlots]
+// -- the eleven gathered fields and phi~ of a node form one 48-byte record
+// (three 16-byte vectors), the layout of the tiled passes' LDS windows.
+constexpr int kFieldSlots = 12;
+
 // block ranges of the flattened kernels
 enum BlockKind {
   BK_R2C = 0,    // (ny/R_r2c) x 3 blocks
@@ -118,6 +124,8 @@ struct InstDesc {
   double* LF;               // adjoint buffers (PIC_FLAG_ADJOINT, else null): [11][ny][nx] mesh-field adjoints,
   double2* LS;              // [11][nxh][ny] their x-transforms (planes 0..2 reused for the J adjoint columns),
   double* LJ;               // [3][ny][nx] adjoint of J
+  double* RB;               // naive charge deposit (PIC_FLAG_NAIVE_RHO, else null): [ny][nx] ion background
+  int naive;                // 1: J holds a fourth plane, the deposited rho; T a fourth component
   TileBufs tb;
   int64_t n;                // particles loaded
   int R_r2c, R_c2r, nb_col; // rows per block of the row kernels; inverse batch of the column kernel
@@ -160,6 +168,9 @@ __device__ __forceinline__ int find_inst(const InstDesc* __restrict__ D, int nin
 // launchers (each returns hipGetLastError() of its launches)
 
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
+// s S(x_g - x_p) of the particles of `parts` (a Parts<float|double>) added to R
+hipError_t launch_charge(int dtype, int degree, const void* parts, int64_t n, GridP g, double s, double* R,
+                         hipStream_t st);
 
 // particles.hip: untiled passes (flattened over instances) and per-instance I/O
 // mode: 0 deposit (position update + deposit), 1 gather + push, 2 fused

@@ -33,7 +33,7 @@ namespace {
 constexpr int kThreads = 256;
 // slots per node of the LDS field window: the eleven gathered fields and one
 // pad, so that a node's record is three 16-byte (float) or six (double) vectors
-constexpr int kNodeSlots = 12;
+constexpr int kNodeSlots = kFieldSlots;
 
 __device__ __forceinline__ void load_node(const float* p, float* q) {
   const float4* v = reinterpret_cast<const float4*>(p);
@@ -286,9 +286,10 @@ __global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __res
 
 enum { MODE_DEPOSIT = 0, MODE_GATHER_PUSH = 1, MODE_FUSED = 2 };
 
-// LDS accumulator of the deposit: float64 for both particle precisions.  On
-// gfx950 the LDS float64 add (ds_add_f64) sustains several times the rate of
-// the float32 add, and it keeps the per-tile partial sums exact to float64.
+// LDS storage unit of the deposit window: 8 bytes for both particle
+// precisions.  Float64 particles add float64 values (on gfx950 the LDS float64
+// add sustains many times the rate of the float32 add, which serialises per
+// lane); float32 particles reuse the storage for the packed fixed-point sums.
 template <typename T>
 struct Acc {
   using type = double;
@@ -365,7 +366,27 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   const int wi = threadIdx.x & (rl - 1), wj0 = threadIdx.x >> lrl, wjs = blockDim.x >> lrl;
   const int gxw = (ox + wi) & (g.nx - 1);
   if (GATHER && wi < W) {
-    if (FIXED) {
+    if constexpr (sizeof(T) == 4) {
+      // float32 fields are node-major in global memory as in LDS: a node is
+      // three 16-byte vectors
+      auto copy_row = [&](int j) {
+        const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
+        const float4* src = reinterpret_cast<const float4*>(F + go * kFieldSlots);
+        float4* dst = reinterpret_cast<float4*>(fw + (j * W + wi) * kNodeSlots);
+        const float4 a0 = src[0], a1 = src[1], a2 = src[2];
+        dst[0] = a0;
+        dst[1] = a1;
+        dst[2] = a2;
+      };
+      if (FIXED) {
+        constexpr int NJ = (G::W + (kThreads >> G::LRL) - 1) / (kThreads >> G::LRL);
+#pragma unroll
+        for (int r = 0; r < NJ; ++r)
+          if (wj0 + r * wjs < W) copy_row(wj0 + r * wjs);
+      } else {
+        for (int j = wj0; j < W; j += wjs) copy_row(j);
+      }
+    } else if (FIXED) {
       // compile-time sweep: a thread's rows (at most NJ) and fields all load
       // before the first LDS store
       constexpr int NJ = (G::W + (kThreads >> G::LRL) - 1) / (kThreads >> G::LRL);

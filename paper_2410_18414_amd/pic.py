@@ -25,6 +25,7 @@ FLAG_NO_SORT = 1
 FLAG_UNFUSED_STEP = 2
 FLAG_NO_GRAPH = 4
 FLAG_ADJOINT = 8
+FLAG_NAIVE_RHO = 16   # rho deposited with the spline instead of continuity (the paper's naive update)
 FIELD_J = 0
 FIELD_MESH = 1
 DIAG_NAMES = ("gauge_l2", "gauge_scale", "gauss_l2", "gauss_scale", "charge", "energy",
