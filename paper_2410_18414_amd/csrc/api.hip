@@ -184,8 +184,8 @@ TileP plan_tiles(const pic_config_t& c) {
 
 struct Layout {
   size_t set_bytes;  // one particle set: 11 arrays (cap x es) + ids
-  size_t parts, J, T, RB, H, U, F64, F32, twx, twy, tcount, tstart, ccount, ccursor, twork, tnwork, tdone, LF, LS,
-      LJ, total;
+  size_t parts, J, T, RB, H, U, F64, F32, twx, twy, tcount, tstart, ccount, ccursor, twork, tnwork, tdone, trank,
+      LF, LS, LJ, total;
   size_t plane_c;    // complex entries per spectral plane
 };
 
@@ -223,6 +223,7 @@ Layout plan_instance(const pic_config_t& c) {
   L.twork = take((size_t)tp.max_work * 16);
   L.tnwork = take(4);
   L.tdone = take(4);
+  L.trank = take((size_t)cap * 4);
   if (c.flags & PIC_FLAG_ADJOINT) {
     L.LF = take(11 * plane_r * 8);
     L.LS = take(11 * L.plane_c * 16);
@@ -614,6 +615,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.tb.work = (int4*)(b + in.L.twork);
     d.tb.nwork = (int32_t*)(b + in.L.tnwork);
     d.tb.done = (int32_t*)(b + in.L.tdone);
+    d.tb.rank = (int32_t*)(b + in.L.trank);
     const bool adj = (cf.flags & PIC_FLAG_ADJOINT) != 0;
     d.LF = adj ? (double*)(b + in.L.LF) : nullptr;
     d.LS = adj ? (double2*)(b + in.L.LS) : nullptr;

@@ -72,10 +72,11 @@ struct TileBufs {
   int32_t* count;    // [ntiles]   particles per tile (written by the cell scan)
   int32_t* start;    // [ntiles+1] first particle of each tile
   int32_t* ccount;   // [nx*ny]    particles per cell; zero between sorts
-  int32_t* ccursor;  // [nx*ny]    next free slot of each cell, from its tile's start
+  int32_t* ccursor;  // [nx*ny]    first slot of each cell, from its tile's start
   int4* work;        // [max_work] (tile, first particle, count, 0)
   int32_t* nwork;    // [1]        chunks in use
   int32_t* done;     // [1]        blocks of the cell scan finished; zero between sorts
+  int32_t* rank;     // [capacity] each particle's slot among its cell's particles (count pass)
 };
 
 struct SchemeCoef {

@@ -134,7 +134,9 @@ __device__ __forceinline__ int wave_group_add(int32_t* __restrict__ counters, in
 
 // Cell histogram of the current positions: each block counts 1024 particles
 // of one instance (flattened over instances, BK_COUNT), one atomic lane per
-// distinct cell of a wave (particles stay nearly sorted).
+// distinct cell of a wave (particles stay nearly sorted).  The counter's old
+// value plus the lane's rank in its wave group is the particle's slot among
+// its cell's particles, kept for the scatter.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_tile_count(const InstDesc* __restrict__ D, int ninst, int set) {
   const int ii = find_inst(D, ninst, BK_COUNT, blockIdx.x);
@@ -149,7 +151,8 @@ __global__ void __launch_bounds__(kThreads) k_tile_count(const InstDesc* __restr
     const bool act = i < d.n;
     const int c = act ? cell_key(px[i], py[i], g, tp) : 0;
     int r;
-    wave_group_add<false>(d.tb.ccount, c, act, r);
+    const int base = wave_group_add<true>(d.tb.ccount, c, act, r);
+    if (act) d.tb.rank[i] = base + r;
   }
 }
 
@@ -251,34 +254,27 @@ __global__ void __launch_bounds__(kThreads) k_cell_scan(const InstDesc* __restri
   if (threadIdx.x == 0) *d.tb.done = 0;  // ready for the next sort
 }
 
-// scatter set `src` into set `src ^ 1`, grouped by cell: one returning global
-// atomic lane per distinct cell of a wave, one round trip per wave
+// scatter set `src` into set `src ^ 1`, grouped by cell: particle i goes to its
+// tile's start + its cell's offset in the tile + its slot in the cell (from the
+// count pass); no atomics, so the copy streams
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __restrict__ D, int ninst, int src) {
   const int ii = find_inst(D, ninst, BK_PART, blockIdx.x);
   const InstDesc& d = D[ii];
   const TileP tp = d.tp;
   const int64_t i = (int64_t)(blockIdx.x - d.blk[BK_PART]) * kThreads + threadIdx.x;
-  const bool act = i < d.n;
+  if (i >= d.n) return;  // no cross-lane operations below
   const void* const* S = d.set[src];
   void* const* Dd = d.set[src ^ 1];
-  // the particle's record is loaded while the cursor atomics are in flight
   T rec[11];
-  int32_t id = 0;
-  if (act) {
 #pragma unroll
-    for (int a = 0; a < 11; ++a) rec[a] = ((const T*)S[a])[i];
-    id = d.ids[src][i];
-  }
-  const int c = act ? cell_key(rec[0], rec[1], d.g, tp) : 0;
-  int rr;
-  const int base = wave_group_add<true>(d.tb.ccursor, c, act, rr);
-  if (act) {
-    const int64_t o = (int64_t)d.tb.start[c >> (2 * tp.log_ts)] + base + rr;
+  for (int a = 0; a < 11; ++a) rec[a] = ((const T*)S[a])[i];
+  const int32_t id = d.ids[src][i], slot = d.tb.rank[i];
+  const int c = cell_key(rec[0], rec[1], d.g, tp);  // the count pass's key of the same positions
+  const int64_t o = (int64_t)d.tb.start[c >> (2 * tp.log_ts)] + d.tb.ccursor[c] + slot;
 #pragma unroll
-    for (int a = 0; a < 11; ++a) ((T*)Dd[a])[o] = rec[a];
-    d.ids[src ^ 1][o] = id;
-  }
+  for (int a = 0; a < 11; ++a) ((T*)Dd[a])[o] = rec[a];
+  d.ids[src ^ 1][o] = id;
 }
 
 // ---------------------------------------------------------------------------
