@@ -288,3 +288,25 @@ def test_graph_replay_matches_oracle_and_direct(gpu_lib, scheme, k):
     errs, bad = compare_particles(pg, o.part, w["lx"], w["ly"], 1e-10)
     assert not bad, errs
     assert rel(pic.get_history(g).cpu().numpy(), hist_to_flat(o.p, o.hist)) <= 1e-10
+
+
+def test_reload_at_every_phase_of_the_sort_cycle(gpu_lib):
+    """Loading particles again after k steps -- whichever pass of the sort
+    cycle came last, including one that already counted cells for a sort that
+    then never runs -- gives the same run as a fresh context (up to the
+    rounding order of the float64 deposit atomics)."""
+    w = cloud_small(seed=61)
+    fresh = make_gpu(w, 3, "bdf", "f64", bdf_order=2)
+    pic.step(fresh, 9)
+    ref = gpu_parts(fresh)
+    data = (torch.as_tensor(w["x"], device=fresh.device), torch.as_tensor(w["y"], device=fresh.device),
+            torch.as_tensor(np.ascontiguousarray(w["P"].T), device=fresh.device))
+    for k in range(1, 14):
+        g = make_gpu(w, 3, "bdf", "f64", bdf_order=2)
+        pic.step(g, k)
+        pic.init_particles(g, *data)
+        pic.step(g, 9)
+        got = gpu_parts(g)
+        errs, bad = compare_particles(got, ref, w["lx"], w["ly"], 1e-12)
+        assert not bad, (k, errs)
+        g.close()
