@@ -7,6 +7,10 @@ held in the history after a step:
   CDF-2  (Sec. 3.1): eps1^{n+1} = (phi^{n+3/2} - phi^{n+1/2})/(c^2 dt) + div A^{n+1};
          E^{n+1/2} = -grad (phi^{n+3/2} + phi^{n-1/2})/2 - (A^{n+1} - A^n)/dt;
          Gauss: div E^{n+1/2} - (rho^{n+3/2} + rho^{n-1/2})/(2 eps0).
+         Reading for the semi-implicit and explicit forms (the paper states the
+         Gauss theorem for the implicit form only; the same steps give): the
+         source level rho^{n+1/2}, and for the explicit form the Laplacian's
+         level, E^{n+1/2} = -grad phi^{n+1/2} - (A^{n+1} - A^n)/dt.
   DIRK-2 (Sec. 3.3): eps1^{n+1} = -phi^{n+1} + phi^n
          - c^2 h (R^{s,n} div A^n + R^{s,n+1} div A^{n+1}), R = sum b_i (1-c_i), sum b_i c_i.
          Reading: Gauss is reported (not guaranteed, remark closing Sec. 3.3) with
@@ -42,11 +46,18 @@ def residuals(state):
         phi, rho = h["phi"][0], h["rho"][0]
         Eh = np.stack([-ikx * phi - dA[0], -iky * phi - dA[1], -dA[2]])
         Ah = h["A"][0]
-    elif p.scheme == "cdf2":
+    elif p.scheme in ("cdf2", "cdf2_semi", "cdf2_explicit"):
         gauge_t = (h["phi"][0] - h["phi"][1]) / (p.c ** 2 * p.dt)
         gauge_d = divA(h["A"][0])
-        phim = 0.5 * (h["phi"][0] + h["phi"][2])
-        rho = 0.5 * (h["rho"][0] + h["rho"][2])
+        if p.scheme == "cdf2":
+            phim = 0.5 * (h["phi"][0] + h["phi"][2])
+            rho = 0.5 * (h["rho"][0] + h["rho"][2])
+        elif p.scheme == "cdf2_semi":
+            phim = 0.5 * (h["phi"][0] + h["phi"][2])
+            rho = h["rho"][1]
+        else:
+            phim = h["phi"][1]
+            rho = h["rho"][1]
         dA = (h["A"][0] - h["A"][1]) / p.dt
         Eh = np.stack([-ikx * phim - dA[0], -iky * phim - dA[1], -dA[2]])
         Ah = 0.5 * (h["A"][0] + h["A"][1])

@@ -26,7 +26,13 @@ Readings (the paper is silent, ambiguous or misprinted):
     stage equations of Sec. 3.3 and dropped in the specialised ones).
   * The DIRK "gauge update" for phi is the gauge constraint, used as the
     diagnostic; phi is advanced by its own stage equations.
-  * CDF-2 is the implicit form (sources averaged over n+1 and n-1).
+  * CDF-2 is the implicit form (sources averaged over n+1 and n-1); the
+    semi-implicit ("cdf2_semi": sources rho^{n+1/2}, J^n, Laplacian averaged
+    over n+1 and n-1) and explicit ("cdf2_explicit": sources rho^{n+1/2}, J^n,
+    Laplacian at n) forms of Sec. 3.1 are the same staggered scheme with the
+    other wave updates.  All three keep rho^{n+3/2} from the staggered
+    continuity equation with J^{n+1} (given J^{n, n+1}, Sec. 3.1) and use
+    phi~ = (phi^{n+3/2} + phi^{n+1/2})/2 for the push.
   * v^{-1} by Taylor expansion: with the cold start below the force at t=0 is
     zero, so v^{-1} = v^0.
   * Cold start: immobile ions are the negative of the t=0 electron charge, so
@@ -52,12 +58,16 @@ FIELD_NAMES = ("dphi_dx", "dphi_dy", "Ax", "Ay", "Az",
                "dAx_dx", "dAy_dx", "dAz_dx", "dAx_dy", "dAy_dy", "dAz_dy", "phi")
 
 
+# the staggered centred-difference schemes of Sec. 3.1
+CDF2_FORMS = ("cdf2", "cdf2_semi", "cdf2_explicit")
+
+
 class Params:
     def __init__(self, nx, ny, lx, ly, degree, scheme, dt, c=1.0, eps0=1.0,
                  mu0=1.0, q=-1.0, m=1.0, bdf_order=2, naive=False):
-        if scheme not in ("bdf", "cdf2", "dirk2"):
+        if scheme not in ("bdf",) + CDF2_FORMS + ("dirk2",):
             raise ValueError(scheme)
-        if naive and scheme == "cdf2":
+        if naive and scheme in CDF2_FORMS:
             raise ValueError("the naive charge deposit needs BDF-k or DIRK-2")
         self.naive = bool(naive)
         if abs(c * c * eps0 * mu0 - 1.0) > 1e-12:
@@ -216,7 +226,7 @@ def cold_history(p):
         k = p.bdf_order
         return dict(rho=[z() for _ in range(k)], phi=[z() for _ in range(2 * k)],
                     A=[z3() for _ in range(2 * k)])
-    if p.scheme == "cdf2":
+    if p.scheme in CDF2_FORMS:
         return dict(rho=[z() for _ in range(3)], phi=[z() for _ in range(3)],
                     A=[z3() for _ in range(2)], J=[z3() for _ in range(2)])
     return dict(rho=[z(), z()], phi=[z(), z()], vphi=z(), A=[z3(), z3()], vA=z3(), J=z3())
@@ -230,13 +240,15 @@ def field_update(p, hist, Jh, rho_h=None):
     """Continuity + wave update given J^{n+1} (spectral).  Returns (hist', phi~, A).
     rho_h: the deposited rho^{n+1} (spectral) of the naive comparison, used in
     place of continuity (BDF-k and DIRK-2)."""
-    if rho_h is not None and p.scheme == "cdf2":
+    if rho_h is not None and p.scheme in CDF2_FORMS:
         raise ValueError("the naive charge deposit needs BDF-k or DIRK-2")
     extra = () if rho_h is None else (rho_h,)
     if p.scheme == "bdf":
         return _bdf_update(p, hist, Jh, *extra)
     if p.scheme == "cdf2":
         return _cdf2_update(p, hist, Jh)
+    if p.scheme in CDF2_FORMS:
+        return _cdf2_other_update(p, hist, Jh)
     return _dirk2_update(p, hist, Jh, *extra)
 
 
@@ -276,6 +288,31 @@ def _cdf2_update(p, hist, Jh):
     phi_tilde = 0.5 * (phi_new + phi_h)                     # Sec. 4.1, staggered phi
     out = dict(rho=[rho_new, rho_h, rho_mh], phi=[phi_new, phi_h, phi_mh],
                A=[A_new, A_n], J=[Jh, hist["J"][0]])
+    return out, phi_tilde, A_new
+
+
+def _cdf2_other_update(p, hist, Jh):
+    # Sec. 3.1, semi-implicit and explicit forms: the wave equations take the
+    # sources at the middle level (rho^{n+1/2}, J^n); the semi-implicit form
+    # averages the Laplacian over n+1 and n-1 (the L solve of the implicit
+    # form with Gamma = 2 S^n), the explicit form takes it at level n (no solve)
+    rho_h, rho_mh = hist["rho"][0], hist["rho"][1]          # rho^{n+1/2}, rho^{n-1/2}
+    phi_h, phi_mh = hist["phi"][0], hist["phi"][1]          # phi^{n+1/2}, phi^{n-1/2}
+    A_n, A_m = hist["A"][0], hist["A"][1]                   # A^n, A^{n-1}
+    J_n = hist["J"][0]                                      # J^n
+    rho_new = rho_h - p.dt * div(p, Jh)                     # rho^{n+3/2}, continuity
+    if p.scheme == "cdf2_semi":
+        alpha2 = 2.0 / (p.c * p.dt) ** 2
+        Lh = 1.0 - p.lap / alpha2
+        phi_new = -phi_mh + (2.0 * phi_h + 2.0 * rho_h / (alpha2 * p.eps0)) / Lh
+        A_new = -A_m + (2.0 * A_n + 2.0 * p.mu0 * J_n / alpha2) / Lh
+    else:
+        c2dt2 = (p.c * p.dt) ** 2
+        phi_new = 2.0 * phi_h - phi_mh + c2dt2 * (p.lap * phi_h + rho_h / p.eps0)
+        A_new = 2.0 * A_n - A_m + c2dt2 * (p.lap * A_n + p.mu0 * J_n)
+    phi_tilde = 0.5 * (phi_new + phi_h)
+    out = dict(rho=[rho_new, rho_h, rho_mh], phi=[phi_new, phi_h, phi_mh],
+               A=[A_new, A_n], J=[Jh, J_n])
     return out, phi_tilde, A_new
 
 

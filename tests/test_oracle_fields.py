@@ -209,3 +209,39 @@ def test_dirk2_dispersion():
     np.testing.assert_allclose(out["vphi"][MODE[1], MODE[0]], 1j * om * z ** n, rtol=1e-11)
     np.testing.assert_allclose(out["A"][0][0][MODE[1], MODE[0]], z ** n, rtol=1e-11)
     assert abs(abs(z) - 1) < 1e-14
+
+
+@pytest.mark.parametrize("scheme", ["cdf2_semi", "cdf2_explicit"])
+def test_cdf2_other_forms_dispersion(scheme):
+    """Source free, the semi-implicit form is the implicit one's recursion,
+    L(u^{n+1} + u^{n-1}) = 2 u^n, so z + 1/z = 2/(1 + theta^2/2); the
+    explicit form is leapfrog, z + 1/z = 2 - theta^2 (|z| = 1 for theta <= 2,
+    the CFL bound of the explicit wave update)."""
+    p = _params(scheme, dt=0.05)
+    th = _theta(p)
+    assert th < 2.0
+    r = 1.0 / (1.0 + th * th / 2) if scheme == "cdf2_semi" else 1.0 - th * th / 2
+    z = r + 1j * np.sqrt(1 - r * r)
+    hist = pic.cold_history(p)
+    hist["phi"] = [_mode_field(p, z ** (-j)) for j in range(3)]
+    hist["A"] = [np.stack([_mode_field(p, z ** (-j))] * 3) for j in range(2)]
+    n = 100
+    out = _run(p, hist, n)
+    np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** n, rtol=1e-11)
+    np.testing.assert_allclose(out["A"][0][2][MODE[1], MODE[0]], z ** n, rtol=1e-11)
+    assert abs(abs(z) - 1) < 1e-15
+
+
+def test_cdf2_explicit_is_unstable_beyond_cfl():
+    """Above theta = 2 the leapfrog roots leave the unit circle: a single mode
+    grows like the larger root |z| = |r| + sqrt(r^2 - 1), r = 1 - theta^2/2."""
+    p = _params("cdf2_explicit", dt=0.09)
+    th = _theta(p)
+    r = 1.0 - th * th / 2
+    assert r < -1.0
+    z = r - np.sqrt(r * r - 1)                       # |z| > 1
+    hist = pic.cold_history(p)
+    hist["phi"] = [_mode_field(p, z ** (-j)) for j in range(3)]
+    hist["A"] = [np.stack([_mode_field(p, z ** (-j))] * 3) for j in range(2)]
+    out = _run(p, hist, 20)
+    np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** 20, rtol=1e-9)

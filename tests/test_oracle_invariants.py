@@ -3,6 +3,8 @@
 * Gauge residual at round-off every step: implicit CDF-2 (Sec. 3.1 theorem),
   BDF-k (Sec. 3.2 theorem), s-stage DIRK (Sec. 3.3 theorem, continuity implies
   gauge), given the cold start's zero initial residuals.
+* the semi-implicit and explicit CDF-2 forms (Sec. 3.1 theorems: gauge iff
+  continuity), with Gauss's law in each form's own levels;
 * Gauss's law at round-off for CDF-2 and BDF-k (Sec. 3.1 and 3.2 theorems);
   DIRK-2 is not expected to satisfy it (remark closing Sec. 3.3).
 * div B = 0 identically; total charge constant (k = 0 mode of continuity).
@@ -27,7 +29,8 @@ def _state(scheme, k=2, degree=2, c=1.0, nx=16, ny=16, ppc=4, seed=7):
     return pic.State(p, w["x"], w["y"], w["P"])
 
 
-CASES = [("bdf", 1, 2), ("bdf", 2, 3), ("bdf", 3, 2), ("cdf2", 2, 3), ("dirk2", 2, 2)]
+CASES = [("bdf", 1, 2), ("bdf", 2, 3), ("bdf", 3, 2), ("cdf2", 2, 3), ("cdf2_semi", 2, 2),
+         ("cdf2_explicit", 2, 3), ("dirk2", 2, 2)]
 
 
 @pytest.mark.parametrize("scheme,k,degree", CASES)
@@ -38,6 +41,9 @@ def test_gauge_and_gauss(scheme, k, degree, c):
     for _ in range(25):
         s.step()
         d = diagnostics.residuals(s)
+        if d["gauge_scale"] == 0.0:      # sources at the middle level: a quiet first step
+            assert d["gauge_l2"] == 0.0 and d["gauss_l2"] == 0.0
+            continue
         assert d["gauge_l2"] <= 1e3 * EPS * d["gauge_scale"], d
         assert d["divB_linf"] == 0.0
         assert abs(d["charge"]) <= 1e3 * EPS * d["gauss_scale"]
