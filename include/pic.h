@@ -66,7 +66,20 @@ typedef enum {
   PIC_ERR_NONFINITE = 6    /* pic_diagnostics found a NaN/Inf particle value   */
 } pic_status_t;
 
-typedef enum { PIC_SCHEME_BDF = 0, PIC_SCHEME_CDF2 = 1, PIC_SCHEME_DIRK2 = 2 } pic_scheme_t;
+/* PIC_SCHEME_CDF2 is the implicit centred-difference form of Sec. 3.1 (sources
+ * averaged over n+1 and n-1); PIC_SCHEME_CDF2_SEMI and PIC_SCHEME_CDF2_EXPLICIT
+ * are its semi-implicit and explicit forms (sources rho^{n+1/2}, J^n; the
+ * Laplacian averaged over n+1 and n-1, or at level n -- the explicit wave
+ * update is stable for c dt |k| <= 2 on every mode).  All three take
+ * rho^{n+3/2} from the staggered continuity equation with J^{n+1} and push
+ * with phi~ = (phi^{n+3/2} + phi^{n+1/2})/2; their history layout is the same. */
+typedef enum {
+  PIC_SCHEME_BDF = 0,
+  PIC_SCHEME_CDF2 = 1,
+  PIC_SCHEME_DIRK2 = 2,
+  PIC_SCHEME_CDF2_SEMI = 3,
+  PIC_SCHEME_CDF2_EXPLICIT = 4
+} pic_scheme_t;
 typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
 
 /* flags */

@@ -46,6 +46,15 @@ struct Hist {
   int nexport = 0;
 };
 
+// the three centred-difference forms share the CDF-2 family's history and
+// kernels; the form selects the wave update
+int scheme_family(int scheme) {
+  return scheme == PIC_SCHEME_CDF2_SEMI || scheme == PIC_SCHEME_CDF2_EXPLICIT ? PIC_SCHEME_CDF2 : scheme;
+}
+int cdf_form(int scheme) {
+  return scheme == PIC_SCHEME_CDF2_SEMI ? 1 : (scheme == PIC_SCHEME_CDF2_EXPLICIT ? 2 : 0);
+}
+
 Hist plan_history(const pic_config_t& c) {
   Hist h;
   int b = 0;
@@ -55,13 +64,14 @@ Hist plan_history(const pic_config_t& c) {
     r.width = width;
     b += size * width;
   };
-  if (c.scheme == PIC_SCHEME_BDF) {
+  const int family = scheme_family(c.scheme);
+  if (family == PIC_SCHEME_BDF) {
     const int k = c.bdf_order;
     mk(h.rho, k, 1);
     mk(h.phi, 2 * k, 1);
     mk(h.A, 2 * k, 3);
     h.nexport = k + 2 * k + 6 * k;
-  } else if (c.scheme == PIC_SCHEME_CDF2) {
+  } else if (family == PIC_SCHEME_CDF2) {
     mk(h.rho, 3, 1);
     mk(h.phi, 3, 1);
     mk(h.A, 2, 3);
@@ -107,7 +117,7 @@ bool validate(const pic_config_t* c, std::string& msg) {
     return false;
   }
   if (c->spline_degree < 1 || c->spline_degree > 3) { msg = "spline_degree must be 1, 2 or 3"; return false; }
-  if (c->scheme < PIC_SCHEME_BDF || c->scheme > PIC_SCHEME_DIRK2) { msg = "unknown scheme"; return false; }
+  if (c->scheme < PIC_SCHEME_BDF || c->scheme > PIC_SCHEME_CDF2_EXPLICIT) { msg = "unknown scheme"; return false; }
   if (c->scheme == PIC_SCHEME_BDF && (c->bdf_order < 1 || c->bdf_order > 6)) {
     msg = "bdf_order must be 1..6";
     return false;
@@ -259,7 +269,8 @@ void bdf_coefficients(int k, double* a) {
 
 SchemeCoef make_scheme(const pic_config_t& c) {
   SchemeCoef sc{};
-  sc.scheme = c.scheme;
+  sc.scheme = scheme_family(c.scheme);
+  sc.form = cdf_form(c.scheme);
   sc.k = c.scheme == PIC_SCHEME_BDF ? c.bdf_order : 0;
   sc.dt = c.dt;
   sc.c = c.c;
@@ -274,8 +285,8 @@ SchemeCoef make_scheme(const pic_config_t& c) {
     for (int i = 0; i <= 2 * sc.k; ++i) sc.Cn[i] = C[i] / C[0];
     const double alpha = sc.a[0] / (c.c * c.dt);
     sc.inv_alpha2 = 1.0 / (alpha * alpha);
-  } else if (c.scheme == PIC_SCHEME_CDF2) {
-    sc.inv_alpha2 = 0.5 * c.c * c.c * c.dt * c.dt;  // alpha = sqrt(2)/(c dt), Sec. 3.1
+  } else if (sc.scheme == PIC_SCHEME_CDF2) {
+    sc.inv_alpha2 = 0.5 * c.c * c.c * c.dt * c.dt;  // alpha = sqrt(2)/(c dt), Sec. 3.1 (explicit: c^2 dt^2 / 2)
   } else {
     // Qin-Zhang two-stage symplectic DIRK (the printed tableau in Sec. 5 is
     // garbled; this is the consistent second-order, |R(i theta)| = 1 scheme)
@@ -515,7 +526,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     }
   }
   if (cfgs[0].flags & PIC_FLAG_NAIVE_RHO) {
-    if (cfgs[0].scheme == PIC_SCHEME_CDF2) {
+    if (scheme_family(cfgs[0].scheme) == PIC_SCHEME_CDF2) {
       g_err = "the naive charge deposit needs BDF-k or DIRK-2 (CDF-2 needs rho at half levels)";
       return PIC_ERR_UNSUPPORTED;
     }
@@ -560,7 +571,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
   c->use_graphs = (cfgs[0].flags & PIC_FLAG_NO_GRAPH) == 0;
   c->dtype = cfgs[0].particle_dtype;
   c->degree = cfgs[0].spline_degree;
-  c->scheme = cfgs[0].scheme;
+  c->scheme = scheme_family(cfgs[0].scheme);
   // the naive charge deposit runs on the untiled passes
   c->sorted = (cfgs[0].flags & (PIC_FLAG_NO_SORT | PIC_FLAG_NAIVE_RHO)) == 0;
   c->d_desc = (InstDesc*)c->ws;
@@ -627,7 +638,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.R_c2r = rows_c2r_R(cf.nx, cf.ny);
     d.nb_col = columns_nb(cf.ny);
     // flattened block ranges
-    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * (3 + d.naive), (cf.nx / 2 + 1) * columns_parts(cf.scheme),
+    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * (3 + d.naive), (cf.nx / 2 + 1) * columns_parts(scheme_family(cf.scheme)),
                                cf.ny / d.R_c2r * 6, d.tp.max_work,
                                ceil_div(cf.max_particles, 256), ceil_div(cf.max_particles, 1024),
                                ceil_div(d.tp.ntiles, 4)};
@@ -637,7 +648,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     }
     c->lds_r2c = std::max(c->lds_r2c, rows_r2c_lds_bytes(cf.nx, cf.ny));
     c->lds_c2r = std::max(c->lds_c2r, rows_c2r_lds_bytes(cf.nx, cf.ny));
-    c->lds_col = std::max(c->lds_col, columns_parts(cf.scheme) > 1 ? columns_split_lds_bytes(cf.ny)
+    c->lds_col = std::max(c->lds_col, columns_parts(scheme_family(cf.scheme)) > 1 ? columns_split_lds_bytes(cf.ny)
                                                                     : columns_lds_bytes(cf.ny));
     if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, columns_lds_bytes(cf.ny));
     for (int mode = 0; mode < 3; ++mode)

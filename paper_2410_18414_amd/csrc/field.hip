@@ -330,9 +330,10 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
         h2[m] = at(hs.phi[0], ky);
         h3[m] = at(hs.phi[1], ky);
       } else {
+        // J^{n-1} for the implicit form's averaged source, J^n for the others
         h0[m] = at(hs.A[0] + c0, ky);
         h1[m] = at(hs.A[1] + c0, ky);
-        h2[m] = at(hs.J[1] + c0, ky);
+        h2[m] = at(hs.J[sc.form == 0 ? 1 : 0] + c0, ky);
       }
     }
   }
@@ -358,9 +359,21 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
         at(hs.phi_new, ky) = phi;
         out = phi;
       } else {
-        const double2 rho = csub(h0[m], cscale(divJ, sc.dt));  // rho^{n+3/2}
-        const double2 rhs = cadd(cscale(h2[m], 2.0), cscale(cadd(rho, h1[m]), sc.inv_alpha2 / sc.eps0));
-        const double2 phi = csub(cdivr(rhs, Lh), h3[m]);
+        // rho^{n+3/2} from the staggered continuity equation; h0..h3 =
+        // rho^{n+1/2}, rho^{n-1/2}, phi^{n+1/2}, phi^{n-1/2}
+        const double2 rho = csub(h0[m], cscale(divJ, sc.dt));
+        double2 phi;
+        if (sc.form == 0) {  // implicit: sources averaged over n+3/2 and n-1/2
+          const double2 rhs = cadd(cscale(h2[m], 2.0), cscale(cadd(rho, h1[m]), sc.inv_alpha2 / sc.eps0));
+          phi = csub(cdivr(rhs, Lh), h3[m]);
+        } else if (sc.form == 1) {  // semi-implicit: source rho^{n+1/2}
+          const double2 rhs = cadd(cscale(h2[m], 2.0), cscale(h0[m], 2.0 * sc.inv_alpha2 / sc.eps0));
+          phi = csub(cdivr(rhs, Lh), h3[m]);
+        } else {  // explicit: 2 phi - phi_old + c^2 dt^2 (Lap phi + rho/eps0), c^2 dt^2 = 2/alpha^2
+          const double kap = kxs * kxs + kys * kys;
+          phi = cadd(csub(cscale(h2[m], 2.0), h3[m]),
+                     cscale(csub(cscale(h0[m], 1.0 / sc.eps0), cscale(h2[m], kap)), 2.0 * sc.inv_alpha2));
+        }
         at(hs.rho_new, ky) = rho;
         at(hs.phi_new, ky) = phi;
         out = cscale(cadd(phi, h2[m]), 0.5);
@@ -372,8 +385,19 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
         at(hs.A_new + c0, ky) = A;
         out = A;
       } else {
-        const double2 r = cadd(cscale(h0[m], 2.0), cscale(cadd(Jl, h2[m]), sc.mu0 * sc.inv_alpha2));
-        const double2 A = csub(cdivr(r, Lh), h1[m]);
+        // h0, h1, h2 = A^n, A^{n-1}, and J^{n-1} (implicit) or J^n
+        double2 A;
+        if (sc.form == 0) {
+          const double2 r = cadd(cscale(h0[m], 2.0), cscale(cadd(Jl, h2[m]), sc.mu0 * sc.inv_alpha2));
+          A = csub(cdivr(r, Lh), h1[m]);
+        } else if (sc.form == 1) {
+          const double2 r = cadd(cscale(h0[m], 2.0), cscale(h2[m], 2.0 * sc.mu0 * sc.inv_alpha2));
+          A = csub(cdivr(r, Lh), h1[m]);
+        } else {
+          const double kap = kxs * kxs + kys * kys;
+          A = cadd(csub(cscale(h0[m], 2.0), h1[m]),
+                   cscale(csub(cscale(h2[m], sc.mu0), cscale(h0[m], kap)), 2.0 * sc.inv_alpha2));
+        }
         at(hs.A_new + c0, ky) = A;
         at(hs.J_new + c0, ky) = Jl;
         out = A;
@@ -511,8 +535,11 @@ __global__ void __launch_bounds__(1024) k_field_diag(const double2* __restrict__
     } else if (SCHEME == PIC_SCHEME_CDF2) {
       gt = cscale(csub(at(hs.phi[0], m), at(hs.phi[1], m)), 1.0 / (sc.c * sc.c * sc.dt));
       gd = divA(hs.A[0]);
-      phi = cscale(cadd(at(hs.phi[0], m), at(hs.phi[2], m)), 0.5);
-      rho = cscale(cadd(at(hs.rho[0], m), at(hs.rho[2], m)), 0.5);
+      // Gauss in each form's levels: phi averaged over n+3/2 and n-1/2
+      // (explicit: phi^{n+1/2}); rho averaged the same way (implicit) or
+      // rho^{n+1/2} (semi-implicit, explicit)
+      phi = sc.form == 2 ? at(hs.phi[1], m) : cscale(cadd(at(hs.phi[0], m), at(hs.phi[2], m)), 0.5);
+      rho = sc.form == 0 ? cscale(cadd(at(hs.rho[0], m), at(hs.rho[2], m)), 0.5) : at(hs.rho[1], m);
       double2 dA[3];
       for (int l = 0; l < 3; ++l) {
         dA[l] = cscale(csub(at(hs.A[0] + l, m), at(hs.A[1] + l, m)), 1.0 / sc.dt);

@@ -68,7 +68,7 @@ def hist_to_flat(p, hist):
     if p.scheme == "dirk2":
         out += [hist["vA"][0], hist["vA"][1], hist["vA"][2]]
         out += [hist["J"][0], hist["J"][1], hist["J"][2]]
-    if p.scheme == "cdf2":
+    if p.scheme in ("cdf2", "cdf2_semi", "cdf2_explicit"):
         for J in hist["J"]:
             out += [J[0], J[1], J[2]]
     return np.stack(out)

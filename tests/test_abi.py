@@ -51,7 +51,13 @@ def test_valid_config_and_history_counts():
     assert pic.history_fields(_cfg(scheme="bdf", bdf_order=2)) == 18
     assert pic.history_fields(_cfg(scheme="bdf", bdf_order=3)) == 27
     assert pic.history_fields(_cfg(scheme="cdf2")) == 18
+    assert pic.history_fields(_cfg(scheme="cdf2_semi")) == 18
+    assert pic.history_fields(_cfg(scheme="cdf2_explicit")) == 18
     assert pic.history_fields(_cfg(scheme="dirk2")) == 17
+    cfg = _cfg()
+    cfg.scheme = 5                       # no such scheme
+    assert pic.load().pic_workspace_bytes(ctypes.byref(cfg)) == 0
+    assert b"scheme" in pic.load().pic_last_error(None)
 
 
 def test_create_rejects_bad_workspace_without_gpu():
