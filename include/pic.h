@@ -78,7 +78,13 @@ typedef enum {
   PIC_SCHEME_CDF2 = 1,
   PIC_SCHEME_DIRK2 = 2,
   PIC_SCHEME_CDF2_SEMI = 3,
-  PIC_SCHEME_CDF2_EXPLICIT = 4
+  PIC_SCHEME_CDF2_EXPLICIT = 4,
+  /* three-stage DIRK (Sec. 3.3, s = 3): implicit-midpoint substeps of lengths
+   * b_i dt composed in sequence (a_ij = b_j for j < i, a_ii = b_i/2), with the
+   * fourth-order weights b_1 = b_3 = 1/(2 - 2^{1/3}), b_2 = 1 - 2 b_1; the
+   * composition with b = (1/2, 1/2) is DIRK-2's tableau.  Same history layout
+   * as PIC_SCHEME_DIRK2. */
+  PIC_SCHEME_DIRK3 = 5
 } pic_scheme_t;
 typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
 

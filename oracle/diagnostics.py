@@ -62,7 +62,7 @@ def residuals(state):
         Eh = np.stack([-ikx * phim - dA[0], -iky * phim - dA[1], -dA[2]])
         Ah = 0.5 * (h["A"][0] + h["A"][1])
     else:
-        b, cc = schemes.DIRK2_B, schemes.DIRK2_C
+        _, b, cc = schemes.dirk_tableau(p.scheme)
         Rn, Rn1 = float(np.sum(b * (1 - cc))), float(np.sum(b * cc))
         gauge_t = -(h["phi"][0] - h["phi"][1])
         gauge_d = -p.c ** 2 * p.dt * (Rn * divA(h["A"][1]) + Rn1 * divA(h["A"][0]))

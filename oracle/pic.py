@@ -60,12 +60,15 @@ FIELD_NAMES = ("dphi_dx", "dphi_dy", "Ax", "Ay", "Az",
 
 # the staggered centred-difference schemes of Sec. 3.1
 CDF2_FORMS = ("cdf2", "cdf2_semi", "cdf2_explicit")
+# the DIRK schemes of Sec. 3.3: the two-stage Qin-Zhang tableau and the
+# three-stage fourth-order composition (schemes.dirk_tableau)
+DIRK_FORMS = ("dirk2", "dirk3")
 
 
 class Params:
     def __init__(self, nx, ny, lx, ly, degree, scheme, dt, c=1.0, eps0=1.0,
                  mu0=1.0, q=-1.0, m=1.0, bdf_order=2, naive=False):
-        if scheme not in ("bdf",) + CDF2_FORMS + ("dirk2",):
+        if scheme not in ("bdf",) + CDF2_FORMS + DIRK_FORMS:
             raise ValueError(scheme)
         if naive and scheme in CDF2_FORMS:
             raise ValueError("the naive charge deposit needs BDF-k or DIRK-2")
@@ -249,7 +252,7 @@ def field_update(p, hist, Jh, rho_h=None):
         return _cdf2_update(p, hist, Jh)
     if p.scheme in CDF2_FORMS:
         return _cdf2_other_update(p, hist, Jh)
-    return _dirk2_update(p, hist, Jh, *extra)
+    return _dirk_update(p, hist, Jh, *extra)
 
 
 def _bdf_update(p, hist, Jh, rho_h=None):
@@ -316,9 +319,9 @@ def _cdf2_other_update(p, hist, Jh):
     return out, phi_tilde, A_new
 
 
-def _dirk2_update(p, hist, Jh, rho_h=None):
+def _dirk_update(p, hist, Jh, rho_h=None):
     # Sec. 3.3: s-stage DIRK on (u, v) with u' = v, v' = c^2 (S + Lap u)
-    A_t, b, cc = schemes.DIRK2_A, schemes.DIRK2_B, schemes.DIRK2_C
+    A_t, b, cc = schemes.dirk_tableau(p.scheme)
     s = len(b)
     h, c2, lap = p.dt, p.c ** 2, p.lap
     J_n = hist["J"]

@@ -61,3 +61,28 @@ def bdf_C_exact(k):
 DIRK2_A = np.array([[0.25, 0.0], [0.5, 0.25]])
 DIRK2_B = np.array([0.5, 0.5])
 DIRK2_C = np.array([0.25, 0.75])
+
+
+def dirk_composed(b):
+    """The s-stage DIRK that composes s implicit-midpoint substeps of lengths
+    b_i h in sequence: a_ij = b_j for j < i, a_ii = b_i / 2, c_i = sum_j a_ij.
+    Symplectic for any weights; b = (1/2, 1/2) is the Qin-Zhang tableau above."""
+    b = np.asarray(b, np.float64)
+    s = len(b)
+    A = np.zeros((s, s))
+    for i in range(s):
+        A[i, :i] = b[:i]
+        A[i, i] = 0.5 * b[i]
+    return A, b, A.sum(1)
+
+
+# DIRK-3 (general s-stage DIRK of Sec. 3.3 with s = 3): the composition with
+# the symmetric fourth-order "triple jump" weights b_1 = b_3 = 1/(2 - 2^{1/3}),
+# b_2 = 1 - 2 b_1 (Yoshida's construction); stability function
+# prod_i (1 + b_i z/2)/(1 - b_i z/2), modulus one on the imaginary axis.
+_W1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+DIRK3_A, DIRK3_B, DIRK3_C = dirk_composed([_W1, 1.0 - 2.0 * _W1, _W1])
+
+
+def dirk_tableau(scheme):
+    return (DIRK2_A, DIRK2_B, DIRK2_C) if scheme == "dirk2" else (DIRK3_A, DIRK3_B, DIRK3_C)

@@ -49,7 +49,8 @@ struct Hist {
 // the three centred-difference forms share the CDF-2 family's history and
 // kernels; the form selects the wave update
 int scheme_family(int scheme) {
-  return scheme == PIC_SCHEME_CDF2_SEMI || scheme == PIC_SCHEME_CDF2_EXPLICIT ? PIC_SCHEME_CDF2 : scheme;
+  if (scheme == PIC_SCHEME_CDF2_SEMI || scheme == PIC_SCHEME_CDF2_EXPLICIT) return PIC_SCHEME_CDF2;
+  return scheme == PIC_SCHEME_DIRK3 ? PIC_SCHEME_DIRK2 : scheme;  // every DIRK shares one layout
 }
 int cdf_form(int scheme) {
   return scheme == PIC_SCHEME_CDF2_SEMI ? 1 : (scheme == PIC_SCHEME_CDF2_EXPLICIT ? 2 : 0);
@@ -117,7 +118,7 @@ bool validate(const pic_config_t* c, std::string& msg) {
     return false;
   }
   if (c->spline_degree < 1 || c->spline_degree > 3) { msg = "spline_degree must be 1, 2 or 3"; return false; }
-  if (c->scheme < PIC_SCHEME_BDF || c->scheme > PIC_SCHEME_CDF2_EXPLICIT) { msg = "unknown scheme"; return false; }
+  if (c->scheme < PIC_SCHEME_BDF || c->scheme > PIC_SCHEME_DIRK3) { msg = "unknown scheme"; return false; }
   if (c->scheme == PIC_SCHEME_BDF && (c->bdf_order < 1 || c->bdf_order > 6)) {
     msg = "bdf_order must be 1..6";
     return false;
@@ -288,15 +289,29 @@ SchemeCoef make_scheme(const pic_config_t& c) {
   } else if (sc.scheme == PIC_SCHEME_CDF2) {
     sc.inv_alpha2 = 0.5 * c.c * c.c * c.dt * c.dt;  // alpha = sqrt(2)/(c dt), Sec. 3.1 (explicit: c^2 dt^2 / 2)
   } else {
-    // Qin-Zhang two-stage symplectic DIRK (the printed tableau in Sec. 5 is
-    // garbled; this is the consistent second-order, |R(i theta)| = 1 scheme)
-    sc.dirkA[0][0] = 0.25;
-    sc.dirkA[0][1] = 0.0;
-    sc.dirkA[1][0] = 0.5;
-    sc.dirkA[1][1] = 0.25;
-    sc.dirkB[0] = sc.dirkB[1] = 0.5;
-    sc.dirkC[0] = 0.25;
-    sc.dirkC[1] = 0.75;
+    // DIRK as a composition of implicit-midpoint substeps of lengths b_i dt:
+    // a_ij = b_j (j < i), a_ii = b_i / 2, c_i = sum_j a_ij.  Two stages with
+    // b = (1/2, 1/2) give the Qin-Zhang symplectic DIRK-2 (the printed
+    // tableau in Sec. 5 is garbled; this is the consistent second-order,
+    // |R(i theta)| = 1 scheme); three with the symmetric fourth-order weights
+    // give DIRK-3.
+    double b[3];
+    if (c.scheme == PIC_SCHEME_DIRK3) {
+      sc.stages = 3;
+      b[0] = b[2] = 1.0 / (2.0 - std::cbrt(2.0));
+      b[1] = 1.0 - 2.0 * b[0];
+    } else {
+      sc.stages = 2;
+      b[0] = b[1] = 0.5;
+    }
+    for (int i = 0; i < sc.stages; ++i) {
+      sc.dirkB[i] = b[i];
+      sc.dirkC[i] = 0.0;
+      for (int j = 0; j < sc.stages; ++j) {
+        sc.dirkA[i][j] = j < i ? b[j] : (j == i ? 0.5 * b[i] : 0.0);
+        sc.dirkC[i] += sc.dirkA[i][j];
+      }
+    }
   }
   return sc;
 }

@@ -137,11 +137,12 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
       at(hs.J_new + l) = Jn1[l];
       o.A[l] = A;
     }
-  } else {  // DIRK-2
+  } else {  // DIRK (sc.stages = 2 or 3 stages)
     const double h = sc.dt, c2 = sc.c * sc.c;
-    double2 Jn[3], Jst[2][3];
+    const int ns = sc.stages;
+    double2 Jn[3], Jst[3][3];
     for (int l = 0; l < 3; ++l) Jn[l] = at(hs.J[0] + l);
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < ns; ++i)
       for (int l = 0; l < 3; ++l)
         Jst[i][l] = cadd(cscale(Jn[l], 1.0 - sc.dirkC[i]), cscale(Jn1[l], sc.dirkC[i]));
     const double2 rho_n = at(hs.rho[0]);
@@ -149,13 +150,13 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
     if (rho_dep)
       rho = *rho_dep;  // naive comparison: the deposited rho^{n+1}
     else
-      for (int i = 0; i < 2; ++i) rho = csub(rho, cscale(divv(Jst[i][0], Jst[i][1]), h * sc.dirkB[i]));
-    double2 rst[2];
-    for (int i = 0; i < 2; ++i) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
+      for (int i = 0; i < ns; ++i) rho = csub(rho, cscale(divv(Jst[i][0], Jst[i][1]), h * sc.dirkB[i]));
+    double2 rst[3];
+    for (int i = 0; i < ns; ++i) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
     // one scalar wave component: (u, v)' = (v, c^2 (S + Lap u)), Lap = -kappa
-    auto advance = [&](double2& u, double2& v, const double2 S[2]) {
-      double2 ku[2], kv[2];
-      for (int i = 0; i < 2; ++i) {
+    auto advance = [&](double2& u, double2& v, const double2* S) {
+      double2 ku[3], kv[3];
+      for (int i = 0; i < ns; ++i) {
         double2 U = u, V = v;
         for (int j = 0; j < i; ++j) {
           U = cadd(U, cscale(ku[j], h * sc.dirkA[i][j]));
@@ -167,14 +168,15 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
         ku[i] = cdivr(cadd(V, cscale(src, hai * c2)), Li);
         kv[i] = cdivr(csub(cscale(src, c2), cscale(V, hai * c2 * kappa)), Li);
       }
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < ns; ++i) {
         u = cadd(u, cscale(ku[i], h * sc.dirkB[i]));
         v = cadd(v, cscale(kv[i], h * sc.dirkB[i]));
       }
     };
     double2 u = at(hs.phi[0]), v = at(hs.vphi);
     {
-      const double2 S[2] = {cscale(rst[0], 1.0 / sc.eps0), cscale(rst[1], 1.0 / sc.eps0)};
+      double2 S[3];
+      for (int i = 0; i < ns; ++i) S[i] = cscale(rst[i], 1.0 / sc.eps0);
       advance(u, v, S);
     }
     at(hs.rho_new) = rho;
@@ -183,7 +185,8 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
     o.phi = u;
     for (int l = 0; l < 3; ++l) {
       double2 ua = at(hs.A[0] + l), va = at(hs.vA + l);
-      const double2 S[2] = {cscale(Jst[0][l], sc.mu0), cscale(Jst[1][l], sc.mu0)};
+      double2 S[3];
+      for (int i = 0; i < ns; ++i) S[i] = cscale(Jst[i][l], sc.mu0);
       advance(ua, va, S);
       at(hs.A_new + l) = ua;
       at(hs.vA + l) = va;
@@ -264,7 +267,7 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
 // part inverse-transforms its two outputs (phi~ and d_y phi~, or A_l and
 // d_y A_l).  The history terms of the update do not depend on J^{n+1}: they
 // are loaded and summed before the forward transform, so their loads overlap
-// it.  (DIRK-2 keeps the one-block-per-kx kernel: its single J history slot
+// it.  (DIRK keeps the one-block-per-kx kernel: its single J history slot
 // is read by every component's update and overwritten by each.)
 constexpr int kColParts = 4;
 constexpr int kColMaxModes = 4;  // modes per thread: ny <= 1024 with 256 threads
@@ -549,8 +552,11 @@ __global__ void __launch_bounds__(1024) k_field_diag(const double2* __restrict__
       E[1] = csub(mul_i(cscale(phi, -kys)), dA[1]);
       E[2] = cscale(dA[2], -1.0);
     } else {
-      const double Rn = sc.dirkB[0] * (1 - sc.dirkC[0]) + sc.dirkB[1] * (1 - sc.dirkC[1]);
-      const double Rn1 = sc.dirkB[0] * sc.dirkC[0] + sc.dirkB[1] * sc.dirkC[1];
+      double Rn = 0.0, Rn1 = 0.0;  // R^{s,n} = sum b_i (1 - c_i), R^{s,n+1} = sum b_i c_i
+      for (int i = 0; i < sc.stages; ++i) {
+        Rn += sc.dirkB[i] * (1 - sc.dirkC[i]);
+        Rn1 += sc.dirkB[i] * sc.dirkC[i];
+      }
       gt = cscale(csub(at(hs.phi[0], m), at(hs.phi[1], m)), -1.0);
       gd = cscale(cadd(cscale(divA(hs.A[1]), Rn), cscale(divA(hs.A[0]), Rn1)), -sc.c * sc.c * sc.dt);
       phi = at(hs.phi[0], m);

@@ -80,12 +80,13 @@ struct TileBufs {
 };
 
 struct SchemeCoef {
-  int scheme, k;            // scheme family (BDF, CDF2, DIRK2); BDF order
+  int scheme, k;            // scheme family (BDF, CDF2, DIRK2 = every DIRK); BDF order
   int form;                 // CDF2 family: 0 implicit, 1 semi-implicit, 2 explicit
   double a[7];              // BDF first-derivative coefficients (step dt)
   double Cn[13];            // C_i / C_0 of the twice-applied operator
   double inv_alpha2;        // 1/alpha^2 of the single Helmholtz solve (BDF, CDF-2)
-  double dirkA[2][2], dirkB[2], dirkC[2];
+  int stages;               // DIRK family: 2 or 3
+  double dirkA[3][3], dirkB[3], dirkC[3];
   double dt, c, eps0, mu0;
 };
 

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpic.so")
 
 PIC_ABI_VERSION = 1
-SCHEMES = {"bdf": 0, "cdf2": 1, "dirk2": 2, "cdf2_semi": 3, "cdf2_explicit": 4}
+SCHEMES = {"bdf": 0, "cdf2": 1, "dirk2": 2, "cdf2_semi": 3, "cdf2_explicit": 4, "dirk3": 5}
 DTYPES = {"f32": 0, "f64": 1}
 FLAG_NO_SORT = 1
 FLAG_UNFUSED_STEP = 2

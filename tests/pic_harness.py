@@ -61,11 +61,11 @@ def hist_to_flat(p, hist):
     out = []
     out += list(hist["rho"])
     out += list(hist["phi"])
-    if p.scheme == "dirk2":
+    if p.scheme in ("dirk2", "dirk3"):
         out.append(hist["vphi"])
     for A in hist["A"]:
         out += [A[0], A[1], A[2]]
-    if p.scheme == "dirk2":
+    if p.scheme in ("dirk2", "dirk3"):
         out += [hist["vA"][0], hist["vA"][1], hist["vA"][2]]
         out += [hist["J"][0], hist["J"][1], hist["J"][2]]
     if p.scheme in ("cdf2", "cdf2_semi", "cdf2_explicit"):

@@ -54,8 +54,9 @@ def test_valid_config_and_history_counts():
     assert pic.history_fields(_cfg(scheme="cdf2_semi")) == 18
     assert pic.history_fields(_cfg(scheme="cdf2_explicit")) == 18
     assert pic.history_fields(_cfg(scheme="dirk2")) == 17
+    assert pic.history_fields(_cfg(scheme="dirk3")) == 17
     cfg = _cfg()
-    cfg.scheme = 5                       # no such scheme
+    cfg.scheme = 6                       # no such scheme
     assert pic.load().pic_workspace_bytes(ctypes.byref(cfg)) == 0
     assert b"scheme" in pic.load().pic_last_error(None)
 

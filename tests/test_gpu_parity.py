@@ -266,7 +266,7 @@ def test_full_size_weibel_one_step_f32(gpu_lib):
     assert d["gauge_l2"] <= 1e3 * EPS * d["gauge_scale"]
 
 
-@pytest.mark.parametrize("scheme,k", [("bdf", 2), ("cdf2", 2), ("dirk2", 2)])
+@pytest.mark.parametrize("scheme,k", [("bdf", 2), ("cdf2", 2), ("dirk2", 2), ("dirk3", 2)])
 def test_graph_replay_matches_oracle_and_direct(gpu_lib, scheme, k):
     """step() replays captured HIP graphs for long calls; results are those of
     direct launches and of the oracle."""

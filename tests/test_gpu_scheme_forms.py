@@ -1,10 +1,11 @@
-"""The semi-implicit and explicit CDF-2 forms (Sec. 3.1) on the GPU against the
-oracle (needs an MI355X).
+"""The semi-implicit and explicit CDF-2 forms (Sec. 3.1) and the three-stage DIRK
+(Sec. 3.3, s = 3) on the GPU against the oracle (needs an MI355X).
 
 Trajectories through step() (graph replay included) against the oracle at
 1e-10 (float64) and 1e-4 (float32): particle state and the spectral history;
-the gauge residual and Gauss's law at round-off (the Sec. 3.1 theorems for
-these forms; Gauss in each form's own levels) and equal to the oracle's.
+the gauge residual at round-off (the Sec. 3.1 and 3.3 theorems), Gauss's law
+at round-off for the CDF-2 forms (in each form's own levels; the DIRK remark
+closing Sec. 3.3 does not promise it), and equal to the oracle's.
 The explicit form runs at dt = 0.4 dx / c, inside its CFL bound on every
 mode of the grid.
 """
@@ -20,9 +21,9 @@ pytestmark = pytest.mark.gpu
 EPS = np.finfo(float).eps
 
 
-@pytest.mark.parametrize("scheme", ["cdf2_semi", "cdf2_explicit"])
+@pytest.mark.parametrize("scheme", ["cdf2_semi", "cdf2_explicit", "dirk3"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_cdf2_form_trajectory(gpu_lib, scheme, dtype):
+def test_scheme_form_trajectory(gpu_lib, scheme, dtype):
     w = workloads.weibel(nx=32, ny=64, ppc=5, seed=71, drift=0.1)
     w = dict(w, dt=0.8 * w["dt"])
     o = make_oracle(w, 3, scheme)
@@ -37,7 +38,9 @@ def test_cdf2_form_trajectory(gpu_lib, scheme, dtype):
     dg, do = pic.diagnostics(g), odiag.residuals(o)
     if dtype == "f64":
         assert dg["gauge_l2"] <= 1e3 * EPS * dg["gauge_scale"], dg
-        assert dg["gauss_l2"] <= 1e3 * EPS * dg["gauss_scale"], dg
+        if scheme != "dirk3":
+            assert dg["gauss_l2"] <= 1e3 * EPS * dg["gauss_scale"], dg
+        assert rel(dg["gauss_l2"], do["gauss_l2"]) <= 1e-8 or dg["gauss_l2"] <= 1e3 * EPS * dg["gauss_scale"]
         assert rel(dg["energy"], do["energy"]) <= 1e-10
         assert rel(dg["gauss_scale"], do["gauss_scale"]) <= 1e-10
     g.close()

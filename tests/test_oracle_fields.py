@@ -245,3 +245,44 @@ def test_cdf2_explicit_is_unstable_beyond_cfl():
     hist["A"] = [np.stack([_mode_field(p, z ** (-j))] * 3) for j in range(2)]
     out = _run(p, hist, 20)
     np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** 20, rtol=1e-9)
+
+
+def test_dirk_composition_tableaux():
+    """The composition of implicit-midpoint substeps reproduces the Qin-Zhang
+    tableau for b = (1/2, 1/2); the three-stage triple-jump composition has
+    order four (stability function vs exp, a Taylor check) and modulus one on
+    the imaginary axis, and satisfies the symplecticity condition
+    b_i a_ij + b_j a_ji - b_i b_j = 0."""
+    A, b, c = schemes.dirk_composed([0.5, 0.5])
+    np.testing.assert_array_equal(A, schemes.DIRK2_A)
+    np.testing.assert_array_equal(c, schemes.DIRK2_C)
+    A3, b3, c3 = schemes.DIRK3_A, schemes.DIRK3_B, schemes.DIRK3_C
+    assert abs(b3.sum() - 1.0) < 1e-15
+    M = b3[:, None] * A3 + (b3[:, None] * A3).T - np.outer(b3, b3)
+    np.testing.assert_allclose(M, 0, atol=1e-14)
+
+    def R(z):   # R(z) = 1 + z b^T (I - z A)^{-1} 1
+        return 1.0 + z * b3 @ np.linalg.solve(np.eye(3) - z * A3, np.ones(3))
+    for th in (0.3, 1.0, 3.0):
+        assert abs(abs(R(1j * th)) - 1.0) < 1e-13
+    # order 4: the error of R against exp scales as z^5
+    e1, e2 = abs(R(0.02) - np.exp(0.02)), abs(R(0.01) - np.exp(0.01))
+    assert 25.0 < e1 / e2 < 40.0        # 2^5 = 32
+
+
+def test_dirk3_dispersion():
+    p = _params("dirk3")
+    th = _theta(p)
+    om = th / p.dt
+    z = np.prod([(1 + 0.5j * bi * th) / (1 - 0.5j * bi * th) for bi in schemes.DIRK3_B])
+    hist = pic.cold_history(p)
+    hist["phi"] = [_mode_field(p, 1.0), _mode_field(p, 0.0)]
+    hist["vphi"] = _mode_field(p, 1j * om)
+    hist["A"] = [np.stack([_mode_field(p, 1.0)] * 3), np.zeros((3,) + p.spec_shape, complex)]
+    hist["vA"] = np.stack([_mode_field(p, 1j * om)] * 3)
+    n = 100
+    out = _run(p, hist, n)
+    np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** n, rtol=1e-10)
+    np.testing.assert_allclose(out["vphi"][MODE[1], MODE[0]], 1j * om * z ** n, rtol=1e-10)
+    np.testing.assert_allclose(out["A"][0][0][MODE[1], MODE[0]], z ** n, rtol=1e-10)
+    assert abs(abs(z) - 1) < 1e-14

@@ -61,7 +61,7 @@ def test_wrong_bdf_alpha_fails_dispersion(monkeypatch):
 
 def test_missing_c2_in_dirk_kv_fails_dispersion(monkeypatch):
     """The c^2 the specialised DIRK stage equations drop is caught with c != 1."""
-    src = pic._dirk2_update
+    src = pic._dirk_update
 
     def patched(p, hist, Jh):
         # the same update with k^v's source term lacking c^2, i.e. c2 -> 1 there
@@ -87,6 +87,6 @@ def test_missing_c2_in_dirk_kv_fails_dispersion(monkeypatch):
         return (dict(rho=hist["rho"], phi=[phi, hist["phi"][0]], vphi=vphi,
                      A=[A, hist["A"][0]], vA=vA, J=Jh), phi, A)
     assert src is not None
-    monkeypatch.setattr(pic, "_dirk2_update", patched)
+    monkeypatch.setattr(pic, "_dirk_update", patched)
     with pytest.raises(AssertionError):
         F.test_dirk2_dispersion()
