@@ -123,8 +123,8 @@ def deposit_current(p, x, y, v):
     n = p.nx * p.ny
     J = np.zeros((3, n))
     qv = p.q * v
-    for a in range(4):
-        for b in range(4):
+    for a in range(gx.shape[1]):
+        for b in range(gy.shape[1]):
             idx = (gy[:, b] % p.ny) * p.nx + (gx[:, a] % p.nx)
             w = wx[:, a] * wy[:, b] / (p.dx * p.dy)
             for c in range(3):
@@ -199,8 +199,8 @@ def gather(p, fields, x, y):
     gy, wy = bspline.stencil(p.degree, y / p.dy)
     F = fields.reshape(fields.shape[0], -1)
     out = np.zeros((x.shape[0], fields.shape[0]))
-    for a in range(4):
-        for b in range(4):
+    for a in range(gx.shape[1]):
+        for b in range(gy.shape[1]):
             idx = (gy[:, b] % p.ny) * p.nx + (gx[:, a] % p.nx)
             out += (wx[:, a] * wy[:, b])[:, None] * F[:, idx].T
     return out

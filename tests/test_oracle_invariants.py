@@ -32,7 +32,7 @@ def _state(scheme, k=2, degree=2, c=1.0, nx=16, ny=16, ppc=4, seed=7):
 
 
 CASES = [("bdf", 1, 2), ("bdf", 2, 3), ("bdf", 3, 2), ("cdf2", 2, 3), ("cdf2_semi", 2, 2),
-         ("cdf2_explicit", 2, 3), ("dirk2", 2, 2), ("dirk3", 2, 3)]
+         ("cdf2_explicit", 2, 3), ("dirk2", 2, 2), ("dirk3", 2, 3), ("bdf", 2, 4), ("cdf2", 2, 5)]
 
 
 @pytest.mark.parametrize("scheme,k,degree", CASES)
