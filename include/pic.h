@@ -105,7 +105,8 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
 typedef struct {                /* [host] */
   int32_t abi_version;          /* == PIC_ABI_VERSION                                    */
   int32_t nx, ny;               /* mesh nodes per axis: powers of two, 8 .. 1024          */
-  int32_t spline_degree;        /* 1 (linear), 2 (quadratic, the paper's), 3 (cubic)      */
+  int32_t spline_degree;        /* 1 (linear), 2 (quadratic, the paper's), 3 (cubic),
+                                   4, 5 (quartic, quintic; not with the adjoint)         */
   double lx, ly;                /* periodic box [0,lx) x [0,ly)                          */
   int32_t scheme;               /* pic_scheme_t                                          */
   int32_t bdf_order;            /* BDF-k order 1..6 (Sec. 3.2), used when scheme == BDF  */

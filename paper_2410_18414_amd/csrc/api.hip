@@ -117,7 +117,7 @@ bool validate(const pic_config_t* c, std::string& msg) {
     msg = "lx, ly must be positive and finite";
     return false;
   }
-  if (c->spline_degree < 1 || c->spline_degree > 3) { msg = "spline_degree must be 1, 2 or 3"; return false; }
+  if (c->spline_degree < 1 || c->spline_degree > 5) { msg = "spline_degree must be 1..5"; return false; }
   if (c->scheme < PIC_SCHEME_BDF || c->scheme > PIC_SCHEME_DIRK3) { msg = "unknown scheme"; return false; }
   if (c->scheme == PIC_SCHEME_BDF && (c->bdf_order < 1 || c->bdf_order > 6)) {
     msg = "bdf_order must be 1..6";
@@ -1106,8 +1106,9 @@ static pic_status_t adjoint_check(pic_ctx_t c, bool need_ready) {
   if (c->ninst() != 1) return c->fail(PIC_ERR_UNSUPPORTED, "the adjoint runs on single-instance contexts");
   if (!(c->I().cfg.flags & PIC_FLAG_ADJOINT))
     return c->fail(PIC_ERR_UNSUPPORTED, "the adjoint needs a context created with PIC_FLAG_ADJOINT");
-  if (c->dtype != PIC_F64 || c->scheme != PIC_SCHEME_BDF)
-    return c->fail(PIC_ERR_UNSUPPORTED, "the adjoint supports float64 particles and the BDF-k stepper");
+  if (c->dtype != PIC_F64 || c->scheme != PIC_SCHEME_BDF || c->degree > 3)
+    return c->fail(PIC_ERR_UNSUPPORTED,
+                   "the adjoint supports float64 particles, the BDF-k stepper and spline degrees 1..3");
   if (need_ready && c->phase != READY) return c->fail(PIC_ERR_STATE, "adjoint_seed_energy and step_adjoint need phase READY");
   if (c->phase == EMPTY) return c->fail(PIC_ERR_STATE, "no particles loaded");
   return PIC_OK;

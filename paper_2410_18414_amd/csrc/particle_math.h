@@ -30,7 +30,7 @@ struct Spline {
       w[0] = T(0.5) * a * a;
       w[1] = T(0.75) - d * d;
       w[2] = T(0.5) * b * b;
-    } else {
+    } else if (DEG == 3) {
       const T f = floor(xi);
       const T d = xi - f;  // in [0, 1)
       s = (int)f - 1;
@@ -40,11 +40,50 @@ struct Spline {
       w[1] = (T(4) - T(6) * d2 + T(3) * d3) * sixth;
       w[2] = (T(1) + T(3) * d + T(3) * d2 - T(3) * d3) * sixth;
       w[3] = d3 * sixth;
+    } else if (DEG == 4) {
+      // quartic: nodes round(xi) - 2 .. + 2, w_k = M_4(k - 2 - d) by the
+      // pieces of M_4 on |t| < 1/2, 1/2 .. 3/2, 3/2 .. 5/2
+      const T f = floor(xi + T(0.5));
+      const T d = xi - f;  // in [-1/2, 1/2)
+      s = (int)f - 2;
+      auto mid = [](T u) {
+        const T u2 = u * u;
+        return (T(55) + T(20) * u - T(120) * u2 + T(80) * u2 * u - T(16) * u2 * u2) * (T(1) / T(96));
+      };
+      const T a = T(1) - T(2) * d, b = T(1) + T(2) * d, d2 = d * d;
+      w[0] = a * a * a * a * (T(1) / T(384));
+      w[1] = mid(T(1) + d);
+      w[2] = T(115) / T(192) - T(0.625) * d2 + T(0.25) * d2 * d2;
+      w[3] = mid(T(1) - d);
+      w[4] = b * b * b * b * (T(1) / T(384));
+    } else {
+      // quintic: nodes floor(xi) - 2 .. + 3, w_k = M_5(k - 2 - d) by the
+      // pieces of M_5 on |t| < 1, 1 .. 2, 2 .. 3
+      const T f = floor(xi);
+      const T d = xi - f;  // in [0, 1)
+      s = (int)f - 2;
+      auto inner = [](T u) {
+        const T u2 = u * u;
+        return T(0.55) - T(0.5) * u2 + T(0.25) * u2 * u2 - u2 * u2 * u * (T(1) / T(12));
+      };
+      auto mid = [](T u) {
+        const T u2 = u * u;
+        return T(17) / T(40) + T(0.625) * u - T(1.75) * u2 + T(1.25) * u2 * u - T(0.375) * u2 * u2 +
+               u2 * u2 * u * (T(1) / T(24));
+      };
+      const T e = T(1) - d, e2 = e * e, d2 = d * d;
+      w[0] = e2 * e2 * e * (T(1) / T(120));
+      w[1] = mid(T(1) + d);
+      w[2] = inner(d);
+      w[3] = inner(e);
+      w[4] = mid(T(2) - d);
+      w[5] = d2 * d2 * d * (T(1) / T(120));
     }
   }
   // weights and their derivatives dw/dxi (the adjoint passes differentiate
   // through the particle position)
   __device__ __forceinline__ static void eval_d(T xi, int& s, T* w, T* dw) {
+    static_assert(DEG <= 3, "the adjoint passes support spline degrees 1..3");
     eval(xi, s, w);
     if (DEG == 1) {
       dw[0] = T(-1);

@@ -187,11 +187,15 @@ hipError_t launch_charge(int dtype, int degree, const void* parts, int64_t n, Gr
     const Parts<float>& p = *(const Parts<float>*)parts;
     if (degree == 1) hipLaunchKernelGGL((k_charge<float, 1>), nb, th, 0, st, p, n, g, s, R);
     else if (degree == 2) hipLaunchKernelGGL((k_charge<float, 2>), nb, th, 0, st, p, n, g, s, R);
+    else if (degree == 4) hipLaunchKernelGGL((k_charge<float, 4>), nb, th, 0, st, p, n, g, s, R);
+    else if (degree == 5) hipLaunchKernelGGL((k_charge<float, 5>), nb, th, 0, st, p, n, g, s, R);
     else hipLaunchKernelGGL((k_charge<float, 3>), nb, th, 0, st, p, n, g, s, R);
   } else {
     const Parts<double>& p = *(const Parts<double>*)parts;
     if (degree == 1) hipLaunchKernelGGL((k_charge<double, 1>), nb, th, 0, st, p, n, g, s, R);
     else if (degree == 2) hipLaunchKernelGGL((k_charge<double, 2>), nb, th, 0, st, p, n, g, s, R);
+    else if (degree == 4) hipLaunchKernelGGL((k_charge<double, 4>), nb, th, 0, st, p, n, g, s, R);
+    else if (degree == 5) hipLaunchKernelGGL((k_charge<double, 5>), nb, th, 0, st, p, n, g, s, R);
     else hipLaunchKernelGGL((k_charge<double, 3>), nb, th, 0, st, p, n, g, s, R);
   }
   return hipGetLastError();
@@ -215,6 +219,8 @@ static hipError_t launch_untiled_deg(int degree, const InstDesc* D, int ninst, i
   switch (degree) {
     case 1: hipLaunchKernelGGL((k_untiled<T, 1, MODE>), dim3(nblocks), dim3(256), 0, s, D, ninst, sa); break;
     case 2: hipLaunchKernelGGL((k_untiled<T, 2, MODE>), dim3(nblocks), dim3(256), 0, s, D, ninst, sa); break;
+    case 4: hipLaunchKernelGGL((k_untiled<T, 4, MODE>), dim3(nblocks), dim3(256), 0, s, D, ninst, sa); break;
+    case 5: hipLaunchKernelGGL((k_untiled<T, 5, MODE>), dim3(nblocks), dim3(256), 0, s, D, ninst, sa); break;
     default: hipLaunchKernelGGL((k_untiled<T, 3, MODE>), dim3(nblocks), dim3(256), 0, s, D, ninst, sa); break;
   }
   return hipGetLastError();

@@ -435,7 +435,9 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   float qscale = 1.0f;
   double inv_qscale = 1.0;
   if (FIXEDPT) {
-    const double wmax = DEG == 1 ? 1.0 : (DEG == 2 ? 0.5625 : 4.0 / 9.0);
+    // largest 2-D weight: M_DEG(0)^2
+    const double m0 = DEG == 1 ? 1.0 : (DEG == 2 ? 0.75 : (DEG == 3 ? 2.0 / 3.0 : (DEG == 4 ? 115.0 / 192.0 : 0.55)));
+    const double wmax = m0 * m0;
     const double cmax = fabs(ph.q) * ph.c * g.inv_area * wmax * (double)max(it.z, 1);
     int e = cmax > 0 ? (int)floor(log2(1073741824.0 / cmax)) : 0;
     e = e > 100 ? 100 : (e < -100 ? -100 : e);  // a float scale, whatever q, c and the cell area
@@ -625,6 +627,8 @@ hipError_t launch_tiled_deg(int degree, int geo, const InstDesc* D, int ninst, i
   switch (degree) {
     case 1: return launch_tiled_t<T, 1, MODE>(geo, D, ninst, nblocks, lds, sa, s);
     case 2: return launch_tiled_t<T, 2, MODE>(geo, D, ninst, nblocks, lds, sa, s);
+    case 4: return launch_tiled_t<T, 4, MODE>(geo, D, ninst, nblocks, lds, sa, s);
+    case 5: return launch_tiled_t<T, 5, MODE>(geo, D, ninst, nblocks, lds, sa, s);
     default: return launch_tiled_t<T, 3, MODE>(geo, D, ninst, nblocks, lds, sa, s);
   }
 }

@@ -38,7 +38,7 @@ def _cfg(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(nx=30), dict(ny=4), dict(nx=2048), dict(degree=4), dict(degree=0), dict(bdf_order=7),
+    dict(nx=30), dict(ny=4), dict(nx=2048), dict(degree=6), dict(degree=0), dict(bdf_order=7),
     dict(dt=0.0), dict(dt=2.0), dict(c=2.0), dict(max_particles=0), dict(m=0.0), dict(lx=-1.0)])
 def test_invalid_configs_rejected(bad):
     cfg = _cfg(**bad)

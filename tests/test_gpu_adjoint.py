@@ -153,6 +153,14 @@ def test_adjoint_rejects_unsupported_contexts(gpu_lib):
     with pytest.raises(pic.PicError) as e:
         pic.step_adjoint(ctx, lam, hist)
     assert e.value.status == 2
+    # quartic spline (the adjoint covers degrees 1..3)
+    cfg = pic.make_config(16, 16, w["lx"], w["ly"], w["dt"], degree=4, scheme="bdf", bdf_order=2,
+                          dtype="f64", q=w["q"], m=w["m"], max_particles=n, flags=pic.FLAG_ADJOINT)
+    ctx = pic.Context(cfg)
+    pic.init_particles(ctx, _dev(w["x"]), _dev(w["y"]), _dev(w["P"].T))
+    with pytest.raises(pic.PicError) as e:
+        pic.step_adjoint(ctx, lam, hist)
+    assert e.value.status == 2
     # wrong phase: after deposit_current
     ctx = _ctx(pic, w)
     pic.init_particles(ctx, _dev(w["x"]), _dev(w["y"]), _dev(w["P"].T))

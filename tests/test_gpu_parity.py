@@ -34,7 +34,7 @@ SCHEMES = [("bdf", 1), ("bdf", 2), ("bdf", 3), ("cdf2", 2), ("dirk2", 2)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("degree", [1, 2, 3])
+@pytest.mark.parametrize("degree", [1, 2, 3, 4, 5])
 def test_deposit_parity(gpu_lib, dtype, degree):
     w = weibel_small()
     o = make_oracle(w, degree, "bdf")
@@ -310,3 +310,23 @@ def test_reload_at_every_phase_of_the_sort_cycle(gpu_lib):
         errs, bad = compare_particles(got, ref, w["lx"], w["ly"], 1e-12)
         assert not bad, (k, errs)
         g.close()
+
+
+@pytest.mark.parametrize("degree", [4, 5])
+@pytest.mark.parametrize("scheme,k", [("bdf", 2), ("dirk2", 2)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("flags", [0, pic.FLAG_NO_SORT])
+def test_quartic_quintic_trajectory(gpu_lib, degree, scheme, k, dtype, flags):
+    """Quartic and quintic splines (the higher-order weighting of the DIRK-2
+    study, Sec. 5.1) through step(), tiled and untiled, against the oracle."""
+    w = weibel_small(nx=32, ny=32, ppc=5, seed=80 + degree)
+    o = make_oracle(w, degree, scheme, k)
+    g = make_gpu(w, degree, scheme, dtype, bdf_order=k, flags=flags)
+    for n in (1, 12):
+        o.step(n)
+        pic.step(g, n)
+    tol = DT_TOL[dtype]
+    errs, bad = compare_particles(gpu_parts(g), o.part, w["lx"], w["ly"], tol)
+    assert not bad, errs
+    assert rel(pic.get_history(g).cpu().numpy(), hist_to_flat(o.p, o.hist)) <= tol
+    g.close()
