@@ -2,13 +2,14 @@
 // the fused gather/push/position/deposit pass, and particle state I/O.
 //
 // Paper: IAEM (Sec. 4.1) and Algorithm 1 (Sec. 4.2); current deposition with
-// tensor-product B-splines at x^{n+1} weighted by q v^n (Sec. 4.1, Sec. 5:
-// "J^{n+1} from x^{n+1}, v^n and q"), full order in every direction; the
-// velocity from the generalized momentum (Sec. 2.2).
+// tensor-product B-splines at x^{n+1} weighted by q v^n (Sec. 4.1: the
+// positions place the weights, the old velocities carry the value), full
+// order in every direction; the velocity from the generalized momentum
+// (Sec. 2.2).
 //
 // Spline (the paper cites it without printing it): nodes at i dx, centred
 // cardinal B-spline of degree DEG; a particle at xi = x/dx touches nodes
-// s .. s+DEG with the per-node weights of eval_spline below.
+// s .. s+DEG with the per-node weights of Spline::eval (particle_math.h).
 #include <algorithm>
 
 #include "particle_math.h"
@@ -17,8 +18,9 @@ namespace pic {
 
 namespace {
 
-// Untiled passes (PIC_FLAG_NO_SORT): one particle per thread, gather from the
-// planar mesh fields in global memory, deposit with global float64 atomics.
+// Untiled passes (PIC_FLAG_NO_SORT, and the naive charge deposit): one
+// particle per thread, gather from the mesh fields in global memory (float64
+// planar, float32 node-major), deposit with global float64 atomics.
 // Flattened over instances (BK_PART blocks of 256 particles each).
 template <typename T, int DEG, int MODE>
 __global__ void __launch_bounds__(256) k_untiled(const InstDesc* __restrict__ D, int ninst, StepArgs sa) {

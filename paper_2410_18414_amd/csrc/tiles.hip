@@ -651,8 +651,8 @@ size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp) {
          (mode != MODE_GATHER_PUSH ? (size_t)(dtype == PIC_F32 ? 12 : 24) * (tp.win_pad + 8) + 8 : 0);
 }
 
-// count (BK_COUNT blocks), tile scan (one block per instance), cell scan
-// (BK_TILES blocks), scatter (BK_PART blocks)
+// count (BK_COUNT blocks), cell scan with the tile scan in its last block
+// per instance (BK_TILES blocks), scatter (BK_PART blocks)
 hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_tiles, int nb_part,
                             int src_set, hipStream_t s) {
   if (nb_count) {
