@@ -47,6 +47,10 @@ ion background, which is the negative of the t = 0 electron charge (so
 rho^0 = 0 as in the cold start).  Readings: rho is deposited at x^{n+1}, the
 positions J^{n+1} is deposited at; BDF-k and DIRK-2 only, since CDF-2 needs
 rho at half levels, which the particle positions never occupy.
+
+v* in the current (Params(jvstar=True); Sec. 4.2 allows it as an alternative
+to v^n): step 2 becomes J^{n+1} = sum_p q v*_p S(x - x_p^{n+1}) with the push's
+extrapolation v* = 2 v^n - v^{n-1}; step 1 still moves the particles with v^n.
 """
 
 import numpy as np
@@ -67,12 +71,13 @@ DIRK_FORMS = ("dirk2", "dirk3")
 
 class Params:
     def __init__(self, nx, ny, lx, ly, degree, scheme, dt, c=1.0, eps0=1.0,
-                 mu0=1.0, q=-1.0, m=1.0, bdf_order=2, naive=False):
+                 mu0=1.0, q=-1.0, m=1.0, bdf_order=2, naive=False, jvstar=False):
         if scheme not in ("bdf",) + CDF2_FORMS + DIRK_FORMS:
             raise ValueError(scheme)
         if naive and scheme in CDF2_FORMS:
             raise ValueError("the naive charge deposit needs BDF-k or DIRK-2")
         self.naive = bool(naive)
+        self.jvstar = bool(jvstar)
         if abs(c * c * eps0 * mu0 - 1.0) > 1e-12:
             raise ValueError("c^2 eps0 mu0 must equal 1")
         self.nx, self.ny, self.lx, self.ly = int(nx), int(ny), float(lx), float(ly)
@@ -384,7 +389,8 @@ class State:
     def deposit(self):
         pt = self.part
         pt["x"], pt["y"] = position_update(self.p, pt["x"], pt["y"], pt["v"])
-        self.J = deposit_current(self.p, pt["x"], pt["y"], pt["v"])
+        vj = 2.0 * pt["v"] - pt["vprev"] if self.p.jvstar else pt["v"]
+        self.J = deposit_current(self.p, pt["x"], pt["y"], vj)
         if self.p.naive:
             self.rho = deposit_charge(self.p, pt["x"], pt["y"]) + self.rho_bg
         return self.J
