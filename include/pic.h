@@ -101,6 +101,12 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
  * (CDF-2 needs rho at half levels): PIC_ERR_UNSUPPORTED otherwise, and with
  * PIC_FLAG_ADJOINT.  The particle passes are the untiled ones (global atomics). */
 #define PIC_FLAG_NAIVE_RHO 16u
+/* J^{n+1} carries the extrapolated velocity v* = 2 v^n - v^{n-1} of the push
+ * (Sec. 4.2, the alternative the paper allows for the current) instead of v^n;
+ * positions still move with v^n.  rho follows from continuity with that J, so
+ * the gauge property is unchanged.  Every scheme and spline; not with
+ * PIC_FLAG_ADJOINT (PIC_ERR_UNSUPPORTED). */
+#define PIC_FLAG_JVSTAR 32u
 
 typedef struct {                /* [host] */
   int32_t abi_version;          /* == PIC_ABI_VERSION                                    */

@@ -147,6 +147,11 @@ bool validate(const pic_config_t* c, std::string& msg) {
   }
   if (c->chunk && (c->chunk < 64 || c->chunk > 65536)) { msg = "chunk must be 0 or in [64, 65536]"; return false; }
   if (c->slack < 0 || c->slack > 8) { msg = "slack must be in [0, 8]"; return false; }
+  if (c->flags & ~(PIC_FLAG_NO_SORT | PIC_FLAG_UNFUSED_STEP | PIC_FLAG_NO_GRAPH | PIC_FLAG_ADJOINT |
+                   PIC_FLAG_NAIVE_RHO | PIC_FLAG_JVSTAR)) {
+    msg = "unknown flag bits";
+    return false;
+  }
   for (int i = 0; i < 4; ++i)
     if (c->reserved[i]) { msg = "reserved fields must be zero"; return false; }
   return true;
@@ -540,6 +545,10 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
       return PIC_ERR_INVALID_ARG;
     }
   }
+  if ((cfgs[0].flags & PIC_FLAG_JVSTAR) && (cfgs[0].flags & PIC_FLAG_ADJOINT)) {
+    g_err = "the adjoint is not available with v* in the current";
+    return PIC_ERR_UNSUPPORTED;
+  }
   if (cfgs[0].flags & PIC_FLAG_NAIVE_RHO) {
     if (scheme_family(cfgs[0].scheme) == PIC_SCHEME_CDF2) {
       g_err = "the naive charge deposit needs BDF-k or DIRK-2 (CDF-2 needs rho at half levels)";
@@ -647,6 +656,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.LS = adj ? (double2*)(b + in.L.LS) : nullptr;
     d.LJ = adj ? (double*)(b + in.L.LJ) : nullptr;
     d.naive = (cf.flags & PIC_FLAG_NAIVE_RHO) ? 1 : 0;
+    d.jvstar = (cf.flags & PIC_FLAG_JVSTAR) ? 1 : 0;
     d.RB = d.naive ? (double*)(b + in.L.RB) : nullptr;
     d.n = 0;
     d.R_r2c = rows_r2c_R(cf.nx, cf.ny);

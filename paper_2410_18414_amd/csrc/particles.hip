@@ -35,6 +35,13 @@ __global__ void __launch_bounds__(256) k_untiled(const InstDesc* __restrict__ D,
   const T dt = T(ph.dt), q = T(ph.q);
   T x = p.x[i], y = p.y[i];
   T vx = p.v[0][i], vy = p.v[1][i], vz = p.v[2][i];
+  // the velocity one level older than the deposited one (v* = 2 v - u in J)
+  T ux = T(0), uy = T(0), uz = T(0);
+  if (MODE == 0 && d.jvstar) {
+    ux = p.w[0][i];
+    uy = p.w[1][i];
+    uz = p.w[2][i];
+  }
   if (MODE != 0) {
     const T* __restrict__ F = d.F32 ? (const T*)(const void*)d.F32 : (const T*)(const void*)d.F64;
     T gv[11];
@@ -49,6 +56,9 @@ __global__ void __launch_bounds__(256) k_untiled(const InstDesc* __restrict__ D,
     p.w[0][i] = nx;
     p.w[1][i] = ny;
     p.w[2][i] = nz;
+    ux = vx;
+    uy = vy;
+    uz = vz;
     vx = nx;
     vy = ny;
     vz = nz;
@@ -59,7 +69,8 @@ __global__ void __launch_bounds__(256) k_untiled(const InstDesc* __restrict__ D,
     p.x[i] = x;
     p.y[i] = y;
     const T s = q * T(g.inv_area);
-    deposit_one<T, DEG>(x, y, s * vx, s * vy, s * vz, J, g);
+    if (d.jvstar) deposit_one<T, DEG>(x, y, s * (T(2) * vx - ux), s * (T(2) * vy - uy), s * (T(2) * vz - uz), J, g);
+    else deposit_one<T, DEG>(x, y, s * vx, s * vy, s * vz, J, g);
     // naive comparison: rho^{n+1} from the same spline at x^{n+1}
     if (d.naive) deposit_scalar_one<T, DEG>(x, y, s, J + 3 * (size_t)g.nx * g.ny, g);
   }

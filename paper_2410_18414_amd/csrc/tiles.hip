@@ -340,6 +340,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   const int lane = threadIdx.x & 63;
   T cx = T(0), cy = T(0), cvx = T(0), cvy = T(0), cvz = T(0), cP[3] = {T(0), T(0), T(0)},
     cw[3] = {T(0), T(0), T(0)};
+  // J carries v* = 2 v - v_prev: the deposit needs the older velocity too
+  const bool jv = d.jvstar != 0;
   auto load = [&](int64_t i) {
     cx = p.x[i];
     cy = p.y[i];
@@ -348,10 +350,11 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
     cvz = p.v[2][i];
     if (GATHER) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        cP[c] = p.P[c][i];
-        cw[c] = p.w[c][i];
-      }
+      for (int c = 0; c < 3; ++c) cP[c] = p.P[c][i];
+    }
+    if (GATHER || jv) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cw[c] = p.w[c][i];
     }
   };
   // the first particle's inputs are in flight while the window loads
@@ -428,8 +431,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   // of int32 in a 64-bit integer atomic, J_z in a 32-bit one (two LDS atomics
   // per node instead of three float64 ones).  The scale is a power of two
   // chosen per chunk so that no window sum can leave int32: every
-  // contribution is bounded by |q| c max(w) / (dx dy) (|v| < c), and a node
-  // collects at most one per particle of the chunk.
+  // contribution is bounded by |q| c max(w) / (dx dy) (|v| < c; 3c for
+  // |2 v - v_prev|), and a node collects at most one per particle of the chunk.
   unsigned long long* jxy_w = reinterpret_cast<unsigned long long*>(jw);     // [JWP]
   uint32_t* jz_w = reinterpret_cast<uint32_t*>(jw + JWP);                      // [JWP]
   float qscale = 1.0f;
@@ -438,7 +441,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
     // largest 2-D weight: M_DEG(0)^2
     const double m0 = DEG == 1 ? 1.0 : (DEG == 2 ? 0.75 : (DEG == 3 ? 2.0 / 3.0 : (DEG == 4 ? 115.0 / 192.0 : 0.55)));
     const double wmax = m0 * m0;
-    const double cmax = fabs(ph.q) * ph.c * g.inv_area * wmax * (double)max(it.z, 1);
+    const double cmax = fabs(ph.q) * ph.c * (jv ? 3.0 : 1.0) * g.inv_area * wmax * (double)max(it.z, 1);
     int e = cmax > 0 ? (int)floor(log2(1073741824.0 / cmax)) : 0;
     e = e > 100 ? 100 : (e < -100 ? -100 : e);  // a float scale, whatever q, c and the cell area
     qscale = (float)ldexp(1.0, e);
@@ -486,6 +489,9 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       p.w[0][i] = nvx;
       p.w[1][i] = nvy;
       p.w[2][i] = nvz;
+      w0 = vx;
+      w1 = vy;
+      w2 = vz;
       vx = nvx;
       vy = nvy;
       vz = nvz;
@@ -506,9 +512,15 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         if (in_box(xi, eta, g)) {
           S::eval(xi, sx, wx);
           S::eval(eta, sy, wy);
-          jx = qs * vx;
-          jy = qs * vy;
-          jz = qs * vz;
+          if (jv) {
+            jx = qs * (T(2) * vx - w0);
+            jy = qs * (T(2) * vy - w1);
+            jz = qs * (T(2) * vz - w2);
+          } else {
+            jx = qs * vx;
+            jy = qs * vy;
+            jz = qs * vz;
+          }
           lx = (sx - ox) & (g.nx - 1);
           ly = (sy - oy) & (g.ny - 1);
           inw = lx + DEG < W && ly + DEG < W;

@@ -26,6 +26,7 @@ FLAG_UNFUSED_STEP = 2
 FLAG_NO_GRAPH = 4
 FLAG_ADJOINT = 8
 FLAG_NAIVE_RHO = 16   # rho deposited with the spline instead of continuity (the paper's naive update)
+FLAG_JVSTAR = 32      # J carries v* = 2 v^n - v^{n-1} instead of v^n
 FIELD_J = 0
 FIELD_MESH = 1
 DIAG_NAMES = ("gauge_l2", "gauge_scale", "gauss_l2", "gauss_scale", "charge", "energy",

@@ -39,7 +39,8 @@ def _cfg(**kw):
 
 @pytest.mark.parametrize("bad", [
     dict(nx=30), dict(ny=4), dict(nx=2048), dict(degree=6), dict(degree=0), dict(bdf_order=7),
-    dict(dt=0.0), dict(dt=2.0), dict(c=2.0), dict(max_particles=0), dict(m=0.0), dict(lx=-1.0)])
+    dict(dt=0.0), dict(dt=2.0), dict(c=2.0), dict(max_particles=0), dict(m=0.0), dict(lx=-1.0),
+    dict(flags=64)])
 def test_invalid_configs_rejected(bad):
     cfg = _cfg(**bad)
     assert pic.load().pic_workspace_bytes(ctypes.byref(cfg)) == 0
@@ -72,6 +73,19 @@ def test_create_rejects_bad_workspace_without_gpu():
     cfg.abi_version = 99
     assert lib.pic_create(ctypes.byref(cfg), ctypes.c_void_p(256), 1 << 40, None,
                           ctypes.byref(h)) == 1
+
+
+@pytest.mark.parametrize("flags,scheme", [(pic.FLAG_JVSTAR | pic.FLAG_ADJOINT, "bdf"),
+                                          (pic.FLAG_NAIVE_RHO | pic.FLAG_ADJOINT, "bdf"),
+                                          (pic.FLAG_NAIVE_RHO, "cdf2_semi")])
+def test_create_rejects_unsupported_combinations_without_gpu(flags, scheme):
+    """Unsupported flag/scheme combinations fail (PIC_ERR_UNSUPPORTED) before
+    the workspace is looked at."""
+    lib = pic.load()
+    cfg = _cfg(flags=flags, scheme=scheme)
+    h = ctypes.c_void_p()
+    assert lib.pic_create(ctypes.byref(cfg), None, 0, None, ctypes.byref(h)) == 2
+    assert not h.value
 
 
 def test_null_context_calls_fail_cleanly():
