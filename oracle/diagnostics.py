@@ -15,6 +15,10 @@ held in the history after a step:
          - c^2 h (R^{s,n} div A^n + R^{s,n+1} div A^{n+1}), R = sum b_i (1-c_i), sum b_i c_i.
          Reading: Gauss is reported (not guaranteed, remark closing Sec. 3.3) with
          E^{n+1} = -grad phi^{n+1} - v_A^{n+1}.
+         Sub-stepped stage currents (Params.dirk_substep): the gauge is the
+         stage-value form, eps1^{n+1} = v_phi^{n+1} + c^2 div A^{n+1} (zero at
+         every stage implies the printed phi^{n+1} = phi^n - c^2 h sum b_i div A^(i)
+         with A^(i) the RK stage values); Gauss as above.
 Norms (the paper does not define them): discrete L2 = sqrt(dx dy sum f^2) and
 L-infinity over the mesh.  Field energy W = (dx dy / 2) sum (eps0 |E|^2 + |B|^2/mu0)
 with B = curl A (B_x = d_y A_z, B_y = -d_x A_z, B_z = d_x A_y - d_y A_x).
@@ -64,8 +68,13 @@ def residuals(state):
     else:
         _, b, cc = schemes.dirk_tableau(p.scheme)
         Rn, Rn1 = float(np.sum(b * (1 - cc))), float(np.sum(b * cc))
-        gauge_t = -(h["phi"][0] - h["phi"][1])
-        gauge_d = -p.c ** 2 * p.dt * (Rn * divA(h["A"][1]) + Rn1 * divA(h["A"][0]))
+        if p.dirk_substep:
+            # stage-value gauge: v_phi + c^2 div A at the new level
+            gauge_t = h["vphi"]
+            gauge_d = p.c ** 2 * divA(h["A"][0])
+        else:
+            gauge_t = -(h["phi"][0] - h["phi"][1])
+            gauge_d = -p.c ** 2 * p.dt * (Rn * divA(h["A"][1]) + Rn1 * divA(h["A"][0]))
         phi, rho = h["phi"][0], h["rho"][0]
         Eh = np.stack([-ikx * phi - h["vA"][0], -iky * phi - h["vA"][1], -h["vA"][2]])
         Ah = h["A"][0]

@@ -51,6 +51,21 @@ rho at half levels, which the particle positions never occupy.
 v* in the current (Params(jvstar=True); Sec. 4.2 allows it as an alternative
 to v^n): step 2 becomes J^{n+1} = sum_p q v*_p S(x - x_p^{n+1}) with the push's
 extrapolation v* = 2 v^n - v^{n-1}; step 1 still moves the particles with v^n.
+
+DIRK stage currents by particle sub-stepping (Params(dirk_substep=True), the
+alternative to linear interpolation named with the DIRK continuity update of
+Algorithm 1): stage i deposits J^(i) = sum_p q v_p^n S(x - x_p^n - c_i dt v_p^n),
+the particles advanced by the IAEM position update over c_i dt (the same
+"position places the weight, v^n carries the value" rule as J^{n+1}).
+Reading: the stage charge densities are the Runge-Kutta stage values of the
+continuity equation, rho^(i) = rho^n - dt sum_{j<=i} a_ij div J^(j), whose
+final stage is the printed rho^{n+1} = rho^n - dt sum_i b_i div J^(i).  (The
+linear interpolation between rho^n and rho^{n+1} that Sec. 3.3 uses holds the
+gauge only for linearly interpolated currents.)  With this reading the RK
+stages keep v_phi + c^2 div A = 0 and Gauss's law with E = -grad phi - v_A
+exactly, since the pair of those two residuals obeys a source-free linear
+system that the RK method advances from zero.  The J history level holds
+sum_i b_i J^(i), the current of the step's continuity update.
 """
 
 import numpy as np
@@ -71,13 +86,17 @@ DIRK_FORMS = ("dirk2", "dirk3")
 
 class Params:
     def __init__(self, nx, ny, lx, ly, degree, scheme, dt, c=1.0, eps0=1.0,
-                 mu0=1.0, q=-1.0, m=1.0, bdf_order=2, naive=False, jvstar=False):
+                 mu0=1.0, q=-1.0, m=1.0, bdf_order=2, naive=False, jvstar=False,
+                 dirk_substep=False):
         if scheme not in ("bdf",) + CDF2_FORMS + DIRK_FORMS:
             raise ValueError(scheme)
         if naive and scheme in CDF2_FORMS:
             raise ValueError("the naive charge deposit needs BDF-k or DIRK-2")
         self.naive = bool(naive)
         self.jvstar = bool(jvstar)
+        if dirk_substep and (scheme not in DIRK_FORMS or naive):
+            raise ValueError("sub-stepped stage currents need a DIRK scheme and continuity")
+        self.dirk_substep = bool(dirk_substep)
         if abs(c * c * eps0 * mu0 - 1.0) > 1e-12:
             raise ValueError("c^2 eps0 mu0 must equal 1")
         self.nx, self.ny, self.lx, self.ly = int(nx), int(ny), float(lx), float(ly)
@@ -119,6 +138,11 @@ def init_particles(p, x, y, P):
 
 def position_update(p, x, y, v):
     return wrap(x + v[:, 0] * p.dt, p.lx), wrap(y + v[:, 1] * p.dt, p.ly)
+
+
+def stage_positions(p, x, y, v, frac):
+    """The IAEM position update over frac * dt (a DIRK stage time)."""
+    return wrap(x + v[:, 0] * (frac * p.dt), p.lx), wrap(y + v[:, 1] * (frac * p.dt), p.ly)
 
 
 def deposit_current(p, x, y, v):
@@ -324,19 +348,34 @@ def _cdf2_other_update(p, hist, Jh):
     return out, phi_tilde, A_new
 
 
+def _stage_rho(A_t, b, cc, rho_n, dv, h):
+    """RK stage values of the continuity equation rho' = -div J given the
+    stage divergences dv: rho^(i) = rho^n - h sum_{j<=i} a_ij dv_j."""
+    return [rho_n - h * sum(A_t[i, j] * dv[j] for j in range(i + 1)) for i in range(len(b))]
+
+
 def _dirk_update(p, hist, Jh, rho_h=None):
     # Sec. 3.3: s-stage DIRK on (u, v) with u' = v, v' = c^2 (S + Lap u)
+    # Jh: J^{n+1}, or with dirk_substep the s stage currents [s, 3, ...]
     A_t, b, cc = schemes.dirk_tableau(p.scheme)
     s = len(b)
     h, c2, lap = p.dt, p.c ** 2, p.lap
-    J_n = hist["J"]
-    J_st = [(1.0 - cc[i]) * J_n + cc[i] * Jh for i in range(s)]
     rho_n = hist["rho"][0]
-    if rho_h is None:
-        rho_new = rho_n - h * sum(b[i] * div(p, J_st[i]) for i in range(s))
+    if p.dirk_substep:
+        J_st = [Jh[i] for i in range(s)]
+        dv = [div(p, J_st[i]) for i in range(s)]
+        rho_new = rho_n - h * sum(b[i] * dv[i] for i in range(s))
+        rho_st = _stage_rho(A_t, b, cc, rho_n, dv, h)
+        J_keep = sum(b[i] * J_st[i] for i in range(s))
     else:
-        rho_new = rho_h
-    rho_st = [(1.0 - cc[i]) * rho_n + cc[i] * rho_new for i in range(s)]
+        J_n = hist["J"]
+        J_st = [(1.0 - cc[i]) * J_n + cc[i] * Jh for i in range(s)]
+        if rho_h is None:
+            rho_new = rho_n - h * sum(b[i] * div(p, J_st[i]) for i in range(s))
+        else:
+            rho_new = rho_h
+        rho_st = [(1.0 - cc[i]) * rho_n + cc[i] * rho_new for i in range(s)]
+        J_keep = Jh
 
     def advance(u, v, S):
         ku, kv = [], []
@@ -351,13 +390,13 @@ def _dirk_update(p, hist, Jh, rho_h=None):
 
     phi_new, vphi_new = advance(hist["phi"][0], hist["vphi"],
                                 [rho_st[i] / p.eps0 for i in range(s)])
-    A_new = np.empty_like(Jh)
-    vA_new = np.empty_like(Jh)
+    A_new = np.empty_like(J_keep)
+    vA_new = np.empty_like(J_keep)
     for l in range(3):
         A_new[l], vA_new[l] = advance(hist["A"][0][l], hist["vA"][l],
                                       [p.mu0 * J_st[i][l] for i in range(s)])
     out = dict(rho=[rho_new, rho_n], phi=[phi_new, hist["phi"][0]], vphi=vphi_new,
-               A=[A_new, hist["A"][0]], vA=vA_new, J=Jh)
+               A=[A_new, hist["A"][0]], vA=vA_new, J=J_keep)
     return out, phi_new, A_new
 
 
@@ -388,15 +427,24 @@ class State:
 
     def deposit(self):
         pt = self.part
+        x0, y0 = pt["x"], pt["y"]
         pt["x"], pt["y"] = position_update(self.p, pt["x"], pt["y"], pt["v"])
         vj = 2.0 * pt["v"] - pt["vprev"] if self.p.jvstar else pt["v"]
-        self.J = deposit_current(self.p, pt["x"], pt["y"], vj)
+        if self.p.dirk_substep:
+            _, _, cc = schemes.dirk_tableau(self.p.scheme)
+            self.J = np.stack([deposit_current(self.p, *stage_positions(self.p, x0, y0, pt["v"], ci), vj)
+                               for ci in cc])
+        else:
+            self.J = deposit_current(self.p, pt["x"], pt["y"], vj)
         if self.p.naive:
             self.rho = deposit_charge(self.p, pt["x"], pt["y"]) + self.rho_bg
         return self.J
 
     def solve(self):
-        Jh = np.stack([spectral.fft2(self.J[c]) for c in range(3)])
+        if self.p.dirk_substep:
+            Jh = np.stack([[spectral.fft2(Ji[c]) for c in range(3)] for Ji in self.J])
+        else:
+            Jh = np.stack([spectral.fft2(self.J[c]) for c in range(3)])
         rho_h = spectral.fft2(self.rho) if self.p.naive else None
         self.hist, phi_t, A_new = field_update(self.p, self.hist, Jh, rho_h)
         self.fields = gradient_fields(self.p, phi_t, A_new)

@@ -13,14 +13,15 @@ from oracle import pic as opic
 DT_TOL = {"f64": 1e-10, "f32": 1e-4}
 
 
-def oracle_params(w, degree, scheme, bdf_order=2, naive=False, jvstar=False):
+def oracle_params(w, degree, scheme, bdf_order=2, naive=False, jvstar=False, dirk_substep=False):
     return opic.Params(w["nx"], w["ny"], w["lx"], w["ly"], degree, scheme, w["dt"],
                        c=w.get("c", 1.0), eps0=w.get("eps0", 1.0), mu0=w.get("mu0", 1.0),
-                       q=w["q"], m=w["m"], bdf_order=bdf_order, naive=naive, jvstar=jvstar)
+                       q=w["q"], m=w["m"], bdf_order=bdf_order, naive=naive, jvstar=jvstar,
+                       dirk_substep=dirk_substep)
 
 
-def make_oracle(w, degree, scheme, bdf_order=2, naive=False, jvstar=False):
-    p = oracle_params(w, degree, scheme, bdf_order, naive, jvstar)
+def make_oracle(w, degree, scheme, bdf_order=2, naive=False, jvstar=False, dirk_substep=False):
+    p = oracle_params(w, degree, scheme, bdf_order, naive, jvstar, dirk_substep)
     return opic.State(p, w["x"], w["y"], w["P"])
 
 

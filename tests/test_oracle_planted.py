@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import bspline, pic, schemes
+import test_oracle_dirk_substep as D
 import test_oracle_fields as F
 import test_oracle_invariants as I
 import test_oracle_spline_deposit as S
@@ -90,3 +91,14 @@ def test_missing_c2_in_dirk_kv_fails_dispersion(monkeypatch):
     monkeypatch.setattr(pic, "_dirk_update", patched)
     with pytest.raises(AssertionError):
         F.test_dirk2_dispersion()
+
+
+def test_linear_stage_rho_with_substepped_currents_breaks_gauge(monkeypatch):
+    """The stage charge densities interpolated linearly between rho^n and
+    rho^{n+1} (Sec. 3.3's interpolation) while the currents are sub-stepped."""
+    def linear(A_t, b, cc, rho_n, dv, h):
+        rho_new = rho_n - h * sum(b[i] * dv[i] for i in range(len(b)))
+        return [(1 - cc[i]) * rho_n + cc[i] * rho_new for i in range(len(b))]
+    monkeypatch.setattr(pic, "_stage_rho", linear)
+    with pytest.raises(AssertionError):
+        D.test_gauge_and_gauss_at_round_off("dirk2")
