@@ -196,6 +196,45 @@ def bench_naive(steps=20):
     return out
 
 
+def bench_variants(steps=40):
+    """The current and stepper options on the plain workload (128 x 128,
+    64 particles/cell, cubic, float32 particles): v* in J against the plain
+    BDF-2 step, and DIRK-2 / DIRK-3 with interpolated or sub-stepped stage
+    currents; step rate and the relative gauge and Gauss residuals after
+    `steps` steps."""
+    import torch
+    from paper_2410_18414_amd import pic, workloads
+    w = workloads.make(2)
+    n = len(w["x"])
+    dev = torch.device("cuda:0")
+    data = (torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
+            torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev))
+    out = dict(workload="weibel-128x128-64ppc-cubic-f32, %d steps" % steps, particles=n, steps=steps)
+    variants = (("bdf2", "bdf", 0), ("bdf2_jvstar", "bdf", pic.FLAG_JVSTAR),
+                ("dirk2", "dirk2", 0), ("dirk2_substep", "dirk2", pic.FLAG_DIRK_SUBSTEP),
+                ("dirk3", "dirk3", 0), ("dirk3_substep", "dirk3", pic.FLAG_DIRK_SUBSTEP))
+    for name, scheme, flags in variants:
+        cfg = pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=3, scheme=scheme, bdf_order=2,
+                              dtype="f32", q=w["q"], m=w["m"], max_particles=n, flags=flags)
+        ctx = pic.Context(cfg)
+        pic.init_particles(ctx, *data)
+        pic.step(ctx, pic.graph_period(ctx) + 1)
+        pic.init_particles(ctx, *data)
+        a, b = _events(ctx.stream)
+        torch.cuda.synchronize()
+        a.record(ctx.stream)
+        pic.step(ctx, steps)
+        b.record(ctx.stream)
+        torch.cuda.synchronize()
+        d = pic.diagnostics(ctx)
+        ms = a.elapsed_time(b) / steps
+        out[name] = dict(ms_per_step=round(ms, 5), value=round(n / (ms * 1e-3), 1),
+                         gauge_rel=d["gauge_l2"] / d["gauge_scale"] if d["gauge_scale"] else 0.0,
+                         gauss_rel=d["gauss_l2"] / d["gauss_scale"] if d["gauss_scale"] else 0.0)
+        ctx.close()
+    return out
+
+
 def bench_adjoint(every=5):
     """Gradient of the final field energy through 20 BDF-2 steps of the
     128 x 128, 64 particles/cell anisotropic workload with drift (float64,
@@ -262,6 +301,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance ensemble section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) section")
     ap.add_argument("--no-naive", action="store_true", help="skip the naive charge-deposit comparison section")
+    ap.add_argument("--no-variants", action="store_true", help="skip the current/stepper options section")
     ap.add_argument("--batched-steps", type=int, default=20)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (counter calibration)")
@@ -370,6 +410,8 @@ def main():
         out["adjoint"] = bench_adjoint()
     if not args.no_naive:
         out["naive"] = bench_naive()
+    if not args.no_variants:
+        out["variants"] = bench_variants()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, spec, args.cpu_steps)
     print(json.dumps(out), flush=True)

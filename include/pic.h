@@ -107,6 +107,18 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
  * the gauge property is unchanged.  Every scheme and spline; not with
  * PIC_FLAG_ADJOINT (PIC_ERR_UNSUPPORTED). */
 #define PIC_FLAG_JVSTAR 32u
+/* DIRK stage currents by particle sub-stepping (the alternative to linear
+ * interpolation named with the DIRK continuity update of Algorithm 1): stage i
+ * deposits J^(i) from the particles advanced by the IAEM position update over
+ * c_i dt (x^n + c_i dt v^n, weighted by q v^n, or q v* with PIC_FLAG_JVSTAR),
+ * one deposit pass per stage.  The stage charge densities are the RK stage
+ * values of the continuity equation, rho^(i) = rho^n - dt sum_{j<=i} a_ij
+ * div J^(i), so v_phi + c^2 div A = 0 and Gauss's law (E = -grad phi - v_A)
+ * hold to round-off; pic_diagnostics reports that gauge form.  The DIRK J
+ * history level holds sum_i b_i J^(i).  DIRK-2 and DIRK-3 only; not with
+ * PIC_FLAG_NAIVE_RHO or PIC_FLAG_ADJOINT (PIC_ERR_UNSUPPORTED).  step() runs
+ * the gather/push and the stage deposits as separate passes. */
+#define PIC_FLAG_DIRK_SUBSTEP 64u
 
 typedef struct {                /* [host] */
   int32_t abi_version;          /* == PIC_ABI_VERSION                                    */
@@ -187,6 +199,8 @@ pic_status_t pic_set_particles(pic_ctx_t ctx, const double* in);
 
 /* Real mesh fields, float64 device dst:
  *   PIC_FIELD_J      [3][ny][nx]  J^{n+1}; valid in phase DEPOSITED
+ *                    (PIC_FLAG_DIRK_SUBSTEP: [3 stages][ny][nx], stage i at
+ *                    planes 3i .. 3i+2)
  *   PIC_FIELD_MESH  [12][ny][nx]  the gathered fields, valid in phase SOLVED:
  *        dphi/dx, dphi/dy, Ax, Ay, Az, dAx/dx, dAy/dx, dAz/dx,
  *        dAx/dy, dAy/dy, dAz/dy, phi~   (phi~ = phi^{n+1}; CDF-2: the mean
@@ -200,6 +214,8 @@ pic_status_t pic_get_field(pic_ctx_t ctx, int32_t which, double* dst);
  *   BDF-k : rho (k levels), phi (2k), A (2k levels x 3 components)
  *   CDF-2 : rho^{n+1/2..n-3/2} (3), phi (3), A^{n..n-1} (2 x 3), J^{n..n-1} (2 x 3)
  *   DIRK-2: rho (2), phi (2), v_phi (1), A (2 x 3), v_A (3), J^n (3)
+ *           (DIRK-3 the same; with PIC_FLAG_DIRK_SUBSTEP the J level is
+ *           sum_i b_i J^(i) of the last step)
  * (v_phi, v_A: the time derivatives the DIRK first-order system carries.) */
 int32_t pic_history_fields(const pic_config_t* cfg);
 pic_status_t pic_get_history(pic_ctx_t ctx, double* dst);

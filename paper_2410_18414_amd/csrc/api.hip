@@ -148,7 +148,7 @@ bool validate(const pic_config_t* c, std::string& msg) {
   if (c->chunk && (c->chunk < 64 || c->chunk > 65536)) { msg = "chunk must be 0 or in [64, 65536]"; return false; }
   if (c->slack < 0 || c->slack > 8) { msg = "slack must be in [0, 8]"; return false; }
   if (c->flags & ~(PIC_FLAG_NO_SORT | PIC_FLAG_UNFUSED_STEP | PIC_FLAG_NO_GRAPH | PIC_FLAG_ADJOINT |
-                   PIC_FLAG_NAIVE_RHO | PIC_FLAG_JVSTAR)) {
+                   PIC_FLAG_NAIVE_RHO | PIC_FLAG_JVSTAR | PIC_FLAG_DIRK_SUBSTEP)) {
     msg = "unknown flag bits";
     return false;
   }
@@ -205,6 +205,8 @@ struct Layout {
   size_t plane_c;    // complex entries per spectral plane
 };
 
+SchemeCoef make_scheme(const pic_config_t& c);
+
 Layout plan_instance(const pic_config_t& c) {
   Layout L{};
   const size_t es = c.particle_dtype == PIC_F32 ? 4 : 8;
@@ -223,8 +225,9 @@ Layout plan_instance(const pic_config_t& c) {
   L.set_bytes = 11 * array_bytes(cap, es) + align_up(cap * 4);
   L.parts = take(2 * L.set_bytes);
   const bool naive = (c.flags & PIC_FLAG_NAIVE_RHO) != 0;
-  L.J = take((naive ? 4 : 3) * plane_r * 8);
-  L.T = take((naive ? 4 : 3) * L.plane_c * 16);
+  const int njp = j_planes(make_scheme(c), naive ? 1 : 0);
+  L.J = take(njp * plane_r * 8);
+  L.T = take(njp * L.plane_c * 16);
   L.RB = naive ? take(plane_r * 8) : 0;
   L.H = take((size_t)h.nslots * L.plane_c * 16);
   L.U = take(8 * L.plane_c * 16);
@@ -309,6 +312,7 @@ SchemeCoef make_scheme(const pic_config_t& c) {
       sc.stages = 2;
       b[0] = b[1] = 0.5;
     }
+    sc.substep = (c.flags & PIC_FLAG_DIRK_SUBSTEP) ? 1 : 0;
     for (int i = 0; i < sc.stages; ++i) {
       sc.dirkB[i] = b[i];
       sc.dirkC[i] = 0.0;
@@ -390,7 +394,7 @@ struct pic_ctx_s {
   }
   int ninst() const { return (int)inst.size(); }
   Instance& I() { return inst[sel]; }
-  StepArgs sargs() const { return StepArgs{cur, vflip}; }
+  StepArgs sargs(int stage = -1) const { return StepArgs{cur, vflip, stage}; }
 
   // fold pending pairs into the totals (synchronises the stream)
   hipError_t fold_timing() {
@@ -475,10 +479,16 @@ pic_status_t particle_pass(pic_ctx_t c, int mode) {
   }
   static const int cls[3] = {0, 2, 3};
   auto* t = c->begin_timed(cls[mode]);
-  hipError_t e = c->sorted ? launch_tiled(c->dtype, mode, c->degree, c->geo, c->d_desc, c->ninst(), c->nblk[BK_WORK],
-                                          c->lds_tiled[mode], c->sargs(), c->stream)
-                           : launch_untiled(c->dtype, mode, c->degree, c->d_desc, c->ninst(), c->nblk[BK_PART],
-                                            c->sargs(), c->stream);
+  // sub-stepped DIRK currents: one deposit pass per stage (the last one also
+  // writes x^{n+1})
+  const SchemeCoef& sc = c->inst[0].d.sc;
+  const int nst = mode == 0 && sc.substep ? sc.stages : 0;
+  hipError_t e = hipSuccess;
+  for (int k = nst ? 0 : -1; k < nst && e == hipSuccess; ++k)
+    e = c->sorted ? launch_tiled(c->dtype, mode, c->degree, c->geo, c->d_desc, c->ninst(), c->nblk[BK_WORK],
+                                 c->lds_tiled[mode], c->sargs(k), c->stream)
+                  : launch_untiled(c->dtype, mode, c->degree, c->d_desc, c->ninst(), c->nblk[BK_PART], c->sargs(k),
+                                   c->stream);
   c->end_timed(t);
   pic_status_t st = c->hip(e, "particle pass");
   if (st) return st;
@@ -509,7 +519,8 @@ pic_status_t reset_fields(pic_ctx_t c, Instance& in) {
   pic_status_t st = c->hip(launch_fill_f64((double*)d.H, (size_t)c->hist.nslots * in.L.plane_c * 2, 0.0, c->stream),
                            "history fill");
   if (st) return st;
-  st = c->hip(launch_fill_f64(d.J, (size_t)3 * in.cfg.nx * in.cfg.ny, 0.0, c->stream), "J fill");
+  // every J plane but the naive mode's rho plane (set to the ion background by init_particles)
+  st = c->hip(launch_fill_f64(d.J, (size_t)j_planes(d.sc, 0) * in.cfg.nx * in.cfg.ny, 0.0, c->stream), "J fill");
   if (st || !d.LF) return st;
   return c->hip(launch_fill_f64(d.LF, (size_t)11 * in.cfg.nx * in.cfg.ny, 0.0, c->stream), "adjoint fill");
 }
@@ -543,6 +554,16 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     if (!validate(&cfgs[i], m) || !compatible(cfgs[0], cfgs[i], m)) {
       g_err = ninst > 1 ? "instance " + std::to_string(i) + ": " + m : m;
       return PIC_ERR_INVALID_ARG;
+    }
+  }
+  if (cfgs[0].flags & PIC_FLAG_DIRK_SUBSTEP) {
+    if (scheme_family(cfgs[0].scheme) != PIC_SCHEME_DIRK2) {
+      g_err = "sub-stepped stage currents need a DIRK scheme";
+      return PIC_ERR_UNSUPPORTED;
+    }
+    if (cfgs[0].flags & (PIC_FLAG_NAIVE_RHO | PIC_FLAG_ADJOINT)) {
+      g_err = "sub-stepped stage currents are not available with the naive deposit or the adjoint";
+      return PIC_ERR_UNSUPPORTED;
     }
   }
   if ((cfgs[0].flags & PIC_FLAG_JVSTAR) && (cfgs[0].flags & PIC_FLAG_ADJOINT)) {
@@ -663,7 +684,8 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.R_c2r = rows_c2r_R(cf.nx, cf.ny);
     d.nb_col = columns_nb(cf.ny);
     // flattened block ranges
-    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * (3 + d.naive), (cf.nx / 2 + 1) * columns_parts(scheme_family(cf.scheme)),
+    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * j_planes(d.sc, d.naive),
+                               (cf.nx / 2 + 1) * columns_parts(scheme_family(cf.scheme)),
                                cf.ny / d.R_c2r * 6, d.tp.max_work,
                                ceil_div(cf.max_particles, 256), ceil_div(cf.max_particles, 1024),
                                ceil_div(d.tp.ntiles, 4)};
@@ -673,9 +695,10 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     }
     c->lds_r2c = std::max(c->lds_r2c, rows_r2c_lds_bytes(cf.nx, cf.ny));
     c->lds_c2r = std::max(c->lds_c2r, rows_c2r_lds_bytes(cf.nx, cf.ny));
-    c->lds_col = std::max(c->lds_col, columns_parts(scheme_family(cf.scheme)) > 1 ? columns_split_lds_bytes(cf.ny)
-                                                                    : columns_lds_bytes(cf.ny));
-    if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, columns_lds_bytes(cf.ny));
+    c->lds_col = std::max(c->lds_col, columns_parts(scheme_family(cf.scheme)) > 1
+                                          ? columns_split_lds_bytes(cf.ny)
+                                          : columns_lds_bytes(cf.ny, d.sc.substep ? 3 * d.sc.stages : 4));
+    if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, columns_lds_bytes(cf.ny, 4));
     for (int mode = 0; mode < 3; ++mode)
       c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp));
     // a position update moves a particle by less than c dt; the window's slack
@@ -853,7 +876,8 @@ pic_status_t run_steps(pic_ctx_t c, int32_t nsteps) {
   if (nsteps < 0) return c->fail(PIC_ERR_INVALID_ARG, "nsteps must be >= 0");
   if (c->phase != READY) return c->fail(PIC_ERR_STATE, "step needs phase READY");
   if (nsteps == 0) return PIC_OK;
-  const bool unfused = (c->inst[0].cfg.flags & PIC_FLAG_UNFUSED_STEP) != 0;
+  // sub-stepped DIRK currents need their own deposit passes after the push
+  const bool unfused = (c->inst[0].cfg.flags & PIC_FLAG_UNFUSED_STEP) != 0 || c->inst[0].d.sc.substep;
   pic_status_t st = particle_pass(c, 0);
   int iters = nsteps - 1;
   // the host-side launch state repeats after lcm(ring sizes, 2 sort intervals)
@@ -1058,7 +1082,9 @@ pic_status_t pic_get_field(pic_ctx_t c, int32_t which, double* dst) {
   const size_t plane = (size_t)in.cfg.nx * in.cfg.ny;
   if (which == PIC_FIELD_J) {
     if (c->phase != DEPOSITED) return c->fail(PIC_ERR_STATE, "J is valid in phase DEPOSITED");
-    return c->hip(hipMemcpyAsync(dst, in.d.J, 3 * plane * 8, hipMemcpyDeviceToDevice, c->stream), "copy J");
+    return c->hip(hipMemcpyAsync(dst, in.d.J, (size_t)j_planes(in.d.sc, 0) * plane * 8, hipMemcpyDeviceToDevice,
+                                 c->stream),
+                  "copy J");
   }
   if (which == PIC_FIELD_MESH) {
     if (c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "mesh fields are valid in phase SOLVED");

@@ -87,9 +87,11 @@ struct ModeOut {
 // K: the BDF order as a compile-time constant (0 for the other steppers), so
 // that every history slot index is static and all history loads issue at once
 template <int SCHEME, int K>
+// stage: the sub-stepped DIRK stage currents of this mode (component l of
+// stage i at stage[(3 i + l) * sstride]), else null
 __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, double2 J0, double2 J1,
-                               double2 J2, const double2* rho_dep, double kxs, double kys, const SchemeCoef& sc,
-                               const HistSlots& hs) {
+                               double2 J2, const double2* rho_dep, const double2* stage, int sstride, double kxs,
+                               double kys, const SchemeCoef& sc, const HistSlots& hs) {
   const double kappa = kxs * kxs + kys * kys;  // -Laplacian symbol
   auto at = [&](int slot) -> double2& { return H[(size_t)slot * plane + m]; };
   // i k . J
@@ -140,19 +142,40 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
   } else {  // DIRK (sc.stages = 2 or 3 stages)
     const double h = sc.dt, c2 = sc.c * sc.c;
     const int ns = sc.stages;
-    double2 Jn[3], Jst[3][3];
-    for (int l = 0; l < 3; ++l) Jn[l] = at(hs.J[0] + l);
-    for (int i = 0; i < ns; ++i)
-      for (int l = 0; l < 3; ++l)
-        Jst[i][l] = cadd(cscale(Jn[l], 1.0 - sc.dirkC[i]), cscale(Jn1[l], sc.dirkC[i]));
+    double2 Jst[3][3], Jkeep[3];
     const double2 rho_n = at(hs.rho[0]);
     double2 rho = rho_n;
-    if (rho_dep)
-      rho = *rho_dep;  // naive comparison: the deposited rho^{n+1}
-    else
-      for (int i = 0; i < ns; ++i) rho = csub(rho, cscale(divv(Jst[i][0], Jst[i][1]), h * sc.dirkB[i]));
     double2 rst[3];
-    for (int i = 0; i < ns; ++i) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
+    if (stage) {
+      // sub-stepped stage currents; rho^(i) are the RK stage values of the
+      // continuity equation, rho^{n+1} its final stage
+      double2 dv[3];
+      for (int i = 0; i < ns; ++i) {
+        for (int l = 0; l < 3; ++l) Jst[i][l] = stage[(3 * i + l) * sstride];
+        dv[i] = divv(Jst[i][0], Jst[i][1]);
+        rho = csub(rho, cscale(dv[i], h * sc.dirkB[i]));
+      }
+      for (int i = 0; i < ns; ++i) {
+        rst[i] = rho_n;
+        for (int j = 0; j <= i; ++j) rst[i] = csub(rst[i], cscale(dv[j], h * sc.dirkA[i][j]));
+      }
+      for (int l = 0; l < 3; ++l) {
+        Jkeep[l] = make_double2(0.0, 0.0);
+        for (int i = 0; i < ns; ++i) Jkeep[l] = cadd(Jkeep[l], cscale(Jst[i][l], sc.dirkB[i]));
+      }
+    } else {
+      double2 Jn[3];
+      for (int l = 0; l < 3; ++l) Jn[l] = at(hs.J[0] + l);
+      for (int i = 0; i < ns; ++i)
+        for (int l = 0; l < 3; ++l)
+          Jst[i][l] = cadd(cscale(Jn[l], 1.0 - sc.dirkC[i]), cscale(Jn1[l], sc.dirkC[i]));
+      if (rho_dep)
+        rho = *rho_dep;  // naive comparison: the deposited rho^{n+1}
+      else
+        for (int i = 0; i < ns; ++i) rho = csub(rho, cscale(divv(Jst[i][0], Jst[i][1]), h * sc.dirkB[i]));
+      for (int i = 0; i < ns; ++i) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
+      for (int l = 0; l < 3; ++l) Jkeep[l] = Jn1[l];
+    }
     // one scalar wave component: (u, v)' = (v, c^2 (S + Lap u)), Lap = -kappa
     auto advance = [&](double2& u, double2& v, const double2* S) {
       double2 ku[3], kv[3];
@@ -190,7 +213,7 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
       advance(ua, va, S);
       at(hs.A_new + l) = ua;
       at(hs.vA + l) = va;
-      at(hs.J[0] + l) = Jn1[l];
+      at(hs.J[0] + l) = Jkeep[l];
       o.A[l] = ua;
     }
   }
@@ -199,9 +222,12 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
 
 template <int SCHEME, int K>
 __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
-  // LDS: store [0, 4N) = phi~, A0, A1, A2 (scaled); work buffers from 4N:
-  // forward 2 x 3N, inverse 2 x NB*N (NB = 8, 4 or 2 fields per batch); then
-  // the N twiddles (ny <= 512)
+  // LDS: store [0, NS*N) with NS = 4 (phi~, A0, A1, A2, scaled), or with
+  // sub-stepped DIRK currents NS = 3 per stage: the stage spectra, whose first
+  // four columns become the store once each mode has been updated (the thread
+  // of mode ky reads all its stage values before writing its outputs); work
+  // buffers from NS*N: forward 2 x 3N (naive: 2 x 4N), inverse 2 x NB*N
+  // (NB = 8, 4 or 2 fields per batch); then the N twiddles (ny <= 512)
   extern __shared__ double2 sm[];
   const int ii = find_inst(D, ninst, BK_COL, blockIdx.x);
   const InstDesc& d = D[ii];
@@ -213,8 +239,9 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
   double2* __restrict__ H = d.H;
   double2* __restrict__ U = d.U;
   const size_t plane = (size_t)g.nxh * g.ny;
+  const int nst = sc.substep ? sc.stages : 0;  // sub-stepped DIRK stages
   double2* store = sm;
-  double2* wk = sm + 4 * N;
+  double2* wk = sm + (nst ? 3 * nst : 4) * N;
   // twiddles staged in LDS where they fit (ny <= 512), else read from global
   const double2* tws = d.twy;
   if (N <= 512) {
@@ -222,19 +249,30 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
     for (int t = threadIdx.x; t < N; t += blockDim.x) t_lds[t] = d.twy[t];
     tws = t_lds;
   }
-  const int ncol = 3 + d.naive;  // J (and the naive mode's deposited rho)
-  for (int t = threadIdx.x; t < ncol * N; t += blockDim.x) {
-    const int c = t / N, y = t - c * N;
-    wk[t] = T[((size_t)c * g.nxh + kx) * N + y];
+  // forward y-FFTs: J (and the naive mode's deposited rho) in one batch, or
+  // the stage currents stage by stage into the stage region
+  const double2* Jh = nullptr;
+  for (int st = 0; st < (nst ? nst : 1); ++st) {
+    const int ncol = nst ? 3 : 3 + d.naive;
+    const int cb = 3 * st;  // first T component of the batch
+    for (int t = threadIdx.x; t < ncol * N; t += blockDim.x) {
+      const int c = t / N, y = t - c * N;
+      wk[t] = T[((size_t)(cb + c) * g.nxh + kx) * N + y];
+    }
+    __syncthreads();
+    Jh = fft_lds<false>(wk, wk + ncol * N, N, ncol, tws);
+    if (nst) {
+      for (int t = threadIdx.x; t < 3 * N; t += blockDim.x) store[cb * N + t] = Jh[t];
+      __syncthreads();
+    }
   }
-  __syncthreads();
-  const double2* Jh = fft_lds<false>(wk, wk + ncol * N, N, ncol, tws);
   const double kxs = kx_sym(kx, g);
   const double scale = 1.0 / ((double)g.nx * g.ny);
   for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
     const double2 J0 = Jh[ky], J1 = Jh[N + ky], J2 = Jh[2 * N + ky];
     const ModeOut o = mode_update<SCHEME, K>(H, plane, (size_t)kx * N + ky, J0, J1, J2,
-                                          d.naive ? Jh + 3 * N + ky : nullptr, kxs, ky_sym(ky, g), sc, hs);
+                                          d.naive ? Jh + 3 * N + ky : nullptr, nst ? store + ky : nullptr, N, kxs,
+                                          ky_sym(ky, g), sc, hs);
     store[ky] = cscale(o.phi, scale);
     store[N + ky] = cscale(o.A[0], scale);
     store[2 * N + ky] = cscale(o.A[1], scale);
@@ -557,8 +595,13 @@ __global__ void __launch_bounds__(1024) k_field_diag(const double2* __restrict__
         Rn += sc.dirkB[i] * (1 - sc.dirkC[i]);
         Rn1 += sc.dirkB[i] * sc.dirkC[i];
       }
-      gt = cscale(csub(at(hs.phi[0], m), at(hs.phi[1], m)), -1.0);
-      gd = cscale(cadd(cscale(divA(hs.A[1]), Rn), cscale(divA(hs.A[0]), Rn1)), -sc.c * sc.c * sc.dt);
+      if (sc.substep) {  // stage-value gauge: v_phi + c^2 div A
+        gt = at(hs.vphi, m);
+        gd = cscale(divA(hs.A[0]), sc.c * sc.c);
+      } else {
+        gt = cscale(csub(at(hs.phi[0], m), at(hs.phi[1], m)), -1.0);
+        gd = cscale(cadd(cscale(divA(hs.A[1]), Rn), cscale(divA(hs.A[0]), Rn1)), -sc.c * sc.c * sc.dt);
+      }
       phi = at(hs.phi[0], m);
       rho = at(hs.rho[0], m);
       E[0] = csub(mul_i(cscale(phi, -kxs)), at(hs.vA, m));
@@ -649,9 +692,9 @@ size_t rows_r2c_lds_bytes(int nx, int ny) { return (size_t)(rows_r2c_R(nx, ny) +
 size_t rows_c2r_lds_bytes(int nx, int ny) { return (size_t)(2 * rows_c2r_R(nx, ny) + 1) * nx * sizeof(double2); }
 // inverse batch size of the column kernel and its LDS bytes (<= 160 KiB)
 int columns_nb(int ny) { return ny <= 256 ? 8 : (ny <= 512 ? 4 : 2); }
-size_t columns_lds_bytes(int ny) {
+size_t columns_lds_bytes(int ny, int nstore) {
   const int nb = columns_nb(ny);
-  return (size_t)(4 + std::max(8, 2 * nb) + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2);
+  return (size_t)(nstore + std::max(8, 2 * nb) + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2);
 }
 
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {

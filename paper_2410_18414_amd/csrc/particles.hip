@@ -64,10 +64,23 @@ __global__ void __launch_bounds__(256) k_untiled(const InstDesc* __restrict__ D,
     vz = nz;
   }
   if (MODE != 1) {  // position update and deposit with the newest velocity
-    x = wrapx<T>(x + vx * dt, T(g.lx));
-    y = wrapx<T>(y + vy * dt, T(g.ly));
-    p.x[i] = x;
-    p.y[i] = y;
+    if (MODE == 0 && sa.stage >= 0) {
+      // sub-stepped DIRK stage: deposit at x + c_i dt v into J planes
+      // 3i..3i+2; only the last stage writes x^{n+1}
+      if (sa.stage == d.sc.stages - 1) {
+        p.x[i] = wrapx<T>(x + vx * dt, T(g.lx));
+        p.y[i] = wrapx<T>(y + vy * dt, T(g.ly));
+      }
+      const T sdt = T(ph.dt * d.sc.dirkC[sa.stage]);
+      x = wrapx<T>(x + vx * sdt, T(g.lx));
+      y = wrapx<T>(y + vy * sdt, T(g.ly));
+      J += (size_t)3 * sa.stage * g.nx * g.ny;
+    } else {
+      x = wrapx<T>(x + vx * dt, T(g.lx));
+      y = wrapx<T>(y + vy * dt, T(g.ly));
+      p.x[i] = x;
+      p.y[i] = y;
+    }
     const T s = q * T(g.inv_area);
     if (d.jvstar) deposit_one<T, DEG>(x, y, s * (T(2) * vx - ux), s * (T(2) * vy - uy), s * (T(2) * vz - uz), J, g);
     else deposit_one<T, DEG>(x, y, s * vx, s * vy, s * vz, J, g);

@@ -86,6 +86,7 @@ struct SchemeCoef {
   double Cn[13];            // C_i / C_0 of the twice-applied operator
   double inv_alpha2;        // 1/alpha^2 of the single Helmholtz solve (BDF, CDF-2)
   int stages;               // DIRK family: 2 or 3
+  int substep;              // DIRK family: 1 = stage currents deposited per stage (PIC_FLAG_DIRK_SUBSTEP)
   double dirkA[3][3], dirkB[3], dirkC[3];
   double dt, c, eps0, mu0;
 };
@@ -140,7 +141,15 @@ struct InstDesc {
 struct StepArgs {
   int cur;    // current particle set (0/1)
   int vflip;  // 0: V0 = v^n, V1 = v^{n-1}; 1: swapped
+  int stage;  // deposit passes: -1 = x^{n+1} and J^{n+1}; i >= 0 = DIRK stage i of the
+              // sub-stepped currents (deposit at x + c_i dt v into J planes 3i..3i+2;
+              // the last stage also writes x^{n+1})
 };
+
+// real J planes of an instance: 3, a fourth (the naive mode's rho), or three per DIRK stage
+__host__ __device__ inline int j_planes(const SchemeCoef& sc, int naive) {
+  return sc.substep ? 3 * sc.stages : 3 + naive;
+}
 
 template <typename T>
 __host__ __device__ inline Parts<T> make_parts(const InstDesc& d, int set, int vflip) {
@@ -202,7 +211,7 @@ int rows_c2r_R(int nx, int ny);
 int columns_nb(int ny);
 size_t rows_r2c_lds_bytes(int nx, int ny);
 size_t rows_c2r_lds_bytes(int nx, int ny);
-size_t columns_lds_bytes(int ny);
+size_t columns_lds_bytes(int ny, int nstore);  // nstore: LDS store columns (4, or 3 per sub-stepped DIRK stage)
 // blocks per kx of the forward column kernel (4 for BDF-k and CDF-2, split
 // by output; 1 for DIRK-2) and the split kernel's LDS bytes
 int columns_parts(int scheme);

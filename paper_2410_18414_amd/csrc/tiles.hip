@@ -321,7 +321,10 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   const TileP tp = d.tp;
   const Parts<T> p = make_parts<T>(d, sa.cur, sa.vflip);
   const T* __restrict__ F = GATHER ? (d.F32 ? (const T*)(const void*)d.F32 : (const T*)(const void*)d.F64) : nullptr;
-  double* __restrict__ J = d.J;
+  // sub-stepped DIRK stage (deposit-only passes): deposit at x + c_i dt v into
+  // J planes 3i..3i+2; only the last stage writes x^{n+1}
+  const bool staged = !GATHER && sa.stage >= 0;
+  double* __restrict__ J = d.J + (staged ? (size_t)3 * sa.stage * d.g.nx * d.g.ny : 0);
   const int W = FIXED ? G::W : tp.win;
   const int WP = FIXED ? G::WP : tp.win_pad;  // plane stride of the LDS windows (field f at f*WP)
   // plane stride of the float64 J window: WP + 8 puts the three components of
@@ -504,10 +507,20 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       for (int a = 0; a < NW; ++a) wx[a] = wy[a] = T(0);
       T jx = T(0), jy = T(0), jz = T(0);
       if (act) {
-        x = wrapx<T>(x + vx * dt, T(g.lx));
-        y = wrapx<T>(y + vy * dt, T(g.ly));
-        p.x[i] = x;
-        p.y[i] = y;
+        if (staged) {
+          if (sa.stage == d.sc.stages - 1) {
+            p.x[i] = wrapx<T>(x + vx * dt, T(g.lx));
+            p.y[i] = wrapx<T>(y + vy * dt, T(g.ly));
+          }
+          const T sdt = T(ph.dt * d.sc.dirkC[sa.stage]);
+          x = wrapx<T>(x + vx * sdt, T(g.lx));
+          y = wrapx<T>(y + vy * sdt, T(g.ly));
+        } else {
+          x = wrapx<T>(x + vx * dt, T(g.lx));
+          y = wrapx<T>(y + vy * dt, T(g.ly));
+          p.x[i] = x;
+          p.y[i] = y;
+        }
         const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
         if (in_box(xi, eta, g)) {
           S::eval(xi, sx, wx);

@@ -27,6 +27,7 @@ FLAG_NO_GRAPH = 4
 FLAG_ADJOINT = 8
 FLAG_NAIVE_RHO = 16   # rho deposited with the spline instead of continuity (the paper's naive update)
 FLAG_JVSTAR = 32      # J carries v* = 2 v^n - v^{n-1} instead of v^n
+FLAG_DIRK_SUBSTEP = 64  # DIRK stage currents from particles sub-stepped to each stage time
 FIELD_J = 0
 FIELD_MESH = 1
 DIAG_NAMES = ("gauge_l2", "gauge_scale", "gauss_l2", "gauss_scale", "charge", "energy",
@@ -276,8 +277,16 @@ def set_particles(ctx, parts):
     ctx.check(load().pic_set_particles(ctx.handle, _ptr(parts)))
 
 
+def j_planes(cfg):
+    """Real J planes PIC_FIELD_J exports: 3, or 3 per DIRK stage when the
+    stage currents are sub-stepped."""
+    if cfg.flags & FLAG_DIRK_SUBSTEP:
+        return 9 if cfg.scheme == SCHEMES["dirk3"] else 6
+    return 3
+
+
 def get_field(ctx, which):
-    nf = 3 if which == FIELD_J else 12
+    nf = j_planes(ctx.cfgs[ctx.sel]) if which == FIELD_J else 12
     out = torch.empty((nf, ctx.ny, ctx.nx), dtype=torch.float64, device=ctx.device)
     ctx.check(load().pic_get_field(ctx.handle, int(which), _ptr(out)))
     return out
