@@ -87,12 +87,18 @@ def maxwellian_cloud(nx, ny, ppc, seed, dx=0.1, sigma=0.1, vth=0.05):
 
 def ensemble(count=64, draw_seed=4999, seed_base=4000, sizes=(32, 64, 128, 256), ppc_range=(4, 64)):
     """The uneven ensemble: `count` Maxwellian clouds (sigma = 0.1 L, v_th =
-    0.05c) whose grid sides are drawn independently from `sizes` and whose
-    particles per cell are uniform integers in `ppc_range`; the draws use
-    `draw_seed`, member i samples its particles with seed seed_base + i."""
+    0.05c) whose grid sides are drawn independently from `sizes` (a tuple of
+    sides, or a (lo, hi) range given as a slice for uniform integers in
+    [lo, hi]) and whose particles per cell are uniform integers in
+    `ppc_range`; the draws use `draw_seed`, member i samples its particles
+    with seed seed_base + i."""
     rng = np.random.default_rng(draw_seed)
-    nx = rng.choice(sizes, count)
-    ny = rng.choice(sizes, count)
+    if isinstance(sizes, slice):
+        nx = rng.integers(sizes.start, sizes.stop + 1, count)
+        ny = rng.integers(sizes.start, sizes.stop + 1, count)
+    else:
+        nx = rng.choice(sizes, count)
+        ny = rng.choice(sizes, count)
     ppc = rng.integers(ppc_range[0], ppc_range[1] + 1, count)
     return [maxwellian_cloud(int(nx[i]), int(ny[i]), int(ppc[i]), seed_base + i, dx=0.1, sigma=0.1, vth=0.05)
             for i in range(count)]

@@ -33,7 +33,7 @@ def direct_dft2(f):
     return out
 
 
-@pytest.mark.parametrize("nx,ny", [(4, 4), (8, 6), (16, 16)])
+@pytest.mark.parametrize("nx,ny", [(4, 4), (8, 6), (16, 16), (9, 6), (7, 11), (15, 5), (12, 10)])
 def test_fft_matches_direct_dft(nx, ny):
     f = np.random.default_rng(nx * ny).normal(size=(ny, nx))
     np.testing.assert_allclose(spectral.fft2(f), direct_dft2(f), atol=1e-11)
@@ -57,6 +57,31 @@ def test_spectral_derivatives_of_trig_polynomial():
     np.testing.assert_allclose(
         lf, -(ax ** 2 + ay ** 2) * np.sin(ax * X) * np.cos(ay * Y)
         - 0.5 * (2 * np.pi * 7 / lx) ** 2 * np.cos(2 * np.pi * 7 / lx * X), atol=1e-10)
+
+
+@pytest.mark.parametrize("nx,ny", [(15, 9), (12, 7), (11, 10)])
+def test_spectral_derivatives_on_odd_and_other_grids(nx, ny):
+    """Sides that are odd or not powers of two: every resolved mode, up to the
+    highest one of an odd side (which has no Nyquist partner), is
+    differentiated exactly."""
+    lx, ly = 1.7, 0.9
+    ikx, iky, lap = spectral.symbols(nx, ny, lx, ly)
+    X, Y = np.meshgrid(np.arange(nx) * lx / nx, np.arange(ny) * ly / ny)
+    mx = (nx - 1) // 2          # highest x mode below any Nyquist index
+    my = (ny - 1) // 2
+    ax, ay = 2 * np.pi * mx / lx, 2 * np.pi * my / ly
+    f = np.cos(ax * X + 0.3) * np.sin(ay * Y - 0.2) + np.sin(2 * np.pi / lx * X)
+    fh = spectral.fft2(f)
+    dfx = spectral.ifft2(ikx * fh, nx, ny)
+    dfy = spectral.ifft2(iky * fh, nx, ny)
+    lf = spectral.ifft2(lap * fh, nx, ny)
+    np.testing.assert_allclose(dfx, -ax * np.sin(ax * X + 0.3) * np.sin(ay * Y - 0.2)
+                               + 2 * np.pi / lx * np.cos(2 * np.pi / lx * X), atol=1e-11)
+    np.testing.assert_allclose(dfy, ay * np.cos(ax * X + 0.3) * np.cos(ay * Y - 0.2), atol=1e-11)
+    np.testing.assert_allclose(lf, -(ax ** 2 + ay ** 2) * np.cos(ax * X + 0.3) * np.sin(ay * Y - 0.2)
+                               - (2 * np.pi / lx) ** 2 * np.sin(2 * np.pi / lx * X), atol=1e-9)
+    if nx % 2:
+        assert np.count_nonzero(ikx[0] == 0) == 1     # no Nyquist index: only kx = 0 vanishes
 
 
 def test_nyquist_rule_div_grad_equals_laplacian():

@@ -132,10 +132,11 @@ def _idft(fh, nx, ny):
     return out / (nx * ny)
 
 
-@pytest.mark.parametrize("scheme", ["bdf", "cdf2", "dirk2"])
-def test_whole_step_brute_force(scheme):
+@pytest.mark.parametrize("scheme,nx,ny", [("bdf", 4, 4), ("cdf2", 4, 4), ("dirk2", 4, 4),
+                                          ("bdf", 5, 3), ("dirk2", 6, 5)])
+def test_whole_step_brute_force(scheme, nx, ny):
     rng = np.random.default_rng(5)
-    p = pic.Params(4, 4, 1.0, 1.0, 2, scheme, 0.1, q=-0.4, m=0.5, bdf_order=2)
+    p = pic.Params(nx, ny, 1.0, 1.0, 2, scheme, 0.1, q=-0.4, m=0.5, bdf_order=2)
     x, y = rng.uniform(0, 1, 3), rng.uniform(0, 1, 3)
     P = rng.normal(0, 0.3, (3, 3))
     fast = pic.State(p, x, y, P)
@@ -159,3 +160,19 @@ def test_whole_step_brute_force(scheme):
     for key in ("x", "y", "P", "v", "vprev"):
         np.testing.assert_allclose(fast.part[key], slow.part[key], rtol=0, atol=1e-13)
     np.testing.assert_allclose(fast.fields, F, atol=1e-12)
+
+
+@pytest.mark.parametrize("scheme,nx,ny", [("bdf", 24, 18), ("cdf2", 21, 15), ("dirk2", 20, 27),
+                                          ("bdf", 37, 29)])
+def test_gauge_and_gauss_on_other_grids(scheme, nx, ny):
+    """Sides that are not powers of two (even, odd, prime): the gauge residual
+    (and Gauss's law for BDF-k and CDF-2) at round-off."""
+    from paper_2410_18414_amd import workloads
+    w = workloads.cloud(nx=nx, ny=ny, ppc=3, seed=nx * ny, drift=0.2, vth=0.05)
+    p = pic.Params(w["nx"], w["ny"], w["lx"], w["ly"], 3, scheme, w["dt"], q=w["q"], m=w["m"])
+    s = pic.State(p, w["x"], w["y"], w["P"])
+    s.step(10)
+    r = diagnostics.residuals(s)
+    assert r["gauge_l2"] <= 1e3 * EPS * r["gauge_scale"], r
+    if scheme != "dirk2":
+        assert r["gauss_l2"] <= 1e3 * EPS * r["gauss_scale"], r
