@@ -160,6 +160,38 @@ def bench_batched(steps, warmup):
                 tile_plan_cached=bool(plan.get("cached")))
 
 
+def bench_batched_integer_sides(steps=5, warmup=1):
+    """The uneven ensemble under the strict reading of its grid draw: 64
+    Maxwellian clouds whose sides are uniform integers in [32, 256] (most not
+    powers of two: mixed-radix FFTs, untiled particle passes), 4..64
+    particles/cell, cubic, BDF-2, float32, as one context."""
+    import torch
+    from paper_2410_18414_amd import pic, workloads
+    ws = workloads.ensemble(sizes=slice(32, 256))
+    dev = torch.device("cuda:0")
+    total = sum(len(w["x"]) for w in ws)
+    cfgs = [pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=3, scheme="bdf", bdf_order=2,
+                            dtype="f32", q=w["q"], m=w["m"], max_particles=len(w["x"])) for w in ws]
+    ctx = pic.Context(cfgs)
+    for i, w in enumerate(ws):
+        pic.select_instance(ctx, i)
+        pic.init_particles(ctx, torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
+                           torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev))
+    pic.step_batched(ctx, warmup)
+    a, b = _events(ctx.stream)
+    torch.cuda.synchronize()
+    a.record(ctx.stream)
+    pic.step_batched(ctx, steps)
+    b.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    pow2 = sum(1 for w in ws if not (w["nx"] & (w["nx"] - 1) or w["ny"] & (w["ny"] - 1)))
+    ctx.close()
+    return dict(workload="ensemble of 64 Maxwellian clouds, sides uniform integers in [32, 256], 4..64 ppc, "
+                         "cubic, BDF-2, f32", instances=len(ws), power_of_two_instances=pow2, particles=total,
+                steps=steps, ms_per_step=round(ms, 5), value=round(total / (ms * 1e-3), 1))
+
+
 def bench_naive(steps=20):
     """The paper's naive comparison (rho mapped with the spline instead of
     continuity) on the plain workload: its step rate, and the relative gauge
@@ -406,6 +438,7 @@ def main():
     ctx.close()
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_steps, 6)
+        out["batched_integer_sides"] = bench_batched_integer_sides()
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint()
     if not args.no_naive:

@@ -109,8 +109,8 @@ HistSlots slots_of(const Hist& r, int64_t s) {
 bool validate(const pic_config_t* c, std::string& msg) {
   if (!c) { msg = "cfg is NULL"; return false; }
   if (c->abi_version != PIC_ABI_VERSION) { msg = "abi_version mismatch"; return false; }
-  if (!pow2(c->nx) || !pow2(c->ny) || c->nx < 8 || c->ny < 8 || c->nx > 1024 || c->ny > 1024) {
-    msg = "nx, ny must be powers of two in [8, 1024]";
+  if (c->nx < 8 || c->ny < 8 || c->nx > 1024 || c->ny > 1024) {
+    msg = "nx, ny must be in [8, 1024]";
     return false;
   }
   if (!(c->lx > 0) || !(c->ly > 0) || !std::isfinite(c->lx) || !std::isfinite(c->ly)) {
@@ -140,8 +140,10 @@ bool validate(const pic_config_t* c, std::string& msg) {
     return false;
   }
   if (c->sort_interval < 0) { msg = "sort_interval must be >= 0"; return false; }
-  if (c->tile_cells && (!pow2(c->tile_cells) || c->tile_cells < 4 || c->tile_cells > 64 ||
-                        c->tile_cells > c->nx || c->tile_cells > c->ny)) {
+  // (tiles apply to power-of-two grids only; other grids take the untiled passes)
+  if (c->tile_cells && pow2(c->nx) && pow2(c->ny) &&
+      (!pow2(c->tile_cells) || c->tile_cells < 4 || c->tile_cells > 64 || c->tile_cells > c->nx ||
+       c->tile_cells > c->ny)) {
     msg = "tile_cells must be 0 or a power of two in [4, 64] not above nx, ny";
     return false;
   }
@@ -176,7 +178,7 @@ TileP plan_tiles(const pic_config_t& c) {
   TileP t{};
   t.nx = c.nx;
   t.ny = c.ny;
-  t.ts = c.tile_cells ? c.tile_cells : std::min(16, std::min(c.nx, c.ny));
+  t.ts = c.tile_cells && pow2(c.nx) && pow2(c.ny) ? c.tile_cells : std::min(16, std::min(c.nx, c.ny));
   t.ntx = c.nx / t.ts;
   t.nty = c.ny / t.ts;
   t.ntiles = t.ntx * t.nty;
@@ -566,6 +568,13 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
       return PIC_ERR_UNSUPPORTED;
     }
   }
+  if (cfgs[0].flags & PIC_FLAG_ADJOINT) {
+    for (int i = 0; i < ninst; ++i)
+      if (!pow2(cfgs[i].nx) || !pow2(cfgs[i].ny)) {
+        g_err = "the adjoint needs power-of-two grid sides";
+        return PIC_ERR_UNSUPPORTED;
+      }
+  }
   if ((cfgs[0].flags & PIC_FLAG_JVSTAR) && (cfgs[0].flags & PIC_FLAG_ADJOINT)) {
     g_err = "the adjoint is not available with v* in the current";
     return PIC_ERR_UNSUPPORTED;
@@ -618,7 +627,10 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
   c->degree = cfgs[0].spline_degree;
   c->scheme = scheme_family(cfgs[0].scheme);
   // the naive charge deposit runs on the untiled passes
-  c->sorted = (cfgs[0].flags & (PIC_FLAG_NO_SORT | PIC_FLAG_NAIVE_RHO)) == 0;
+  // cell-sorted tiles need power-of-two grids (every instance of an ensemble)
+  bool all_pow2 = true;
+  for (int i = 0; i < ninst; ++i) all_pow2 = all_pow2 && pow2(cfgs[i].nx) && pow2(cfgs[i].ny);
+  c->sorted = (cfgs[0].flags & (PIC_FLAG_NO_SORT | PIC_FLAG_NAIVE_RHO)) == 0 && all_pow2;
   c->d_desc = (InstDesc*)c->ws;
   c->d_diag = (double*)(c->ws + align_up(ninst * sizeof(InstDesc)));
   c->inst.resize(ninst);
@@ -684,9 +696,9 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.R_c2r = rows_c2r_R(cf.nx, cf.ny);
     d.nb_col = columns_nb(cf.ny);
     // flattened block ranges
-    const int nb[BK_NKINDS] = {cf.ny / d.R_r2c * j_planes(d.sc, d.naive),
+    const int nb[BK_NKINDS] = {ceil_div(cf.ny, d.R_r2c) * j_planes(d.sc, d.naive),
                                (cf.nx / 2 + 1) * columns_parts(scheme_family(cf.scheme)),
-                               cf.ny / d.R_c2r * 6, d.tp.max_work,
+                               ceil_div(cf.ny, d.R_c2r) * 6, d.tp.max_work,
                                ceil_div(cf.max_particles, 256), ceil_div(cf.max_particles, 1024),
                                ceil_div(d.tp.ntiles, 4)};
     for (int k = 0; k < BK_NKINDS; ++k) {
@@ -727,8 +739,8 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     delete c;
     return PIC_ERR_HIP;
   }
-  const size_t lds_need = std::max({c->lds_col, c->lds_adj_col, c->lds_r2c, c->lds_c2r, c->lds_tiled[0], c->lds_tiled[1],
-                                    c->lds_tiled[2]});
+  size_t lds_need = std::max({c->lds_col, c->lds_adj_col, c->lds_r2c, c->lds_c2r});
+  if (c->sorted) lds_need = std::max({lds_need, c->lds_tiled[0], c->lds_tiled[1], c->lds_tiled[2]});
   if (lds_need > (size_t)max_lds) {
     g_err = "grid or tile too large for this device's LDS";
     delete c;

@@ -32,16 +32,19 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // rows: R real rows (R even) of one J component -> R/2 complex FFTs along x.
-// Flattened over instances: local block = component * (ny/R) + row group.
+// Flattened over instances: local block = component * ceil(ny/R) + row group;
+// rows past ny in the last group (ny not a multiple of R) read as zero and are
+// not written.
 // adj: the same transform of the 11 adjoint mesh fields LF into LS.
 __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D, int ninst, int adj) {
   extern __shared__ double2 sm[];
   const int ii = find_inst(D, ninst, BK_R2C, blockIdx.x);
   const InstDesc& d = D[ii];
   const GridP g = d.g;
-  const int R = d.R_r2c, ngr = g.ny / R;
+  const int R = d.R_r2c, ngr = (g.ny + R - 1) / R;
   const int lb = blockIdx.x - d.blk[BK_R2C];
   const int c = lb / ngr, y0 = (lb - c * ngr) * R;
+  const int nr = min(R, g.ny - y0);  // rows of this group
   double* __restrict__ Jc = (adj ? d.LF : d.J) + (size_t)c * g.nx * g.ny;
   // the naive mode's rho plane restarts from the ion background
   const double* __restrict__ reset = (!adj && c == 3) ? d.RB : nullptr;
@@ -54,17 +57,20 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     const int r = t / N, x = t - r * N;
     const size_t i0 = (size_t)(y0 + 2 * r) * N + x, i1 = i0 + N;
-    a[t] = make_double2(Jc[i0], Jc[i1]);
-    Jc[i0] = reset ? reset[i0] : 0.0;  // consumed: ready for the next deposit (or adjoint scatter)
-    Jc[i1] = reset ? reset[i1] : 0.0;
+    const bool h0 = 2 * r < nr, h1 = 2 * r + 1 < nr;
+    a[t] = make_double2(h0 ? Jc[i0] : 0.0, h1 ? Jc[i1] : 0.0);
+    // consumed: ready for the next deposit (or adjoint scatter)
+    if (h0) Jc[i0] = reset ? reset[i0] : 0.0;
+    if (h1) Jc[i1] = reset ? reset[i1] : 0.0;
   }
   __syncthreads();
   const double2* res = fft_lds<false>(a, b, N, B, tws);
   // split the two real transforms: X = (Z_k + conj Z_{N-k})/2, Y = (Z_k - conj Z_{N-k})/(2i)
   for (int t = threadIdx.x; t < g.nxh * R; t += blockDim.x) {
     const int k = t / R, rr = t - k * R, r = rr >> 1;
+    if (rr >= nr) continue;
     const double2 zk = res[r * N + k];
-    const double2 zn = cconj(res[r * N + ((N - k) & (N - 1))]);
+    const double2 zn = cconj(res[r * N + (k ? N - k : 0)]);
     double2 o;
     if ((rr & 1) == 0) {
       o = cscale(cadd(zk, zn), 0.5);
@@ -85,10 +91,10 @@ struct ModeOut {
 };
 
 // K: the BDF order as a compile-time constant (0 for the other steppers), so
-// that every history slot index is static and all history loads issue at once
-template <int SCHEME, int K>
+// that every history slot index is static and all history loads issue at once.
 // stage: the sub-stepped DIRK stage currents of this mode (component l of
 // stage i at stage[(3 i + l) * sstride]), else null
+template <int SCHEME, int K>
 __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, double2 J0, double2 J1,
                                double2 J2, const double2* rho_dep, const double2* stage, int sstride, double kxs,
                                double kys, const SchemeCoef& sc, const HistSlots& hs) {
@@ -480,13 +486,15 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
   const int ii = find_inst(D, ninst, BK_C2R, blockIdx.x);
   const InstDesc& d = D[ii];
   const GridP g = d.g;
-  const int R = d.R_c2r, ngr = g.ny / R;
+  const int R = d.R_c2r, ngr = (g.ny + R - 1) / R;
   const int lb = blockIdx.x - d.blk[BK_C2R];
   const int pr = lb / ngr, y0 = (lb - pr * ngr) * R;
+  const int nr = min(R, g.ny - y0);  // rows of this group (the last may be partial)
   const double2* __restrict__ U = adj ? d.LS : d.U;
   double* __restrict__ F64 = adj ? d.LJ : d.F64;
   float* __restrict__ F32 = adj ? nullptr : d.F32;
-  const int N = g.nx, h = N >> 1;
+  const int N = g.nx;
+  const int nyq = (N & 1) ? -1 : N >> 1;  // Nyquist bin (even nx only)
   double2* a = sm;
   double2* b = sm + R * N;
   double2* tws = sm + 2 * R * N;  // twiddles staged in LDS
@@ -496,22 +504,27 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
   const bool has1 = !adj || s1 < 3;
   for (int t = threadIdx.x; t < g.nxh * R; t += blockDim.x) {
     const int k = t / R, r = t - k * R;
-    const double kxs = 2.0 * M_PI * k / g.lx * ((k == h) ? 0.0 : 1.0);
+    if (r >= nr) {  // past the last row: zero input, output not written
+      a[r * N + k] = make_double2(0.0, 0.0);
+      if (k > 0 && k != nyq) a[r * N + N - k] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double kxs = 2.0 * M_PI * k / g.lx * ((k == nyq) ? 0.0 : 1.0);
     double2 X = U[((size_t)g0 * g.nxh + k) * g.ny + y0 + r];
     double2 Y = has1 ? U[((size_t)g1 * g.nxh + k) * g.ny + y0 + r] : make_double2(0.0, 0.0);
     if (!adj && kMulKx[s0]) X = mul_i(cscale(X, kxs));
     if (!adj && kMulKx[s1]) Y = mul_i(cscale(Y, kxs));
-    if (k == 0 || k == h) {  // real-signal spectrum: these bins are real
+    if (k == 0 || k == nyq) {  // real-signal spectrum: these bins are real
       X.y = 0.0;
       Y.y = 0.0;
     }
     a[r * N + k] = cadd(X, mul_i(Y));
-    if (k > 0 && k < h) a[r * N + N - k] = cadd(cconj(X), mul_i(cconj(Y)));
+    if (k > 0 && k != nyq) a[r * N + N - k] = cadd(cconj(X), mul_i(cconj(Y)));
   }
   __syncthreads();
   const double2* res = fft_lds<true>(a, b, N, R, tws);
   const size_t plane = (size_t)g.nx * g.ny;
-  for (int t = threadIdx.x; t < R * N; t += blockDim.x) {
+  for (int t = threadIdx.x; t < nr * N; t += blockDim.x) {
     const int r = t / N, x = t - r * N;
     const size_t o = (size_t)(y0 + r) * N + x;
     const double2 z = res[t];

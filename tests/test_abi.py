@@ -38,7 +38,7 @@ def _cfg(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(nx=30), dict(ny=4), dict(nx=2048), dict(degree=6), dict(degree=0), dict(bdf_order=7),
+    dict(nx=7), dict(ny=4), dict(nx=2048), dict(ny=1025), dict(degree=6), dict(degree=0), dict(bdf_order=7),
     dict(dt=0.0), dict(dt=2.0), dict(c=2.0), dict(max_particles=0), dict(m=0.0), dict(lx=-1.0),
     dict(flags=128)])
 def test_invalid_configs_rejected(bad):
@@ -49,6 +49,7 @@ def test_invalid_configs_rejected(bad):
 
 def test_valid_config_and_history_counts():
     assert pic.workspace_bytes(_cfg()) > 0
+    assert pic.workspace_bytes(_cfg(nx=30, ny=1021)) > 0      # any side in [8, 1024]
     assert pic.history_fields(_cfg(scheme="bdf", bdf_order=2)) == 18
     assert pic.history_fields(_cfg(scheme="bdf", bdf_order=3)) == 27
     assert pic.history_fields(_cfg(scheme="cdf2")) == 18
@@ -79,12 +80,13 @@ def test_create_rejects_bad_workspace_without_gpu():
                                           (pic.FLAG_NAIVE_RHO | pic.FLAG_ADJOINT, "bdf"),
                                           (pic.FLAG_NAIVE_RHO, "cdf2_semi"),
                                           (pic.FLAG_DIRK_SUBSTEP, "bdf"),
-                                          (pic.FLAG_DIRK_SUBSTEP | pic.FLAG_NAIVE_RHO, "dirk2")])
+                                          (pic.FLAG_DIRK_SUBSTEP | pic.FLAG_NAIVE_RHO, "dirk2"),
+                                          (pic.FLAG_ADJOINT, "bdf-odd")])
 def test_create_rejects_unsupported_combinations_without_gpu(flags, scheme):
     """Unsupported flag/scheme combinations fail (PIC_ERR_UNSUPPORTED) before
     the workspace is looked at."""
     lib = pic.load()
-    cfg = _cfg(flags=flags, scheme=scheme)
+    cfg = _cfg(flags=flags, scheme="bdf", nx=30) if scheme == "bdf-odd" else _cfg(flags=flags, scheme=scheme)
     h = ctypes.c_void_p()
     assert lib.pic_create(ctypes.byref(cfg), None, 0, None, ctypes.byref(h)) == 2
     assert not h.value
