@@ -690,6 +690,16 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.LJ = adj ? (double*)(b + in.L.LJ) : nullptr;
     d.naive = (cf.flags & PIC_FLAG_NAIVE_RHO) ? 1 : 0;
     d.jvstar = (cf.flags & PIC_FLAG_JVSTAR) ? 1 : 0;
+    {
+      // fixed-point deposit exponent (float32 particles): the largest single
+      // contribution B = |q| c max(w) / (dx dy), max(w) = M_deg(0)^2, |v| < c
+      // (3c for v*); B = m 2^p with m in [0.5, 1) gives B 2^(29 - p) < 2^29
+      static const double m0[6] = {0.0, 1.0, 0.75, 2.0 / 3.0, 115.0 / 192.0, 0.55};
+      const double B = std::fabs(cf.q) * cf.c * (d.jvstar ? 3.0 : 1.0) * g.inv_area * m0[cf.spline_degree] *
+                       m0[cf.spline_degree];
+      int p = 0;
+      d.qe0 = (B > 0 && std::isfinite(B)) ? (std::frexp(B, &p), 29 - p) : 0;
+    }
     d.RB = d.naive ? (double*)(b + in.L.RB) : nullptr;
     d.n = 0;
     d.R_r2c = rows_r2c_R(cf.nx, cf.ny);

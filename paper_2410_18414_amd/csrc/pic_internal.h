@@ -131,6 +131,7 @@ struct InstDesc {
   double* RB;               // naive charge deposit (PIC_FLAG_NAIVE_RHO, else null): [ny][nx] ion background
   int naive;                // 1: J holds a fourth plane, the deposited rho; T a fourth component
   int jvstar;               // 1: J carries v* = 2 v - v_prev (PIC_FLAG_JVSTAR)
+  int qe0;                  // float32 fixed-point deposit: B 2^qe0 < 2^29 for the contribution bound B
   TileBufs tb;
   int64_t n;                // particles loaded
   int R_r2c, R_c2r, nb_col; // rows per block of the row kernels; inverse batch of the column kernel

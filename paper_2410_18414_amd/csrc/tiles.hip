@@ -34,6 +34,10 @@ constexpr int kThreads = 256;
 // slots per node of the LDS field window: the eleven gathered fields and one
 // pad, so that a node's record is three 16-byte (float) or six (double) vectors
 constexpr int kNodeSlots = kFieldSlots;
+// fixed-point rounding by one FMA: 1.5 * 2^23 and its bit pattern
+constexpr float kMagic = 12582912.0f;
+constexpr uint32_t kMagicBits = 0x4B400000u;
+constexpr uint64_t kMagicPair = ((uint64_t)kMagicBits << 32) | kMagicBits;
 
 __device__ __forceinline__ void load_node(const float* p, float* q) {
   const float4* v = reinterpret_cast<const float4*>(p);
@@ -433,22 +437,20 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   // Float32 particles deposit in fixed point: J_x and J_y as one packed pair
   // of int32 in a 64-bit integer atomic, J_z in a 32-bit one (two LDS atomics
   // per node instead of three float64 ones).  The scale is a power of two
-  // chosen per chunk so that no window sum can leave int32: every
-  // contribution is bounded by |q| c max(w) / (dx dy) (|v| < c; 3c for
-  // |2 v - v_prev|), and a node collects at most one per particle of the chunk.
+  // 2^e chosen per chunk: every contribution is bounded by B = |q| c max(w) /
+  // (dx dy) (|v| < c; 3c for |2 v - v_prev|), and B 2^qe0 < 2^29 (qe0 from the
+  // host, d.qe0), so with e = qe0 - max(ceil(log2 count), 8) a node's sum over
+  // the chunk stays below 2^29 and a single contribution below 2^21.
   unsigned long long* jxy_w = reinterpret_cast<unsigned long long*>(jw);     // [JWP]
   uint32_t* jz_w = reinterpret_cast<uint32_t*>(jw + JWP);                      // [JWP]
   float qscale = 1.0f;
   double inv_qscale = 1.0;
   if (FIXEDPT) {
-    // largest 2-D weight: M_DEG(0)^2
-    const double m0 = DEG == 1 ? 1.0 : (DEG == 2 ? 0.75 : (DEG == 3 ? 2.0 / 3.0 : (DEG == 4 ? 115.0 / 192.0 : 0.55)));
-    const double wmax = m0 * m0;
-    const double cmax = fabs(ph.q) * ph.c * (jv ? 3.0 : 1.0) * g.inv_area * wmax * (double)max(it.z, 1);
-    int e = cmax > 0 ? (int)floor(log2(1073741824.0 / cmax)) : 0;
-    e = e > 100 ? 100 : (e < -100 ? -100 : e);  // a float scale, whatever q, c and the cell area
-    qscale = (float)ldexp(1.0, e);
-    inv_qscale = ldexp(1.0, -e);
+    const int lz = it.z > 1 ? 32 - __clz(it.z - 1) : 0;  // ceil(log2 count)
+    int e = d.qe0 - (lz > 8 ? lz : 8);
+    e = e > 100 ? 100 : (e < -100 ? -100 : e);  // a normal float scale, whatever q, c and the cell area
+    qscale = __int_as_float((e + 127) << 23);
+    inv_qscale = __longlong_as_double((long long)(1023 - e) << 52);
   }
   for (int k0 = 0; k0 < it.z; k0 += blockDim.x) {
     const int k = k0 + threadIdx.x;
@@ -573,16 +575,18 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
 #pragma unroll
             for (int a = 0; a < NW; ++a) {
               const T w = wxr[a] * wyr[b];
-              // round to nearest even: unbiased at the exact halves that
-              // scaled float32 products often are (rounding halves up would
-              // shift the mean current)
-              const int ix = __float2int_rn(sjx * w);
-              const int iy = __float2int_rn(sjy * w);
-              const int iz = __float2int_rn(sjz * w);
-              // (int64) ix + 2^32 (int64) iy, modulo 2^64
-              const uint64_t pk = (uint64_t)(int64_t)ix + ((uint64_t)(uint32_t)iy << 32);
+              // the exact product rounded to the nearest integer, ties to
+              // even (unbiased at the exact halves that scaled float32
+              // products often are), in one FMA: for |s w| < 2^22 the sum
+              // s w + 1.5 * 2^23 has unit spacing, so its bits are
+              // kMagicBits + round(s w)
+              const uint32_t bx = __float_as_uint(__builtin_fmaf(sjx, w, kMagic));
+              const uint32_t by = __float_as_uint(__builtin_fmaf(sjy, w, kMagic));
+              const uint32_t bz = __float_as_uint(__builtin_fmaf(sjz, w, kMagic));
+              // (int64) ix + 2^32 (int64) iy modulo 2^64, ix = bx - kMagicBits, iy = by - kMagicBits
+              const uint64_t pk = (((uint64_t)by << 32) | bx) - kMagicPair;
               atomicAdd(reinterpret_cast<unsigned long long*>(xy_row + cxy[a]), (unsigned long long)pk);
-              atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a]), (uint32_t)iz);
+              atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a]), bz - kMagicBits);
             }
           }
         }
