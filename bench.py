@@ -160,24 +160,33 @@ def bench_batched(steps, warmup):
                 tile_plan_cached=bool(plan.get("cached")))
 
 
-def bench_batched_integer_sides(steps=5, warmup=1):
+def bench_batched_integer_sides(steps=20, warmup=6):
     """The uneven ensemble under the strict reading of its grid draw: 64
-    Maxwellian clouds whose sides are uniform integers in [32, 256] (most not
-    powers of two: mixed-radix FFTs, untiled particle passes), 4..64
-    particles/cell, cubic, BDF-2, float32, as one context."""
+    Maxwellian clouds whose sides are uniform integers in [32, 256] (none a
+    power of two here: mixed-radix FFTs, partial tiles, the generic tiled
+    kernel), 4..64 particles/cell, cubic, BDF-2, float32, as one context with
+    the autotuner's tile plan."""
     import torch
-    from paper_2410_18414_amd import pic, workloads
+    from paper_2410_18414_amd import autotune, pic, workloads
     ws = workloads.ensemble(sizes=slice(32, 256))
     dev = torch.device("cuda:0")
+    data = [(torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
+             torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev)) for w in ws]
     total = sum(len(w["x"]) for w in ws)
-    cfgs = [pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=3, scheme="bdf", bdf_order=2,
-                            dtype="f32", q=w["q"], m=w["m"], max_particles=len(w["x"])) for w in ws]
-    ctx = pic.Context(cfgs)
-    for i, w in enumerate(ws):
-        pic.select_instance(ctx, i)
-        pic.init_particles(ctx, torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
-                           torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev))
-    pic.step_batched(ctx, warmup)
+
+    def make_cfgs():
+        return [pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=3, scheme="bdf", bdf_order=2,
+                                dtype="f32", q=w["q"], m=w["m"], max_particles=len(w["x"])) for w in ws]
+
+    def load(ctx):
+        for i, (x, y, P) in enumerate(data):
+            pic.select_instance(ctx, i)
+            pic.init_particles(ctx, x, y, P)
+
+    plan = autotune.tune("ensemble64-intsides32-256-draw4999-seeds4000-cubic-bdf2-f32", make_cfgs, load)
+    ctx = pic.Context(autotune.apply(make_cfgs(), plan))
+    load(ctx)
+    pic.step_batched(ctx, max(warmup, pic.graph_period(ctx) + 1))
     a, b = _events(ctx.stream)
     torch.cuda.synchronize()
     a.record(ctx.stream)
@@ -189,7 +198,8 @@ def bench_batched_integer_sides(steps=5, warmup=1):
     ctx.close()
     return dict(workload="ensemble of 64 Maxwellian clouds, sides uniform integers in [32, 256], 4..64 ppc, "
                          "cubic, BDF-2, f32", instances=len(ws), power_of_two_instances=pow2, particles=total,
-                steps=steps, ms_per_step=round(ms, 5), value=round(total / (ms * 1e-3), 1))
+                steps=steps, ms_per_step=round(ms, 5), value=round(total / (ms * 1e-3), 1),
+                tile_plan={k: plan[k] for k in autotune.KNOBS}, tile_plan_cached=bool(plan.get("cached")))
 
 
 def bench_naive(steps=20):

@@ -140,15 +140,18 @@ bool validate(const pic_config_t* c, std::string& msg) {
     return false;
   }
   if (c->sort_interval < 0) { msg = "sort_interval must be >= 0"; return false; }
-  // (tiles apply to power-of-two grids only; other grids take the untiled passes)
-  if (c->tile_cells && pow2(c->nx) && pow2(c->ny) &&
-      (!pow2(c->tile_cells) || c->tile_cells < 4 || c->tile_cells > 64 || c->tile_cells > c->nx ||
-       c->tile_cells > c->ny)) {
+  if (c->tile_cells && (!pow2(c->tile_cells) || c->tile_cells < 4 || c->tile_cells > 64 ||
+                        c->tile_cells > c->nx || c->tile_cells > c->ny)) {
     msg = "tile_cells must be 0 or a power of two in [4, 64] not above nx, ny";
     return false;
   }
   if (c->chunk && (c->chunk < 64 || c->chunk > 65536)) { msg = "chunk must be 0 or in [64, 65536]"; return false; }
   if (c->slack < 0 || c->slack > 8) { msg = "slack must be in [0, 8]"; return false; }
+  // the tiled passes wrap window offsets by one period on such grids
+  if ((!pow2(c->nx) || !pow2(c->ny)) && (c->slack ? c->slack : 3) + 2 > std::min(c->nx, c->ny)) {
+    msg = "slack must be at most min(nx, ny) - 2 on grids that are not powers of two";
+    return false;
+  }
   if (c->flags & ~(PIC_FLAG_NO_SORT | PIC_FLAG_UNFUSED_STEP | PIC_FLAG_NO_GRAPH | PIC_FLAG_ADJOINT |
                    PIC_FLAG_NAIVE_RHO | PIC_FLAG_JVSTAR | PIC_FLAG_DIRK_SUBSTEP)) {
     msg = "unknown flag bits";
@@ -178,9 +181,14 @@ TileP plan_tiles(const pic_config_t& c) {
   TileP t{};
   t.nx = c.nx;
   t.ny = c.ny;
-  t.ts = c.tile_cells && pow2(c.nx) && pow2(c.ny) ? c.tile_cells : std::min(16, std::min(c.nx, c.ny));
-  t.ntx = c.nx / t.ts;
-  t.nty = c.ny / t.ts;
+  t.pow2 = pow2(c.nx) && pow2(c.ny) ? 1 : 0;
+  // tile edge: a power of two not above either side (16 by default); a side
+  // that is not a multiple of it ends in a partial tile
+  int ts = 16;
+  while (ts > std::min(c.nx, c.ny)) ts >>= 1;
+  t.ts = c.tile_cells ? c.tile_cells : ts;
+  t.ntx = (c.nx + t.ts - 1) / t.ts;
+  t.nty = (c.ny + t.ts - 1) / t.ts;
   t.ntiles = t.ntx * t.nty;
   t.log_ts = 0;
   while ((1 << t.log_ts) < t.ts) t.log_ts++;
@@ -239,8 +247,9 @@ Layout plan_instance(const pic_config_t& c) {
   L.twy = take((size_t)c.ny * 16);
   L.tcount = take((size_t)tp.ntiles * 4);
   L.tstart = take(((size_t)tp.ntiles + 1) * 4);
-  L.ccount = take(plane_r * 4);
-  L.ccursor = take(plane_r * 4);
+  const size_t ckeys = (size_t)tp.ntiles * tp.ts * tp.ts;  // cell keys (>= nx ny)
+  L.ccount = take(ckeys * 4);
+  L.ccursor = take(ckeys * 4);
   L.twork = take((size_t)tp.max_work * 16);
   L.tnwork = take(4);
   L.tdone = take(4);
@@ -627,10 +636,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
   c->degree = cfgs[0].spline_degree;
   c->scheme = scheme_family(cfgs[0].scheme);
   // the naive charge deposit runs on the untiled passes
-  // cell-sorted tiles need power-of-two grids (every instance of an ensemble)
-  bool all_pow2 = true;
-  for (int i = 0; i < ninst; ++i) all_pow2 = all_pow2 && pow2(cfgs[i].nx) && pow2(cfgs[i].ny);
-  c->sorted = (cfgs[0].flags & (PIC_FLAG_NO_SORT | PIC_FLAG_NAIVE_RHO)) == 0 && all_pow2;
+  c->sorted = (cfgs[0].flags & (PIC_FLAG_NO_SORT | PIC_FLAG_NAIVE_RHO)) == 0;
   c->d_desc = (InstDesc*)c->ws;
   c->d_diag = (double*)(c->ws + align_up(ninst * sizeof(InstDesc)));
   c->inst.resize(ninst);
@@ -737,7 +743,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
       e = hipMemcpy((void*)d.twy, tw.data(), (size_t)cf.ny * 16, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMemset(d.tb.count, 0, (size_t)d.tp.ntiles * 4);
-    if (e == hipSuccess) e = hipMemset(d.tb.ccount, 0, (size_t)cf.nx * cf.ny * 4);
+    if (e == hipSuccess) e = hipMemset(d.tb.ccount, 0, (size_t)d.tp.ntiles * d.tp.ts * d.tp.ts * 4);
     if (e == hipSuccess) e = hipMemset(d.tb.done, 0, 4);
   }
   c->sort_every = every;

@@ -54,7 +54,7 @@ struct HistSlots {
 struct TileP {
   int nx, ny;      // mesh nodes
   int ts;          // tile edge in cells
-  int ntx, nty, ntiles;
+  int ntx, nty, ntiles;  // ceil(n / ts): the last tile of a row or column may be partial
   int log_ts, log_ntx;
   int slack;       // cells a particle may drift after the sort and stay in the window
   int win;         // window edge in nodes: ts + 2*slack + 3
@@ -63,6 +63,7 @@ struct TileP {
   int log_row_lanes;
   int chunk;       // max particles per workgroup
   int max_work;    // ntiles + ceil(capacity/chunk): bound on the chunk count
+  int pow2;        // 1: nx and ny are powers of two (node indices wrap by masks)
 };
 
 // Particles are counting-sorted by cell, cells numbered tile-major (the
@@ -71,8 +72,8 @@ struct TileP {
 struct TileBufs {
   int32_t* count;    // [ntiles]   particles per tile (written by the cell scan)
   int32_t* start;    // [ntiles+1] first particle of each tile
-  int32_t* ccount;   // [nx*ny]    particles per cell; zero between sorts
-  int32_t* ccursor;  // [nx*ny]    first slot of each cell, from its tile's start
+  int32_t* ccount;   // [ntiles*ts*ts] particles per cell key; zero between sorts
+  int32_t* ccursor;  // [ntiles*ts*ts] first slot of each cell, from its tile's start
   int4* work;        // [max_work] (tile, first particle, count, 0)
   int32_t* nwork;    // [1]        chunks in use
   int32_t* done;     // [1]        blocks of the cell scan finished; zero between sorts

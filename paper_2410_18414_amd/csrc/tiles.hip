@@ -335,7 +335,15 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   // a node 16 banks apart (WP itself is a multiple of the 64-bank cycle)
   const int JWP = WP + 8;
   const int ts = FIXED ? TS : tp.ts, slack = FIXED ? SL : tp.slack;
-  const int tiy = it.x >> tp.log_ntx, tix = it.x - (tiy << tp.log_ntx);
+  // node indices modulo the grid: masks on power-of-two grids (the only ones
+  // the fixed-geometry kernels run on), otherwise remainders; tiles of a grid
+  // side that is not a multiple of the tile edge are partial at the high end
+  const bool pw = FIXED || tp.pow2;
+  auto modn = [&](int v, int n) { return pw ? (v & (n - 1)) : ((v % n) + n) % n; };
+  // a stencil origin relative to the window origin: in [-n, 2n) because the
+  // slack is below n - 1 (validated for grids that are not powers of two)
+  auto modw = [&](int v, int n) { return pw ? (v & (n - 1)) : (v < 0 ? v + n : (v >= n ? v - n : v)); };
+  const int tiy = pw ? it.x >> tp.log_ntx : it.x / tp.ntx, tix = it.x - tiy * tp.ntx;
   const int ox = tix * ts - slack - 1, oy = tiy * ts - slack - 1;
   extern __shared__ __align__(16) unsigned char smem[];
   T* fw = reinterpret_cast<T*>(smem);
@@ -370,13 +378,13 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   // (row_lanes >= W, a power of two), row-groups cover y
   const int rl = FIXED ? G::RL : tp.row_lanes, lrl = FIXED ? G::LRL : tp.log_row_lanes;
   const int wi = threadIdx.x & (rl - 1), wj0 = threadIdx.x >> lrl, wjs = blockDim.x >> lrl;
-  const int gxw = (ox + wi) & (g.nx - 1);
+  const int gxw = modn(ox + wi, g.nx);
   if (GATHER && wi < W) {
     if constexpr (sizeof(T) == 4) {
       // float32 fields are node-major in global memory as in LDS: a node is
       // three 16-byte vectors
       auto copy_row = [&](int j) {
-        const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
+        const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
         const float4* src = reinterpret_cast<const float4*>(F + go * kFieldSlots);
         float4* dst = reinterpret_cast<float4*>(fw + (j * W + wi) * kNodeSlots);
         const float4 a0 = src[0], a1 = src[1], a2 = src[2];
@@ -401,7 +409,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       for (int r = 0; r < NJ; ++r) {
         const int j = wj0 + r * wjs;
         if (j < W) {
-          const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
+          const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
 #pragma unroll
           for (int f = 0; f < 11; ++f) v[r][f] = F[f * plane + go];
         }
@@ -416,7 +424,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       }
     } else {
       for (int j = wj0; j < W; j += wjs) {
-        const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
+        const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
         const int node = j * W + wi;
 #pragma unroll
         for (int f = 0; f < 11; ++f) fw[node * kNodeSlots + f] = F[f * plane + go];
@@ -469,7 +477,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         T wx[NW], wy[NW];
         S::eval(xi, sx, wx);
         S::eval(eta, sy, wy);
-        const int lx = (sx - ox) & (g.nx - 1), ly = (sy - oy) & (g.ny - 1);
+        const int lx = modw(sx - ox, g.nx), ly = modw(sy - oy, g.ny);
         if (lx + DEG < W && ly + DEG < W) {
           const T* nd0 = fw + (ly * W + lx) * kNodeSlots;
 #pragma unroll
@@ -536,8 +544,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
             jy = qs * vy;
             jz = qs * vz;
           }
-          lx = (sx - ox) & (g.nx - 1);
-          ly = (sy - oy) & (g.ny - 1);
+          lx = modw(sx - ox, g.nx);
+          ly = modw(sy - oy, g.ny);
           inw = lx + DEG < W && ly + DEG < W;
           if (!inw) deposit_global<T, DEG>(sx, sy, wx, wy, jx, jy, jz, J, g);
         }
@@ -610,7 +618,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
     __syncthreads();
     if (wi < W) {
       for (int j = wj0; j < W; j += wjs) {
-        const size_t go = (size_t)((oy + j) & (g.ny - 1)) * g.nx + gxw;
+        const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
         const int node = j * W + wi;
         if (FIXEDPT) {
           const uint64_t v = jxy_w[node];
@@ -701,6 +709,7 @@ hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_coun
 }
 
 int tiled_geometry(const TileP& tp) {
+  if (!tp.pow2) return 0;  // the fixed geometries wrap node indices by masks
   if (tp.slack == 3 && tp.ts == 16) return 1;
   if (tp.slack == 3 && tp.ts == 8) return 2;
   return 0;
