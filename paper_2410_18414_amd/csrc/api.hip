@@ -726,7 +726,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     c->lds_col = std::max(c->lds_col, columns_parts(scheme_family(cf.scheme)) > 1
                                           ? columns_split_lds_bytes(cf.ny)
                                           : columns_lds_bytes(cf.ny, d.sc.substep ? 3 * d.sc.stages : 4));
-    if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, columns_lds_bytes(cf.ny, 4));
+    if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, adj_columns_lds_bytes(cf.ny));
     for (int mode = 0; mode < 3; ++mode)
       c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp));
     // a position update moves a particle by less than c dt; the window's slack

@@ -226,6 +226,15 @@ __device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, 
   return o;
 }
 
+// work-buffer columns of k_columns (in units of ny complex values): the
+// forward batch (3 J columns and the naive rho: 2 x 4; a DIRK stage: 2 x 3;
+// one column when ny > 512: 2 x 1) or the inverse batches (2 x nb),
+// whichever is larger
+__host__ __device__ inline int columns_work_cols(int ny, int nb, int nstore) {
+  const int fwd = nstore != 4 ? 6 : (ny > 512 ? 2 : 8);
+  return fwd > 2 * nb ? fwd : 2 * nb;
+}
+
 template <int SCHEME, int K>
 __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
   // LDS: store [0, NS*N) with NS = 4 (phi~, A0, A1, A2, scaled), or with
@@ -246,32 +255,41 @@ __global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D,
   double2* __restrict__ U = d.U;
   const size_t plane = (size_t)g.nxh * g.ny;
   const int nst = sc.substep ? sc.stages : 0;  // sub-stepped DIRK stages
+  // ny > 512: the J columns are transformed one at a time into the store
+  // region (as the stage currents are), so the work buffers shrink to the
+  // inverse batches
+  const bool percol = !nst && N > 512;
+  const int nstore = nst ? 3 * nst : 4;
   double2* store = sm;
-  double2* wk = sm + (nst ? 3 * nst : 4) * N;
+  double2* wk = sm + nstore * N;
   // twiddles staged in LDS where they fit (ny <= 512), else read from global
   const double2* tws = d.twy;
   if (N <= 512) {
-    double2* t_lds = wk + max(8, 2 * NB) * N;
+    double2* t_lds = wk + columns_work_cols(N, NB, nstore) * N;
     for (int t = threadIdx.x; t < N; t += blockDim.x) t_lds[t] = d.twy[t];
     tws = t_lds;
   }
-  // forward y-FFTs: J (and the naive mode's deposited rho) in one batch, or
-  // the stage currents stage by stage into the stage region
+  // forward y-FFTs: J (and the naive mode's deposited rho) in one batch, the
+  // stage currents stage by stage, or (ny > 512) column by column
   const double2* Jh = nullptr;
-  for (int st = 0; st < (nst ? nst : 1); ++st) {
-    const int ncol = nst ? 3 : 3 + d.naive;
-    const int cb = 3 * st;  // first T component of the batch
+  const int nbatch = nst ? nst : (percol ? 3 + d.naive : 1);
+  for (int st = 0; st < nbatch; ++st) {
+    const int ncol = nst ? 3 : (percol ? 1 : 3 + d.naive);
+    const int cb = nst ? 3 * st : st;  // first T component of the batch
     for (int t = threadIdx.x; t < ncol * N; t += blockDim.x) {
       const int c = t / N, y = t - c * N;
       wk[t] = T[((size_t)(cb + c) * g.nxh + kx) * N + y];
     }
     __syncthreads();
     Jh = fft_lds<false>(wk, wk + ncol * N, N, ncol, tws);
-    if (nst) {
-      for (int t = threadIdx.x; t < 3 * N; t += blockDim.x) store[cb * N + t] = Jh[t];
+    if (nst || percol) {
+      for (int t = threadIdx.x; t < ncol * N; t += blockDim.x) store[cb * N + t] = Jh[t];
       __syncthreads();
     }
   }
+  // the store region holds the spectra now; each mode's thread reads its
+  // values before writing its outputs over them
+  if (percol) Jh = store;
   const double kxs = kx_sym(kx, g);
   const double scale = 1.0 / ((double)g.nx * g.ny);
   for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
@@ -707,7 +725,13 @@ size_t rows_c2r_lds_bytes(int nx, int ny) { return (size_t)(2 * rows_c2r_R(nx, n
 int columns_nb(int ny) { return ny <= 256 ? 8 : (ny <= 512 ? 4 : 2); }
 size_t columns_lds_bytes(int ny, int nstore) {
   const int nb = columns_nb(ny);
-  return (size_t)(nstore + std::max(8, 2 * nb) + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2);
+  return (size_t)(nstore + columns_work_cols(ny, nb, nstore) + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2);
+}
+// k_adj_columns: accumulators 4 ny, work buffers max(6, 2 nb) ny (bounded here
+// by max(8, 2 nb)), twiddles
+size_t adj_columns_lds_bytes(int ny) {
+  const int nb = columns_nb(ny);
+  return (size_t)(4 + std::max(8, 2 * nb) + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2);
 }
 
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {

@@ -214,6 +214,7 @@ int columns_nb(int ny);
 size_t rows_r2c_lds_bytes(int nx, int ny);
 size_t rows_c2r_lds_bytes(int nx, int ny);
 size_t columns_lds_bytes(int ny, int nstore);  // nstore: LDS store columns (4, or 3 per sub-stepped DIRK stage)
+size_t adj_columns_lds_bytes(int ny);
 // blocks per kx of the forward column kernel (4 for BDF-k and CDF-2, split
 // by output; 1 for DIRK-2) and the split kernel's LDS bytes
 int columns_parts(int scheme);

@@ -82,12 +82,16 @@ def test_uniform_plasma_partial_tiles(gpu_lib, nx, ny, dtype):
     u.close()
 
 
-@pytest.mark.parametrize("nx,ny", [(1021, 10), (12, 1000)])
-def test_largest_sides_match_oracle(gpu_lib, nx, ny):
-    print("case", nx, ny, flush=True)
+@pytest.mark.parametrize("nx,ny,scheme,flags", [(1021, 10, "bdf", 0), (12, 1000, "bdf", 0),
+                                                (16, 1024, "dirk2", 0), (10, 1000, "dirk3", 0),
+                                                (16, 1024, "dirk2", pic.FLAG_NAIVE_RHO)])
+def test_largest_sides_match_oracle(gpu_lib, nx, ny, scheme, flags):
+    """The largest FFT lengths, and DIRK with ny above 512 (its column kernel
+    then transforms the J columns one at a time)."""
+    print("case", nx, ny, scheme, flags, flush=True)
     w = cloud(nx, ny, ppc=1, seed=92)
-    o = make_oracle(w, 2, "bdf", 2)
-    g = make_gpu(w, 2, "bdf", "f64")
+    o = make_oracle(w, 2, scheme, 2, naive=bool(flags & pic.FLAG_NAIVE_RHO))
+    g = make_gpu(w, 2, scheme, "f64", flags=flags)
     o.step(3)
     pic.step(g, 3)
     errs, bad = compare_particles(gpu_parts(g), o.part, w["lx"], w["ly"], 1e-10)

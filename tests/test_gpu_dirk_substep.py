@@ -109,3 +109,12 @@ def test_substep_refused(gpu_lib, scheme, flags):
     with pytest.raises(pic.PicError) as e:
         make_gpu(w, 3, scheme, "f64", flags=flags)
     assert e.value.status == 2     # PIC_ERR_UNSUPPORTED
+
+
+def test_substep_refused_beyond_lds(gpu_lib):
+    """Three stage regions and the work buffers exceed the LDS at ny = 1024:
+    creation fails cleanly."""
+    w = workloads.cloud(nx=16, ny=1024, ppc=1, seed=83, drift=0.2, vth=0.05)
+    with pytest.raises(pic.PicError) as e:
+        make_gpu(w, 2, "dirk3", "f64", flags=F)
+    assert e.value.status == 2
