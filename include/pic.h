@@ -122,7 +122,9 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
 
 typedef struct {                /* [host] */
   int32_t abi_version;          /* == PIC_ABI_VERSION                                    */
-  int32_t nx, ny;               /* mesh nodes per axis: powers of two, 8 .. 1024          */
+  int32_t nx, ny;               /* mesh nodes per axis, 8 .. 1024 (any integer: mixed-
+                                   radix FFTs; powers of two take the compiled tile
+                                   geometries and are required by PIC_FLAG_ADJOINT)     */
   int32_t spline_degree;        /* 1 (linear), 2 (quadratic, the paper's), 3 (cubic),
                                    4, 5 (quartic, quintic; not with the adjoint)         */
   double lx, ly;                /* periodic box [0,lx) x [0,ly)                          */
@@ -139,11 +141,14 @@ typedef struct {                /* [host] */
   int64_t max_particles;        /* capacity, >= 1                                        */
   uint32_t flags;               /* PIC_FLAG_*                                            */
   int32_t tile_cells;           /* tile edge in cells for the sorted passes (power of two,
-                                   4..64, at most nx and ny); 0 = default (16)           */
+                                   4..64, at most nx and ny); 0 = default (16, or the
+                                   largest power of two not above nx and ny); a side
+                                   that is no multiple of it ends in a partial tile     */
   int32_t chunk;                /* particles per workgroup of the sorted passes
                                    (64..65536); 0 = default (512)                        */
   int32_t slack;                /* cells a particle may drift from its tile and still use
-                                   the tile's LDS window (1..8); 0 = default (3)         */
+                                   the tile's LDS window (1..8); 0 = default (3); at
+                                   most min(nx, ny) - 2 when a side is no power of two */
   int32_t reserved[4];          /* must be zero                                          */
 } pic_config_t;
 
