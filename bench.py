@@ -30,12 +30,12 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-steps/s per full PIC step; batched and adjoint vs plain at 1e-10 rel"
 HBM_PEAK_GBS = 8000.0
 
-# name -> (workload id in paper_2410_18414_amd.workloads, overrides, label)
+# name -> (workload name in paper_2410_18414_amd.workloads, overrides, label)
 WORKLOADS = {
-    "weibel128": (2, {}, "weibel-128x128-64ppc-cubic-bdf2-f32"),
-    "weibel512-dirk2": (3, {}, "weibel-512x512-256ppc-cubic-dirk2-f32"),
-    "weibel512-cdf2": (3, {"scheme": "cdf2"}, "weibel-512x512-256ppc-cubic-cdf2-f32"),
-    "cloud32": (1, {}, "cloud-32x32-4ppc-quadratic-bdf1-f64"),
+    "weibel128": ("weibel128", {}, "weibel-128x128-64ppc-cubic-bdf2-f32"),
+    "weibel512-dirk2": ("weibel512", {}, "weibel-512x512-256ppc-cubic-dirk2-f32"),
+    "weibel512-cdf2": ("weibel512", {"scheme": "cdf2"}, "weibel-512x512-256ppc-cubic-cdf2-f32"),
+    "cloud32": ("cloud32", {}, "cloud-32x32-4ppc-quadratic-bdf1-f64"),
 }
 
 
@@ -208,7 +208,7 @@ def bench_naive(steps=20):
     and Gauss residuals after `steps` steps for both updates."""
     import torch
     from paper_2410_18414_amd import pic, workloads
-    w = workloads.make(2)
+    w = workloads.make("weibel128")
     n = len(w["x"])
     dev = torch.device("cuda:0")
     data = (torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
@@ -246,7 +246,7 @@ def bench_variants(steps=40):
     `steps` steps."""
     import torch
     from paper_2410_18414_amd import pic, workloads
-    w = workloads.make(2)
+    w = workloads.make("weibel128")
     n = len(w["x"])
     dev = torch.device("cuda:0")
     data = (torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
@@ -283,7 +283,7 @@ def bench_adjoint(every=5):
     cubic, checkpoints every 5 steps) against the plain float64 forward."""
     import torch
     from paper_2410_18414_amd import adjoint, pic, workloads
-    w = workloads.make(5)
+    w = workloads.make("weibel128-drift")
     nsteps = w["steps"]
     n = len(w["x"])
     dev = torch.device("cuda:0")

@@ -104,22 +104,22 @@ def ensemble(count=64, draw_seed=4999, seed_base=4000, sizes=(32, 64, 128, 256),
             for i in range(count)]
 
 
-# The five workloads: (generator, kwargs, spline degree, stepper, BDF order,
+# The named workloads: (generator, kwargs, spline degree, stepper, BDF order,
 # particle precision, steps).
 CONFIGS = {
-    1: dict(gen="cloud", kw=dict(nx=32, ny=32, ppc=4, seed=1001), degree=2,
-            scheme="bdf", bdf_order=1, dtype="f64", steps=50),
-    2: dict(gen="weibel", kw=dict(nx=128, ny=128, ppc=64, seed=1002), degree=3,
-            scheme="bdf", bdf_order=2, dtype="f32", steps=200),
-    3: dict(gen="weibel", kw=dict(nx=512, ny=512, ppc=256, seed=1003), degree=3,
-            scheme="dirk2", bdf_order=2, dtype="f32", steps=100),
-    5: dict(gen="weibel", kw=dict(nx=128, ny=128, ppc=64, seed=1005, drift=0.1),
-            degree=3, scheme="bdf", bdf_order=2, dtype="f64", steps=20),
+    "cloud32": dict(gen="cloud", kw=dict(nx=32, ny=32, ppc=4, seed=1001), degree=2,
+                    scheme="bdf", bdf_order=1, dtype="f64", steps=50),
+    "weibel128": dict(gen="weibel", kw=dict(nx=128, ny=128, ppc=64, seed=1002), degree=3,
+                      scheme="bdf", bdf_order=2, dtype="f32", steps=200),
+    "weibel512": dict(gen="weibel", kw=dict(nx=512, ny=512, ppc=256, seed=1003), degree=3,
+                      scheme="dirk2", bdf_order=2, dtype="f32", steps=100),
+    "weibel128-drift": dict(gen="weibel", kw=dict(nx=128, ny=128, ppc=64, seed=1005, drift=0.1),
+                            degree=3, scheme="bdf", bdf_order=2, dtype="f64", steps=20),
 }
 
 
-def make(config_id, **override):
-    cfg = dict(CONFIGS[config_id])
+def make(name, **override):
+    cfg = dict(CONFIGS[name])
     kw = dict(cfg["kw"], **override)
     gen = {"cloud": cloud, "weibel": weibel}[cfg["gen"]]
     out = gen(**kw)

@@ -187,7 +187,7 @@ def test_full_size_gradient_matches_finite_differences(gpu_lib):
     5 steps) against Richardson-extrapolated central differences."""
     from paper_2410_18414_amd import adjoint
     pic = gpu_lib
-    w = workloads.make(5)
+    w = workloads.make("weibel128-drift")
     nsteps = w["steps"]
     pos, xi = workloads.weibel_normals(128, 128, 64, 1005)
     xi_t = _dev(xi)

@@ -1,4 +1,4 @@
-"""Full-size checks at the workload sizes the bench and the survey name.
+"""Full-size checks at the workload sizes the benchmark runs.
 
 The 512 x 512, 256 particles/cell case (67,108,864 float32 particles, cubic,
 DIRK-2 and CDF-2) is too large for a full oracle step, so the oracle computes
@@ -30,7 +30,7 @@ EPS = np.finfo(np.float64).eps
 def big():
     import time
     t0 = time.time()
-    w = workloads.make(3)
+    w = workloads.make("weibel512")
     assert len(w["x"]) == 512 * 512 * 256
     print("generated 67M particles in %.0f s" % (time.time() - t0), flush=True)
     p = oracle_params(w, 3, "dirk2")
@@ -81,7 +81,7 @@ def test_512_first_step_sampled_and_invariants(gpu_lib, big, scheme):
 
 
 def test_128_graph_replay_invariants_and_direct_equality(gpu_lib):
-    w = workloads.make(2)
+    w = workloads.make("weibel128")
     ctx = make_gpu(w, 3, "bdf", "f32")
     pic.step(ctx, 30)  # captured once, then replayed
     d = pic.diagnostics(ctx)

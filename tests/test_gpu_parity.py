@@ -254,7 +254,7 @@ def test_nonfinite_detected(gpu_lib):
 # full size of the 128 x 128, 64 particles/cell anisotropic workload
 
 def test_full_size_weibel_one_step_f32(gpu_lib):
-    w = workloads.make(2)
+    w = workloads.make("weibel128")
     o = make_oracle(w, 3, "bdf", 2)
     ctx = make_gpu(w, 3, "bdf", "f32", bdf_order=2)
     o.step(2)
