@@ -86,9 +86,18 @@ def cpu_baseline(w, spec, nsteps):
     s.step(nsteps)
     dt = time.perf_counter() - t0
     n = len(w["x"])
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=n * nsteps / dt, unit="particle-steps/s", cores=1, kind="oracle",
                 sample="%d full steps of the same %d-particle workload (numpy float64, one thread)"
-                       % (nsteps, n))
+                       % (nsteps, n), cpu_model=model)
 
 
 def _events(stream):
@@ -426,6 +435,10 @@ def main():
     traffic = measured_traffic(args.workload) if default_launch else None
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                # the rocprofv3-measured bytes over the same live launch time
+                traffic_gbs=round(traffic / (avg_fused * 1e-3) / 1e9, 1) if traffic and avg_fused > 0 else None,
+                traffic_frac=(round(traffic / (avg_fused * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                              if traffic and avg_fused > 0 else None),
                 kernel="k_tiled<float,3,2,16,3> (fused gather/push/position/deposit)",
                 avg_launch_us=round(avg_fused * 1e3, 2),
                 algorithmic_bytes_per_launch=int(alg))
