@@ -145,7 +145,8 @@ typedef struct {                /* [host] */
                                    largest power of two not above nx and ny); a side
                                    that is no multiple of it ends in a partial tile     */
   int32_t chunk;                /* particles per workgroup of the sorted passes
-                                   (64..65536); 0 = default (512)                        */
+                                   (64..65536); 0 = default: the largest of 512, 1024,
+                                   2048 leaving >= 8192 chunks at max_particles          */
   int32_t slack;                /* cells a particle may drift from its tile and still use
                                    the tile's LDS window (1..8); 0 = default (3); at
                                    most min(nx, ny) - 2 when a side is no power of two */

@@ -203,7 +203,12 @@ TileP plan_tiles(const pic_config_t& c) {
     t.row_lanes <<= 1;
     t.log_row_lanes += 1;
   }
-  t.chunk = c.chunk ? c.chunk : 512;
+  // default chunk: the largest of 512, 1024, 2048 particles that still leaves
+  // at least 8192 chunks (32 per CU) at full capacity; bigger chunks amortise
+  // the window load and flush once parallelism is plentiful
+  int chunk = 512;
+  while (chunk < 2048 && c.max_particles / (2 * chunk) >= 8192) chunk *= 2;
+  t.chunk = c.chunk ? c.chunk : chunk;
   t.max_work = t.ntiles + ceil_div(c.max_particles, t.chunk);
   return t;
 }
