@@ -84,7 +84,7 @@ Hist plan_history(const pic_config_t& c) {
     mk(h.vphi, 1, 1);
     mk(h.A, 2, 3);
     mk(h.vA, 1, 3);
-    mk(h.J, 1, 3);
+    mk(h.J, 2, 3);  // J^n read and J^{n+1} written by different blocks: two levels, the newest exported
     h.nexport = 17;
   }
   h.nslots = b;
@@ -728,9 +728,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     }
     c->lds_r2c = std::max(c->lds_r2c, rows_r2c_lds_bytes(cf.nx, cf.ny));
     c->lds_c2r = std::max(c->lds_c2r, rows_c2r_lds_bytes(cf.nx, cf.ny));
-    c->lds_col = std::max(c->lds_col, columns_parts(scheme_family(cf.scheme)) > 1
-                                          ? columns_split_lds_bytes(cf.ny)
-                                          : columns_lds_bytes(cf.ny, d.sc.substep ? 3 * d.sc.stages : 4));
+    c->lds_col = std::max(c->lds_col, columns_split_lds_bytes(cf.ny, d.sc.substep ? d.sc.stages : 0));
     if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, adj_columns_lds_bytes(cf.ny));
     for (int mode = 0; mode < 3; ++mode)
       c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp));
@@ -796,7 +794,7 @@ std::vector<int> export_slots(pic_ctx_t c) {
   if (c->scheme == PIC_SCHEME_DIRK2) ring(h.vphi, 1);
   ring(h.A, h.A.size);
   if (c->scheme == PIC_SCHEME_DIRK2) ring(h.vA, 1);
-  if (c->scheme != PIC_SCHEME_BDF) ring(h.J, h.J.size);
+  if (c->scheme != PIC_SCHEME_BDF) ring(h.J, c->scheme == PIC_SCHEME_DIRK2 ? 1 : h.J.size);
   return v;
 }
 

@@ -83,261 +83,25 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
 }
 
 // ---------------------------------------------------------------------------
-// columns: one block per kx.  Forward y-FFT of the three J columns, the
-// stepper's update for every ky of this column, and inverse y-FFTs of the
-// eight columns phi~, d_y phi~, A_l, d_y A_l (scaled by 1/(nx ny)).
-struct ModeOut {
-  double2 phi, A[3];
-};
-
-// K: the BDF order as a compile-time constant (0 for the other steppers), so
-// that every history slot index is static and all history loads issue at once.
-// stage: the sub-stepped DIRK stage currents of this mode (component l of
-// stage i at stage[(3 i + l) * sstride]), else null
-template <int SCHEME, int K>
-__device__ ModeOut mode_update(double2* __restrict__ H, size_t plane, size_t m, double2 J0, double2 J1,
-                               double2 J2, const double2* rho_dep, const double2* stage, int sstride, double kxs,
-                               double kys, const SchemeCoef& sc, const HistSlots& hs) {
-  const double kappa = kxs * kxs + kys * kys;  // -Laplacian symbol
-  auto at = [&](int slot) -> double2& { return H[(size_t)slot * plane + m]; };
-  // i k . J
-  auto divv = [&](double2 X, double2 Y) { return mul_i(make_double2(kxs * X.x + kys * Y.x, kxs * X.y + kys * Y.y)); };
-  ModeOut o;
-  const double2 Jn1[3] = {J0, J1, J2};
-  if (SCHEME == PIC_SCHEME_BDF) {
-    constexpr int k = K;
-    // continuity: sum_j a_j rho^{n+1-j} + dt div J^{n+1} = 0
-    double2 acc = cscale(divv(J0, J1), sc.dt);
-#pragma unroll
-    for (int j = 1; j <= k; ++j) acc = cadd(acc, cscale(at(hs.rho[j - 1]), sc.a[j]));
-    const double2 rho = cscale(acc, -1.0 / sc.a[0]);
-    const double Lh = 1.0 + kappa * sc.inv_alpha2;
-    double2 s = cscale(rho, sc.inv_alpha2 / sc.eps0);
-#pragma unroll
-    for (int i = 1; i <= 2 * k; ++i) s = csub(s, cscale(at(hs.phi[i - 1]), sc.Cn[i]));
-    const double2 phi = cdivr(s, Lh);
-    at(hs.rho_new) = rho;
-    at(hs.phi_new) = phi;
-    o.phi = phi;
-    for (int l = 0; l < 3; ++l) {
-      double2 sa = cscale(Jn1[l], sc.mu0 * sc.inv_alpha2);
-#pragma unroll
-      for (int i = 1; i <= 2 * k; ++i) sa = csub(sa, cscale(at(hs.A[i - 1] + l), sc.Cn[i]));
-      const double2 A = cdivr(sa, Lh);
-      at(hs.A_new + l) = A;
-      o.A[l] = A;
-    }
-  } else if (SCHEME == PIC_SCHEME_CDF2) {
-    const double2 rho_h = at(hs.rho[0]), rho_mh = at(hs.rho[1]);
-    const double2 rho = csub(rho_h, cscale(divv(J0, J1), sc.dt));  // rho^{n+3/2}
-    const double Lh = 1.0 + kappa * sc.inv_alpha2;
-    const double2 phi_h = at(hs.phi[0]), phi_mh = at(hs.phi[1]);
-    const double2 rhs = cadd(cscale(phi_h, 2.0), cscale(cadd(rho, rho_mh), sc.inv_alpha2 / sc.eps0));
-    const double2 phi = csub(cdivr(rhs, Lh), phi_mh);
-    at(hs.rho_new) = rho;
-    at(hs.phi_new) = phi;
-    o.phi = cscale(cadd(phi, phi_h), 0.5);
-    for (int l = 0; l < 3; ++l) {
-      const double2 An = at(hs.A[0] + l), Am = at(hs.A[1] + l), Jm = at(hs.J[1] + l);
-      const double2 r = cadd(cscale(An, 2.0), cscale(cadd(Jn1[l], Jm), sc.mu0 * sc.inv_alpha2));
-      const double2 A = csub(cdivr(r, Lh), Am);
-      at(hs.A_new + l) = A;
-      at(hs.J_new + l) = Jn1[l];
-      o.A[l] = A;
-    }
-  } else {  // DIRK (sc.stages = 2 or 3 stages)
-    const double h = sc.dt, c2 = sc.c * sc.c;
-    const int ns = sc.stages;
-    double2 Jst[3][3], Jkeep[3];
-    const double2 rho_n = at(hs.rho[0]);
-    double2 rho = rho_n;
-    double2 rst[3];
-    if (stage) {
-      // sub-stepped stage currents; rho^(i) are the RK stage values of the
-      // continuity equation, rho^{n+1} its final stage
-      double2 dv[3];
-      for (int i = 0; i < ns; ++i) {
-        for (int l = 0; l < 3; ++l) Jst[i][l] = stage[(3 * i + l) * sstride];
-        dv[i] = divv(Jst[i][0], Jst[i][1]);
-        rho = csub(rho, cscale(dv[i], h * sc.dirkB[i]));
-      }
-      for (int i = 0; i < ns; ++i) {
-        rst[i] = rho_n;
-        for (int j = 0; j <= i; ++j) rst[i] = csub(rst[i], cscale(dv[j], h * sc.dirkA[i][j]));
-      }
-      for (int l = 0; l < 3; ++l) {
-        Jkeep[l] = make_double2(0.0, 0.0);
-        for (int i = 0; i < ns; ++i) Jkeep[l] = cadd(Jkeep[l], cscale(Jst[i][l], sc.dirkB[i]));
-      }
-    } else {
-      double2 Jn[3];
-      for (int l = 0; l < 3; ++l) Jn[l] = at(hs.J[0] + l);
-      for (int i = 0; i < ns; ++i)
-        for (int l = 0; l < 3; ++l)
-          Jst[i][l] = cadd(cscale(Jn[l], 1.0 - sc.dirkC[i]), cscale(Jn1[l], sc.dirkC[i]));
-      if (rho_dep)
-        rho = *rho_dep;  // naive comparison: the deposited rho^{n+1}
-      else
-        for (int i = 0; i < ns; ++i) rho = csub(rho, cscale(divv(Jst[i][0], Jst[i][1]), h * sc.dirkB[i]));
-      for (int i = 0; i < ns; ++i) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
-      for (int l = 0; l < 3; ++l) Jkeep[l] = Jn1[l];
-    }
-    // one scalar wave component: (u, v)' = (v, c^2 (S + Lap u)), Lap = -kappa
-    auto advance = [&](double2& u, double2& v, const double2* S) {
-      double2 ku[3], kv[3];
-      for (int i = 0; i < ns; ++i) {
-        double2 U = u, V = v;
-        for (int j = 0; j < i; ++j) {
-          U = cadd(U, cscale(ku[j], h * sc.dirkA[i][j]));
-          V = cadd(V, cscale(kv[j], h * sc.dirkA[i][j]));
-        }
-        const double hai = h * sc.dirkA[i][i];
-        const double Li = 1.0 + hai * hai * c2 * kappa;
-        const double2 src = csub(S[i], cscale(U, kappa));  // S + Lap U
-        ku[i] = cdivr(cadd(V, cscale(src, hai * c2)), Li);
-        kv[i] = cdivr(csub(cscale(src, c2), cscale(V, hai * c2 * kappa)), Li);
-      }
-      for (int i = 0; i < ns; ++i) {
-        u = cadd(u, cscale(ku[i], h * sc.dirkB[i]));
-        v = cadd(v, cscale(kv[i], h * sc.dirkB[i]));
-      }
-    };
-    double2 u = at(hs.phi[0]), v = at(hs.vphi);
-    {
-      double2 S[3];
-      for (int i = 0; i < ns; ++i) S[i] = cscale(rst[i], 1.0 / sc.eps0);
-      advance(u, v, S);
-    }
-    at(hs.rho_new) = rho;
-    at(hs.phi_new) = u;
-    at(hs.vphi) = v;
-    o.phi = u;
-    for (int l = 0; l < 3; ++l) {
-      double2 ua = at(hs.A[0] + l), va = at(hs.vA + l);
-      double2 S[3];
-      for (int i = 0; i < ns; ++i) S[i] = cscale(Jst[i][l], sc.mu0);
-      advance(ua, va, S);
-      at(hs.A_new + l) = ua;
-      at(hs.vA + l) = va;
-      at(hs.J[0] + l) = Jkeep[l];
-      o.A[l] = ua;
-    }
-  }
-  return o;
-}
-
-// work-buffer columns of k_columns (in units of ny complex values): the
-// forward batch (3 J columns and the naive rho: 2 x 4; a DIRK stage: 2 x 3;
-// one column when ny > 512: 2 x 1) or the inverse batches (2 x nb),
-// whichever is larger
-__host__ __device__ inline int columns_work_cols(int ny, int nb, int nstore) {
-  const int fwd = nstore != 4 ? 6 : (ny > 512 ? 2 : 8);
-  return fwd > 2 * nb ? fwd : 2 * nb;
-}
-
-template <int SCHEME, int K>
-__global__ void __launch_bounds__(256) k_columns(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
-  // LDS: store [0, NS*N) with NS = 4 (phi~, A0, A1, A2, scaled), or with
-  // sub-stepped DIRK currents NS = 3 per stage: the stage spectra, whose first
-  // four columns become the store once each mode has been updated (the thread
-  // of mode ky reads all its stage values before writing its outputs); work
-  // buffers from NS*N: forward 2 x 3N (naive: 2 x 4N), inverse 2 x NB*N
-  // (NB = 8, 4 or 2 fields per batch); then the N twiddles (ny <= 512)
-  extern __shared__ double2 sm[];
-  const int ii = find_inst(D, ninst, BK_COL, blockIdx.x);
-  const InstDesc& d = D[ii];
-  const GridP g = d.g;
-  const SchemeCoef sc = d.sc;
-  const int kx = blockIdx.x - d.blk[BK_COL];
-  const int N = g.ny, NB = d.nb_col;
-  const double2* __restrict__ T = d.T;
-  double2* __restrict__ H = d.H;
-  double2* __restrict__ U = d.U;
-  const size_t plane = (size_t)g.nxh * g.ny;
-  const int nst = sc.substep ? sc.stages : 0;  // sub-stepped DIRK stages
-  // ny > 512: the J columns are transformed one at a time into the store
-  // region (as the stage currents are), so the work buffers shrink to the
-  // inverse batches
-  const bool percol = !nst && N > 512;
-  const int nstore = nst ? 3 * nst : 4;
-  double2* store = sm;
-  double2* wk = sm + nstore * N;
-  // twiddles staged in LDS where they fit (ny <= 512), else read from global
-  const double2* tws = d.twy;
-  if (N <= 512) {
-    double2* t_lds = wk + columns_work_cols(N, NB, nstore) * N;
-    for (int t = threadIdx.x; t < N; t += blockDim.x) t_lds[t] = d.twy[t];
-    tws = t_lds;
-  }
-  // forward y-FFTs: J (and the naive mode's deposited rho) in one batch, the
-  // stage currents stage by stage, or (ny > 512) column by column
-  const double2* Jh = nullptr;
-  const int nbatch = nst ? nst : (percol ? 3 + d.naive : 1);
-  for (int st = 0; st < nbatch; ++st) {
-    const int ncol = nst ? 3 : (percol ? 1 : 3 + d.naive);
-    const int cb = nst ? 3 * st : st;  // first T component of the batch
-    for (int t = threadIdx.x; t < ncol * N; t += blockDim.x) {
-      const int c = t / N, y = t - c * N;
-      wk[t] = T[((size_t)(cb + c) * g.nxh + kx) * N + y];
-    }
-    __syncthreads();
-    Jh = fft_lds<false>(wk, wk + ncol * N, N, ncol, tws);
-    if (nst || percol) {
-      for (int t = threadIdx.x; t < ncol * N; t += blockDim.x) store[cb * N + t] = Jh[t];
-      __syncthreads();
-    }
-  }
-  // the store region holds the spectra now; each mode's thread reads its
-  // values before writing its outputs over them
-  if (percol) Jh = store;
-  const double kxs = kx_sym(kx, g);
-  const double scale = 1.0 / ((double)g.nx * g.ny);
-  for (int ky = threadIdx.x; ky < N; ky += blockDim.x) {
-    const double2 J0 = Jh[ky], J1 = Jh[N + ky], J2 = Jh[2 * N + ky];
-    const ModeOut o = mode_update<SCHEME, K>(H, plane, (size_t)kx * N + ky, J0, J1, J2,
-                                          d.naive ? Jh + 3 * N + ky : nullptr, nst ? store + ky : nullptr, N, kxs,
-                                          ky_sym(ky, g), sc, hs);
-    store[ky] = cscale(o.phi, scale);
-    store[N + ky] = cscale(o.A[0], scale);
-    store[2 * N + ky] = cscale(o.A[1], scale);
-    store[3 * N + ky] = cscale(o.A[2], scale);
-  }
-  __syncthreads();
-  // eight outputs G0..G7 = phi~, d_y phi~, Ax, Ay, Az, d_y Ax, d_y Ay, d_y Az
-  const int src[8] = {0, 0, 1, 2, 3, 1, 2, 3};
-  for (int f0 = 0; f0 < 8; f0 += NB) {
-    for (int t = threadIdx.x; t < NB * N; t += blockDim.x) {
-      const int q = t / N, ky = t - q * N, f = f0 + q;
-      double2 v = store[src[f] * N + ky];
-      if (f == 1 || f >= 5) v = mul_i(cscale(v, ky_sym(ky, g)));
-      wk[t] = v;
-    }
-    __syncthreads();
-    const double2* res = fft_lds<true>(wk, wk + NB * N, N, NB, tws);
-    for (int t = threadIdx.x; t < NB * N; t += blockDim.x) {
-      const int q = t / N, y = t - q * N;
-      U[((size_t)(f0 + q) * g.nxh + kx) * N + y] = res[t];
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// columns split by output (BDF-k and CDF-2): four blocks per kx.  Part 0
-// updates rho and phi from the forward y-FFTs of J_x and J_y (the
-// divergence); part 1 + l updates A_l from the forward y-FFT of J_l.  Each
-// part inverse-transforms its two outputs (phi~ and d_y phi~, or A_l and
-// d_y A_l).  The history terms of the update do not depend on J^{n+1}: they
-// are loaded and summed before the forward transform, so their loads overlap
-// it.  (DIRK keeps the one-block-per-kx kernel: its single J history slot
-// is read by every component's update and overwritten by each.)
+// columns: four blocks per kx, one per output.  Forward y-FFT of the J
+// columns, the stepper's update for every ky of this column, and inverse
+// y-FFTs of the part's two outputs (scaled by 1/(nx ny)).  Part 0 updates
+// rho and phi (DIRK: and v_phi) from the forward y-FFTs of J_x and J_y (the
+// divergence); part 1 + l updates A_l (DIRK: and v_A,l) from the forward
+// y-FFT of J_l.  Each part inverse-transforms its two outputs (phi~ and
+// d_y phi~, or A_l and d_y A_l).  The history terms of the update do not
+// depend on J^{n+1}: they are loaded (BDF-k: summed) before the forward
+// transform, so their loads overlap it.  Parts share no written state: DIRK's
+// J^n history is a ring of two levels, read at J[0] by parts 0 and 1 + l and
+// written at J_new by part 1 + l only.
 constexpr int kColParts = 4;
 constexpr int kColMaxModes = 4;  // modes per thread: ny <= 1024 with 256 threads
 
 template <int SCHEME, int K>
 __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
   // LDS: [0, N) the scaled output column; [N, 5N) work (two ping-pong pairs
-  // of two columns); then the N twiddles (ny <= 512)
+  // of two columns); then the N twiddles (ny <= 512); then, for sub-stepped
+  // DIRK currents, the transformed stage columns (two per stage)
   extern __shared__ double2 sm[];
   const int ii = find_inst(D, ninst, BK_COL, blockIdx.x);
   const InstDesc& d = D[ii];
@@ -358,6 +122,9 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
     for (int i = tid; i < N; i += nth) t_lds[i] = d.twy[i];
     tws = t_lds;
   }
+  double2* stg = sm + (N <= 512 ? 6 : 5) * N;
+  // sub-stepped DIRK stages (their currents sit at T components 3 i .. 3 i + 2)
+  const int nst = SCHEME == PIC_SCHEME_DIRK2 && sc.substep ? sc.stages : 0;
   // part 0 transforms J_x, J_y (the divergence), or in the naive mode the
   // deposited rho (component 3); part 1 + l transforms J_l
   const bool naive_rho = part == 0 && d.naive;
@@ -369,11 +136,11 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
   }
   // history terms of this thread's modes ky = tid + m * nth
   auto at = [&](int slot, int ky) -> double2& { return H[(size_t)slot * plane + (size_t)kx * N + ky]; };
-  double2 h0[kColMaxModes], h1[kColMaxModes], h2[kColMaxModes], h3[kColMaxModes];
+  double2 h0[kColMaxModes], h1[kColMaxModes], h2[kColMaxModes], h3[kColMaxModes], h4[kColMaxModes];
 #pragma unroll
   for (int m = 0; m < kColMaxModes; ++m) {
     const int ky = tid + m * nth;
-    h0[m] = h1[m] = h2[m] = h3[m] = make_double2(0.0, 0.0);
+    h0[m] = h1[m] = h2[m] = h3[m] = h4[m] = make_double2(0.0, 0.0);
     if (ky >= N) continue;
     if (SCHEME == PIC_SCHEME_BDF) {
       if (part == 0) {
@@ -388,7 +155,7 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
 #pragma unroll
         for (int i = 1; i <= 2 * K; ++i) h0[m] = cadd(h0[m], cscale(at(hs.A[i - 1] + c0, ky), sc.Cn[i]));
       }
-    } else {  // CDF-2
+    } else if (SCHEME == PIC_SCHEME_CDF2) {
       if (part == 0) {
         h0[m] = at(hs.rho[0], ky);
         h1[m] = at(hs.rho[1], ky);
@@ -400,10 +167,42 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
         h1[m] = at(hs.A[1] + c0, ky);
         h2[m] = at(hs.J[sc.form == 0 ? 1 : 0] + c0, ky);
       }
+    } else {  // DIRK: u^n, v^n of the part's wave component, and J^n for interpolated stages
+      if (part == 0) {
+        h0[m] = at(hs.rho[0], ky);
+        h1[m] = at(hs.phi[0], ky);
+        h2[m] = at(hs.vphi, ky);
+        if (!nst && !naive_rho) {
+          h3[m] = at(hs.J[0], ky);
+          h4[m] = at(hs.J[0] + 1, ky);
+        }
+      } else {
+        h0[m] = at(hs.A[0] + c0, ky);
+        h1[m] = at(hs.vA + c0, ky);
+        if (!nst) h2[m] = at(hs.J[0] + c0, ky);
+      }
     }
   }
   __syncthreads();
-  const double2* Jh = fft_lds<false>(wk, wk + 2 * N, N, ncol, tws);
+  const double2* Jh;
+  if (nst) {
+    // stage by stage into the stage region (stage i at stg + i * ncol * N)
+    for (int st = 0; st < nst; ++st) {
+      if (st > 0) {
+        for (int i = tid; i < ncol * N; i += nth) {
+          const int c = i / N, y = i - c * N;
+          wk[i] = T[((size_t)(3 * st + c0 + c) * g.nxh + kx) * N + y];
+        }
+        __syncthreads();
+      }
+      const double2* r = fft_lds<false>(wk, wk + 2 * N, N, ncol, tws);
+      for (int i = tid; i < ncol * N; i += nth) stg[st * ncol * N + i] = r[i];
+      __syncthreads();
+    }
+    Jh = stg;
+  } else {
+    Jh = fft_lds<false>(wk, wk + 2 * N, N, ncol, tws);
+  }
   const double kxs = kx_sym(kx, g);
   const double scale = 1.0 / ((double)g.nx * g.ny);
 #pragma unroll
@@ -413,9 +212,89 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
     const double kys = ky_sym(ky, g);
     const double Lh = 1.0 + (kxs * kxs + kys * kys) * sc.inv_alpha2;
     double2 out;
-    if (part == 0) {
+    // i k . V
+    auto divv = [&](double2 X, double2 Y) { return mul_i(make_double2(kxs * X.x + kys * Y.x, kxs * X.y + kys * Y.y)); };
+    if (SCHEME == PIC_SCHEME_DIRK2) {
+      // Sec. 3.3: s-stage DIRK on (u, v)' = (v, c^2 (S + Lap u)), Lap = -kappa,
+      // one scalar wave component per part
+      const double h = sc.dt, c2 = sc.c * sc.c, kappa = kxs * kxs + kys * kys;
+      const int ns = sc.stages;
+      auto advance = [&](double2& u, double2& v, const double2* S) {
+        double2 ku[3], kv[3];
+        for (int i = 0; i < ns; ++i) {
+          double2 U = u, V = v;
+          for (int j = 0; j < i; ++j) {
+            U = cadd(U, cscale(ku[j], h * sc.dirkA[i][j]));
+            V = cadd(V, cscale(kv[j], h * sc.dirkA[i][j]));
+          }
+          const double hai = h * sc.dirkA[i][i];
+          const double Li = 1.0 + hai * hai * c2 * kappa;
+          const double2 src = csub(S[i], cscale(U, kappa));  // S + Lap U
+          ku[i] = cdivr(cadd(V, cscale(src, hai * c2)), Li);
+          kv[i] = cdivr(csub(cscale(src, c2), cscale(V, hai * c2 * kappa)), Li);
+        }
+        for (int i = 0; i < ns; ++i) {
+          u = cadd(u, cscale(ku[i], h * sc.dirkB[i]));
+          v = cadd(v, cscale(kv[i], h * sc.dirkB[i]));
+        }
+      };
+      double2 S[3];
+      if (part == 0) {
+        const double2 rho_n = h0[m];
+        double2 rho = rho_n, rst[3];
+        if (nst) {
+          // sub-stepped currents: rho^(i) are the RK stage values of the
+          // continuity equation, rho^{n+1} its final stage
+          double2 dv[3];
+          for (int i = 0; i < ns; ++i) {
+            dv[i] = divv(Jh[(2 * i) * N + ky], Jh[(2 * i + 1) * N + ky]);
+            rho = csub(rho, cscale(dv[i], h * sc.dirkB[i]));
+          }
+          for (int i = 0; i < ns; ++i) {
+            rst[i] = rho_n;
+            for (int j = 0; j <= i; ++j) rst[i] = csub(rst[i], cscale(dv[j], h * sc.dirkA[i][j]));
+          }
+        } else {
+          if (naive_rho) {
+            rho = Jh[ky];  // naive comparison: the deposited rho^{n+1}
+          } else {
+            const double2 J0 = Jh[ky], J1 = Jh[N + ky];
+            for (int i = 0; i < ns; ++i) {
+              const double2 X = cadd(cscale(h3[m], 1.0 - sc.dirkC[i]), cscale(J0, sc.dirkC[i]));
+              const double2 Y = cadd(cscale(h4[m], 1.0 - sc.dirkC[i]), cscale(J1, sc.dirkC[i]));
+              rho = csub(rho, cscale(divv(X, Y), h * sc.dirkB[i]));
+            }
+          }
+          for (int i = 0; i < ns; ++i) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
+        }
+        for (int i = 0; i < ns; ++i) S[i] = cscale(rst[i], 1.0 / sc.eps0);
+        double2 u = h1[m], v = h2[m];
+        advance(u, v, S);
+        at(hs.rho_new, ky) = rho;
+        at(hs.phi_new, ky) = u;
+        at(hs.vphi, ky) = v;
+        out = u;
+      } else {
+        double2 keep = make_double2(0.0, 0.0);
+        for (int i = 0; i < ns; ++i) {
+          // stage current: sub-stepped, or interpolated between J^n and J^{n+1}
+          const double2 Ji = nst ? Jh[i * N + ky]
+                                 : cadd(cscale(h2[m], 1.0 - sc.dirkC[i]), cscale(Jh[ky], sc.dirkC[i]));
+          S[i] = cscale(Ji, sc.mu0);
+          keep = cadd(keep, cscale(Ji, sc.dirkB[i]));
+        }
+        // J history: sum_i b_i J^(i) when sub-stepped, else J^{n+1}
+        if (!nst) keep = Jh[ky];
+        double2 u = h0[m], v = h1[m];
+        advance(u, v, S);
+        at(hs.A_new + c0, ky) = u;
+        at(hs.vA + c0, ky) = v;
+        at(hs.J_new + c0, ky) = keep;
+        out = u;
+      }
+    } else if (part == 0) {
       const double2 J0 = Jh[ky], J1 = naive_rho ? J0 : Jh[N + ky];
-      const double2 divJ = mul_i(make_double2(kxs * J0.x + kys * J1.x, kxs * J0.y + kys * J1.y));  // i k . J
+      const double2 divJ = divv(J0, J1);  // i k . J
       if (SCHEME == PIC_SCHEME_BDF) {
         // continuity: sum_j a_j rho^{n+1-j} + dt div J^{n+1} = 0 (naive: the deposited rho)
         const double2 rho = naive_rho ? J0 : cscale(cadd(cscale(divJ, sc.dt), h0[m]), -1.0 / sc.a[0]);
@@ -723,10 +602,6 @@ size_t rows_r2c_lds_bytes(int nx, int ny) { return (size_t)(rows_r2c_R(nx, ny) +
 size_t rows_c2r_lds_bytes(int nx, int ny) { return (size_t)(2 * rows_c2r_R(nx, ny) + 1) * nx * sizeof(double2); }
 // inverse batch size of the column kernel and its LDS bytes (<= 160 KiB)
 int columns_nb(int ny) { return ny <= 256 ? 8 : (ny <= 512 ? 4 : 2); }
-size_t columns_lds_bytes(int ny, int nstore) {
-  const int nb = columns_nb(ny);
-  return (size_t)(nstore + columns_work_cols(ny, nb, nstore) + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2);
-}
 // k_adj_columns: accumulators 4 ny, work buffers max(6, 2 nb) ny (bounded here
 // by max(8, 2 nb)), twiddles
 size_t adj_columns_lds_bytes(int ny) {
@@ -741,14 +616,6 @@ hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds
 }
 
 template <int SCHEME, int K>
-static hipError_t launch_columns_t(const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
-                                   hipStream_t s) {
-  (void)hipFuncSetAttribute((const void*)k_columns<SCHEME, K>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_columns<SCHEME, K>), dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
-  return hipGetLastError();
-}
-
-template <int SCHEME, int K>
 static hipError_t launch_columns_split_t(const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
                                          hipStream_t s) {
   (void)hipFuncSetAttribute((const void*)k_columns_split<SCHEME, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -757,13 +624,17 @@ static hipError_t launch_columns_split_t(const InstDesc* D, int ninst, int nbloc
   return hipGetLastError();
 }
 
-int columns_parts(int scheme) { return scheme == PIC_SCHEME_DIRK2 ? 1 : kColParts; }
-size_t columns_split_lds_bytes(int ny) { return (size_t)(5 + (ny <= 512 ? 1 : 0)) * ny * sizeof(double2); }
+int columns_parts(int) { return kColParts; }
+// output column, work buffers (4 ny), twiddles (ny <= 512), stage columns
+// (two per sub-stepped DIRK stage)
+size_t columns_split_lds_bytes(int ny, int nstage) {
+  return (size_t)(5 + (ny <= 512 ? 1 : 0) + 2 * nstage) * ny * sizeof(double2);
+}
 
 hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int ninst, int nblocks, size_t lds,
                           HistSlots hs, hipStream_t s) {
   if (scheme == PIC_SCHEME_CDF2) return launch_columns_split_t<PIC_SCHEME_CDF2, 0>(D, ninst, nblocks, lds, hs, s);
-  if (scheme == PIC_SCHEME_DIRK2) return launch_columns_t<PIC_SCHEME_DIRK2, 0>(D, ninst, nblocks, lds, hs, s);
+  if (scheme == PIC_SCHEME_DIRK2) return launch_columns_split_t<PIC_SCHEME_DIRK2, 0>(D, ninst, nblocks, lds, hs, s);
   switch (bdf_order) {
     case 1: return launch_columns_split_t<PIC_SCHEME_BDF, 1>(D, ninst, nblocks, lds, hs, s);
     case 2: return launch_columns_split_t<PIC_SCHEME_BDF, 2>(D, ninst, nblocks, lds, hs, s);

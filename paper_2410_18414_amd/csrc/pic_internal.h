@@ -135,7 +135,7 @@ struct InstDesc {
   int qe0;                  // float32 fixed-point deposit: B 2^qe0 < 2^29 for the contribution bound B
   TileBufs tb;
   int64_t n;                // particles loaded
-  int R_r2c, R_c2r, nb_col; // rows per block of the row kernels; inverse batch of the column kernel
+  int R_r2c, R_c2r, nb_col; // rows per block of the row kernels; forward batch of the adjoint column kernel
   int blk[BK_NKINDS];       // first block of this instance in each flattened grid
 };
 
@@ -213,12 +213,11 @@ int rows_c2r_R(int nx, int ny);
 int columns_nb(int ny);
 size_t rows_r2c_lds_bytes(int nx, int ny);
 size_t rows_c2r_lds_bytes(int nx, int ny);
-size_t columns_lds_bytes(int ny, int nstore);  // nstore: LDS store columns (4, or 3 per sub-stepped DIRK stage)
 size_t adj_columns_lds_bytes(int ny);
 // blocks per kx of the forward column kernel (4 for BDF-k and CDF-2, split
 // by output; 1 for DIRK-2) and the split kernel's LDS bytes
 int columns_parts(int scheme);
-size_t columns_split_lds_bytes(int ny);
+size_t columns_split_lds_bytes(int ny, int nstage);  // nstage: sub-stepped DIRK stages (else 0)
 // adj = true: the adjoint field solve's transforms (LF -> LS, LS -> LJ; one instance)
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false);
 hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int ninst, int nblocks, size_t lds,
