@@ -132,9 +132,12 @@ typedef struct {                /* [host] */
   int32_t bdf_order;            /* BDF-k order 1..6 (Sec. 3.2), used when scheme == BDF  */
   int32_t particle_dtype;       /* pic_dtype_t of particle state and gather; mesh FFT and
                                    spectral history are float64 in both cases           */
-  int32_t sort_interval;        /* position updates between re-sorts; 0 = the worst case
-                                   slack / (c dt / min(dx, dy)), no particle leaving its
-                                   window (longer intervals stay correct)               */
+  int32_t sort_interval;        /* position updates between re-sorts; 0 = from the
+                                   particles init_particles loads: slack / (max(|v_x|,
+                                   |v_y|) dt / min(dx, dy)), kept between the speed-of-
+                                   light interval and twice it (a particle that leaves
+                                   its window takes the global path: results never
+                                   depend on the interval)                              */
   double dt;                    /* time step                                             */
   double c, eps0, mu0;          /* |c^2 eps0 mu0 - 1| <= 1e-12 required (Sec. 2.1)      */
   double q, m;                  /* macro-particle charge and mass                        */

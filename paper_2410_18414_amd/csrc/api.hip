@@ -343,6 +343,8 @@ SchemeCoef make_scheme(const pic_config_t& c) {
 
 struct Instance {
   pic_config_t cfg{};
+  int every_worst = 1;  // sort interval if particles moved at c: slack / (c dt / min(dx, dy))
+  int every = 1;        // this instance's sort interval (explicit, or from the loaded particles)
   Layout L{};
   size_t off = 0;  // byte offset of the instance region in the workspace
   InstDesc d{};    // host copy of the device descriptor
@@ -736,7 +738,9 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     // absorbs sort_every updates without any particle leaving it
     const double cells = cf.c * cf.dt / std::min(g.dx, g.dy);
     const int auto_every = std::max(1, (int)std::floor(d.tp.slack / std::max(cells, 1e-300)));
-    every = std::min(every, cf.sort_interval > 0 ? cf.sort_interval : auto_every);
+    in.every_worst = std::min(auto_every, 64);
+    in.every = cf.sort_interval > 0 ? cf.sort_interval : in.every_worst;
+    every = std::min(every, in.every);
     // twiddles
     tw.assign(2 * (size_t)std::max(cf.nx, cf.ny), 0.0);
     fft_make_twiddles(cf.nx, tw.data());
@@ -849,7 +853,7 @@ pic_status_t loop_body(pic_ctx_t c, bool unfused) {
 int graph_period(pic_ctx_t c) {
   int period = 2 * c->sort_every;
   while (period % c->lr) period += 2 * c->sort_every;
-  return period <= 256 ? period : 0;
+  return period <= 512 ? period : 0;
 }
 
 void state_key(pic_ctx_t c, int64_t* k) {
@@ -1045,6 +1049,29 @@ pic_status_t init_particles(pic_ctx_t c, int64_t n, const double* x, const doubl
   in.d.n = n;
   st = c->upload_desc();
   if (st) return st;
+  if (in.cfg.sort_interval == 0 && n > 0) {
+    // sort interval from the loaded particles: a position update moves a
+    // particle by at most max(|v_x|, |v_y|) dt in x and y, so the window's
+    // slack lasts slack / (that / min(dx, dy)) updates; kept between the
+    // speed-of-light interval and twice it (longer intervals let particles
+    // that speed up escape their windows often enough to cost more in the
+    // fused pass than they save in sorts).  A particle that outruns it takes
+    // the global path until the next sort, so results never depend on it.
+    uint32_t* d_vmax = reinterpret_cast<uint32_t*>(c->d_diag);
+    uint32_t h_vmax = 0;
+    st = c->hip(hipMemsetAsync(d_vmax, 0, sizeof(uint32_t), c->stream), "speed reset");
+    if (!st) st = c->hip(launch_max_inplane(c->dtype, &pa, n, d_vmax, c->stream), "speed launch");
+    if (!st) st = c->hip(hipMemcpyAsync(&h_vmax, d_vmax, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream), "speed copy");
+    if (!st) st = c->hip(hipStreamSynchronize(c->stream), "speed sync");
+    if (st) return st;
+    float vmax;
+    std::memcpy(&vmax, &h_vmax, sizeof(float));
+    const double cells = (double)vmax * in.cfg.dt / std::min(in.d.g.dx, in.d.g.dy);
+    const double k = cells > 0 ? std::floor(in.d.tp.slack / cells) : 1e9;
+    in.every = (int)std::max<double>(in.every_worst, std::min<double>(k, 2.0 * in.every_worst));
+  }
+  c->sort_every = 64;
+  for (const Instance& other : c->inst) c->sort_every = std::min(c->sort_every, other.every);
   c->moves = c->sort_every;  // sort before the next particle pass
   c->phase = READY;
   return PIC_OK;

@@ -269,6 +269,36 @@ hipError_t launch_untiled(int dtype, int mode, int degree, const InstDesc* D, in
   return launch_untiled_mode<double>(mode, degree, D, ninst, nblocks, sa, s);
 }
 
+// largest in-plane velocity component max(|v_x|, |v_y|) of the set, as the
+// bits of a non-negative float (which order like the float); a non-finite
+// velocity counts as +inf
+template <typename T>
+__global__ void __launch_bounds__(256) k_max_inplane(Parts<T> p, int64_t n, uint32_t* __restrict__ out) {
+  __shared__ float red[256];
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float a = fmaxf(fabsf((float)p.v[0][i]), fabsf((float)p.v[1][i]));
+    m = a == a ? fmaxf(m, a) : __int_as_float(0x7f800000);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+
+hipError_t launch_max_inplane(int dtype, const void* parts, int64_t n, uint32_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  if (dtype == PIC_F32)
+    hipLaunchKernelGGL(k_max_inplane<float>, dim3(blocks), dim3(256), 0, s, *(const Parts<float>*)parts, n, out);
+  else
+    hipLaunchKernelGGL(k_max_inplane<double>, dim3(blocks), dim3(256), 0, s, *(const Parts<double>*)parts, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_get_particles(int dtype, const void* parts, int64_t n, double* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (dtype == PIC_F32)

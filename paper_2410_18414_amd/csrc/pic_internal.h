@@ -194,6 +194,8 @@ hipError_t launch_untiled(int dtype, int mode, int degree, const InstDesc* D, in
 hipError_t launch_init_particles(int dtype, const void* parts, int64_t n, const double* x, const double* y,
                                  const double* P, GridP g, PhysP ph, hipStream_t s);
 hipError_t launch_get_particles(int dtype, const void* parts, int64_t n, double* out, hipStream_t s);
+// max(|v_x|, |v_y|) over the set as float bits, atomically maxed into *out (zeroed by the caller)
+hipError_t launch_max_inplane(int dtype, const void* parts, int64_t n, uint32_t* out, hipStream_t s);
 hipError_t launch_set_particles(int dtype, const void* parts, int64_t n, const double* in, GridP g, hipStream_t s);
 hipError_t launch_particle_diag(int dtype, const void* parts, int64_t n, PhysP ph, double* out2, hipStream_t s);
 

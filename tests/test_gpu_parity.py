@@ -330,3 +330,24 @@ def test_quartic_quintic_trajectory(gpu_lib, degree, scheme, k, dtype, flags):
     assert not bad, errs
     assert rel(pic.get_history(g).cpu().numpy(), hist_to_flat(o.p, o.hist)) <= tol
     g.close()
+
+
+def test_sort_interval_follows_inplane_speed(gpu_lib):
+    """With sort_interval 0 the interval comes from the loaded particles'
+    largest in-plane velocity: particles at rest get twice the speed-of-light
+    interval, particles at 0.95c in x get the speed-of-light one (the graph
+    period, two sort intervals rounded to the history rings, shows it); the
+    slow run still matches the oracle."""
+    w = cloud_small(seed=71)
+    cold = dict(w, P=0.0 * w["P"])
+    hot = dict(w, P=np.zeros_like(w["P"]))
+    hot["P"][:, 0] = w["m"] * 0.95 / np.sqrt(1.0 - 0.95 ** 2)      # u_x for v_x = 0.95c
+    gc = make_gpu(cold, 2, "bdf", "f64", bdf_order=2)
+    gh = make_gpu(hot, 2, "bdf", "f64", bdf_order=2)
+    # speed-of-light interval: slack 3 cells / (c dt / dx) = 6 steps here
+    assert pic.graph_period(gh) == 12 and pic.graph_period(gc) == 24, (pic.graph_period(gh), pic.graph_period(gc))
+    o = make_oracle(hot, 2, "bdf", 2)
+    o.step(30)
+    pic.step(gh, 30)
+    errs, bad = compare_particles(gpu_parts(gh), o.part, w["lx"], w["ly"], 1e-10)
+    assert not bad, errs
