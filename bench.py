@@ -250,9 +250,9 @@ def bench_naive(steps=20):
 def bench_variants(steps=40):
     """The current and stepper options on the plain workload (128 x 128,
     64 particles/cell, cubic, float32 particles): v* in J against the plain
-    BDF-2 step, and DIRK-2 / DIRK-3 with interpolated or sub-stepped stage
-    currents; step rate and the relative gauge and Gauss residuals after
-    `steps` steps."""
+    BDF-2 step, the deterministic deposit, and DIRK-2 / DIRK-3 with
+    interpolated or sub-stepped stage currents; step rate and the relative
+    gauge and Gauss residuals after `steps` steps."""
     import torch
     from paper_2410_18414_amd import pic, workloads
     w = workloads.make("weibel128")
@@ -262,6 +262,7 @@ def bench_variants(steps=40):
             torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev))
     out = dict(workload="weibel-128x128-64ppc-cubic-f32, %d steps" % steps, particles=n, steps=steps)
     variants = (("bdf2", "bdf", 0), ("bdf2_jvstar", "bdf", pic.FLAG_JVSTAR),
+                ("bdf2_deterministic", "bdf", pic.FLAG_DETERMINISTIC),
                 ("dirk2", "dirk2", 0), ("dirk2_substep", "dirk2", pic.FLAG_DIRK_SUBSTEP),
                 ("dirk3", "dirk3", 0), ("dirk3_substep", "dirk3", pic.FLAG_DIRK_SUBSTEP))
     for name, scheme, flags in variants:

@@ -119,6 +119,16 @@ typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype_t;
  * PIC_FLAG_NAIVE_RHO or PIC_FLAG_ADJOINT (PIC_ERR_UNSUPPORTED).  step() runs
  * the gather/push and the stage deposits as separate passes. */
 #define PIC_FLAG_DIRK_SUBSTEP 64u
+/* Deterministic deposit: J is accumulated in 64-bit integers at a fixed
+ * power-of-two scale per instance (the LDS windows and their flush alike), so
+ * every sum is exact and independent of the order particles or workgroups
+ * arrive in; runs repeat bit for bit (and a resumed run equals the
+ * uninterrupted one).  The quantisation is one rounding per contribution at
+ * the fixed scale (float32 particles: the same scale the default mode uses
+ * for full chunks; float64: below 2^-40 of the largest contribution).  Sorted
+ * passes only: PIC_ERR_UNSUPPORTED with PIC_FLAG_NO_SORT, PIC_FLAG_NAIVE_RHO
+ * or PIC_FLAG_ADJOINT. */
+#define PIC_FLAG_DETERMINISTIC 128u
 
 typedef struct {                /* [host] */
   int32_t abi_version;          /* == PIC_ABI_VERSION                                    */

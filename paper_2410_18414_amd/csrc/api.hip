@@ -153,7 +153,7 @@ bool validate(const pic_config_t* c, std::string& msg) {
     return false;
   }
   if (c->flags & ~(PIC_FLAG_NO_SORT | PIC_FLAG_UNFUSED_STEP | PIC_FLAG_NO_GRAPH | PIC_FLAG_ADJOINT |
-                   PIC_FLAG_NAIVE_RHO | PIC_FLAG_JVSTAR | PIC_FLAG_DIRK_SUBSTEP)) {
+                   PIC_FLAG_NAIVE_RHO | PIC_FLAG_JVSTAR | PIC_FLAG_DIRK_SUBSTEP | PIC_FLAG_DETERMINISTIC)) {
     msg = "unknown flag bits";
     return false;
   }
@@ -574,6 +574,11 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
       return PIC_ERR_INVALID_ARG;
     }
   }
+  if ((cfgs[0].flags & PIC_FLAG_DETERMINISTIC) &&
+      (cfgs[0].flags & (PIC_FLAG_NO_SORT | PIC_FLAG_NAIVE_RHO | PIC_FLAG_ADJOINT))) {
+    g_err = "the deterministic deposit needs the sorted passes (not with NO_SORT, NAIVE_RHO or ADJOINT)";
+    return PIC_ERR_UNSUPPORTED;
+  }
   if (cfgs[0].flags & PIC_FLAG_DIRK_SUBSTEP) {
     if (scheme_family(cfgs[0].scheme) != PIC_SCHEME_DIRK2) {
       g_err = "sub-stepped stage currents need a DIRK scheme";
@@ -711,7 +716,22 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
       const double B = std::fabs(cf.q) * cf.c * (d.jvstar ? 3.0 : 1.0) * g.inv_area * m0[cf.spline_degree] *
                        m0[cf.spline_degree];
       int p = 0;
-      d.qe0 = (B > 0 && std::isfinite(B)) ? (std::frexp(B, &p), 29 - p) : 0;
+      const bool ok = B > 0 && std::isfinite(B);
+      if (ok) std::frexp(B, &p);
+      d.qe0 = ok ? 29 - p : 0;
+      // deterministic deposit: one scale for every contribution of the
+      // instance.  Float32: the window scale of a full chunk (a chunk's sum
+      // below 2^29, so int64 sums of every chunk cannot overflow).  Float64:
+      // capacity x B 2^e < 2^62 bounds every int64 sum, window or global.
+      d.det = (cf.flags & PIC_FLAG_DETERMINISTIC) ? 1 : 0;
+      int cl2_chunk = 0, cl2_cap = 0;
+      while ((1 << cl2_chunk) < d.tp.chunk) ++cl2_chunk;
+      while (((int64_t)1 << cl2_cap) < cf.max_particles) ++cl2_cap;
+      int e = cf.particle_dtype == PIC_F32 ? d.qe0 - std::max(cl2_chunk, 8) : (ok ? 62 - p - cl2_cap : 0);
+      e = cf.particle_dtype == PIC_F32 ? std::max(-100, std::min(100, e)) : std::max(-1000, std::min(1000, e));
+      d.qe_det = e;
+      d.det_scale = std::ldexp(1.0, e);
+      d.det_unscale = std::ldexp(1.0, -e);
     }
     d.RB = d.naive ? (double*)(b + in.L.RB) : nullptr;
     d.n = 0;
@@ -1140,9 +1160,11 @@ pic_status_t pic_get_field(pic_ctx_t c, int32_t which, double* dst) {
   const size_t plane = (size_t)in.cfg.nx * in.cfg.ny;
   if (which == PIC_FIELD_J) {
     if (c->phase != DEPOSITED) return c->fail(PIC_ERR_STATE, "J is valid in phase DEPOSITED");
-    return c->hip(hipMemcpyAsync(dst, in.d.J, (size_t)j_planes(in.d.sc, 0) * plane * 8, hipMemcpyDeviceToDevice,
-                                 c->stream),
-                  "copy J");
+    const size_t nj = (size_t)j_planes(in.d.sc, 0) * plane;
+    if (in.d.det)  // int64 at scale 2^qe_det
+      return c->hip(launch_j_export(reinterpret_cast<const long long*>(in.d.J), dst, nj, in.d.det_unscale, c->stream),
+                    "export J");
+    return c->hip(hipMemcpyAsync(dst, in.d.J, nj * 8, hipMemcpyDeviceToDevice, c->stream), "copy J");
   }
   if (which == PIC_FIELD_MESH) {
     if (c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "mesh fields are valid in phase SOLVED");

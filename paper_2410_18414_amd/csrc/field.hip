@@ -48,6 +48,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
   double* __restrict__ Jc = (adj ? d.LF : d.J) + (size_t)c * g.nx * g.ny;
   // the naive mode's rho plane restarts from the ion background
   const double* __restrict__ reset = (!adj && c == 3) ? d.RB : nullptr;
+  const bool det = !adj && d.det;
   double2* __restrict__ T = adj ? d.LS : d.T;
   const int N = g.nx, B = R >> 1;
   double2* a = sm;
@@ -58,7 +59,12 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
     const int r = t / N, x = t - r * N;
     const size_t i0 = (size_t)(y0 + 2 * r) * N + x, i1 = i0 + N;
     const bool h0 = 2 * r < nr, h1 = 2 * r + 1 < nr;
-    a[t] = make_double2(h0 ? Jc[i0] : 0.0, h1 ? Jc[i1] : 0.0);
+    if (det) {  // deterministic deposit: int64 sums at scale 2^qe_det
+      const long long* Jq = reinterpret_cast<const long long*>(Jc);
+      a[t] = make_double2(h0 ? (double)Jq[i0] * d.det_unscale : 0.0, h1 ? (double)Jq[i1] * d.det_unscale : 0.0);
+    } else {
+      a[t] = make_double2(h0 ? Jc[i0] : 0.0, h1 ? Jc[i1] : 0.0);
+    }
     // consumed: ready for the next deposit (or adjoint scatter)
     if (h0) Jc[i0] = reset ? reset[i0] : 0.0;
     if (h1) Jc[i1] = reset ? reset[i1] : 0.0;
@@ -643,6 +649,17 @@ hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int nins
     case 5: return launch_columns_split_t<PIC_SCHEME_BDF, 5>(D, ninst, nblocks, lds, hs, s);
     default: return launch_columns_split_t<PIC_SCHEME_BDF, 6>(D, ninst, nblocks, lds, hs, s);
   }
+}
+
+__global__ void k_j_export(const long long* __restrict__ src, double* __restrict__ dst, size_t n, double unscale) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i] * unscale;
+}
+
+hipError_t launch_j_export(const long long* src, double* dst, size_t n, double unscale, hipStream_t s) {
+  const int blocks = (int)std::min<size_t>(4096, (n + 255) / 256);
+  if (n) hipLaunchKernelGGL(k_j_export, dim3(blocks), dim3(256), 0, s, src, dst, n, unscale);
+  return hipGetLastError();
 }
 
 hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {

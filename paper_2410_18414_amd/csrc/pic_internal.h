@@ -133,6 +133,9 @@ struct InstDesc {
   int naive;                // 1: J holds a fourth plane, the deposited rho; T a fourth component
   int jvstar;               // 1: J carries v* = 2 v - v_prev (PIC_FLAG_JVSTAR)
   int qe0;                  // float32 fixed-point deposit: B 2^qe0 < 2^29 for the contribution bound B
+  int det;                  // 1: deterministic deposit (PIC_FLAG_DETERMINISTIC): J planes hold int64 at scale 2^qe_det
+  int qe_det;               // that scale's exponent (float32: every chunk's window scale too)
+  double det_scale, det_unscale;  // 2^qe_det, 2^-qe_det
   TileBufs tb;
   int64_t n;                // particles loaded
   int R_r2c, R_c2r, nb_col; // rows per block of the row kernels; forward batch of the adjoint column kernel
@@ -196,6 +199,8 @@ hipError_t launch_init_particles(int dtype, const void* parts, int64_t n, const 
 hipError_t launch_get_particles(int dtype, const void* parts, int64_t n, double* out, hipStream_t s);
 // max(|v_x|, |v_y|) over the set as float bits, atomically maxed into *out (zeroed by the caller)
 hipError_t launch_max_inplane(int dtype, const void* parts, int64_t n, uint32_t* out, hipStream_t s);
+// deterministic deposit: the int64 J planes of an instance as float64 (J export)
+hipError_t launch_j_export(const long long* src, double* dst, size_t n, double unscale, hipStream_t s);
 hipError_t launch_set_particles(int dtype, const void* parts, int64_t n, const double* in, GridP g, hipStream_t s);
 hipError_t launch_particle_diag(int dtype, const void* parts, int64_t n, PhysP ph, double* out2, hipStream_t s);
 

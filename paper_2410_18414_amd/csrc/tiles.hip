@@ -83,6 +83,36 @@ __device__ __forceinline__ void rotate_lanes(float (&v)[NW], int r) {
 }
 
 
+// deterministic deposit's fallback for a stencil outside the window: each
+// contribution rounded at the instance's fixed scale (float32: the window's
+// one-FMA rounding; float64: llrint of the scaled product) and added to the
+// int64 J planes
+template <typename T, int DEG>
+__device__ __forceinline__ void deposit_global_fixed(int sx, int sy, const T* wx, const T* wy, T sjx, T sjy, T sjz,
+                                                     double* __restrict__ J, const GridP& g) {
+  using S = Spline<T, DEG>;
+  const size_t plane = (size_t)g.nx * g.ny;
+  unsigned long long* Jq = reinterpret_cast<unsigned long long*>(J);
+  auto q = [](T v, T w) -> long long {
+    if constexpr (sizeof(T) == 4)
+      return (long long)(int32_t)(__float_as_uint(__builtin_fmaf(v, w, kMagic)) - kMagicBits);
+    else
+      return llrint(v * w);
+  };
+#pragma unroll
+  for (int b = 0; b < S::NW; ++b) {
+    const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
+#pragma unroll
+    for (int a = 0; a < S::NW; ++a) {
+      const T w = wx[a] * wy[b];
+      const size_t o = row + wrapi(sx + a, g.nx);
+      atomicAdd(Jq + o, (unsigned long long)q(sjx, w));
+      atomicAdd(Jq + plane + o, (unsigned long long)q(sjy, w));
+      atomicAdd(Jq + 2 * plane + o, (unsigned long long)q(sjz, w));
+    }
+  }
+}
+
 // cell key of a position (cells floor(xi), clamped into the grid), numbered
 // tile-major: tile * ts^2 + (row in tile) * ts + (column in tile)
 __device__ __forceinline__ int cell_of(float xi, float eta, const TileP& tp) {
@@ -357,6 +387,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
     cw[3] = {T(0), T(0), T(0)};
   // J carries v* = 2 v - v_prev: the deposit needs the older velocity too
   const bool jv = d.jvstar != 0;
+  const bool det = d.det != 0;  // deterministic deposit: int64 J at the instance's fixed scale
   auto load = [&](int64_t i) {
     cx = p.x[i];
     cy = p.y[i];
@@ -455,7 +486,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   double inv_qscale = 1.0;
   if (FIXEDPT) {
     const int lz = it.z > 1 ? 32 - __clz(it.z - 1) : 0;  // ceil(log2 count)
-    int e = d.qe0 - (lz > 8 ? lz : 8);
+    // deterministic deposit: the instance's fixed scale (that of a full chunk)
+    int e = det ? d.qe_det : d.qe0 - (lz > 8 ? lz : 8);
     e = e > 100 ? 100 : (e < -100 ? -100 : e);  // a normal float scale, whatever q, c and the cell area
     qscale = __int_as_float((e + 127) << 23);
     inv_qscale = __longlong_as_double((long long)(1023 - e) << 52);
@@ -547,7 +579,14 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
           lx = modw(sx - ox, g.nx);
           ly = modw(sy - oy, g.ny);
           inw = lx + DEG < W && ly + DEG < W;
-          if (!inw) deposit_global<T, DEG>(sx, sy, wx, wy, jx, jy, jz, J, g);
+          if (!inw) {
+            if (det) {
+              const T sc = FIXEDPT ? T(qscale) : T(d.det_scale);
+              deposit_global_fixed<T, DEG>(sx, sy, wx, wy, jx * sc, jy * sc, jz * sc, J, g);
+            } else {
+              deposit_global<T, DEG>(sx, sy, wx, wy, jx, jy, jz, J, g);
+            }
+          }
         }
       }
       if constexpr (ROTATE) {
@@ -598,6 +637,22 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
             }
           }
         }
+      } else if (inw && det) {
+        // deterministic deposit (float64): int64 window sums of the products
+        // rounded at the instance's fixed scale
+        unsigned long long* nq0 = reinterpret_cast<unsigned long long*>(jw) + ly * W + lx;
+        const T sjx = jx * T(d.det_scale), sjy = jy * T(d.det_scale), sjz = jz * T(d.det_scale);
+#pragma unroll
+        for (int b = 0; b < NW; ++b) {
+#pragma unroll
+          for (int a = 0; a < NW; ++a) {
+            const T w = wx[a] * wy[b];
+            unsigned long long* nq = nq0 + b * W + a;
+            atomicAdd(nq, (unsigned long long)llrint(sjx * w));
+            atomicAdd(nq + JWP, (unsigned long long)llrint(sjy * w));
+            atomicAdd(nq + 2 * JWP, (unsigned long long)llrint(sjz * w));
+          }
+        }
       } else if (inw) {
         A* nd0 = jw + ly * W + lx;
 #pragma unroll
@@ -625,9 +680,24 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
           const int32_t X = (int32_t)(uint32_t)v;
           const int32_t Y = (int32_t)((int64_t)(v - (uint64_t)(int64_t)X) >> 32);
           const int32_t Z = (int32_t)jz_w[node];
-          if (X) atomicAdd(J + go, X * inv_qscale);
-          if (Y) atomicAdd(J + plane + go, Y * inv_qscale);
-          if (Z) atomicAdd(J + 2 * plane + go, Z * inv_qscale);
+          if (det) {  // int64 J planes at the same fixed scale: exact, order-free sums
+            unsigned long long* Jq = reinterpret_cast<unsigned long long*>(J);
+            if (X) atomicAdd(Jq + go, (unsigned long long)(long long)X);
+            if (Y) atomicAdd(Jq + plane + go, (unsigned long long)(long long)Y);
+            if (Z) atomicAdd(Jq + 2 * plane + go, (unsigned long long)(long long)Z);
+          } else {
+            if (X) atomicAdd(J + go, X * inv_qscale);
+            if (Y) atomicAdd(J + plane + go, Y * inv_qscale);
+            if (Z) atomicAdd(J + 2 * plane + go, Z * inv_qscale);
+          }
+        } else if (det) {
+          const unsigned long long* jq = reinterpret_cast<const unsigned long long*>(jw);
+          unsigned long long* Jq = reinterpret_cast<unsigned long long*>(J);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const unsigned long long v = jq[c * JWP + node];
+            if (v) atomicAdd(Jq + c * plane + go, v);
+          }
         } else {
 #pragma unroll
           for (int c = 0; c < 3; ++c) {

@@ -28,6 +28,7 @@ FLAG_ADJOINT = 8
 FLAG_NAIVE_RHO = 16   # rho deposited with the spline instead of continuity (the paper's naive update)
 FLAG_JVSTAR = 32      # J carries v* = 2 v^n - v^{n-1} instead of v^n
 FLAG_DIRK_SUBSTEP = 64  # DIRK stage currents from particles sub-stepped to each stage time
+FLAG_DETERMINISTIC = 128  # J summed in int64 at a fixed scale: runs repeat bit for bit
 FIELD_J = 0
 FIELD_MESH = 1
 DIAG_NAMES = ("gauge_l2", "gauge_scale", "gauss_l2", "gauss_scale", "charge", "energy",

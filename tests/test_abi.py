@@ -40,7 +40,7 @@ def _cfg(**kw):
 @pytest.mark.parametrize("bad", [
     dict(nx=7), dict(ny=4), dict(nx=2048), dict(ny=1025), dict(degree=6), dict(degree=0), dict(bdf_order=7),
     dict(dt=0.0), dict(dt=2.0), dict(c=2.0), dict(max_particles=0), dict(m=0.0), dict(lx=-1.0),
-    dict(flags=128)])
+    dict(flags=256)])
 def test_invalid_configs_rejected(bad):
     cfg = _cfg(**bad)
     assert pic.load().pic_workspace_bytes(ctypes.byref(cfg)) == 0
@@ -81,7 +81,10 @@ def test_create_rejects_bad_workspace_without_gpu():
                                           (pic.FLAG_NAIVE_RHO, "cdf2_semi"),
                                           (pic.FLAG_DIRK_SUBSTEP, "bdf"),
                                           (pic.FLAG_DIRK_SUBSTEP | pic.FLAG_NAIVE_RHO, "dirk2"),
-                                          (pic.FLAG_ADJOINT, "bdf-odd")])
+                                          (pic.FLAG_ADJOINT, "bdf-odd"),
+                                          (pic.FLAG_DETERMINISTIC | pic.FLAG_NO_SORT, "bdf"),
+                                          (pic.FLAG_DETERMINISTIC | pic.FLAG_NAIVE_RHO, "bdf"),
+                                          (pic.FLAG_DETERMINISTIC | pic.FLAG_ADJOINT, "bdf")])
 def test_create_rejects_unsupported_combinations_without_gpu(flags, scheme):
     """Unsupported flag/scheme combinations fail (PIC_ERR_UNSUPPORTED) before
     the workspace is looked at."""
