@@ -113,3 +113,9 @@ def test_batch_config_rules_without_gpu():
     assert lib.pic_batch_workspace_bytes(arr2, 2) == 0
     assert b"share" in lib.pic_last_error(None)
     assert lib.pic_batch_workspace_bytes(arr, 0) == 0
+
+
+def test_checkpoint_keys_are_config_fields():
+    from paper_2410_18414_amd import state
+    names = [n for n, _ in pic.ConfigStruct._fields_]
+    assert all(k in names for k in state._KEYS)
