@@ -75,6 +75,27 @@ def hist_to_flat(p, hist):
     return np.stack(out)
 
 
+def flat_to_hist_bdf(p, flat):
+    """[nfield, ny, nx/2+1] in pic.h's BDF-k export order -> oracle history dict."""
+    k = p.bdf_order
+    flat = np.asarray(flat, np.complex128)
+    rho = [flat[j] for j in range(k)]
+    phi = [flat[k + j] for j in range(2 * k)]
+    A = [np.stack([flat[3 * k + 3 * j + l] for l in range(3)]) for j in range(2 * k)]
+    return dict(rho=rho, phi=phi, A=A)
+
+
+def oracle_from_gpu(p, ctx, w):
+    """An oracle State holding the GPU context's particles and BDF-k history
+    (promoted to float64)."""
+    from paper_2410_18414_amd import pic
+    s = opic.State(p, w["x"], w["y"], w["P"])
+    a = pic.get_particles(ctx).cpu().numpy()
+    s.part = dict(x=a[0].copy(), y=a[1].copy(), P=a[2:5].T.copy(), v=a[5:8].T.copy(), vprev=a[8:11].T.copy())
+    s.hist = flat_to_hist_bdf(p, pic.get_history(ctx).cpu().numpy())
+    return s
+
+
 def rel(a, b):
     """Normwise relative error ||a - b||_inf / ||b||_inf (absolute if b == 0)."""
     a, b = np.asarray(a), np.asarray(b)

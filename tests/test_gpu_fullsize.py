@@ -99,3 +99,77 @@ def test_128_graph_replay_invariants_and_direct_equality(gpu_lib):
     for k in range(11):
         assert rel(a[k], b[k]) <= 1e-10, k
     assert rel(pic.get_history(g).cpu().numpy(), pic.get_history(n).cpu().numpy()) <= 1e-10
+
+
+def test_cloud32_full_run_f64(gpu_lib):
+    """The 32x32, 4 particles/cell drifting cloud (quadratic, BDF-1, float64)
+    over its full 50 steps through graph-replayed step() against the oracle."""
+    from pic_harness import compare_particles, gpu_parts, hist_to_flat, make_gpu, make_oracle
+    w = workloads.make("cloud32")
+    o = make_oracle(w, 2, "bdf", 1)
+    g = make_gpu(w, 2, "bdf", "f64", bdf_order=1)
+    o.step(50)
+    pic.step(g, 50)
+    errs, bad = compare_particles(gpu_parts(g), o.part, w["lx"], w["ly"], 1e-10)
+    assert not bad, errs
+    assert rel(pic.get_history(g).cpu().numpy(), hist_to_flat(o.p, o.hist)) <= 1e-10
+    d = pic.diagnostics(g)
+    assert d["gauge_l2"] <= 1e3 * EPS * d["gauge_scale"]
+    g.close()
+
+
+def test_weibel128_200_steps_shadow_stepping(gpu_lib):
+    """The 128x128, 64 particles/cell float32 workload over its full 200 steps
+    in the bench's launch configuration; every 20 steps the oracle is loaded
+    with the GPU state (promoted to float64) and one step of each is compared
+    (float32 parity 1e-4), and the gauge stays at round-off."""
+    import time
+    from pic_harness import compare_particles, gpu_parts, make_gpu, oracle_from_gpu
+    w = workloads.make("weibel128")
+    p = oracle_params(w, 3, "bdf", 2)
+    g = make_gpu(w, 3, "bdf", "f32", bdf_order=2)
+    t0 = time.time()
+    done = 0
+    while done < 200:
+        pic.step(g, 19)
+        o = oracle_from_gpu(p, g, w)
+        o.step(1)
+        pic.step(g, 1)
+        done += 20
+        errs, bad = compare_particles(gpu_parts(g), o.part, w["lx"], w["ly"], 1e-4)
+        assert not bad, (done, errs)
+        print("step %d shadow ok (%.0f s)" % (done, time.time() - t0), flush=True)
+    d = pic.diagnostics(g)
+    assert d["nonfinite"] == 0
+    assert d["gauge_l2"] <= 1e3 * np.finfo(np.float64).eps * d["gauge_scale"], d
+    g.close()
+
+
+def test_full_ensemble_sampled(gpu_lib):
+    """The 64-instance uneven ensemble (31M float32 particles) as the bench
+    runs it (one context, graph-replayed step_batched): the four smallest
+    instances against the oracle after 3 steps (1e-4), every instance's gauge
+    residual at round-off."""
+    import torch
+    from pic_harness import compare_particles, gpu_parts, make_oracle
+    ws = workloads.ensemble()
+    cfgs = [pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=3, scheme="bdf", bdf_order=2,
+                            dtype="f32", q=w["q"], m=w["m"], max_particles=len(w["x"])) for w in ws]
+    b = pic.Context(cfgs)
+    for i, w in enumerate(ws):
+        pic.select_instance(b, i)
+        pic.init_particles(b, torch.as_tensor(w["x"], device=b.device), torch.as_tensor(w["y"], device=b.device),
+                           torch.as_tensor(np.ascontiguousarray(w["P"].T), device=b.device))
+    pic.step_batched(b, 3)
+    for i in np.argsort([len(w["x"]) for w in ws])[:4]:
+        w = ws[i]
+        o = make_oracle(w, 3, "bdf", 2)
+        o.step(3)
+        pic.select_instance(b, int(i))
+        errs, bad = compare_particles(gpu_parts(b), o.part, w["lx"], w["ly"], 1e-4)
+        assert not bad, (int(i), errs)
+    for i in range(len(ws)):
+        pic.select_instance(b, i)
+        d = pic.diagnostics(b)
+        assert d["nonfinite"] == 0 and d["gauge_l2"] <= 1e3 * EPS * d["gauge_scale"], (i, d)
+    b.close()
