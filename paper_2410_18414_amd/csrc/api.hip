@@ -1168,6 +1168,14 @@ pic_status_t pic_get_field(pic_ctx_t c, int32_t which, double* dst) {
   }
   if (which == PIC_FIELD_MESH) {
     if (c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "mesh fields are valid in phase SOLVED");
+    if (c->dtype == PIC_F32) {
+      // the step writes only the float32 copy: the float64 planes from the
+      // solve's spectra (U is valid until the next solve)
+      pic_status_t st = c->hip(launch_rows_c2r(c->d_desc, c->ninst(), c->nblk[BK_C2R], c->lds_c2r, c->stream,
+                                               false, true),
+                               "mesh field export");
+      if (st) return st;
+    }
     return c->hip(hipMemcpyAsync(dst, in.d.F64, 12 * plane * 8, hipMemcpyDeviceToDevice, c->stream),
                   "copy mesh fields");
   }

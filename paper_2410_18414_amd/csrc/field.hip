@@ -384,7 +384,10 @@ __constant__ int kMulKx[12] = {1, 0, 0, 0, 0, 1, 1, 1, 0, 0, 0, 0};
 //
 // adj: the three columns LS[0..2] of the adjoint solve to the real fields LJ
 // (pairs (0, 1) and (2, -); no kx factor).
-__global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D, int ninst, int adj) {
+// f64out: also write the float64 planes (always for float64 particles and the
+// adjoint; float32 contexts read only the node-major float32 copy, and their
+// float64 planes are written on demand for the mesh-field export)
+__global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D, int ninst, int adj, int f64out) {
   extern __shared__ double2 sm[];
   const int ii = find_inst(D, ninst, BK_C2R, blockIdx.x);
   const InstDesc& d = D[ii];
@@ -431,8 +434,10 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
     const int r = t / N, x = t - r * N;
     const size_t o = (size_t)(y0 + r) * N + x;
     const double2 z = res[t];
-    F64[s0 * plane + o] = z.x;
-    if (has1) F64[s1 * plane + o] = z.y;
+    if (f64out || !F32) {
+      F64[s0 * plane + o] = z.x;
+      if (has1) F64[s1 * plane + o] = z.y;
+    }
     if (F32)  // node-major record: slots s0, s0 + 1 of node o
       *reinterpret_cast<float2*>(F32 + o * kFieldSlots + s0) = make_float2((float)z.x, (float)z.y);
   }
@@ -662,9 +667,10 @@ hipError_t launch_j_export(const long long* src, double* dst, size_t n, double u
   return hipGetLastError();
 }
 
-hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {
+hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj,
+                           bool f64out) {
   hipFuncSetAttribute((const void*)k_rows_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k_rows_c2r, dim3(nblocks), dim3(256), lds, s, D, ninst, adj ? 1 : 0);
+  hipLaunchKernelGGL(k_rows_c2r, dim3(nblocks), dim3(256), lds, s, D, ninst, adj ? 1 : 0, f64out ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -229,7 +229,9 @@ size_t columns_split_lds_bytes(int ny, int nstage);  // nstage: sub-stepped DIRK
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false);
 hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int ninst, int nblocks, size_t lds,
                           HistSlots hs, hipStream_t s);
-hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false);
+// f64out: the float64 mesh planes too (float32 contexts skip them in the step)
+hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false,
+                           bool f64out = false);
 hipError_t launch_hist_transpose(const double2* src, double2* dst, int nfield, GridP g, bool to_external,
                                  hipStream_t s);
 // adjoint.hip (one float64 BDF-k instance; D[0])
