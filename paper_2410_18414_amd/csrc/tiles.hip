@@ -288,15 +288,28 @@ __global__ void __launch_bounds__(kThreads) k_cell_scan(const InstDesc* __restri
   if (threadIdx.x == 0) *d.tb.done = 0;  // ready for the next sort
 }
 
+// XCD-contiguous block order: the dispatcher deals consecutive workgroups to
+// the eight XCDs in turn (block b to XCD b mod 8); this bijection of [0, nb)
+// gives each XCD one contiguous run of logical blocks instead of every eighth
+__device__ __forceinline__ int xcd_contiguous(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, j = b >> 3;
+  return x * q + min(x, r) + j;
+}
+
 // scatter set `src` into set `src ^ 1`, grouped by cell: particle i goes to its
 // tile's start + its cell's offset in the tile + its slot in the cell (from the
-// count pass); no atomics, so the copy streams
+// count pass); no atomics, so the copy streams.  The source is in the previous
+// sort's cell order, so an XCD-contiguous run of source blocks covers one
+// region of the grid, and the short runs its waves write per destination cell
+// mostly land in that region: neighbouring runs of one cache line are then
+// written through the same L2 rather than from several XCDs.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __restrict__ D, int ninst, int src) {
-  const int ii = find_inst(D, ninst, BK_PART, blockIdx.x);
+  const int bb = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int ii = find_inst(D, ninst, BK_PART, bb);
   const InstDesc& d = D[ii];
   const TileP tp = d.tp;
-  const int64_t i = (int64_t)(blockIdx.x - d.blk[BK_PART]) * kThreads + threadIdx.x;
+  const int64_t i = (int64_t)(bb - d.blk[BK_PART]) * kThreads + threadIdx.x;
   if (i >= d.n) return;  // no cross-lane operations below
   const void* const* S = d.set[src];
   void* const* Dd = d.set[src ^ 1];
