@@ -400,14 +400,14 @@ struct pic_ctx_s {
   double t_n[PIC_KCLASS_COUNT] = {0};
 
   ~pic_ctx_s() {
-    if (gexec) hipGraphExecDestroy(gexec);
-    if (cap_stream) hipStreamDestroy(cap_stream);
-    if (side) hipStreamDestroy(side);
-    if (ev_fork) hipEventDestroy(ev_fork);
-    if (ev_join) hipEventDestroy(ev_join);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
     for (auto& e : ev) {
-      if (e.a) hipEventDestroy(e.a);
-      if (e.b) hipEventDestroy(e.b);
+      if (e.a) (void)hipEventDestroy(e.a);
+      if (e.b) (void)hipEventDestroy(e.b);
     }
   }
   int ninst() const { return (int)inst.size(); }
@@ -440,11 +440,11 @@ struct pic_ctx_s {
     }
     EvPair* p = &ev[ev_used++];
     p->cls = cls;
-    hipEventRecord(p->a, stream);
+    (void)hipEventRecord(p->a, stream);
     return p;
   }
   void end_timed(EvPair* p) {
-    if (p) hipEventRecord(p->b, stream);
+    if (p) (void)hipEventRecord(p->b, stream);
   }
 
   pic_status_t fail(pic_status_t st, const std::string& m) {
@@ -625,7 +625,10 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     return PIC_ERR_HIP;
   }
   int max_lds = 0;
-  hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    g_err = "hipDeviceGetAttribute (LDS per block) failed";
+    return PIC_ERR_HIP;
+  }
   auto* c = new pic_ctx_s();
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)workspace;
@@ -887,7 +890,7 @@ void state_key(pic_ctx_t c, int64_t* k) {
 // capture itself advances the host-side state by `period` iterations)
 pic_status_t capture_and_launch(pic_ctx_t c, bool unfused, int period) {
   if (c->gexec) {
-    hipGraphExecDestroy(c->gexec);
+    (void)hipGraphExecDestroy(c->gexec);
     c->gexec = nullptr;
   }
   if (!c->cap_stream) {
@@ -903,7 +906,7 @@ pic_status_t capture_and_launch(pic_ctx_t c, bool unfused, int period) {
   if (st) return st;
   st = c->hip(hipEventRecord(ev, user), "capture event record");
   if (!st) st = c->hip(hipStreamWaitEvent(c->cap_stream, ev, 0), "capture wait");
-  hipEventDestroy(ev);
+  (void)hipEventDestroy(ev);
   if (st) return st;
   st = c->hip(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed), "begin capture");
   if (st) return st;
@@ -913,11 +916,11 @@ pic_status_t capture_and_launch(pic_ctx_t c, bool unfused, int period) {
   hipGraph_t graph = nullptr;
   pic_status_t st2 = c->hip(hipStreamEndCapture(c->cap_stream, &graph), "end capture");
   if (st || st2) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return st ? st : st2;
   }
   st = c->hip(hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0), "graph instantiate");
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (st) return st;
   state_key(c, k1);
   c->gperiod = period;

@@ -621,7 +621,7 @@ size_t adj_columns_lds_bytes(int ny) {
 }
 
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj) {
-  hipFuncSetAttribute((const void*)k_rows_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)k_rows_r2c, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_rows_r2c, dim3(nblocks), dim3(256), lds, s, D, ninst, adj ? 1 : 0);
   return hipGetLastError();
 }
@@ -669,7 +669,7 @@ hipError_t launch_j_export(const long long* src, double* dst, size_t n, double u
 
 hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj,
                            bool f64out) {
-  hipFuncSetAttribute((const void*)k_rows_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)k_rows_c2r, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k_rows_c2r, dim3(nblocks), dim3(256), lds, s, D, ninst, adj ? 1 : 0, f64out ? 1 : 0);
   return hipGetLastError();
 }
