@@ -215,7 +215,8 @@ TileP plan_tiles(const pic_config_t& c) {
 
 struct Layout {
   size_t set_bytes;  // one particle set: 11 arrays (cap x es) + ids
-  size_t parts, J, T, RB, H, U, F64, F32, twx, twy, tcount, tstart, ccount, ccursor, twork, tnwork, tdone, trank,
+  size_t parts, J, T, RB, H, U, F64, F32, twx, twy, tcount, tstart, tcstart, ccount, ccursor, twork, tnwork, tdone,
+      trank,
       LF, LS, LJ, total;
   size_t plane_c;    // complex entries per spectral plane
 };
@@ -252,6 +253,7 @@ Layout plan_instance(const pic_config_t& c) {
   L.twy = take((size_t)c.ny * 16);
   L.tcount = take((size_t)tp.ntiles * 4);
   L.tstart = take(((size_t)tp.ntiles + 1) * 4);
+  L.tcstart = take((size_t)tp.ntiles * 4);
   const size_t ckeys = (size_t)tp.ntiles * tp.ts * tp.ts;  // cell keys (>= nx ny)
   L.ccount = take(ckeys * 4);
   L.ccursor = take(ckeys * 4);
@@ -702,6 +704,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.tb.ccount = (int32_t*)(b + in.L.ccount);
     d.tb.ccursor = (int32_t*)(b + in.L.ccursor);
     d.tb.work = (int4*)(b + in.L.twork);
+    d.tb.cstart = (int32_t*)(b + in.L.tcstart);
     d.tb.nwork = (int32_t*)(b + in.L.tnwork);
     d.tb.done = (int32_t*)(b + in.L.tdone);
     d.tb.rank = (int32_t*)(b + in.L.trank);

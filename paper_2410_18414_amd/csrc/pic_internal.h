@@ -74,7 +74,9 @@ struct TileBufs {
   int32_t* start;    // [ntiles+1] first particle of each tile
   int32_t* ccount;   // [ntiles*ts*ts] particles per cell key; zero between sorts
   int32_t* ccursor;  // [ntiles*ts*ts] first slot of each cell, from its tile's start
-  int4* work;        // [max_work] (tile, first particle, count, 0)
+  int4* work;        // [max_work] (tile, first particle, count, rows): rows = r0 | r1 << 16, the
+                     //            tile-local cell rows of the chunk's first and last particle at the sort
+  int32_t* cstart;   // [ntiles]   each tile's first chunk in work
   int32_t* nwork;    // [1]        chunks in use
   int32_t* done;     // [1]        blocks of the cell scan finished; zero between sorts
   int32_t* rank;     // [capacity] each particle's slot among its cell's particles (count pass)

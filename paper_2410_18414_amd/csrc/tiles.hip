@@ -222,6 +222,7 @@ __device__ void tile_scan_block(const InstDesc& d, const TileP& tp) {
     const int k0 = carry_c + s_chk[tid] - k;
     if (t < tp.ntiles) {
       d.tb.start[t] = p0;
+      d.tb.cstart[t] = k0;
       for (int j = 0; j < k; ++j) {
         const int s = p0 + j * tp.chunk;
         const int e = min(p0 + c, s + tp.chunk);
@@ -318,10 +319,25 @@ __global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __res
   for (int a = 0; a < 11; ++a) rec[a] = ((const T*)S[a])[i];
   const int32_t id = d.ids[src][i], slot = d.tb.rank[i];
   const int c = cell_key(rec[0], rec[1], d.g, tp);  // the count pass's key of the same positions
-  const int64_t o = (int64_t)d.tb.start[c >> (2 * tp.log_ts)] + d.tb.ccursor[c] + slot;
+  const int tt = c >> (2 * tp.log_ts);
+  const int32_t t0 = d.tb.start[tt];
+  const int rel = d.tb.ccursor[c] + slot;  // slot in the tile
+  const int64_t o = (int64_t)t0 + rel;
 #pragma unroll
   for (int a = 0; a < 11; ++a) ((T*)Dd[a])[o] = rec[a];
   d.ids[src ^ 1][o] = id;
+  // a chunk's first and last particles record its span of cell rows (slots
+  // are in cell order, cells row-major in the tile) for the tiled pass's
+  // field-window rows; the cell scan wrote the field as zero
+  const int j = rel / tp.chunk, in_chunk = rel - j * tp.chunk;
+  const bool first = in_chunk == 0;
+  const bool last = in_chunk == tp.chunk - 1 || rel == d.tb.start[tt + 1] - t0 - 1;
+  if (first || last) {
+    const int row = (c & ((1 << (2 * tp.log_ts)) - 1)) >> tp.log_ts;
+    int* rows = reinterpret_cast<int*>(d.tb.work + d.tb.cstart[tt] + j) + 3;
+    if (first) atomicOr(rows, row);
+    if (last) atomicOr(rows, row << 16);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -388,6 +404,12 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   auto modw = [&](int v, int n) { return pw ? (v & (n - 1)) : (v < 0 ? v + n : (v >= n ? v - n : v)); };
   const int tiy = pw ? it.x >> tp.log_ntx : it.x / tp.ntx, tix = it.x - tiy * tp.ntx;
   const int ox = tix * ts - slack - 1, oy = tiy * ts - slack - 1;
+  // field-window rows this chunk can read: its particles' cell rows at the
+  // sort lie in [r0, r1] (tile-local), they have moved at most the slack since
+  // (the sort interval keeps them there), and a stencil of any degree starts
+  // at most two nodes below its cell and spans at most six; a stencil outside
+  // [jlo, jhi) takes the global gather, so the bound is a speed-up only
+  const int jlo = max(0, (it.w & 0xffff) - 1), jhi = min(W, (it.w >> 16) + 2 * slack + 5);
   extern __shared__ __align__(16) unsigned char smem[];
   T* fw = reinterpret_cast<T*>(smem);
   A* jw = reinterpret_cast<A*>(smem + (GATHER ? (size_t)kNodeSlots * WP * sizeof(T) : 0));
@@ -439,10 +461,13 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       if (FIXED) {
         constexpr int NJ = (G::W + (kThreads >> G::LRL) - 1) / (kThreads >> G::LRL);
 #pragma unroll
-        for (int r = 0; r < NJ; ++r)
-          if (wj0 + r * wjs < W) copy_row(wj0 + r * wjs);
+        for (int r = 0; r < NJ; ++r) {
+          const int j = wj0 + r * wjs;
+          if (j >= jlo && j < jhi) copy_row(j);
+        }
       } else {
-        for (int j = wj0; j < W; j += wjs) copy_row(j);
+        for (int j = wj0; j < W; j += wjs)
+          if (j >= jlo && j < jhi) copy_row(j);
       }
     } else if (FIXED) {
       // compile-time sweep: a thread's rows (at most NJ) and fields all load
@@ -452,7 +477,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
 #pragma unroll
       for (int r = 0; r < NJ; ++r) {
         const int j = wj0 + r * wjs;
-        if (j < W) {
+        if (j >= jlo && j < jhi) {
           const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
 #pragma unroll
           for (int f = 0; f < 11; ++f) v[r][f] = F[f * plane + go];
@@ -461,13 +486,14 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
 #pragma unroll
       for (int r = 0; r < NJ; ++r) {
         const int j = wj0 + r * wjs;
-        if (j < W) {
+        if (j >= jlo && j < jhi) {
 #pragma unroll
           for (int f = 0; f < 11; ++f) fw[(j * W + wi) * kNodeSlots + f] = v[r][f];
         }
       }
     } else {
       for (int j = wj0; j < W; j += wjs) {
+        if (j < jlo || j >= jhi) continue;
         const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
         const int node = j * W + wi;
 #pragma unroll
@@ -523,7 +549,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         S::eval(xi, sx, wx);
         S::eval(eta, sy, wy);
         const int lx = modw(sx - ox, g.nx), ly = modw(sy - oy, g.ny);
-        if (lx + DEG < W && ly + DEG < W) {
+        if (lx + DEG < W && ly >= jlo && ly + DEG < jhi) {
           const T* nd0 = fw + (ly * W + lx) * kNodeSlots;
 #pragma unroll
           for (int b = 0; b < NW; ++b) {
