@@ -1,19 +1,24 @@
 """Throughput of the full PIC step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload weibel128]
+    python bench.py [--steps K] [--warmup W] [--repeats R] [--gpus 1] [--workload weibel512-dirk2]
 
 One step = Algorithm 1 once over every particle: position update and current
 deposit, FFT field solve (continuity + stepper update + spectral gradients),
 gather and IAEM push (the libpic `step` entry point, gather/push of step n
 fused with the deposit of step n+1).  Inputs are resident in HBM before the
-timed region; the K timed steps are bracketed by stream synchronisations.
+timed regions; each of R timed regions of exactly K steps is bracketed by
+device synchronisations, and the median region is reported.
 
-Prints one JSON line with the particle-steps/s value, a roofline entry for the
-dominant kernel (the fused gather/push/deposit particle pass, timed with HIP
-events on the library's stream inside the timed region), the batched form
-(64-instance uneven ensemble, tile plan from the autotuner) and the adjoint
-form (gradient through 20 float64 steps) against the plain step, and the FP64
-oracle timed on the host on a bounded sample of the same workload.
+The headline workload is the 512 x 512 grid with 256 particles per cell
+(67,108,864 float32 particles, cubic splines, DIRK-2), the largest
+single-GPU configuration.  Prints one JSON line with its particle-steps/s
+value, a roofline entry for the dominant kernel (the fused
+gather/push/deposit particle pass, timed with HIP events on the library's
+stream), the same workload under CDF-2 and the 128 x 128 workload as
+sections, the batched form (64-instance uneven ensemble, tile plan from the
+autotuner) and the adjoint form (gradient through 20 float64 steps) against
+the plain step, and the FP64 oracle timed on one host core on a bounded
+sample of the headline workload.
 """
 
 import argparse
@@ -76,28 +81,57 @@ def measured_traffic(tag):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, spec, nsteps):
-    """The FP64 oracle (numpy, single thread) on the same particles and grid."""
-    from oracle import pic as opic
-    p = opic.Params(w["nx"], w["ny"], w["lx"], w["ly"], spec["degree"], spec["scheme"], w["dt"],
-                    q=w["q"], m=w["m"], bdf_order=spec["bdf_order"])
-    s = opic.State(p, w["x"], w["y"], w["P"])
-    t0 = time.perf_counter()
-    s.step(nsteps)
-    dt = time.perf_counter() - t0
-    n = len(w["x"])
-    model = "unknown"
+def cpu_description():
+    """The host CPU as /proc/cpuinfo names it (model string, vendor, family,
+    model and stepping numbers, clock and cache of the first logical CPU) and
+    the logical CPUs this process may run on."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
+                if not line.strip():
+                    break  # first logical CPU only
+                key, _, val = line.partition(":")
+                info[key.strip()] = val.strip()
     except OSError:
         pass
-    return dict(value=n * nsteps / dt, unit="particle-steps/s", cores=1, kind="oracle",
-                sample="%d full steps of the same %d-particle workload (numpy float64, one thread)"
-                       % (nsteps, n), cpu_model=model)
+    keys = ("model name", "vendor_id", "cpu family", "model", "stepping", "cpu MHz", "cache size")
+    desc = "; ".join("%s: %s" % (k, info[k]) for k in keys if k in info) or "unknown"
+    return desc, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(w, spec, nsub, nsteps):
+    """The FP64 oracle (numpy) on a bounded sample of the same workload: its
+    first `nsub` particles (uniformly placed, so the sample keeps the
+    workload's spatial distribution at nsub / n of its density) on the full
+    grid with the same stepper, `nsteps` complete steps, on ONE host core:
+    the calling thread is pinned to one CPU and the BLAS/OpenMP pools are
+    limited to one thread while the oracle runs."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pic as opic
+    nsub = min(nsub, len(w["x"]))
+    p = opic.Params(w["nx"], w["ny"], w["lx"], w["ly"], spec["degree"], spec["scheme"], w["dt"],
+                    q=w["q"], m=w["m"], bdf_order=spec["bdf_order"])
+    x, y, P = w["x"][:nsub].copy(), w["y"][:nsub].copy(), w["P"][:nsub].copy()
+    mask = os.sched_getaffinity(0)
+    core = min(mask)
+    os.sched_setaffinity(0, {core})
+    try:
+        with threadpool_limits(limits=1):
+            s = opic.State(p, x, y, P)
+            t0, c0 = time.perf_counter(), time.thread_time()
+            s.step(nsteps)
+            dt, cpu = time.perf_counter() - t0, time.thread_time() - c0
+    finally:
+        os.sched_setaffinity(0, mask)
+    desc, ncpu = cpu_description()
+    return dict(value=nsub * nsteps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample="%d full %s steps of the first %d of the workload's %d particles on its full %dx%d grid "
+                       "(numpy float64; one thread pinned to one core)"
+                       % (nsteps, spec["scheme"], nsub, len(w["x"]), w["nx"], w["ny"]),
+                seconds=round(dt, 2), thread_cpu_seconds=round(cpu, 2),
+                cpu_model=desc, host_logical_cpus=ncpu)
 
 
 def _events(stream):
@@ -336,13 +370,122 @@ def bench_adjoint(every=5):
                 particle_steps_per_s=round(n * nsteps / (ms_grad * 1e-3), 1))
 
 
+def kernel_label(spec, nx, ny, tile_cells=0, slack=0):
+    """The fused pass's template instance: k_tiled<T, degree, MODE_FUSED = 2,
+    tile edge, slack>; the compiled window geometries (16- or 8-cell tiles with
+    a slack of 3) run on power-of-two grids, every other plan on <.., 0, 0>."""
+    t = "float" if spec["dtype"] == "f32" else "double"
+    pow2 = not (nx & (nx - 1) or ny & (ny - 1))
+    ts = tile_cells or 16
+    while ts > min(nx, ny):
+        ts //= 2
+    sl = slack or 3
+    geo = (ts, sl) if pow2 and sl == 3 and ts in (16, 8) else (0, 0)
+    return "k_tiled<%s, %d, 2, %d, %d>" % (t, spec["degree"], geo[0], geo[1])
+
+
+def measure_plain(w, spec, args, steps, warmup, repeats, flags=0, traffic_tag=None):
+    """Throughput of `step` on one workload: `warmup` untimed steps, then
+    `repeats` timed regions of exactly `steps` steps each (HIP events on the
+    library's stream, bracketed by device synchronisations), reported as the
+    median; then one more region of `steps` steps with HIP events around every
+    launch group (kernel durations for the roofline)."""
+    import torch
+    from paper_2410_18414_amd import pic
+    n = len(w["x"])
+    cfg = pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=spec["degree"],
+                          scheme=spec["scheme"], bdf_order=spec["bdf_order"], dtype=spec["dtype"],
+                          q=w["q"], m=w["m"], max_particles=n, flags=flags,
+                          sort_interval=args.sort_interval, tile_cells=args.tile_cells,
+                          chunk=args.chunk, slack=args.slack)
+    ctx = pic.Context(cfg, device="cuda:0")
+    dev = ctx.device
+    pic.init_particles(ctx, torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
+                       torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev))
+    # untimed warm-up; when a timed region is long enough to replay the
+    # captured step graph, the warm-up spans one graph period plus a step so
+    # that the one-time capture stays out of the timed regions
+    period = pic.graph_period(ctx)
+    if period and steps - 1 >= period:
+        warmup = max(warmup, period + 1)
+    pic.step(ctx, warmup)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps, walls = [], []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        start.record(ctx.stream)
+        t0 = time.perf_counter()
+        pic.step(ctx, steps)
+        stop.record(ctx.stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        reps.append(start.elapsed_time(stop))
+    ms = float(np.median(reps))
+    # kernel durations: the same number of steps with events around every launch group
+    pic.set_kernel_timing(ctx, True)
+    pic.kernel_timing(ctx)  # reset
+    torch.cuda.synchronize()
+    start.record(ctx.stream)
+    pic.step(ctx, steps)
+    stop.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms_events = start.elapsed_time(stop)
+    kt = pic.kernel_timing(ctx)
+    pic.set_kernel_timing(ctx, False)
+    diag = pic.diagnostics(ctx)
+    ctx.close()
+    fused_ms, fused_n = kt["fused"]
+    if fused_n == 0:  # unfused run: deposit + gather/push stand in for the fused pass
+        fused_ms, fused_n = kt["deposit"][0] + kt["gather_push"][0], max(kt["gather_push"][1], 1)
+    avg_fused = fused_ms / max(fused_n, 1)
+    alg = n * particle_bytes(spec["dtype"]) + grid_bytes(w["nx"], w["ny"], spec["dtype"])
+    achieved = alg / (avg_fused * 1e-3) / 1e9 if avg_fused > 0 else 0.0
+    traffic = measured_traffic(traffic_tag) if traffic_tag else None
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                # the rocprofv3-measured bytes over the same live launch time
+                traffic_gbs=round(traffic / (avg_fused * 1e-3) / 1e9, 1) if traffic and avg_fused > 0 else None,
+                traffic_frac=(round(traffic / (avg_fused * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                              if traffic and avg_fused > 0 else None),
+                kernel=kernel_label(spec, w["nx"], w["ny"], args.tile_cells, args.slack)
+                + " (fused gather/push/position/deposit)",
+                avg_launch_us=round(avg_fused * 1e3, 2), launches=int(fused_n),
+                algorithmic_bytes_per_launch=int(alg))
+    return dict(n=n, warmup=warmup, ms=ms, reps=reps, wall=walls, ms_events=ms_events, kt=kt,
+                roofline=roof, diag=diag)
+
+
+def workload_config(label, w, spec):
+    return {"workload": label, "grid": [w["nx"], w["ny"]], "particles": len(w["x"]),
+            "ppc": len(w["x"]) // (w["nx"] * w["ny"]), "spline_degree": spec["degree"],
+            "scheme": spec["scheme"] + (str(spec["bdf_order"]) if spec["scheme"] == "bdf" else ""),
+            "particle_dtype": spec["dtype"], "field_dtype": "f64"}
+
+
+def section(label, w, spec, res, steps):
+    """A secondary workload's figures (same protocol as the headline)."""
+    d = res["diag"]
+    return dict(workload=label, particles=res["n"], steps=steps, repeats=len(res["reps"]),
+                ms_per_step=round(res["ms"] / steps, 5),
+                value=round(res["n"] * steps / (res["ms"] * 1e-3), 1),
+                repeat_ms_per_step=[round(r / steps, 5) for r in res["reps"]],
+                roofline=res["roofline"],
+                kernels_ms_per_step={k: round(v[0] / max(steps, 1), 5) for k, v in res["kt"].items()},
+                gauge_rel=d["gauge_l2"] / d["gauge_scale"] if d["gauge_scale"] else 0.0,
+                config=workload_config(label, w, spec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="weibel128", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--repeats", type=int, default=5, help="timed regions of --steps steps; the median is reported")
+    ap.add_argument("--workload", default="weibel512-dirk2", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-particles", type=int, default=1 << 21,
+                    help="particles of the oracle's bounded sample (the first ones of the workload)")
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--unfused", action="store_true", help="run deposit and gather/push as separate kernels")
     ap.add_argument("--no-sort", action="store_true", help="plain global-atomic kernels, no tile sort")
@@ -350,6 +493,8 @@ def main():
     ap.add_argument("--tile-cells", type=int, default=0)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--slack", type=int, default=0)
+    ap.add_argument("--no-sections", action="store_true",
+                    help="skip the second 512x512 stepper and the 128x128 workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance ensemble section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint (gradient) section")
     ap.add_argument("--no-naive", action="store_true", help="skip the naive charge-deposit comparison section")
@@ -365,7 +510,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2410_18414_amd import pic, workloads
+    from paper_2410_18414_amd import workloads
 
     wid, over, label = WORKLOADS[args.workload]
     w = workloads.make(wid)
@@ -382,84 +527,42 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    cfg = pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=spec["degree"],
-                          scheme=spec["scheme"], bdf_order=spec["bdf_order"], dtype=spec["dtype"],
-                          q=w["q"], m=w["m"], max_particles=n,
-                          flags=(pic.FLAG_UNFUSED_STEP if args.unfused else 0)
-                          | (pic.FLAG_NO_SORT if args.no_sort else 0),
-                          sort_interval=args.sort_interval, tile_cells=args.tile_cells,
-                          chunk=args.chunk, slack=args.slack)
-    ctx = pic.Context(cfg, device="cuda:0")
-    dev = ctx.device
-    pic.init_particles(ctx, torch.as_tensor(w["x"], device=dev), torch.as_tensor(w["y"], device=dev),
-                       torch.as_tensor(np.ascontiguousarray(w["P"].T), device=dev))
-    # untimed warm-up; it spans at least one graph period plus a step so that
-    # the one-time graph capture stays out of the timed region
-    warmup = max(args.warmup, pic.graph_period(ctx) + 1)
-    pic.step(ctx, warmup)
-    torch.cuda.synchronize()
-
-    # timed region: K steps through the library's step() (graph replays)
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(ctx.stream)
-    t0 = time.perf_counter()
-    pic.step(ctx, args.steps)
-    stop.record(ctx.stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(stop)
-    # second timed region of the same K steps with HIP events around every
-    # launch group on the library's stream (direct launches): kernel durations
-    pic.set_kernel_timing(ctx, True)
-    pic.kernel_timing(ctx)  # reset
-    torch.cuda.synchronize()
-    start.record(ctx.stream)
-    pic.step(ctx, args.steps)
-    stop.record(ctx.stream)
-    torch.cuda.synchronize()
-    ms_events = start.elapsed_time(stop)
-    kt = pic.kernel_timing(ctx)
-    pic.set_kernel_timing(ctx, False)
-    diag = pic.diagnostics(ctx)
-
-    ms_step = ms / args.steps
-    value = n * args.steps / (ms * 1e-3)
-    fused_ms, fused_n = kt["fused"]
-    if fused_n == 0:  # unfused run: deposit + gather/push stand in for the fused pass
-        fused_ms, fused_n = kt["deposit"][0] + kt["gather_push"][0], max(kt["gather_push"][1], 1)
-    avg_fused = fused_ms / max(fused_n, 1)
-    alg = n * particle_bytes(spec["dtype"]) + grid_bytes(w["nx"], w["ny"], spec["dtype"])
-    achieved = alg / (avg_fused * 1e-3) / 1e9 if avg_fused > 0 else 0.0
+    from paper_2410_18414_amd import pic
+    flags = (pic.FLAG_UNFUSED_STEP if args.unfused else 0) | (pic.FLAG_NO_SORT if args.no_sort else 0)
     default_launch = not (args.unfused or args.no_sort or args.sort_interval or args.tile_cells
                           or args.chunk or args.slack)
-    traffic = measured_traffic(args.workload) if default_launch else None
-    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                # the rocprofv3-measured bytes over the same live launch time
-                traffic_gbs=round(traffic / (avg_fused * 1e-3) / 1e9, 1) if traffic and avg_fused > 0 else None,
-                traffic_frac=(round(traffic / (avg_fused * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-                              if traffic and avg_fused > 0 else None),
-                kernel="k_tiled<float,3,2,16,3> (fused gather/push/position/deposit)",
-                avg_launch_us=round(avg_fused * 1e3, 2),
-                algorithmic_bytes_per_launch=int(alg))
+    res = measure_plain(w, spec, args, args.steps, args.warmup, args.repeats, flags=flags,
+                        traffic_tag=args.workload if default_launch else None)
+    ms_step = res["ms"] / args.steps
+    value = n * args.steps / (res["ms"] * 1e-3)
+    diag = res["diag"]
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "particle-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": warmup, "ms_per_step": round(ms_step, 5),
+        "steps": args.steps, "warmup": res["warmup"], "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": spec["dtype"], "data": "synthetic",
-        "config": {"workload": label, "grid": [w["nx"], w["ny"]], "particles": n,
-                   "ppc": n // (w["nx"] * w["ny"]), "spline_degree": spec["degree"],
-                   "scheme": spec["scheme"] + (str(spec["bdf_order"]) if spec["scheme"] == "bdf" else ""),
-                   "particle_dtype": spec["dtype"], "field_dtype": "f64",
-                   "parallelism": "single-gpu"},
-        "roofline": roof,
-        "kernels_ms_per_step": {k: round(v[0] / max(args.steps, 1), 5) for k, v in kt.items()},
-        "ms_per_step_event_pass": round(ms_events / args.steps, 5),
-        "wall_s": round(wall, 4),
+        "config": dict(workload_config(label, w, spec), parallelism="single-gpu"),
+        "roofline": res["roofline"],
+        "repeats": args.repeats,
+        "repeat_ms_per_step": [round(r / args.steps, 5) for r in res["reps"]],
+        "kernels_ms_per_step": {k: round(v[0] / max(args.steps, 1), 5) for k, v in res["kt"].items()},
+        "ms_per_step_event_pass": round(res["ms_events"] / args.steps, 5),
+        "wall_s": round(float(np.median(res["wall"])), 4),
         "gauge_rel": diag["gauge_l2"] / diag["gauge_scale"] if diag["gauge_scale"] else 0.0,
     }
-    ctx.close()
+    if not args.no_sections:
+        # the other stepper on the same 512x512 particles, and the 128x128 workload
+        others = {"weibel512-dirk2": "weibel512-cdf2", "weibel512-cdf2": "weibel512-dirk2"}
+        todo = ([others[args.workload]] if args.workload in others else []) + \
+               (["weibel128"] if args.workload != "weibel128" else [])
+        for name in todo:
+            wid2, over2, label2 = WORKLOADS[name]
+            w2 = w if wid2 == wid else workloads.make(wid2)
+            spec2 = dict(degree=w2["degree"], scheme=over2.get("scheme", w2["scheme"]),
+                         bdf_order=w2["bdf_order"], dtype=w2["dtype"])
+            r2 = measure_plain(w2, spec2, args, args.steps, args.warmup, args.repeats, flags=flags,
+                               traffic_tag=name if default_launch else None)
+            out[name] = section(label2, w2, spec2, r2, args.steps)
     if not args.no_batched:
         out["batched"] = bench_batched(args.batched_steps, 6)
         out["batched_integer_sides"] = bench_batched_integer_sides()
@@ -470,7 +573,7 @@ def main():
     if not args.no_variants:
         out["variants"] = bench_variants()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, spec, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(w, spec, args.cpu_particles, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 
