@@ -45,22 +45,22 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
   const int lb = blockIdx.x - d.blk[BK_R2C];
   const int c = lb / ngr, y0 = (lb - c * ngr) * R;
   const int nr = min(R, g.ny - y0);  // rows of this group
-  double* __restrict__ Jc = (adj ? d.LF : d.J) + (size_t)c * g.nx * g.ny;
+  const gptr<double> Jc = gp((adj ? d.LF : d.J) + (size_t)c * g.nx * g.ny);
   // the naive mode's rho plane restarts from the ion background
-  const double* __restrict__ reset = (!adj && c == 3) ? d.RB : nullptr;
+  const gptr<const double> reset = gp((const double*)((!adj && c == 3) ? d.RB : nullptr));
   const bool det = !adj && d.det;
-  double2* __restrict__ T = adj ? d.LS : d.T;
+  const gptr<double2> T = gp(adj ? d.LS : d.T);
   const int N = g.nx, B = R >> 1;
   double2* a = sm;
   double2* b = sm + B * N;
   double2* tws = sm + R * N;  // twiddles staged in LDS
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = d.twx[t];
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = gp(d.twx)[t];
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     const int r = t / N, x = t - r * N;
     const size_t i0 = (size_t)(y0 + 2 * r) * N + x, i1 = i0 + N;
     const bool h0 = 2 * r < nr, h1 = 2 * r + 1 < nr;
     if (det) {  // deterministic deposit: int64 sums at scale 2^qe_det
-      const long long* Jq = reinterpret_cast<const long long*>(Jc);
+      const gptr<const long long> Jq = reinterpret_cast<gptr<const long long>>(Jc);
       a[t] = make_double2(h0 ? (double)Jq[i0] * d.det_unscale : 0.0, h1 ? (double)Jq[i1] * d.det_unscale : 0.0);
     } else {
       a[t] = make_double2(h0 ? Jc[i0] : 0.0, h1 ? Jc[i1] : 0.0);
@@ -116,16 +116,16 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
   const int lb = blockIdx.x - d.blk[BK_COL];
   const int kx = lb / kColParts, part = lb - kx * kColParts;
   const int N = g.ny, tid = threadIdx.x, nth = blockDim.x;
-  const double2* __restrict__ T = d.T;
-  double2* __restrict__ H = d.H;
-  double2* __restrict__ U = d.U;
+  const gptr<const double2> T = gp((const double2*)d.T);
+  const gptr<double2> H = gp(d.H);
+  const gptr<double2> U = gp(d.U);
   const size_t plane = (size_t)g.nxh * N;
   double2* store = sm;
   double2* wk = sm + N;
   const double2* tws = d.twy;
   if (N <= 512) {
     double2* t_lds = sm + 5 * N;
-    for (int i = tid; i < N; i += nth) t_lds[i] = d.twy[i];
+    for (int i = tid; i < N; i += nth) t_lds[i] = gp(d.twy)[i];
     tws = t_lds;
   }
   double2* stg = sm + (N <= 512 ? 6 : 5) * N;
@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
     wk[i] = T[((size_t)(c0 + c) * g.nxh + kx) * N + y];
   }
   // history terms of this thread's modes ky = tid + m * nth
-  auto at = [&](int slot, int ky) -> double2& { return H[(size_t)slot * plane + (size_t)kx * N + ky]; };
+  auto at = [&](int slot, int ky) -> decltype(auto) { return H[(size_t)slot * plane + (size_t)kx * N + ky]; };
   double2 h0[kColMaxModes], h1[kColMaxModes], h2[kColMaxModes], h3[kColMaxModes], h4[kColMaxModes];
 #pragma unroll
   for (int m = 0; m < kColMaxModes; ++m) {
@@ -396,15 +396,15 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
   const int lb = blockIdx.x - d.blk[BK_C2R];
   const int pr = lb / ngr, y0 = (lb - pr * ngr) * R;
   const int nr = min(R, g.ny - y0);  // rows of this group (the last may be partial)
-  const double2* __restrict__ U = adj ? d.LS : d.U;
-  double* __restrict__ F64 = adj ? d.LJ : d.F64;
-  float* __restrict__ F32 = adj ? nullptr : d.F32;
+  const gptr<const double2> U = gp((const double2*)(adj ? d.LS : d.U));
+  const gptr<double> F64 = gp(adj ? d.LJ : d.F64);
+  const gptr<float> F32 = gp(adj ? nullptr : d.F32);
   const int N = g.nx;
   const int nyq = (N & 1) ? -1 : N >> 1;  // Nyquist bin (even nx only)
   double2* a = sm;
   double2* b = sm + R * N;
   double2* tws = sm + 2 * R * N;  // twiddles staged in LDS
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = d.twx[t];
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = gp(d.twx)[t];
   const int s0 = 2 * pr, s1 = s0 + 1;
   const int g0 = adj ? s0 : kSrcG[s0], g1 = adj ? s1 : kSrcG[s1];
   const bool has1 = !adj || s1 < 3;
@@ -417,7 +417,8 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
     }
     const double kxs = 2.0 * M_PI * k / g.lx * ((k == nyq) ? 0.0 : 1.0);
     double2 X = U[((size_t)g0 * g.nxh + k) * g.ny + y0 + r];
-    double2 Y = has1 ? U[((size_t)g1 * g.nxh + k) * g.ny + y0 + r] : make_double2(0.0, 0.0);
+    double2 Y = make_double2(0.0, 0.0);
+    if (has1) Y = U[((size_t)g1 * g.nxh + k) * g.ny + y0 + r];
     if (!adj && kMulKx[s0]) X = mul_i(cscale(X, kxs));
     if (!adj && kMulKx[s1]) Y = mul_i(cscale(Y, kxs));
     if (k == 0 || k == nyq) {  // real-signal spectrum: these bins are real
@@ -439,7 +440,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
       if (has1) F64[s1 * plane + o] = z.y;
     }
     if (F32)  // node-major record: slots s0, s0 + 1 of node o
-      *reinterpret_cast<float2*>(F32 + o * kFieldSlots + s0) = make_float2((float)z.x, (float)z.y);
+      *reinterpret_cast<gptr<float2>>(F32 + o * kFieldSlots + s0) = make_float2((float)z.x, (float)z.y);
   }
 }
 

@@ -128,6 +128,7 @@ __device__ __forceinline__ void deposit_global(int sx, int sy, const T* wx, cons
                                                double* __restrict__ J, const GridP& g) {
   using S = Spline<T, DEG>;
   const size_t plane = (size_t)g.nx * g.ny;
+  const gptr<double> Jg = gp(J);
 #pragma unroll
   for (int b = 0; b < S::NW; ++b) {
     const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
@@ -135,9 +136,9 @@ __device__ __forceinline__ void deposit_global(int sx, int sy, const T* wx, cons
     for (int a = 0; a < S::NW; ++a) {
       const T w = wx[a] * wy[b];
       const size_t o = row + wrapi(sx + a, g.nx);
-      atomicAdd(J + o, (double)(jx * w));
-      atomicAdd(J + plane + o, (double)(jy * w));
-      atomicAdd(J + 2 * plane + o, (double)(jz * w));
+      gadd(Jg + o, (double)(jx * w));
+      gadd(Jg + plane + o, (double)(jy * w));
+      gadd(Jg + 2 * plane + o, (double)(jz * w));
     }
   }
 }
@@ -178,7 +179,7 @@ __device__ __forceinline__ void deposit_one(T x, T y, T jx, T jy, T jz, double* 
 // Mesh fields read by the gathers: float64 planar, float32 node-major (see
 // kFieldSlots)
 template <typename T>
-__device__ __forceinline__ T field_at(const T* __restrict__ F, int f, size_t node, size_t plane) {
+__device__ __forceinline__ T field_at(const gptr<const T> F, int f, size_t node, size_t plane) {
   if constexpr (sizeof(T) == 4)
     return F[node * kFieldSlots + f];
   else
@@ -190,6 +191,7 @@ __device__ __forceinline__ void gather_global(int sx, int sy, const T* wx, const
                                               const GridP& g, T* out) {
   using S = Spline<T, DEG>;
   const size_t plane = (size_t)g.nx * g.ny;
+  const gptr<const T> Fg = gp(F);
 #pragma unroll
   for (int b = 0; b < S::NW; ++b) {
     const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
@@ -200,7 +202,7 @@ __device__ __forceinline__ void gather_global(int sx, int sy, const T* wx, const
     for (int a = 0; a < S::NW; ++a) {
       const size_t o = row + wrapi(sx + a, g.nx);
 #pragma unroll
-      for (int f = 0; f < 11; ++f) acc[f] += wx[a] * field_at(F, f, o, plane);
+      for (int f = 0; f < 11; ++f) acc[f] += wx[a] * field_at<T>(Fg, f, o, plane);
     }
 #pragma unroll
     for (int f = 0; f < 11; ++f) out[f] += wy[b] * acc[f];

@@ -39,6 +39,49 @@ struct Parts {
   int32_t* id;
 };
 
+// Device pointers into global memory.  A pointer the compiler reads from a
+// descriptor in memory is generic to it, and generic (flat) loads and stores
+// count against the LDS wait counter as well as the vector-memory one: a wave
+// that waits for its LDS reads would then also wait for every global load it
+// has in flight (e.g. the next particle's prefetch).  Kernels cast such
+// pointers into the global address space before using them.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(T* p) {
+  return (gptr<T>)p;
+}
+// relaxed device-scope atomic add through a global pointer
+template <typename T>
+__device__ __forceinline__ void gadd(gptr<T> p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Particle SoA pointers in the global address space (device code)
+template <typename T>
+struct GParts {
+  gptr<T> x;
+  gptr<T> y;
+  gptr<T> P[3];
+  gptr<T> v[3];
+  gptr<T> w[3];
+  gptr<int32_t> id;
+};
+
+template <typename T>
+__device__ __forceinline__ GParts<T> global_parts(const Parts<T>& p) {
+  GParts<T> g;
+  g.x = gp(p.x);
+  g.y = gp(p.y);
+  for (int c = 0; c < 3; ++c) {
+    g.P[c] = gp(p.P[c]);
+    g.v[c] = gp(p.v[c]);
+    g.w[c] = gp(p.w[c]);
+  }
+  g.id = gp(p.id);
+  return g;
+}
+
 // Spectral history slot table for one update: slot index of each (group, level).
 struct HistSlots {
   int rho[6];

@@ -92,7 +92,7 @@ __device__ __forceinline__ void deposit_global_fixed(int sx, int sy, const T* wx
                                                      double* __restrict__ J, const GridP& g) {
   using S = Spline<T, DEG>;
   const size_t plane = (size_t)g.nx * g.ny;
-  unsigned long long* Jq = reinterpret_cast<unsigned long long*>(J);
+  const gptr<unsigned long long> Jq = gp(reinterpret_cast<unsigned long long*>(J));
   auto q = [](T v, T w) -> long long {
     if constexpr (sizeof(T) == 4)
       return (long long)(int32_t)(__float_as_uint(__builtin_fmaf(v, w, kMagic)) - kMagicBits);
@@ -106,9 +106,9 @@ __device__ __forceinline__ void deposit_global_fixed(int sx, int sy, const T* wx
     for (int a = 0; a < S::NW; ++a) {
       const T w = wx[a] * wy[b];
       const size_t o = row + wrapi(sx + a, g.nx);
-      atomicAdd(Jq + o, (unsigned long long)q(sjx, w));
-      atomicAdd(Jq + plane + o, (unsigned long long)q(sjy, w));
-      atomicAdd(Jq + 2 * plane + o, (unsigned long long)q(sjz, w));
+      gadd(Jq + o, (unsigned long long)q(sjx, w));
+      gadd(Jq + plane + o, (unsigned long long)q(sjy, w));
+      gadd(Jq + 2 * plane + o, (unsigned long long)q(sjz, w));
     }
   }
 }
@@ -158,10 +158,11 @@ __device__ __forceinline__ int wave_group_add(int32_t* __restrict__ counters, in
   rank = __popcll(grp & ((1ull << lane) - 1ull));
   int b = 0;
   if (active && lane == leader) {
+    const gptr<int32_t> ctr = gp(counters) + key;
     if (RET)
-      b = atomicAdd(&counters[key], __popcll(grp));
+      b = __hip_atomic_fetch_add(ctr, (int32_t)__popcll(grp), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
-      atomicAdd(&counters[key], __popcll(grp));
+      gadd(ctr, (int32_t)__popcll(grp));
   }
   return RET ? __shfl(b, leader) : 0;
 }
@@ -177,8 +178,9 @@ __global__ void __launch_bounds__(kThreads) k_tile_count(const InstDesc* __restr
   const InstDesc& d = D[ii];
   const TileP tp = d.tp;
   const GridP g = d.g;
-  const T* __restrict__ px = (const T*)d.set[set][0];
-  const T* __restrict__ py = (const T*)d.set[set][1];
+  const gptr<const T> px = gp((const T*)d.set[set][0]);
+  const gptr<const T> py = gp((const T*)d.set[set][1]);
+  const gptr<int32_t> rank = gp(d.tb.rank);
   const int64_t base = (int64_t)(blockIdx.x - d.blk[BK_COUNT]) * 1024;
   for (int k = 0; k < 4; ++k) {  // whole waves stay in the loop
     const int64_t i = base + k * kThreads + threadIdx.x;
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(kThreads) k_tile_count(const InstDesc* __restr
     const int c = act ? cell_key(px[i], py[i], g, tp) : 0;
     int r;
     const int base = wave_group_add<true>(d.tb.ccount, c, act, r);
-    if (act) d.tb.rank[i] = base + r;
+    if (act) rank[i] = base + r;
   }
 }
 
@@ -316,27 +318,28 @@ __global__ void __launch_bounds__(kThreads) k_tile_scatter(const InstDesc* __res
   void* const* Dd = d.set[src ^ 1];
   T rec[11];
 #pragma unroll
-  for (int a = 0; a < 11; ++a) rec[a] = ((const T*)S[a])[i];
-  const int32_t id = d.ids[src][i], slot = d.tb.rank[i];
+  for (int a = 0; a < 11; ++a) rec[a] = gp((const T*)S[a])[i];
+  const int32_t id = gp(d.ids[src])[i], slot = gp(d.tb.rank)[i];
   const int c = cell_key(rec[0], rec[1], d.g, tp);  // the count pass's key of the same positions
   const int tt = c >> (2 * tp.log_ts);
-  const int32_t t0 = d.tb.start[tt];
-  const int rel = d.tb.ccursor[c] + slot;  // slot in the tile
+  const gptr<const int32_t> start = gp((const int32_t*)d.tb.start);
+  const int32_t t0 = start[tt];
+  const int rel = gp((const int32_t*)d.tb.ccursor)[c] + slot;  // slot in the tile
   const int64_t o = (int64_t)t0 + rel;
 #pragma unroll
-  for (int a = 0; a < 11; ++a) ((T*)Dd[a])[o] = rec[a];
-  d.ids[src ^ 1][o] = id;
+  for (int a = 0; a < 11; ++a) gp((T*)Dd[a])[o] = rec[a];
+  gp(d.ids[src ^ 1])[o] = id;
   // a chunk's first and last particles record its span of cell rows (slots
   // are in cell order, cells row-major in the tile) for the tiled pass's
   // field-window rows; the cell scan wrote the field as zero
   const int j = rel / tp.chunk, in_chunk = rel - j * tp.chunk;
   const bool first = in_chunk == 0;
-  const bool last = in_chunk == tp.chunk - 1 || rel == d.tb.start[tt + 1] - t0 - 1;
+  const bool last = in_chunk == tp.chunk - 1 || rel == start[tt + 1] - t0 - 1;
   if (first || last) {
     const int row = (c & ((1 << (2 * tp.log_ts)) - 1)) >> tp.log_ts;
-    int* rows = reinterpret_cast<int*>(d.tb.work + d.tb.cstart[tt] + j) + 3;
-    if (first) atomicOr(rows, row);
-    if (last) atomicOr(rows, row << 16);
+    const gptr<int> rows = gp(reinterpret_cast<int*>(d.tb.work + d.tb.cstart[tt] + j) + 3);
+    if (first) __hip_atomic_fetch_or(rows, row, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (last) __hip_atomic_fetch_or(rows, row << 16, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -377,17 +380,19 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   const int ii = find_inst(D, ninst, BK_WORK, blockIdx.x);
   const InstDesc& d = D[ii];
   const int item = blockIdx.x - d.blk[BK_WORK];
-  if (item >= *d.tb.nwork) return;
-  const int4 it = d.tb.work[item];
+  if (item >= *gp(d.tb.nwork)) return;
+  const int4 it = gp(d.tb.work)[item];
   const GridP g = d.g;
   const PhysP ph = d.ph;
   const TileP tp = d.tp;
-  const Parts<T> p = make_parts<T>(d, sa.cur, sa.vflip);
+  const GParts<T> p = global_parts(make_parts<T>(d, sa.cur, sa.vflip));
   const T* __restrict__ F = GATHER ? (d.F32 ? (const T*)(const void*)d.F32 : (const T*)(const void*)d.F64) : nullptr;
+  const gptr<const T> Fg = gp(F);
   // sub-stepped DIRK stage (deposit-only passes): deposit at x + c_i dt v into
   // J planes 3i..3i+2; only the last stage writes x^{n+1}
   const bool staged = !GATHER && sa.stage >= 0;
   double* __restrict__ J = d.J + (staged ? (size_t)3 * sa.stage * d.g.nx * d.g.ny : 0);
+  const gptr<double> Jg = gp(J);
   const int W = FIXED ? G::W : tp.win;
   const int WP = FIXED ? G::WP : tp.win_pad;  // plane stride of the LDS windows (field f at f*WP)
   // plane stride of the float64 J window: WP + 8 puts the three components of
@@ -451,7 +456,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       // three 16-byte vectors
       auto copy_row = [&](int j) {
         const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
-        const float4* src = reinterpret_cast<const float4*>(F + go * kFieldSlots);
+        const gptr<const float4> src = reinterpret_cast<gptr<const float4>>(Fg + go * kFieldSlots);
         float4* dst = reinterpret_cast<float4*>(fw + (j * W + wi) * kNodeSlots);
         const float4 a0 = src[0], a1 = src[1], a2 = src[2];
         dst[0] = a0;
@@ -480,7 +485,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         if (j >= jlo && j < jhi) {
           const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
 #pragma unroll
-          for (int f = 0; f < 11; ++f) v[r][f] = F[f * plane + go];
+          for (int f = 0; f < 11; ++f) v[r][f] = Fg[f * plane + go];
         }
       }
 #pragma unroll
@@ -497,7 +502,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
         const int node = j * W + wi;
 #pragma unroll
-        for (int f = 0; f < 11; ++f) fw[node * kNodeSlots + f] = F[f * plane + go];
+        for (int f = 0; f < 11; ++f) fw[node * kNodeSlots + f] = Fg[f * plane + go];
       }
     }
   }
@@ -720,28 +725,28 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
           const int32_t Y = (int32_t)((int64_t)(v - (uint64_t)(int64_t)X) >> 32);
           const int32_t Z = (int32_t)jz_w[node];
           if (det) {  // int64 J planes at the same fixed scale: exact, order-free sums
-            unsigned long long* Jq = reinterpret_cast<unsigned long long*>(J);
-            if (X) atomicAdd(Jq + go, (unsigned long long)(long long)X);
-            if (Y) atomicAdd(Jq + plane + go, (unsigned long long)(long long)Y);
-            if (Z) atomicAdd(Jq + 2 * plane + go, (unsigned long long)(long long)Z);
+            const gptr<unsigned long long> Jq = gp(reinterpret_cast<unsigned long long*>(J));
+            if (X) gadd(Jq + go, (unsigned long long)(long long)X);
+            if (Y) gadd(Jq + plane + go, (unsigned long long)(long long)Y);
+            if (Z) gadd(Jq + 2 * plane + go, (unsigned long long)(long long)Z);
           } else {
-            if (X) atomicAdd(J + go, X * inv_qscale);
-            if (Y) atomicAdd(J + plane + go, Y * inv_qscale);
-            if (Z) atomicAdd(J + 2 * plane + go, Z * inv_qscale);
+            if (X) gadd(Jg + go, X * inv_qscale);
+            if (Y) gadd(Jg + plane + go, Y * inv_qscale);
+            if (Z) gadd(Jg + 2 * plane + go, Z * inv_qscale);
           }
         } else if (det) {
           const unsigned long long* jq = reinterpret_cast<const unsigned long long*>(jw);
-          unsigned long long* Jq = reinterpret_cast<unsigned long long*>(J);
+          const gptr<unsigned long long> Jq = gp(reinterpret_cast<unsigned long long*>(J));
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const unsigned long long v = jq[c * JWP + node];
-            if (v) atomicAdd(Jq + c * plane + go, v);
+            if (v) gadd(Jq + c * plane + go, v);
           }
         } else {
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const A v = jw[c * JWP + node];
-            if (v != A(0)) atomicAdd(J + c * plane + go, (double)v);
+            if (v != A(0)) gadd(Jg + c * plane + go, (double)v);
           }
         }
       }
