@@ -203,6 +203,68 @@ def test_bdf_dispersion(k):
     np.testing.assert_allclose(out["A"][0][2][MODE[1], MODE[0]], 0.5 * z ** n, rtol=1e-11)
 
 
+def _bdf_golden(k):
+    return [float(Fraction(v)) for v in GOLD["bdf_first_derivative_over_dt"][str(k)]]
+
+
+def _bdf_roots(k, th):
+    """Source free, u^n = z^n solves the BDF-k wave update when the BDF-k
+    first-derivative polynomial A(w) = sum_j a_j w^j at w = 1/z equals
+    +-i theta, since the second difference is the first applied twice
+    (C = a * a, Table 1): A(w)^2 + theta^2 = 0.  The 2k roots z = 1/w from
+    numpy.roots of the degree-k polynomials A(w) -+ i theta, with the
+    textbook a_j (golden table)."""
+    a = _bdf_golden(k)
+    zs = []
+    for s in (1, -1):
+        c = list(reversed(a))
+        c[-1] = a[0] - s * 1j * th
+        zs += [1.0 / w for w in np.roots(c)]
+    return zs
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("dt", [0.02, 0.05])
+def test_bdf_k_dispersion_roots(k, dt):
+    """Every BDF order against its characteristic roots: the history seeded
+    with the dominant eigen-solution z^{-j} comes back as z^n after 100 steps
+    (the dominant root, so that round-off in the other eigen-directions cannot
+    grow faster than it)."""
+    p = _params("bdf", k, dt=dt)
+    th = _theta(p)
+    z = max(_bdf_roots(k, th), key=abs)
+    hist = pic.cold_history(p)
+    hist["phi"] = [_mode_field(p, z ** (-j)) for j in range(2 * k)]
+    hist["A"] = [np.stack([_mode_field(p, (0.5 - 0.25j) * z ** (-j))] * 3) for j in range(2 * k)]
+    n = 100
+    out = _run(p, hist, n)
+    np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** n, rtol=1e-10)
+    np.testing.assert_allclose(out["A"][0][1][MODE[1], MODE[0]], (0.5 - 0.25j) * z ** n, rtol=1e-10)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_bdf_k_stability_on_the_imaginary_axis(k):
+    """The remark of Sec. 3.2 that BDF-k beyond k = 2 is only A(alpha)-stable:
+    on the wave equation's imaginary eigenvalues, BDF-1 and BDF-2 keep every
+    root inside the unit circle, while BDF-3..6 have a range of theta where a
+    root leaves it -- and the oracle's update grows by exactly that root."""
+    ths = np.linspace(0.05, 6.0, 120)
+    worst = max((max(abs(z) for z in _bdf_roots(k, th)), th) for th in ths)
+    if k <= 2:
+        assert worst[0] <= 1.0
+        return
+    assert worst[0] > 1.01
+    # the oracle at that theta: dt chosen so that c |k| dt = theta for MODE
+    p0 = _params("bdf", k)
+    p = _params("bdf", k, dt=worst[1] / (_theta(p0) / p0.dt))
+    z = max(_bdf_roots(k, _theta(p)), key=abs)
+    assert abs(z) > 1.01
+    hist = pic.cold_history(p)
+    hist["phi"] = [_mode_field(p, z ** (-j)) for j in range(2 * k)]
+    out = _run(p, hist, 40)
+    np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** 40, rtol=1e-10)
+
+
 def test_cdf2_dispersion():
     p = _params("cdf2")
     th = _theta(p)

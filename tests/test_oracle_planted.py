@@ -8,8 +8,9 @@ that should catch it.
 import numpy as np
 import pytest
 
-from oracle import bspline, pic, schemes
+from oracle import adjoint, bspline, pic, schemes, spectral
 import test_oracle_dirk_substep as D
+import test_oracle_energy as E
 import test_oracle_fields as F
 import test_oracle_invariants as I
 import test_oracle_spline_deposit as S
@@ -102,3 +103,59 @@ def test_linear_stage_rho_with_substepped_currents_breaks_gauge(monkeypatch):
     monkeypatch.setattr(pic, "_stage_rho", linear)
     with pytest.raises(AssertionError):
         D.test_gauge_and_gauss_at_round_off("dirk2")
+
+
+def test_wrong_bdf4_coefficient_fails_dispersion(monkeypatch):
+    """A sign slip in one term of the backward-difference series (BDF-4's
+    a_3) moves the characteristic roots."""
+    orig = schemes.bdf_a
+
+    def patched(k):
+        a = orig(k)
+        if k == 4:
+            a = a.copy()
+            a[3] = -a[3]
+        return a
+    monkeypatch.setattr(schemes, "bdf_a", patched)
+    with pytest.raises(AssertionError):
+        F.test_bdf_k_dispersion_roots(4, 0.02)
+
+
+def test_flipped_time_derivative_in_E_fails_energy(monkeypatch):
+    """E = -grad phi + dA/dt (the sign of the time-derivative term flipped)."""
+    orig = schemes.bdf_a
+    monkeypatch.setattr(schemes, "bdf_a", lambda k: -orig(k))
+    with pytest.raises(AssertionError):
+        E.test_bdf_energy_closed_form(2)
+
+
+def test_transposed_derivatives_fail_energy(monkeypatch):
+    """d/dx and d/dy symbols exchanged (a transposed operand in grad and curl)."""
+    orig = spectral.symbols
+
+    def swapped(nx, ny, lx, ly):
+        ikx, iky, lap = orig(nx, ny, lx, ly)
+        return iky, ikx, lap
+    monkeypatch.setattr(spectral, "symbols", swapped)
+    with pytest.raises(AssertionError):
+        E.test_cdf2_energy_closed_form("cdf2")
+
+
+def test_curl_index_slip_fails_energy(monkeypatch):
+    """B_z = d_x A_y + d_y A_x (the sign of curl's second term lost) in the
+    adjoint workload's loss."""
+    import torch
+
+    def patched(pr, hist):
+        p = pr.p
+        a = pr.a
+        phi = hist["phi"][0]
+        A0 = hist["A"][0]
+        dA = sum(a[j] * hist["A"][j] for j in range(p.bdf_order + 1)) / p.dt
+        Eh = [-pr.ikx * phi - dA[0], -pr.iky * phi - dA[1], -dA[2]]
+        Bh = [pr.iky * A0[2], -pr.ikx * A0[2], pr.ikx * A0[1] + pr.iky * A0[0]]
+        r = lambda f: torch.fft.irfft2(f, s=(p.ny, p.nx))  # noqa: E731
+        return 0.5 * p.dx * p.dy * (p.eps0 * sum(r(e) ** 2 for e in Eh) + sum(r(b) ** 2 for b in Bh) / p.mu0).sum()
+    monkeypatch.setattr(adjoint, "energy", patched)
+    with pytest.raises(AssertionError):
+        E.test_autograd_energy_closed_form(2)
