@@ -49,12 +49,12 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
   // the naive mode's rho plane restarts from the ion background
   const gptr<const double> reset = gp((const double*)((!adj && c == 3) ? d.RB : nullptr));
   const bool det = !adj && d.det;
-  const gptr<double2> T = gp(adj ? d.LS : d.T);
+  const GC2 T = gc2(adj ? d.LS : d.T);
   const int N = g.nx, B = R >> 1;
   double2* a = sm;
   double2* b = sm + B * N;
   double2* tws = sm + R * N;  // twiddles staged in LDS
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = gp(d.twx)[t];
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = gc2(d.twx)[t];
   for (int t = threadIdx.x; t < B * N; t += blockDim.x) {
     const int r = t / N, x = t - r * N;
     const size_t i0 = (size_t)(y0 + 2 * r) * N + x, i1 = i0 + N;
@@ -116,16 +116,16 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
   const int lb = blockIdx.x - d.blk[BK_COL];
   const int kx = lb / kColParts, part = lb - kx * kColParts;
   const int N = g.ny, tid = threadIdx.x, nth = blockDim.x;
-  const gptr<const double2> T = gp((const double2*)d.T);
-  const gptr<double2> H = gp(d.H);
-  const gptr<double2> U = gp(d.U);
+  const GC2 T = gc2(d.T);
+  const GC2 H = gc2(d.H);
+  const GC2 U = gc2(d.U);
   const size_t plane = (size_t)g.nxh * N;
   double2* store = sm;
   double2* wk = sm + N;
   const double2* tws = d.twy;
   if (N <= 512) {
     double2* t_lds = sm + 5 * N;
-    for (int i = tid; i < N; i += nth) t_lds[i] = gp(d.twy)[i];
+    for (int i = tid; i < N; i += nth) t_lds[i] = gc2(d.twy)[i];
     tws = t_lds;
   }
   double2* stg = sm + (N <= 512 ? 6 : 5) * N;
@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
   const int lb = blockIdx.x - d.blk[BK_C2R];
   const int pr = lb / ngr, y0 = (lb - pr * ngr) * R;
   const int nr = min(R, g.ny - y0);  // rows of this group (the last may be partial)
-  const gptr<const double2> U = gp((const double2*)(adj ? d.LS : d.U));
+  const GC2 U = gc2(adj ? d.LS : d.U);
   const gptr<double> F64 = gp(adj ? d.LJ : d.F64);
   const gptr<float> F32 = gp(adj ? nullptr : d.F32);
   const int N = g.nx;
@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
   double2* a = sm;
   double2* b = sm + R * N;
   double2* tws = sm + 2 * R * N;  // twiddles staged in LDS
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = gp(d.twx)[t];
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = gc2(d.twx)[t];
   const int s0 = 2 * pr, s1 = s0 + 1;
   const int g0 = adj ? s0 : kSrcG[s0], g1 = adj ? s1 : kSrcG[s1];
   const bool has1 = !adj || s1 < 3;
@@ -439,8 +439,10 @@ __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D
       F64[s0 * plane + o] = z.x;
       if (has1) F64[s1 * plane + o] = z.y;
     }
-    if (F32)  // node-major record: slots s0, s0 + 1 of node o
-      *reinterpret_cast<gptr<float2>>(F32 + o * kFieldSlots + s0) = make_float2((float)z.x, (float)z.y);
+    if (F32) {  // node-major record: slots s0, s0 + 1 of node o
+      F32[o * kFieldSlots + s0] = (float)z.x;
+      F32[o * kFieldSlots + s0 + 1] = (float)z.y;
+    }
   }
 }
 

@@ -106,13 +106,13 @@ struct Spline {
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// x in (-L, 2L) -> [0, L); a value that rounds to L is set to 0
+// x in (-L, 2L) -> [0, L); a value that rounds to L is set to 0 (selects,
+// not branches: a wave's lanes take different arms)
 template <typename T>
 __device__ __forceinline__ T wrapx(T x, T L) {
-  if (x < T(0)) x += L;
-  else if (x >= L) x -= L;
-  if (x >= L) x = T(0);
-  return x;
+  x = x < T(0) ? x + L : x;
+  x = x >= L ? x - L : x;
+  return x >= L ? T(0) : x;
 }
 
 // node coordinates xi = x/dx, eta = y/dy inside [0, n] (NaN fails the test);
@@ -186,6 +186,11 @@ __device__ __forceinline__ T field_at(const gptr<const T> F, int f, size_t node,
     return F[f * plane + node];
 }
 
+// The summation order is that of the tiled passes' LDS-window gather (node
+// weight wx[a] wy[b], rows outer, columns inner, one multiply-add per field),
+// so a particle gathers the same bits from either path: which path it takes
+// depends on how far it drifted since the last sort, and the deterministic
+// mode's results must not.
 template <typename T, int DEG>
 __device__ __forceinline__ void gather_global(int sx, int sy, const T* wx, const T* wy, const T* __restrict__ F,
                                               const GridP& g, T* out) {
@@ -195,17 +200,13 @@ __device__ __forceinline__ void gather_global(int sx, int sy, const T* wx, const
 #pragma unroll
   for (int b = 0; b < S::NW; ++b) {
     const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
-    T acc[11];
-#pragma unroll
-    for (int f = 0; f < 11; ++f) acc[f] = T(0);
 #pragma unroll
     for (int a = 0; a < S::NW; ++a) {
       const size_t o = row + wrapi(sx + a, g.nx);
+      const T w = wx[a] * wy[b];
 #pragma unroll
-      for (int f = 0; f < 11; ++f) acc[f] += wx[a] * field_at<T>(Fg, f, o, plane);
+      for (int f = 0; f < 11; ++f) out[f] += w * field_at<T>(Fg, f, o, plane);
     }
-#pragma unroll
-    for (int f = 0; f < 11; ++f) out[f] += wy[b] * acc[f];
   }
 }
 
@@ -223,20 +224,33 @@ __device__ __forceinline__ void gather_one(T x, T y, const T* __restrict__ F, co
   gather_global<T, DEG>(sx, sy, wx, wy, F, g, out);
 }
 
+// a * b + c, one rounding
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // IAEM: v* = 2 v^n - v^{n-1}; P += q dt (-grad phi + (grad A).v*) (x, y only:
 // d/dz = 0); v = c^2 u / sqrt(c^2 |u|^2 + (m c^2)^2), u = P - q A.
+// A sum of two products can be contracted into a multiply-add either way;
+// those sums are written with explicit multiply-adds so that every copy of
+// this code the compiler makes rounds the same way (the deterministic mode
+// relies on it).
 template <typename T>
 __device__ __forceinline__ void push_one(const T* gv, T& Px, T& Py, T Pz, T vx, T vy, T vz, T wx, T wy,
                                          T wz, const PhysP& ph, T& nx, T& ny, T& nz) {
   const T q = T(ph.q), dt = T(ph.dt), c = T(ph.c), m = T(ph.m);
   const T sx = T(2) * vx - wx, sy = T(2) * vy - wy, sz = T(2) * vz - wz;
-  const T Fx = -gv[0] + sx * gv[5] + sy * gv[6] + sz * gv[7];
-  const T Fy = -gv[1] + sx * gv[8] + sy * gv[9] + sz * gv[10];
-  Px += q * Fx * dt;
-  Py += q * Fy * dt;
-  const T ux = Px - q * gv[2], uy = Py - q * gv[3], uz = Pz - q * gv[4];
+  const T Fx = fmat(sz, gv[7], fmat(sy, gv[6], fmat(sx, gv[5], -gv[0])));
+  const T Fy = fmat(sz, gv[10], fmat(sy, gv[9], fmat(sx, gv[8], -gv[1])));
+  Px = fmat(q * Fx, dt, Px);
+  Py = fmat(q * Fy, dt, Py);
+  const T ux = fmat(-q, gv[2], Px), uy = fmat(-q, gv[3], Py), uz = fmat(-q, gv[4], Pz);
   const T c2 = c * c, mc2 = m * c2;
-  const T inv = c2 / sqrt(c2 * (ux * ux + uy * uy + uz * uz) + mc2 * mc2);
+  const T s2 = fmat(c2, fmat(uz, uz, fmat(uy, uy, ux * ux)), mc2 * mc2);
+  T inv;
+  if constexpr (sizeof(T) == 4)
+    inv = c2 * __builtin_amdgcn_rsqf(s2);  // hardware reciprocal square root, about 1 ulp
+  else
+    inv = c2 / sqrt(s2);
   nx = ux * inv;
   ny = uy * inv;
   nz = uz * inv;

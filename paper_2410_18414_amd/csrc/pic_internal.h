@@ -57,6 +57,30 @@ __device__ __forceinline__ void gadd(gptr<T> p, T v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A complex128 array in global memory.  Elements are read and written through
+// their two float64 parts (HIP's vector classes cannot be loaded or stored
+// through address-space pointers); the compiler merges each pair into one
+// 16-byte access.
+struct GC2Ref {
+  gptr<double> p;
+  __device__ __forceinline__ operator double2() const { return make_double2(p[0], p[1]); }
+  __device__ __forceinline__ const GC2Ref& operator=(const double2& v) const {
+    p[0] = v.x;
+    p[1] = v.y;
+    return *this;
+  }
+};
+struct GC2 {
+  gptr<double> p;
+  __device__ __forceinline__ GC2Ref operator[](size_t i) const { return GC2Ref{p + 2 * i}; }
+};
+__device__ __forceinline__ GC2 gc2(const double2* a) {
+  return GC2{gp(const_cast<double*>(reinterpret_cast<const double*>(a)))};
+}
+// 16 bytes of global memory as four floats or ints (a compiler vector type)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
 // Particle SoA pointers in the global address space (device code)
 template <typename T>
 struct GParts {
@@ -67,6 +91,14 @@ struct GParts {
   gptr<T> w[3];
   gptr<int32_t> id;
 };
+
+// element k of a global array whose base b is wave-uniform: the byte offset
+// stays 32-bit, so the access is one global instruction with the base in
+// scalar registers and the offset in a vector register
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T& elt(gptr<T> b, uint32_t k) {
+  return *(gptr<T>)((__attribute__((address_space(1))) char*)b + k * (uint32_t)sizeof(T));
+}
 
 template <typename T>
 __device__ __forceinline__ GParts<T> global_parts(const Parts<T>& p) {
@@ -79,6 +111,21 @@ __device__ __forceinline__ GParts<T> global_parts(const Parts<T>& p) {
     g.w[c] = gp(p.w[c]);
   }
   g.id = gp(p.id);
+  return g;
+}
+
+// the same arrays from particle `first` on (first is the same for the whole
+// workgroup, so the new bases stay in scalar registers)
+template <typename T>
+__device__ __forceinline__ GParts<T> parts_from(GParts<T> g, int64_t first) {
+  g.x += first;
+  g.y += first;
+  for (int c = 0; c < 3; ++c) {
+    g.P[c] += first;
+    g.v[c] += first;
+    g.w[c] += first;
+  }
+  g.id += first;
   return g;
 }
 

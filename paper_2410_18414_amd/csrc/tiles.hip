@@ -381,11 +381,13 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   const InstDesc& d = D[ii];
   const int item = blockIdx.x - d.blk[BK_WORK];
   if (item >= *gp(d.tb.nwork)) return;
-  const int4 it = gp(d.tb.work)[item];
+  const i32x4 itv = *reinterpret_cast<gptr<const i32x4>>(gp(d.tb.work + item));
+  const int4 it = make_int4(itv.x, itv.y, itv.z, itv.w);
   const GridP g = d.g;
   const PhysP ph = d.ph;
   const TileP tp = d.tp;
-  const GParts<T> p = global_parts(make_parts<T>(d, sa.cur, sa.vflip));
+  // the chunk's particles from its first one on: lane offsets stay 32-bit
+  const GParts<T> p = parts_from(global_parts(make_parts<T>(d, sa.cur, sa.vflip)), it.y);
   const T* __restrict__ F = GATHER ? (d.F32 ? (const T*)(const void*)d.F32 : (const T*)(const void*)d.F64) : nullptr;
   const gptr<const T> Fg = gp(F);
   // sub-stepped DIRK stage (deposit-only passes): deposit at x + c_i dt v into
@@ -428,23 +430,23 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   // J carries v* = 2 v - v_prev: the deposit needs the older velocity too
   const bool jv = d.jvstar != 0;
   const bool det = d.det != 0;  // deterministic deposit: int64 J at the instance's fixed scale
-  auto load = [&](int64_t i) {
-    cx = p.x[i];
-    cy = p.y[i];
-    cvx = p.v[0][i];
-    cvy = p.v[1][i];
-    cvz = p.v[2][i];
+  auto load = [&](uint32_t k) {
+    cx = elt(p.x, k);
+    cy = elt(p.y, k);
+    cvx = elt(p.v[0], k);
+    cvy = elt(p.v[1], k);
+    cvz = elt(p.v[2], k);
     if (GATHER) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cP[c] = p.P[c][i];
+      for (int c = 0; c < 3; ++c) cP[c] = elt(p.P[c], k);
     }
     if (GATHER || jv) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cw[c] = p.w[c][i];
+      for (int c = 0; c < 3; ++c) cw[c] = elt(p.w[c], k);
     }
   };
   // the first particle's inputs are in flight while the window loads
-  if ((int)threadIdx.x < it.z) load(it.y + threadIdx.x);
+  if ((int)threadIdx.x < it.z) load(threadIdx.x);
   // window sweeps without integer division: lanes of a row-group cover x
   // (row_lanes >= W, a power of two), row-groups cover y
   const int rl = FIXED ? G::RL : tp.row_lanes, lrl = FIXED ? G::LRL : tp.log_row_lanes;
@@ -456,9 +458,9 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       // three 16-byte vectors
       auto copy_row = [&](int j) {
         const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
-        const gptr<const float4> src = reinterpret_cast<gptr<const float4>>(Fg + go * kFieldSlots);
-        float4* dst = reinterpret_cast<float4*>(fw + (j * W + wi) * kNodeSlots);
-        const float4 a0 = src[0], a1 = src[1], a2 = src[2];
+        const gptr<const f32x4> src = reinterpret_cast<gptr<const f32x4>>(Fg + go * kFieldSlots);
+        f32x4* dst = reinterpret_cast<f32x4*>(fw + (j * W + wi) * kNodeSlots);
+        const f32x4 a0 = src[0], a1 = src[1], a2 = src[2];
         dst[0] = a0;
         dst[1] = a1;
         dst[2] = a2;
@@ -539,10 +541,9 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   for (int k0 = 0; k0 < it.z; k0 += blockDim.x) {
     const int k = k0 + threadIdx.x;
     const bool act = k < it.z;
-    const int64_t i = it.y + k;
     T x = cx, y = cy, vx = cvx, vy = cvy, vz = cvz;
     T Px = cP[0], Py = cP[1], Pz = cP[2], w0 = cw[0], w1 = cw[1], w2 = cw[2];
-    if (k + (int)blockDim.x < it.z) load(i + blockDim.x);  // next particle, in flight meanwhile
+    if (k + (int)blockDim.x < it.z) load(k + blockDim.x);  // next particle, in flight meanwhile
     if (GATHER && act) {
       T gv[11];
 #pragma unroll
@@ -573,11 +574,11 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       }
       T nvx, nvy, nvz;
       push_one<T>(gv, Px, Py, Pz, vx, vy, vz, w0, w1, w2, ph, nvx, nvy, nvz);
-      p.P[0][i] = Px;
-      p.P[1][i] = Py;
-      p.w[0][i] = nvx;
-      p.w[1][i] = nvy;
-      p.w[2][i] = nvz;
+      elt(p.P[0], k) = Px;
+      elt(p.P[1], k) = Py;
+      elt(p.w[0], k) = nvx;
+      elt(p.w[1], k) = nvy;
+      elt(p.w[2], k) = nvz;
       w0 = vx;
       w1 = vy;
       w2 = vz;
@@ -595,8 +596,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       if (act) {
         if (staged) {
           if (sa.stage == d.sc.stages - 1) {
-            p.x[i] = wrapx<T>(x + vx * dt, T(g.lx));
-            p.y[i] = wrapx<T>(y + vy * dt, T(g.ly));
+            elt(p.x, k) = wrapx<T>(x + vx * dt, T(g.lx));
+            elt(p.y, k) = wrapx<T>(y + vy * dt, T(g.ly));
           }
           const T sdt = T(ph.dt * d.sc.dirkC[sa.stage]);
           x = wrapx<T>(x + vx * sdt, T(g.lx));
@@ -604,8 +605,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         } else {
           x = wrapx<T>(x + vx * dt, T(g.lx));
           y = wrapx<T>(y + vy * dt, T(g.ly));
-          p.x[i] = x;
-          p.y[i] = y;
+          elt(p.x, k) = x;
+          elt(p.y, k) = y;
         }
         const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
         if (in_box(xi, eta, g)) {
@@ -634,10 +635,14 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         }
       }
       if constexpr (ROTATE) {
-        // per-lane rotation of stencil columns and rows: lanes of one cell
-        // (neighbours in the cell-sorted order) add to different window
-        // addresses at each instruction
-        const int ra = lane % NW, rb = (lane / NW) % NW;
+        // per-lane rotation of stencil columns and rows: at step (a, b) lane l
+        // adds to the stencil node whose absolute indices are congruent to
+        // (a + l, b + l / NW) modulo NW (a stencil holds one node of every
+        // residue pair), so two lanes can meet on one window address only when
+        // their lane indices agree modulo NW^2 -- at most 64 / NW^2 lanes per
+        // address, whatever cells the wave's particles are in (a rotation by
+        // lane index alone lets lanes of neighbouring cells collide)
+        const int ra = ((lane - sx) % NW + NW) % NW, rb = ((lane / NW - sy) % NW + NW) % NW;
         T wxr[NW], wyr[NW];
         int roff[NW], cxy[NW], cz[NW];  // rotated row offsets (nodes), column offsets (bytes)
 #pragma unroll

@@ -2,8 +2,12 @@
 context from the same seeded workload, convert state between them, and
 measure normwise relative errors.
 
-Inputs flow one way only: workload -> both sides, or oracle -> GPU.  No value
-read back from the GPU is ever fed to the oracle.
+Inputs come from the seeded workloads, which both sides receive.  The one
+exception is shadow stepping (the parity protocol for long float32 runs, whose
+chaotic growth amplifies rounding differences beyond the tolerance): there
+the oracle is loaded with the GPU's state, promoted to float64
+(`oracle_from_gpu`, `shadow_step`), and one step of each is compared.  No
+expected value is ever taken from the GPU.
 """
 
 import numpy as np
@@ -85,6 +89,29 @@ def flat_to_hist_bdf(p, flat):
     return dict(rho=rho, phi=phi, A=A)
 
 
+def flat_to_hist(p, flat):
+    """[nfield, ny, nx/2+1] in pic.h's export order -> oracle history dict
+    (every stepper: the inverse of hist_to_flat)."""
+    flat = np.asarray(flat, np.complex128)
+    if p.scheme == "bdf":
+        return flat_to_hist_bdf(p, flat)
+    it = iter(range(flat.shape[0]))
+
+    def take(count):
+        return [flat[next(it)] for _ in range(count)]
+
+    def take3(levels):
+        return [np.stack(take(3)) for _ in range(levels)]
+    if p.scheme in ("cdf2", "cdf2_semi", "cdf2_explicit"):
+        return dict(rho=take(3), phi=take(3), A=take3(2), J=take3(2))
+    h = dict(rho=take(2), phi=take(2))
+    h["vphi"] = take(1)[0]
+    h["A"] = take3(2)
+    h["vA"] = take3(1)[0]
+    h["J"] = take3(1)[0]
+    return h
+
+
 def oracle_from_gpu(p, ctx, w):
     """An oracle State holding the GPU context's particles and BDF-k history
     (promoted to float64)."""
@@ -116,3 +143,54 @@ def compare_particles(gp, op, lx, ly, tol):
                 P=rel(gp["P"], op["P"]), v=rel(gp["v"], op["v"]), vprev=rel(gp["vprev"], op["vprev"]))
     bad = {k: v for k, v in errs.items() if not v <= tol}
     return errs, bad
+
+
+def _workers():
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def chunked_deposit(p, x, y, v, chunks=64):
+    """oracle deposit_current over the whole particle set, summed over
+    particle chunks deposited on host threads (each chunk is the oracle's own
+    float64 deposit; only the order of the final summation differs from one
+    pass over all particles)."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = x.shape[0]
+    bounds = [(i * n // chunks, (i + 1) * n // chunks) for i in range(chunks)]
+    with ThreadPoolExecutor(_workers()) as ex:
+        parts = list(ex.map(lambda b: opic.deposit_current(p, x[b[0]:b[1]], y[b[0]:b[1]], v[b[0]:b[1]]), bounds))
+    J = parts[0]
+    for q in parts[1:]:
+        J = J + q
+    return J
+
+
+def chunked_gather(p, fields, x, y, chunks=32):
+    """oracle gather of the mesh fields at the given particles, by chunks on
+    host threads (each particle's interpolation is the oracle's own)."""
+    from concurrent.futures import ThreadPoolExecutor
+    n = x.shape[0]
+    bounds = [(i * n // chunks, (i + 1) * n // chunks) for i in range(chunks)]
+    with ThreadPoolExecutor(_workers()) as ex:
+        parts = list(ex.map(lambda b: opic.gather(p, fields, x[b[0]:b[1]], y[b[0]:b[1]]), bounds))
+    return np.concatenate(parts)
+
+
+def shadow_step(p, x, y, v, hist, sample, P_s, vprev_s):
+    """One oracle step (Algorithm 1) from a particle state and history: the
+    position update and J deposit over every particle (positions x, y and
+    velocities v of all of them), the field update and spectral gradients,
+    then the gather and IAEM push of the particles in `sample` only, whose
+    momenta P_s and older velocities vprev_s are given (the other particles'
+    pushes do not affect any output of this step).  Returns (history after
+    the step, particle dict of the sample after the step)."""
+    from oracle import spectral
+    x1, y1 = opic.position_update(p, x, y, v)
+    J = chunked_deposit(p, x1, y1, v)
+    Jh = np.stack([spectral.fft2(J[c]) for c in range(3)])
+    hist1, phi_t, A = opic.field_update(p, hist, Jh)
+    fields = opic.gradient_fields(p, phi_t, A)
+    g = chunked_gather(p, fields, x1[sample], y1[sample])
+    Pn, vn = opic.push(p, P_s, v[sample], vprev_s, g)
+    return hist1, dict(x=x1[sample], y=y1[sample], P=Pn, v=vn, vprev=v[sample])

@@ -71,6 +71,41 @@ def test_independent_of_tiles_fusion_and_sort_interval(gpu_lib, dtype):
             assert same(st, ref), kw
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fast_particles_leaving_their_windows(gpu_lib, dtype):
+    """In-plane speeds near c (proper velocity spread 0.9c, isotropic) move a
+    particle a third of a cell per step, so between sorts 40 steps apart most
+    particles outrun the 3-cell slack and gather and deposit through the
+    global-memory paths; the window and global paths sum in the same order and
+    round at the same scale, so the state is still identical bit for bit to
+    runs that re-sort every step or use other tiles, and a run resumed at
+    another point of the sort cycle equals the uninterrupted one."""
+    w = workloads.weibel(nx=32, ny=32, ppc=4, seed=135, vth=0.9, aniso=1.0)
+    n = w["x"].shape[0]
+
+    def run(steps, start=None, **kw):
+        cfg = pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=3, scheme="bdf", bdf_order=2,
+                              dtype=dtype, q=w["q"], m=w["m"], max_particles=n, flags=DET, **kw)
+        g = pic.Context(cfg)
+        pic.init_particles(g, torch.as_tensor(w["x"], device=g.device), torch.as_tensor(w["y"], device=g.device),
+                           torch.as_tensor(np.ascontiguousarray(w["P"].T), device=g.device))
+        if start is not None:
+            pic.set_particles(g, start[0].to(g.device))
+            pic.set_history(g, start[1].to(g.device))
+        pic.step(g, steps)
+        st = state(g)
+        g.close()
+        return st
+
+    ref = run(50, sort_interval=40)
+    v = ref[0][5:7].abs().max()
+    assert float(v) > 0.5  # in-plane speeds above c/2
+    for kw in (dict(sort_interval=1), dict(tile_cells=8, sort_interval=40), dict(sort_interval=7)):
+        assert same(run(50, **kw), ref), kw
+    mid = run(23, sort_interval=40)
+    assert same(run(27, start=mid, sort_interval=40), ref)
+
+
 def test_matches_oracle_and_atomic_mode(gpu_lib):
     w = plasma(seed=133)
     for dtype in ("f64", "f32"):

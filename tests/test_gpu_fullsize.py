@@ -1,12 +1,14 @@
 """Full-size checks at the workload sizes the benchmark runs.
 
 The 512 x 512, 256 particles/cell case (67,108,864 float32 particles, cubic,
-DIRK-2 and CDF-2) is too large for a full oracle step, so the oracle computes
-outputs one by one from the original inputs: J at sampled nodes (the
-definition summed over all particles) and the first update's spectral history
-at sampled modes (the direct Fourier sum of the deposit, then the per-mode
-stepper update).  After a few more steps, invariants that hold at any size:
-gauge residual at round-off, zero net charge, finite state.
+DIRK-2 and CDF-2): from the original inputs, the oracle computes outputs one
+by one -- J at sampled nodes (the definition summed over all particles) and
+the first update's spectral history at sampled modes (the direct Fourier sum
+of the deposit, then the per-mode stepper update); over the full 100 steps it
+shadow-steps (the GPU state at steps 49 and 99 loaded into the oracle, one
+step of each compared: the whole spectral history and a seeded sample of
+1,048,576 particles).  Invariants that hold at any size: gauge residual at
+round-off, zero net charge, finite state, |v| < c.
 
 The 128 x 128 / 1,048,576-particle case runs through step() with HIP graph
 replay (the launch configuration bench.py times): invariants over 30 steps,
@@ -19,7 +21,7 @@ import torch
 
 from oracle import pic as opic
 from paper_2410_18414_amd import pic, workloads
-from pic_harness import hist_to_flat, make_gpu, oracle_params, rel
+from pic_harness import compare_particles, hist_to_flat, make_gpu, oracle_params, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -78,6 +80,60 @@ def test_512_first_step_sampled_and_invariants(gpu_lib, big, scheme):
     v2 = (parts[5:8] ** 2).sum(0)
     assert float(v2.max()) < 1.0
     ctx.close()
+
+
+@pytest.mark.parametrize("scheme", ["dirk2", "cdf2"])
+def test_512_100_steps_shadow_stepping(gpu_lib, big, scheme):
+    """The 512x512 / 67,108,864-particle float32 workload over its full 100
+    steps in the bench's launch configuration (step(), default tile plan).
+    At steps 50 and 100 the oracle takes the GPU state (promoted to float64)
+    and runs that step: the deposit over every particle, the field update and
+    gradients, and the gather and push of a seeded sample of 1,048,576
+    particles; the GPU's full spectral history (every field, every level) and
+    the sampled particles must agree at the float32 tolerance (1e-4).  The
+    gauge residual stays at round-off, the net charge at zero, |v| < c."""
+    import time
+    from pic_harness import flat_to_hist, shadow_step
+    w = big["w"]
+    n = len(w["x"])
+    p = oracle_params(w, 3, scheme)
+    g = make_gpu(w, 3, scheme, "f32")
+    rng = np.random.default_rng(5120 + len(scheme))
+    sample = np.sort(rng.choice(n, 1 << 20, replace=False))
+    s_dev = torch.as_tensor(sample, device=g.device)
+    t0 = time.time()
+    done = 0
+    for shadow_at in (50, 100):
+        pic.step(g, shadow_at - 1 - done)
+        a = pic.get_particles(g)
+        x, y = a[0].cpu().numpy(), a[1].cpu().numpy()
+        v = a[5:8].T.contiguous().cpu().numpy()
+        P_s = a[2:5][:, s_dev].T.contiguous().cpu().numpy()
+        vprev_s = a[8:11][:, s_dev].T.contiguous().cpu().numpy()
+        del a
+        hist = flat_to_hist(p, pic.get_history(g).cpu().numpy())
+        pic.step(g, 1)
+        done = shadow_at
+        print("%s: GPU state exported at step %d (%.0f s)" % (scheme, shadow_at - 1, time.time() - t0), flush=True)
+        ohist, opart = shadow_step(p, x, y, v, hist, sample, P_s, vprev_s)
+        del x, y, v
+        print("%s: oracle step %d done (%.0f s)" % (scheme, shadow_at, time.time() - t0), flush=True)
+        b = pic.get_particles(g)[:, s_dev].cpu().numpy()
+        gpart = dict(x=b[0], y=b[1], P=b[2:5].T, v=b[5:8].T, vprev=b[8:11].T)
+        errs, bad = compare_particles(gpart, opart, w["lx"], w["ly"], 1e-4)
+        assert not bad, (shadow_at, errs)
+        H = pic.get_history(g).cpu().numpy()
+        Ho = hist_to_flat(p, ohist)
+        worst = max(rel(H[f], Ho[f]) for f in range(H.shape[0]))
+        assert worst <= 1e-4, (shadow_at, worst)
+        print("%s: step %d shadow ok, particles %s, history %.2e" % (scheme, shadow_at, errs, worst), flush=True)
+    d = pic.diagnostics(g)
+    assert d["nonfinite"] == 0
+    assert d["gauge_l2"] <= 1e3 * EPS * d["gauge_scale"], d
+    assert abs(d["charge"]) <= 1e-9 * abs(w["q"]) * n, d
+    v2 = (pic.get_particles(g)[5:8] ** 2).sum(0)
+    assert float(v2.max()) < 1.0
+    g.close()
 
 
 def test_128_graph_replay_invariants_and_direct_equality(gpu_lib):

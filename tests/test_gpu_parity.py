@@ -30,7 +30,11 @@ def cloud_small(nx=32, ny=32, ppc=3, seed=12):
     return workloads.cloud(nx=nx, ny=ny, ppc=ppc, seed=seed, drift=0.2, vth=0.05)
 
 
-SCHEMES = [("bdf", 1), ("bdf", 2), ("bdf", 3), ("cdf2", 2), ("dirk2", 2)]
+# BDF-4..6 are A(alpha)-stable only (Sec. 3.2): on the wave equation's
+# imaginary eigenvalues a few modes grow slowly, identically on both sides
+# (a 1e-15 perturbation of the cloud run's momenta stays below 2e-14 after
+# 30 BDF-6 steps on the oracle)
+SCHEMES = [("bdf", 1), ("bdf", 2), ("bdf", 3), ("bdf", 4), ("bdf", 5), ("bdf", 6), ("cdf2", 2), ("dirk2", 2)]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
