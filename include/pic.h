@@ -145,7 +145,7 @@ typedef struct {                /* [host] */
   int32_t sort_interval;        /* position updates between re-sorts; 0 = from the
                                    particles init_particles loads: slack / (max(|v_x|,
                                    |v_y|) dt / min(dx, dy)), kept between the speed-of-
-                                   light interval and twice it (a particle that leaves
+                                   light interval and three times it (a particle that leaves
                                    its window takes the global path: results never
                                    depend on the interval)                              */
   double dt;                    /* time step                                             */
@@ -159,7 +159,7 @@ typedef struct {                /* [host] */
                                    that is no multiple of it ends in a partial tile     */
   int32_t chunk;                /* particles per workgroup of the sorted passes
                                    (64..65536); 0 = default: the largest of 512, 1024,
-                                   2048 leaving >= 8192 chunks at max_particles          */
+                                   2048, 4096 leaving >= 8192 chunks at max_particles    */
   int32_t slack;                /* cells a particle may drift from its tile and still use
                                    the tile's LDS window (1..8); 0 = default (3); at
                                    most min(nx, ny) - 2 when a side is no power of two */
@@ -216,6 +216,25 @@ pic_status_t pic_get_particles(pic_ctx_t ctx, double* out);
  * are wrapped. */
 pic_status_t pic_set_particles(pic_ctx_t ctx, const double* in);
 
+/* Saved states: the complete state of a context in phase READY (every
+ * instance's particles in their current sorted order with their original
+ * indices, the tile metadata of the last sort, the spectral history ring,
+ * and the step, ring and sort counters), in a caller-owned DEVICE buffer of
+ * pic_state_bytes(ctx) bytes, 256-byte aligned.  pic_save_state enqueues
+ * device-to-device copies (no synchronisation, no allocation); pic_load_state
+ * restores a state saved by a context of the same configuration (it reads
+ * the buffer's header, synchronising the stream), after
+ * which the context steps exactly as it would have from the saved point --
+ * no conversion to float64 and no re-sort, unlike pic_get/set_particles and
+ * pic_get/set_history.  pic_load_state accepts any phase (it replaces the
+ * whole state and leaves phase READY); pic_save_state returns PIC_ERR_STATE
+ * in phases other than READY.  The layout is private to the library version:
+ * PIC_ERR_INVALID_ARG for a buffer from another configuration or not 256-byte
+ * aligned. */
+size_t pic_state_bytes(pic_ctx_t ctx);
+pic_status_t pic_save_state(pic_ctx_t ctx, void* dst);
+pic_status_t pic_load_state(pic_ctx_t ctx, const void* src);
+
 /* Real mesh fields, float64 device dst:
  *   PIC_FIELD_J      [3][ny][nx]  J^{n+1}; valid in phase DEPOSITED
  *                    (PIC_FLAG_DIRK_SUBSTEP: [3 stages][ny][nx], stage i at
@@ -250,6 +269,22 @@ pic_status_t pic_set_history(pic_ctx_t ctx, const double* src);
  * out[7] > 0 (the values are still written). */
 #define PIC_DIAG_COUNT 8
 pic_status_t pic_diagnostics(pic_ctx_t ctx, double* out);
+
+/* General s-stage DIRK (Sec. 3.3: the stage equations, the continuity update
+ * and the gauge theorem are stated for any diagonally implicit tableau).
+ * Replaces the tableau of a PIC_SCHEME_DIRK2 / PIC_SCHEME_DIRK3 context (every
+ * instance of an ensemble) by [host] A[stages*stages] (row-major, lower
+ * triangular, positive diagonal: each stage solves one modified-Helmholtz
+ * problem with alpha_i = 1/(dt a_ii c)), b[stages] (summing to one) and
+ * c[stages] (the row sums of A; stage currents interpolate J^n and J^{n+1} at
+ * c_i, or are deposited at x^n + c_i dt v^n with PIC_FLAG_DIRK_SUBSTEP).
+ * stages must be the scheme's: 2 for PIC_SCHEME_DIRK2, 3 for
+ * PIC_SCHEME_DIRK3.  Phase READY or before particles are loaded; the next
+ * steps use the new tableau (the history layout does not change).
+ * PIC_ERR_UNSUPPORTED for other schemes, PIC_ERR_INVALID_ARG for a tableau
+ * outside these rules. */
+pic_status_t pic_set_dirk_tableau(pic_ctx_t ctx, int32_t stages, const double* A, const double* b,
+                                  const double* c);
 
 /* ---- Ensembles (batched instances) ----------------------------------------
  * A context may hold ninst independent instances of the method: an ensemble
@@ -291,13 +326,25 @@ pic_status_t step_batched(pic_ctx_t ctx, int32_t nsteps);
  * step_adjoint: phase READY with the context holding S^n.  Recomputes the
  * position update, deposit and field solve of step n -> n+1 (as
  * deposit_current + field_solve; phase -> SOLVED afterwards, so the caller
- * reloads the next state with pic_set_particles and pic_set_history), then
- * maps (lam, lam_hist) = lambda^{n+1} to lambda^n = (dS^{n+1}/dS^n)^T
- * lambda^{n+1}: the push and gather adjoint (a scatter onto the 11 gathered
- * mesh fields; spline derivative weights for the position), the field-solve
- * adjoint (conjugate transforms and the transposed per-mode BDF recurrence)
- * and the deposit adjoint (a gather of d/dJ with spline and derivative
- * weights).  Wrap-around of positions counts as the identity.
+ * reloads the next state, with pic_load_state or pic_set_particles and
+ * pic_set_history), then maps (lam, lam_hist) = lambda^{n+1} to lambda^n =
+ * (dS^{n+1}/dS^n)^T lambda^{n+1}: the push and gather adjoint (a scatter onto
+ * the 11 gathered mesh fields; spline derivative weights for the position),
+ * the field-solve adjoint (conjugate transforms and the transposed per-mode
+ * BDF recurrence) and the deposit adjoint (a gather of d/dJ with spline and
+ * derivative weights).  Wrap-around of positions counts as the identity.
+ * lam NULL: the particle adjoint is the one the context holds (below) and
+ * stays there, so a sweep of many steps exchanges it only at its ends.
+ *
+ * The held particle adjoint: the context keeps lam in the order of its
+ * particle slots, so the adjoint passes read and write it with contiguous
+ * accesses; it is permuted only when a sort changes the order (a device-side
+ * check of the order on every step, no host synchronisation).
+ * pic_adjoint_set_particles: lam [11][n] in original order (NULL: zero) into
+ * the context, for the particles loaded now.  pic_adjoint_get_particles: the
+ * held adjoint back out in original order (PIC_ERR_STATE if none is held for
+ * the loaded particle count).  step_adjoint with a non-NULL lam is
+ * set_particles, the NULL form, get_particles.
  *
  * adjoint_initial: any loaded phase.  Maps the adjoint of S^0 to the adjoint of
  * the init_particles inputs, P0 [3n] as given to init_particles (original
@@ -306,6 +353,8 @@ pic_status_t step_batched(pic_ctx_t ctx, int32_t nsteps);
  * already d/dx0, d/dy0. */
 pic_status_t adjoint_seed_energy(pic_ctx_t ctx, double scale, double* lam_hist);
 pic_status_t step_adjoint(pic_ctx_t ctx, double* lam, double* lam_hist);
+pic_status_t pic_adjoint_set_particles(pic_ctx_t ctx, const double* lam);
+pic_status_t pic_adjoint_get_particles(pic_ctx_t ctx, double* lam);
 pic_status_t adjoint_initial(pic_ctx_t ctx, const double* P0, double* lam);
 
 /* Kernel timing with HIP events recorded on the context's stream around each

@@ -66,7 +66,7 @@ def residuals(state):
         Eh = np.stack([-ikx * phim - dA[0], -iky * phim - dA[1], -dA[2]])
         Ah = 0.5 * (h["A"][0] + h["A"][1])
     else:
-        _, b, cc = schemes.dirk_tableau(p.scheme)
+        _, b, cc = p.tableau()
         Rn, Rn1 = float(np.sum(b * (1 - cc))), float(np.sum(b * cc))
         if p.dirk_substep:
             # stage-value gauge: v_phi + c^2 div A at the new level

@@ -87,9 +87,20 @@ DIRK_FORMS = ("dirk2", "dirk3")
 class Params:
     def __init__(self, nx, ny, lx, ly, degree, scheme, dt, c=1.0, eps0=1.0,
                  mu0=1.0, q=-1.0, m=1.0, bdf_order=2, naive=False, jvstar=False,
-                 dirk_substep=False):
+                 dirk_substep=False, dirk_tableau=None):
         if scheme not in ("bdf",) + CDF2_FORMS + DIRK_FORMS:
             raise ValueError(scheme)
+        # a general s-stage DIRK tableau (A lower triangular, b, c) replacing
+        # the scheme's own (Sec. 3.3 states the method for any tableau)
+        if dirk_tableau is not None:
+            if scheme not in DIRK_FORMS:
+                raise ValueError("a DIRK tableau needs a DIRK scheme")
+            A_t, b, cc = (np.array(t, np.float64) for t in dirk_tableau)
+            if A_t.shape != (len(b), len(b)) or cc.shape != b.shape or np.any(np.triu(A_t, 1) != 0):
+                raise ValueError("the tableau must be a lower-triangular s x s A with b, c of length s")
+            self.dirk_tab = (A_t, b, cc)
+        else:
+            self.dirk_tab = None
         if naive and scheme in CDF2_FORMS:
             raise ValueError("the naive charge deposit needs BDF-k or DIRK-2")
         self.naive = bool(naive)
@@ -109,6 +120,10 @@ class Params:
     @property
     def spec_shape(self):
         return (self.ny, self.nx // 2 + 1)
+
+    def tableau(self):
+        """(A, b, c) of the DIRK stepper: the one given, else the scheme's."""
+        return self.dirk_tab if self.dirk_tab is not None else schemes.dirk_tableau(self.scheme)
 
 
 # ----------------------------------------------------------------------------
@@ -357,7 +372,7 @@ def _stage_rho(A_t, b, cc, rho_n, dv, h):
 def _dirk_update(p, hist, Jh, rho_h=None):
     # Sec. 3.3: s-stage DIRK on (u, v) with u' = v, v' = c^2 (S + Lap u)
     # Jh: J^{n+1}, or with dirk_substep the s stage currents [s, 3, ...]
-    A_t, b, cc = schemes.dirk_tableau(p.scheme)
+    A_t, b, cc = p.tableau()
     s = len(b)
     h, c2, lap = p.dt, p.c ** 2, p.lap
     rho_n = hist["rho"][0]
@@ -431,7 +446,7 @@ class State:
         pt["x"], pt["y"] = position_update(self.p, pt["x"], pt["y"], pt["v"])
         vj = 2.0 * pt["v"] - pt["vprev"] if self.p.jvstar else pt["v"]
         if self.p.dirk_substep:
-            _, _, cc = schemes.dirk_tableau(self.p.scheme)
+            _, _, cc = self.p.tableau()
             self.J = np.stack([deposit_current(self.p, *stage_positions(self.p, x0, y0, pt["v"], ci), vj)
                                for ci in cc])
         else:

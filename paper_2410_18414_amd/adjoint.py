@@ -9,9 +9,12 @@ The forward runs `nsteps` steps from the cold start of init_particles and
 returns the field energy of the final level (pic_diagnostics out[5]).  The
 backward walks the run in reverse with libpic's discrete adjoint
 (adjoint_seed_energy, step_adjoint, adjoint_initial): the state is kept every
-`every` steps during the forward (checkpoints: particles + spectral history);
-each segment is replayed forward from its checkpoint to recover the states
-inside it, then the adjoint steps through the segment backwards.  every=1
+`every` steps during the forward (checkpoints: pic_save_state, the context's
+raw device state -- particles in their sorted order, tile metadata, history
+ring); each segment is replayed forward from its checkpoint into a pool of
+saved states, then the adjoint steps through the segment backwards, loading
+each state with pic_load_state (no conversion and no re-sort); the particle
+adjoint stays inside the context in slot order for the whole sweep.  every=1
 stores every state (no replay).  Only argument marshalling happens here:
 every step and every adjoint step runs in the library's kernels.
 """
@@ -28,11 +31,11 @@ class _FieldEnergy(torch.autograd.Function):
         ckpts = []
         s = 0
         while s < nsteps:
-            ckpts.append((s, pic.get_particles(ctx), pic.get_history(ctx)))
+            ckpts.append((s, pic.save_state(ctx)))
             k = min(every, nsteps - s)
             pic.step(ctx, k)
             s += k
-        final = (pic.get_particles(ctx), pic.get_history(ctx))
+        final = pic.save_state(ctx)
         W = pic.diagnostics(ctx)["energy"]
         fctx.sim = ctx
         fctx.ckpts = ckpts
@@ -46,25 +49,26 @@ class _FieldEnergy(torch.autograd.Function):
     def backward(fctx, gW):
         ctx = fctx.sim
         (P0,) = fctx.saved_tensors
-        n = ctx.n
         # the seed needs the final history loaded
-        pic.set_particles(ctx, fctx.final[0])
-        pic.set_history(ctx, fctx.final[1])
-        lam = torch.zeros((11, n), dtype=torch.float64, device=ctx.device)
+        pic.load_state(ctx, fctx.final)
+        pic.adjoint_set_particles(ctx, None)  # the particle adjoint of W is zero
         lam_hist = pic.adjoint_seed_energy(ctx, float(gW))
-        for s0, parts, hist in reversed(fctx.ckpts):
+        # states inside a segment are replayed into a pool of saved states
+        pool = []
+        for s0, ck in reversed(fctx.ckpts):
             seg = min(fctx.every, fctx.nsteps - s0)
-            states = [(parts, hist)]
+            states = [ck]
             if seg > 1:
-                pic.set_particles(ctx, parts)
-                pic.set_history(ctx, hist)
-                for _ in range(1, seg):
+                pic.load_state(ctx, ck)
+                for j in range(1, seg):
                     pic.step(ctx, 1)
-                    states.append((pic.get_particles(ctx), pic.get_history(ctx)))
-            for parts_j, hist_j in reversed(states):
-                pic.set_particles(ctx, parts_j)
-                pic.set_history(ctx, hist_j)
-                pic.step_adjoint(ctx, lam, lam_hist)
+                    if len(pool) < j:
+                        pool.append(pic.State(ctx))
+                    states.append(pic.save_state(ctx, pool[j - 1]))
+            for st in reversed(states):
+                pic.load_state(ctx, st)
+                pic.step_adjoint(ctx, None, lam_hist)
+        lam = pic.adjoint_get_particles(ctx)
         pic.adjoint_initial(ctx, P0.detach(), lam)
         return lam[0].clone(), lam[1].clone(), lam[2:5].clone(), None, None, None
 

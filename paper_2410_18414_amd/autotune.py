@@ -31,7 +31,7 @@ from . import pic
 # correct -- particles that leave their window take the global path -- and pay
 # off when particles are slower than c)
 CANDIDATES = [dict(tile_cells=t, chunk=c, unfused=u, sort_interval=si)
-              for t in (8, 16) for c in (512, 1024, 2048) for u in (False, True) for si in (0, 12)]
+              for t in (8, 16) for c in (512, 1024, 2048, 4096) for u in (False, True) for si in (0, 12)]
 KNOBS = ("tile_cells", "chunk", "unfused", "sort_interval")
 
 

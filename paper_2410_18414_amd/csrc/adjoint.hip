@@ -27,8 +27,11 @@
 // (w_kx / N) rfft2(lambda_F) with w = 1 on the kx = 0 and kx = nx/2 columns
 // and 2 elsewhere.
 //
-// Adjoint particle state lam[11][n] (original particle order, like
-// pic_get_particles): x, y, Px, Py, Pz, v^n (3), v^{n-1} (3).
+// Adjoint particle state LAM[11][ls] in the slot order of the particle set
+// the step runs on (so every access coalesces): x, y, Px, Py, Pz, v^n (3),
+// v^{n-1} (3).  LIDS[i] names the original particle held in slot i; when a
+// sort changes the set's order, k_lam_* permute LAM to the new one.  Callers
+// exchange it in original order (k_lam_set / k_lam_get).
 #include "fft_lds.h"
 #include "particle_math.h"
 
@@ -38,14 +41,24 @@ namespace pic {
 
 namespace {
 
+// one particle's adjoint: slot k of the arrays at b (wave-uniform base), f * ls apart
+struct LamRef {
+  gptr<double> b;
+  int64_t ls;
+  uint32_t k;
+  __device__ __forceinline__ __attribute__((address_space(1))) double& operator()(int f) const {
+    return elt(b + f * ls, k);
+  }
+};
+
 // Push adjoint of one particle: gathered values gv (and their x, y
 // derivatives gdx, gdy, per unit node coordinate) at x^{n+1}; P^n, v^n,
-// v^{n-1}; lambda^{n+1} in lam[.][o] in, lambda (all but the deposit part) out.
+// v^{n-1}; lambda^{n+1} in lam in, lambda (all but the deposit part) out.
 // Returns lambda_g in lg[11] (to be scattered onto the mesh fields).
 __device__ __forceinline__ void adj_push_one(const double* gv, const double* gdx, const double* gdy, double P0,
                                              double P1, double P2, double v0, double v1, double v2, double w0,
                                              double w1, double w2, const PhysP& ph, const GridP& g,
-                                             double* __restrict__ lam, int64_t n, int64_t o, double* lg) {
+                                             const LamRef& lam, double* lg) {
   // forward push (IAEM) with its intermediates
   const double q = ph.q, dt = ph.dt, c2 = ph.c * ph.c, mc2 = ph.m * c2;
   const double s0 = 2.0 * v0 - w0, s1 = 2.0 * v1 - w1, s2 = 2.0 * v2 - w2;
@@ -56,12 +69,12 @@ __device__ __forceinline__ void adj_push_one(const double* gv, const double* gdx
   const double uz = P2 - q * gv[4];
   const double ss = sqrt(c2 * (ux * ux + uy * uy + uz * uz) + mc2 * mc2);
   // adjoint of v' = c^2 u / ss
-  const double lvx = lam[5 * n + o], lvy = lam[6 * n + o], lvz = lam[7 * n + o];
+  const double lvx = lam(5), lvy = lam(6), lvz = lam(7);
   const double ud = (ux * lvx + uy * lvy + uz * lvz) * c2 / (ss * ss);
   const double k1 = c2 / ss;
   const double lux = k1 * (lvx - ud * ux), luy = k1 * (lvy - ud * uy), luz = k1 * (lvz - ud * uz);
   // P' = P + q dt (Fx, Fy, 0), u = P' - q A
-  const double lPx = lam[2 * n + o] + lux, lPy = lam[3 * n + o] + luy, lPz = lam[4 * n + o] + luz;
+  const double lPx = lam(2) + lux, lPy = lam(3) + luy, lPz = lam(4) + luz;
   const double lFx = q * dt * lPx, lFy = q * dt * lPy;
   lg[0] = -lFx;
   lg[1] = -lFy;
@@ -84,25 +97,25 @@ __device__ __forceinline__ void adj_push_one(const double* gv, const double* gdx
     lxg += lg[f] * gdx[f];
     lyg += lg[f] * gdy[f];
   }
-  lam[o] += lxg * g.inv_dx;  // lambda of x^{n+1}, deposit part still to come
-  lam[n + o] += lyg * g.inv_dy;
-  lam[2 * n + o] = lPx;  // final: P enters only through P'
-  lam[3 * n + o] = lPy;
-  lam[4 * n + o] = lPz;
+  lam(0) += lxg * g.inv_dx;  // lambda of x^{n+1}, deposit part still to come
+  lam(1) += lyg * g.inv_dy;
+  lam(2) = lPx;  // final: P enters only through P'
+  lam(3) = lPy;
+  lam(4) = lPz;
   // v^n: the outgoing v^{n-1} slot of S^{n+1} is v^n itself, plus 2 lambda_v*
-  lam[5 * n + o] = lam[8 * n + o] + 2.0 * lsx;
-  lam[6 * n + o] = lam[9 * n + o] + 2.0 * lsy;
-  lam[7 * n + o] = lam[10 * n + o] + 2.0 * lsz;
-  lam[8 * n + o] = -lsx;
-  lam[9 * n + o] = -lsy;
-  lam[10 * n + o] = -lsz;
+  lam(5) = lam(8) + 2.0 * lsx;
+  lam(6) = lam(9) + 2.0 * lsy;
+  lam(7) = lam(10) + 2.0 * lsz;
+  lam(8) = -lsx;
+  lam(9) = -lsy;
+  lam(10) = -lsz;
 }
 
 // gathered values and their node-coordinate derivatives from planar fields
 // F[f * stride + node] with nodes (sx + a, sy + b) at row pitch `pitch` (a
 // window, or the global mesh with wrapped indices when `wrap`)
-template <int DEG, int NF>
-__device__ __forceinline__ void gather_d(const double* __restrict__ F, size_t stride, const double* wx,
+template <int DEG, int NF, typename Ptr>
+__device__ __forceinline__ void gather_d(Ptr F, size_t stride, const double* wx,
                                          const double* dwx, const double* wy, const double* dwy, int sx, int sy,
                                          const GridP& g, int pitch, bool wrap, double* gv, double* gdx,
                                          double* gdy) {
@@ -138,18 +151,19 @@ __device__ __forceinline__ void gather_d(const double* __restrict__ F, size_t st
 // push + gather adjoint.  Particle arrays hold x^{n+1} (recomputed), P^n, v^n
 // and v^{n-1}; F64 holds the mesh fields of level n+1.
 template <int DEG>
-__global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D, StepArgs sa, double* __restrict__ lam) {
+__global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D, StepArgs sa, double* lam_,
+                                                  int64_t ls) {
   using S = Spline<double, DEG>;
   const InstDesc& d = D[0];
   const int64_t n = d.n;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 256, i = i0 + threadIdx.x;
   if (i >= n) return;
   const GridP g = d.g;
   const PhysP ph = d.ph;
-  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
-  const int64_t o = p.id[i];
+  const GParts<double> p = global_parts(make_parts<double>(d, sa.cur, sa.vflip));
+  const LamRef lam{gp(lam_) + i0, ls, threadIdx.x};
   const size_t plane = (size_t)g.nx * g.ny;
-  const double* __restrict__ F = d.F64;
+  const gptr<const double> F = gp((const double*)d.F64);
   const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
   const bool inside = in_box(xi, eta, g);
   int sx = 0, sy = 0;
@@ -164,9 +178,9 @@ __global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D
   }
   double lg[11];
   adj_push_one(gv, gdx, gdy, p.P[0][i], p.P[1][i], p.P[2][i], p.v[0][i], p.v[1][i], p.v[2][i], p.w[0][i],
-               p.w[1][i], p.w[2][i], ph, g, lam, n, o, lg);
+               p.w[1][i], p.w[2][i], ph, g, lam, lg);
   if (!inside) return;
-  double* __restrict__ LF = d.LF;
+  const gptr<double> LF = gp(d.LF);
 #pragma unroll
   for (int b = 0; b < S::NW; ++b) {
     const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
@@ -175,7 +189,7 @@ __global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D
       const size_t m = row + wrapi(sx + a, g.nx);
       const double w = wx[a] * wy[b];
 #pragma unroll
-      for (int f = 0; f < 11; ++f) atomicAdd(LF + f * plane + m, lg[f] * w);
+      for (int f = 0; f < 11; ++f) gadd(LF + f * plane + m, lg[f] * w);
     }
   }
 }
@@ -207,7 +221,7 @@ __device__ __forceinline__ AdjWin adj_window(const InstDesc& d, const int4& it) 
 }
 
 // copy nf planes of the mesh array src[f][ny][nx] into the window dst[f][WP]
-__device__ __forceinline__ void adj_load_window(double* __restrict__ dst, const double* __restrict__ src, int nf,
+__device__ __forceinline__ void adj_load_window(double* __restrict__ dst, gptr<const double> src, int nf,
                                                 const AdjWin& a, const GridP& g) {
   const size_t plane = (size_t)g.nx * g.ny;
   if (a.wi < a.W)
@@ -225,7 +239,7 @@ constexpr int kAdjPushThreads = 512;
 
 template <int DEG>
 __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* __restrict__ D, StepArgs sa,
-                                                                double* __restrict__ lam) {
+                                                                double* lam_, int64_t ls) {
   using S = Spline<double, DEG>;
   constexpr int NW = S::NW;
   const InstDesc& d = D[0];
@@ -233,15 +247,17 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
   const int4 it = d.tb.work[blockIdx.x];
   const GridP g = d.g;
   const PhysP ph = d.ph;
-  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
-  const int64_t n = d.n;
+  const GParts<double> p = parts_from(global_parts(make_parts<double>(d, sa.cur, sa.vflip)), it.y);
+  const gptr<double> lamb = gp(lam_) + it.y;
+  const gptr<const double> F = gp((const double*)d.F64);
+  const gptr<double> LF = gp(d.LF);
   const size_t plane = (size_t)g.nx * g.ny;
   const AdjWin a = adj_window(d, it);
   const int W = a.W, WP = a.WP;
   extern __shared__ double2 sm[];
   double* fw = reinterpret_cast<double*>(sm);  // [11][WP] mesh fields of level n+1
   double* lw = fw + 11 * WP;                   // [11][WP] their adjoints
-  adj_load_window(fw, d.F64, 11, a, g);
+  adj_load_window(fw, F, 11, a, g);
   for (int t = threadIdx.x; t < 11 * WP; t += blockDim.x) lw[t] = 0.0;
   __syncthreads();
   // lanes of one cell (neighbours in the cell-sorted order) scatter in a
@@ -249,9 +265,8 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
   const int lane = threadIdx.x & 63;
   const int ra = lane % NW, rb = (lane / NW) % NW;
   for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
-    const int64_t i = it.y + k;
-    const int64_t o = p.id[i];
-    const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
+    const LamRef lam{lamb, ls, (uint32_t)k};
+    const double xi = elt(p.x, k) * g.inv_dx, eta = elt(p.y, k) * g.inv_dy;
     const bool inside = in_box(xi, eta, g);
     int sx = 0, sy = 0, lx = 0, ly = 0;
     bool inw = false;
@@ -268,11 +283,11 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
       if (inw)
         gather_d<DEG, 11>(fw + ly * W + lx, WP, wx, dwx, wy, dwy, 0, 0, g, W, false, gv, gdx, gdy);
       else
-        gather_d<DEG, 11>(d.F64, plane, wx, dwx, wy, dwy, sx, sy, g, 0, true, gv, gdx, gdy);
+        gather_d<DEG, 11>(F, plane, wx, dwx, wy, dwy, sx, sy, g, 0, true, gv, gdx, gdy);
     }
     double lg[11];
-    adj_push_one(gv, gdx, gdy, p.P[0][i], p.P[1][i], p.P[2][i], p.v[0][i], p.v[1][i], p.v[2][i], p.w[0][i],
-                 p.w[1][i], p.w[2][i], ph, g, lam, n, o, lg);
+    adj_push_one(gv, gdx, gdy, elt(p.P[0], k), elt(p.P[1], k), elt(p.P[2], k), elt(p.v[0], k), elt(p.v[1], k),
+                 elt(p.v[2], k), elt(p.w[0], k), elt(p.w[1], k), elt(p.w[2], k), ph, g, lam, lg);
     if (inw) {
       double* nd0 = lw + ly * W + lx;
 #pragma unroll
@@ -304,7 +319,7 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
           const size_t m = row + wrapi(sx + aa, g.nx);
           const double w = wx[aa] * wy[b];
 #pragma unroll
-          for (int f = 0; f < 11; ++f) atomicAdd(d.LF + f * plane + m, lg[f] * w);
+          for (int f = 0; f < 11; ++f) gadd(LF + f * plane + m, lg[f] * w);
         }
       }
     }
@@ -316,14 +331,14 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
       const int node = j * W + a.wi;
       for (int f = 0; f < 11; ++f) {
         const double v = lw[f * WP + node];
-        if (v != 0.0) atomicAdd(d.LF + f * plane + go, v);
+        if (v != 0.0) gadd(LF + f * plane + go, v);
       }
     }
 }
 
 template <int DEG>
 __global__ void __launch_bounds__(256) k_adj_deposit_t(const InstDesc* __restrict__ D, StepArgs sa,
-                                                       double* __restrict__ lam) {
+                                                       double* lam_, int64_t ls) {
   using S = Spline<double, DEG>;
   constexpr int NW = S::NW;
   const InstDesc& d = D[0];
@@ -331,20 +346,20 @@ __global__ void __launch_bounds__(256) k_adj_deposit_t(const InstDesc* __restric
   const int4 it = d.tb.work[blockIdx.x];
   const GridP g = d.g;
   const PhysP ph = d.ph;
-  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
-  const int64_t n = d.n;
+  const GParts<double> p = parts_from(global_parts(make_parts<double>(d, sa.cur, sa.vflip)), it.y);
+  const gptr<double> lamb = gp(lam_) + it.y;
+  const gptr<const double> LJ = gp((const double*)d.LJ);
   const size_t plane = (size_t)g.nx * g.ny;
   const AdjWin a = adj_window(d, it);
   const int W = a.W, WP = a.WP;
   extern __shared__ double2 sm[];
   double* jw = reinterpret_cast<double*>(sm);  // [3][WP] lambda_J
-  adj_load_window(jw, d.LJ, 3, a, g);
+  adj_load_window(jw, LJ, 3, a, g);
   __syncthreads();
   const double s = ph.q * g.inv_area;
   for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
-    const int64_t i = it.y + k;
-    const int64_t o = p.id[i];
-    const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
+    const LamRef lam{lamb, ls, (uint32_t)k};
+    const double xi = elt(p.x, k) * g.inv_dx, eta = elt(p.y, k) * g.inv_dy;
     double av[3] = {0, 0, 0}, bx[3] = {0, 0, 0}, by[3] = {0, 0, 0};
     if (in_box(xi, eta, g)) {
       int sx, sy;
@@ -355,16 +370,16 @@ __global__ void __launch_bounds__(256) k_adj_deposit_t(const InstDesc* __restric
       if (lx + DEG < W && ly + DEG < W)
         gather_d<DEG, 3>(jw + ly * W + lx, WP, wx, dwx, wy, dwy, 0, 0, g, W, false, av, bx, by);
       else
-        gather_d<DEG, 3>(d.LJ, plane, wx, dwx, wy, dwy, sx, sy, g, 0, true, av, bx, by);
+        gather_d<DEG, 3>(LJ, plane, wx, dwx, wy, dwy, sx, sy, g, 0, true, av, bx, by);
     }
-    const double v0 = p.v[0][i], v1 = p.v[1][i], v2 = p.v[2][i];
-    const double lx_ = lam[o] + s * (v0 * bx[0] + v1 * bx[1] + v2 * bx[2]) * g.inv_dx;
-    const double ly_ = lam[n + o] + s * (v0 * by[0] + v1 * by[1] + v2 * by[2]) * g.inv_dy;
-    lam[o] = lx_;
-    lam[n + o] = ly_;
-    lam[5 * n + o] += s * av[0] + ph.dt * lx_;
-    lam[6 * n + o] += s * av[1] + ph.dt * ly_;
-    lam[7 * n + o] += s * av[2];
+    const double v0 = elt(p.v[0], k), v1 = elt(p.v[1], k), v2 = elt(p.v[2], k);
+    const double lx_ = lam(0) + s * (v0 * bx[0] + v1 * bx[1] + v2 * bx[2]) * g.inv_dx;
+    const double ly_ = lam(1) + s * (v0 * by[0] + v1 * by[1] + v2 * by[2]) * g.inv_dy;
+    lam(0) = lx_;
+    lam(1) = ly_;
+    lam(5) += s * av[0] + ph.dt * lx_;
+    lam(6) += s * av[1] + ph.dt * ly_;
+    lam(7) += s * av[2];
   }
 }
 
@@ -488,19 +503,19 @@ __global__ void __launch_bounds__(256) k_adj_columns(const InstDesc* __restrict_
 // deposit adjoint + position update adjoint.  Particle arrays hold x^{n+1}
 // and v^n; LJ holds lambda_J.
 template <int DEG>
-__global__ void __launch_bounds__(256) k_adj_deposit(const InstDesc* __restrict__ D, StepArgs sa,
-                                                     double* __restrict__ lam) {
+__global__ void __launch_bounds__(256) k_adj_deposit(const InstDesc* __restrict__ D, StepArgs sa, double* lam_,
+                                                     int64_t ls) {
   using S = Spline<double, DEG>;
   const InstDesc& d = D[0];
   const int64_t n = d.n;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 256, i = i0 + threadIdx.x;
   if (i >= n) return;
   const GridP g = d.g;
   const PhysP ph = d.ph;
-  const Parts<double> p = make_parts<double>(d, sa.cur, sa.vflip);
-  const int64_t o = p.id[i];
+  const GParts<double> p = global_parts(make_parts<double>(d, sa.cur, sa.vflip));
+  const LamRef lam{gp(lam_) + i0, ls, threadIdx.x};
   const size_t plane = (size_t)g.nx * g.ny;
-  const double* __restrict__ LJ = d.LJ;
+  const gptr<const double> LJ = gp((const double*)d.LJ);
   const double xi = p.x[i] * g.inv_dx, eta = p.y[i] * g.inv_dy;
   double av[3] = {0, 0, 0}, bx[3] = {0, 0, 0}, by[3] = {0, 0, 0};
   if (in_box(xi, eta, g)) {
@@ -533,14 +548,14 @@ __global__ void __launch_bounds__(256) k_adj_deposit(const InstDesc* __restrict_
   // J = sum q v^n S(x' - X) / (dx dy)
   const double s = ph.q * g.inv_area;
   const double v0 = p.v[0][i], v1 = p.v[1][i], v2 = p.v[2][i];
-  const double lx = lam[o] + s * (v0 * bx[0] + v1 * bx[1] + v2 * bx[2]) * g.inv_dx;
-  const double ly = lam[n + o] + s * (v0 * by[0] + v1 * by[1] + v2 * by[2]) * g.inv_dy;
+  const double lx = lam(0) + s * (v0 * bx[0] + v1 * bx[1] + v2 * bx[2]) * g.inv_dx;
+  const double ly = lam(1) + s * (v0 * by[0] + v1 * by[1] + v2 * by[2]) * g.inv_dy;
   // x' = wrap(x + v^n dt): unit derivative in x, dt in v
-  lam[o] = lx;
-  lam[n + o] = ly;
-  lam[5 * n + o] += s * av[0] + ph.dt * lx;
-  lam[6 * n + o] += s * av[1] + ph.dt * ly;
-  lam[7 * n + o] += s * av[2];
+  lam(0) = lx;
+  lam(1) = ly;
+  lam(5) += s * av[0] + ph.dt * lx;
+  lam(6) += s * av[1] + ph.dt * ly;
+  lam(7) += s * av[2];
 }
 
 // ---------------------------------------------------------------------------
@@ -608,26 +623,114 @@ __global__ void k_adj_initial(int64_t n, const double* __restrict__ P, PhysP ph,
   for (int c = 5; c < 11; ++c) lam[c * n + i] = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// The held particle adjoint.  k_lam_set: from original order (lam[11][n],
+// null: zero), slot i holding particle i.  k_lam_get: back to original order.
+__global__ void k_lam_set(int64_t n, const double* __restrict__ src, double* __restrict__ LAM, int64_t ls,
+                          int32_t* __restrict__ LIDS) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int f = 0; f < 11; ++f) LAM[f * ls + i] = src ? src[f * n + i] : 0.0;
+  LIDS[i] = (int32_t)i;
+}
+
+__global__ void k_lam_get(int64_t n, const double* __restrict__ LAM, int64_t ls, const int32_t* __restrict__ LIDS,
+                          double* __restrict__ dst) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = LIDS[i];
+  for (int f = 0; f < 11; ++f) dst[f * n + o] = LAM[f * ls + i];
+}
+
+// Following the particle set's order: flag = (LIDS differs from ids anywhere);
+// then, only if set, LINV = the slot of each particle in LAM, LAM2 = LAM in
+// the order of ids, and LAM, LIDS = LAM2, ids.  The host never reads the flag,
+// so a step without a sort costs one pass over the two index arrays.
+__global__ void k_lam_flag_clear(int32_t* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
+
+__global__ void k_lam_check(int64_t n, const int32_t* __restrict__ LIDS, const int32_t* __restrict__ ids,
+                            int32_t* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool diff = i < n && LIDS[i] != ids[i];
+  if (__any(diff) && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
+__global__ void k_lam_inverse(int64_t n, const int32_t* __restrict__ LIDS, int32_t* __restrict__ LINV,
+                              const int32_t* flag) {
+  if (!*flag) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) LINV[LIDS[i]] = (int32_t)i;
+}
+
+__global__ void k_lam_permute(int64_t n, const double* __restrict__ LAM, double* __restrict__ LAM2, int64_t ls,
+                              const int32_t* __restrict__ ids, const int32_t* __restrict__ LINV,
+                              const int32_t* flag) {
+  if (!*flag) return;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t src = LINV[ids[j]];
+  for (int f = 0; f < 11; ++f) LAM2[f * ls + j] = LAM[f * ls + src];
+}
+
+__global__ void k_lam_commit(int64_t n, const double* __restrict__ LAM2, double* __restrict__ LAM, int64_t ls,
+                             const int32_t* __restrict__ ids, int32_t* __restrict__ LIDS, const int32_t* flag) {
+  if (!*flag) return;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int f = 0; f < 11; ++f) LAM[f * ls + j] = LAM2[f * ls + j];
+  LIDS[j] = ids[j];
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-hipError_t launch_adj_push(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s) {
+hipError_t launch_lam_set(int64_t n, const double* src, double* LAM, int64_t ls, int32_t* LIDS, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lam_set, dim3(blocks_for(n)), dim3(256), 0, s, n, src, LAM, ls, LIDS);
+  return hipGetLastError();
+}
+
+hipError_t launch_lam_get(int64_t n, const double* LAM, int64_t ls, const int32_t* LIDS, double* dst, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lam_get, dim3(blocks_for(n)), dim3(256), 0, s, n, LAM, ls, LIDS, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_lam_follow(int64_t n, const int32_t* ids, double* LAM, double* LAM2, int64_t ls, int32_t* LIDS,
+                             int32_t* LINV, int32_t* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid(blocks_for(n)), block(256);
+  hipLaunchKernelGGL(k_lam_flag_clear, dim3(1), dim3(64), 0, s, flag);
+  hipLaunchKernelGGL(k_lam_check, grid, block, 0, s, n, (const int32_t*)LIDS, ids, flag);
+  hipLaunchKernelGGL(k_lam_inverse, grid, block, 0, s, n, (const int32_t*)LIDS, LINV, (const int32_t*)flag);
+  hipLaunchKernelGGL(k_lam_permute, grid, block, 0, s, n, (const double*)LAM, LAM2, ls, ids, (const int32_t*)LINV,
+                     (const int32_t*)flag);
+  hipLaunchKernelGGL(k_lam_commit, grid, block, 0, s, n, (const double*)LAM2, LAM, ls, ids, LIDS,
+                     (const int32_t*)flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_push(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, int64_t ls,
+                           hipStream_t s) {
   if (n == 0) return hipSuccess;
   switch (degree) {
-    case 1: hipLaunchKernelGGL(k_adj_push<1>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
-    case 2: hipLaunchKernelGGL(k_adj_push<2>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
-    default: hipLaunchKernelGGL(k_adj_push<3>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
+    case 1: hipLaunchKernelGGL(k_adj_push<1>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam, ls); break;
+    case 2: hipLaunchKernelGGL(k_adj_push<2>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam, ls); break;
+    default: hipLaunchKernelGGL(k_adj_push<3>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam, ls); break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s) {
+hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, int64_t ls,
+                              hipStream_t s) {
   if (n == 0) return hipSuccess;
   switch (degree) {
-    case 1: hipLaunchKernelGGL(k_adj_deposit<1>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
-    case 2: hipLaunchKernelGGL(k_adj_deposit<2>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
-    default: hipLaunchKernelGGL(k_adj_deposit<3>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam); break;
+    case 1: hipLaunchKernelGGL(k_adj_deposit<1>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam, ls); break;
+    case 2: hipLaunchKernelGGL(k_adj_deposit<2>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam, ls); break;
+    default: hipLaunchKernelGGL(k_adj_deposit<3>, dim3(blocks_for(n)), dim3(256), 0, s, D, sa, lam, ls); break;
   }
   return hipGetLastError();
 }
@@ -635,7 +738,7 @@ hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs
 size_t adj_tiled_lds_bytes(const TileP& tp, bool push) { return (size_t)(push ? 22 : 3) * tp.win_pad * 8; }
 
 hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblocks, size_t lds, StepArgs sa,
-                            double* lam, hipStream_t s) {
+                            double* lam, int64_t ls, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   const void* fn = nullptr;
   if (push)
@@ -647,17 +750,17 @@ hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblock
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (push) {
     switch (degree) {
-      case 1: hipLaunchKernelGGL(k_adj_push_t<1>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam); break;
-      case 2: hipLaunchKernelGGL(k_adj_push_t<2>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam); break;
+      case 1: hipLaunchKernelGGL(k_adj_push_t<1>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam, ls); break;
+      case 2: hipLaunchKernelGGL(k_adj_push_t<2>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam, ls); break;
       default:
-        hipLaunchKernelGGL(k_adj_push_t<3>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam);
+        hipLaunchKernelGGL(k_adj_push_t<3>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam, ls);
         break;
     }
   } else {
     switch (degree) {
-      case 1: hipLaunchKernelGGL(k_adj_deposit_t<1>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
-      case 2: hipLaunchKernelGGL(k_adj_deposit_t<2>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
-      default: hipLaunchKernelGGL(k_adj_deposit_t<3>, dim3(nblocks), dim3(256), lds, s, D, sa, lam); break;
+      case 1: hipLaunchKernelGGL(k_adj_deposit_t<1>, dim3(nblocks), dim3(256), lds, s, D, sa, lam, ls); break;
+      case 2: hipLaunchKernelGGL(k_adj_deposit_t<2>, dim3(nblocks), dim3(256), lds, s, D, sa, lam, ls); break;
+      default: hipLaunchKernelGGL(k_adj_deposit_t<3>, dim3(nblocks), dim3(256), lds, s, D, sa, lam, ls); break;
     }
   }
   return hipGetLastError();

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -203,11 +204,11 @@ TileP plan_tiles(const pic_config_t& c) {
     t.row_lanes <<= 1;
     t.log_row_lanes += 1;
   }
-  // default chunk: the largest of 512, 1024, 2048 particles that still leaves
+  // default chunk: the largest of 512 .. 4096 particles that still leaves
   // at least 8192 chunks (32 per CU) at full capacity; bigger chunks amortise
   // the window load and flush once parallelism is plentiful
   int chunk = 512;
-  while (chunk < 2048 && c.max_particles / (2 * chunk) >= 8192) chunk *= 2;
+  while (chunk < 4096 && c.max_particles / (2 * chunk) >= 8192) chunk *= 2;
   t.chunk = c.chunk ? c.chunk : chunk;
   t.max_work = t.ntiles + ceil_div(c.max_particles, t.chunk);
   return t;
@@ -217,7 +218,7 @@ struct Layout {
   size_t set_bytes;  // one particle set: 11 arrays (cap x es) + ids
   size_t parts, J, T, RB, H, U, F64, F32, twx, twy, tcount, tstart, tcstart, ccount, ccursor, twork, tnwork, tdone,
       trank,
-      LF, LS, LJ, total;
+      LF, LS, LJ, LAM, LAM2, LIDS, LINV, LFLAG, total;
   size_t plane_c;    // complex entries per spectral plane
 };
 
@@ -265,12 +266,19 @@ Layout plan_instance(const pic_config_t& c) {
     L.LF = take(11 * plane_r * 8);
     L.LS = take(11 * L.plane_c * 16);
     L.LJ = take(3 * plane_r * 8);
+    L.LAM = take(11 * cap * 8);
+    L.LAM2 = take(11 * cap * 8);
+    L.LIDS = take(cap * 4);
+    L.LINV = take(cap * 4);
+    L.LFLAG = take(4);
   }
   L.total = o;
   return L;
 }
 
 // context-level buffers ahead of the instances: descriptors and diagnostics
+// diagnostics buffer: the field reduction's six values (16 slots), then 256
+// block partials of the kinetic energy and the non-finite count
 constexpr size_t kDiagDoubles = 16 + 2 * 256;
 size_t head_bytes(int ninst) { return align_up(ninst * sizeof(InstDesc)) + align_up(kDiagDoubles * 8); }
 
@@ -354,6 +362,35 @@ struct Instance {
 
 }  // namespace
 
+
+// ---------------------------------------------------------------------------
+// Saved states (pic_save_state / pic_load_state): a 256-byte header, then per
+// instance its particle count, the current particle set (11 arrays and the
+// original indices, n entries each), the tile metadata of the last sort
+// (tile starts, each tile's first chunk, the chunk list and its length), the
+// spectral history ring and, with the naive current, the background charge
+// plane init_particles computed.
+constexpr uint64_t kStateMagic = 0x70696373746174ull;  // "picstat"
+constexpr int kStateHeaderWords = 16;
+
+namespace {
+
+__global__ void k_state_header(int64_t* h, int64_t a0, int64_t a1, int64_t a2, int64_t a3, int64_t a4, int64_t a5,
+                               int64_t a6, int64_t a7) {
+  if (threadIdx.x == 0) {
+    h[0] = a0;
+    h[1] = a1;
+    h[2] = a2;
+    h[3] = a3;
+    h[4] = a4;
+    h[5] = a5;
+    h[6] = a6;
+    h[7] = a7;
+  }
+}
+
+}  // namespace
+
 struct pic_ctx_s {
   std::vector<Instance> inst;
   int sel = 0;  // instance addressed by the per-instance entry points
@@ -373,6 +410,7 @@ struct pic_ctx_s {
   int cur = 0;       // current particle set
   int moves = 0;     // position updates since the last sort
   bool stepped = false;
+  int64_t lam_n = -1;  // particle count of the held adjoint (-1: none)
   Phase phase = EMPTY;
   std::string err;
 
@@ -712,6 +750,11 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     d.LF = adj ? (double*)(b + in.L.LF) : nullptr;
     d.LS = adj ? (double2*)(b + in.L.LS) : nullptr;
     d.LJ = adj ? (double*)(b + in.L.LJ) : nullptr;
+    d.LAM = adj ? (double*)(b + in.L.LAM) : nullptr;
+    d.LAM2 = adj ? (double*)(b + in.L.LAM2) : nullptr;
+    d.LIDS = adj ? (int32_t*)(b + in.L.LIDS) : nullptr;
+    d.LINV = adj ? (int32_t*)(b + in.L.LINV) : nullptr;
+    d.LFLAG = adj ? (int32_t*)(b + in.L.LFLAG) : nullptr;
     d.naive = (cf.flags & PIC_FLAG_NAIVE_RHO) ? 1 : 0;
     d.jvstar = (cf.flags & PIC_FLAG_JVSTAR) ? 1 : 0;
     {
@@ -1079,9 +1122,10 @@ pic_status_t init_particles(pic_ctx_t c, int64_t n, const double* x, const doubl
     // sort interval from the loaded particles: a position update moves a
     // particle by at most max(|v_x|, |v_y|) dt in x and y, so the window's
     // slack lasts slack / (that / min(dx, dy)) updates; kept between the
-    // speed-of-light interval and twice it (longer intervals let particles
-    // that speed up escape their windows often enough to cost more in the
-    // fused pass than they save in sorts).  A particle that outruns it takes
+    // speed-of-light interval and three times it (longer intervals let
+    // particles that speed up escape their windows, and let the cell order
+    // inside a tile decay, enough to cost more in the fused pass than they
+    // save in sorts).  A particle that outruns it takes
     // the global path until the next sort, so results never depend on it.
     uint32_t* d_vmax = reinterpret_cast<uint32_t*>(c->d_diag);
     uint32_t h_vmax = 0;
@@ -1094,7 +1138,7 @@ pic_status_t init_particles(pic_ctx_t c, int64_t n, const double* x, const doubl
     std::memcpy(&vmax, &h_vmax, sizeof(float));
     const double cells = (double)vmax * in.cfg.dt / std::min(in.d.g.dx, in.d.g.dy);
     const double k = cells > 0 ? std::floor(in.d.tp.slack / cells) : 1e9;
-    in.every = (int)std::max<double>(in.every_worst, std::min<double>(k, 2.0 * in.every_worst));
+    in.every = (int)std::max<double>(in.every_worst, std::min<double>(k, 3.0 * in.every_worst));
   }
   c->sort_every = 64;
   for (const Instance& other : c->inst) c->sort_every = std::min(c->sort_every, other.every);
@@ -1229,6 +1273,196 @@ pic_status_t pic_diagnostics(pic_ctx_t c, double* out) {
   return bad > 0 ? c->fail(PIC_ERR_NONFINITE, "non-finite particle values") : PIC_OK;
 }
 
+pic_status_t pic_set_dirk_tableau(pic_ctx_t c, int32_t stages, const double* A, const double* b,
+                                  const double* cc) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  if (scheme_family(c->scheme) != PIC_SCHEME_DIRK2)
+    return c->fail(PIC_ERR_UNSUPPORTED, "a DIRK tableau needs a DIRK scheme (PIC_SCHEME_DIRK2 or PIC_SCHEME_DIRK3)");
+  if (!A || !b || !cc) return c->fail(PIC_ERR_INVALID_ARG, "A, b and c must be host arrays");
+  const int ns = c->inst[0].d.sc.stages;
+  if (stages != ns)
+    return c->fail(PIC_ERR_INVALID_ARG, "the context's scheme has " + std::to_string(ns) +
+                                            " stages (PIC_SCHEME_DIRK2: 2, PIC_SCHEME_DIRK3: 3)");
+  if (c->phase == DEPOSITED || c->phase == SOLVED)
+    return c->fail(PIC_ERR_STATE, "the tableau changes between steps only (phase READY or no particles yet)");
+  double sb = 0;
+  for (int i = 0; i < ns; ++i) {
+    double row = 0;
+    for (int j = 0; j < ns; ++j) {
+      const double a = A[i * ns + j];
+      if (!std::isfinite(a)) return c->fail(PIC_ERR_INVALID_ARG, "tableau entries must be finite");
+      if (j > i && a != 0.0) return c->fail(PIC_ERR_INVALID_ARG, "A must be lower triangular (a DIRK)");
+      row += a;
+    }
+    if (!(A[i * ns + i] > 0.0)) return c->fail(PIC_ERR_INVALID_ARG, "the diagonal of A must be positive");
+    if (!std::isfinite(b[i]) || !std::isfinite(cc[i])) return c->fail(PIC_ERR_INVALID_ARG, "b and c must be finite");
+    if (std::fabs(cc[i] - row) > 1e-12 * std::max(1.0, std::fabs(row)))
+      return c->fail(PIC_ERR_INVALID_ARG, "c_i must equal the row sums of A");
+    sb += b[i];
+  }
+  if (std::fabs(sb - 1.0) > 1e-12) return c->fail(PIC_ERR_INVALID_ARG, "the weights b must sum to one");
+  for (auto& in : c->inst) {
+    SchemeCoef& sc = in.d.sc;
+    for (int i = 0; i < ns; ++i) {
+      sc.dirkB[i] = b[i];
+      sc.dirkC[i] = cc[i];
+      for (int j = 0; j < ns; ++j) sc.dirkA[i][j] = A[i * ns + j];
+    }
+  }
+  return c->upload_desc();
+}
+
+// byte offsets of one instance's parts inside a saved state
+struct StateLayout {
+  size_t n, parts, ids, start, cstart, work, nwork, hist, rb, end;
+};
+static StateLayout state_layout(pic_ctx_t c, const Instance& in, size_t base) {
+  StateLayout L{};
+  const size_t es = c->dtype == PIC_F32 ? 4 : 8;
+  const size_t cap = (size_t)in.cfg.max_particles;
+  size_t o = base;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.n = take(8);
+  L.parts = take(11 * array_bytes(cap, es));
+  L.ids = take(cap * 4);
+  L.start = take(((size_t)in.d.tp.ntiles + 1) * 4);
+  L.cstart = take((size_t)in.d.tp.ntiles * 4);
+  L.work = take((size_t)in.d.tp.max_work * 16);
+  L.nwork = take(4);
+  L.hist = take((size_t)c->hist.nslots * in.L.plane_c * 16);
+  L.rb = take(in.d.RB ? (size_t)in.cfg.nx * in.cfg.ny * 8 : 0);
+  L.end = o;
+  return L;
+}
+
+size_t pic_state_bytes(pic_ctx_t c) {
+  if (!c) return 0;
+  size_t o = align_up(kStateHeaderWords * 8);
+  for (const auto& in : c->inst) o = state_layout(c, in, o).end;
+  return o;
+}
+
+// the context's fingerprint in a saved state: the workspace layout and the
+// configuration that fix what the bytes mean
+static int64_t state_fingerprint(pic_ctx_t c) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  mix(c->ninst());
+  for (const auto& in : c->inst) {
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(&in.cfg);
+    for (size_t k = 0; k < sizeof(pic_config_t); ++k) mix(b[k]);
+  }
+  return (int64_t)(h & 0x7fffffffffffffffull);
+}
+
+pic_status_t pic_save_state(pic_ctx_t c, void* dst) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  if (!dst || ((uintptr_t)dst & (kAlign - 1))) return c->fail(PIC_ERR_INVALID_ARG, "dst must be a 256-byte aligned device pointer");
+  if (c->phase != READY) return c->fail(PIC_ERR_STATE, "save_state needs phase READY");
+  char* b = static_cast<char*>(dst);
+  hipLaunchKernelGGL(k_state_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(b),
+                     (int64_t)kStateMagic, state_fingerprint(c), c->nupd, c->vflip, c->cur, c->moves,
+                     c->stepped ? 1 : 0, (int64_t)pic_state_bytes(c));
+  pic_status_t st = c->hip(hipGetLastError(), "state header");
+  if (!st) {
+    hipLaunchKernelGGL(k_state_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(b) + 8,
+                       (int64_t)c->sort_every, 0, 0, 0, 0, 0, 0, 0);
+    st = c->hip(hipGetLastError(), "state header");
+  }
+  size_t o = align_up(kStateHeaderWords * 8);
+  const size_t es = c->dtype == PIC_F32 ? 4 : 8;
+  for (auto& in : c->inst) {
+    const StateLayout L = state_layout(c, in, o);
+    const InstDesc& d = in.d;
+    const size_t n = (size_t)d.n;
+    const int64_t nn = d.n;
+    auto cp = [&](size_t off, const void* src, size_t bytes, const char* what) {
+      if (!st && bytes) st = c->hip(hipMemcpyAsync(b + off, src, bytes, hipMemcpyDeviceToDevice, c->stream), what);
+    };
+    if (!st) {
+      hipLaunchKernelGGL(k_state_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(b + L.n), nn,
+                         0, 0, 0, 0, 0, 0, 0);
+      st = c->hip(hipGetLastError(), "state n");
+    }
+    const size_t ab = array_bytes((size_t)in.cfg.max_particles, es);
+    for (int a = 0; a < 11; ++a) cp(L.parts + a * ab, d.set[c->cur][a], n * es, "state particles");
+    cp(L.ids, d.ids[c->cur], n * 4, "state ids");
+    cp(L.start, d.tb.start, ((size_t)d.tp.ntiles + 1) * 4, "state tile starts");
+    cp(L.cstart, d.tb.cstart, (size_t)d.tp.ntiles * 4, "state chunk starts");
+    cp(L.work, d.tb.work, (size_t)d.tp.max_work * 16, "state chunks");
+    cp(L.nwork, d.tb.nwork, 4, "state chunk count");
+    cp(L.hist, d.H, (size_t)c->hist.nslots * in.L.plane_c * 16, "state history");
+    if (d.RB) cp(L.rb, d.RB, (size_t)in.cfg.nx * in.cfg.ny * 8, "state background charge");
+    o = L.end;
+  }
+  return st;
+}
+
+pic_status_t pic_load_state(pic_ctx_t c, const void* src) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  if (!src || ((uintptr_t)src & (kAlign - 1))) return c->fail(PIC_ERR_INVALID_ARG, "src must be a 256-byte aligned device pointer");
+  const char* b = static_cast<const char*>(src);
+  int64_t h[kStateHeaderWords];
+  pic_status_t st = c->hip(hipMemcpyAsync(h, b, sizeof(h), hipMemcpyDeviceToHost, c->stream), "state header read");
+  if (!st) st = c->hip(hipStreamSynchronize(c->stream), "state header sync");
+  if (st) return st;
+  if (h[0] != (int64_t)kStateMagic || h[1] != state_fingerprint(c) || h[7] != (int64_t)pic_state_bytes(c))
+    return c->fail(PIC_ERR_INVALID_ARG, "src is not a state saved by a context of this configuration");
+  std::vector<int64_t> ns(c->ninst());
+  size_t o = align_up(kStateHeaderWords * 8);
+  for (int i = 0; i < c->ninst(); ++i) {
+    const StateLayout L = state_layout(c, c->inst[i], o);
+    if (!st) st = c->hip(hipMemcpyAsync(&ns[i], b + L.n, 8, hipMemcpyDeviceToHost, c->stream), "state n read");
+    o = L.end;
+  }
+  if (!st) st = c->hip(hipStreamSynchronize(c->stream), "state n sync");
+  if (st) return st;
+  const int cur = (int)h[4];
+  const size_t es = c->dtype == PIC_F32 ? 4 : 8;
+  o = align_up(kStateHeaderWords * 8);
+  for (int i = 0; i < c->ninst(); ++i) {
+    Instance& in = c->inst[i];
+    if (ns[i] < 0 || ns[i] > in.cfg.max_particles)
+      return c->fail(PIC_ERR_INVALID_ARG, "src holds a particle count beyond the capacity");
+  }
+  for (int i = 0; i < c->ninst() && !st; ++i) {
+    Instance& in = c->inst[i];
+    const StateLayout L = state_layout(c, in, o);
+    InstDesc& d = in.d;
+    const size_t n = (size_t)ns[i];
+    auto cp = [&](void* dst, size_t off, size_t bytes, const char* what) {
+      if (!st && bytes) st = c->hip(hipMemcpyAsync(dst, b + off, bytes, hipMemcpyDeviceToDevice, c->stream), what);
+    };
+    const size_t ab = array_bytes((size_t)in.cfg.max_particles, es);
+    for (int a = 0; a < 11; ++a) cp(d.set[cur][a], L.parts + a * ab, n * es, "state particles");
+    cp(d.ids[cur], L.ids, n * 4, "state ids");
+    cp(d.tb.start, L.start, ((size_t)d.tp.ntiles + 1) * 4, "state tile starts");
+    cp(d.tb.cstart, L.cstart, (size_t)d.tp.ntiles * 4, "state chunk starts");
+    cp(d.tb.work, L.work, (size_t)d.tp.max_work * 16, "state chunks");
+    cp(d.tb.nwork, L.nwork, 4, "state chunk count");
+    cp(d.H, L.hist, (size_t)c->hist.nslots * in.L.plane_c * 16, "state history");
+    if (d.RB) cp(d.RB, L.rb, (size_t)in.cfg.nx * in.cfg.ny * 8, "state background charge");
+    d.n = ns[i];
+    o = L.end;
+  }
+  if (st) return st;
+  c->nupd = h[2];
+  c->vflip = (int)h[3];
+  c->cur = cur;
+  c->moves = (int)h[5];
+  c->stepped = h[6] != 0;
+  c->sort_every = (int)std::min<int64_t>(std::max<int64_t>(h[8], 1), 64);
+  c->phase = READY;
+  return c->upload_desc();
+}
+
 // ---------------------------------------------------------------------------
 // discrete adjoint (float64 BDF-k, one instance, PIC_FLAG_ADJOINT)
 
@@ -1255,18 +1489,50 @@ pic_status_t adjoint_seed_energy(pic_ctx_t c, double scale, double* lam_hist) {
                 "adjoint seed");
 }
 
+pic_status_t pic_adjoint_set_particles(pic_ctx_t c, const double* lam) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  pic_status_t st = adjoint_check(c, false);
+  if (st) return st;
+  Instance& in = c->I();
+  st = c->hip(launch_lam_set(in.d.n, lam, in.d.LAM, in.cfg.max_particles, in.d.LIDS, c->stream), "adjoint set");
+  c->lam_n = st ? -1 : in.d.n;
+  return st;
+}
+
+pic_status_t pic_adjoint_get_particles(pic_ctx_t c, double* lam) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  pic_status_t st = adjoint_check(c, false);
+  if (st) return st;
+  Instance& in = c->I();
+  if (in.d.n > 0 && !lam) return c->fail(PIC_ERR_INVALID_ARG, "lam is NULL");
+  if (c->lam_n != in.d.n) return c->fail(PIC_ERR_STATE, "no particle adjoint held for the loaded particles");
+  return c->hip(launch_lam_get(in.d.n, in.d.LAM, in.cfg.max_particles, in.d.LIDS, lam, c->stream), "adjoint get");
+}
+
 pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
   if (!c) return PIC_ERR_INVALID_ARG;
   pic_status_t st = adjoint_check(c, true);
   if (st) return st;
   Instance& in = c->I();
-  if (!lam_hist || (in.d.n > 0 && !lam)) return c->fail(PIC_ERR_INVALID_ARG, "lam and lam_hist must be device pointers");
+  if (!lam_hist) return c->fail(PIC_ERR_INVALID_ARG, "lam_hist must be a device pointer");
+  if (lam) {
+    st = pic_adjoint_set_particles(c, lam);
+    if (st) return st;
+  } else if (c->lam_n != in.d.n) {
+    return c->fail(PIC_ERR_STATE, "lam is NULL and no particle adjoint is held for the loaded particles");
+  }
   // recompute x^{n+1}, J^{n+1} and the level-(n+1) fields from the loaded state
   st = particle_pass(c, 0);
   if (!st) st = do_solve(c);
   const InstDesc* D = c->d_desc;
   const int nx = in.cfg.nx, ny = in.cfg.ny;
   const StepArgs sa = c->sargs();
+  const int64_t ls = in.cfg.max_particles;
+  // the held adjoint follows the order of the set the passes run on
+  if (!st)
+    st = c->hip(launch_lam_follow(in.d.n, in.d.ids[c->cur], in.d.LAM, in.d.LAM2, ls, in.d.LIDS, in.d.LINV,
+                                  in.d.LFLAG, c->stream),
+                "adjoint order");
   // the cell-sorted passes when the forward is sorted and the windows fit in LDS
   int max_lds = 0, dev = 0;
   (void)hipGetDevice(&dev);
@@ -1274,16 +1540,18 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
   const size_t lds_push = adj_tiled_lds_bytes(in.d.tp, true), lds_dep = adj_tiled_lds_bytes(in.d.tp, false);
   const bool tiled = c->sorted && lds_push <= (size_t)max_lds;
   if (!st)
-    st = c->hip(tiled ? launch_adj_tiled(true, c->degree, D, c->nblk[BK_WORK], lds_push, sa, lam, c->stream)
-                      : launch_adj_push(c->degree, D, in.d.n, sa, lam, c->stream),
+    st = c->hip(tiled ? launch_adj_tiled(true, c->degree, D, c->nblk[BK_WORK], lds_push, sa, in.d.LAM, ls, c->stream)
+                      : launch_adj_push(c->degree, D, in.d.n, sa, in.d.LAM, ls, c->stream),
                 "adjoint push");
   if (!st) st = c->hip(launch_rows_r2c(D, 1, 11 * (ny / in.d.R_r2c), c->lds_r2c, c->stream, true), "adjoint rows_r2c");
   if (!st) st = c->hip(launch_adj_columns(in.cfg.bdf_order, D, nx / 2 + 1, c->lds_adj_col, lam_hist, c->stream), "adjoint columns");
   if (!st) st = c->hip(launch_rows_c2r(D, 1, 2 * (ny / in.d.R_c2r), c->lds_c2r, c->stream, true), "adjoint rows_c2r");
   if (!st)
-    st = c->hip(tiled ? launch_adj_tiled(false, c->degree, D, c->nblk[BK_WORK], lds_dep, sa, lam, c->stream)
-                      : launch_adj_deposit(c->degree, D, in.d.n, sa, lam, c->stream),
+    st = c->hip(tiled ? launch_adj_tiled(false, c->degree, D, c->nblk[BK_WORK], lds_dep, sa, in.d.LAM, ls, c->stream)
+                      : launch_adj_deposit(c->degree, D, in.d.n, sa, in.d.LAM, ls, c->stream),
                 "adjoint deposit");
+  if (!st && lam) st = pic_adjoint_get_particles(c, lam);
+  if (st) c->lam_n = -1;
   c->phase = st ? EMPTY : SOLVED;
   return st;
 }

@@ -220,7 +220,12 @@ struct InstDesc {
   const double2* twy;
   double* LF;               // adjoint buffers (PIC_FLAG_ADJOINT, else null): [11][ny][nx] mesh-field adjoints,
   double2* LS;              // [11][nxh][ny] their x-transforms (planes 0..2 reused for the J adjoint columns),
-  double* LJ;               // [3][ny][nx] adjoint of J
+  double* LJ;               // [3][ny][nx] adjoint of J,
+  double* LAM;              // [11][capacity] the held particle adjoint in slot order, LAM2 its permutation buffer,
+  double* LAM2;
+  int32_t* LIDS;            // [capacity] the original particle of each LAM slot, LINV its inverse,
+  int32_t* LINV;
+  int32_t* LFLAG;           // set when the particle order differs from LIDS
   double* RB;               // naive charge deposit (PIC_FLAG_NAIVE_RHO, else null): [ny][nx] ion background
   int naive;                // 1: J holds a fourth plane, the deposited rho; T a fourth component
   int jvstar;               // 1: J carries v* = 2 v - v_prev (PIC_FLAG_JVSTAR)
@@ -327,13 +332,19 @@ hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds
 hipError_t launch_hist_transpose(const double2* src, double2* dst, int nfield, GridP g, bool to_external,
                                  hipStream_t s);
 // adjoint.hip (one float64 BDF-k instance; D[0])
-hipError_t launch_adj_push(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s);
-hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, hipStream_t s);
+hipError_t launch_adj_push(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, int64_t ls,
+                           hipStream_t s);
+hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, int64_t ls,
+                              hipStream_t s);
+hipError_t launch_lam_set(int64_t n, const double* src, double* LAM, int64_t ls, int32_t* LIDS, hipStream_t s);
+hipError_t launch_lam_get(int64_t n, const double* LAM, int64_t ls, const int32_t* LIDS, double* dst, hipStream_t s);
+hipError_t launch_lam_follow(int64_t n, const int32_t* ids, double* LAM, double* LAM2, int64_t ls, int32_t* LIDS,
+                             int32_t* LINV, int32_t* flag, hipStream_t s);
 // cell-sorted variants over the forward's chunks (push: mesh fields and their
 // adjoints in LDS windows; deposit: lambda_J window)
 size_t adj_tiled_lds_bytes(const TileP& tp, bool push);
 hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblocks, size_t lds, StepArgs sa,
-                            double* lam, hipStream_t s);
+                            double* lam, int64_t ls, hipStream_t s);
 hipError_t launch_adj_columns(int bdf_order, const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s);
 hipError_t launch_adj_seed_energy(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double scale,
                                   double* lam_hist, int nf, hipStream_t s);

@@ -43,7 +43,9 @@ EXPORTS = ("pic_workspace_bytes", "pic_create", "pic_destroy", "pic_last_error",
            "pic_get_history", "pic_set_history", "pic_diagnostics", "pic_set_kernel_timing",
            "pic_kernel_timing", "pic_batch_workspace_bytes", "pic_batch_create",
            "pic_instance_count", "pic_select_instance", "step_batched", "adjoint_seed_energy",
-           "step_adjoint", "adjoint_initial", "pic_graph_period")
+           "step_adjoint", "adjoint_initial", "pic_graph_period",
+           "pic_set_dirk_tableau", "pic_state_bytes", "pic_save_state", "pic_load_state",
+           "pic_adjoint_set_particles", "pic_adjoint_get_particles")
 KCLASSES = ("deposit", "field_solve", "gather_push", "fused", "sort")
 
 
@@ -96,6 +98,12 @@ def load():
         "pic_get_history": (I32, [P, P]),
         "pic_set_history": (I32, [P, P]),
         "pic_diagnostics": (I32, [P, ctypes.POINTER(D)]),
+        "pic_set_dirk_tableau": (I32, [P, I32, P, P, P]),
+        "pic_state_bytes": (SZ, [P]),
+        "pic_save_state": (I32, [P, P]),
+        "pic_load_state": (I32, [P, P]),
+        "pic_adjoint_set_particles": (I32, [P, P]),
+        "pic_adjoint_get_particles": (I32, [P, P]),
         "pic_set_kernel_timing": (I32, [P, I32]),
         "pic_kernel_timing": (I32, [P, ctypes.POINTER(D)]),
         "pic_batch_workspace_bytes": (SZ, [cfgp, I32]),
@@ -316,6 +324,40 @@ def diagnostics(ctx, allow_nonfinite=False):
     return dict(zip(DIAG_NAMES, list(buf)))
 
 
+class State:
+    """A device buffer holding one saved state of a context (pic_save_state)."""
+
+    def __init__(self, ctx):
+        nbytes = load().pic_state_bytes(ctx.handle)
+        self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
+        self.ptr = ctypes.c_void_p(self.buf.data_ptr() + (-self.buf.data_ptr()) % 256)
+        self.ns = None
+
+
+def save_state(ctx, state=None):
+    """Save the context's state (phase READY) into `state` (a new State if None)."""
+    state = state or State(ctx)
+    ctx.check(load().pic_save_state(ctx.handle, state.ptr))
+    state.ns = list(ctx.ns)
+    return state
+
+
+def load_state(ctx, state):
+    ctx.check(load().pic_load_state(ctx.handle, state.ptr))
+    ctx.ns = list(state.ns)
+
+
+def set_dirk_tableau(ctx, A, b, c):
+    """Replace the DIRK tableau (A: s x s lower triangular, b, c: length s;
+    host values)."""
+    import numpy as np
+    A = np.ascontiguousarray(A, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    c = np.ascontiguousarray(c, np.float64)
+    ctx.check(load().pic_set_dirk_tableau(ctx.handle, b.shape[0], ctypes.c_void_p(A.ctypes.data),
+                                          ctypes.c_void_p(b.ctypes.data), ctypes.c_void_p(c.ctypes.data)))
+
+
 def set_kernel_timing(ctx, enable=True):
     ctx.check(load().pic_set_kernel_timing(ctx.handle, 1 if enable else 0))
 
@@ -336,11 +378,28 @@ def adjoint_seed_energy(ctx, scale=1.0):
 
 
 def step_adjoint(ctx, lam, lam_hist):
-    """lambda^{n+1} -> lambda^n in place; the context must hold S^n (phase READY)."""
-    assert lam.dtype == torch.float64 and lam.is_contiguous() and lam.shape == (11, ctx.n)
+    """lambda^{n+1} -> lambda^n in place; the context must hold S^n (phase READY).
+    lam None: the particle adjoint the context holds (adjoint_set_particles)."""
+    if lam is not None:
+        assert lam.dtype == torch.float64 and lam.is_contiguous() and lam.shape == (11, ctx.n)
     assert lam_hist.dtype == torch.complex128 and lam_hist.is_contiguous()
     assert lam_hist.shape == (history_fields(ctx.cfgs[ctx.sel]), ctx.ny, ctx.nx // 2 + 1)
-    ctx.check(load().step_adjoint(ctx.handle, _ptr(lam), _ptr(lam_hist)))
+    ctx.check(load().step_adjoint(ctx.handle, None if lam is None else _ptr(lam), _ptr(lam_hist)))
+
+
+def adjoint_set_particles(ctx, lam=None):
+    """Hold lam [11, n] (original order; None: zero) as the context's particle adjoint."""
+    if lam is not None:
+        assert lam.dtype == torch.float64 and lam.is_contiguous() and lam.shape == (11, ctx.n)
+        ctx._inputs = (lam,)
+    ctx.check(load().pic_adjoint_set_particles(ctx.handle, None if lam is None else _ptr(lam)))
+
+
+def adjoint_get_particles(ctx):
+    """The held particle adjoint as [11, n] float64 in original order."""
+    out = torch.empty((11, ctx.n), dtype=torch.float64, device=ctx.device)
+    ctx.check(load().pic_adjoint_get_particles(ctx.handle, _ptr(out)))
+    return out
 
 
 def adjoint_initial(ctx, P0, lam):

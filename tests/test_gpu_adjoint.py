@@ -133,6 +133,45 @@ def test_checkpointed_equals_store_all(gpu_lib):
             assert rel(a, b) <= 1e-12
 
 
+def test_held_adjoint_equals_explicit_across_sorts(gpu_lib):
+    """The particle adjoint held in slot order (permuted when a sort changes
+    the order) equals the one passed in original order at every step, over a
+    sweep whose states straddle several sorts (sort interval 2)."""
+    pic = gpu_lib
+    w = _weibel(nx=32, ny=32, ppc=4, seed=47)
+    n = w["x"].shape[0]
+    cfg = pic.make_config(w["nx"], w["ny"], w["lx"], w["ly"], w["dt"], degree=3, scheme="bdf", bdf_order=2,
+                          dtype="f64", q=w["q"], m=w["m"], max_particles=n + 5, flags=pic.FLAG_ADJOINT,
+                          sort_interval=2)
+    ctx = pic.Context(cfg)
+    pic.init_particles(ctx, _dev(w["x"]), _dev(w["y"]), _dev(w["P"].T))
+    states = []
+    for _ in range(7):
+        states.append(pic.save_state(ctx))
+        pic.step(ctx, 1)
+    seed_h = pic.adjoint_seed_energy(ctx, 1.0)
+    g = torch.Generator().manual_seed(5)
+    lam0 = torch.randn((11, n), generator=g, dtype=torch.float64).to("cuda")
+    lam_e, h_e = lam0.clone(), seed_h.clone()
+    for st in reversed(states):
+        pic.load_state(ctx, st)
+        pic.step_adjoint(ctx, lam_e, h_e)
+    pic.adjoint_set_particles(ctx, lam0)
+    h_h = seed_h.clone()
+    for st in reversed(states):
+        pic.load_state(ctx, st)
+        pic.step_adjoint(ctx, None, h_h)
+    lam_h = pic.adjoint_get_particles(ctx)
+    assert rel(lam_h.cpu().numpy(), lam_e.cpu().numpy()) <= 1e-12
+    assert rel(h_h.cpu().numpy(), h_e.cpu().numpy()) <= 1e-12
+    # nothing held for another particle count
+    pic.init_particles(ctx, _dev(w["x"][:-3]), _dev(w["y"][:-3]), _dev(w["P"][:-3].T))
+    with pytest.raises(pic.PicError):
+        pic.adjoint_get_particles(ctx)
+    with pytest.raises(pic.PicError):
+        pic.step_adjoint(ctx, None, h_h)
+
+
 def test_adjoint_rejects_unsupported_contexts(gpu_lib):
     pic = gpu_lib
     w = _weibel(nx=16, ny=16, ppc=2, seed=5)

@@ -373,3 +373,67 @@ def test_dirk3_dispersion():
     np.testing.assert_allclose(out["vphi"][MODE[1], MODE[0]], 1j * om * z ** n, rtol=1e-10)
     np.testing.assert_allclose(out["A"][0][0][MODE[1], MODE[0]], z ** n, rtol=1e-10)
     assert abs(abs(z) - 1) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# general s-stage DIRK tableaux (Sec. 3.3 states the method for any tableau)
+
+def sdirk(s):
+    """Alexander's singly diagonally implicit tableau of `s` stages from the
+    golden expressions (gamma: 1 - 1/sqrt(2), or the root in (1/6, 1/2) of
+    6 g^3 - 18 g^2 + 9 g - 1)."""
+    if s == 2:
+        g = 1.0 - 1.0 / np.sqrt(2.0)
+    else:
+        r = np.roots([6.0, -18.0, 9.0, -1.0])
+        g = float(next(x.real for x in r if abs(x.imag) < 1e-12 and 1 / 6 < x.real < 0.5))
+    ev = lambda e: float(eval(e, {"g": g}))  # noqa: E731  (arithmetic of g only)
+    t = GOLD["sdirk_alexander"][str(s)]
+    return (np.array([[ev(e) for e in row] for row in t["A"]]), np.array([ev(e) for e in t["b"]]),
+            np.array([ev(e) for e in t["c"]]))
+
+
+def _R(A, b, z):
+    """Stability function R(z) = 1 + z b^T (I - z A)^{-1} 1."""
+    return 1.0 + z * b @ np.linalg.solve(np.eye(len(b)) - z * A, np.ones(len(b)))
+
+
+@pytest.mark.parametrize("s", [2, 3])
+def test_sdirk_tableaux_order_and_stability(s):
+    """The golden tableaux are what they claim: consistent (c = row sums),
+    of order s (order conditions up to s), L-stable (R -> 0 at -infinity,
+    |R| <= 1 on the imaginary axis) -- and, unlike the symplectic
+    compositions, dissipative (|R(i theta)| < 1)."""
+    A, b, c = sdirk(s)
+    np.testing.assert_allclose(A.sum(1), c, atol=1e-15)
+    assert abs(b.sum() - 1) < 1e-15 and abs(b @ c - 0.5) < 1e-15
+    if s == 3:
+        assert abs(b @ c ** 2 - 1 / 3) < 1e-14 and abs(b @ A @ c - 1 / 6) < 1e-14
+    assert abs(_R(A, b, -1e9)) < 1e-6
+    for th in (0.1, 1.0, 3.0):
+        assert abs(_R(A, b, 1j * th)) < 1.0
+
+
+@pytest.mark.parametrize("s", [2, 3])
+def test_general_dirk_dispersion(s):
+    """The oracle with a non-composed tableau: the eigen-solution (u, v) =
+    (1, i omega) of the source-free wave equation, omega = c |k|, returns
+    R(i theta)^n after 100 steps, R from the matrix form of the stability
+    function (not the oracle's stage-by-stage recursion)."""
+    A, b, c = sdirk(s)
+    p = pic.Params(16, 16, 1.6, 1.2, 3, "dirk2" if s == 2 else "dirk3", 0.07, c=C_LIGHT, eps0=1.0,
+                   mu0=1.0 / C_LIGHT ** 2, dirk_tableau=(A, b, c))
+    th = _theta(p)
+    om = th / p.dt
+    z = _R(A, b, 1j * th)
+    hist = pic.cold_history(p)
+    hist["phi"] = [_mode_field(p, 1.0), _mode_field(p, 0.0)]
+    hist["vphi"] = _mode_field(p, 1j * om)
+    hist["A"] = [np.stack([_mode_field(p, 1.0)] * 3), np.zeros((3,) + p.spec_shape, complex)]
+    hist["vA"] = np.stack([_mode_field(p, 1j * om)] * 3)
+    n = 100
+    out = _run(p, hist, n)
+    np.testing.assert_allclose(out["phi"][0][MODE[1], MODE[0]], z ** n, rtol=1e-10)
+    np.testing.assert_allclose(out["vphi"][MODE[1], MODE[0]], 1j * om * z ** n, rtol=1e-10)
+    np.testing.assert_allclose(out["A"][0][2][MODE[1], MODE[0]], z ** n, rtol=1e-10)
+    assert abs(z) < 1.0

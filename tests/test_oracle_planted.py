@@ -159,3 +159,10 @@ def test_curl_index_slip_fails_energy(monkeypatch):
     monkeypatch.setattr(adjoint, "energy", patched)
     with pytest.raises(AssertionError):
         E.test_autograd_energy_closed_form(2)
+
+
+def test_ignored_dirk_tableau_fails_dispersion(monkeypatch):
+    """A general tableau silently replaced by the scheme's own."""
+    monkeypatch.setattr(pic.Params, "tableau", lambda self: schemes.dirk_tableau(self.scheme))
+    with pytest.raises(AssertionError):
+        F.test_general_dirk_dispersion(2)
