@@ -760,23 +760,23 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     {
       // fixed-point deposit exponent (float32 particles): the largest single
       // contribution B = |q| c max(w) / (dx dy), max(w) = M_deg(0)^2, |v| < c
-      // (3c for v*); B = m 2^p with m in [0.5, 1) gives B 2^(29 - p) < 2^29
+      // (3c for v*); B = m 2^p with m in [0.5, 1) gives B 2^(30 - p) < 2^30
       static const double m0[6] = {0.0, 1.0, 0.75, 2.0 / 3.0, 115.0 / 192.0, 0.55};
       const double B = std::fabs(cf.q) * cf.c * (d.jvstar ? 3.0 : 1.0) * g.inv_area * m0[cf.spline_degree] *
                        m0[cf.spline_degree];
       int p = 0;
       const bool ok = B > 0 && std::isfinite(B);
       if (ok) std::frexp(B, &p);
-      d.qe0 = ok ? 29 - p : 0;
+      d.qe0 = ok ? 30 - p : 0;
       // deterministic deposit: one scale for every contribution of the
       // instance.  Float32: the window scale of a full chunk (a chunk's sum
-      // below 2^29, so int64 sums of every chunk cannot overflow).  Float64:
+      // below 2^30, so int64 sums of every chunk cannot overflow).  Float64:
       // capacity x B 2^e < 2^62 bounds every int64 sum, window or global.
       d.det = (cf.flags & PIC_FLAG_DETERMINISTIC) ? 1 : 0;
       int cl2_chunk = 0, cl2_cap = 0;
       while ((1 << cl2_chunk) < d.tp.chunk) ++cl2_chunk;
       while (((int64_t)1 << cl2_cap) < cf.max_particles) ++cl2_cap;
-      int e = cf.particle_dtype == PIC_F32 ? d.qe0 - std::max(cl2_chunk, 8) : (ok ? 62 - p - cl2_cap : 0);
+      int e = cf.particle_dtype == PIC_F32 ? d.qe0 - std::max(cl2_chunk, 9) : (ok ? 62 - p - cl2_cap : 0);
       e = cf.particle_dtype == PIC_F32 ? std::max(-100, std::min(100, e)) : std::max(-1000, std::min(1000, e));
       d.qe_det = e;
       d.det_scale = std::ldexp(1.0, e);

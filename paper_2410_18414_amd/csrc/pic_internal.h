@@ -229,7 +229,7 @@ struct InstDesc {
   double* RB;               // naive charge deposit (PIC_FLAG_NAIVE_RHO, else null): [ny][nx] ion background
   int naive;                // 1: J holds a fourth plane, the deposited rho; T a fourth component
   int jvstar;               // 1: J carries v* = 2 v - v_prev (PIC_FLAG_JVSTAR)
-  int qe0;                  // float32 fixed-point deposit: B 2^qe0 < 2^29 for the contribution bound B
+  int qe0;                  // float32 fixed-point deposit: B 2^qe0 < 2^30 for the contribution bound B
   int det;                  // 1: deterministic deposit (PIC_FLAG_DETERMINISTIC): J planes hold int64 at scale 2^qe_det
   int qe_det;               // that scale's exponent (float32: every chunk's window scale too)
   double det_scale, det_unscale;  // 2^qe_det, 2^-qe_det

@@ -523,9 +523,10 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   // of int32 in a 64-bit integer atomic, J_z in a 32-bit one (two LDS atomics
   // per node instead of three float64 ones).  The scale is a power of two
   // 2^e chosen per chunk: every contribution is bounded by B = |q| c max(w) /
-  // (dx dy) (|v| < c; 3c for |2 v - v_prev|), and B 2^qe0 < 2^29 (qe0 from the
-  // host, d.qe0), so with e = qe0 - max(ceil(log2 count), 8) a node's sum over
-  // the chunk stays below 2^29 and a single contribution below 2^21.
+  // (dx dy) (|v| < c; 3c for |2 v - v_prev|), and B 2^qe0 < 2^30 (qe0 from the
+  // host, d.qe0), so with e = qe0 - max(ceil(log2 count), 9) a node's sum over
+  // the chunk stays below 2^30 (each packed half decodes for |sum| < 2^31) and
+  // a single contribution below 2^21 (the rounding FMA needs below 2^22).
   unsigned long long* jxy_w = reinterpret_cast<unsigned long long*>(jw);     // [JWP]
   uint32_t* jz_w = reinterpret_cast<uint32_t*>(jw + JWP);                      // [JWP]
   float qscale = 1.0f;
@@ -533,7 +534,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   if (FIXEDPT) {
     const int lz = it.z > 1 ? 32 - __clz(it.z - 1) : 0;  // ceil(log2 count)
     // deterministic deposit: the instance's fixed scale (that of a full chunk)
-    int e = det ? d.qe_det : d.qe0 - (lz > 8 ? lz : 8);
+    int e = det ? d.qe_det : d.qe0 - (lz > 9 ? lz : 9);
     e = e > 100 ? 100 : (e < -100 ? -100 : e);  // a normal float scale, whatever q, c and the cell area
     qscale = __int_as_float((e + 127) << 23);
     inv_qscale = __longlong_as_double((long long)(1023 - e) << 52);

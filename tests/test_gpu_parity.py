@@ -338,8 +338,8 @@ def test_quartic_quintic_trajectory(gpu_lib, degree, scheme, k, dtype, flags):
 
 def test_sort_interval_follows_inplane_speed(gpu_lib):
     """With sort_interval 0 the interval comes from the loaded particles'
-    largest in-plane velocity: particles at rest get twice the speed-of-light
-    interval, particles at 0.95c in x get the speed-of-light one (the graph
+    largest in-plane velocity: particles at rest get three times the speed-of-
+    light interval, particles at 0.95c in x get the speed-of-light one (the graph
     period, two sort intervals rounded to the history rings, shows it); the
     slow run still matches the oracle."""
     w = cloud_small(seed=71)
@@ -349,7 +349,7 @@ def test_sort_interval_follows_inplane_speed(gpu_lib):
     gc = make_gpu(cold, 2, "bdf", "f64", bdf_order=2)
     gh = make_gpu(hot, 2, "bdf", "f64", bdf_order=2)
     # speed-of-light interval: slack 3 cells / (c dt / dx) = 6 steps here
-    assert pic.graph_period(gh) == 12 and pic.graph_period(gc) == 24, (pic.graph_period(gh), pic.graph_period(gc))
+    assert pic.graph_period(gh) == 12 and pic.graph_period(gc) == 36, (pic.graph_period(gh), pic.graph_period(gc))
     o = make_oracle(hot, 2, "bdf", 2)
     o.step(30)
     pic.step(gh, 30)
