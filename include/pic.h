@@ -286,6 +286,24 @@ pic_status_t pic_diagnostics(pic_ctx_t ctx, double* out);
 pic_status_t pic_set_dirk_tableau(pic_ctx_t ctx, int32_t stages, const double* A, const double* b,
                                   const double* c);
 
+/* Diagnostics of every instance, for callers that cannot allocate device
+ * memory or synchronise (code under HIP graph capture, serving loops): the
+ * values of pic_diagnostics for each instance i of the context (the selected
+ * one alone for a plain context) are written to the DEVICE array
+ * out[i * PIC_DIAG_COUNT + k], in the pic_diagnostics order, by kernels
+ * enqueued on the context's stream; nothing is synchronised, no device memory
+ * is allocated and no host buffer is touched (results are valid once the
+ * stream has synchronised; a non-finite particle shows in out[i*8 + 7], and
+ * the call itself returns PIC_OK).  The reduction partials live in a fixed
+ * scratch array of the library, PIC_DIAG_ALL_MAX instances x 528 doubles
+ * (270 KB), one copy per GPU the library runs on, held until the process
+ * ends; contexts with more instances get PIC_ERR_INVALID_ARG.  Every call on
+ * one GPU shares that GPU's scratch: calls that overlap in time on one GPU
+ * (from two streams or two host threads) race and may return each other's
+ * values; calls ordered on one stream do not. */
+#define PIC_DIAG_ALL_MAX 64
+pic_status_t pic_diagnostics_all(pic_ctx_t ctx, double* out);
+
 /* ---- Ensembles (batched instances) ----------------------------------------
  * A context may hold ninst independent instances of the method: an ensemble
  * of uneven workloads (different grids, particle counts, time steps).  They must share scheme, bdf_order, particle_dtype, spline_degree,

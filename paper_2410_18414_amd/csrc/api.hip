@@ -362,6 +362,53 @@ struct Instance {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of pic_diagnostics_all: the per-instance reduction partials (the
+// field reduction's six values, then 256 block partials of the kinetic energy
+// and the non-finite count) of at most kDiagAllMax instances, in a
+// file-scope device array.  Each GPU the library runs on holds its own copy
+// until the process ends.  In host code the array's name is not a device
+// address: host code uses only the address hipGetSymbolAddress returns for
+// the current device, looked up once per device (scratch_on).
+constexpr int kDiagAllMax = 64;
+static __device__ __align__(256) double scratch[kDiagAllMax * kDiagDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[kMaxDevices] = {};
+
+// scratch's address on device dev (which must be current); nullptr on failure
+double* scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch[dev];
+}
+
+// out[i][0..5] = instance i's field values, out[i][6] = its kinetic energy,
+// out[i][7] = its non-finite count: the block partials summed in block order,
+// as pic_diagnostics sums them on the host
+__global__ void k_diag_finalize(const double* __restrict__ part, int ninst, double* __restrict__ out) {
+  const int i = blockIdx.x;
+  if (i >= ninst || threadIdx.x != 0) return;
+  const double* p = part + (size_t)i * kDiagDoubles;
+  for (int k = 0; k < 6; ++k) out[i * PIC_DIAG_COUNT + k] = p[k];
+  double ke = 0, bad = 0;
+  for (int b = 0; b < 256; ++b) {
+    ke += p[16 + 2 * b];
+    bad += p[16 + 2 * b + 1];
+  }
+  out[i * PIC_DIAG_COUNT + 6] = ke;
+  out[i * PIC_DIAG_COUNT + 7] = bad;
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // Saved states (pic_save_state / pic_load_state): a 256-byte header, then per
@@ -399,6 +446,7 @@ struct pic_ctx_s {
   Hist hist{};
   InstDesc* d_desc = nullptr;
   double* d_diag = nullptr;
+  double* d_scratch = nullptr;  // scratch's address on the context's device
   int nblk[BK_NKINDS] = {0};
   size_t lds_r2c = 0, lds_c2r = 0, lds_col = 0, lds_adj_col = 0, lds_tiled[3] = {0, 0, 0};
   int dtype = 0, degree = 3, scheme = 0;
@@ -669,7 +717,13 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     g_err = "hipDeviceGetAttribute (LDS per block) failed";
     return PIC_ERR_HIP;
   }
+  double* scr = scratch_on(dev);
+  if (!scr) {
+    g_err = "hipGetSymbolAddress of the diagnostics scratch failed";
+    return PIC_ERR_HIP;
+  }
   auto* c = new pic_ctx_s();
+  c->d_scratch = scr;
   c->stream = (hipStream_t)hip_stream;
   c->ws = (char*)workspace;
   c->hist = plan_history(cfgs[0]);
@@ -1461,6 +1515,27 @@ pic_status_t pic_load_state(pic_ctx_t c, const void* src) {
   c->sort_every = (int)std::min<int64_t>(std::max<int64_t>(h[8], 1), 64);
   c->phase = READY;
   return c->upload_desc();
+}
+
+pic_status_t pic_diagnostics_all(pic_ctx_t c, double* out) {
+  if (!c) return PIC_ERR_INVALID_ARG;
+  if (!out) return c->fail(PIC_ERR_INVALID_ARG, "out is NULL");
+  const int n = c->ninst();
+  if (n > kDiagAllMax)
+    return c->fail(PIC_ERR_INVALID_ARG, "pic_diagnostics_all covers at most " + std::to_string(kDiagAllMax) +
+                                            " instances (the context holds " + std::to_string(n) + ")");
+  const HistSlots hs = slots_of(c->hist, c->nupd);
+  for (int i = 0; i < n; ++i) {
+    const InstDesc& d = c->inst[i].d;
+    double* p = c->d_scratch + (size_t)i * kDiagDoubles;
+    pic_status_t st = c->hip(launch_field_diag(d.H, d.g, d.sc, hs, p, c->stream), "field diag");
+    if (st) return st;
+    auto pa = parts_of(c, d, c->cur);
+    st = c->hip(launch_particle_diag(c->dtype, &pa, d.n, d.ph, p + 16, c->stream), "particle diag");
+    if (st) return st;
+  }
+  hipLaunchKernelGGL(k_diag_finalize, dim3(n), dim3(64), 0, c->stream, c->d_scratch, n, out);
+  return c->hip(hipGetLastError(), "diag finalize");
 }
 
 // ---------------------------------------------------------------------------

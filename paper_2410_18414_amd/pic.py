@@ -31,6 +31,7 @@ FLAG_DIRK_SUBSTEP = 64  # DIRK stage currents from particles sub-stepped to each
 FLAG_DETERMINISTIC = 128  # J summed in int64 at a fixed scale: runs repeat bit for bit
 FIELD_J = 0
 FIELD_MESH = 1
+DIAG_ALL_MAX = 64  # instances pic_diagnostics_all covers (its scratch size)
 DIAG_NAMES = ("gauge_l2", "gauge_scale", "gauss_l2", "gauss_scale", "charge", "energy",
               "kinetic", "nonfinite")
 STATUS = {0: "PIC_OK", 1: "PIC_ERR_INVALID_ARG", 2: "PIC_ERR_UNSUPPORTED", 3: "PIC_ERR_WORKSPACE",
@@ -43,7 +44,7 @@ EXPORTS = ("pic_workspace_bytes", "pic_create", "pic_destroy", "pic_last_error",
            "pic_get_history", "pic_set_history", "pic_diagnostics", "pic_set_kernel_timing",
            "pic_kernel_timing", "pic_batch_workspace_bytes", "pic_batch_create",
            "pic_instance_count", "pic_select_instance", "step_batched", "adjoint_seed_energy",
-           "step_adjoint", "adjoint_initial", "pic_graph_period",
+           "step_adjoint", "adjoint_initial", "pic_graph_period", "pic_diagnostics_all",
            "pic_set_dirk_tableau", "pic_state_bytes", "pic_save_state", "pic_load_state",
            "pic_adjoint_set_particles", "pic_adjoint_get_particles")
 KCLASSES = ("deposit", "field_solve", "gather_push", "fused", "sort")
@@ -98,6 +99,7 @@ def load():
         "pic_get_history": (I32, [P, P]),
         "pic_set_history": (I32, [P, P]),
         "pic_diagnostics": (I32, [P, ctypes.POINTER(D)]),
+        "pic_diagnostics_all": (I32, [P, P]),
         "pic_set_dirk_tableau": (I32, [P, I32, P, P, P]),
         "pic_state_bytes": (SZ, [P]),
         "pic_save_state": (I32, [P, P]),
@@ -356,6 +358,15 @@ def set_dirk_tableau(ctx, A, b, c):
     c = np.ascontiguousarray(c, np.float64)
     ctx.check(load().pic_set_dirk_tableau(ctx.handle, b.shape[0], ctypes.c_void_p(A.ctypes.data),
                                           ctypes.c_void_p(b.ctypes.data), ctypes.c_void_p(c.ctypes.data)))
+
+
+def diagnostics_all(ctx):
+    """pic_diagnostics of every instance into a device tensor [ninst, 8] (the
+    DIAG_NAMES order), enqueued on the context's stream without allocation in
+    the library and without synchronisation."""
+    out = torch.empty((instance_count(ctx), 8), dtype=torch.float64, device=ctx.device)
+    ctx.check(load().pic_diagnostics_all(ctx.handle, _ptr(out)))
+    return out
 
 
 def set_kernel_timing(ctx, enable=True):
