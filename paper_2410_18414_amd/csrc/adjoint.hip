@@ -260,10 +260,7 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
   adj_load_window(fw, F, 11, a, g);
   for (int t = threadIdx.x; t < 11 * WP; t += blockDim.x) lw[t] = 0.0;
   __syncthreads();
-  // lanes of one cell (neighbours in the cell-sorted order) scatter in a
-  // rotated node order: different window addresses at each atomic
   const int lane = threadIdx.x & 63;
-  const int ra = lane % NW, rb = (lane / NW) % NW;
   for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
     const LamRef lam{lamb, ls, (uint32_t)k};
     const double xi = elt(p.x, k) * g.inv_dx, eta = elt(p.y, k) * g.inv_dy;
@@ -288,24 +285,34 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
     double lg[11];
     adj_push_one(gv, gdx, gdy, elt(p.P[0], k), elt(p.P[1], k), elt(p.P[2], k), elt(p.v[0], k), elt(p.v[1], k),
                  elt(p.v[2], k), elt(p.w[0], k), elt(p.w[1], k), elt(p.w[2], k), ph, g, lam, lg);
+    // the scatter visits its stencil in the residue-class order of the
+    // forward deposit: at step (a, b) lane l adds to the node whose absolute
+    // indices are congruent to (a + l, b + l / NW) modulo NW, so at most
+    // 64 / NW^2 lanes meet on one window address, whatever cells the wave's
+    // particles are in
+    const int ra = ((lane - sx) % NW + NW) % NW, rb = ((lane / NW - sy) % NW + NW) % NW;
+    double wxr[NW], wyr[NW];
+    int coff[NW], roff[NW];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) {
+      int ia = t + ra, ib = t + rb;
+      ia = ia >= NW ? ia - NW : ia;
+      ib = ib >= NW ? ib - NW : ib;
+      wxr[t] = wx[t];
+      wyr[t] = wy[t];
+      coff[t] = ia;
+      roff[t] = ib * W;
+    }
+    rotate_lanes<NW>(wxr, ra);
+    rotate_lanes<NW>(wyr, rb);
     if (inw) {
       double* nd0 = lw + ly * W + lx;
 #pragma unroll
       for (int tb = 0; tb < NW; ++tb) {
-        int bb = tb + rb;
-        bb = bb >= NW ? bb - NW : bb;
-        double vb = wy[0];
-#pragma unroll
-        for (int u = 1; u < NW; ++u) vb = bb == u ? wy[u] : vb;
 #pragma unroll
         for (int ta = 0; ta < NW; ++ta) {
-          int aa = ta + ra;
-          aa = aa >= NW ? aa - NW : aa;
-          double va = wx[0];
-#pragma unroll
-          for (int u = 1; u < NW; ++u) va = aa == u ? wx[u] : va;
-          const double w = va * vb;
-          double* nd = nd0 + bb * W + aa;
+          const double w = wxr[ta] * wyr[tb];
+          double* nd = nd0 + roff[tb] + coff[ta];
 #pragma unroll
           for (int f = 0; f < 11; ++f) atomicAdd(nd + f * WP, lg[f] * w);
         }

@@ -6,6 +6,7 @@
 // all instances, which advance in lockstep.  The plain API is a context of one
 // instance.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -411,28 +412,57 @@ __global__ void k_diag_finalize(const double* __restrict__ part, int ninst, doub
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Saved states (pic_save_state / pic_load_state): a 256-byte header, then per
-// instance its particle count, the current particle set (11 arrays and the
-// original indices, n entries each), the tile metadata of the last sort
-// (tile starts, each tile's first chunk, the chunk list and its length), the
-// spectral history ring and, with the naive current, the background charge
-// plane init_particles computed.
+// Saved states (pic_save_state / pic_load_state): a header (16 words: magic,
+// configuration fingerprint, counters; then one particle count per instance),
+// then per instance the current particle set (11 arrays and the original
+// indices, n entries each), the tile metadata of the last sort (tile starts,
+// each tile's first chunk, the chunk list and its length), the spectral
+// history ring and, with the naive current, the background charge plane
+// init_particles computed.  A save or a load is one kernel launch over a
+// list of segments.
 constexpr uint64_t kStateMagic = 0x70696373746174ull;  // "picstat"
 constexpr int kStateHeaderWords = 16;
 
 namespace {
 
-__global__ void k_state_header(int64_t* h, int64_t a0, int64_t a1, int64_t a2, int64_t a3, int64_t a4, int64_t a5,
-                               int64_t a6, int64_t a7) {
-  if (threadIdx.x == 0) {
-    h[0] = a0;
-    h[1] = a1;
-    h[2] = a2;
-    h[3] = a3;
-    h[4] = a4;
-    h[5] = a5;
-    h[6] = a6;
-    h[7] = a7;
+struct HeaderWords {
+  int64_t w[kStateHeaderWords];
+};
+
+__global__ void k_state_header(int64_t* h, HeaderWords hw, int count) {
+  if ((int)threadIdx.x < count) h[threadIdx.x] = hw.w[threadIdx.x];
+}
+
+// copy every segment of the list: 16-byte vectors (segments of 16 bytes or
+// more start 16-byte aligned on both sides), a shorter tail in 4-byte words
+constexpr int kCopyMax = 32;
+struct CopyList {
+  int count;
+  uint64_t first[kCopyMax + 1];  // prefix sums of the segments' 16-byte chunks
+  const char* src[kCopyMax];
+  char* dst[kCopyMax];
+  uint64_t bytes[kCopyMax];
+};
+
+__global__ void __launch_bounds__(256) k_copy_list(CopyList L) {
+  const uint64_t total = L.first[L.count];
+  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = L.count - 1;  // the segment holding chunk q: last with first <= q
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (L.first[mid] <= q) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint64_t off = (q - L.first[lo]) * 16, rem = L.bytes[lo] - off;
+    const gptr<const char> src = gp(L.src[lo]) + off;
+    const gptr<char> dst = gp(L.dst[lo]) + off;
+    if (rem >= 16) {
+      *reinterpret_cast<gptr<i32x4>>(dst) = *reinterpret_cast<gptr<const i32x4>>(src);
+    } else {
+      for (uint64_t b = 0; b < rem; b += 4)
+        *reinterpret_cast<gptr<int32_t>>(dst + b) = *reinterpret_cast<gptr<const int32_t>>(src + b);
+    }
   }
 }
 
@@ -1368,7 +1398,7 @@ pic_status_t pic_set_dirk_tableau(pic_ctx_t c, int32_t stages, const double* A, 
 
 // byte offsets of one instance's parts inside a saved state
 struct StateLayout {
-  size_t n, parts, ids, start, cstart, work, nwork, hist, rb, end;
+  size_t parts, ids, start, cstart, work, nwork, hist, rb, end;
 };
 static StateLayout state_layout(pic_ctx_t c, const Instance& in, size_t base) {
   StateLayout L{};
@@ -1380,7 +1410,6 @@ static StateLayout state_layout(pic_ctx_t c, const Instance& in, size_t base) {
     o = align_up(o + bytes);
     return at;
   };
-  L.n = take(8);
   L.parts = take(11 * array_bytes(cap, es));
   L.ids = take(cap * 4);
   L.start = take(((size_t)in.d.tp.ntiles + 1) * 4);
@@ -1393,9 +1422,11 @@ static StateLayout state_layout(pic_ctx_t c, const Instance& in, size_t base) {
   return L;
 }
 
+static size_t state_header_bytes(pic_ctx_t c) { return align_up((size_t)(kStateHeaderWords + c->ninst()) * 8); }
+
 size_t pic_state_bytes(pic_ctx_t c) {
   if (!c) return 0;
-  size_t o = align_up(kStateHeaderWords * 8);
+  size_t o = state_header_bytes(c);
   for (const auto& in : c->inst) o = state_layout(c, in, o).end;
   return o;
 }
@@ -1416,46 +1447,84 @@ static int64_t state_fingerprint(pic_ctx_t c) {
   return (int64_t)(h & 0x7fffffffffffffffull);
 }
 
+// the segments of a state: (state offset, context address, bytes) for every
+// instance, with n_i particles each
+static std::vector<std::array<size_t, 3>> state_segments(pic_ctx_t c, int cur, const std::vector<int64_t>& ns) {
+  std::vector<std::array<size_t, 3>> seg;
+  size_t o = state_header_bytes(c);
+  const size_t es = c->dtype == PIC_F32 ? 4 : 8;
+  for (int i = 0; i < c->ninst(); ++i) {
+    const Instance& in = c->inst[i];
+    const StateLayout L = state_layout(c, in, o);
+    const InstDesc& d = in.d;
+    const size_t n = (size_t)ns[i], ab = array_bytes((size_t)in.cfg.max_particles, es);
+    for (int a = 0; a < 11; ++a) seg.push_back({L.parts + a * ab, (size_t)d.set[cur][a], n * es});
+    seg.push_back({L.ids, (size_t)d.ids[cur], n * 4});
+    seg.push_back({L.start, (size_t)d.tb.start, ((size_t)d.tp.ntiles + 1) * 4});
+    seg.push_back({L.cstart, (size_t)d.tb.cstart, (size_t)d.tp.ntiles * 4});
+    seg.push_back({L.work, (size_t)d.tb.work, (size_t)d.tp.max_work * 16});
+    seg.push_back({L.nwork, (size_t)d.tb.nwork, 4});
+    seg.push_back({L.hist, (size_t)d.H, (size_t)c->hist.nslots * in.L.plane_c * 16});
+    if (d.RB) seg.push_back({L.rb, (size_t)d.RB, (size_t)in.cfg.nx * in.cfg.ny * 8});
+    o = L.end;
+  }
+  return seg;
+}
+
+// copy the segments between the state buffer and the context, in launches of
+// at most kCopyMax segments (one launch for a single-instance context)
+static pic_status_t copy_segments(pic_ctx_t c, const std::vector<std::array<size_t, 3>>& seg, char* state,
+                                  bool to_state) {
+  for (size_t s0 = 0; s0 < seg.size(); s0 += kCopyMax) {
+    CopyList L{};
+    uint64_t chunks = 0;
+    for (size_t k = s0; k < seg.size() && L.count < kCopyMax; ++k) {
+      const auto& g = seg[k];
+      if (g[2] == 0) continue;
+      char* sp = state + g[0];
+      char* cp = reinterpret_cast<char*>(g[1]);
+      if (((uintptr_t)sp | (uintptr_t)cp) & (g[2] >= 16 ? 15 : 3))
+        return c->fail(PIC_ERR_HIP, "state segment misaligned");
+      L.src[L.count] = to_state ? cp : sp;
+      L.dst[L.count] = to_state ? sp : cp;
+      L.bytes[L.count] = g[2];
+      L.first[L.count] = chunks;
+      chunks += (g[2] + 15) / 16;
+      L.count++;
+    }
+    if (!L.count) continue;
+    L.first[L.count] = chunks;
+    const unsigned blocks = (unsigned)std::min<uint64_t>((chunks + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_copy_list, dim3(blocks), dim3(256), 0, c->stream, L);
+    pic_status_t st = c->hip(hipGetLastError(), "state copy");
+    if (st) return st;
+  }
+  return PIC_OK;
+}
+
 pic_status_t pic_save_state(pic_ctx_t c, void* dst) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (!dst || ((uintptr_t)dst & (kAlign - 1))) return c->fail(PIC_ERR_INVALID_ARG, "dst must be a 256-byte aligned device pointer");
   if (c->phase != READY) return c->fail(PIC_ERR_STATE, "save_state needs phase READY");
   char* b = static_cast<char*>(dst);
-  hipLaunchKernelGGL(k_state_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(b),
-                     (int64_t)kStateMagic, state_fingerprint(c), c->nupd, c->vflip, c->cur, c->moves,
-                     c->stepped ? 1 : 0, (int64_t)pic_state_bytes(c));
-  pic_status_t st = c->hip(hipGetLastError(), "state header");
-  if (!st) {
-    hipLaunchKernelGGL(k_state_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(b) + 8,
-                       (int64_t)c->sort_every, 0, 0, 0, 0, 0, 0, 0);
+  const int ni = c->ninst();
+  std::vector<int64_t> ns(ni);
+  for (int i = 0; i < ni; ++i) ns[i] = c->inst[i].d.n;
+  // header: global words, then the particle counts (in launches of 16 words)
+  std::vector<int64_t> words(kStateHeaderWords + ni, 0);
+  const int64_t g[] = {(int64_t)kStateMagic, state_fingerprint(c), c->nupd, c->vflip, c->cur, c->moves,
+                       c->stepped ? 1 : 0, (int64_t)pic_state_bytes(c), c->sort_every};
+  for (size_t k = 0; k < sizeof(g) / sizeof(g[0]); ++k) words[k] = g[k];
+  for (int i = 0; i < ni; ++i) words[kStateHeaderWords + i] = ns[i];
+  pic_status_t st = PIC_OK;
+  for (size_t w0 = 0; w0 < words.size() && !st; w0 += kStateHeaderWords) {
+    HeaderWords hw{};
+    for (int k = 0; k < kStateHeaderWords && w0 + k < words.size(); ++k) hw.w[k] = words[w0 + k];
+    const int cnt = (int)std::min<size_t>(kStateHeaderWords, words.size() - w0);
+    hipLaunchKernelGGL(k_state_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(b) + w0, hw, cnt);
     st = c->hip(hipGetLastError(), "state header");
   }
-  size_t o = align_up(kStateHeaderWords * 8);
-  const size_t es = c->dtype == PIC_F32 ? 4 : 8;
-  for (auto& in : c->inst) {
-    const StateLayout L = state_layout(c, in, o);
-    const InstDesc& d = in.d;
-    const size_t n = (size_t)d.n;
-    const int64_t nn = d.n;
-    auto cp = [&](size_t off, const void* src, size_t bytes, const char* what) {
-      if (!st && bytes) st = c->hip(hipMemcpyAsync(b + off, src, bytes, hipMemcpyDeviceToDevice, c->stream), what);
-    };
-    if (!st) {
-      hipLaunchKernelGGL(k_state_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(b + L.n), nn,
-                         0, 0, 0, 0, 0, 0, 0);
-      st = c->hip(hipGetLastError(), "state n");
-    }
-    const size_t ab = array_bytes((size_t)in.cfg.max_particles, es);
-    for (int a = 0; a < 11; ++a) cp(L.parts + a * ab, d.set[c->cur][a], n * es, "state particles");
-    cp(L.ids, d.ids[c->cur], n * 4, "state ids");
-    cp(L.start, d.tb.start, ((size_t)d.tp.ntiles + 1) * 4, "state tile starts");
-    cp(L.cstart, d.tb.cstart, (size_t)d.tp.ntiles * 4, "state chunk starts");
-    cp(L.work, d.tb.work, (size_t)d.tp.max_work * 16, "state chunks");
-    cp(L.nwork, d.tb.nwork, 4, "state chunk count");
-    cp(L.hist, d.H, (size_t)c->hist.nslots * in.L.plane_c * 16, "state history");
-    if (d.RB) cp(L.rb, d.RB, (size_t)in.cfg.nx * in.cfg.ny * 8, "state background charge");
-    o = L.end;
-  }
+  if (!st) st = copy_segments(c, state_segments(c, c->cur, ns), b, true);
   return st;
 }
 
@@ -1463,50 +1532,29 @@ pic_status_t pic_load_state(pic_ctx_t c, const void* src) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (!src || ((uintptr_t)src & (kAlign - 1))) return c->fail(PIC_ERR_INVALID_ARG, "src must be a 256-byte aligned device pointer");
   const char* b = static_cast<const char*>(src);
-  int64_t h[kStateHeaderWords];
-  pic_status_t st = c->hip(hipMemcpyAsync(h, b, sizeof(h), hipMemcpyDeviceToHost, c->stream), "state header read");
+  const int ni = c->ninst();
+  std::vector<int64_t> h(kStateHeaderWords + ni);
+  pic_status_t st = c->hip(hipMemcpyAsync(h.data(), b, h.size() * 8, hipMemcpyDeviceToHost, c->stream), "state header read");
   if (!st) st = c->hip(hipStreamSynchronize(c->stream), "state header sync");
   if (st) return st;
   if (h[0] != (int64_t)kStateMagic || h[1] != state_fingerprint(c) || h[7] != (int64_t)pic_state_bytes(c))
     return c->fail(PIC_ERR_INVALID_ARG, "src is not a state saved by a context of this configuration");
-  std::vector<int64_t> ns(c->ninst());
-  size_t o = align_up(kStateHeaderWords * 8);
-  for (int i = 0; i < c->ninst(); ++i) {
-    const StateLayout L = state_layout(c, c->inst[i], o);
-    if (!st) st = c->hip(hipMemcpyAsync(&ns[i], b + L.n, 8, hipMemcpyDeviceToHost, c->stream), "state n read");
-    o = L.end;
-  }
-  if (!st) st = c->hip(hipStreamSynchronize(c->stream), "state n sync");
-  if (st) return st;
-  const int cur = (int)h[4];
-  const size_t es = c->dtype == PIC_F32 ? 4 : 8;
-  o = align_up(kStateHeaderWords * 8);
-  for (int i = 0; i < c->ninst(); ++i) {
-    Instance& in = c->inst[i];
-    if (ns[i] < 0 || ns[i] > in.cfg.max_particles)
+  std::vector<int64_t> ns(h.begin() + kStateHeaderWords, h.end());
+  for (int i = 0; i < ni; ++i)
+    if (ns[i] < 0 || ns[i] > c->inst[i].cfg.max_particles)
       return c->fail(PIC_ERR_INVALID_ARG, "src holds a particle count beyond the capacity");
+  const int cur = (int)h[4];
+  if (cur != 0 && cur != 1) return c->fail(PIC_ERR_INVALID_ARG, "src holds an invalid particle set index");
+  st = copy_segments(c, state_segments(c, cur, ns), const_cast<char*>(b), false);
+  if (st) {
+    c->phase = EMPTY;
+    return st;
   }
-  for (int i = 0; i < c->ninst() && !st; ++i) {
-    Instance& in = c->inst[i];
-    const StateLayout L = state_layout(c, in, o);
-    InstDesc& d = in.d;
-    const size_t n = (size_t)ns[i];
-    auto cp = [&](void* dst, size_t off, size_t bytes, const char* what) {
-      if (!st && bytes) st = c->hip(hipMemcpyAsync(dst, b + off, bytes, hipMemcpyDeviceToDevice, c->stream), what);
-    };
-    const size_t ab = array_bytes((size_t)in.cfg.max_particles, es);
-    for (int a = 0; a < 11; ++a) cp(d.set[cur][a], L.parts + a * ab, n * es, "state particles");
-    cp(d.ids[cur], L.ids, n * 4, "state ids");
-    cp(d.tb.start, L.start, ((size_t)d.tp.ntiles + 1) * 4, "state tile starts");
-    cp(d.tb.cstart, L.cstart, (size_t)d.tp.ntiles * 4, "state chunk starts");
-    cp(d.tb.work, L.work, (size_t)d.tp.max_work * 16, "state chunks");
-    cp(d.tb.nwork, L.nwork, 4, "state chunk count");
-    cp(d.H, L.hist, (size_t)c->hist.nslots * in.L.plane_c * 16, "state history");
-    if (d.RB) cp(d.RB, L.rb, (size_t)in.cfg.nx * in.cfg.ny * 8, "state background charge");
-    d.n = ns[i];
-    o = L.end;
+  bool counts_changed = false;
+  for (int i = 0; i < ni; ++i) {
+    counts_changed = counts_changed || c->inst[i].d.n != ns[i];
+    c->inst[i].d.n = ns[i];
   }
-  if (st) return st;
   c->nupd = h[2];
   c->vflip = (int)h[3];
   c->cur = cur;
@@ -1514,7 +1562,8 @@ pic_status_t pic_load_state(pic_ctx_t c, const void* src) {
   c->stepped = h[6] != 0;
   c->sort_every = (int)std::min<int64_t>(std::max<int64_t>(h[8], 1), 64);
   c->phase = READY;
-  return c->upload_desc();
+  // the device descriptors change only with the particle counts
+  return counts_changed ? c->upload_desc() : PIC_OK;
 }
 
 pic_status_t pic_diagnostics_all(pic_ctx_t c, double* out) {

@@ -256,4 +256,34 @@ __device__ __forceinline__ void push_one(const T* gv, T& Px, T& Py, T Pz, T vx, 
   nz = uz * inv;
 }
 
+// v[t] <- v[(t + r) % NW] for a per-lane r in [0, NW): a barrel shifter, one
+// select per element and bit of r, with the lane masks of the bits held in
+// scalar registers (written as explicit selects: the compiler otherwise turns
+// the shifter back into per-element compare chains)
+__device__ __forceinline__ float select_lanes(float a, float b, uint64_t lanes) {
+  float r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(lanes));
+  return r;
+}
+__device__ __forceinline__ double select_lanes(double a, double b, uint64_t lanes) {
+  const float lo = select_lanes(__uint_as_float((uint32_t)__double_as_longlong(a)),
+                                __uint_as_float((uint32_t)__double_as_longlong(b)), lanes);
+  const float hi = select_lanes(__uint_as_float((uint32_t)((unsigned long long)__double_as_longlong(a) >> 32)),
+                                __uint_as_float((uint32_t)((unsigned long long)__double_as_longlong(b) >> 32)),
+                                lanes);
+  return __longlong_as_double((long long)(((unsigned long long)__float_as_uint(hi) << 32) | __float_as_uint(lo)));
+}
+template <int NW, typename T>
+__device__ __forceinline__ void rotate_lanes(T (&v)[NW], int r) {
+#pragma unroll
+  for (int s = 1; s < NW; s <<= 1) {
+    const uint64_t lanes = __ballot((r & s) != 0);
+    T u[NW];
+#pragma unroll
+    for (int t = 0; t < NW; ++t) u[t] = select_lanes(v[t], v[(t + s) % NW], lanes);
+#pragma unroll
+    for (int t = 0; t < NW; ++t) v[t] = u[t];
+  }
+}
+
 }  // namespace pic

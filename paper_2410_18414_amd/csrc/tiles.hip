@@ -60,29 +60,6 @@ __device__ __forceinline__ void load_node(const double* p, double* q) {
   }
 }
 
-// v[t] <- v[(t + r) % NW] for a per-lane r in [0, NW): a barrel shifter, one
-// select per element and bit of r, with the lane masks of the bits held in
-// scalar registers (written as explicit selects: the compiler otherwise turns
-// the shifter back into per-element compare chains)
-__device__ __forceinline__ float select_lanes(float a, float b, uint64_t lanes) {
-  float r;
-  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(lanes));
-  return r;
-}
-template <int NW>
-__device__ __forceinline__ void rotate_lanes(float (&v)[NW], int r) {
-#pragma unroll
-  for (int s = 1; s < NW; s <<= 1) {
-    const uint64_t lanes = __ballot((r & s) != 0);
-    float u[NW];
-#pragma unroll
-    for (int t = 0; t < NW; ++t) u[t] = select_lanes(v[t], v[(t + s) % NW], lanes);
-#pragma unroll
-    for (int t = 0; t < NW; ++t) v[t] = u[t];
-  }
-}
-
-
 // deterministic deposit's fallback for a stencil outside the window: each
 // contribution rounded at the instance's fixed scale (float32: the window's
 // one-FMA rounding; float64: llrint of the scaled product) and added to the
@@ -372,8 +349,7 @@ template <typename T, int DEG, int MODE, int TS, int SL>
 __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__ D, int ninst, StepArgs sa) {
   constexpr bool GATHER = MODE != MODE_DEPOSIT;
   constexpr bool DEPOSIT = MODE != MODE_GATHER_PUSH;
-  constexpr bool ROTATE = sizeof(T) == 4;  // rotated deposit order (float32 particles)
-  constexpr bool FIXEDPT = ROTATE;          // fixed-point window (float32 particles)
+  constexpr bool FIXEDPT = sizeof(T) == 4;  // fixed-point window (float32 particles)
   constexpr bool FIXED = TS > 0;
   using G = Geo<(FIXED ? TS : 1), (FIXED ? SL : 0)>;
   using A = typename Acc<T>::type;
@@ -635,7 +611,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
           }
         }
       }
-      if constexpr (ROTATE) {
+      {
         // per-lane rotation of stencil columns and rows: at step (a, b) lane l
         // adds to the stencil node whose absolute indices are congruent to
         // (a + l, b + l / NW) modulo NW (a stencil holds one node of every
@@ -662,58 +638,63 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         // one packed x/y atomic and one z atomic per node, the same order in
         // every lane (a lane-dependent slot order splits the wave into two
         // halves that each issue both atomics)
-        const T sjx = jx * qscale, sjy = jy * qscale, sjz = jz * qscale;
-        if (inw) {
-          const int base = ly * W + lx;
+        if constexpr (FIXEDPT) {
+          const T sjx = jx * qscale, sjy = jy * qscale, sjz = jz * qscale;
+          if (inw) {
+            const int base = ly * W + lx;
+#pragma unroll
+            for (int b = 0; b < NW; ++b) {
+              unsigned char* xy_row = reinterpret_cast<unsigned char*>(jxy_w + base + roff[b]);
+              unsigned char* z_row = reinterpret_cast<unsigned char*>(jz_w + base + roff[b]);
+#pragma unroll
+              for (int a = 0; a < NW; ++a) {
+                const T w = wxr[a] * wyr[b];
+                // the exact product rounded to the nearest integer, ties to
+                // even (unbiased at the exact halves that scaled float32
+                // products often are), in one FMA: for |s w| < 2^22 the sum
+                // s w + 1.5 * 2^23 has unit spacing, so its bits are
+                // kMagicBits + round(s w)
+                const uint32_t bx = __float_as_uint(__builtin_fmaf(sjx, w, kMagic));
+                const uint32_t by = __float_as_uint(__builtin_fmaf(sjy, w, kMagic));
+                const uint32_t bz = __float_as_uint(__builtin_fmaf(sjz, w, kMagic));
+                // (int64) ix + 2^32 (int64) iy modulo 2^64, ix = bx - kMagicBits, iy = by - kMagicBits
+                const uint64_t pk = (((uint64_t)by << 32) | bx) - kMagicPair;
+                atomicAdd(reinterpret_cast<unsigned long long*>(xy_row + cxy[a]), (unsigned long long)pk);
+                atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a]), bz - kMagicBits);
+              }
+            }
+          }
+        } else if (inw && det) {
+          // deterministic deposit (float64): int64 window sums of the products
+          // rounded at the instance's fixed scale
+          unsigned long long* nq0 = reinterpret_cast<unsigned long long*>(jw) + ly * W + lx;
+          const T dx_ = jx * T(d.det_scale), dy_ = jy * T(d.det_scale), dz_ = jz * T(d.det_scale);
 #pragma unroll
           for (int b = 0; b < NW; ++b) {
-            unsigned char* xy_row = reinterpret_cast<unsigned char*>(jxy_w + base + roff[b]);
-            unsigned char* z_row = reinterpret_cast<unsigned char*>(jz_w + base + roff[b]);
+            unsigned char* row = reinterpret_cast<unsigned char*>(nq0 + roff[b]);
 #pragma unroll
             for (int a = 0; a < NW; ++a) {
               const T w = wxr[a] * wyr[b];
-              // the exact product rounded to the nearest integer, ties to
-              // even (unbiased at the exact halves that scaled float32
-              // products often are), in one FMA: for |s w| < 2^22 the sum
-              // s w + 1.5 * 2^23 has unit spacing, so its bits are
-              // kMagicBits + round(s w)
-              const uint32_t bx = __float_as_uint(__builtin_fmaf(sjx, w, kMagic));
-              const uint32_t by = __float_as_uint(__builtin_fmaf(sjy, w, kMagic));
-              const uint32_t bz = __float_as_uint(__builtin_fmaf(sjz, w, kMagic));
-              // (int64) ix + 2^32 (int64) iy modulo 2^64, ix = bx - kMagicBits, iy = by - kMagicBits
-              const uint64_t pk = (((uint64_t)by << 32) | bx) - kMagicPair;
-              atomicAdd(reinterpret_cast<unsigned long long*>(xy_row + cxy[a]), (unsigned long long)pk);
-              atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a]), bz - kMagicBits);
+              unsigned long long* nq = reinterpret_cast<unsigned long long*>(row + cxy[a]);
+              atomicAdd(nq, (unsigned long long)llrint(dx_ * w));
+              atomicAdd(nq + JWP, (unsigned long long)llrint(dy_ * w));
+              atomicAdd(nq + 2 * JWP, (unsigned long long)llrint(dz_ * w));
             }
           }
-        }
-      } else if (inw && det) {
-        // deterministic deposit (float64): int64 window sums of the products
-        // rounded at the instance's fixed scale
-        unsigned long long* nq0 = reinterpret_cast<unsigned long long*>(jw) + ly * W + lx;
-        const T sjx = jx * T(d.det_scale), sjy = jy * T(d.det_scale), sjz = jz * T(d.det_scale);
+        } else if (inw) {
+          // float64 window: float64 LDS atomics
+          A* nd0 = jw + ly * W + lx;
 #pragma unroll
-        for (int b = 0; b < NW; ++b) {
+          for (int b = 0; b < NW; ++b) {
+            unsigned char* row = reinterpret_cast<unsigned char*>(nd0 + roff[b]);
 #pragma unroll
-          for (int a = 0; a < NW; ++a) {
-            const T w = wx[a] * wy[b];
-            unsigned long long* nq = nq0 + b * W + a;
-            atomicAdd(nq, (unsigned long long)llrint(sjx * w));
-            atomicAdd(nq + JWP, (unsigned long long)llrint(sjy * w));
-            atomicAdd(nq + 2 * JWP, (unsigned long long)llrint(sjz * w));
-          }
-        }
-      } else if (inw) {
-        A* nd0 = jw + ly * W + lx;
-#pragma unroll
-        for (int b = 0; b < NW; ++b) {
-#pragma unroll
-          for (int a = 0; a < NW; ++a) {
-            const T w = wx[a] * wy[b];
-            A* nd = nd0 + b * W + a;
-            atomicAdd(nd, A(jx * w));
-            atomicAdd(nd + JWP, A(jy * w));
-            atomicAdd(nd + 2 * JWP, A(jz * w));
+            for (int a = 0; a < NW; ++a) {
+              const T w = wxr[a] * wyr[b];
+              A* nd = reinterpret_cast<A*>(row + cxy[a]);
+              atomicAdd(nd, A(jx * w));
+              atomicAdd(nd + JWP, A(jy * w));
+              atomicAdd(nd + 2 * JWP, A(jz * w));
+            }
           }
         }
       }
