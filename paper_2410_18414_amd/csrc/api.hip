@@ -774,8 +774,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
   c->dtype = cfgs[0].particle_dtype;
   c->degree = cfgs[0].spline_degree;
   c->scheme = scheme_family(cfgs[0].scheme);
-  // the naive charge deposit runs on the untiled passes
-  c->sorted = (cfgs[0].flags & (PIC_FLAG_NO_SORT | PIC_FLAG_NAIVE_RHO)) == 0;
+  c->sorted = (cfgs[0].flags & PIC_FLAG_NO_SORT) == 0;
   c->d_desc = (InstDesc*)c->ws;
   c->d_diag = (double*)(c->ws + align_up(ninst * sizeof(InstDesc)));
   c->inst.resize(ninst);
@@ -844,10 +843,12 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     {
       // fixed-point deposit exponent (float32 particles): the largest single
       // contribution B = |q| c max(w) / (dx dy), max(w) = M_deg(0)^2, |v| < c
-      // (3c for v*); B = m 2^p with m in [0.5, 1) gives B 2^(30 - p) < 2^30
+      // (3c for v*; the naive charge deposit's |q| max(w) / (dx dy) when that
+      // is larger); B = m 2^p with m in [0.5, 1) gives B 2^(30 - p) < 2^30
       static const double m0[6] = {0.0, 1.0, 0.75, 2.0 / 3.0, 115.0 / 192.0, 0.55};
-      const double B = std::fabs(cf.q) * cf.c * (d.jvstar ? 3.0 : 1.0) * g.inv_area * m0[cf.spline_degree] *
-                       m0[cf.spline_degree];
+      const double vb = std::max(cf.c * ((cf.flags & PIC_FLAG_JVSTAR) ? 3.0 : 1.0),
+                                 (cf.flags & PIC_FLAG_NAIVE_RHO) ? 1.0 : 0.0);
+      const double B = std::fabs(cf.q) * vb * g.inv_area * m0[cf.spline_degree] * m0[cf.spline_degree];
       int p = 0;
       const bool ok = B > 0 && std::isfinite(B);
       if (ok) std::frexp(B, &p);
@@ -886,7 +887,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     c->lds_col = std::max(c->lds_col, columns_split_lds_bytes(cf.ny, d.sc.substep ? d.sc.stages : 0));
     if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, adj_columns_lds_bytes(cf.ny));
     for (int mode = 0; mode < 3; ++mode)
-      c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp));
+      c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp, d.naive != 0));
     // a position update moves a particle by less than c dt; the window's slack
     // absorbs sort_every updates without any particle leaving it
     const double cells = cf.c * cf.dt / std::min(g.dx, g.dy);

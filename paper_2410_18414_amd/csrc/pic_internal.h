@@ -302,7 +302,7 @@ hipError_t launch_set_particles(int dtype, const void* parts, int64_t n, const d
 hipError_t launch_particle_diag(int dtype, const void* parts, int64_t n, PhysP ph, double* out2, hipStream_t s);
 
 // tiles.hip
-size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp);
+size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp, bool naive);
 hipError_t launch_tile_sort(int dtype, const InstDesc* D, int ninst, int nb_count, int nb_tiles, int nb_part,
                             int src_set, hipStream_t s);
 // geometry code of a tile plan: a compiled window shape (1, 2) or 0 (from TileP)

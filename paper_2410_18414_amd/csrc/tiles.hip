@@ -484,10 +484,14 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       }
     }
   }
+  // the naive charge deposit: rho^{n+1} from the same spline at x^{n+1}, a
+  // fourth window plane flushed to the fourth J plane
+  const bool naive = d.naive != 0;
   if (DEPOSIT) {
-    // float64 window: 3 planes of float64; fixed-point window (float32
-    // particles): JWP 64-bit x/y pairs then JWP 32-bit z values
-    const int nzero = sizeof(T) == 4 ? (3 * JWP + 1) / 2 : 3 * JWP;
+    // float64 window: 3 (naive: 4) planes of float64; fixed-point window
+    // (float32 particles): JWP 64-bit x/y pairs then JWP 32-bit z values (and
+    // JWP 32-bit rho values)
+    const int nzero = sizeof(T) == 4 ? (naive ? 2 * JWP : (3 * JWP + 1) / 2) : (naive ? 4 : 3) * JWP;
     for (int idx = threadIdx.x; idx < nzero; idx += blockDim.x) jw[idx] = A(0);
   }
   __syncthreads();
@@ -505,6 +509,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   // a single contribution below 2^21 (the rounding FMA needs below 2^22).
   unsigned long long* jxy_w = reinterpret_cast<unsigned long long*>(jw);     // [JWP]
   uint32_t* jz_w = reinterpret_cast<uint32_t*>(jw + JWP);                      // [JWP]
+  uint32_t* jr_w = jz_w + JWP;                                                  // [JWP] (naive)
   float qscale = 1.0f;
   double inv_qscale = 1.0;
   if (FIXEDPT) {
@@ -607,6 +612,15 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
               deposit_global_fixed<T, DEG>(sx, sy, wx, wy, jx * sc, jy * sc, jz * sc, J, g);
             } else {
               deposit_global<T, DEG>(sx, sy, wx, wy, jx, jy, jz, J, g);
+              if (naive) {
+#pragma unroll
+                for (int b = 0; b < NW; ++b) {
+                  const size_t row = (size_t)wrapi(sy + b, g.ny) * g.nx;
+#pragma unroll
+                  for (int a = 0; a < NW; ++a)
+                    gadd(Jg + 3 * plane + row + wrapi(sx + a, g.nx), (double)(qs * (wx[a] * wy[b])));
+                }
+              }
             }
           }
         }
@@ -639,7 +653,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         // every lane (a lane-dependent slot order splits the wave into two
         // halves that each issue both atomics)
         if constexpr (FIXEDPT) {
-          const T sjx = jx * qscale, sjy = jy * qscale, sjz = jz * qscale;
+          const T sjx = jx * qscale, sjy = jy * qscale, sjz = jz * qscale, sjr = qs * qscale;
           if (inw) {
             const int base = ly * W + lx;
 #pragma unroll
@@ -661,6 +675,10 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
                 const uint64_t pk = (((uint64_t)by << 32) | bx) - kMagicPair;
                 atomicAdd(reinterpret_cast<unsigned long long*>(xy_row + cxy[a]), (unsigned long long)pk);
                 atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a]), bz - kMagicBits);
+                if (naive) {
+                  const uint32_t br = __float_as_uint(__builtin_fmaf(sjr, w, kMagic));
+                  atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a] + 4 * JWP), br - kMagicBits);
+                }
               }
             }
           }
@@ -694,6 +712,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
               atomicAdd(nd, A(jx * w));
               atomicAdd(nd + JWP, A(jy * w));
               atomicAdd(nd + 2 * JWP, A(jz * w));
+              if (naive) atomicAdd(nd + 3 * JWP, A(qs * w));
             }
           }
         }
@@ -720,6 +739,10 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
             if (X) gadd(Jg + go, X * inv_qscale);
             if (Y) gadd(Jg + plane + go, Y * inv_qscale);
             if (Z) gadd(Jg + 2 * plane + go, Z * inv_qscale);
+            if (naive) {
+              const int32_t R = (int32_t)jr_w[node];
+              if (R) gadd(Jg + 3 * plane + go, R * inv_qscale);
+            }
           }
         } else if (det) {
           const unsigned long long* jq = reinterpret_cast<const unsigned long long*>(jw);
@@ -730,8 +753,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
             if (v) gadd(Jq + c * plane + go, v);
           }
         } else {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
+          const int nc = naive ? 4 : 3;
+          for (int c = 0; c < nc; ++c) {
             const A v = jw[c * JWP + node];
             if (v != A(0)) gadd(Jg + c * plane + go, (double)v);
           }
@@ -783,10 +806,13 @@ hipError_t launch_tiled_mode(int mode, int degree, int geo, const InstDesc* D, i
 
 }  // namespace
 
-size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp) {
+size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp, bool naive) {
   const size_t es = dtype == PIC_F32 ? 4 : 8;
+  // J window bytes per node: float32 a packed x/y pair, z (and rho) in 32
+  // bits; float64 three (four) planes
+  const size_t jb = dtype == PIC_F32 ? (naive ? 16 : 12) : (naive ? 32 : 24);
   return (mode != MODE_DEPOSIT ? (size_t)kNodeSlots * tp.win_pad * es : 0) +
-         (mode != MODE_GATHER_PUSH ? (size_t)(dtype == PIC_F32 ? 12 : 24) * (tp.win_pad + 8) + 8 : 0);
+         (mode != MODE_GATHER_PUSH ? jb * (tp.win_pad + 8) + 8 : 0);
 }
 
 // count (BK_COUNT blocks), cell scan with the tile scan in its last block

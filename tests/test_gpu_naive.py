@@ -4,7 +4,8 @@ the oracle's naive mode (needs an MI355X).
 The naive update of the Weibel figures (Sec. 5.1) maps rho^{n+1} to the mesh
 with the same spline as J instead of updating it from continuity.  Checked
 here: particle state and spectral history equal the oracle's naive run
-(1e-10 float64, 1e-4 float32); the gauge and Gauss residuals equal the
+(1e-10 float64, 1e-4 float32) on the tiled passes (with a fourth LDS window
+plane for rho) and on the untiled ones; the gauge and Gauss residuals equal the
 oracle's (both far above round-off, while the continuity run keeps the gauge
 at round-off); particles at rest keep rho = 0; unsupported combinations are
 rejected before anything runs.
@@ -28,10 +29,11 @@ def cloud(nx=32, ny=32, ppc=3, seed=31):
 
 @pytest.mark.parametrize("scheme,k,degree", [("bdf", 1, 2), ("bdf", 2, 3), ("dirk2", 2, 2)])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_naive_matches_oracle(gpu_lib, scheme, k, degree, dtype):
+@pytest.mark.parametrize("extra", [0, pic.FLAG_NO_SORT], ids=["tiled", "untiled"])
+def test_naive_matches_oracle(gpu_lib, scheme, k, degree, dtype, extra):
     w = cloud()
     o = make_oracle(w, degree, scheme, k, naive=True)
-    g = make_gpu(w, degree, scheme, dtype, bdf_order=k, flags=pic.FLAG_NAIVE_RHO)
+    g = make_gpu(w, degree, scheme, dtype, bdf_order=k, flags=pic.FLAG_NAIVE_RHO | extra)
     for n in (1, 6, 5):          # uneven call lengths (direct launches and graph-free steps)
         o.step(n)
         pic.step(g, n)
@@ -45,6 +47,25 @@ def test_naive_matches_oracle(gpu_lib, scheme, k, degree, dtype):
         assert rel(dg["gauss_l2"], do["gauss_l2"]) <= 1e-8
         assert dg["gauge_l2"] >= 1e-6 * dg["gauge_scale"]     # the naive update breaks the gauge
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_naive_charge_of_particles_leaving_their_windows(gpu_lib, dtype):
+    """Fast particles and a long sort interval: stencils that leave their
+    tile's window deposit rho (and J) with global atomics.  The run equals the
+    one that re-sorts every step (every stencil in its window) to the
+    precision's tolerance."""
+    w = workloads.cloud(nx=32, ny=32, ppc=4, seed=34, drift=0.3, vth=0.6)
+    runs = []
+    for si in (40, 1):
+        g = make_gpu(w, 3, "bdf", dtype, bdf_order=2, flags=pic.FLAG_NAIVE_RHO, sort_interval=si)
+        pic.step(g, 24)
+        runs.append((gpu_parts(g), pic.get_history(g).cpu().numpy()))
+        g.close()
+    tol = DT_TOL[dtype]
+    assert rel(runs[0][1], runs[1][1]) <= tol
+    errs, bad = compare_particles(runs[0][0], runs[1][0], w["lx"], w["ly"], tol)
+    assert not bad, errs
 
 
 def test_continuity_keeps_gauge_naive_breaks_it(gpu_lib):
