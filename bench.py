@@ -568,6 +568,10 @@ def main():
         out["batched_integer_sides"] = bench_batched_integer_sides()
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint()
+        # the same gradient storing every state (no replay)
+        store_all = bench_adjoint(every=1)
+        out["adjoint"]["store_every_state"] = {k: store_all[k] for k in (
+            "gradient_ms", "gradient_vs_forward", "forward_ms_per_step")}
     if not args.no_naive:
         out["naive"] = bench_naive()
     if not args.no_variants:

@@ -12,8 +12,9 @@ backward walks the run in reverse with libpic's discrete adjoint
 `every` steps during the forward (checkpoints: pic_save_state, the context's
 raw device state -- particles in their sorted order, tile metadata, history
 ring); each segment is replayed forward from its checkpoint into a pool of
-saved states, then the adjoint steps through the segment backwards, loading
-each state with pic_load_state (no conversion and no re-sort); the particle
+saved states (the last one stays in the context), then the adjoint steps
+through the segment backwards, loading each state with pic_load_state (no
+conversion and no re-sort); the particle
 adjoint stays inside the context in slot order for the whole sweep.  every=1
 stores every state (no replay).  Only argument marshalling happens here:
 every step and every adjoint step runs in the library's kernels.
@@ -62,9 +63,11 @@ class _FieldEnergy(torch.autograd.Function):
                 pic.load_state(ctx, ck)
                 for j in range(1, seg):
                     pic.step(ctx, 1)
-                    if len(pool) < j:
-                        pool.append(pic.State(ctx))
-                    states.append(pic.save_state(ctx, pool[j - 1]))
+                    if j < seg - 1:  # the segment's last state stays in the context
+                        if len(pool) < j:
+                            pool.append(pic.State(ctx))
+                        states.append(pic.save_state(ctx, pool[j - 1]))
+                pic.step_adjoint(ctx, None, lam_hist)
             for st in reversed(states):
                 pic.load_state(ctx, st)
                 pic.step_adjoint(ctx, None, lam_hist)
