@@ -28,6 +28,53 @@ struct PhysP {
   double dt, q, m, c;
 };
 
+// Row pitch (in nodes) of the tiled pass's LDS field window of W x W nodes.
+// A float32 node record is 12 dwords, so at one gather instruction two lanes
+// whose stencils start at nodes n1, n2 read the same bank group when
+// 12 (n1 - n2) = 0 mod 64, i.e. n1 - n2 = 0 mod 16; with row pitch P,
+// n1 - n2 = P dy + dx for the lanes' cell offset (dx, dy).  As the cell order
+// ages between sorts a wave's particles spread over neighbouring cells, and
+// every offset on that lattice adds conflicts (the pitch W = 25 of 16-cell
+// tiles puts (2, -2) on it, W = 17 of 8-cell tiles (1, -1)).  The pitch is the
+// one of W .. W + 7 whose lattice points with |dx|, |dy| <= 3 weigh least
+// (weight 1 / (dx^2 + dy^2)), among those that keep the fused pass's
+// workgroups per CU (160 KB of LDS with the float32 J window beside the field
+// window).
+// Float64 records (24 dwords) keep the pitch W.
+__host__ __device__ constexpr double pitch_conflicts(int P) {
+  double wgt = 0.0;
+  for (int dy = -3; dy <= 3; ++dy)
+    for (int dx = -3; dx <= 3; ++dx)
+      if ((dx != 0 || dy != 0) && (P * dy + dx) % 16 == 0) wgt += 1.0 / (dx * dx + dy * dy);
+  return wgt;
+}
+__host__ __device__ constexpr long fused_lds_f32(int W, int P) {
+  return 48L * W * P + 12L * ((W * W + 63) / 64 * 64 + 8) + 8;
+}
+// workgroups per CU the LDS admits, counted up to 4 (the register file holds
+// about four of the fused pass's 256-thread workgroups)
+__host__ __device__ constexpr long fused_wgs(int W, int P) {
+  return 163840L / fused_lds_f32(W, P) < 4 ? 163840L / fused_lds_f32(W, P) : 4;
+}
+__host__ __device__ constexpr int field_pitch(int W, int es) {
+  if (es != 4) return W;
+  int best = W;
+  double bw = pitch_conflicts(W);
+  for (int P = W + 1; P < W + 8; ++P) {
+    if (fused_wgs(W, P) < fused_wgs(W, W)) continue;
+    const double wgt = pitch_conflicts(P);
+    if (wgt < bw) {
+      bw = wgt;
+      best = P;
+    }
+  }
+  return best;
+}
+// nodes of the field window: W rows of the pitch (float64: padded to 64 nodes)
+__host__ __device__ constexpr int field_window_nodes(int W, int es) {
+  return es == 4 ? W * field_pitch(W, es) : (W * W + 63) / 64 * 64;
+}
+
 // Particle SoA pointers.  v[0..2] = v^n, w[0..2] = v^{n-1} (overwritten with v^{n+1}).
 template <typename T>
 struct Parts {

@@ -372,7 +372,9 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   double* __restrict__ J = d.J + (staged ? (size_t)3 * sa.stage * d.g.nx * d.g.ny : 0);
   const gptr<double> Jg = gp(J);
   const int W = FIXED ? G::W : tp.win;
-  const int WP = FIXED ? G::WP : tp.win_pad;  // plane stride of the LDS windows (field f at f*WP)
+  const int WP = FIXED ? G::WP : tp.win_pad;  // plane stride of the J window planes
+  const int WF = field_pitch(W, (int)sizeof(T));  // row pitch of the field window
+  const int FWN = field_window_nodes(W, (int)sizeof(T));  // its nodes
   // plane stride of the float64 J window: WP + 8 puts the three components of
   // a node 16 banks apart (WP itself is a multiple of the 64-bank cycle)
   const int JWP = WP + 8;
@@ -395,7 +397,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
   const int jlo = max(0, (it.w & 0xffff) - 1), jhi = min(W, (it.w >> 16) + 2 * slack + 5);
   extern __shared__ __align__(16) unsigned char smem[];
   T* fw = reinterpret_cast<T*>(smem);
-  A* jw = reinterpret_cast<A*>(smem + (GATHER ? (size_t)kNodeSlots * WP * sizeof(T) : 0));
+  A* jw = reinterpret_cast<A*>(smem + (GATHER ? (size_t)kNodeSlots * FWN * sizeof(T) : 0));
   const size_t plane = (size_t)g.nx * g.ny;
   // One particle per lane, consecutive lanes on consecutive particles.  The
   // set is sorted by cell, so the lanes of a wave mostly share one or two
@@ -435,7 +437,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       auto copy_row = [&](int j) {
         const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
         const gptr<const f32x4> src = reinterpret_cast<gptr<const f32x4>>(Fg + go * kFieldSlots);
-        f32x4* dst = reinterpret_cast<f32x4*>(fw + (j * W + wi) * kNodeSlots);
+        f32x4* dst = reinterpret_cast<f32x4*>(fw + (j * WF + wi) * kNodeSlots);
         const f32x4 a0 = src[0], a1 = src[1], a2 = src[2];
         dst[0] = a0;
         dst[1] = a1;
@@ -471,14 +473,14 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         const int j = wj0 + r * wjs;
         if (j >= jlo && j < jhi) {
 #pragma unroll
-          for (int f = 0; f < 11; ++f) fw[(j * W + wi) * kNodeSlots + f] = v[r][f];
+          for (int f = 0; f < 11; ++f) fw[(j * WF + wi) * kNodeSlots + f] = v[r][f];
         }
       }
     } else {
       for (int j = wj0; j < W; j += wjs) {
         if (j < jlo || j >= jhi) continue;
         const size_t go = (size_t)modn(oy + j, g.ny) * g.nx + gxw;
-        const int node = j * W + wi;
+        const int node = j * WF + wi;
 #pragma unroll
         for (int f = 0; f < 11; ++f) fw[node * kNodeSlots + f] = Fg[f * plane + go];
       }
@@ -538,14 +540,14 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         S::eval(eta, sy, wy);
         const int lx = modw(sx - ox, g.nx), ly = modw(sy - oy, g.ny);
         if (lx + DEG < W && ly >= jlo && ly + DEG < jhi) {
-          const T* nd0 = fw + (ly * W + lx) * kNodeSlots;
+          const T* nd0 = fw + (ly * WF + lx) * kNodeSlots;
 #pragma unroll
           for (int b = 0; b < NW; ++b) {
 #pragma unroll
             for (int a = 0; a < NW; ++a) {
               const T w = wx[a] * wy[b];
               T q[kNodeSlots];
-              load_node(nd0 + (b * W + a) * kNodeSlots, q);
+              load_node(nd0 + (b * WF + a) * kNodeSlots, q);
 #pragma unroll
               for (int f = 0; f < 11; ++f) gv[f] += w * q[f];
             }
@@ -811,7 +813,7 @@ size_t tiled_lds_bytes(int dtype, int mode, const TileP& tp, bool naive) {
   // J window bytes per node: float32 a packed x/y pair, z (and rho) in 32
   // bits; float64 three (four) planes
   const size_t jb = dtype == PIC_F32 ? (naive ? 16 : 12) : (naive ? 32 : 24);
-  return (mode != MODE_DEPOSIT ? (size_t)kNodeSlots * tp.win_pad * es : 0) +
+  return (mode != MODE_DEPOSIT ? (size_t)kNodeSlots * field_window_nodes(tp.win, (int)es) * es : 0) +
          (mode != MODE_GATHER_PUSH ? jb * (tp.win_pad + 8) + 8 : 0);
 }
 
