@@ -51,13 +51,13 @@ struct LamRef {
   }
 };
 
-// Push adjoint of one particle: gathered values gv (and their x, y
-// derivatives gdx, gdy, per unit node coordinate) at x^{n+1}; P^n, v^n,
-// v^{n-1}; lambda^{n+1} in lam in, lambda (all but the deposit part) out.
-// Returns lambda_g in lg[11] (to be scattered onto the mesh fields).
-__device__ __forceinline__ void adj_push_one(const double* gv, const double* gdx, const double* gdy, double P0,
-                                             double P1, double P2, double v0, double v1, double v2, double w0,
-                                             double w1, double w2, const PhysP& ph, const GridP& g,
+// Push adjoint of one particle: gathered values gv at x^{n+1}; P^n, v^n,
+// v^{n-1}; lambda^{n+1} in lam in, lambda of P, v^n and v^{n-1} out.  Returns
+// lambda_g in lg[11]: the callers scatter it onto the mesh fields and add the
+// gather's position term, sum_f lg[f] d gv[f] / dx, to lambda_x (and the same
+// for y).
+__device__ __forceinline__ void adj_push_one(const double* gv, double P0, double P1, double P2, double v0, double v1,
+                                             double v2, double w0, double w1, double w2, const PhysP& ph,
                                              const LamRef& lam, double* lg) {
   // forward push (IAEM) with its intermediates
   const double q = ph.q, dt = ph.dt, c2 = ph.c * ph.c, mc2 = ph.m * c2;
@@ -91,14 +91,6 @@ __device__ __forceinline__ void adj_push_one(const double* gv, const double* gdx
   const double lsx = lFx * gv[5] + lFy * gv[8];
   const double lsy = lFx * gv[6] + lFy * gv[9];
   const double lsz = lFx * gv[7] + lFy * gv[10];
-  double lxg = 0.0, lyg = 0.0;
-#pragma unroll
-  for (int f = 0; f < 11; ++f) {
-    lxg += lg[f] * gdx[f];
-    lyg += lg[f] * gdy[f];
-  }
-  lam(0) += lxg * g.inv_dx;  // lambda of x^{n+1}, deposit part still to come
-  lam(1) += lyg * g.inv_dy;
   lam(2) = lPx;  // final: P enters only through P'
   lam(3) = lPy;
   lam(4) = lPz;
@@ -177,9 +169,17 @@ __global__ void __launch_bounds__(256) k_adj_push(const InstDesc* __restrict__ D
     gather_d<DEG, 11>(F, plane, wx, dwx, wy, dwy, sx, sy, g, 0, true, gv, gdx, gdy);
   }
   double lg[11];
-  adj_push_one(gv, gdx, gdy, p.P[0][i], p.P[1][i], p.P[2][i], p.v[0][i], p.v[1][i], p.v[2][i], p.w[0][i],
-               p.w[1][i], p.w[2][i], ph, g, lam, lg);
+  adj_push_one(gv, p.P[0][i], p.P[1][i], p.P[2][i], p.v[0][i], p.v[1][i], p.v[2][i], p.w[0][i], p.w[1][i],
+               p.w[2][i], ph, lam, lg);
   if (!inside) return;
+  double lxg = 0.0, lyg = 0.0;
+#pragma unroll
+  for (int f = 0; f < 11; ++f) {
+    lxg += lg[f] * gdx[f];
+    lyg += lg[f] * gdy[f];
+  }
+  lam(0) += lxg * g.inv_dx;  // lambda of x^{n+1}, deposit part still to come
+  lam(1) += lyg * g.inv_dy;
   const gptr<double> LF = gp(d.LF);
 #pragma unroll
   for (int b = 0; b < S::NW; ++b) {
@@ -237,32 +237,46 @@ __device__ __forceinline__ void adj_load_window(double* __restrict__ dst, gptr<c
 // (at most 256 VGPRs each: two waves per SIMD)
 constexpr int kAdjPushThreads = 512;
 
-template <int DEG>
+// the work item of this workgroup, its fields wave-uniform (scalar
+// registers: the particle arrays' bases offset by its first particle stay
+// scalar)
+__device__ __forceinline__ int4 adj_item(const InstDesc& d) {
+  const int4 w = d.tb.work[blockIdx.x];
+  return make_int4(__builtin_amdgcn_readfirstlane(w.x), __builtin_amdgcn_readfirstlane(w.y),
+                   __builtin_amdgcn_readfirstlane(w.z), 0);
+}
+
+template <int DEG, int TS, int SL>
 __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* __restrict__ D, StepArgs sa,
                                                                 double* lam_, int64_t ls) {
   using S = Spline<double, DEG>;
   constexpr int NW = S::NW;
+  constexpr bool FIXED = TS > 0;  // compiled window geometry: immediate LDS offsets
+  using G = Geo<(FIXED ? TS : 1), (FIXED ? SL : 0)>;
   const InstDesc& d = D[0];
   if ((int)blockIdx.x >= *d.tb.nwork) return;
-  const int4 it = d.tb.work[blockIdx.x];
+  const int4 it = adj_item(d);
+  const int first = it.y, count = it.z;
   const GridP g = d.g;
   const PhysP ph = d.ph;
-  const GParts<double> p = parts_from(global_parts(make_parts<double>(d, sa.cur, sa.vflip)), it.y);
-  const gptr<double> lamb = gp(lam_) + it.y;
+  const GParts<double> pall = global_parts(make_parts<double>(d, sa.cur, sa.vflip));
   const gptr<const double> F = gp((const double*)d.F64);
   const gptr<double> LF = gp(d.LF);
   const size_t plane = (size_t)g.nx * g.ny;
-  const AdjWin a = adj_window(d, it);
-  const int W = a.W, WP = a.WP;
   extern __shared__ double2 sm[];
   double* fw = reinterpret_cast<double*>(sm);  // [11][WP] mesh fields of level n+1
-  double* lw = fw + 11 * WP;                   // [11][WP] their adjoints
+  const int lane = threadIdx.x & 63;
+  const AdjWin a = adj_window(d, it);
+  const int W = FIXED ? G::W : a.W, WP = FIXED ? G::WP : a.WP;
+  double* lw = fw + 11 * WP;  // [11][WP] their adjoints
   adj_load_window(fw, F, 11, a, g);
   for (int t = threadIdx.x; t < 11 * WP; t += blockDim.x) lw[t] = 0.0;
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
-    const LamRef lam{lamb, ls, (uint32_t)k};
+  const GParts<double> p = parts_from(pall, first);
+  const gptr<double> lamb = gp(lam_) + first;
+  for (int k0 = threadIdx.x; k0 < count; k0 += blockDim.x) {
+    const uint32_t k = opaque_index(k0);
+    const LamRef lam{lamb, ls, k};
     const double xi = elt(p.x, k) * g.inv_dx, eta = elt(p.y, k) * g.inv_dy;
     const bool inside = in_box(xi, eta, g);
     int sx = 0, sy = 0, lx = 0, ly = 0;
@@ -283,13 +297,16 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
         gather_d<DEG, 11>(F, plane, wx, dwx, wy, dwy, sx, sy, g, 0, true, gv, gdx, gdy);
     }
     double lg[11];
-    adj_push_one(gv, gdx, gdy, elt(p.P[0], k), elt(p.P[1], k), elt(p.P[2], k), elt(p.v[0], k), elt(p.v[1], k),
-                 elt(p.v[2], k), elt(p.w[0], k), elt(p.w[1], k), elt(p.w[2], k), ph, g, lam, lg);
-    // the scatter visits its stencil in the residue-class order of the
-    // forward deposit: at step (a, b) lane l adds to the node whose absolute
-    // indices are congruent to (a + l, b + l / NW) modulo NW, so at most
-    // 64 / NW^2 lanes meet on one window address, whatever cells the wave's
-    // particles are in
+    adj_push_one(gv, elt(p.P[0], k), elt(p.P[1], k), elt(p.P[2], k), elt(p.v[0], k), elt(p.v[1], k),
+                 elt(p.v[2], k), elt(p.w[0], k), elt(p.w[1], k), elt(p.w[2], k), ph, lam, lg);
+    double lxg = 0.0, lyg = 0.0;
+#pragma unroll
+    for (int f = 0; f < 11; ++f) {
+      lxg += lg[f] * gdx[f];
+      lyg += lg[f] * gdy[f];
+    }
+    lam(0) += lxg * g.inv_dx;  // lambda of x^{n+1}, deposit part still to come
+    lam(1) += lyg * g.inv_dy;
     const int ra = ((lane - sx) % NW + NW) % NW, rb = ((lane / NW - sy) % NW + NW) % NW;
     double wxr[NW], wyr[NW];
     int coff[NW], roff[NW];
@@ -343,29 +360,34 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
     }
 }
 
-template <int DEG>
+template <int DEG, int TS, int SL>
 __global__ void __launch_bounds__(256) k_adj_deposit_t(const InstDesc* __restrict__ D, StepArgs sa,
                                                        double* lam_, int64_t ls) {
   using S = Spline<double, DEG>;
   constexpr int NW = S::NW;
+  constexpr bool FIXED = TS > 0;  // compiled window geometry: immediate LDS offsets
+  using G = Geo<(FIXED ? TS : 1), (FIXED ? SL : 0)>;
   const InstDesc& d = D[0];
   if ((int)blockIdx.x >= *d.tb.nwork) return;
-  const int4 it = d.tb.work[blockIdx.x];
+  const int4 it = adj_item(d);
+  const int first = it.y, count = it.z;
   const GridP g = d.g;
   const PhysP ph = d.ph;
-  const GParts<double> p = parts_from(global_parts(make_parts<double>(d, sa.cur, sa.vflip)), it.y);
-  const gptr<double> lamb = gp(lam_) + it.y;
+  const GParts<double> pall = global_parts(make_parts<double>(d, sa.cur, sa.vflip));
   const gptr<const double> LJ = gp((const double*)d.LJ);
   const size_t plane = (size_t)g.nx * g.ny;
-  const AdjWin a = adj_window(d, it);
-  const int W = a.W, WP = a.WP;
   extern __shared__ double2 sm[];
   double* jw = reinterpret_cast<double*>(sm);  // [3][WP] lambda_J
+  const double s = ph.q * g.inv_area;
+  const AdjWin a = adj_window(d, it);
+  const int W = FIXED ? G::W : a.W, WP = FIXED ? G::WP : a.WP;
   adj_load_window(jw, LJ, 3, a, g);
   __syncthreads();
-  const double s = ph.q * g.inv_area;
-  for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
-    const LamRef lam{lamb, ls, (uint32_t)k};
+  const GParts<double> p = parts_from(pall, first);
+  const gptr<double> lamb = gp(lam_) + first;
+  for (int k0 = threadIdx.x; k0 < count; k0 += blockDim.x) {
+    const uint32_t k = opaque_index(k0);
+    const LamRef lam{lamb, ls, k};
     const double xi = elt(p.x, k) * g.inv_dx, eta = elt(p.y, k) * g.inv_dy;
     double av[3] = {0, 0, 0}, bx[3] = {0, 0, 0}, by[3] = {0, 0, 0};
     if (in_box(xi, eta, g)) {
@@ -631,14 +653,16 @@ __global__ void k_adj_initial(int64_t n, const double* __restrict__ P, PhysP ph,
 }
 
 // ---------------------------------------------------------------------------
-// The held particle adjoint.  k_lam_set: from original order (lam[11][n],
-// null: zero), slot i holding particle i.  k_lam_get: back to original order.
+// The held particle adjoint.  k_lam_set: from original order (lam[11][n]),
+// slot i holding particle i; null: zero, in the slot order of the set the
+// passes run on (ids), so that no permutation follows.  k_lam_get: back to
+// original order.
 __global__ void k_lam_set(int64_t n, const double* __restrict__ src, double* __restrict__ LAM, int64_t ls,
-                          int32_t* __restrict__ LIDS) {
+                          int32_t* __restrict__ LIDS, const int32_t* __restrict__ ids) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   for (int f = 0; f < 11; ++f) LAM[f * ls + i] = src ? src[f * n + i] : 0.0;
-  LIDS[i] = (int32_t)i;
+  LIDS[i] = src ? (int32_t)i : ids[i];
 }
 
 __global__ void k_lam_get(int64_t n, const double* __restrict__ LAM, int64_t ls, const int32_t* __restrict__ LIDS,
@@ -694,9 +718,10 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-hipError_t launch_lam_set(int64_t n, const double* src, double* LAM, int64_t ls, int32_t* LIDS, hipStream_t s) {
+hipError_t launch_lam_set(int64_t n, const double* src, double* LAM, int64_t ls, int32_t* LIDS, const int32_t* ids,
+                          hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lam_set, dim3(blocks_for(n)), dim3(256), 0, s, n, src, LAM, ls, LIDS);
+  hipLaunchKernelGGL(k_lam_set, dim3(blocks_for(n)), dim3(256), 0, s, n, src, LAM, ls, LIDS, ids);
   return hipGetLastError();
 }
 
@@ -744,31 +769,47 @@ hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs
 
 size_t adj_tiled_lds_bytes(const TileP& tp, bool push) { return (size_t)(push ? 22 : 3) * tp.win_pad * 8; }
 
-hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblocks, size_t lds, StepArgs sa,
+hipError_t launch_adj_tiled(bool push, int degree, int geo, const InstDesc* D, int nblocks, size_t lds, StepArgs sa,
                             double* lam, int64_t ls, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   const void* fn = nullptr;
   if (push)
-    fn = degree == 1 ? (const void*)k_adj_push_t<1> : degree == 2 ? (const void*)k_adj_push_t<2>
-                                                                     : (const void*)k_adj_push_t<3>;
+    fn = degree == 1 ? (const void*)k_adj_push_t<1, 0, 0>
+         : degree == 2 ? (const void*)k_adj_push_t<2, 0, 0>
+         : geo == 1    ? (const void*)k_adj_push_t<3, 16, 3>
+         : geo == 2    ? (const void*)k_adj_push_t<3, 8, 3>
+                       : (const void*)k_adj_push_t<3, 0, 0>;
   else
-    fn = degree == 1 ? (const void*)k_adj_deposit_t<1> : degree == 2 ? (const void*)k_adj_deposit_t<2>
-                                                                        : (const void*)k_adj_deposit_t<3>;
+    fn = degree == 1 ? (const void*)k_adj_deposit_t<1, 0, 0>
+         : degree == 2 ? (const void*)k_adj_deposit_t<2, 0, 0>
+         : geo == 1    ? (const void*)k_adj_deposit_t<3, 16, 3>
+         : geo == 2    ? (const void*)k_adj_deposit_t<3, 8, 3>
+                       : (const void*)k_adj_deposit_t<3, 0, 0>;
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (push) {
-    switch (degree) {
-      case 1: hipLaunchKernelGGL(k_adj_push_t<1>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam, ls); break;
-      case 2: hipLaunchKernelGGL(k_adj_push_t<2>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam, ls); break;
-      default:
-        hipLaunchKernelGGL(k_adj_push_t<3>, dim3(nblocks), dim3(kAdjPushThreads), lds, s, D, sa, lam, ls);
-        break;
-    }
+    const dim3 grid(nblocks), block(kAdjPushThreads);
+    if (degree == 1)
+      hipLaunchKernelGGL((k_adj_push_t<1, 0, 0>), grid, block, lds, s, D, sa, lam, ls);
+    else if (degree == 2)
+      hipLaunchKernelGGL((k_adj_push_t<2, 0, 0>), grid, block, lds, s, D, sa, lam, ls);
+    else if (geo == 1)
+      hipLaunchKernelGGL((k_adj_push_t<3, 16, 3>), grid, block, lds, s, D, sa, lam, ls);
+    else if (geo == 2)
+      hipLaunchKernelGGL((k_adj_push_t<3, 8, 3>), grid, block, lds, s, D, sa, lam, ls);
+    else
+      hipLaunchKernelGGL((k_adj_push_t<3, 0, 0>), grid, block, lds, s, D, sa, lam, ls);
   } else {
-    switch (degree) {
-      case 1: hipLaunchKernelGGL(k_adj_deposit_t<1>, dim3(nblocks), dim3(256), lds, s, D, sa, lam, ls); break;
-      case 2: hipLaunchKernelGGL(k_adj_deposit_t<2>, dim3(nblocks), dim3(256), lds, s, D, sa, lam, ls); break;
-      default: hipLaunchKernelGGL(k_adj_deposit_t<3>, dim3(nblocks), dim3(256), lds, s, D, sa, lam, ls); break;
-    }
+    const dim3 grid(nblocks), block(256);
+    if (degree == 1)
+      hipLaunchKernelGGL((k_adj_deposit_t<1, 0, 0>), grid, block, lds, s, D, sa, lam, ls);
+    else if (degree == 2)
+      hipLaunchKernelGGL((k_adj_deposit_t<2, 0, 0>), grid, block, lds, s, D, sa, lam, ls);
+    else if (geo == 1)
+      hipLaunchKernelGGL((k_adj_deposit_t<3, 16, 3>), grid, block, lds, s, D, sa, lam, ls);
+    else if (geo == 2)
+      hipLaunchKernelGGL((k_adj_deposit_t<3, 8, 3>), grid, block, lds, s, D, sa, lam, ls);
+    else
+      hipLaunchKernelGGL((k_adj_deposit_t<3, 0, 0>), grid, block, lds, s, D, sa, lam, ls);
   }
   return hipGetLastError();
 }

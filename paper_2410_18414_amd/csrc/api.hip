@@ -433,35 +433,44 @@ __global__ void k_state_header(int64_t* h, HeaderWords hw, int count) {
   if ((int)threadIdx.x < count) h[threadIdx.x] = hw.w[threadIdx.x];
 }
 
-// copy every segment of the list: 16-byte vectors (segments of 16 bytes or
-// more start 16-byte aligned on both sides), a shorter tail in 4-byte words
+// copy every segment of the list: each workgroup copies one span of
+// kCopySpan bytes of one segment (the segment found by a wave-uniform scan of
+// the block prefix sums), every thread kCopyUnroll 16-byte vectors in flight;
+// segments of 16 bytes or more start 16-byte aligned on both sides, a shorter
+// tail goes in 4-byte words
 constexpr int kCopyMax = 32;
+constexpr int kCopyThreads = 256, kCopyUnroll = 4;
+constexpr uint64_t kCopySpan = (uint64_t)kCopyThreads * kCopyUnroll * 16;
 struct CopyList {
   int count;
-  uint64_t first[kCopyMax + 1];  // prefix sums of the segments' 16-byte chunks
+  uint64_t first[kCopyMax + 1];  // prefix sums of the segments' spans (workgroups)
   const char* src[kCopyMax];
   char* dst[kCopyMax];
   uint64_t bytes[kCopyMax];
 };
 
-__global__ void __launch_bounds__(256) k_copy_list(CopyList L) {
-  const uint64_t total = L.first[L.count];
-  for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
-       q += (uint64_t)gridDim.x * blockDim.x) {
-    int lo = 0, hi = L.count - 1;  // the segment holding chunk q: last with first <= q
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (L.first[mid] <= q) lo = mid;
-      else hi = mid - 1;
-    }
-    const uint64_t off = (q - L.first[lo]) * 16, rem = L.bytes[lo] - off;
-    const gptr<const char> src = gp(L.src[lo]) + off;
-    const gptr<char> dst = gp(L.dst[lo]) + off;
-    if (rem >= 16) {
-      *reinterpret_cast<gptr<i32x4>>(dst) = *reinterpret_cast<gptr<const i32x4>>(src);
-    } else {
-      for (uint64_t b = 0; b < rem; b += 4)
-        *reinterpret_cast<gptr<int32_t>>(dst + b) = *reinterpret_cast<gptr<const int32_t>>(src + b);
+__global__ void __launch_bounds__(kCopyThreads) k_copy_list(CopyList L) {
+  const uint64_t b = blockIdx.x;
+  int sg = 0;
+  while (sg + 1 < L.count && L.first[sg + 1] <= b) ++sg;
+  const uint64_t base = (b - L.first[sg]) * kCopySpan;
+  const uint64_t nbytes = L.bytes[sg];
+  const gptr<const char> src = gp(L.src[sg]);
+  const gptr<char> dst = gp(L.dst[sg]);
+  i32x4 v[kCopyUnroll];
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const uint64_t off = base + (uint64_t)(u * kCopyThreads + threadIdx.x) * 16;
+    if (off + 16 <= nbytes) v[u] = *reinterpret_cast<gptr<const i32x4>>(src + off);
+  }
+#pragma unroll
+  for (int u = 0; u < kCopyUnroll; ++u) {
+    const uint64_t off = base + (uint64_t)(u * kCopyThreads + threadIdx.x) * 16;
+    if (off + 16 <= nbytes) {
+      *reinterpret_cast<gptr<i32x4>>(dst + off) = v[u];
+    } else if (off < nbytes) {
+      for (uint64_t q = off; q < nbytes; q += 4)
+        *reinterpret_cast<gptr<int32_t>>(dst + q) = *reinterpret_cast<gptr<const int32_t>>(src + q);
     }
   }
 }
@@ -1476,10 +1485,11 @@ static std::vector<std::array<size_t, 3>> state_segments(pic_ctx_t c, int cur, c
 // at most kCopyMax segments (one launch for a single-instance context)
 static pic_status_t copy_segments(pic_ctx_t c, const std::vector<std::array<size_t, 3>>& seg, char* state,
                                   bool to_state) {
-  for (size_t s0 = 0; s0 < seg.size(); s0 += kCopyMax) {
+  size_t k = 0;  // next segment to copy
+  while (k < seg.size()) {
     CopyList L{};
-    uint64_t chunks = 0;
-    for (size_t k = s0; k < seg.size() && L.count < kCopyMax; ++k) {
+    uint64_t spans = 0;
+    for (; k < seg.size() && L.count < kCopyMax; ++k) {
       const auto& g = seg[k];
       if (g[2] == 0) continue;
       char* sp = state + g[0];
@@ -1489,14 +1499,14 @@ static pic_status_t copy_segments(pic_ctx_t c, const std::vector<std::array<size
       L.src[L.count] = to_state ? cp : sp;
       L.dst[L.count] = to_state ? sp : cp;
       L.bytes[L.count] = g[2];
-      L.first[L.count] = chunks;
-      chunks += (g[2] + 15) / 16;
+      L.first[L.count] = spans;
+      spans += (g[2] + kCopySpan - 1) / kCopySpan;
       L.count++;
     }
     if (!L.count) continue;
-    L.first[L.count] = chunks;
-    const unsigned blocks = (unsigned)std::min<uint64_t>((chunks + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_copy_list, dim3(blocks), dim3(256), 0, c->stream, L);
+    L.first[L.count] = spans;
+    if (spans > 0x7fffffffu) return c->fail(PIC_ERR_INVALID_ARG, "state copy larger than the grid allows");
+    hipLaunchKernelGGL(k_copy_list, dim3((unsigned)spans), dim3(kCopyThreads), 0, c->stream, L);
     pic_status_t st = c->hip(hipGetLastError(), "state copy");
     if (st) return st;
   }
@@ -1619,7 +1629,8 @@ pic_status_t pic_adjoint_set_particles(pic_ctx_t c, const double* lam) {
   pic_status_t st = adjoint_check(c, false);
   if (st) return st;
   Instance& in = c->I();
-  st = c->hip(launch_lam_set(in.d.n, lam, in.d.LAM, in.cfg.max_particles, in.d.LIDS, c->stream), "adjoint set");
+  st = c->hip(launch_lam_set(in.d.n, lam, in.d.LAM, in.cfg.max_particles, in.d.LIDS, in.d.ids[c->cur], c->stream),
+              "adjoint set");
   c->lam_n = st ? -1 : in.d.n;
   return st;
 }
@@ -1664,15 +1675,16 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
   (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   const size_t lds_push = adj_tiled_lds_bytes(in.d.tp, true), lds_dep = adj_tiled_lds_bytes(in.d.tp, false);
   const bool tiled = c->sorted && lds_push <= (size_t)max_lds;
+  const int geo = tiled_geometry(in.d.tp), nwb = c->nblk[BK_WORK];
   if (!st)
-    st = c->hip(tiled ? launch_adj_tiled(true, c->degree, D, c->nblk[BK_WORK], lds_push, sa, in.d.LAM, ls, c->stream)
+    st = c->hip(tiled ? launch_adj_tiled(true, c->degree, geo, D, nwb, lds_push, sa, in.d.LAM, ls, c->stream)
                       : launch_adj_push(c->degree, D, in.d.n, sa, in.d.LAM, ls, c->stream),
                 "adjoint push");
   if (!st) st = c->hip(launch_rows_r2c(D, 1, 11 * (ny / in.d.R_r2c), c->lds_r2c, c->stream, true), "adjoint rows_r2c");
   if (!st) st = c->hip(launch_adj_columns(in.cfg.bdf_order, D, nx / 2 + 1, c->lds_adj_col, lam_hist, c->stream), "adjoint columns");
   if (!st) st = c->hip(launch_rows_c2r(D, 1, 2 * (ny / in.d.R_c2r), c->lds_c2r, c->stream, true), "adjoint rows_c2r");
   if (!st)
-    st = c->hip(tiled ? launch_adj_tiled(false, c->degree, D, c->nblk[BK_WORK], lds_dep, sa, in.d.LAM, ls, c->stream)
+    st = c->hip(tiled ? launch_adj_tiled(false, c->degree, geo, D, nwb, lds_dep, sa, in.d.LAM, ls, c->stream)
                       : launch_adj_deposit(c->degree, D, in.d.n, sa, in.d.LAM, ls, c->stream),
                 "adjoint deposit");
   if (!st && lam) st = pic_adjoint_get_particles(c, lam);

@@ -14,6 +14,24 @@ namespace pic {
 template <typename T, int DEG>
 struct Spline {
   static constexpr int NW = DEG + 1;
+  // eval_unit: the weights times kUnit (cubic: 6 w, its common factor 1/6 left
+  // out; other degrees: w), for passes that fold 1 / kUnit^2 into the
+  // constants the weight products multiply
+  static constexpr double kUnit = DEG == 3 ? 6.0 : 1.0;
+  __device__ __forceinline__ static void eval_unit(T xi, int& s, T* w) {
+    if constexpr (DEG == 3) {
+      const T f = floor(xi);
+      const T d = xi - f;  // in [0, 1)
+      s = (int)f - 1;
+      const T d2 = d * d, d3 = d2 * d, e = T(1) - d;
+      w[0] = e * e * e;
+      w[1] = T(4) - T(6) * d2 + T(3) * d3;
+      w[2] = T(1) + T(3) * d + T(3) * d2 - T(3) * d3;
+      w[3] = d3;
+    } else {
+      eval(xi, s, w);
+    }
+  }
   // first node index s (may be -1 or up to n+1 before wrapping) and weights
   __device__ __forceinline__ static void eval(T xi, int& s, T* w) {
     if (DEG == 1) {

@@ -147,6 +147,15 @@ __device__ __forceinline__ __attribute__((address_space(1))) T& elt(gptr<T> b, u
   return *(gptr<T>)((__attribute__((address_space(1))) char*)b + k * (uint32_t)sizeof(T));
 }
 
+// k with its relation to the previous iteration hidden from the loop
+// optimiser: in a loop over particles, every elt() access then stays scalar
+// base + 32-bit offset instead of becoming a per-lane 64-bit pointer carried
+// around the loop (two VGPRs per array)
+__device__ __forceinline__ uint32_t opaque_index(uint32_t k) {
+  asm volatile("" : "+v"(k));
+  return k;
+}
+
 template <typename T>
 __device__ __forceinline__ GParts<T> global_parts(const Parts<T>& p) {
   GParts<T> g;
@@ -201,6 +210,17 @@ struct TileP {
   int chunk;       // max particles per workgroup
   int max_work;    // ntiles + ceil(capacity/chunk): bound on the chunk count
   int pow2;        // 1: nx and ny are powers of two (node indices wrap by masks)
+};
+
+// Window geometry: compile-time for the compiled tile shapes (TS > 0: tiles of
+// TS x TS cells, slack SL), so that every window offset of the gather and the
+// deposit is an immediate of the LDS instruction; TS = 0 reads it from TileP.
+template <int TS, int SL>
+struct Geo {
+  static constexpr int W = TS + 2 * SL + 3;
+  static constexpr int WP = (W * W + 63) / 64 * 64;
+  static constexpr int RL = W <= 8 ? 8 : (W <= 16 ? 16 : (W <= 32 ? 32 : 64));
+  static constexpr int LRL = RL == 8 ? 3 : (RL == 16 ? 4 : (RL == 32 ? 5 : 6));
 };
 
 // Particles are counting-sorted by cell, cells numbered tile-major (the
@@ -383,14 +403,15 @@ hipError_t launch_adj_push(int degree, const InstDesc* D, int64_t n, StepArgs sa
                            hipStream_t s);
 hipError_t launch_adj_deposit(int degree, const InstDesc* D, int64_t n, StepArgs sa, double* lam, int64_t ls,
                               hipStream_t s);
-hipError_t launch_lam_set(int64_t n, const double* src, double* LAM, int64_t ls, int32_t* LIDS, hipStream_t s);
+hipError_t launch_lam_set(int64_t n, const double* src, double* LAM, int64_t ls, int32_t* LIDS, const int32_t* ids,
+                          hipStream_t s);
 hipError_t launch_lam_get(int64_t n, const double* LAM, int64_t ls, const int32_t* LIDS, double* dst, hipStream_t s);
 hipError_t launch_lam_follow(int64_t n, const int32_t* ids, double* LAM, double* LAM2, int64_t ls, int32_t* LIDS,
                              int32_t* LINV, int32_t* flag, hipStream_t s);
 // cell-sorted variants over the forward's chunks (push: mesh fields and their
 // adjoints in LDS windows; deposit: lambda_J window)
 size_t adj_tiled_lds_bytes(const TileP& tp, bool push);
-hipError_t launch_adj_tiled(bool push, int degree, const InstDesc* D, int nblocks, size_t lds, StepArgs sa,
+hipError_t launch_adj_tiled(bool push, int degree, int geo, const InstDesc* D, int nblocks, size_t lds, StepArgs sa,
                             double* lam, int64_t ls, hipStream_t s);
 hipError_t launch_adj_columns(int bdf_order, const InstDesc* D, int nxh, size_t lds, double* lam_hist, hipStream_t s);
 hipError_t launch_adj_seed_energy(const double2* H, GridP g, SchemeCoef sc, HistSlots hs, double scale,

@@ -25,6 +25,7 @@
 // The per-particle arithmetic (spline weights, IAEM push, position update) is
 // shared with the untiled kernels through particle_math.h.
 #include "particle_math.h"
+#include <type_traits>
 
 namespace pic {
 
@@ -334,17 +335,6 @@ struct Acc {
   using type = double;
 };
 
-// Window geometry: compile-time for the compiled tile shapes (TS > 0: tiles of
-// TS x TS cells, slack SL), so that every window offset of the gather and the
-// deposit is an immediate of the LDS instruction; TS = 0 reads it from TileP.
-template <int TS, int SL>
-struct Geo {
-  static constexpr int W = TS + 2 * SL + 3;
-  static constexpr int WP = (W * W + 63) / 64 * 64;
-  static constexpr int RL = W <= 8 ? 8 : (W <= 16 ? 16 : (W <= 32 ? 32 : 64));
-  static constexpr int LRL = RL == 8 ? 3 : (RL == 16 ? 4 : (RL == 32 ? 5 : 6));
-};
-
 template <typename T, int DEG, int MODE, int TS, int SL>
 __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__ D, int ninst, StepArgs sa) {
   constexpr bool GATHER = MODE != MODE_DEPOSIT;
@@ -500,7 +490,12 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
 
   using S = Spline<T, DEG>;
   constexpr int NW = S::NW;
-  const T dt = T(ph.dt), qs = T(ph.q) * T(g.inv_area);
+  // the spline weights are evaluated times S::kUnit (eval_unit): their products
+  // carry kUnit^2, which the charge factors of the deposit and of the push
+  // take back
+  const T dt = T(ph.dt), qs = T(ph.q * g.inv_area / (S::kUnit * S::kUnit));
+  PhysP phu = ph;
+  phu.q = ph.q / (S::kUnit * S::kUnit);
   // Float32 particles deposit in fixed point: J_x and J_y as one packed pair
   // of int32 in a 64-bit integer atomic, J_z in a 32-bit one (two LDS atomics
   // per node instead of three float64 ones).  The scale is a power of two
@@ -536,8 +531,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       if (in_box(xi, eta, g)) {
         int sx, sy;
         T wx[NW], wy[NW];
-        S::eval(xi, sx, wx);
-        S::eval(eta, sy, wy);
+        S::eval_unit(xi, sx, wx);
+        S::eval_unit(eta, sy, wy);
         const int lx = modw(sx - ox, g.nx), ly = modw(sy - oy, g.ny);
         if (lx + DEG < W && ly >= jlo && ly + DEG < jhi) {
           const T* nd0 = fw + (ly * WF + lx) * kNodeSlots;
@@ -557,7 +552,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         }
       }
       T nvx, nvy, nvz;
-      push_one<T>(gv, Px, Py, Pz, vx, vy, vz, w0, w1, w2, ph, nvx, nvy, nvz);
+      push_one<T>(gv, Px, Py, Pz, vx, vy, vz, w0, w1, w2, phu, nvx, nvy, nvz);
       elt(p.P[0], k) = Px;
       elt(p.P[1], k) = Py;
       elt(p.w[0], k) = nvx;
@@ -592,10 +587,18 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
           elt(p.x, k) = x;
           elt(p.y, k) = y;
         }
-        const T xi = x * T(g.inv_dx), eta = y * T(g.inv_dy);
-        if (in_box(xi, eta, g)) {
-          S::eval(xi, sx, wx);
-          S::eval(eta, sy, wy);
+        // a particle outside the box (not finite, or never wrapped) deposits
+        // zero current with zero weights at a stand-in position inside it: no
+        // branch around the deposit's set-up, whose zero-initialised values
+        // would cost more than the selects
+        const T xi0 = x * T(g.inv_dx), eta0 = y * T(g.inv_dy);
+        const bool box = in_box(xi0, eta0, g);
+        const T xi = box ? xi0 : T(0.5), eta = box ? eta0 : T(0.5);
+        {
+          S::eval_unit(xi, sx, wx);
+          S::eval_unit(eta, sy, wy);
+#pragma unroll
+          for (int a = 0; a < NW; ++a) wx[a] = box ? wx[a] : T(0);
           if (jv) {
             jx = qs * (T(2) * vx - w0);
             jy = qs * (T(2) * vy - w1);
@@ -605,6 +608,9 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
             jy = qs * vy;
             jz = qs * vz;
           }
+          jx = box ? jx : T(0);
+          jy = box ? jy : T(0);
+          jz = box ? jz : T(0);
           lx = modw(sx - ox, g.nx);
           ly = modw(sy - oy, g.ny);
           inw = lx + DEG < W && ly + DEG < W;
@@ -656,7 +662,8 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         // halves that each issue both atomics)
         if constexpr (FIXEDPT) {
           const T sjx = jx * qscale, sjy = jy * qscale, sjz = jz * qscale, sjr = qs * qscale;
-          if (inw) {
+          // the charge plane's test is taken once, outside the node loops
+          auto node_loops = [&](auto with_rho) {
             const int base = ly * W + lx;
 #pragma unroll
             for (int b = 0; b < NW; ++b) {
@@ -677,12 +684,18 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
                 const uint64_t pk = (((uint64_t)by << 32) | bx) - kMagicPair;
                 atomicAdd(reinterpret_cast<unsigned long long*>(xy_row + cxy[a]), (unsigned long long)pk);
                 atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a]), bz - kMagicBits);
-                if (naive) {
+                if constexpr (decltype(with_rho)::value) {
                   const uint32_t br = __float_as_uint(__builtin_fmaf(sjr, w, kMagic));
                   atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a] + 4 * JWP), br - kMagicBits);
                 }
               }
             }
+          };
+          if (inw) {
+            if (naive)
+              node_loops(std::true_type{});
+            else
+              node_loops(std::false_type{});
           }
         } else if (inw && det) {
           // deterministic deposit (float64): int64 window sums of the products
