@@ -25,7 +25,6 @@
 // The per-particle arithmetic (spline weights, IAEM push, position update) is
 // shared with the untiled kernels through particle_math.h.
 #include "particle_math.h"
-#include <type_traits>
 
 namespace pic {
 
@@ -662,8 +661,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
         // halves that each issue both atomics)
         if constexpr (FIXEDPT) {
           const T sjx = jx * qscale, sjy = jy * qscale, sjz = jz * qscale, sjr = qs * qscale;
-          // the charge plane's test is taken once, outside the node loops
-          auto node_loops = [&](auto with_rho) {
+          if (inw) {
             const int base = ly * W + lx;
 #pragma unroll
             for (int b = 0; b < NW; ++b) {
@@ -684,18 +682,21 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
                 const uint64_t pk = (((uint64_t)by << 32) | bx) - kMagicPair;
                 atomicAdd(reinterpret_cast<unsigned long long*>(xy_row + cxy[a]), (unsigned long long)pk);
                 atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a]), bz - kMagicBits);
-                if constexpr (decltype(with_rho)::value) {
-                  const uint32_t br = __float_as_uint(__builtin_fmaf(sjr, w, kMagic));
-                  atomicAdd(reinterpret_cast<uint32_t*>(z_row + cz[a] + 4 * JWP), br - kMagicBits);
+              }
+            }
+            // the naive charge plane in a loop of its own: a test inside the
+            // node loop above costs every node two instructions
+            if (naive) {
+#pragma unroll
+              for (int b = 0; b < NW; ++b) {
+                unsigned char* r_row = reinterpret_cast<unsigned char*>(jr_w + base + roff[b]);
+#pragma unroll
+                for (int a = 0; a < NW; ++a) {
+                  const uint32_t br = __float_as_uint(__builtin_fmaf(sjr, wxr[a] * wyr[b], kMagic));
+                  atomicAdd(reinterpret_cast<uint32_t*>(r_row + cz[a]), br - kMagicBits);
                 }
               }
             }
-          };
-          if (inw) {
-            if (naive)
-              node_loops(std::true_type{});
-            else
-              node_loops(std::false_type{});
           }
         } else if (inw && det) {
           // deterministic deposit (float64): int64 window sums of the products
