@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
 // J^n history is a ring of two levels, read at J[0] by parts 0 and 1 + l and
 // written at J_new by part 1 + l only.
 constexpr int kColParts = 4;
+constexpr int kMaxStages = 3;  // DIRK stages: loops over them unrolled to this bound (registers, not scratch)
 constexpr int kColMaxModes = 4;  // modes per thread: ny <= 1024 with 256 threads
 
 template <int SCHEME, int K>
@@ -226,9 +227,12 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
       const double h = sc.dt, c2 = sc.c * sc.c, kappa = kxs * kxs + kys * kys;
       const int ns = sc.stages;
       auto advance = [&](double2& u, double2& v, const double2* S) {
-        double2 ku[3], kv[3];
-        for (int i = 0; i < ns; ++i) {
+        double2 ku[kMaxStages], kv[kMaxStages];
+#pragma unroll
+        for (int i = 0; i < kMaxStages; ++i) {
+          if (i >= ns) break;
           double2 U = u, V = v;
+#pragma unroll
           for (int j = 0; j < i; ++j) {
             U = cadd(U, cscale(ku[j], h * sc.dirkA[i][j]));
             V = cadd(V, cscale(kv[j], h * sc.dirkA[i][j]));
@@ -239,25 +243,32 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
           ku[i] = cdivr(cadd(V, cscale(src, hai * c2)), Li);
           kv[i] = cdivr(csub(cscale(src, c2), cscale(V, hai * c2 * kappa)), Li);
         }
-        for (int i = 0; i < ns; ++i) {
+#pragma unroll
+        for (int i = 0; i < kMaxStages; ++i) {
+          if (i >= ns) break;
           u = cadd(u, cscale(ku[i], h * sc.dirkB[i]));
           v = cadd(v, cscale(kv[i], h * sc.dirkB[i]));
         }
       };
-      double2 S[3];
+      double2 S[kMaxStages];
       if (part == 0) {
         const double2 rho_n = h0[m];
-        double2 rho = rho_n, rst[3];
+        double2 rho = rho_n, rst[kMaxStages];
         if (nst) {
           // sub-stepped currents: rho^(i) are the RK stage values of the
           // continuity equation, rho^{n+1} its final stage
-          double2 dv[3];
-          for (int i = 0; i < ns; ++i) {
+          double2 dv[kMaxStages];
+#pragma unroll
+          for (int i = 0; i < kMaxStages; ++i) {
+            if (i >= ns) break;
             dv[i] = divv(Jh[(2 * i) * N + ky], Jh[(2 * i + 1) * N + ky]);
             rho = csub(rho, cscale(dv[i], h * sc.dirkB[i]));
           }
-          for (int i = 0; i < ns; ++i) {
+#pragma unroll
+          for (int i = 0; i < kMaxStages; ++i) {
+            if (i >= ns) break;
             rst[i] = rho_n;
+#pragma unroll
             for (int j = 0; j <= i; ++j) rst[i] = csub(rst[i], cscale(dv[j], h * sc.dirkA[i][j]));
           }
         } else {
@@ -265,15 +276,21 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
             rho = Jh[ky];  // naive comparison: the deposited rho^{n+1}
           } else {
             const double2 J0 = Jh[ky], J1 = Jh[N + ky];
-            for (int i = 0; i < ns; ++i) {
+#pragma unroll
+            for (int i = 0; i < kMaxStages; ++i) {
+              if (i >= ns) break;
               const double2 X = cadd(cscale(h3[m], 1.0 - sc.dirkC[i]), cscale(J0, sc.dirkC[i]));
               const double2 Y = cadd(cscale(h4[m], 1.0 - sc.dirkC[i]), cscale(J1, sc.dirkC[i]));
               rho = csub(rho, cscale(divv(X, Y), h * sc.dirkB[i]));
             }
           }
-          for (int i = 0; i < ns; ++i) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
+#pragma unroll
+          for (int i = 0; i < kMaxStages; ++i)
+            if (i < ns) rst[i] = cadd(cscale(rho_n, 1.0 - sc.dirkC[i]), cscale(rho, sc.dirkC[i]));
         }
-        for (int i = 0; i < ns; ++i) S[i] = cscale(rst[i], 1.0 / sc.eps0);
+#pragma unroll
+        for (int i = 0; i < kMaxStages; ++i)
+          if (i < ns) S[i] = cscale(rst[i], 1.0 / sc.eps0);
         double2 u = h1[m], v = h2[m];
         advance(u, v, S);
         at(hs.rho_new, ky) = rho;
@@ -282,7 +299,9 @@ __global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restric
         out = u;
       } else {
         double2 keep = make_double2(0.0, 0.0);
-        for (int i = 0; i < ns; ++i) {
+#pragma unroll
+        for (int i = 0; i < kMaxStages; ++i) {
+          if (i >= ns) break;
           // stage current: sub-stepped, or interpolated between J^n and J^{n+1}
           const double2 Ji = nst ? Jh[i * N + ky]
                                  : cadd(cscale(h2[m], 1.0 - sc.dirkC[i]), cscale(Jh[ky], sc.dirkC[i]));
