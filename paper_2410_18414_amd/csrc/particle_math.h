@@ -137,7 +137,8 @@ __device__ __forceinline__ T wrapx(T x, T L) {
 // the stencil of such a point stays within one period of the wrap
 template <typename T>
 __device__ __forceinline__ bool in_box(T xi, T eta, const GridP& g) {
-  return xi >= T(0) && xi <= T(g.nx) && eta >= T(0) && eta <= T(g.ny);
+  // all four tests evaluated (no short-circuit): one branch on the result
+  return (xi >= T(0)) & (xi <= T(g.nx)) & (eta >= T(0)) & (eta <= T(g.ny));
 }
 
 // deposit with global float64 atomics, stencil already evaluated

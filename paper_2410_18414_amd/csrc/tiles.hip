@@ -565,12 +565,12 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
       vz = nvz;
     }
     if (DEPOSIT) {
+      // set by an active lane; read only where inw, which an inactive lane
+      // leaves false (no zero-initialisation for every particle)
       bool inw = false;
-      int sx = 0, sy = 0, lx = 0, ly = 0;
+      int sx, sy, lx, ly;
       T wx[NW], wy[NW];
-#pragma unroll
-      for (int a = 0; a < NW; ++a) wx[a] = wy[a] = T(0);
-      T jx = T(0), jy = T(0), jz = T(0);
+      T jx, jy, jz;
       if (act) {
         if (staged) {
           if (sa.stage == d.sc.stages - 1) {
@@ -632,7 +632,7 @@ __global__ void __launch_bounds__(kThreads) k_tiled(const InstDesc* __restrict__
           }
         }
       }
-      {
+      if (inw) {
         // per-lane rotation of stencil columns and rows: at step (a, b) lane l
         // adds to the stencil node whose absolute indices are congruent to
         // (a + l, b + l / NW) modulo NW (a stencil holds one node of every
