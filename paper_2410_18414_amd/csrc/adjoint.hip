@@ -307,6 +307,11 @@ __global__ void __launch_bounds__(kAdjPushThreads) k_adj_push_t(const InstDesc* 
     }
     lam(0) += lxg * g.inv_dx;  // lambda of x^{n+1}, deposit part still to come
     lam(1) += lyg * g.inv_dy;
+    // the scatter visits its stencil in the residue-class order of the
+    // forward deposit: at step (a, b) lane l adds to the node whose absolute
+    // indices are congruent to (a + l, b + l / NW) modulo NW, so at most
+    // 64 / NW^2 lanes meet on one window address, whatever cells the wave's
+    // particles are in
     const int ra = ((lane - sx) % NW + NW) % NW, rb = ((lane / NW - sy) % NW + NW) % NW;
     double wxr[NW], wyr[NW];
     int coff[NW], roff[NW];
