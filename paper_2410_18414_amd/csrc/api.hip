@@ -488,6 +488,7 @@ struct pic_ctx_s {
   double* d_scratch = nullptr;  // scratch's address on the context's device
   int nblk[BK_NKINDS] = {0};
   size_t lds_r2c = 0, lds_c2r = 0, lds_col = 0, lds_adj_col = 0, lds_tiled[3] = {0, 0, 0};
+  int max_ny = 0;  // largest grid side in y over the instances (column kernel block size)
   int dtype = 0, degree = 3, scheme = 0;
   int geo = 0;  // compiled window geometry shared by every instance (0: none, runtime geometry)
   bool sorted = true;
@@ -649,7 +650,7 @@ pic_status_t do_solve(pic_ctx_t c) {
   pic_status_t st = c->hip(launch_rows_r2c(c->d_desc, ni, c->nblk[BK_R2C], c->lds_r2c, c->stream), "rows_r2c");
   if (!st)
     st = c->hip(launch_columns(c->scheme, c->inst[0].cfg.bdf_order, c->d_desc, ni, c->nblk[BK_COL], c->lds_col,
-                               slots_of(c->hist, c->nupd), c->stream),
+                               slots_of(c->hist, c->nupd), c->max_ny, c->stream),
                 "columns");
   if (!st) st = c->hip(launch_rows_c2r(c->d_desc, ni, c->nblk[BK_C2R], c->lds_c2r, c->stream), "rows_c2r");
   c->end_timed(t);
@@ -894,6 +895,7 @@ pic_status_t create(const pic_config_t* cfgs, int ninst, void* workspace, size_t
     c->lds_r2c = std::max(c->lds_r2c, rows_r2c_lds_bytes(cf.nx, cf.ny));
     c->lds_c2r = std::max(c->lds_c2r, rows_c2r_lds_bytes(cf.nx, cf.ny));
     c->lds_col = std::max(c->lds_col, columns_split_lds_bytes(cf.ny, d.sc.substep ? d.sc.stages : 0));
+    c->max_ny = std::max(c->max_ny, cf.ny);
     if (cf.flags & PIC_FLAG_ADJOINT) c->lds_adj_col = std::max(c->lds_adj_col, adj_columns_lds_bytes(cf.ny));
     for (int mode = 0; mode < 3; ++mode)
       c->lds_tiled[mode] = std::max(c->lds_tiled[mode], tiled_lds_bytes(cf.particle_dtype, mode, d.tp, d.naive != 0));

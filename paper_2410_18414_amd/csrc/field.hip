@@ -102,10 +102,13 @@ __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D
 // written at J_new by part 1 + l only.
 constexpr int kColParts = 4;
 constexpr int kMaxStages = 3;  // DIRK stages: loops over them unrolled to this bound (registers, not scratch)
-constexpr int kColMaxModes = 4;  // modes per thread: ny <= 1024 with 256 threads
+// modes per thread: 256 threads up to ny = 512, 512 threads above (ny <= 1024);
+// two modes keep the DIRK update's per-mode values within a register budget
+// that admits three waves per SIMD
+constexpr int kColMaxModes = 2;
 
 template <int SCHEME, int K>
-__global__ void __launch_bounds__(256) k_columns_split(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
+__global__ void __launch_bounds__(512) k_columns_split(const InstDesc* __restrict__ D, int ninst, HistSlots hs) {
   // LDS: [0, N) the scaled output column; [N, 5N) work (two ping-pong pairs
   // of two columns); then the N twiddles (ny <= 512); then, for sub-stepped
   // DIRK currents, the transformed stage columns (two per stage)
@@ -650,10 +653,11 @@ hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds
 
 template <int SCHEME, int K>
 static hipError_t launch_columns_split_t(const InstDesc* D, int ninst, int nblocks, size_t lds, HistSlots hs,
-                                         hipStream_t s) {
+                                         int max_ny, hipStream_t s) {
   (void)hipFuncSetAttribute((const void*)k_columns_split<SCHEME, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-  hipLaunchKernelGGL((k_columns_split<SCHEME, K>), dim3(nblocks), dim3(256), lds, s, D, ninst, hs);
+  const int threads = max_ny > 256 * kColMaxModes ? 512 : 256;
+  hipLaunchKernelGGL((k_columns_split<SCHEME, K>), dim3(nblocks), dim3(threads), lds, s, D, ninst, hs);
   return hipGetLastError();
 }
 
@@ -665,16 +669,16 @@ size_t columns_split_lds_bytes(int ny, int nstage) {
 }
 
 hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int ninst, int nblocks, size_t lds,
-                          HistSlots hs, hipStream_t s) {
-  if (scheme == PIC_SCHEME_CDF2) return launch_columns_split_t<PIC_SCHEME_CDF2, 0>(D, ninst, nblocks, lds, hs, s);
-  if (scheme == PIC_SCHEME_DIRK2) return launch_columns_split_t<PIC_SCHEME_DIRK2, 0>(D, ninst, nblocks, lds, hs, s);
+                          HistSlots hs, int max_ny, hipStream_t s) {
+  if (scheme == PIC_SCHEME_CDF2) return launch_columns_split_t<PIC_SCHEME_CDF2, 0>(D, ninst, nblocks, lds, hs, max_ny, s);
+  if (scheme == PIC_SCHEME_DIRK2) return launch_columns_split_t<PIC_SCHEME_DIRK2, 0>(D, ninst, nblocks, lds, hs, max_ny, s);
   switch (bdf_order) {
-    case 1: return launch_columns_split_t<PIC_SCHEME_BDF, 1>(D, ninst, nblocks, lds, hs, s);
-    case 2: return launch_columns_split_t<PIC_SCHEME_BDF, 2>(D, ninst, nblocks, lds, hs, s);
-    case 3: return launch_columns_split_t<PIC_SCHEME_BDF, 3>(D, ninst, nblocks, lds, hs, s);
-    case 4: return launch_columns_split_t<PIC_SCHEME_BDF, 4>(D, ninst, nblocks, lds, hs, s);
-    case 5: return launch_columns_split_t<PIC_SCHEME_BDF, 5>(D, ninst, nblocks, lds, hs, s);
-    default: return launch_columns_split_t<PIC_SCHEME_BDF, 6>(D, ninst, nblocks, lds, hs, s);
+    case 1: return launch_columns_split_t<PIC_SCHEME_BDF, 1>(D, ninst, nblocks, lds, hs, max_ny, s);
+    case 2: return launch_columns_split_t<PIC_SCHEME_BDF, 2>(D, ninst, nblocks, lds, hs, max_ny, s);
+    case 3: return launch_columns_split_t<PIC_SCHEME_BDF, 3>(D, ninst, nblocks, lds, hs, max_ny, s);
+    case 4: return launch_columns_split_t<PIC_SCHEME_BDF, 4>(D, ninst, nblocks, lds, hs, max_ny, s);
+    case 5: return launch_columns_split_t<PIC_SCHEME_BDF, 5>(D, ninst, nblocks, lds, hs, max_ny, s);
+    default: return launch_columns_split_t<PIC_SCHEME_BDF, 6>(D, ninst, nblocks, lds, hs, max_ny, s);
   }
 }
 

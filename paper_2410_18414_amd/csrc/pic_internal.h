@@ -392,7 +392,7 @@ size_t columns_split_lds_bytes(int ny, int nstage);  // nstage: sub-stepped DIRK
 // adj = true: the adjoint field solve's transforms (LF -> LS, LS -> LJ; one instance)
 hipError_t launch_rows_r2c(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false);
 hipError_t launch_columns(int scheme, int bdf_order, const InstDesc* D, int ninst, int nblocks, size_t lds,
-                          HistSlots hs, hipStream_t s);
+                          HistSlots hs, int max_ny, hipStream_t s);
 // f64out: the float64 mesh planes too (float32 contexts skip them in the step)
 hipError_t launch_rows_c2r(const InstDesc* D, int ninst, int nblocks, size_t lds, hipStream_t s, bool adj = false,
                            bool f64out = false);
