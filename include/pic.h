@@ -356,8 +356,11 @@ pic_status_t step_batched(pic_ctx_t ctx, int32_t nsteps);
  *
  * The held particle adjoint: the context keeps lam in the order of its
  * particle slots, so the adjoint passes read and write it with contiguous
- * accesses; it is permuted only when a sort changes the order (a device-side
- * check of the order on every step, no host synchronisation).
+ * accesses; it is permuted only when a sort changes the order.  The context
+ * tags each slot order when it is made (sort, init_particles, set_particles;
+ * a saved state keeps its tag); when the loaded particles carry another tag
+ * than the order the adjoint follows, a device-side check (no host
+ * synchronisation) compares the orders and permutes if they differ.
  * pic_adjoint_set_particles: lam [11][n] in original order (NULL: zero) into
  * the context, for the particles loaded now.  pic_adjoint_get_particles: the
  * held adjoint back out in original order (PIC_ERR_STATE if none is held for

@@ -7,6 +7,7 @@
 // instance.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -477,6 +478,11 @@ __global__ void __launch_bounds__(kCopyThreads) k_copy_list(CopyList L) {
 
 }  // namespace
 
+static uint64_t new_order_tag() {
+  static std::atomic<uint64_t> next{1};
+  return next.fetch_add(1, std::memory_order_relaxed);
+}
+
 struct pic_ctx_s {
   std::vector<Instance> inst;
   int sel = 0;  // instance addressed by the per-instance entry points
@@ -499,6 +505,12 @@ struct pic_ctx_s {
   int moves = 0;     // position updates since the last sort
   bool stepped = false;
   int64_t lam_n = -1;  // particle count of the held adjoint (-1: none)
+  // the slot order of the current particle set: a process-wide serial taken
+  // whenever the order is made (sort, initial load, import) and kept with
+  // saved states, so that equal tags mean equal orders; lam_tag is the order
+  // the held adjoint follows (0: unknown, checked on the device)
+  uint64_t order_tag = new_order_tag();
+  uint64_t lam_tag = 0;
   Phase phase = EMPTY;
   std::string err;
 
@@ -607,6 +619,7 @@ pic_status_t do_sort(pic_ctx_t c) {
   if (st) return st;
   c->cur ^= 1;
   c->moves = 0;
+  c->order_tag = new_order_tag();
   return PIC_OK;
 }
 
@@ -1191,6 +1204,7 @@ pic_status_t init_particles(pic_ctx_t c, int64_t n, const double* x, const doubl
     c->stepped = false;
   }
   auto pa = parts_of(c, in.d, c->cur);
+  c->order_tag = new_order_tag();
   pic_status_t st =
       c->hip(launch_init_particles(c->dtype, &pa, n, x, y, P, in.d.g, in.d.ph, c->stream), "init launch");
   if (st) return st;
@@ -1292,6 +1306,7 @@ pic_status_t pic_set_particles(pic_ctx_t c, const double* src) {
   // J is zero in both phases (consumed by the last field solve)
   if (c->phase != READY && c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "set_particles needs phase READY or SOLVED");
   auto pa = parts_of(c, in.d, c->cur);
+  c->order_tag = new_order_tag();
   pic_status_t st = c->hip(launch_set_particles(c->dtype, &pa, in.d.n, src, in.d.g, c->stream), "set_particles");
   if (st) return st;
   c->moves = c->sort_every;  // re-sort before the next particle pass
@@ -1526,7 +1541,7 @@ pic_status_t pic_save_state(pic_ctx_t c, void* dst) {
   // header: global words, then the particle counts (in launches of 16 words)
   std::vector<int64_t> words(kStateHeaderWords + ni, 0);
   const int64_t g[] = {(int64_t)kStateMagic, state_fingerprint(c), c->nupd, c->vflip, c->cur, c->moves,
-                       c->stepped ? 1 : 0, (int64_t)pic_state_bytes(c), c->sort_every};
+                       c->stepped ? 1 : 0, (int64_t)pic_state_bytes(c), c->sort_every, (int64_t)c->order_tag};
   for (size_t k = 0; k < sizeof(g) / sizeof(g[0]); ++k) words[k] = g[k];
   for (int i = 0; i < ni; ++i) words[kStateHeaderWords + i] = ns[i];
   pic_status_t st = PIC_OK;
@@ -1574,6 +1589,7 @@ pic_status_t pic_load_state(pic_ctx_t c, const void* src) {
   c->moves = (int)h[5];
   c->stepped = h[6] != 0;
   c->sort_every = (int)std::min<int64_t>(std::max<int64_t>(h[8], 1), 64);
+  c->order_tag = (uint64_t)h[9];
   c->phase = READY;
   // the device descriptors change only with the particle counts
   return counts_changed ? c->upload_desc() : PIC_OK;
@@ -1634,6 +1650,8 @@ pic_status_t pic_adjoint_set_particles(pic_ctx_t c, const double* lam) {
   st = c->hip(launch_lam_set(in.d.n, lam, in.d.LAM, in.cfg.max_particles, in.d.LIDS, in.d.ids[c->cur], c->stream),
               "adjoint set");
   c->lam_n = st ? -1 : in.d.n;
+  // NULL: zero in the current slot order; else original order (checked on the device)
+  c->lam_tag = lam ? 0 : c->order_tag;
   return st;
 }
 
@@ -1666,11 +1684,14 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
   const int nx = in.cfg.nx, ny = in.cfg.ny;
   const StepArgs sa = c->sargs();
   const int64_t ls = in.cfg.max_particles;
-  // the held adjoint follows the order of the set the passes run on
-  if (!st)
+  // the held adjoint follows the order of the set the passes run on: checked
+  // (and permuted) on the device unless it already follows this order's tag
+  if (!st && c->lam_tag != c->order_tag) {
     st = c->hip(launch_lam_follow(in.d.n, in.d.ids[c->cur], in.d.LAM, in.d.LAM2, ls, in.d.LIDS, in.d.LINV,
                                   in.d.LFLAG, c->stream),
                 "adjoint order");
+    if (!st) c->lam_tag = c->order_tag;
+  }
   // the cell-sorted passes when the forward is sorted and the windows fit in LDS
   int max_lds = 0, dev = 0;
   (void)hipGetDevice(&dev);
@@ -1690,7 +1711,10 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
                       : launch_adj_deposit(c->degree, D, in.d.n, sa, in.d.LAM, ls, c->stream),
                 "adjoint deposit");
   if (!st && lam) st = pic_adjoint_get_particles(c, lam);
-  if (st) c->lam_n = -1;
+  if (st) {
+    c->lam_n = -1;
+    c->lam_tag = 0;
+  }
   c->phase = st ? EMPTY : SOLVED;
   return st;
 }
