@@ -235,6 +235,20 @@ size_t pic_state_bytes(pic_ctx_t ctx);
 pic_status_t pic_save_state(pic_ctx_t ctx, void* dst);
 pic_status_t pic_load_state(pic_ctx_t ctx, const void* src);
 
+/* The same without the header read: pic_save_state_h also writes the state's
+ * header, pic_state_header_words(ctx) int64 words, to [host] header (NULL:
+ * not written); pic_load_state_h takes the header from [host] header instead
+ * of reading it from src, so it neither synchronises the stream nor waits for
+ * the save to finish (for loops that save and reload many states, e.g. an
+ * adjoint sweep).  header must be the one pic_save_state_h wrote for src, and
+ * src unchanged since; it holds pic_state_header_words(ctx) words of the
+ * loading context (a header of another instance count would be read past its
+ * end); the same validation of the header words applies.
+ * header NULL: pic_load_state. */
+int32_t pic_state_header_words(pic_ctx_t ctx);
+pic_status_t pic_save_state_h(pic_ctx_t ctx, void* dst, int64_t* header);
+pic_status_t pic_load_state_h(pic_ctx_t ctx, const void* src, const int64_t* header);
+
 /* Real mesh fields, float64 device dst:
  *   PIC_FIELD_J      [3][ny][nx]  J^{n+1}; valid in phase DEPOSITED
  *                    (PIC_FLAG_DIRK_SUBSTEP: [3 stages][ny][nx], stage i at

@@ -13,8 +13,9 @@ backward walks the run in reverse with libpic's discrete adjoint
 raw device state -- particles in their sorted order, tile metadata, history
 ring); each segment is replayed forward from its checkpoint into a pool of
 saved states (the last one stays in the context), then the adjoint steps
-through the segment backwards, loading each state with pic_load_state (no
-conversion and no re-sort); the particle
+through the segment backwards, loading each state with pic_load_state_h (no
+conversion and no re-sort; the header kept on the host, so no synchronisation);
+the particle
 adjoint stays inside the context in slot order for the whole sweep.  every=1
 stores every state (no replay).  Only argument marshalling happens here:
 every step and every adjoint step runs in the library's kernels.
@@ -51,7 +52,7 @@ class _FieldEnergy(torch.autograd.Function):
         ctx = fctx.sim
         (P0,) = fctx.saved_tensors
         # the seed needs the final history loaded
-        pic.load_state(ctx, fctx.final)
+        pic.load_state(ctx, fctx.final, trust_header=True)
         pic.adjoint_set_particles(ctx, None)  # the particle adjoint of W is zero
         lam_hist = pic.adjoint_seed_energy(ctx, float(gW))
         # states inside a segment are replayed into a pool of saved states
@@ -60,7 +61,7 @@ class _FieldEnergy(torch.autograd.Function):
             seg = min(fctx.every, fctx.nsteps - s0)
             states = [ck]
             if seg > 1:
-                pic.load_state(ctx, ck)
+                pic.load_state(ctx, ck, trust_header=True)
                 for j in range(1, seg):
                     pic.step(ctx, 1)
                     if j < seg - 1:  # the segment's last state stays in the context
@@ -69,7 +70,7 @@ class _FieldEnergy(torch.autograd.Function):
                         states.append(pic.save_state(ctx, pool[j - 1]))
                 pic.step_adjoint(ctx, None, lam_hist)
             for st in reversed(states):
-                pic.load_state(ctx, st)
+                pic.load_state(ctx, st, trust_header=True)
                 pic.step_adjoint(ctx, None, lam_hist)
         lam = pic.adjoint_get_particles(ctx)
         pic.adjoint_initial(ctx, P0.detach(), lam)

@@ -1530,7 +1530,7 @@ static pic_status_t copy_segments(pic_ctx_t c, const std::vector<std::array<size
   return PIC_OK;
 }
 
-pic_status_t pic_save_state(pic_ctx_t c, void* dst) {
+pic_status_t pic_save_state_h(pic_ctx_t c, void* dst, int64_t* header) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (!dst || ((uintptr_t)dst & (kAlign - 1))) return c->fail(PIC_ERR_INVALID_ARG, "dst must be a 256-byte aligned device pointer");
   if (c->phase != READY) return c->fail(PIC_ERR_STATE, "save_state needs phase READY");
@@ -1553,18 +1553,28 @@ pic_status_t pic_save_state(pic_ctx_t c, void* dst) {
     st = c->hip(hipGetLastError(), "state header");
   }
   if (!st) st = copy_segments(c, state_segments(c, c->cur, ns), b, true);
+  if (!st && header) std::memcpy(header, words.data(), words.size() * sizeof(int64_t));
   return st;
 }
 
-pic_status_t pic_load_state(pic_ctx_t c, const void* src) {
+pic_status_t pic_save_state(pic_ctx_t c, void* dst) { return pic_save_state_h(c, dst, nullptr); }
+
+int32_t pic_state_header_words(pic_ctx_t c) { return c ? kStateHeaderWords + c->ninst() : 0; }
+
+pic_status_t pic_load_state_h(pic_ctx_t c, const void* src, const int64_t* header) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (!src || ((uintptr_t)src & (kAlign - 1))) return c->fail(PIC_ERR_INVALID_ARG, "src must be a 256-byte aligned device pointer");
   const char* b = static_cast<const char*>(src);
   const int ni = c->ninst();
   std::vector<int64_t> h(kStateHeaderWords + ni);
-  pic_status_t st = c->hip(hipMemcpyAsync(h.data(), b, h.size() * 8, hipMemcpyDeviceToHost, c->stream), "state header read");
-  if (!st) st = c->hip(hipStreamSynchronize(c->stream), "state header sync");
-  if (st) return st;
+  pic_status_t st = PIC_OK;
+  if (header) {  // the caller's copy from pic_save_state_h: no read, no synchronisation
+    std::memcpy(h.data(), header, h.size() * sizeof(int64_t));
+  } else {
+    st = c->hip(hipMemcpyAsync(h.data(), b, h.size() * 8, hipMemcpyDeviceToHost, c->stream), "state header read");
+    if (!st) st = c->hip(hipStreamSynchronize(c->stream), "state header sync");
+    if (st) return st;
+  }
   if (h[0] != (int64_t)kStateMagic || h[1] != state_fingerprint(c) || h[7] != (int64_t)pic_state_bytes(c))
     return c->fail(PIC_ERR_INVALID_ARG, "src is not a state saved by a context of this configuration");
   std::vector<int64_t> ns(h.begin() + kStateHeaderWords, h.end());
@@ -1594,6 +1604,8 @@ pic_status_t pic_load_state(pic_ctx_t c, const void* src) {
   // the device descriptors change only with the particle counts
   return counts_changed ? c->upload_desc() : PIC_OK;
 }
+
+pic_status_t pic_load_state(pic_ctx_t c, const void* src) { return pic_load_state_h(c, src, nullptr); }
 
 pic_status_t pic_diagnostics_all(pic_ctx_t c, double* out) {
   if (!c) return PIC_ERR_INVALID_ARG;

@@ -46,7 +46,8 @@ EXPORTS = ("pic_workspace_bytes", "pic_create", "pic_destroy", "pic_last_error",
            "pic_instance_count", "pic_select_instance", "step_batched", "adjoint_seed_energy",
            "step_adjoint", "adjoint_initial", "pic_graph_period", "pic_diagnostics_all",
            "pic_set_dirk_tableau", "pic_state_bytes", "pic_save_state", "pic_load_state",
-           "pic_adjoint_set_particles", "pic_adjoint_get_particles")
+           "pic_adjoint_set_particles", "pic_adjoint_get_particles", "pic_state_header_words",
+           "pic_save_state_h", "pic_load_state_h")
 KCLASSES = ("deposit", "field_solve", "gather_push", "fused", "sort")
 
 
@@ -104,6 +105,9 @@ def load():
         "pic_state_bytes": (SZ, [P]),
         "pic_save_state": (I32, [P, P]),
         "pic_load_state": (I32, [P, P]),
+        "pic_state_header_words": (I32, [P]),
+        "pic_save_state_h": (I32, [P, P, P]),
+        "pic_load_state_h": (I32, [P, P, P]),
         "pic_adjoint_set_particles": (I32, [P, P]),
         "pic_adjoint_get_particles": (I32, [P, P]),
         "pic_set_kernel_timing": (I32, [P, I32]),
@@ -327,25 +331,35 @@ def diagnostics(ctx, allow_nonfinite=False):
 
 
 class State:
-    """A device buffer holding one saved state of a context (pic_save_state)."""
+    """A device buffer holding one saved state of a context (pic_save_state),
+    with a host copy of its header (pic_save_state_h)."""
 
     def __init__(self, ctx):
         nbytes = load().pic_state_bytes(ctx.handle)
         self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=ctx.device)
         self.ptr = ctypes.c_void_p(self.buf.data_ptr() + (-self.buf.data_ptr()) % 256)
+        self.header = (ctypes.c_int64 * load().pic_state_header_words(ctx.handle))()
         self.ns = None
 
 
 def save_state(ctx, state=None):
     """Save the context's state (phase READY) into `state` (a new State if None)."""
     state = state or State(ctx)
-    ctx.check(load().pic_save_state(ctx.handle, state.ptr))
+    ctx.check(load().pic_save_state_h(ctx.handle, state.ptr, ctypes.cast(state.header, ctypes.c_void_p)))
     state.ns = list(ctx.ns)
     return state
 
 
-def load_state(ctx, state):
-    ctx.check(load().pic_load_state(ctx.handle, state.ptr))
+def load_state(ctx, state, trust_header=False):
+    """Restore `state`.  trust_header: take the header saved with it on the
+    host (pic_load_state_h: no read of the buffer, no synchronisation); only
+    for a State whose buffer nothing else wrote since save_state."""
+    if trust_header:
+        if len(state.header) != load().pic_state_header_words(ctx.handle):
+            raise ValueError("the state's header does not fit this context")
+        ctx.check(load().pic_load_state_h(ctx.handle, state.ptr, ctypes.cast(state.header, ctypes.c_void_p)))
+    else:
+        ctx.check(load().pic_load_state(ctx.handle, state.ptr))
     ctx.ns = list(state.ns)
 
 

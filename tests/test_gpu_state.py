@@ -1,9 +1,10 @@
 """Checkpoint files, device-resident saved states (pic_save_state /
-pic_load_state) and the diagnostics log on the GPU (needs an MI355X): a
-deterministic run resumed from a checkpoint file or from a saved state equals
-the uninterrupted run bit for bit (in the same context, in a fresh one, in an
-ensemble, with the naive charge deposit); both refuse a context of another
-configuration; the log has one line per interval with the gauge residual at
+pic_load_state, and the _h forms that keep the header on the host) and the
+diagnostics log on the GPU (needs an MI355X): a deterministic run resumed from
+a checkpoint file or from a saved state equals the uninterrupted run bit for
+bit (in the same context, in a fresh one, in an ensemble, with the naive charge
+deposit, with the header taken from the host); both refuse a context of another
+configuration and a header of another one; the log has one line per interval with the gauge residual at
 round-off."""
 
 import json
@@ -87,6 +88,9 @@ def test_saved_state_resume(gpu_lib, dtype, scheme, k, flags, tol):
     pic.step(b, 7)
     pic.step(b, 11)
     _same(b, full, tol)
+    pic.load_state(b, saved, trust_header=True)   # the header from the host: no read of the buffer
+    pic.step(b, 18)
+    _same(b, full, tol)
     d_full, d_b = pic.diagnostics(full), pic.diagnostics(b)
     for key in ("energy", "kinetic"):
         assert abs(d_b[key] - d_full[key]) <= max(tol, 1e-12) * abs(d_full[key]), key
@@ -129,6 +133,13 @@ def test_saved_state_ensemble_and_refusals(gpu_lib):
         pic.load_state(c, pic.save_state(c))
         pic.deposit_current(c)
         pic.save_state(c)
+    # a host header of another configuration is refused (its length, then its words)
+    foreign = pic.save_state(make_gpu(ws[0], 3, "dirk2", "f32", flags=pic.FLAG_DETERMINISTIC))
+    with pytest.raises(ValueError):
+        pic.load_state(b, foreign, trust_header=True)
+    other = make_gpu(ws[1], 3, "dirk2", "f32", flags=pic.FLAG_DETERMINISTIC)
+    with pytest.raises(pic.PicError):
+        pic.load_state(other, foreign, trust_header=True)
     bad = pic.State(a)
     bad.ptr = type(bad.ptr)(bad.ptr.value + 8)
     with pytest.raises(pic.PicError):
