@@ -357,7 +357,9 @@ pic_status_t step_batched(pic_ctx_t ctx, int32_t nsteps);
  *
  * step_adjoint: phase READY with the context holding S^n.  Recomputes the
  * position update, deposit and field solve of step n -> n+1 (as
- * deposit_current + field_solve; phase -> SOLVED afterwards, so the caller
+ * deposit_current + field_solve, but never re-sorting the particles first: a
+ * particle that has drifted past its tile's window takes the global path, and
+ * the held adjoint keeps its order; phase -> SOLVED afterwards, so the caller
  * reloads the next state, with pic_load_state or pic_set_particles and
  * pic_set_history), then maps (lam, lam_hist) = lambda^{n+1} to lambda^n =
  * (dS^{n+1}/dS^n)^T lambda^{n+1}: the push and gather adjoint (a scatter onto

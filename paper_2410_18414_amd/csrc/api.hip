@@ -511,6 +511,9 @@ struct pic_ctx_s {
   // the held adjoint follows (0: unknown, checked on the device)
   uint64_t order_tag = new_order_tag();
   uint64_t lam_tag = 0;
+  // the order and the tile metadata come from a sort of these particles (not
+  // an initial load or an import): every particle is in its tile's chunks
+  bool from_sort = false;
   Phase phase = EMPTY;
   std::string err;
 
@@ -620,6 +623,7 @@ pic_status_t do_sort(pic_ctx_t c) {
   c->cur ^= 1;
   c->moves = 0;
   c->order_tag = new_order_tag();
+  c->from_sort = true;
   return PIC_OK;
 }
 
@@ -629,10 +633,12 @@ pic_status_t maybe_sort(pic_ctx_t c) {
   return PIC_OK;
 }
 
-// mode: 0 deposit, 1 gather + push, 2 fused
-pic_status_t particle_pass(pic_ctx_t c, int mode) {
+// mode: 0 deposit, 1 gather + push, 2 fused.  may_sort false: no sort even
+// when one is due (the particles keep their order; a particle that drifted
+// past its window takes the global path)
+pic_status_t particle_pass(pic_ctx_t c, int mode, bool may_sort = true) {
   // the phases start with a deposit, so a sort due after loading happens there
-  if (mode != 1) {
+  if (mode != 1 && may_sort) {
     pic_status_t st = maybe_sort(c);
     if (st) return st;
   }
@@ -1205,6 +1211,7 @@ pic_status_t init_particles(pic_ctx_t c, int64_t n, const double* x, const doubl
   }
   auto pa = parts_of(c, in.d, c->cur);
   c->order_tag = new_order_tag();
+  c->from_sort = false;
   pic_status_t st =
       c->hip(launch_init_particles(c->dtype, &pa, n, x, y, P, in.d.g, in.d.ph, c->stream), "init launch");
   if (st) return st;
@@ -1307,6 +1314,7 @@ pic_status_t pic_set_particles(pic_ctx_t c, const double* src) {
   if (c->phase != READY && c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "set_particles needs phase READY or SOLVED");
   auto pa = parts_of(c, in.d, c->cur);
   c->order_tag = new_order_tag();
+  c->from_sort = false;
   pic_status_t st = c->hip(launch_set_particles(c->dtype, &pa, in.d.n, src, in.d.g, c->stream), "set_particles");
   if (st) return st;
   c->moves = c->sort_every;  // re-sort before the next particle pass
@@ -1541,7 +1549,8 @@ pic_status_t pic_save_state_h(pic_ctx_t c, void* dst, int64_t* header) {
   // header: global words, then the particle counts (in launches of 16 words)
   std::vector<int64_t> words(kStateHeaderWords + ni, 0);
   const int64_t g[] = {(int64_t)kStateMagic, state_fingerprint(c), c->nupd, c->vflip, c->cur, c->moves,
-                       c->stepped ? 1 : 0, (int64_t)pic_state_bytes(c), c->sort_every, (int64_t)c->order_tag};
+                       c->stepped ? 1 : 0, (int64_t)pic_state_bytes(c), c->sort_every, (int64_t)c->order_tag,
+                       c->from_sort ? 1 : 0};
   for (size_t k = 0; k < sizeof(g) / sizeof(g[0]); ++k) words[k] = g[k];
   for (int i = 0; i < ni; ++i) words[kStateHeaderWords + i] = ns[i];
   pic_status_t st = PIC_OK;
@@ -1600,6 +1609,7 @@ pic_status_t pic_load_state_h(pic_ctx_t c, const void* src, const int64_t* heade
   c->stepped = h[6] != 0;
   c->sort_every = (int)std::min<int64_t>(std::max<int64_t>(h[8], 1), 64);
   c->order_tag = (uint64_t)h[9];
+  c->from_sort = h[10] != 0;
   c->phase = READY;
   // the device descriptors change only with the particle counts
   return counts_changed ? c->upload_desc() : PIC_OK;
@@ -1689,8 +1699,13 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
   } else if (c->lam_n != in.d.n) {
     return c->fail(PIC_ERR_STATE, "lam is NULL and no particle adjoint is held for the loaded particles");
   }
-  // recompute x^{n+1}, J^{n+1} and the level-(n+1) fields from the loaded state
-  st = particle_pass(c, 0);
+  // recompute x^{n+1}, J^{n+1} and the level-(n+1) fields from the loaded
+  // state, without the sort the forward may have made before this deposit
+  // when the loaded order comes from a sort (its chunks hold every particle):
+  // the next state is loaded over this one anyway, and a sort here would
+  // cost the scatter and two permutations of the held adjoint (into the new
+  // order and back to the next loaded state's)
+  st = particle_pass(c, 0, !c->from_sort);
   if (!st) st = do_solve(c);
   const InstDesc* D = c->d_desc;
   const int nx = in.cfg.nx, ny = in.cfg.ny;
