@@ -38,11 +38,14 @@ namespace {
 // adj: the same transform of the 11 adjoint mesh fields LF into LS.
 __global__ void __launch_bounds__(256) k_rows_r2c(const InstDesc* __restrict__ D, int ninst, int adj) {
   extern __shared__ double2 sm[];
-  const int ii = find_inst(D, ninst, BK_R2C, blockIdx.x);
+  // neighbouring row groups on one XCD: each writes R of the ny values of a
+  // spectrum column, so the groups that fill one cache line share its L2
+  const int bb = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int ii = find_inst(D, ninst, BK_R2C, bb);
   const InstDesc& d = D[ii];
   const GridP g = d.g;
   const int R = d.R_r2c, ngr = (g.ny + R - 1) / R;
-  const int lb = blockIdx.x - d.blk[BK_R2C];
+  const int lb = bb - d.blk[BK_R2C];
   const int c = lb / ngr, y0 = (lb - c * ngr) * R;
   const int nr = min(R, g.ny - y0);  // rows of this group
   const gptr<double> Jc = gp((adj ? d.LF : d.J) + (size_t)c * g.nx * g.ny);
@@ -113,11 +116,14 @@ __global__ void __launch_bounds__(512) k_columns_split(const InstDesc* __restric
   // of two columns); then the N twiddles (ny <= 512); then, for sub-stepped
   // DIRK currents, the transformed stage columns (two per stage)
   extern __shared__ double2 sm[];
-  const int ii = find_inst(D, ninst, BK_COL, blockIdx.x);
+  // the four parts of one column on one XCD: parts 0 and 1 + l read the same
+  // transformed J columns, which then come from one L2
+  const int bb = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int ii = find_inst(D, ninst, BK_COL, bb);
   const InstDesc& d = D[ii];
   const GridP g = d.g;
   const SchemeCoef sc = d.sc;
-  const int lb = blockIdx.x - d.blk[BK_COL];
+  const int lb = bb - d.blk[BK_COL];
   const int kx = lb / kColParts, part = lb - kx * kColParts;
   const int N = g.ny, tid = threadIdx.x, nth = blockDim.x;
   const GC2 T = gc2(d.T);
@@ -411,12 +417,18 @@ __constant__ int kMulKx[12] = {1, 0, 0, 0, 0, 1, 1, 1, 0, 0, 0, 0};
 // float64 planes are written on demand for the mesh-field export)
 __global__ void __launch_bounds__(256) k_rows_c2r(const InstDesc* __restrict__ D, int ninst, int adj, int f64out) {
   extern __shared__ double2 sm[];
-  const int ii = find_inst(D, ninst, BK_C2R, blockIdx.x);
+  // the pairs of one row group in consecutive blocks, and neighbouring blocks
+  // on one XCD: the six pairs of a row group fill each node's record (and
+  // neighbouring row groups read one cache line of a spectrum column) through
+  // one L2
+  const int bb = xcd_contiguous(blockIdx.x, gridDim.x);
+  const int ii = find_inst(D, ninst, BK_C2R, bb);
   const InstDesc& d = D[ii];
   const GridP g = d.g;
-  const int R = d.R_c2r, ngr = (g.ny + R - 1) / R;
-  const int lb = blockIdx.x - d.blk[BK_C2R];
-  const int pr = lb / ngr, y0 = (lb - pr * ngr) * R;
+  const int R = d.R_c2r;
+  const int np = adj ? 2 : 6;  // output pairs per row group
+  const int lb = bb - d.blk[BK_C2R];
+  const int rg = lb / np, pr = lb - rg * np, y0 = rg * R;
   const int nr = min(R, g.ny - y0);  // rows of this group (the last may be partial)
   const GC2 U = gc2(adj ? d.LS : d.U);
   const gptr<double> F64 = gp(adj ? d.LJ : d.F64);
@@ -620,7 +632,10 @@ void fft_make_twiddles(int n, double* h) {
 
 // rows per block of the row kernels: at most 8, within the LDS budget, and
 // small enough that one instance's transform has 256 blocks or more (the row
-// kernels are latency-bound: more, shorter blocks finish sooner)
+// kernels are latency-bound: more, shorter blocks finish sooner).  C2R keeps
+// R nx <= 1024: its (2 R + 1) nx complex values of LDS then let three blocks
+// share a CU at nx = 512 (two rows per block there: the solve 4 us faster
+// than with four)
 int rows_r2c_R(int nx, int ny) {
   int R = 8;
   while (R > 2 && (R > ny || R * nx > 4096)) R >>= 1;
@@ -629,7 +644,7 @@ int rows_r2c_R(int nx, int ny) {
 }
 int rows_c2r_R(int nx, int ny) {
   int R = 8;
-  while (R > 1 && (R > ny || R * nx > 2048)) R >>= 1;
+  while (R > 1 && (R > ny || R * nx > 1024)) R >>= 1;
   while (R > 2 && 6 * (ny / R) < 256) R >>= 1;
   return R;
 }

@@ -156,6 +156,15 @@ __device__ __forceinline__ uint32_t opaque_index(uint32_t k) {
   return k;
 }
 
+// XCD-contiguous block order: the dispatcher deals consecutive workgroups to
+// the eight XCDs in turn (block b to XCD b mod 8); this bijection of [0, nb)
+// gives each XCD one contiguous run of logical blocks instead of every eighth,
+// so that neighbouring logical blocks share one L2
+__device__ __forceinline__ int xcd_contiguous(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, j = b >> 3;
+  return x * q + min(x, r) + j;
+}
+
 template <typename T>
 __device__ __forceinline__ GParts<T> global_parts(const Parts<T>& p) {
   GParts<T> g;

@@ -268,14 +268,6 @@ __global__ void __launch_bounds__(kThreads) k_cell_scan(const InstDesc* __restri
   if (threadIdx.x == 0) *d.tb.done = 0;  // ready for the next sort
 }
 
-// XCD-contiguous block order: the dispatcher deals consecutive workgroups to
-// the eight XCDs in turn (block b to XCD b mod 8); this bijection of [0, nb)
-// gives each XCD one contiguous run of logical blocks instead of every eighth
-__device__ __forceinline__ int xcd_contiguous(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7, x = b & 7, j = b >> 3;
-  return x * q + min(x, r) + j;
-}
-
 // scatter set `src` into set `src ^ 1`, grouped by cell: particle i goes to its
 // tile's start + its cell's offset in the tile + its slot in the cell (from the
 // count pass); no atomics, so the copy streams.  The source is in the previous
