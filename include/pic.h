@@ -59,7 +59,7 @@ typedef struct pic_ctx_s* pic_ctx_t;
 typedef enum {
   PIC_OK = 0,
   PIC_ERR_INVALID_ARG = 1, /* a pointer, size or parameter is invalid          */
-  PIC_ERR_UNSUPPORTED = 2, /* a valid parameter this build does not implement  */
+  PIC_ERR_UNSUPPORTED = 2, /* a valid parameter the library does not implement */
   PIC_ERR_WORKSPACE = 3,   /* workspace too small or misaligned (256 B)        */
   PIC_ERR_HIP = 4,         /* a HIP runtime call or launch failed              */
   PIC_ERR_STATE = 5,       /* call out of order (see the phase rules below)    */
