@@ -216,10 +216,11 @@ pic_status_t pic_get_particles(pic_ctx_t ctx, double* out);
  * are wrapped. */
 pic_status_t pic_set_particles(pic_ctx_t ctx, const double* in);
 
-/* Saved states: the complete state of a context in phase READY (every
- * instance's particles in their current sorted order with their original
- * indices, the tile metadata of the last sort, the spectral history ring,
- * and the step, ring and sort counters), in a caller-owned DEVICE buffer of
+/* Saved states: the complete state of a context in phase READY or SOLVED
+ * (every instance's particles in their current sorted order with their
+ * original indices, the tile metadata of the last sort, the spectral history
+ * ring, the step, ring and sort counters, and in phase SOLVED the mesh fields
+ * of the last solve), in a caller-owned DEVICE buffer of
  * pic_state_bytes(ctx) bytes, 256-byte aligned.  pic_save_state enqueues
  * device-to-device copies (no synchronisation, no allocation); pic_load_state
  * restores a state saved by a context of the same configuration (it reads
@@ -227,8 +228,9 @@ pic_status_t pic_set_particles(pic_ctx_t ctx, const double* in);
  * which the context steps exactly as it would have from the saved point --
  * no conversion to float64 and no re-sort, unlike pic_get/set_particles and
  * pic_get/set_history.  pic_load_state accepts any phase (it replaces the
- * whole state and leaves phase READY); pic_save_state returns PIC_ERR_STATE
- * in phases other than READY.  The layout is private to the library version:
+ * whole state and leaves the saved phase, READY or SOLVED); pic_save_state
+ * returns PIC_ERR_STATE in phases EMPTY and DEPOSITED.  The layout is private
+ * to the library version:
  * PIC_ERR_INVALID_ARG for a buffer from another configuration or not 256-byte
  * aligned. */
 size_t pic_state_bytes(pic_ctx_t ctx);
@@ -355,13 +357,17 @@ pic_status_t step_batched(pic_ctx_t ctx, int32_t nsteps);
  * BDF-k time derivative of A, Sec. 2.2 and 3.2).  The particle adjoint of W is
  * zero (the caller clears lam).
  *
- * step_adjoint: phase READY with the context holding S^n.  Recomputes the
- * position update, deposit and field solve of step n -> n+1 (as
- * deposit_current + field_solve, but never re-sorting the particles first: a
- * particle that has drifted past its tile's window takes the global path, and
- * the held adjoint keeps its order; phase -> SOLVED afterwards, so the caller
- * reloads the next state, with pic_load_state or pic_set_particles and
- * pic_set_history), then maps (lam, lam_hist) = lambda^{n+1} to lambda^n =
+ * step_adjoint: phase READY with the context holding S^n, or phase SOLVED
+ * with S^n advanced by deposit_current + field_solve (a state saved there by
+ * pic_save_state, or those two calls).  In phase READY it first recomputes
+ * the position update, deposit and field solve of step n -> n+1 (as
+ * deposit_current + field_solve, but without re-sorting particles whose
+ * order comes from a sort: a particle that has drifted past its tile's
+ * window takes the global path, and the held adjoint keeps its order).
+ * Phase -> SOLVED afterwards, marked as used: a second step_adjoint before
+ * another state is loaded (pic_load_state, or pic_set_particles and
+ * pic_set_history) or solved returns PIC_ERR_STATE.  It maps
+ * (lam, lam_hist) = lambda^{n+1} to lambda^n =
  * (dS^{n+1}/dS^n)^T lambda^{n+1}: the push and gather adjoint (a scatter onto
  * the 11 gathered mesh fields; spline derivative weights for the position),
  * the field-solve adjoint (conjugate transforms and the transposed per-mode

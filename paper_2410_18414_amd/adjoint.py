@@ -11,14 +11,16 @@ backward walks the run in reverse with libpic's discrete adjoint
 (adjoint_seed_energy, step_adjoint, adjoint_initial): the state is kept every
 `every` steps during the forward (checkpoints: pic_save_state, the context's
 raw device state -- particles in their sorted order, tile metadata, history
-ring); each segment is replayed forward from its checkpoint into a pool of
-saved states (the last one stays in the context), then the adjoint steps
-through the segment backwards, loading each state with pic_load_state_h (no
-conversion and no re-sort; the header kept on the host, so no synchronisation);
-the particle
-adjoint stays inside the context in slot order for the whole sweep.  every=1
-stores every state (no replay).  Only argument marshalling happens here:
-every step and every adjoint step runs in the library's kernels.
+ring); each segment is replayed forward from its checkpoint, step by step as
+deposit_current, field_solve and gather_push, saving the state after each
+solve (phase SOLVED: the positions, current and fields step_adjoint needs,
+so it recomputes nothing) into a pool of saved states (the last one stays in
+the context); then the adjoint steps through the segment backwards, loading
+each state with pic_load_state_h (no conversion and no re-sort; the header
+kept on the host, so no synchronisation); the particle adjoint stays inside
+the context in slot order for the whole sweep.  Only argument marshalling
+happens here: every step and every adjoint step runs in the library's
+kernels.
 """
 
 import torch
@@ -55,20 +57,22 @@ class _FieldEnergy(torch.autograd.Function):
         pic.load_state(ctx, fctx.final, trust_header=True)
         pic.adjoint_set_particles(ctx, None)  # the particle adjoint of W is zero
         lam_hist = pic.adjoint_seed_energy(ctx, float(gW))
-        # states inside a segment are replayed into a pool of saved states
+        # each segment is replayed from its checkpoint; the state after each
+        # step's deposit and solve goes into a pool of saved states
         pool = []
         for s0, ck in reversed(fctx.ckpts):
             seg = min(fctx.every, fctx.nsteps - s0)
-            states = [ck]
-            if seg > 1:
-                pic.load_state(ctx, ck, trust_header=True)
-                for j in range(1, seg):
-                    pic.step(ctx, 1)
-                    if j < seg - 1:  # the segment's last state stays in the context
-                        if len(pool) < j:
-                            pool.append(pic.State(ctx))
-                        states.append(pic.save_state(ctx, pool[j - 1]))
-                pic.step_adjoint(ctx, None, lam_hist)
+            pic.load_state(ctx, ck, trust_header=True)
+            states = []
+            for j in range(seg):
+                pic.deposit_current(ctx)
+                pic.field_solve(ctx)
+                if j < seg - 1:  # the segment's last solved state stays in the context
+                    if len(pool) <= j:
+                        pool.append(pic.State(ctx))
+                    states.append(pic.save_state(ctx, pool[j]))
+                    pic.gather_push(ctx)
+            pic.step_adjoint(ctx, None, lam_hist)
             for st in reversed(states):
                 pic.load_state(ctx, st, trust_header=True)
                 pic.step_adjoint(ctx, None, lam_hist)

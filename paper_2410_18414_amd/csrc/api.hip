@@ -514,6 +514,9 @@ struct pic_ctx_s {
   // the order and the tile metadata come from a sort of these particles (not
   // an initial load or an import): every particle is in its tile's chunks
   bool from_sort = false;
+  // step_adjoint has run on the current phase-SOLVED state (a second call
+  // would apply the same step's transpose again)
+  bool adjoined = false;
   Phase phase = EMPTY;
   std::string err;
 
@@ -676,6 +679,7 @@ pic_status_t do_solve(pic_ctx_t c) {
   if (st) return st;
   c->nupd += 1;
   c->stepped = true;
+  c->adjoined = false;
   return PIC_OK;
 }
 
@@ -1433,8 +1437,14 @@ pic_status_t pic_set_dirk_tableau(pic_ctx_t c, int32_t stages, const double* A, 
 
 // byte offsets of one instance's parts inside a saved state
 struct StateLayout {
-  size_t parts, ids, start, cstart, work, nwork, hist, rb, end;
+  size_t parts, ids, start, cstart, work, nwork, hist, rb, fields, end;
 };
+// the mesh fields the gather reads (float32 contexts: the node-major copy;
+// float64: the twelve planes), kept by states saved in phase SOLVED
+static size_t field_state_bytes(const Instance& in) {
+  const size_t plane = (size_t)in.cfg.nx * in.cfg.ny;
+  return in.d.F32 ? 12 * plane * 4 : 12 * plane * 8;
+}
 static StateLayout state_layout(pic_ctx_t c, const Instance& in, size_t base) {
   StateLayout L{};
   const size_t es = c->dtype == PIC_F32 ? 4 : 8;
@@ -1453,6 +1463,7 @@ static StateLayout state_layout(pic_ctx_t c, const Instance& in, size_t base) {
   L.nwork = take(4);
   L.hist = take((size_t)c->hist.nslots * in.L.plane_c * 16);
   L.rb = take(in.d.RB ? (size_t)in.cfg.nx * in.cfg.ny * 8 : 0);
+  L.fields = take(field_state_bytes(in));
   L.end = o;
   return L;
 }
@@ -1483,8 +1494,9 @@ static int64_t state_fingerprint(pic_ctx_t c) {
 }
 
 // the segments of a state: (state offset, context address, bytes) for every
-// instance, with n_i particles each
-static std::vector<std::array<size_t, 3>> state_segments(pic_ctx_t c, int cur, const std::vector<int64_t>& ns) {
+// instance, with n_i particles each; solved: also the mesh fields
+static std::vector<std::array<size_t, 3>> state_segments(pic_ctx_t c, int cur, const std::vector<int64_t>& ns,
+                                                         bool solved) {
   std::vector<std::array<size_t, 3>> seg;
   size_t o = state_header_bytes(c);
   const size_t es = c->dtype == PIC_F32 ? 4 : 8;
@@ -1501,6 +1513,7 @@ static std::vector<std::array<size_t, 3>> state_segments(pic_ctx_t c, int cur, c
     seg.push_back({L.nwork, (size_t)d.tb.nwork, 4});
     seg.push_back({L.hist, (size_t)d.H, (size_t)c->hist.nslots * in.L.plane_c * 16});
     if (d.RB) seg.push_back({L.rb, (size_t)d.RB, (size_t)in.cfg.nx * in.cfg.ny * 8});
+    if (solved) seg.push_back({L.fields, d.F32 ? (size_t)d.F32 : (size_t)d.F64, field_state_bytes(in)});
     o = L.end;
   }
   return seg;
@@ -1541,7 +1554,8 @@ static pic_status_t copy_segments(pic_ctx_t c, const std::vector<std::array<size
 pic_status_t pic_save_state_h(pic_ctx_t c, void* dst, int64_t* header) {
   if (!c) return PIC_ERR_INVALID_ARG;
   if (!dst || ((uintptr_t)dst & (kAlign - 1))) return c->fail(PIC_ERR_INVALID_ARG, "dst must be a 256-byte aligned device pointer");
-  if (c->phase != READY) return c->fail(PIC_ERR_STATE, "save_state needs phase READY");
+  if (c->phase != READY && c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "save_state needs phase READY or SOLVED");
+  const bool solved = c->phase == SOLVED;
   char* b = static_cast<char*>(dst);
   const int ni = c->ninst();
   std::vector<int64_t> ns(ni);
@@ -1550,7 +1564,7 @@ pic_status_t pic_save_state_h(pic_ctx_t c, void* dst, int64_t* header) {
   std::vector<int64_t> words(kStateHeaderWords + ni, 0);
   const int64_t g[] = {(int64_t)kStateMagic, state_fingerprint(c), c->nupd, c->vflip, c->cur, c->moves,
                        c->stepped ? 1 : 0, (int64_t)pic_state_bytes(c), c->sort_every, (int64_t)c->order_tag,
-                       c->from_sort ? 1 : 0};
+                       c->from_sort ? 1 : 0, solved ? 1 : 0, c->adjoined ? 1 : 0};
   for (size_t k = 0; k < sizeof(g) / sizeof(g[0]); ++k) words[k] = g[k];
   for (int i = 0; i < ni; ++i) words[kStateHeaderWords + i] = ns[i];
   pic_status_t st = PIC_OK;
@@ -1561,7 +1575,7 @@ pic_status_t pic_save_state_h(pic_ctx_t c, void* dst, int64_t* header) {
     hipLaunchKernelGGL(k_state_header, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int64_t*>(b) + w0, hw, cnt);
     st = c->hip(hipGetLastError(), "state header");
   }
-  if (!st) st = copy_segments(c, state_segments(c, c->cur, ns), b, true);
+  if (!st) st = copy_segments(c, state_segments(c, c->cur, ns, solved), b, true);
   if (!st && header) std::memcpy(header, words.data(), words.size() * sizeof(int64_t));
   return st;
 }
@@ -1592,7 +1606,9 @@ pic_status_t pic_load_state_h(pic_ctx_t c, const void* src, const int64_t* heade
       return c->fail(PIC_ERR_INVALID_ARG, "src holds a particle count beyond the capacity");
   const int cur = (int)h[4];
   if (cur != 0 && cur != 1) return c->fail(PIC_ERR_INVALID_ARG, "src holds an invalid particle set index");
-  st = copy_segments(c, state_segments(c, cur, ns), const_cast<char*>(b), false);
+  if (h[11] != 0 && h[11] != 1) return c->fail(PIC_ERR_INVALID_ARG, "src holds an invalid phase");
+  const bool solved = h[11] == 1;
+  st = copy_segments(c, state_segments(c, cur, ns, solved), const_cast<char*>(b), false);
   if (st) {
     c->phase = EMPTY;
     return st;
@@ -1610,7 +1626,8 @@ pic_status_t pic_load_state_h(pic_ctx_t c, const void* src, const int64_t* heade
   c->sort_every = (int)std::min<int64_t>(std::max<int64_t>(h[8], 1), 64);
   c->order_tag = (uint64_t)h[9];
   c->from_sort = h[10] != 0;
-  c->phase = READY;
+  c->adjoined = h[12] != 0;
+  c->phase = solved ? SOLVED : READY;
   // the device descriptors change only with the particle counts
   return counts_changed ? c->upload_desc() : PIC_OK;
 }
@@ -1689,8 +1706,11 @@ pic_status_t pic_adjoint_get_particles(pic_ctx_t c, double* lam) {
 
 pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
   if (!c) return PIC_ERR_INVALID_ARG;
-  pic_status_t st = adjoint_check(c, true);
+  pic_status_t st = adjoint_check(c, false);
   if (st) return st;
+  if (c->phase != READY && c->phase != SOLVED) return c->fail(PIC_ERR_STATE, "step_adjoint needs phase READY or SOLVED");
+  if (c->phase == SOLVED && c->adjoined)
+    return c->fail(PIC_ERR_STATE, "step_adjoint already ran on this state (load the next one)");
   Instance& in = c->I();
   if (!lam_hist) return c->fail(PIC_ERR_INVALID_ARG, "lam_hist must be a device pointer");
   if (lam) {
@@ -1699,14 +1719,18 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
   } else if (c->lam_n != in.d.n) {
     return c->fail(PIC_ERR_STATE, "lam is NULL and no particle adjoint is held for the loaded particles");
   }
-  // recompute x^{n+1}, J^{n+1} and the level-(n+1) fields from the loaded
-  // state, without the sort the forward may have made before this deposit
-  // when the loaded order comes from a sort (its chunks hold every particle):
-  // the next state is loaded over this one anyway, and a sort here would
-  // cost the scatter and two permutations of the held adjoint (into the new
-  // order and back to the next loaded state's)
-  st = particle_pass(c, 0, !c->from_sort);
-  if (!st) st = do_solve(c);
+  // phase READY: recompute x^{n+1}, J^{n+1} and the level-(n+1) fields from
+  // the loaded state, without the sort the forward may have made before this
+  // deposit when the loaded order comes from a sort (its chunks hold every
+  // particle): the next state is loaded over this one anyway, and a sort here
+  // would cost the scatter and two permutations of the held adjoint (into the
+  // new order and back to the next loaded state's).  Phase SOLVED: the
+  // context already holds them (a state saved after deposit_current and
+  // field_solve)
+  if (c->phase == READY) {
+    st = particle_pass(c, 0, !c->from_sort);
+    if (!st) st = do_solve(c);
+  }
   const InstDesc* D = c->d_desc;
   const int nx = in.cfg.nx, ny = in.cfg.ny;
   const StepArgs sa = c->sargs();
@@ -1743,6 +1767,7 @@ pic_status_t step_adjoint(pic_ctx_t c, double* lam, double* lam_hist) {
     c->lam_tag = 0;
   }
   c->phase = st ? EMPTY : SOLVED;
+  c->adjoined = !st;
   return st;
 }
 

@@ -343,7 +343,7 @@ class State:
 
 
 def save_state(ctx, state=None):
-    """Save the context's state (phase READY) into `state` (a new State if None)."""
+    """Save the context's state (phase READY or SOLVED) into `state` (a new State if None)."""
     state = state or State(ctx)
     ctx.check(load().pic_save_state_h(ctx.handle, state.ptr, ctypes.cast(state.header, ctypes.c_void_p)))
     state.ns = list(ctx.ns)

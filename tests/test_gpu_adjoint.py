@@ -172,6 +172,44 @@ def test_held_adjoint_equals_explicit_across_sorts(gpu_lib):
         pic.step_adjoint(ctx, None, h_h)
 
 
+def test_step_adjoint_from_solved_state_equals_recompute(gpu_lib):
+    """step_adjoint on a state saved after deposit_current + field_solve
+    (phase SOLVED: nothing recomputed) equals step_adjoint on the state
+    before them (phase READY: recomputed); a second step_adjoint on the same
+    state is refused; the SOLVED state steps on like the context it was
+    saved from."""
+    pic = gpu_lib
+    w = _weibel(nx=32, ny=32, ppc=4, seed=59)
+    n = w["x"].shape[0]
+    ctx = _ctx(pic, w)
+    pic.init_particles(ctx, _dev(w["x"]), _dev(w["y"]), _dev(w["P"].T))
+    pic.step(ctx, 3)
+    ready = pic.save_state(ctx)
+    pic.deposit_current(ctx)
+    pic.field_solve(ctx)
+    solved = pic.save_state(ctx)
+    pic.gather_push(ctx)
+    p_ref = pic.get_particles(ctx).cpu().numpy()
+    g = torch.Generator().manual_seed(11)
+    lam0 = torch.randn((11, n), generator=g, dtype=torch.float64).to("cuda")
+    h0 = pic.adjoint_seed_energy(ctx, 1.0)
+    h0 = h0 + torch.randn(h0.shape, generator=g, dtype=torch.complex128).to("cuda")
+    pic.load_state(ctx, ready)
+    lam_a, h_a = lam0.clone(), h0.clone()
+    pic.step_adjoint(ctx, lam_a, h_a)
+    with pytest.raises(pic.PicError) as e:
+        pic.step_adjoint(ctx, lam0.clone(), h0.clone())
+    assert e.value.status == 5
+    pic.load_state(ctx, solved, trust_header=True)
+    lam_b, h_b = lam0.clone(), h0.clone()
+    pic.step_adjoint(ctx, lam_b, h_b)
+    assert rel(lam_b.cpu().numpy(), lam_a.cpu().numpy()) <= 1e-12
+    assert rel(h_b.cpu().numpy(), h_a.cpu().numpy()) <= 1e-12
+    pic.load_state(ctx, solved)
+    pic.gather_push(ctx)
+    assert rel(pic.get_particles(ctx).cpu().numpy(), p_ref) <= 1e-14
+
+
 def test_gradient_with_particles_past_their_windows(gpu_lib):
     """Counter-streaming particles at |v_x| up to about 0.67 c (0.33 cells a
     step) with a sort every 10 position updates: before each sort, and in
