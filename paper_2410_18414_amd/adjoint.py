@@ -13,14 +13,15 @@ backward walks the run in reverse with libpic's discrete adjoint
 raw device state -- particles in their sorted order, tile metadata, history
 ring); each segment is replayed forward from its checkpoint, step by step as
 deposit_current, field_solve and gather_push, saving the state after each
-solve (phase SOLVED: the positions, current and fields step_adjoint needs,
+solve (phase SOLVED: the new positions and fields step_adjoint needs,
 so it recomputes nothing) into a pool of saved states (the last one stays in
 the context); then the adjoint steps through the segment backwards, loading
 each state with pic_load_state_h (no conversion and no re-sort; the header
 kept on the host, so no synchronisation); the particle adjoint stays inside
-the context in slot order for the whole sweep.  Only argument marshalling
-happens here: every step and every adjoint step runs in the library's
-kernels.
+the context in slot order for the whole sweep.  every=1 keeps every state,
+saved after its step's deposit and solve (no replay, no recompute).  Only
+argument marshalling happens here: every step and every adjoint step runs in
+the library's kernels.
 """
 
 import torch
@@ -33,12 +34,21 @@ class _FieldEnergy(torch.autograd.Function):
     def forward(fctx, x0, y0, P0, ctx, nsteps, every):
         pic.init_particles(ctx, x0.detach(), y0.detach(), P0.detach())
         ckpts = []
-        s = 0
-        while s < nsteps:
-            ckpts.append((s, pic.save_state(ctx)))
-            k = min(every, nsteps - s)
-            pic.step(ctx, k)
-            s += k
+        if every == 1:
+            # every state kept, each after its step's deposit and solve (phase
+            # SOLVED), so the adjoint steps recompute nothing
+            for s in range(nsteps):
+                pic.deposit_current(ctx)
+                pic.field_solve(ctx)
+                ckpts.append((s, pic.save_state(ctx)))
+                pic.gather_push(ctx)
+        else:
+            s = 0
+            while s < nsteps:
+                ckpts.append((s, pic.save_state(ctx)))
+                k = min(every, nsteps - s)
+                pic.step(ctx, k)
+                s += k
         final = pic.save_state(ctx)
         W = pic.diagnostics(ctx)["energy"]
         fctx.sim = ctx
@@ -61,6 +71,10 @@ class _FieldEnergy(torch.autograd.Function):
         # step's deposit and solve goes into a pool of saved states
         pool = []
         for s0, ck in reversed(fctx.ckpts):
+            if fctx.every == 1:  # a solved state per step: no replay
+                pic.load_state(ctx, ck, trust_header=True)
+                pic.step_adjoint(ctx, None, lam_hist)
+                continue
             seg = min(fctx.every, fctx.nsteps - s0)
             pic.load_state(ctx, ck, trust_header=True)
             states = []
